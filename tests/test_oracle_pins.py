@@ -1,0 +1,246 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a closed form
+derived by hand from the structure of Eq. (17), a library routine on the dense
+matrix, the BSS identity of Eq. (18), the positivity that the paper's anti-unitary
+symmetry guarantees, a finite-difference derivative, or an exact identity of the
+pseudofermion method (Eq. 19-21) and of leapfrog (Methods D).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import closed_forms as C
+import synth_inputs as S
+
+
+def tiny(**kw):
+    return O.Model(L=4, Lt=8, **kw)
+
+
+@pytest.fixture(scope="module")
+def tiny_inputs():
+    phi0, trajs = S.hmc_inputs(0, 4, 8, 1.0, 1)
+    pi, etas, u = trajs[0]
+    return phi0, pi, etas, u
+
+
+def test_model_validation():
+    for bad in [dict(L=5, Lt=8), dict(L=2, Lt=8), dict(L=4, Lt=1), dict(L=4, Lt=8, dtau=0.0)]:
+        with pytest.raises(ValueError):
+            O.Model(**bad)
+
+
+def test_index_map_is_row_major_alpha_s_tau_x_y():
+    m = O.Model(L=6, Lt=4)
+    seen = set()
+    for a in range(2):
+        for s in range(2):
+            for t in range(4):
+                for x in range(6):
+                    for y in range(6):
+                        i = O.spinor_index(m, a, s, t, x, y)
+                        assert i == np.ravel_multi_index((a, s, t, x, y), m.spinor_shape())
+                        seen.add(i)
+    assert seen == set(range(m.dim))
+
+
+def test_dense_matches_matrix_free(tiny_inputs):
+    phi = tiny_inputs[0]
+    m = tiny()
+    D = O.dense_M(m, phi)
+    g = S.rng(11)
+    for v in S.draw_spinor(g, 4, 8, 3):
+        assert np.abs(D @ v.ravel() - O.apply_M(m, phi, v).ravel()).max() < 1e-13
+        assert np.abs(D.conj().T @ v.ravel() - O.apply_Mdag(m, phi, v).ravel()).max() < 1e-13
+
+
+def test_adjoint_identity(tiny_inputs):
+    phi = tiny_inputs[0]
+    m = O.Model(L=6, Lt=10, lam=0.8, mu=(0.3, -0.2))
+    g = S.rng(3)
+    phi = S.draw_phi(g, 6, 10, 1.0)
+    u_, v_ = S.draw_spinor(g, 6, 10, 2)
+    lhs = np.vdot(u_.ravel(), O.apply_M(m, phi, v_).ravel())
+    rhs = np.vdot(O.apply_Mdag(m, phi, u_).ravel(), v_.ravel())
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_time_local_block_is_hermitian(tiny_inputs):
+    m = tiny()
+    A = O.time_slice_block(m, tiny_inputs[0], 3)
+    assert np.abs(A - A.conj().T).max() == 0.0
+
+
+def test_free_limit_logdet_and_spectrum():
+    """g = 0: log det and spectrum of M^dagger M against the hand-derived closed form."""
+    for kw in [dict(), dict(mu=(0.3, -0.4), t=((1.0, 0.7), (0.2, 1.3)), dtau=0.15)]:
+        m = tiny(lam=0.0, **kw)
+        A = O.dense_MdagM(m, np.zeros(m.phi_shape()))
+        assert abs(np.linalg.slogdet(A)[1] - C.free_logdet_MdagM(m)) < 1e-10
+        ev = np.linalg.eigvalsh(A)
+        assert np.abs(np.sort(ev) - C.free_spectrum_MdagM(m)).max() < 1e-12
+
+
+def test_free_limit_periodic_time_would_fail():
+    """The antiperiodic sign matters: a periodic closed form (1 - b^N) differs."""
+    m = tiny(lam=0.0)
+    kx, ky = np.meshgrid(2 * np.pi * np.arange(4) / 4, 2 * np.pi * np.arange(4) / 4, indexing="ij")
+    periodic = sum(4 * np.log(np.abs(1 - (1 + 0.1 * (0.5 + 2 * m.t[a][0] * np.cos(kx)
+                                                     + 2 * m.t[a][1] * np.cos(ky))) ** 8)).sum()
+                   for a in range(2))
+    A = O.dense_MdagM(m, np.zeros(m.phi_shape()))
+    assert abs(np.linalg.slogdet(A)[1] - periodic) > 1.0
+
+
+def test_uniform_field_determinant():
+    """Constant phi: closed form with the band x (k) / band y (k + Q_AF) pairing."""
+    m = tiny(lam=1.3)
+    for pv in [np.array([0.3, -0.7, 1.1]), np.array([0.0, 0.0, 2.0]), np.array([1.5, 0.2, 0.0])]:
+        phi = np.broadcast_to(pv[:, None, None, None], m.phi_shape()).copy()
+        sign, logabs = np.linalg.slogdet(O.dense_M(m, phi))
+        ref = C.uniform_field_logdet_M(m, pv)
+        assert abs(logabs - ref.real) < 1e-10
+        assert abs(sign - 1.0) < 1e-10
+
+
+def test_bss_determinant_identity(tiny_inputs):
+    """Eq. (18): det M = det(1 + prod_tau B_tau) for a random field."""
+    m = O.Model(L=4, Lt=4)
+    phi = S.draw_phi(S.rng(5), 4, 4, 1.0)
+    blocks = [O.time_slice_block(m, phi, t) for t in range(4)]
+    d1 = C.bss_det(m, blocks)
+    d2 = np.linalg.det(O.dense_M(m, phi))
+    assert abs(d1 - d2) < 1e-9 * abs(d2)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_det_real_positive(seed):
+    """The inter-band anti-unitary symmetry makes det M real and positive."""
+    m = tiny()
+    phi = S.draw_phi(S.rng(seed), 4, 8, 1.0)
+    sign, _ = np.linalg.slogdet(O.dense_M(m, phi))
+    assert abs(sign - 1.0) < 1e-12
+
+
+def test_cg_against_dense_solve(tiny_inputs):
+    m = tiny()
+    phi, _, etas, _ = tiny_inputs
+    chi = O.heatbath(m, phi, etas[0])
+    x, it, res = O.cg_solve(m, phi, chi, tol=1e-10)
+    assert res <= 1e-10
+    xd = np.linalg.solve(O.dense_MdagM(m, phi), chi.ravel())
+    assert np.linalg.norm(x.ravel() - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
+def test_heatbath_action_equals_eta_norm(tiny_inputs):
+    m = tiny()
+    phi, _, etas, _ = tiny_inputs
+    chis = [O.heatbath(m, phi, e) for e in etas]
+    ref = float((np.abs(etas) ** 2).sum())
+    assert abs(O.pf_action_dense(m, phi, chis) - ref) < 1e-12 * ref
+
+
+def test_pf_force_central_differences(tiny_inputs):
+    m = tiny()
+    phi, _, etas, _ = tiny_inputs
+    chis = [O.heatbath(m, phi, e) for e in etas]
+    A = O.dense_MdagM(m, phi)
+    xs = [np.linalg.solve(A, c.ravel()).reshape(m.spinor_shape()) for c in chis]
+    F = O.pf_force(m, phi, xs)
+    h = 1e-6
+    g = S.rng(9)
+    for _ in range(6):
+        l, t, a, b = g.integers(0, 3), g.integers(0, 8), g.integers(0, 4), g.integers(0, 4)
+        pp = phi.copy(); pp[l, t, a, b] += h
+        pm = phi.copy(); pm[l, t, a, b] -= h
+        fd = (O.pf_action_dense(m, pp, chis) - O.pf_action_dense(m, pm, chis)) / (2 * h)
+        assert abs(F[l, t, a, b] - fd) < 2e-7 + 1e-6 * abs(fd)
+
+
+def test_boson_action_fourier_and_force_fd():
+    m = O.Model(L=4, Lt=8, r=0.3, c=1.5)
+    phi = S.draw_phi(S.rng(2), 4, 8, 1.0)
+    assert abs(O.boson_action(m, phi) - C.free_boson_action(m, phi)) < 1e-10 * O.boson_action(m, phi)
+    mq = O.Model(L=4, Lt=8, r=0.3, c=1.5, u=0.2)
+    F = O.boson_force(mq, phi)
+    h = 1e-6
+    for (l, t, a, b) in [(0, 0, 0, 0), (1, 3, 2, 1), (2, 7, 3, 2)]:
+        pp = phi.copy(); pp[l, t, a, b] += h
+        pm = phi.copy(); pm[l, t, a, b] -= h
+        fd = (O.boson_action(mq, pp) - O.boson_action(mq, pm)) / (2 * h)
+        assert abs(F[l, t, a, b] - fd) < 1e-5 * max(1.0, abs(fd))
+
+
+def test_logdet_ratio_pseudofermion_estimate():
+    """Eq. (19): E_{xi ~ CN(0, A)} exp(-xi^dagger (A'^-1 - A^-1) xi) = det A' / det A."""
+    m = tiny()
+    g = S.rng(21)
+    phi = S.draw_phi(g, 4, 8, 1.0)
+    phi2 = phi + 0.02 * S.draw_phi(g, 4, 8, 1.0)
+    A = O.dense_MdagM(m, phi)
+    A2 = O.dense_MdagM(m, phi2)
+    exact = np.exp(np.linalg.slogdet(A2)[1] - np.linalg.slogdet(A)[1])
+    Mdag = O.dense_M(m, phi).conj().T
+    Ainv, A2inv = np.linalg.inv(A), np.linalg.inv(A2)
+    n = 4000
+    etas = S.draw_eta(g, 4, 8, n).reshape(n, -1)
+    xis = etas @ Mdag.T                   # xi = M^dagger eta ~ CN(0, M^dagger M)
+    q = np.einsum("ni,ij,nj->n", xis.conj(), A2inv - Ainv, xis).real
+    w = np.exp(-q)
+    est, err = w.mean(), w.std() / np.sqrt(n)
+    assert abs(est - exact) < 4 * err + 1e-12, (est, err, exact)
+
+
+def test_mean_force_is_logdet_gradient():
+    """E_chi[dS_PF/dphi] = -d log det(M^dagger M)/dphi for chi ~ CN(0, M^dagger M)."""
+    m = tiny()
+    g = S.rng(22)
+    phi = S.draw_phi(g, 4, 8, 1.0)
+    A = O.dense_MdagM(m, phi)
+    Ainv = np.linalg.inv(A)
+    site = (1, 2, 1, 3)
+    h = 1e-5
+    pp = phi.copy(); pp[site] += h
+    pm = phi.copy(); pm[site] -= h
+    dlogdet = (np.linalg.slogdet(O.dense_MdagM(m, pp))[1]
+               - np.linalg.slogdet(O.dense_MdagM(m, pm))[1]) / (2 * h)
+    n = 400
+    etas = S.draw_eta(g, 4, 8, n)
+    vals = []
+    for e in etas:
+        chi = O.heatbath(m, phi, e)
+        x = (Ainv @ chi.ravel()).reshape(m.spinor_shape())
+        vals.append(O.pf_force(m, phi, [x])[site])
+    vals = np.array(vals)
+    est, err = vals.mean(), vals.std() / np.sqrt(n)
+    assert abs(est + dlogdet) < 4 * err, (est, err, -dlogdet)
+
+
+def test_leapfrog_reversible_and_second_order(tiny_inputs):
+    m = tiny()
+    phi, pi, etas, u = tiny_inputs
+    r = O.trajectory(m, phi, pi, list(etas), u, 0.01, 10)
+    back = O.leapfrog(m, r["phi_proposed"], -r["pi_proposed"], r["chis"], 0.01, 10)
+    assert np.abs(back[0] - phi).max() < 1e-10
+    assert np.abs(back[1] + pi).max() < 1e-9
+    dh = [O.trajectory(m, phi, pi, list(etas), u, eps, int(round(0.1 / eps)))["dH"]
+          for eps in (0.02, 0.01, 0.005)]
+    for a, b in zip(dh, dh[1:]):
+        assert 3.6 < a / b < 4.4
+
+
+def test_free_boson_leapfrog_closed_form():
+    m = O.Model(L=4, Lt=8, lam=0.0, r=0.5)
+    g = S.rng(4)
+    phi, pi = S.draw_phi(g, 4, 8), S.draw_momentum(g, 4, 8)
+    a, b, *_ = O.leapfrog(m, phi, pi, [], 0.05, 7)
+    c, d = C.free_boson_leapfrog(m, phi, pi, 0.05, 7)
+    assert np.abs(a - c).max() < 1e-12 and np.abs(b - d).max() < 1e-12
+
+
+def test_metropolis_rule():
+    assert O.metropolis_accept(-1.0, 0.999)
+    assert O.metropolis_accept(0.5, np.exp(-0.5) - 1e-12)
+    assert not O.metropolis_accept(0.5, np.exp(-0.5))
+    assert not O.metropolis_accept(np.inf, 0.0)
