@@ -1,0 +1,205 @@
+/*
+ * hmc.h -- C ABI of the MI355X (gfx950) HIP library for the Hybrid Monte Carlo hot path
+ * of the O(3) spin-fermion model (Lunts, Albergo, Lindsey, arXiv:2204.14241).
+ *
+ * The library applies the space-time fermion matrix M[phi] of Eq. (17) and its adjoint,
+ * solves the normal equations (M^dagger M) x = chi by conjugate gradient (Methods C,
+ * Eq. 22), evaluates the pseudofermion action of Eq. (21) and its gradient, the boson
+ * action of Eq. (2), and runs leapfrog HMC trajectories with a Metropolis decision
+ * (Methods D, Eq. 27-29).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Return value: HMC_OK (0) on success, a negative HMC_ERR_* code otherwise; no
+ *    exception crosses the ABI.  hmc_last_error() gives a message for the calling thread.
+ *  - Pointers named phi, in, out, b, x, chi, eta, pi, force are DEVICE pointers owned
+ *    by the caller; they must be 16-byte aligned.  Host pointers are marked "host".
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *    enqueued on it; entry points that must read a device scalar back (CG convergence,
+ *    actions, trajectories) synchronise with it before returning.
+ *  - Layouts (row-major, index order of Eq. 17):
+ *      boson field phi     : double[3][L_tau][L][L]   (float for the *_f32 entry points)
+ *      spinor (one vector) : complex[4][L_tau][L][L] with component c = 2*band + spin,
+ *                            band 0 = the paper's band x, spin 0 = up; complex numbers
+ *                            are interleaved (re, im) pairs: complex128 for FP64 entry
+ *                            points, complex64 for *_f32 ones.
+ *      n vectors           : n consecutive spinors, stride 4*L_tau*L*L complex.
+ *  - A context is bound to the device current at hmc_create and is not thread-safe; use
+ *    one context per stream.
+ *  - The library allocates no device memory.  Scratch space is a caller-owned device
+ *    buffer of hmc_workspace_bytes() bytes handed over with hmc_set_workspace(); entry
+ *    points that need it fail with HMC_ERR_WORKSPACE until it is set.  The library
+ *    allocates a small pinned host buffer and events for its own status reads.
+ */
+#ifndef HMC_H
+#define HMC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HMC_OK                 0
+#define HMC_ERR_INVALID_ARG   -1   /* bad size, parameter or pointer                     */
+#define HMC_ERR_NOT_CONVERGED -2   /* CG hit cg_maxit; x and stats are still written     */
+#define HMC_ERR_NONFINITE     -3   /* NaN/Inf met in a reduction; trajectory rejected    */
+#define HMC_ERR_HIP           -4   /* a HIP runtime call failed (see hmc_last_error)     */
+#define HMC_ERR_WORKSPACE     -5   /* workspace missing or too small                     */
+
+#define HMC_FP64  0                /* all arithmetic in double                           */
+#define HMC_MIXED 1                /* FP32 Krylov iterations, FP64 reliable updates      */
+
+#define HMC_MAX_RHS 16             /* most right-hand sides one solve accepts            */
+
+/* Model and run parameters.  Eq. (17) for the fermion terms, Eq. (2) for the boson. */
+typedef struct hmc_params {
+    double t[2][2];      /* nearest-neighbour hopping t[band][direction]; direction 0 is
+                            the slower spatial index x, 1 the faster index y             */
+    double mu[2];        /* chemical potential per band                                  */
+    double lambda;       /* Yukawa coefficient (the paper's g in Eq. 17)                 */
+    double r, c, u;      /* boson mass squared, velocity, quartic coupling (Eq. 2)       */
+    double eps;          /* leapfrog step                                                */
+    int    n_leap;       /* leapfrog steps per trajectory                                */
+    int    n_pf;         /* pseudofermions per trajectory (each carries full weight)     */
+    double cg_tol;       /* relative true-residual target ||b - A x|| / ||b||            */
+    int    cg_maxit;     /* iteration cap per solve                                      */
+    int    precision;    /* HMC_FP64 or HMC_MIXED                                        */
+    int    reliable_every; /* mixed precision: FP64 reliable update every k iterations    */
+    int    max_rhs;      /* right-hand sides the workspace is sized for (0: n_pf)        */
+} hmc_params;
+
+/* Per-solve statistics (host struct filled by the solver entry points). */
+typedef struct hmc_cg_stats {
+    int    n;                          /* right-hand sides solved                          */
+    int    status;                     /* HMC_OK, HMC_ERR_NOT_CONVERGED or NONFINITE       */
+    int    iterations[HMC_MAX_RHS];    /* Krylov iterations per right-hand side            */
+    int    reliable_updates[HMC_MAX_RHS]; /* FP64 true-residual recomputations             */
+    double true_resid[HMC_MAX_RHS];    /* final ||b - A x|| / ||b|| evaluated in FP64       */
+} hmc_cg_stats;
+
+/* Per-trajectory statistics (host struct). */
+typedef struct hmc_traj_stats {
+    double dH;            /* H(end) - H(start)                                           */
+    double H0, H1;        /* Hamiltonians of Eq. (28) at the two ends                    */
+    double S_pf0, S_pf1;  /* pseudofermion action at the start (|eta|^2) and end         */
+    double S_b0, S_b1;    /* boson action                                                */
+    double K0, K1;        /* kinetic energy 1/2 |pi|^2                                   */
+    int    accepted;      /* 1 if u < exp(-dH)                                           */
+    int    cg_solves;     /* solves run (n_leap + 1, each over n_pf right-hand sides)    */
+    long   cg_iterations; /* Krylov iterations summed over solves and right-hand sides   */
+    double max_true_resid;/* largest final relative residual over all solves             */
+    int    status;        /* worst status met                                            */
+} hmc_traj_stats;
+
+typedef struct hmc_ctx hmc_ctx;
+
+/* Create a context for an L x L x L_tau lattice with Trotter step dtau (Methods A).
+ * L must be even (the ordering-vector phase (-1)^(x+y) needs it), 4 <= L <= 256;
+ * L_tau >= 2; L_tau*L*L < 2^26; dtau > 0.  params is copied.  *out receives the handle.
+ * Errors: HMC_ERR_INVALID_ARG, HMC_ERR_HIP. */
+int hmc_create(int L, int L_tau, double dtau, const hmc_params* params, hmc_ctx** out);
+
+/* Release the context (not the caller's buffers). */
+int hmc_destroy(hmc_ctx* ctx);
+
+/* Update run parameters (eps, n_leap, n_pf, cg_tol, cg_maxit, precision, reliable_every
+ * and the model couplings).  n_pf and max_rhs may not exceed the capacity the workspace
+ * was sized for.  Errors: HMC_ERR_INVALID_ARG. */
+int hmc_set_params(hmc_ctx* ctx, const hmc_params* params);
+
+/* Bytes of device workspace the context needs (sized for max_rhs right-hand sides in
+ * the precision set at creation, plus trajectory state). */
+size_t hmc_workspace_bytes(const hmc_ctx* ctx);
+
+/* Hand over a device buffer of at least hmc_workspace_bytes() bytes, 256-byte aligned.
+ * The caller keeps ownership and must keep it alive while the context uses it.
+ * Errors: HMC_ERR_INVALID_ARG, HMC_ERR_WORKSPACE. */
+int hmc_set_workspace(hmc_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* out_k = M[phi] in_k for k < n (Eq. 17): diagonal -(1 + dtau mu_band), forward time
+ * link +1 (-1 from the last slice to the first: antiperiodic), hopping -dtau t, on-site
+ * dtau lambda (-1)^(x+y) (phi . Pauli) across the two bands.  in and out must not
+ * overlap.  No workspace needed.  Errors: HMC_ERR_INVALID_ARG, HMC_ERR_HIP. */
+int hmc_apply_M(hmc_ctx* ctx, const double* phi, const void* in, void* out, int n, void* stream);
+
+/* out_k = M[phi]^dagger in_k: the same time-local part (it is Hermitian) and the
+ * backward time link from tau - 1 with the sign of that link. */
+int hmc_apply_Mdag(hmc_ctx* ctx, const double* phi, const void* in, void* out, int n, void* stream);
+
+/* out_k = M^dagger M in_k, the normal operator of Eq. (22).  Uses the workspace for the
+ * intermediate M in_k (n <= max_rhs).  Errors as above plus HMC_ERR_WORKSPACE. */
+int hmc_apply_MdagM(hmc_ctx* ctx, const double* phi, const void* in, void* out, int n, void* stream);
+
+/* FP32 forms of the three applies: phi is float[3][L_tau][L][L], spinors complex64.
+ * Arithmetic and accumulation are FP32. */
+int hmc_apply_M_f32(hmc_ctx* ctx, const float* phi, const void* in, void* out, int n, void* stream);
+int hmc_apply_Mdag_f32(hmc_ctx* ctx, const float* phi, const void* in, void* out, int n, void* stream);
+int hmc_apply_MdagM_f32(hmc_ctx* ctx, const float* phi, const void* in, void* out, int n, void* stream);
+
+/* Solve (M^dagger M) x_k = b_k, k < n <= max_rhs, by conjugate gradient from x = 0
+ * (Methods C).  b, x: complex128 spinors.  Convergence: the FP64 true residual
+ * ||b - A x|| / ||b|| <= cg_tol, evaluated once the iterated residual passes that bound
+ * (CG restarts from the true residual if it does not).  With precision HMC_MIXED the
+ * Krylov iterations run in FP32 (complex64 vectors, FP32 phi, FP64 dot products) and x,
+ * r are refreshed in FP64 every reliable_every iterations.  stats (host, may be NULL)
+ * receives per-right-hand-side counts and residuals.  Synchronises the stream.
+ * Errors: HMC_ERR_NOT_CONVERGED (x still written), HMC_ERR_NONFINITE, INVALID_ARG,
+ * WORKSPACE, HIP. */
+int hmc_cg_solve(hmc_ctx* ctx, const double* phi, const void* b, void* x, int n,
+                 hmc_cg_stats* stats, void* stream);
+
+/* Pseudofermion heat-bath (Methods D): chi_k = M[phi]^dagger eta_k for standard complex
+ * Gaussian eta_k (drawn by the caller), so that chi ~ CN(0, M^dagger M). */
+int hmc_heatbath(hmc_ctx* ctx, const double* phi, const void* eta, void* chi, int n_pf, void* stream);
+
+#define HMC_FORCE_PF    1          /* include dS_PF/dphi                                  */
+#define HMC_FORCE_BOSON 2          /* include dS_B/dphi                                   */
+
+/* Gradient dS/dphi of S = S_PF + S_B (selected by flags) at phi, with
+ * S_PF = sum_k chi_k^dagger (M^dagger M)^{-1} chi_k (Eq. 21).  Solves by CG (settings of
+ * the context), then per site: Y = M x, dS_PF/dphi_l = -2 dtau lambda (-1)^(x+y)
+ * Re sum_k [Y_{band x}^dagger Pauli_l x_{band y} + Y_{band y}^dagger Pauli_l x_{band x}].
+ * force: double[3][L_tau][L][L] (overwritten).  S_pf (host, may be NULL) receives
+ * sum_k Re <chi_k, x_k>; stats (host, may be NULL) the solver statistics.
+ * Synchronises the stream.  Errors as hmc_cg_solve. */
+int hmc_force(hmc_ctx* ctx, const double* phi, const void* chi, int n_pf, double* force,
+              double* S_pf, int flags, hmc_cg_stats* stats, void* stream);
+
+/* The same gradient from given solutions x_k of (M^dagger M) x_k = chi_k (no solve):
+ * for callers that keep the solutions.  Does not synchronise. */
+int hmc_force_from_solution(hmc_ctx* ctx, const double* phi, const void* x, int n_pf,
+                            double* force, int flags, void* stream);
+
+/* Pseudofermion action sum_k chi_k^dagger (M^dagger M)^{-1} chi_k (Eq. 21) by CG; the
+ * solutions are written to x (device, n_pf complex128 spinors) when x is not NULL.
+ * S (host) receives the value.  Synchronises the stream. */
+int hmc_pf_action(hmc_ctx* ctx, const double* phi, const void* chi, int n_pf, void* x,
+                  double* S, hmc_cg_stats* stats, void* stream);
+
+/* Boson action S_B (Eq. 2; time-derivative coefficient 1/(2 c^2), forward differences,
+ * periodic in time and space).  S (host) receives it.  Synchronises the stream. */
+int hmc_boson_action(hmc_ctx* ctx, const double* phi, double* S, void* stream);
+
+/* One HMC trajectory (Methods D).  chi_k = M[phi0]^dagger eta_k; H0 = |pi0|^2/2 + S_B +
+ * sum_k |eta_k|^2; n_leap kick-drift-kick steps of size eps (half kicks kept separate),
+ * each drift followed by a CG solve per pseudofermion and the gradient; H1 uses the
+ * last solve.  Accept iff u_uniform < exp(-dH).  phi_inout holds phi0 on entry and the
+ * chain's next field on return (the proposal if accepted, phi0 otherwise).  pi0 is not
+ * modified.  stats (host) receives energies, the decision and solver counts.
+ * Synchronises the stream.  Errors: as hmc_cg_solve; on any error phi_inout is
+ * restored to phi0 and the trajectory counts as rejected. */
+int hmc_trajectory(hmc_ctx* ctx, double* phi_inout, const double* pi0, const void* eta,
+                   int n_pf, double u_uniform, hmc_traj_stats* stats, void* stream);
+
+/* Text for an HMC_* code. */
+const char* hmc_strerror(int code);
+
+/* Message describing the last error raised on the calling thread ("" if none). */
+const char* hmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMC_H */

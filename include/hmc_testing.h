@@ -1,0 +1,34 @@
+/*
+ * hmc_testing.h -- host-callable integer helpers of libhmc, exported so that the lattice
+ * indexing the kernels use can be checked bit for bit on a machine without a GPU.
+ *
+ * They are the same __host__ __device__ functions the kernels call, compiled for the
+ * host.  All arguments are plain integers; nothing here touches a device.
+ */
+#ifndef HMC_TESTING_H
+#define HMC_TESTING_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Decompose a site index s = (tau*L + x)*L + y of an L x L x L_tau lattice into
+ * (tau, x, y) and its six neighbours in the order x+1, x-1, y+1, y-1, tau+1, tau-1
+ * (periodic wrap), plus the signs of the two time links as the kernels apply them:
+ * sign_fwd is the coefficient of psi(tau+1) in M (-1 on the last slice, +1 otherwise,
+ * Eq. 17), sign_bwd that of psi(tau-1) in M^dagger (-1 on the first slice).
+ * out[0..2] = tau, x, y; out[3..8] = neighbours; out[9] = sign_fwd; out[10] = sign_bwd;
+ * out[11] = the staggered phase (-1)^(x+y).  Returns 0, or -1 for an argument the
+ * kernels reject (odd L, L < 4, L > 256, L_tau < 2, volume >= 2^26, s out of range). */
+int hmc_test_site(int L, int L_tau, int s, int out[12]);
+
+/* The block-index permutation the kernels use to keep neighbouring lattice tiles on one
+ * of the MI355X's 8 XCDs: maps a hardware workgroup id (dispatched round-robin over the
+ * XCDs) to a logical tile id.  A bijection on [0, nblocks). */
+int hmc_test_xcd_remap(int bid, int nblocks);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMC_TESTING_H */

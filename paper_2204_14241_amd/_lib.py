@@ -1,0 +1,134 @@
+"""ctypes declarations of the libhmc C ABI (include/hmc.h, include/hmc_testing.h).
+
+Loading fails loudly when the library has not been built: there is no fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhmc.so")
+
+HMC_OK = 0
+HMC_ERR_INVALID_ARG = -1
+HMC_ERR_NOT_CONVERGED = -2
+HMC_ERR_NONFINITE = -3
+HMC_ERR_HIP = -4
+HMC_ERR_WORKSPACE = -5
+HMC_FP64 = 0
+HMC_MIXED = 1
+HMC_MAX_RHS = 16
+HMC_FORCE_PF = 1
+HMC_FORCE_BOSON = 2
+
+EXPORTED = [
+    "hmc_create", "hmc_destroy", "hmc_set_params", "hmc_workspace_bytes", "hmc_set_workspace",
+    "hmc_apply_M", "hmc_apply_Mdag", "hmc_apply_MdagM", "hmc_apply_M_f32", "hmc_apply_Mdag_f32",
+    "hmc_apply_MdagM_f32", "hmc_cg_solve", "hmc_heatbath", "hmc_force",
+    "hmc_force_from_solution", "hmc_pf_action", "hmc_boson_action", "hmc_trajectory",
+    "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap",
+]
+
+
+class HmcParams(ctypes.Structure):
+    _fields_ = [
+        ("t", (ctypes.c_double * 2) * 2),
+        ("mu", ctypes.c_double * 2),
+        ("lambda_", ctypes.c_double),
+        ("r", ctypes.c_double),
+        ("c", ctypes.c_double),
+        ("u", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("n_leap", ctypes.c_int),
+        ("n_pf", ctypes.c_int),
+        ("cg_tol", ctypes.c_double),
+        ("cg_maxit", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("reliable_every", ctypes.c_int),
+        ("max_rhs", ctypes.c_int),
+    ]
+
+
+class HmcCgStats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int),
+        ("status", ctypes.c_int),
+        ("iterations", ctypes.c_int * HMC_MAX_RHS),
+        ("reliable_updates", ctypes.c_int * HMC_MAX_RHS),
+        ("true_resid", ctypes.c_double * HMC_MAX_RHS),
+    ]
+
+
+class HmcTrajStats(ctypes.Structure):
+    _fields_ = [
+        ("dH", ctypes.c_double),
+        ("H0", ctypes.c_double), ("H1", ctypes.c_double),
+        ("S_pf0", ctypes.c_double), ("S_pf1", ctypes.c_double),
+        ("S_b0", ctypes.c_double), ("S_b1", ctypes.c_double),
+        ("K0", ctypes.c_double), ("K1", ctypes.c_double),
+        ("accepted", ctypes.c_int),
+        ("cg_solves", ctypes.c_int),
+        ("cg_iterations", ctypes.c_long),
+        ("max_true_resid", ctypes.c_double),
+        ("status", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load libhmc.so and declare its signatures.  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2204_14241_amd.build` "
+            "(there is no fallback implementation)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    ctx_pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "hmc_create": (I, [I, I, D, ctypes.POINTER(HmcParams), ctx_pp]),
+        "hmc_destroy": (I, [P]),
+        "hmc_set_params": (I, [P, ctypes.POINTER(HmcParams)]),
+        "hmc_workspace_bytes": (S, [P]),
+        "hmc_set_workspace": (I, [P, P, S]),
+        "hmc_apply_M": (I, [P, P, P, P, I, P]),
+        "hmc_apply_Mdag": (I, [P, P, P, P, I, P]),
+        "hmc_apply_MdagM": (I, [P, P, P, P, I, P]),
+        "hmc_apply_M_f32": (I, [P, P, P, P, I, P]),
+        "hmc_apply_Mdag_f32": (I, [P, P, P, P, I, P]),
+        "hmc_apply_MdagM_f32": (I, [P, P, P, P, I, P]),
+        "hmc_cg_solve": (I, [P, P, P, P, I, ctypes.POINTER(HmcCgStats), P]),
+        "hmc_heatbath": (I, [P, P, P, P, I, P]),
+        "hmc_force": (I, [P, P, P, I, P, ctypes.POINTER(D), I, ctypes.POINTER(HmcCgStats), P]),
+        "hmc_force_from_solution": (I, [P, P, P, I, P, I, P]),
+        "hmc_pf_action": (I, [P, P, P, I, P, ctypes.POINTER(D), ctypes.POINTER(HmcCgStats), P]),
+        "hmc_boson_action": (I, [P, P, ctypes.POINTER(D), P]),
+        "hmc_trajectory": (I, [P, P, P, P, I, D, ctypes.POINTER(HmcTrajStats), P]),
+        "hmc_strerror": (ctypes.c_char_p, [I]),
+        "hmc_last_error": (ctypes.c_char_p, []),
+        "hmc_test_site": (I, [I, I, I, ctypes.POINTER(ctypes.c_int)]),
+        "hmc_test_xcd_remap": (I, [I, I]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class HmcError(RuntimeError):
+    def __init__(self, code, where):
+        lib = load()
+        msg = lib.hmc_last_error().decode() or lib.hmc_strerror(code).decode()
+        super().__init__(f"{where}: {lib.hmc_strerror(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def check(code, where):
+    if code != HMC_OK:
+        raise HmcError(code, where)
+    return code

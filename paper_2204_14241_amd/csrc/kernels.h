@@ -1,0 +1,623 @@
+// kernels.h -- gfx950 kernels of libhmc: the fermion-matrix stencil (Eq. 17) and its
+// adjoint, the fused conjugate-gradient steps on M^dagger M (Eq. 22), FP64 reliable
+// updates, deterministic FP64 reductions, the pseudofermion and boson gradients and the
+// leapfrog updates (Methods D).
+//
+// Work decomposition: one thread per lattice site handles all four spinor components
+// (the Yukawa term couples them); a 256-thread workgroup covers 256 consecutive sites in
+// (tau, x, y) order, workgroup ids are permuted so each XCD sweeps a contiguous slab of
+// the lattice (stencil neighbours then hit its L2), and right-hand sides are laid end to
+// end in the grid.  Every operation here is a bandwidth-bound sparse stencil or vector
+// update, so no matrix cores are used.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lattice.h"
+
+namespace hmc {
+
+constexpr int kBlock = 256;
+
+// ------------------------------------------------------------------------------------
+// complex helpers (interleaved re, im)
+template <typename R> struct CT;
+template <> struct CT<double> { using T = double2; };
+template <> struct CT<float> { using T = float2; };
+template <typename R> using C2 = typename CT<R>::T;
+
+template <typename R>
+__device__ __forceinline__ C2<R> mk(R re, R im) { C2<R> z; z.x = re; z.y = im; return z; }
+template <typename R>
+__device__ __forceinline__ C2<R> add(C2<R> a, C2<R> b) { return mk<R>(a.x + b.x, a.y + b.y); }
+template <typename R>
+__device__ __forceinline__ C2<R> sub(C2<R> a, C2<R> b) { return mk<R>(a.x - b.x, a.y - b.y); }
+template <typename R>
+__device__ __forceinline__ C2<R> scl(R s, C2<R> a) { return mk<R>(s * a.x, s * a.y); }
+// a + s*b
+template <typename R>
+__device__ __forceinline__ C2<R> axpy(R s, C2<R> b, C2<R> a) { return mk<R>(a.x + s * b.x, a.y + s * b.y); }
+template <typename R>
+__device__ __forceinline__ R norm2(C2<R> a) { return a.x * a.x + a.y * a.y; }
+
+// ------------------------------------------------------------------------------------
+// CG bookkeeping kept on the device, one record per right-hand side.
+enum CgMode : int {
+    CG_ACTIVE = 0,      // iterating
+    CG_CONV_ITER = 1,   // iterated residual passed; FP64 true residual not yet checked
+    CG_MAXIT = 2,       // iteration cap reached; x not yet finalised
+    CG_DONE = 3,        // true residual passed
+    CG_STOPPED = 4,     // iteration cap reached, x finalised
+    CG_FAILED = 5,      // a reduction was not finite
+};
+enum : int {
+    F_ACTIVE = 1 << CG_ACTIVE,
+    F_CONV_ITER = 1 << CG_CONV_ITER,
+    F_MAXIT = 1 << CG_MAXIT,
+};
+
+struct CgState {
+    double bb;          // |b|^2
+    double stop_rr;     // tol^2 |b|^2
+    double rr;          // current iterated |r|^2
+    double rr_prev;     // |r|^2 of the previous iteration
+    double alpha;       // step still to be added to x along the current p (pending)
+    double alpha_cur;   // step of the iteration in flight
+    double beta;        // coefficient of the next direction update p <- r + beta p
+    double rr_true;     // last FP64 true residual |b - A x|^2
+    int mode;
+    int iters;
+    int pbuf;           // which of the two direction buffers holds the current p
+    int n_ru;           // FP64 true-residual recomputations
+    int maxit;
+    int pad[3];
+};
+
+// ------------------------------------------------------------------------------------
+// Deterministic reductions: butterfly within a wavefront, fixed-order sum over the
+// wavefronts of a workgroup, per-workgroup partials in global memory, and the last
+// workgroup to arrive (atomic ticket) sums the partials in index order.  The result
+// depends only on the grid shape, never on scheduling.
+template <int NQ>
+__device__ __forceinline__ void block_reduce(double (&v)[NQ]) {
+    __shared__ double sh[NQ][16];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double a = v[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+        v[q] = a;
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sh[q][w] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            double a = 0.0;
+            for (int i = 0; i < nw; ++i) a += sh[q][i];
+            v[q] = a;
+        }
+    }
+    __syncthreads();
+}
+
+// Returns true in every thread of the last workgroup; thread 0 of it then holds the
+// grid totals in v.  partial has NQ rows of `stride` doubles.
+template <int NQ>
+__device__ __forceinline__ bool grid_reduce(double (&v)[NQ], double* partial, int stride,
+                                            int nblk, int blk, unsigned* cnt) {
+    __shared__ int last;
+    block_reduce<NQ>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) partial[q * stride + blk] = v[q];
+        __threadfence();
+        const unsigned old = atomicAdd(cnt, 1u);
+        last = (old == unsigned(nblk - 1));
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double a[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        a[q] = 0.0;
+        for (int j = threadIdx.x; j < nblk; j += blockDim.x)
+            a[q] += __hip_atomic_load(partial + q * stride + j, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+    }
+    block_reduce<NQ>(a);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[q] = a[q];
+        __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool finite(double x) { return x - x == 0.0; }
+
+// ------------------------------------------------------------------------------------
+// The stencil of Eq. (17) at one site.  Src(c, i) yields component c of the input at
+// site i (a plain load, or an expression such as r + beta p evaluated on the fly).
+//   (M psi)_c     = diag_b psi_c + sum_d hop_bd [psi_c(r+d) + psi_c(r-d)]
+//                   + sfwd psi_c(tau+1) + Yukawa_c
+//   (M^+ psi)_c   = the same with sbwd psi_c(tau-1)
+//   Yukawa (band a, spin s) = dtau lambda (-1)^(x+y) sum_s' (phi . Pauli)_{s s'} psi_{other band, s'}
+// with phi . Pauli = [[phi3, phi1 - i phi2], [phi1 + i phi2, -phi3]].
+template <typename R, bool DAG, class Src>
+__device__ __forceinline__ void dslash_site(const Src& src, const R* __restrict__ phi,
+                                            const Lat& lat, const Coef<R>& cf, const Nbr& nb,
+                                            int s, C2<R> (&out)[4], C2<R> (&cen)[4]) {
+    const int vol = lat.vol;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) cen[c] = src(c, s);
+    const int st = DAG ? nb.tm : nb.tp;
+    const R ts = R(DAG ? nb.sbwd : nb.sfwd);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int a = c >> 1;
+        const C2<R> hx = add<R>(src(c, nb.xp), src(c, nb.xm));
+        const C2<R> hy = add<R>(src(c, nb.yp), src(c, nb.ym));
+        const C2<R> tt = src(c, st);
+        C2<R> o = scl<R>(cf.diag[a], cen[c]);
+        o = axpy<R>(cf.hop[a][0], hx, o);
+        o = axpy<R>(cf.hop[a][1], hy, o);
+        o = axpy<R>(ts, tt, o);
+        out[c] = o;
+    }
+    const R g = cf.cpl * R(nb.stag);
+    const R q1 = g * phi[s], q2 = g * phi[vol + s], q3 = g * phi[2 * vol + s];
+    // (q1 - i q2) z and (q1 + i q2) z
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const C2<R> u = cen[2 * (1 - a)], w = cen[2 * (1 - a) + 1];
+        // spin up:   q3 u + (q1 - i q2) w
+        out[2 * a].x += q3 * u.x + q1 * w.x + q2 * w.y;
+        out[2 * a].y += q3 * u.y + q1 * w.y - q2 * w.x;
+        // spin down: (q1 + i q2) u - q3 w
+        out[2 * a + 1].x += q1 * u.x - q2 * u.y - q3 * w.x;
+        out[2 * a + 1].y += q1 * u.y + q2 * u.x - q3 * w.y;
+    }
+}
+
+template <typename R>
+struct SrcPlain {
+    const C2<R>* __restrict__ v;
+    int vol;
+    __device__ __forceinline__ C2<R> operator()(int c, int i) const { return v[c * vol + i]; }
+};
+
+// p_new = r + beta * p_old, formed at every stencil point
+template <typename R>
+struct SrcXpay {
+    const C2<R>* __restrict__ r;
+    const C2<R>* __restrict__ p;
+    R beta;
+    int vol;
+    __device__ __forceinline__ C2<R> operator()(int c, int i) const {
+        return axpy<R>(beta, p[c * vol + i], r[c * vol + i]);
+    }
+};
+
+// ------------------------------------------------------------------------------------
+// out_k = M in_k (or M^dagger), k < n.  When st is given, right-hand sides whose mode
+// is not in `filter` are skipped.
+template <typename R, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_apply(const C2<R>* __restrict__ in,
+                                                  C2<R>* __restrict__ out,
+                                                  const R* __restrict__ phi, Lat lat, Coef<R> cf,
+                                                  int nblk, const CgState* st, int filter) {
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const int k = logical / nblk, blk = logical - k * nblk;
+    if (st != nullptr && !((1 << st[k].mode) & filter)) return;
+    const int s = blk * kBlock + threadIdx.x;
+    if (s >= lat.vol) return;
+    const size_t off = size_t(k) * 4 * lat.vol;
+    SrcPlain<R> src{in + off, lat.vol};
+    const Nbr nb = neighbours(lat, s);
+    C2<R> o[4], cen[4];
+    dslash_site<R, DAG>(src, phi, lat, cf, nb, s, o, cen);
+    C2<R>* dst = out + off;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dst[c * lat.vol + s] = o[c];
+}
+
+// Vectors of one conjugate-gradient solve in the Krylov precision R.
+template <typename R>
+struct CgVecs {
+    C2<R>* r;       // residual
+    C2<R>* p0;      // direction, buffer 0
+    C2<R>* p1;      // direction, buffer 1
+    C2<R>* t;       // M p
+    C2<R>* x;       // solution accumulated in R (the caller's x in FP64 mode)
+};
+
+// CG step A (iteration k):  x += alpha_{k-1} p_{k-1};  p_k = r_k + beta_{k-1} p_{k-1};
+// t = M p_k;  |t|^2 = <p_k, M^dagger M p_k>.  The last workgroup sets alpha_k = |r|^2/|t|^2.
+// p is double-buffered because neighbouring sites read the old direction.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_cg_a(CgVecs<R> v, const R* __restrict__ phi, Lat lat,
+                                                 Coef<R> cf, int nblk, CgState* st,
+                                                 double* partial, unsigned* cnt) {
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const int k = logical / nblk, blk = logical - k * nblk;
+    CgState* S = st + k;
+    if (S->mode != CG_ACTIVE) return;
+    const R alpha = R(S->alpha), beta = R(S->beta);
+    const int pb = S->pbuf;
+    const size_t off = size_t(k) * 4 * lat.vol;
+    const C2<R>* pin = (pb ? v.p1 : v.p0) + off;
+    C2<R>* pout = (pb ? v.p0 : v.p1) + off;
+    const C2<R>* r = v.r + off;
+    const int s = blk * kBlock + threadIdx.x;
+    double part[1] = {0.0};
+    if (s < lat.vol) {
+        SrcXpay<R> src{r, pin, beta, lat.vol};
+        const Nbr nb = neighbours(lat, s);
+        C2<R> o[4], pn[4];
+        dslash_site<R, false>(src, phi, lat, cf, nb, s, o, pn);
+        C2<R>* x = v.x + off;
+        C2<R>* t = v.t + off;
+        R acc = R(0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = c * lat.vol + s;
+            x[i] = axpy<R>(alpha, pin[i], x[i]);
+            pout[i] = pn[c];
+            t[i] = o[c];
+            acc += norm2<R>(o[c]);
+        }
+        part[0] = double(acc);
+    }
+    if (grid_reduce<1>(part, partial + size_t(k) * nblk, 0, nblk, blk, cnt + k)) {
+        if (threadIdx.x == 0) {
+            const double tt = part[0];
+            S->alpha = 0.0;
+            S->pbuf = 1 - pb;
+            if (!(tt > 0.0) || !finite(tt)) {
+                S->mode = CG_FAILED;
+            } else {
+                S->alpha_cur = S->rr / tt;
+            }
+        }
+    }
+}
+
+// CG step B:  r -= alpha_k M^dagger t;  |r|^2.  The last workgroup sets beta_k, checks the
+// iterated residual against tol^2 |b|^2 and the iteration cap.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_cg_b(CgVecs<R> v, const R* __restrict__ phi, Lat lat,
+                                                 Coef<R> cf, int nblk, CgState* st,
+                                                 double* partial, unsigned* cnt) {
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const int k = logical / nblk, blk = logical - k * nblk;
+    CgState* S = st + k;
+    if (S->mode != CG_ACTIVE) return;
+    const R alpha = R(S->alpha_cur);
+    const size_t off = size_t(k) * 4 * lat.vol;
+    const int s = blk * kBlock + threadIdx.x;
+    double part[1] = {0.0};
+    if (s < lat.vol) {
+        SrcPlain<R> src{v.t + off, lat.vol};
+        const Nbr nb = neighbours(lat, s);
+        C2<R> o[4], cen[4];
+        dslash_site<R, true>(src, phi, lat, cf, nb, s, o, cen);
+        C2<R>* r = v.r + off;
+        R acc = R(0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = c * lat.vol + s;
+            const C2<R> rn = axpy<R>(-alpha, o[c], r[i]);
+            r[i] = rn;
+            acc += norm2<R>(rn);
+        }
+        part[0] = double(acc);
+    }
+    if (grid_reduce<1>(part, partial + size_t(k) * nblk, 0, nblk, blk, cnt + k)) {
+        if (threadIdx.x == 0) {
+            const double rr = part[0];
+            if (!finite(rr)) {
+                S->mode = CG_FAILED;
+            } else {
+                S->rr_prev = S->rr;
+                S->beta = rr / S->rr;
+                S->rr = rr;
+                S->alpha = S->alpha_cur;
+                S->iters += 1;
+                if (rr <= S->stop_rr) S->mode = CG_CONV_ITER;
+                else if (S->iters >= S->maxit) S->mode = CG_MAXIT;
+            }
+        }
+    }
+}
+
+// Reliable update, part 1 (elementwise): fold the pending step into the FP64 solution,
+// x64 += x_lo + alpha p (mixed) or x64 += alpha p (FP64, x_lo == nullptr), and clear x_lo.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_ru_fold(double2* __restrict__ x64, CgVecs<R> v,
+                                                    Lat lat, int nblk, const CgState* st,
+                                                    int filter) {
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const int k = logical / nblk, blk = logical - k * nblk;
+    const CgState* S = st + k;
+    if (!((1 << S->mode) & filter)) return;
+    const double alpha = S->alpha;
+    const size_t off = size_t(k) * 4 * lat.vol;
+    const C2<R>* p = (S->pbuf ? v.p1 : v.p0) + off;
+    const int s = blk * kBlock + threadIdx.x;
+    if (s >= lat.vol) return;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const size_t i = off + size_t(c) * lat.vol + s;
+        const C2<R> pc = p[c * lat.vol + s];
+        double2 xv = x64[i];
+        xv.x += alpha * double(pc.x);
+        xv.y += alpha * double(pc.y);
+        if (v.x != nullptr && (void*)v.x != (void*)x64) {
+            const C2<R> xl = v.x[i];
+            xv.x += double(xl.x);
+            xv.y += double(xl.y);
+            v.x[i] = mk<R>(R(0), R(0));
+        }
+        x64[i] = xv;
+    }
+}
+
+// Reliable update, part 3: r = b - M^dagger t64 in FP64 (t64 = M x64 from k_apply), stored
+// in the Krylov precision; |r|^2 in FP64.  The last workgroup records the true residual and
+// moves the right-hand side to DONE, STOPPED or back to ACTIVE (keeping p, with
+// beta = |r_true|^2 / |r_prev|^2).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_ru_resid(const double2* __restrict__ b,
+                                                     const double2* __restrict__ t64,
+                                                     const double* __restrict__ phi, Lat lat,
+                                                     Coef<double> cf, C2<R>* __restrict__ r,
+                                                     int nblk, CgState* st, int filter,
+                                                     double* partial, unsigned* cnt) {
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const int k = logical / nblk, blk = logical - k * nblk;
+    CgState* S = st + k;
+    const int mode = S->mode;
+    if (!((1 << mode) & filter)) return;
+    const size_t off = size_t(k) * 4 * lat.vol;
+    const int s = blk * kBlock + threadIdx.x;
+    double part[1] = {0.0};
+    if (s < lat.vol) {
+        SrcPlain<double> src{t64 + off, lat.vol};
+        const Nbr nb = neighbours(lat, s);
+        double2 o[4], cen[4];
+        dslash_site<double, true>(src, phi, lat, cf, nb, s, o, cen);
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const size_t i = off + size_t(c) * lat.vol + s;
+            const double2 rv = sub<double>(b[i], o[c]);
+            acc += norm2<double>(rv);
+            r[i] = mk<R>(R(rv.x), R(rv.y));
+        }
+        part[0] = acc;
+    }
+    if (grid_reduce<1>(part, partial + size_t(k) * nblk, 0, nblk, blk, cnt + k)) {
+        if (threadIdx.x == 0) {
+            const double rr = part[0];
+            S->rr_true = rr;
+            S->n_ru += 1;
+            S->alpha = 0.0;
+            if (!finite(rr)) {
+                S->mode = CG_FAILED;
+            } else if (rr <= S->stop_rr) {
+                S->mode = CG_DONE;
+            } else if (mode == CG_MAXIT) {
+                S->mode = CG_STOPPED;
+            } else {
+                S->beta = rr / S->rr_prev;
+                S->rr = rr;
+                S->mode = CG_ACTIVE;
+            }
+        }
+    }
+}
+
+// CG start from x = 0: x64 = 0, r = b, both direction buffers and x_lo cleared, |b|^2.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_cg_init(const double2* __restrict__ b,
+                                                    double2* __restrict__ x64, CgVecs<R> v,
+                                                    Lat lat, int nblk, CgState* st,
+                                                    double tol2, int maxit, double* partial,
+                                                    unsigned* cnt) {
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const int k = logical / nblk, blk = logical - k * nblk;
+    const int s = blk * kBlock + threadIdx.x;
+    double part[1] = {0.0};
+    if (s < lat.vol) {
+        const size_t off = size_t(k) * 4 * lat.vol;
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const size_t i = off + size_t(c) * lat.vol + s;
+            const double2 bv = b[i];
+            acc += norm2<double>(bv);
+            x64[i] = make_double2(0.0, 0.0);
+            v.r[i] = mk<R>(R(bv.x), R(bv.y));
+            v.p0[i] = mk<R>(R(0), R(0));
+            v.p1[i] = mk<R>(R(0), R(0));
+            if ((void*)v.x != (void*)x64) v.x[i] = mk<R>(R(0), R(0));
+        }
+        part[0] = acc;
+    }
+    if (grid_reduce<1>(part, partial + size_t(k) * nblk, 0, nblk, blk, cnt + k)) {
+        if (threadIdx.x == 0) {
+            CgState* S = st + k;
+            const double bb = part[0];
+            S->bb = bb;
+            S->stop_rr = tol2 * bb;
+            S->rr = bb;
+            S->rr_prev = bb;
+            S->alpha = 0.0;
+            S->alpha_cur = 0.0;
+            S->beta = 0.0;
+            S->rr_true = bb;
+            S->iters = 0;
+            S->pbuf = 0;
+            S->n_ru = 0;
+            S->maxit = maxit;
+            S->mode = !finite(bb) ? CG_FAILED : (bb > 0.0 ? CG_ACTIVE : CG_DONE);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Gradient dS/dphi at one site (FP64).  Pseudofermion part: for each solution x_k,
+// Y = M x_k at the site, then -2 dtau lambda (-1)^(x+y) Re[Y_bx^+ Pauli_l X_by + Y_by^+ Pauli_l X_bx]
+// (bx, by: the two bands, each a spin doublet).  Boson part: the derivative of the lattice
+// boson action, a 7-point Laplacian form plus mass and quartic terms.
+// Output: F written to `force` (if non-null) and/or `nkick` half kicks pi -= h F applied
+// one after another (the leapfrog's neighbouring half kicks kept separate).
+__device__ __forceinline__ void pauli_contract(double2 u0, double2 u1, double2 v0, double2 v1,
+                                               double& f1, double& f2, double& f3) {
+    // Re/Im of conj(a) b
+    const double re01 = u0.x * v1.x + u0.y * v1.y, im01 = u0.x * v1.y - u0.y * v1.x;
+    const double re10 = u1.x * v0.x + u1.y * v0.y, im10 = u1.x * v0.y - u1.y * v0.x;
+    const double re00 = u0.x * v0.x + u0.y * v0.y;
+    const double re11 = u1.x * v1.x + u1.y * v1.y;
+    f1 += re01 + re10;     // Pauli x
+    f2 += im01 - im10;     // Pauli y: Re(-i conj(u0) v1 + i conj(u1) v0)
+    f3 += re00 - re11;     // Pauli z
+}
+
+__global__ __launch_bounds__(kBlock) void k_force(const double2* __restrict__ x, int npf,
+                                                  const double* __restrict__ phi, Lat lat,
+                                                  Coef<double> cf, BosonCoef bc, int do_pf,
+                                                  int do_boson, double* __restrict__ force,
+                                                  double* __restrict__ pi, double h, int nkick) {
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int s = blk * kBlock + threadIdx.x;
+    if (s >= lat.vol) return;
+    const int vol = lat.vol;
+    const Nbr nb = neighbours(lat, s);
+    double F[3] = {0.0, 0.0, 0.0};
+    if (do_pf) {
+        double f1 = 0.0, f2 = 0.0, f3 = 0.0;
+        for (int k = 0; k < npf; ++k) {
+            SrcPlain<double> src{x + size_t(k) * 4 * vol, vol};
+            double2 Y[4], X[4];
+            dslash_site<double, false>(src, phi, lat, cf, nb, s, Y, X);
+            pauli_contract(Y[0], Y[1], X[2], X[3], f1, f2, f3);
+            pauli_contract(Y[2], Y[3], X[0], X[1], f1, f2, f3);
+        }
+        const double pre = -2.0 * cf.cpl * double(nb.stag);
+        F[0] = pre * f1;
+        F[1] = pre * f2;
+        F[2] = pre * f3;
+    }
+    if (do_boson) {
+        double p[3];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) p[l] = phi[l * vol + s];
+        const double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const double* f = phi + l * vol;
+            const double lt = 2.0 * p[l] - f[nb.tp] - f[nb.tm];
+            const double ls = 4.0 * p[l] - f[nb.xp] - f[nb.xm] - f[nb.yp] - f[nb.ym];
+            F[l] += bc.kt * lt + bc.ks * ls + bc.kr * p[l] + bc.ku * p2 * p[l];
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if (force != nullptr) force[l * vol + s] = F[l];
+        if (pi != nullptr) {
+            double pv = pi[l * vol + s];
+            for (int j = 0; j < nkick; ++j) pv = pv - h * F[l];
+            pi[l * vol + s] = pv;
+        }
+    }
+}
+
+// Kinetic energy 1/2 |pi|^2 and boson action S_B (Eq. 2 on the lattice) in one pass.
+// Results: out[0] = K, out[1] = S_B (written by the last workgroup).
+__global__ __launch_bounds__(kBlock) void k_energy(const double* __restrict__ pi,
+                                                   const double* __restrict__ phi, Lat lat,
+                                                   BosonCoef bc, double* out, double* partial,
+                                                   int stride, unsigned* cnt) {
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int nblk = gridDim.x;
+    const int s = blk * kBlock + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (s < lat.vol) {
+        const int vol = lat.vol;
+        const Nbr nb = neighbours(lat, s);
+        double kin = 0.0, st = 0.0, ss = 0.0, p2 = 0.0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const double* f = phi + l * vol;
+            const double c = f[s];
+            if (pi != nullptr) kin += pi[l * vol + s] * pi[l * vol + s];
+            const double dt = f[nb.tp] - c, dx = f[nb.xp] - c, dy = f[nb.yp] - c;
+            st += dt * dt;
+            ss += dx * dx + dy * dy;
+            p2 += c * c;
+        }
+        v[0] = 0.5 * kin;
+        v[1] = 0.5 * bc.kt * st + 0.5 * bc.ks * ss + 0.5 * bc.kr * p2 + 0.25 * bc.ku * p2 * p2;
+    }
+    if (grid_reduce<2>(v, partial, stride, nblk, blk, cnt)) {
+        if (threadIdx.x == 0) {
+            out[0] = v[0];
+            out[1] = v[1];
+        }
+    }
+}
+
+// sum_k Re <a_k, b_k> over n spinors (complex128).  out[0] receives the sum.
+__global__ __launch_bounds__(kBlock) void k_dot_re(const double2* __restrict__ a,
+                                                   const double2* __restrict__ b, int n, Lat lat,
+                                                   double* out, double* partial, unsigned* cnt) {
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int nblk = gridDim.x;
+    const int s = blk * kBlock + threadIdx.x;
+    double v[1] = {0.0};
+    if (s < lat.vol) {
+        for (int k = 0; k < n; ++k) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const size_t i = (size_t(k) * 4 + c) * lat.vol + s;
+                const double2 u = a[i], w = b[i];
+                v[0] += u.x * w.x + u.y * w.y;
+            }
+        }
+    }
+    if (grid_reduce<1>(v, partial, 0, nblk, blk, cnt)) {
+        if (threadIdx.x == 0) out[0] = v[0];
+    }
+}
+
+// phi += eps * pi (the leapfrog drift), elementwise over 3 * vol values.
+__global__ __launch_bounds__(kBlock) void k_drift(double* __restrict__ phi,
+                                                  const double* __restrict__ pi, double eps,
+                                                  int n) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) phi[i] = phi[i] + eps * pi[i];
+}
+
+// phi32 = (float) phi64
+__global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ a,
+                                                   float* __restrict__ b, int n) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) b[i] = float(a[i]);
+}
+
+// Zero a buffer of n 32-bit words (used instead of memset so the sequence stays
+// capturable).
+__global__ __launch_bounds__(kBlock) void k_zero_u32(unsigned* __restrict__ a, int n) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) a[i] = 0u;
+}
+
+}  // namespace hmc

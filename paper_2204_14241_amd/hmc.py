@@ -1,0 +1,239 @@
+"""Python binding of libhmc: argument marshalling only.
+
+Every numerical step runs in the HIP kernels behind the C ABI; this module checks
+shapes and dtypes, hands over device pointers and the current HIP stream, and owns the
+workspace tensor.  PyTorch serves as the device-memory and stream provider.
+
+Tensor conventions (see include/hmc.h):
+  phi     float64 (3, L_tau, L, L) on the GPU (float32 for the *_f32 calls)
+  spinors complex128 (n, 2, 2, L_tau, L, L) or (n, 4, L_tau, L, L); complex64 for *_f32
+"""
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import (HMC_FORCE_BOSON, HMC_FORCE_PF, HMC_FP64, HMC_MIXED, HmcCgStats, HmcParams,
+                   HmcTrajStats, check)
+
+DEFAULT_MODEL = dict(t=((1.0, 0.5), (0.5, 1.0)), mu=(0.5, 0.5), lam=1.0, r=0.0, c=1.0, u=0.0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+@dataclass
+class CgStats:
+    iterations: list
+    reliable_updates: list
+    true_resid: list
+    status: int
+
+
+def _cg_stats(s, n):
+    return CgStats(list(s.iterations[:n]), list(s.reliable_updates[:n]), list(s.true_resid[:n]),
+                   s.status)
+
+
+class HMC:
+    """One lattice context on the current CUDA (HIP) device."""
+
+    def __init__(self, L, Lt, dtau=0.1, model=None, eps=0.01, n_leap=10, n_pf=1, cg_tol=1e-10,
+                 cg_maxit=20000, precision="fp64", reliable_every=50, max_rhs=0, device=None):
+        self.lib = _lib.load()
+        self.L, self.Lt, self.dtau = int(L), int(Lt), float(dtau)
+        self.vol = self.Lt * self.L * self.L
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.model = dict(DEFAULT_MODEL, **(model or {}))
+        self._p = HmcParams()
+        self._fill(eps=eps, n_leap=n_leap, n_pf=n_pf, cg_tol=cg_tol, cg_maxit=cg_maxit,
+                   precision=precision, reliable_every=reliable_every, max_rhs=max_rhs)
+        self._ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(self.lib.hmc_create(self.L, self.Lt, self.dtau, ctypes.byref(self._p),
+                                      ctypes.byref(self._ctx)), "hmc_create")
+            nbytes = int(self.lib.hmc_workspace_bytes(self._ctx))
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) // 256 * 256
+            check(self.lib.hmc_set_workspace(self._ctx, ctypes.c_void_p(aligned), nbytes),
+                  "hmc_set_workspace")
+        self.capacity = self._p.max_rhs if self._p.max_rhs > 0 else max(self._p.n_pf, 1)
+
+    # ---------------------------------------------------------------- parameters
+    def _fill(self, eps, n_leap, n_pf, cg_tol, cg_maxit, precision, reliable_every, max_rhs):
+        m = self.model
+        p = self._p
+        for a in range(2):
+            for d in range(2):
+                p.t[a][d] = float(m["t"][a][d])
+            p.mu[a] = float(m["mu"][a])
+        p.lambda_ = float(m["lam"])
+        p.r, p.c, p.u = float(m["r"]), float(m["c"]), float(m["u"])
+        p.eps = float(eps)
+        p.n_leap = int(n_leap)
+        p.n_pf = int(n_pf)
+        p.cg_tol = float(cg_tol)
+        p.cg_maxit = int(cg_maxit)
+        p.precision = {"fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]
+        p.reliable_every = int(reliable_every)
+        p.max_rhs = int(max_rhs)
+
+    def set_params(self, **kw):
+        p = self._p
+        cur = dict(eps=p.eps, n_leap=p.n_leap, n_pf=p.n_pf, cg_tol=p.cg_tol, cg_maxit=p.cg_maxit,
+                   precision={HMC_FP64: "fp64", HMC_MIXED: "mixed"}[p.precision],
+                   reliable_every=p.reliable_every, max_rhs=p.max_rhs)
+        model = kw.pop("model", None)
+        if model:
+            self.model = dict(self.model, **model)
+        cur.update(kw)
+        self._fill(**cur)
+        check(self.lib.hmc_set_params(self._ctx, ctypes.byref(self._p)), "hmc_set_params")
+
+    @property
+    def precision(self):
+        return "mixed" if self._p.precision == HMC_MIXED else "fp64"
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self.lib.hmc_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- checks
+    def _phi(self, phi, dtype=torch.float64):
+        if phi.dtype != dtype or phi.device != self.device or not phi.is_contiguous():
+            raise ValueError(f"phi must be a contiguous {dtype} tensor on {self.device}")
+        if tuple(phi.shape) != (3, self.Lt, self.L, self.L):
+            raise ValueError(f"phi shape {tuple(phi.shape)} != (3, {self.Lt}, {self.L}, {self.L})")
+        return phi
+
+    def _spinors(self, v, dtype=torch.complex128):
+        if v.dtype != dtype or v.device != self.device or not v.is_contiguous():
+            raise ValueError(f"spinors must be contiguous {dtype} tensors on {self.device}")
+        if v.numel() % (4 * self.vol) or v.numel() == 0:
+            raise ValueError("spinor tensor size is not a positive multiple of 4*L_tau*L*L")
+        return v, v.numel() // (4 * self.vol)
+
+    def _call(self, name, *args):
+        check(getattr(self.lib, name)(self._ctx, *args), name)
+
+    # ---------------------------------------------------------------- operators
+    def _apply(self, name, phi, psi, f32=False):
+        cdt, rdt = (torch.complex64, torch.float32) if f32 else (torch.complex128, torch.float64)
+        self._phi(phi, rdt)
+        psi, n = self._spinors(psi, cdt)
+        out = torch.empty_like(psi)
+        self._call(name, _ptr(phi), _ptr(psi), _ptr(out), n, _stream())
+        return out
+
+    def apply_M(self, phi, psi):
+        return self._apply("hmc_apply_M", phi, psi)
+
+    def apply_Mdag(self, phi, psi):
+        return self._apply("hmc_apply_Mdag", phi, psi)
+
+    def apply_MdagM(self, phi, psi):
+        return self._apply("hmc_apply_MdagM", phi, psi)
+
+    def apply_M_f32(self, phi32, psi):
+        return self._apply("hmc_apply_M_f32", phi32, psi, True)
+
+    def apply_Mdag_f32(self, phi32, psi):
+        return self._apply("hmc_apply_Mdag_f32", phi32, psi, True)
+
+    def apply_MdagM_f32(self, phi32, psi):
+        return self._apply("hmc_apply_MdagM_f32", phi32, psi, True)
+
+    def apply_into(self, name, phi, psi, out, n):
+        """Raw launch for benchmarks: no allocation, no checks beyond the library's."""
+        self._call(name, _ptr(phi), _ptr(psi), _ptr(out), n, _stream())
+
+    # ---------------------------------------------------------------- solver and HMC
+    def cg_solve(self, phi, b, x=None):
+        self._phi(phi)
+        b, n = self._spinors(b)
+        if x is None:
+            x = torch.empty_like(b)
+        st = HmcCgStats()
+        code = self.lib.hmc_cg_solve(self._ctx, _ptr(phi), _ptr(b), _ptr(x), n, ctypes.byref(st), _stream())
+        if code not in (_lib.HMC_OK, _lib.HMC_ERR_NOT_CONVERGED):
+            check(code, "hmc_cg_solve")
+        return x, _cg_stats(st, n)
+
+    def heatbath(self, phi, eta):
+        return self._apply("hmc_heatbath", phi, eta)
+
+    def force(self, phi, chi=None, flags=HMC_FORCE_PF | HMC_FORCE_BOSON):
+        self._phi(phi)
+        n = 0
+        if flags & HMC_FORCE_PF:
+            chi, n = self._spinors(chi)
+        F = torch.empty_like(phi)
+        S = ctypes.c_double(0.0)
+        st = HmcCgStats()
+        self._call("hmc_force", _ptr(phi), _ptr(chi) if chi is not None else None, n, _ptr(F),
+                   ctypes.byref(S), flags, ctypes.byref(st), _stream())
+        return F, S.value, _cg_stats(st, n)
+
+    def force_from_solution(self, phi, x, flags=HMC_FORCE_PF):
+        self._phi(phi)
+        x, n = self._spinors(x)
+        F = torch.empty_like(phi)
+        self._call("hmc_force_from_solution", _ptr(phi), _ptr(x), n, _ptr(F), flags, _stream())
+        return F
+
+    def pf_action(self, phi, chi, x=None):
+        self._phi(phi)
+        chi, n = self._spinors(chi)
+        S = ctypes.c_double(0.0)
+        st = HmcCgStats()
+        self._call("hmc_pf_action", _ptr(phi), _ptr(chi), n, _ptr(x), ctypes.byref(S),
+                   ctypes.byref(st), _stream())
+        return S.value, _cg_stats(st, n)
+
+    def boson_action(self, phi):
+        self._phi(phi)
+        S = ctypes.c_double(0.0)
+        self._call("hmc_boson_action", _ptr(phi), ctypes.byref(S), _stream())
+        return S.value
+
+    def trajectory(self, phi, pi0, eta, u):
+        """One trajectory; phi is updated in place.  Returns the stats as a dict."""
+        self._phi(phi)
+        self._phi(pi0)
+        n = 0
+        if eta is not None and eta.numel() > 0:
+            eta, n = self._spinors(eta)
+        st = HmcTrajStats()
+        code = self.lib.hmc_trajectory(self._ctx, _ptr(phi), _ptr(pi0), _ptr(eta) if n else None,
+                                       n, float(u), ctypes.byref(st), _stream())
+        out = {f: getattr(st, f) for f, _ in HmcTrajStats._fields_}
+        out["code"] = code
+        if code != _lib.HMC_OK:
+            check(code, "hmc_trajectory")
+        return out
+
+
+def test_site(L, Lt, s):
+    """Host-side lattice geometry of the kernels (no GPU needed)."""
+    lib = _lib.load()
+    out = (ctypes.c_int * 12)()
+    rc = lib.hmc_test_site(L, Lt, s, out)
+    return None if rc else list(out)
+
+
+def test_xcd_remap(bid, nb):
+    return _lib.load().hmc_test_xcd_remap(bid, nb)
