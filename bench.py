@@ -1,0 +1,289 @@
+#!/usr/bin/env python
+"""Benchmark of the HMC hot path on one MI355X.
+
+A step is one full HMC trajectory at 80 x 80 x 200 (dtau 0.1, one pseudofermion, 20
+leapfrog steps): pseudofermion heat-bath, 21 conjugate-gradient solves of
+(M^dagger M) x = chi in mixed precision (FP32 Krylov iterations, FP64 reliable update
+every 50 iterations, FP64 true residual <= 1e-10), the FP64 gradient and leapfrog
+updates, and the Metropolis decision.  Inputs (phi ~ N(0, 0.5), momenta, pseudofermion
+noise, uniforms) are drawn from a seed and moved to HBM before the timed region.
+
+value = M^dagger M applies per second inside the timed trajectories (one apply per CG
+iteration).  Also reported: trajectories/h for the mixed form and for plain FP64 on the
+same seeds, the isolated two-pass M^dagger M apply rate and GB/s with buffers rotated
+through more than 512 MB (so the 256 MB MALL cannot serve them), the roofline of the
+dominant kernel from live HIP-event samples, and the FP64 oracle timed on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "M^dag M applies/s + HBM GB/s at 80x80x200; HMC traj/h mixed vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per lattice site of each kernel (each vector counted once per pass).
+# A spinor is 4 complex numbers per site (64 B in FP64, 32 B in FP32); phi is 3 reals.
+BYTES_PER_SITE = {
+    # t = M p_new with p_new = r + beta p_old, x += alpha p_old: reads r, p_old, x, phi;
+    # writes p_new, t, x
+    "cg_a_f32": 6 * 32 + 12,
+    "cg_a_f64": 6 * 64 + 24,
+    # r -= alpha M^dagger t: reads t, r, phi; writes r
+    "cg_b_f32": 3 * 32 + 12,
+    "cg_b_f64": 3 * 64 + 24,
+    # one M or M^dagger apply: reads psi, phi; writes psi
+    "apply_f32": 2 * 32 + 12,
+    "apply_f64": 2 * 64 + 24,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--workload", default="large_80x80x200")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--apply-reps", type=int, default=40)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed mixed trajectories (for profiler runs)")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="short fixed sequence for counter runs: a 512 MiB device copy (the "
+                         "byte-counter calibration), FP32/FP64 M and M^dagger applies and 60 "
+                         "mixed-precision CG iterations at the workload size")
+    return ap.parse_args()
+
+
+def profile_kernels(args):
+    """A short, fixed kernel sequence for rocprofv3 counter collection."""
+    import torch
+    import synth_inputs as S
+    from paper_2204_14241_amd import hmc as hmcmod
+    cfg = S.WORKLOADS[args.workload]
+    L, Lt = cfg["L"], cfg["Lt"]
+    dev = torch.device("cuda")
+    a = torch.empty(512 * 2 ** 20, dtype=torch.uint8, device=dev).fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)                      # reads 512 MiB, writes 512 MiB
+    del a, b
+    g = S.rng(args.seed)
+    phi = torch.from_numpy(S.draw_phi(g, L, Lt, cfg["phi_var"])).to(dev)
+    psi = torch.from_numpy(S.draw_spinor(g, L, Lt, 1)).to(dev)
+    h = hmcmod.HMC(L, Lt, precision="mixed", cg_maxit=60, reliable_every=50)
+    phi32, psi32 = phi.float(), psi.to(torch.complex64)
+    out32, out64 = torch.empty_like(psi32), torch.empty_like(psi)
+    for _ in range(3):
+        h.apply_into("hmc_apply_M_f32", phi32, psi32, out32, 1)
+        h.apply_into("hmc_apply_Mdag_f32", phi32, psi32, out32, 1)
+        h.apply_into("hmc_apply_M", phi, psi, out64, 1)
+        h.apply_into("hmc_apply_Mdag", phi, psi, out64, 1)
+    x, st = h.cg_solve(phi, psi)
+    torch.cuda.synchronize()
+    log(f"profile sequence done: cg iterations {st.iterations}")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_info():
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def apply_bench(hmcmod, torch, L, Lt, f32, reps, seed):
+    """Isolated two-pass M^dagger M: M then M^dagger through the C ABI, buffer sets rotated
+    so their combined footprint exceeds 512 MB.  Returns (applies/s, GB/s, ms/apply)."""
+    import numpy as np
+    import synth_inputs as S
+    dev = torch.device("cuda")
+    vol = Lt * L * L
+    cdt, rdt = (torch.complex64, torch.float32) if f32 else (torch.complex128, torch.float64)
+    set_bytes = vol * (3 * 4 * (8 if f32 else 16) + 3 * (4 if f32 else 8))
+    nsets = max(3, int(np.ceil(600e6 / set_bytes)))
+    h = hmcmod.HMC(L, Lt)
+    g = S.rng(seed)
+    sets = []
+    for _ in range(nsets):
+        phi = torch.from_numpy(S.draw_phi(g, L, Lt, 0.5)).to(dev, rdt)
+        psi = torch.from_numpy(S.draw_spinor(g, L, Lt, 1)).to(dev, cdt)
+        sets.append((phi, psi, torch.empty_like(psi), torch.empty_like(psi)))
+    nm, nd = ("hmc_apply_M_f32", "hmc_apply_Mdag_f32") if f32 else ("hmc_apply_M", "hmc_apply_Mdag")
+
+    def one(i):
+        phi, psi, tmp, out = sets[i % nsets]
+        h.apply_into(nm, phi, psi, tmp, 1)
+        h.apply_into(nd, phi, tmp, out, 1)
+
+    for i in range(2 * nsets):
+        one(i)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        one(i)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    bps = 2 * BYTES_PER_SITE["apply_f32" if f32 else "apply_f64"] * vol
+    h.close()
+    return 1e3 / ms, bps / (ms * 1e-3) / 1e9, ms, nsets
+
+
+def cpu_baseline(L, Lt, seed, budget_s=15.0):
+    """The FP64 oracle's M^dagger M apply on the host (NumPy, one thread), bounded sample."""
+    import oracle as O
+    import synth_inputs as S
+    m = O.Model(L=L, Lt=Lt)
+    g = S.rng(seed)
+    phi = S.draw_phi(g, L, Lt, 0.5)
+    psi = S.draw_spinor(g, L, Lt, 1)[0]
+    O.apply_MdagM(m, phi, psi)             # warm-up (page faults of first use)
+    n, t0 = 0, time.perf_counter()
+    while True:
+        O.apply_MdagM(m, phi, psi)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 50:
+            break
+    return dict(value=n / el, unit="M^dag M applies/s", cores=1, kind="oracle",
+                sample=f"{n} FP64 oracle M^dag M applies at {L}x{L}x{Lt} ({el:.1f} s, NumPy, 1 thread)")
+
+
+def main():
+    args = parse()
+    if args.profile_kernels:
+        profile_kernels(args)
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: the one-GPU build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth_inputs as S
+    from paper_2204_14241_amd import hmc as hmcmod
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    cfg = S.WORKLOADS[args.workload]
+    L, Lt, n_pf, n_leap, eps = cfg["L"], cfg["Lt"], cfg["n_pf"], cfg["n_leap"], cfg["eps"]
+    vol = Lt * L * L
+    dev = torch.device("cuda")
+    K, W = args.steps, args.warmup
+    nt = W + max(K, args.fp64_steps)
+    phi0, trajs = S.hmc_inputs(args.seed, L, Lt, cfg["phi_var"], n_pf, n_traj=nt)
+    d_traj = [(torch.from_numpy(p).to(dev), torch.from_numpy(e).to(dev), u) for p, e, u in trajs]
+    common = dict(eps=eps, n_leap=n_leap, n_pf=n_pf, cg_tol=1e-10, cg_maxit=20000,
+                  reliable_every=50, max_rhs=n_pf)
+
+    def run(precision, nsteps, nwarm, timing=False):
+        h = hmcmod.HMC(L, Lt, precision=precision, **common)
+        phi = torch.from_numpy(phi0).to(dev)
+        for i in range(nwarm):
+            p, e, u = d_traj[i]
+            h.trajectory(phi, p, e, u)
+        if timing:
+            h.set_kernel_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = []
+        for i in range(nwarm, nwarm + nsteps):
+            p, e, u = d_traj[i]
+            out.append(h.trajectory(phi, p, e, u))
+            log(f"[{precision}] trajectory {i}: dH {out[-1]['dH']:.6g} acc {out[-1]['accepted']} "
+                f"cg iters {out[-1]['cg_iterations']} max resid {out[-1]['max_true_resid']:.2e}")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kt = h.kernel_times() if timing else None
+        h.close()
+        return el, out, kt
+
+    log(f"mixed-precision trajectories at {L}x{L}x{Lt}: warmup {W}, timed {K}")
+    el, out, kt = run("mixed", K, W, timing=True)
+    iters = sum(o["cg_iterations"] for o in out)
+    value = iters / el
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "M^dag M applies/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * el / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "L": L, "L_tau": Lt, "dtau": 0.1, "n_pf": n_pf,
+                   "n_leap": n_leap, "eps": eps, "precision": "mixed", "reliable_every": 50,
+                   "cg_tol": 1e-10, "phi": f"N(0,{cfg['phi_var']})", "seed": args.seed},
+    }
+    # roofline of the dominant kernel from the live samples
+    dom = max(("cg_a_f32", "cg_b_f32"), key=lambda n: (kt[n][0] or 0.0))
+    ms_dom, nsamp = kt[dom]
+    if ms_dom:
+        bytes_launch = BYTES_PER_SITE[dom] * vol
+        ach = bytes_launch / (ms_dom * 1e-3) / 1e9
+        result["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                              "kernel": {"cg_a_f32": "hmc::k_cg_a<float>", "cg_b_f32": "hmc::k_cg_b<float>"}[dom],
+                              "avg_ms": ms_dom, "samples": nsamp,
+                              "bytes_per_launch": bytes_launch}
+    extras = {
+        "traj_per_hour_mixed": 3600.0 * K / el,
+        "cg_iterations_per_traj_mixed": iters / K,
+        "dH_mixed": [o["dH"] for o in out],
+        "accepted_mixed": [o["accepted"] for o in out],
+        "max_true_resid_mixed": max(o["max_true_resid"] for o in out),
+        "kernel_ms": {k: v[0] for k, v in kt.items() if v[0]},
+    }
+    if kt.get("cg_a_f32")[0] and kt.get("cg_b_f32")[0]:
+        it_ms = kt["cg_a_f32"][0] + kt["cg_b_f32"][0]
+        extras["cg_iteration_f32"] = {"ms": it_ms, "GB/s": (BYTES_PER_SITE["cg_a_f32"] + BYTES_PER_SITE["cg_b_f32"]) * vol / (it_ms * 1e-3) / 1e9}
+    if not args.no_extras:
+        if args.fp64_steps > 0:
+            log("plain FP64 trajectories on the same seeds")
+            el64, out64, _ = run("fp64", args.fp64_steps, W)
+            extras["traj_per_hour_fp64"] = 3600.0 * args.fp64_steps / el64
+            extras["cg_iterations_per_traj_fp64"] = sum(o["cg_iterations"] for o in out64) / args.fp64_steps
+            extras["dH_fp64"] = [o["dH"] for o in out64]
+            extras["mixed_vs_fp64_traj_speedup"] = extras["traj_per_hour_mixed"] / extras["traj_per_hour_fp64"]
+        for f32 in (True, False):
+            aps, gbs, ms, nsets = apply_bench(hmcmod, torch, L, Lt, f32, args.apply_reps, args.seed + 1)
+            extras["mdagm_apply_" + ("f32" if f32 else "f64")] = {
+                "applies_per_s": aps, "GB/s": gbs, "ms": ms, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
+                "buffer_sets": nsets, "bytes_per_site": 2 * BYTES_PER_SITE["apply_f32" if f32 else "apply_f64"]}
+            log(f"isolated M^dag M {'f32' if f32 else 'f64'}: {aps:.0f} applies/s, {gbs:.0f} GB/s")
+        if not args.no_cpu:
+            model, ncpu = cpu_info()
+            result["cpu_baseline"] = cpu_baseline(L, Lt, args.seed)
+            result["cpu_baseline"]["host"] = f"{model}, {ncpu} logical CPUs"
+    result["extras"] = extras
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

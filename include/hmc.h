@@ -192,6 +192,27 @@ int hmc_boson_action(hmc_ctx* ctx, const double* phi, double* S, void* stream);
 int hmc_trajectory(hmc_ctx* ctx, double* phi_inout, const double* pi0, const void* eta,
                    int n_pf, double u_uniform, hmc_traj_stats* stats, void* stream);
 
+/* Sampled kernel timing, for measuring the solver kernels inside real work.  When
+ * enabled, the CG driver brackets the first iteration of every status chunk in which all
+ * right-hand sides are still iterating with HIP events on the caller's stream, and adds
+ * the two kernel durations to the accumulators below.  Enabling resets them.
+ * Index: [0] CG step A (t = M p with the fused x and p updates), FP32 Krylov precision;
+ * [1] CG step B (r -= alpha M^dagger t), FP32; [2] step A, FP64; [3] step B, FP64. */
+typedef struct hmc_kernel_times {
+    double ms[4];        /* summed durations in milliseconds                              */
+    long   count[4];     /* number of sampled launches                                    */
+} hmc_kernel_times;
+
+int hmc_set_kernel_timing(hmc_ctx* ctx, int enable);
+
+/* Launch shape of the CG kernels: at most max_per_rhs workgroups per right-hand side
+ * (1..4096; default 1024), each sweeping a contiguous range of 256-site tiles.  Results
+ * do not depend on it beyond the order of the FP64 partial sums.  hmc_get_cg_workgroups
+ * returns the count in use (the request rounded so that no workgroup is idle). */
+int hmc_set_cg_workgroups(hmc_ctx* ctx, int max_per_rhs);
+int hmc_get_cg_workgroups(const hmc_ctx* ctx);
+int hmc_get_kernel_times(const hmc_ctx* ctx, hmc_kernel_times* out);
+
 /* Text for an HMC_* code. */
 const char* hmc_strerror(int code);
 

@@ -26,6 +26,8 @@ EXPORTED = [
     "hmc_apply_MdagM_f32", "hmc_cg_solve", "hmc_heatbath", "hmc_force",
     "hmc_force_from_solution", "hmc_pf_action", "hmc_boson_action", "hmc_trajectory",
     "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap",
+    "hmc_set_kernel_timing", "hmc_get_kernel_times", "hmc_set_cg_workgroups",
+    "hmc_get_cg_workgroups",
 ]
 
 
@@ -73,6 +75,12 @@ class HmcTrajStats(ctypes.Structure):
     ]
 
 
+class HmcKernelTimes(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 4), ("count", ctypes.c_long * 4)]
+
+
+KT_NAMES = ("cg_a_f32", "cg_b_f32", "cg_a_f64", "cg_b_f64")
+
 _lib = None
 
 
@@ -111,6 +119,10 @@ def load():
         "hmc_last_error": (ctypes.c_char_p, []),
         "hmc_test_site": (I, [I, I, I, ctypes.POINTER(ctypes.c_int)]),
         "hmc_test_xcd_remap": (I, [I, I]),
+        "hmc_set_kernel_timing": (I, [P, I]),
+        "hmc_get_kernel_times": (I, [P, ctypes.POINTER(HmcKernelTimes)]),
+        "hmc_set_cg_workgroups": (I, [P, I]),
+        "hmc_get_cg_workgroups": (I, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -50,6 +50,8 @@ size_t align_up(size_t n, size_t a) { return (n + a - 1) / a * a; }
 
 constexpr int kCheckEvery = 32;     // FP64 CG: iterations between host status reads
 constexpr int kSlots = 32;          // device scalars (energies, actions)
+constexpr int kDefaultBpr = 1024;   // default CG workgroups per right-hand side
+constexpr int kMaxBpr = 4096;       // largest accepted (sizes the partial-sum buffer)
 
 // Slot indices in the device scalar area.
 enum Slot : int {
@@ -65,7 +67,10 @@ struct hmc_ctx {
     double dtau = 0.0;
     hmc_params p{};
     int cap = 1;            // right-hand sides the workspace holds
-    int nblk = 0;           // workgroups per right-hand side
+    int nblk = 0;           // 256-site tiles per right-hand side
+    int bpr = 0;            // CG workgroups per right-hand side
+    int tpb = 0;            // tiles per CG workgroup
+    int seq = 0;            // CG launch counter (selects the state record buffer)
     Lat lat{};
     Coef<double> cf64{};
     Coef<float> cf32{};
@@ -76,9 +81,9 @@ struct hmc_ctx {
     size_t ws_bytes = 0;
     size_t need = 0;
     // carved pointers
-    CgState* st = nullptr;
-    unsigned* cnt = nullptr;     // cap + 1 counters (the last for generic reductions)
-    double* partial = nullptr;   // max(cap, 2) * nblk
+    CgState* st = nullptr;       // 2 * cap records (double-buffered by launch parity)
+    double* part = nullptr;      // CG partial sums: 4 kinds * cap * bpr
+    double* gpart = nullptr;     // generic reductions: 2 * nblk
     double* slots = nullptr;
     double2 *r64 = nullptr, *p064 = nullptr, *p164 = nullptr, *t64 = nullptr;
     float2 *r32 = nullptr, *p032 = nullptr, *p132 = nullptr, *t32 = nullptr, *x32 = nullptr;
@@ -90,6 +95,11 @@ struct hmc_ctx {
     CgState* h_st = nullptr;     // 2 * cap records (double buffer)
     double* h_slots = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
+
+    // sampled kernel timing (timing-enabled events, one triple per status slot)
+    bool timing = false;
+    hipEvent_t tev[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    hmc_kernel_times kt{};
 };
 
 // --------------------------------------------------------------------------------------
@@ -172,19 +182,38 @@ template <> struct KrylovBufs<float> {
 
 static bool finished(int mode) { return mode == CG_DONE || mode == CG_STOPPED || mode == CG_FAILED; }
 
-// Enqueue the reliable-update / true-residual sequence for right-hand sides in `filter`.
+// Control block for the next CG launch; advances the state-record parity.
+static CgCtl next_ctl(hmc_ctx* c) {
+    CgCtl k;
+    k.st_in = c->st + size_t(c->seq & 1) * c->cap;
+    k.st_out = c->st + size_t((c->seq + 1) & 1) * c->cap;
+    k.part = c->part;
+    k.cap = c->cap;
+    k.bpr = c->bpr;
+    k.tpb = c->tpb;
+    k.ntiles = c->nblk;
+    c->seq += 1;
+    return k;
+}
+
+static const CgState* current_states(const hmc_ctx* c) { return c->st + size_t(c->seq & 1) * c->cap; }
+
+// Enqueue the reliable-update / true-residual sequence for right-hand sides in `filter`,
+// then reduce what is pending so the published records are complete.
 template <typename R>
 static int enqueue_ru(hmc_ctx* c, const double* phi64, const double2* b, double2* x, int n,
                       int filter, hipStream_t s) {
     CgVecs<R> v = KrylovBufs<R>::get(c, x);
-    const int g = grid_for(c, n);
-    hipLaunchKernelGGL(k_ru_fold<R>, dim3(g), dim3(kBlock), 0, s, x, v, c->lat, c->nblk, c->st, filter);
+    const int g = c->bpr * n;
+    hipLaunchKernelGGL(k_ru_fold<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c), x, v, c->lat, filter);
     LAUNCHCHK();
-    hipLaunchKernelGGL((k_apply<double, false>), dim3(g), dim3(kBlock), 0, s, x, c->t64, phi64,
-                       c->lat, c->cf64, c->nblk, c->st, filter);
+    hipLaunchKernelGGL(k_ru_apply, dim3(g), dim3(kBlock), 0, s, next_ctl(c), x, c->t64, phi64,
+                       c->lat, c->cf64, filter);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_ru_resid<R>, dim3(g), dim3(kBlock), 0, s, b, c->t64, phi64, c->lat,
-                       c->cf64, v.r, c->nblk, c->st, filter, c->partial, c->cnt);
+    hipLaunchKernelGGL(k_ru_resid<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c), b, c->t64, phi64,
+                       c->lat, c->cf64, v.r, filter);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_cg_finalize, dim3(n), dim3(kBlock), 0, s, next_ctl(c));
     LAUNCHCHK();
     return HMC_OK;
 }
@@ -196,15 +225,16 @@ static int cg_run(hmc_ctx* c, const double* phi64, const double2* b, double2* x,
     CgVecs<R> v = KrylovBufs<R>::get(c, x);
     const R* phik = KrylovBufs<R>::phi(c, phi64);
     const Coef<R> cf = KrylovBufs<R>::cf(c);
-    const int g = grid_for(c, n);
+    const int g = c->bpr * n;
     if (mixed) {
         hipLaunchKernelGGL(k_to_f32, dim3(elem_grid(3LL * c->vol)), dim3(kBlock), 0, s, phi64,
                            c->phi32, 3 * c->vol);
         LAUNCHCHK();
     }
     const double tol = c->p.cg_tol;
-    hipLaunchKernelGGL(k_cg_init<R>, dim3(g), dim3(kBlock), 0, s, b, x, v, c->lat, c->nblk,
-                       c->st, tol * tol, c->p.cg_maxit, c->partial, c->cnt);
+    c->seq = 0;
+    hipLaunchKernelGGL(k_cg_init<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c), b, x, v, c->lat,
+                       tol * tol, c->p.cg_maxit);
     LAUNCHCHK();
 
     const int chunk = mixed ? c->p.reliable_every : kCheckEvery;
@@ -213,27 +243,47 @@ static int cg_run(hmc_ctx* c, const double* phi64, const double2* b, double2* x,
     int issued = 0;
     int k = 0;
     bool have_prev = false;
+    const int kt_a = mixed ? 0 : 2;
+    bool start_active_prev = true;   // were all right-hand sides iterating when chunk k-1 began
     // Chunks are issued one ahead of the status read, so the GPU never idles on the host;
     // once every right-hand side is finished the remaining launches return at once.
     for (;;) {
         for (int i = 0; i < chunk; ++i) {
-            hipLaunchKernelGGL(k_cg_a<R>, dim3(g), dim3(kBlock), 0, s, v, phik, c->lat, cf,
-                               c->nblk, c->st, c->partial, c->cnt);
+            const bool sample = c->timing && i == chunk / 2;
+            if (sample) HIPCHK(hipEventRecord(c->tev[k & 1][0], s));
+            hipLaunchKernelGGL(k_cg_a<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c), v, phik, c->lat, cf);
             LAUNCHCHK();
-            hipLaunchKernelGGL(k_cg_b<R>, dim3(g), dim3(kBlock), 0, s, v, phik, c->lat, cf,
-                               c->nblk, c->st, c->partial, c->cnt);
+            if (sample) HIPCHK(hipEventRecord(c->tev[k & 1][1], s));
+            hipLaunchKernelGGL(k_cg_b<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c), v, phik, c->lat, cf);
             LAUNCHCHK();
+            if (sample) HIPCHK(hipEventRecord(c->tev[k & 1][2], s));
         }
         issued += chunk;
         int rc = enqueue_ru<R>(c, phi64, b, x, n, ru_filter, s);
         if (rc) return rc;
-        HIPCHK(hipMemcpyAsync(c->h_st + (k & 1) * c->cap, c->st, st_bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(c->h_st + (k & 1) * c->cap, current_states(c), st_bytes,
+                              hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(c->ev[k & 1], s));
         if (have_prev) {
             HIPCHK(hipEventSynchronize(c->ev[(k - 1) & 1]));
             const CgState* hs = c->h_st + ((k - 1) & 1) * c->cap;
-            bool all = true;
-            for (int j = 0; j < n; ++j) all = all && finished(hs[j].mode);
+            bool all = true, all_active = true;
+            for (int j = 0; j < n; ++j) {
+                all = all && finished(hs[j].mode);
+                all_active = all_active && hs[j].mode == CG_ACTIVE;
+            }
+            // chunk k-1 began in the state chunk k-2 ended in; if every right-hand side was
+            // iterating then and is still iterating at its end, its mid-chunk sample did full work
+            if (c->timing && start_active_prev && all_active) {
+                float ta = 0.f, tb = 0.f;
+                HIPCHK(hipEventElapsedTime(&ta, c->tev[(k - 1) & 1][0], c->tev[(k - 1) & 1][1]));
+                HIPCHK(hipEventElapsedTime(&tb, c->tev[(k - 1) & 1][1], c->tev[(k - 1) & 1][2]));
+                c->kt.ms[kt_a] += ta;
+                c->kt.ms[kt_a + 1] += tb;
+                c->kt.count[kt_a] += 1;
+                c->kt.count[kt_a + 1] += 1;
+            }
+            start_active_prev = all_active;
             if (all) break;
         }
         have_prev = true;
@@ -241,7 +291,7 @@ static int cg_run(hmc_ctx* c, const double* phi64, const double2* b, double2* x,
         // the device enforces cg_maxit; this bound only guards the host loop
         if (issued > c->p.cg_maxit + 4 * chunk) break;
     }
-    HIPCHK(hipMemcpyAsync(c->h_st, c->st, st_bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(c->h_st, current_states(c), st_bytes, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     int status = HMC_OK;
     for (int j = 0; j < n; ++j) {
@@ -278,6 +328,58 @@ static void merge_stats(hmc_traj_stats* t, const hmc_cg_stats& cs) {
         t->cg_iterations += cs.iterations[j];
         if (cs.true_resid[j] > t->max_true_resid) t->max_true_resid = cs.true_resid[j];
     }
+}
+
+// Workspace layout: one walk that either only measures (base == nullptr) or also
+// assigns the carved pointers.  Returns the bytes needed.
+static size_t ws_layout(hmc_ctx* c, char* base) {
+    const size_t V = size_t(c->vol);
+    const size_t sp64 = 4 * V * sizeof(double2), sp32 = 4 * V * sizeof(float2);
+    const size_t cap = size_t(c->cap);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off = align_up(off + bytes, 256);
+        return p;
+    };
+    char* st = take(sizeof(CgState) * 2 * cap);
+    char* part = take(sizeof(double) * 4 * cap * size_t(kMaxBpr));
+    char* gpart = take(sizeof(double) * 2 * size_t(c->nblk));
+    char* slots = take(sizeof(double) * kSlots);
+    char* v64 = take(4 * cap * sp64);
+    char* v32 = take(5 * cap * sp32);
+    char* tr = take(2 * cap * sp64);
+    char* bos = take(2 * 3 * V * sizeof(double));
+    char* f32 = take(3 * V * sizeof(float));
+    if (base) {
+        c->st = reinterpret_cast<CgState*>(st);
+        c->part = reinterpret_cast<double*>(part);
+        c->gpart = reinterpret_cast<double*>(gpart);
+        c->slots = reinterpret_cast<double*>(slots);
+        c->r64 = reinterpret_cast<double2*>(v64);
+        c->p064 = reinterpret_cast<double2*>(v64 + cap * sp64);
+        c->p164 = reinterpret_cast<double2*>(v64 + 2 * cap * sp64);
+        c->t64 = reinterpret_cast<double2*>(v64 + 3 * cap * sp64);
+        c->r32 = reinterpret_cast<float2*>(v32);
+        c->p032 = reinterpret_cast<float2*>(v32 + cap * sp32);
+        c->p132 = reinterpret_cast<float2*>(v32 + 2 * cap * sp32);
+        c->t32 = reinterpret_cast<float2*>(v32 + 3 * cap * sp32);
+        c->x32 = reinterpret_cast<float2*>(v32 + 4 * cap * sp32);
+        c->chi = reinterpret_cast<double2*>(tr);
+        c->xsol = reinterpret_cast<double2*>(tr + cap * sp64);
+        c->pi = reinterpret_cast<double*>(bos);
+        c->phi_save = reinterpret_cast<double*>(bos + 3 * V * sizeof(double));
+        c->phi32 = reinterpret_cast<float*>(f32);
+    }
+    return off;
+}
+
+// CG launch shape: at most kMaxBpr workgroups per right-hand side, each sweeping a
+// contiguous range of tiles (so every consumer reduces at most kMaxBpr partials).
+static void set_cg_shape(hmc_ctx* c, int max_bpr) {
+    const int bpr0 = c->nblk < max_bpr ? c->nblk : max_bpr;
+    c->tpb = (c->nblk + bpr0 - 1) / bpr0;
+    c->bpr = (c->nblk + c->tpb - 1) / c->tpb;
 }
 
 // --------------------------------------------------------------------------------------
@@ -339,23 +441,9 @@ int hmc_create(int L, int Lt, double dtau, const hmc_params* params, hmc_ctx** o
         delete c;
         return fail(HMC_ERR_HIP, "hipGetDevice failed");
     }
-    // workspace plan
-    const size_t V = size_t(c->vol);
-    const size_t sp64 = 4 * V * sizeof(double2), sp32 = 4 * V * sizeof(float2);
-    const size_t cap = size_t(c->cap);
-    size_t off = 0;
-    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-    (void)take(sizeof(CgState) * cap);                          // st
-    (void)take(sizeof(unsigned) * (cap + 1));                   // cnt
-    (void)take(sizeof(double) * (cap > 2 ? cap : 2) * c->nblk); // partial
-    (void)take(sizeof(double) * kSlots);                        // slots
-    (void)take(4 * cap * sp64);                                 // r64, p064, p164, t64
-    (void)take(5 * cap * sp32);                                 // r32, p032, p132, t32, x32
-    (void)take(2 * cap * sp64);                                 // chi, xsol
-    (void)take(2 * 3 * V * sizeof(double));                     // pi, phi_save
-    (void)take(3 * V * sizeof(float));                          // phi32
-    c->need = off;
-    if (hipHostMalloc((void**)&c->h_st, sizeof(CgState) * 2 * cap, hipHostMallocDefault) != hipSuccess ||
+    set_cg_shape(c, kDefaultBpr);
+    c->need = ws_layout(c, nullptr);
+    if (hipHostMalloc((void**)&c->h_st, sizeof(CgState) * 2 * size_t(c->cap), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_slots, sizeof(double) * kSlots, hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess) {
@@ -366,8 +454,38 @@ int hmc_create(int L, int Lt, double dtau, const hmc_params* params, hmc_ctx** o
     return HMC_OK;
 }
 
+int hmc_set_kernel_timing(hmc_ctx* c, int enable) {
+    if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
+    if (enable && c->tev[0][0] == nullptr) {
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 3; ++j) HIPCHK(hipEventCreate(&c->tev[i][j]));
+    }
+    c->timing = enable != 0;
+    std::memset(&c->kt, 0, sizeof(c->kt));
+    return HMC_OK;
+}
+
+int hmc_set_cg_workgroups(hmc_ctx* c, int max_per_rhs) {
+    if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
+    if (max_per_rhs < 1 || max_per_rhs > kMaxBpr)
+        return fail(HMC_ERR_INVALID_ARG, "workgroups per right-hand side must lie in [1, %d]", kMaxBpr);
+    set_cg_shape(c, max_per_rhs);
+    return HMC_OK;
+}
+
+int hmc_get_cg_workgroups(const hmc_ctx* c) { return c ? c->bpr : -1; }
+
+int hmc_get_kernel_times(const hmc_ctx* c, hmc_kernel_times* out) {
+    if (c == nullptr || out == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    *out = c->kt;
+    return HMC_OK;
+}
+
 int hmc_destroy(hmc_ctx* c) {
     if (c == nullptr) return HMC_OK;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j)
+            if (c->tev[i][j]) (void)hipEventDestroy(c->tev[i][j]);
     if (c->h_st) (void)hipHostFree(c->h_st);
     if (c->h_slots) (void)hipHostFree(c->h_slots);
     for (int i = 0; i < 2; ++i)
@@ -393,40 +511,10 @@ int hmc_set_workspace(hmc_ctx* c, void* ptr, size_t bytes) {
     if (c == nullptr || ptr == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL ctx or workspace");
     if ((reinterpret_cast<uintptr_t>(ptr) & 255u) != 0) return fail(HMC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     if (bytes < c->need) return fail(HMC_ERR_WORKSPACE, "workspace of %zu bytes < %zu needed", bytes, c->need);
-    const size_t V = size_t(c->vol);
-    const size_t sp64 = 4 * V * sizeof(double2), sp32 = 4 * V * sizeof(float2);
-    const size_t cap = size_t(c->cap);
     char* base = static_cast<char*>(ptr);
-    size_t off = 0;
-    auto take = [&](size_t b) { char* p = base + off; off = align_up(off + b, 256); return p; };
-    c->st = reinterpret_cast<CgState*>(take(sizeof(CgState) * cap));
-    c->cnt = reinterpret_cast<unsigned*>(take(sizeof(unsigned) * (cap + 1)));
-    c->partial = reinterpret_cast<double*>(take(sizeof(double) * (cap > 2 ? cap : 2) * c->nblk));
-    c->slots = reinterpret_cast<double*>(take(sizeof(double) * kSlots));
-    char* v64 = take(4 * cap * sp64);
-    c->r64 = reinterpret_cast<double2*>(v64);
-    c->p064 = reinterpret_cast<double2*>(v64 + cap * sp64);
-    c->p164 = reinterpret_cast<double2*>(v64 + 2 * cap * sp64);
-    c->t64 = reinterpret_cast<double2*>(v64 + 3 * cap * sp64);
-    char* v32 = take(5 * cap * sp32);
-    c->r32 = reinterpret_cast<float2*>(v32);
-    c->p032 = reinterpret_cast<float2*>(v32 + cap * sp32);
-    c->p132 = reinterpret_cast<float2*>(v32 + 2 * cap * sp32);
-    c->t32 = reinterpret_cast<float2*>(v32 + 3 * cap * sp32);
-    c->x32 = reinterpret_cast<float2*>(v32 + 4 * cap * sp32);
-    char* tr = take(2 * cap * sp64);
-    c->chi = reinterpret_cast<double2*>(tr);
-    c->xsol = reinterpret_cast<double2*>(tr + cap * sp64);
-    char* bos = take(2 * 3 * V * sizeof(double));
-    c->pi = reinterpret_cast<double*>(bos);
-    c->phi_save = reinterpret_cast<double*>(bos + 3 * V * sizeof(double));
-    c->phi32 = reinterpret_cast<float*>(take(3 * V * sizeof(float)));
+    (void)ws_layout(c, base);
     c->ws = base;
     c->ws_bytes = bytes;
-    // counters start at zero; the reductions leave them at zero
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, nullptr, c->cnt, int(cap + 1));
-    LAUNCHCHK();
-    HIPCHK(hipStreamSynchronize(nullptr));
     return HMC_OK;
 }
 
@@ -446,7 +534,7 @@ static int apply_impl(hmc_ctx* c, const R* phi, const void* in, void* out, int n
     if constexpr (sizeof(R) == sizeof(double)) cf = &c->cf64; else cf = &c->cf32;
     hipLaunchKernelGGL((k_apply<R, DAG>), dim3(grid_for(c, n)), dim3(kBlock), 0, (hipStream_t)stream,
                        static_cast<const C2<R>*>(in), static_cast<C2<R>*>(out), phi, c->lat, *cf,
-                       c->nblk, nullptr, 0);
+                       c->nblk);
     LAUNCHCHK();
     return HMC_OK;
 }
@@ -520,8 +608,19 @@ static int launch_force(hmc_ctx* c, const double* phi, const double2* x, int npf
 }
 
 static int dot_re(hmc_ctx* c, const double2* a, const double2* b, int n, double* slot, hipStream_t s) {
-    hipLaunchKernelGGL(k_dot_re, dim3(c->nblk), dim3(kBlock), 0, s, a, b, n, c->lat, slot,
-                       c->partial, c->cnt + c->cap);
+    hipLaunchKernelGGL(k_dot_re, dim3(c->nblk), dim3(kBlock), 0, s, a, b, n, c->lat, c->gpart);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, c->gpart, c->nblk, 1, 0, slot);
+    LAUNCHCHK();
+    return HMC_OK;
+}
+
+// K = |pi|^2 / 2 (pi may be NULL) and S_B into slot[0], slot[1].
+static int energy(hmc_ctx* c, const double* pi, const double* phi, double* slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy, dim3(c->nblk), dim3(kBlock), 0, s, pi, phi, c->lat, c->bc,
+                       c->gpart, c->nblk);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, c->gpart, c->nblk, 2, c->nblk, slot);
     LAUNCHCHK();
     return HMC_OK;
 }
@@ -592,9 +691,8 @@ int hmc_boson_action(hmc_ctx* c, const double* phi, double* S, void* stream) {
     int rc = need_ws(c);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_energy, dim3(c->nblk), dim3(kBlock), 0, s, nullptr, phi, c->lat, c->bc,
-                       c->slots + SL_TMP, c->partial, c->nblk, c->cnt + c->cap);
-    LAUNCHCHK();
+    rc = energy(c, nullptr, phi, c->slots + SL_TMP, s);
+    if (rc) return rc;
     rc = read_slots(c, s);
     if (rc) return rc;
     *S = c->h_slots[SL_TMP + 1];
@@ -629,9 +727,8 @@ int hmc_trajectory(hmc_ctx* c, double* phi, const double* pi0, const void* eta, 
                     c->slots + SL_SPF0, s);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_energy, dim3(c->nblk), dim3(kBlock), 0, s, c->pi, phi, c->lat, c->bc,
-                       c->slots + SL_K0, c->partial, c->nblk, c->cnt + c->cap);
-    LAUNCHCHK();
+    rc = energy(c, c->pi, phi, c->slots + SL_K0, s);
+    if (rc) return rc;
 
     auto solve = [&]() -> int {
         if (n_pf == 0) return HMC_OK;
@@ -667,9 +764,8 @@ int hmc_trajectory(hmc_ctx* c, double* phi, const double* pi0, const void* eta, 
         rc = dot_re(c, c->chi, c->xsol, n_pf, c->slots + SL_SPF1, s);
         if (rc) return restore(rc);
     }
-    hipLaunchKernelGGL(k_energy, dim3(c->nblk), dim3(kBlock), 0, s, c->pi, phi, c->lat, c->bc,
-                       c->slots + SL_K1, c->partial, c->nblk, c->cnt + c->cap);
-    if (hipGetLastError() != hipSuccess) return restore(fail(HMC_ERR_HIP, "energy launch failed"));
+    rc = energy(c, c->pi, phi, c->slots + SL_K1, s);
+    if (rc) return restore(rc);
     rc = read_slots(c, s);
     if (rc) return restore(rc);
     const double* hs = c->h_slots;

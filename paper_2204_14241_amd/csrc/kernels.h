@@ -4,11 +4,16 @@
 // leapfrog updates (Methods D).
 //
 // Work decomposition: one thread per lattice site handles all four spinor components
-// (the Yukawa term couples them); a 256-thread workgroup covers 256 consecutive sites in
-// (tau, x, y) order, workgroup ids are permuted so each XCD sweeps a contiguous slab of
-// the lattice (stencil neighbours then hit its L2), and right-hand sides are laid end to
-// end in the grid.  Every operation here is a bandwidth-bound sparse stencil or vector
-// update, so no matrix cores are used.
+// (the Yukawa term couples them); a 256-thread tile covers 256 consecutive sites in
+// (tau, x, y) order.  Workgroup ids are permuted so each of the 8 XCDs sweeps a
+// contiguous slab of the lattice (stencil neighbours then hit its L2).  Every operation
+// here is a bandwidth-bound sparse stencil or vector update, so no matrix cores are used.
+//
+// Global reductions never use fences or atomics: on the multi-XCD gfx950 an agent-scope
+// release writes back the whole L2, which would serialise thousands of workgroups.
+// Instead each workgroup stores one partial sum, and the consumer -- the next kernel in
+// the stream -- sums the partials in index order at its start (every workgroup obtains
+// the bit-identical total), or a one-workgroup kernel does.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -41,44 +46,11 @@ __device__ __forceinline__ C2<R> axpy(R s, C2<R> b, C2<R> a) { return mk<R>(a.x 
 template <typename R>
 __device__ __forceinline__ R norm2(C2<R> a) { return a.x * a.x + a.y * a.y; }
 
-// ------------------------------------------------------------------------------------
-// CG bookkeeping kept on the device, one record per right-hand side.
-enum CgMode : int {
-    CG_ACTIVE = 0,      // iterating
-    CG_CONV_ITER = 1,   // iterated residual passed; FP64 true residual not yet checked
-    CG_MAXIT = 2,       // iteration cap reached; x not yet finalised
-    CG_DONE = 3,        // true residual passed
-    CG_STOPPED = 4,     // iteration cap reached, x finalised
-    CG_FAILED = 5,      // a reduction was not finite
-};
-enum : int {
-    F_ACTIVE = 1 << CG_ACTIVE,
-    F_CONV_ITER = 1 << CG_CONV_ITER,
-    F_MAXIT = 1 << CG_MAXIT,
-};
-
-struct CgState {
-    double bb;          // |b|^2
-    double stop_rr;     // tol^2 |b|^2
-    double rr;          // current iterated |r|^2
-    double rr_prev;     // |r|^2 of the previous iteration
-    double alpha;       // step still to be added to x along the current p (pending)
-    double alpha_cur;   // step of the iteration in flight
-    double beta;        // coefficient of the next direction update p <- r + beta p
-    double rr_true;     // last FP64 true residual |b - A x|^2
-    int mode;
-    int iters;
-    int pbuf;           // which of the two direction buffers holds the current p
-    int n_ru;           // FP64 true-residual recomputations
-    int maxit;
-    int pad[3];
-};
+__device__ __forceinline__ bool finite(double x) { return x - x == 0.0; }
 
 // ------------------------------------------------------------------------------------
-// Deterministic reductions: butterfly within a wavefront, fixed-order sum over the
-// wavefronts of a workgroup, per-workgroup partials in global memory, and the last
-// workgroup to arrive (atomic ticket) sums the partials in index order.  The result
-// depends only on the grid shape, never on scheduling.
+// Deterministic block reduction of NQ doubles: butterfly within each 64-wide wavefront,
+// then a fixed-order sum over the wavefronts.  Totals are valid in thread 0.
 template <int NQ>
 __device__ __forceinline__ void block_reduce(double (&v)[NQ]) {
     __shared__ double sh[NQ][16];
@@ -106,41 +78,134 @@ __device__ __forceinline__ void block_reduce(double (&v)[NQ]) {
     __syncthreads();
 }
 
-// Returns true in every thread of the last workgroup; thread 0 of it then holds the
-// grid totals in v.  partial has NQ rows of `stride` doubles.
-template <int NQ>
-__device__ __forceinline__ bool grid_reduce(double (&v)[NQ], double* partial, int stride,
-                                            int nblk, int blk, unsigned* cnt) {
-    __shared__ int last;
-    block_reduce<NQ>(v);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) partial[q * stride + blk] = v[q];
-        __threadfence();
-        const unsigned old = atomicAdd(cnt, 1u);
-        last = (old == unsigned(nblk - 1));
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double a[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        a[q] = 0.0;
-        for (int j = threadIdx.x; j < nblk; j += blockDim.x)
-            a[q] += __hip_atomic_load(partial + q * stride + j, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-    }
-    block_reduce<NQ>(a);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) v[q] = a[q];
-        __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return true;
+// Sum n partials in a fixed order (strided by thread, then block_reduce); valid in thread 0.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ p, int n) {
+    double v[1] = {0.0};
+    for (int j = threadIdx.x; j < n; j += blockDim.x) v[0] += p[j];
+    block_reduce<1>(v);
+    return v[0];
 }
 
-__device__ __forceinline__ bool finite(double x) { return x - x == 0.0; }
+// ------------------------------------------------------------------------------------
+// CG bookkeeping kept on the device, one record per right-hand side, double-buffered:
+// kernel number s of a solve reads records[s % 2] and (workgroup 0) writes
+// records[(s + 1) % 2], so no workgroup ever sees a record changed by its own launch.
+enum CgMode : int {
+    CG_ACTIVE = 0,      // iterating
+    CG_CONV_ITER = 1,   // iterated residual passed; FP64 true residual not yet checked
+    CG_MAXIT = 2,       // iteration cap reached; x not yet finalised
+    CG_DONE = 3,        // true residual passed
+    CG_STOPPED = 4,     // iteration cap reached, x finalised
+    CG_FAILED = 5,      // a reduction was not finite
+};
+enum : int {
+    F_ACTIVE = 1 << CG_ACTIVE,
+    F_CONV_ITER = 1 << CG_CONV_ITER,
+    F_MAXIT = 1 << CG_MAXIT,
+};
+// Which partial sums the previous kernel left to be reduced.
+enum CgPending : int { PEND_NONE = 0, PEND_BB = 1, PEND_TT = 2, PEND_RR = 3, PEND_RU = 4 };
+
+struct CgState {
+    double bb;          // |b|^2
+    double tol2;        // tol^2
+    double stop_rr;     // tol^2 |b|^2
+    double rr;          // current iterated |r|^2
+    double rr_prev;     // |r|^2 of the previous iteration
+    double alpha;       // step still to be added to x along the current p (pending)
+    double alpha_cur;   // step of the iteration in flight
+    double beta;        // coefficient of the next direction update p <- r + beta p
+    double rr_true;     // last FP64 true residual |b - A x|^2
+    int mode;
+    int iters;
+    int pbuf;           // which of the two direction buffers holds the current p
+    int n_ru;           // FP64 true-residual recomputations
+    int maxit;
+    int pending;        // CgPending
+};
+
+// Launch geometry and shared buffers of the CG kernels.
+struct CgCtl {
+    const CgState* st_in;
+    CgState* st_out;
+    double* part;       // partial sums [4 kinds][cap][bpr]
+    int cap;            // right-hand sides the buffers hold
+    int bpr;            // workgroups per right-hand side
+    int tpb;            // 256-site tiles per workgroup
+    int ntiles;         // tiles per right-hand side
+};
+
+__device__ __forceinline__ double* part_slot(const CgCtl& c, int kind, int k) {
+    return c.part + (size_t(kind - 1) * c.cap + k) * c.bpr;
+}
+
+// Reduce the pending partials of right-hand side k and advance its state machine.
+// Every workgroup computes the same record (deterministic order); returned in S.
+__device__ __forceinline__ void cg_finalize(const CgCtl& c, int k, CgState& S) {
+    __shared__ CgState sh;
+    if (threadIdx.x == 0) sh = c.st_in[k];
+    __syncthreads();
+    const int pend = sh.pending;
+    double tot = 0.0;
+    if (pend != PEND_NONE) tot = sum_partials(part_slot(c, pend, k), c.bpr);
+    if (threadIdx.x == 0 && pend != PEND_NONE) {
+        CgState& s = sh;
+        switch (pend) {
+            case PEND_BB:
+                s.bb = tot;
+                s.stop_rr = s.tol2 * tot;
+                s.rr = s.rr_prev = s.rr_true = tot;
+                s.mode = !finite(tot) ? CG_FAILED : (tot > 0.0 ? CG_ACTIVE : CG_DONE);
+                break;
+            case PEND_TT:
+                if (s.mode == CG_ACTIVE) {
+                    if (!(tot > 0.0) || !finite(tot)) s.mode = CG_FAILED;
+                    else s.alpha_cur = s.rr / tot;
+                }
+                break;
+            case PEND_RR:
+                if (s.mode == CG_ACTIVE) {
+                    if (!finite(tot)) {
+                        s.mode = CG_FAILED;
+                    } else {
+                        s.rr_prev = s.rr;
+                        s.beta = tot / s.rr;
+                        s.rr = tot;
+                        s.alpha = s.alpha_cur;
+                        s.iters += 1;
+                        if (tot <= s.stop_rr) s.mode = CG_CONV_ITER;
+                        else if (s.iters >= s.maxit) s.mode = CG_MAXIT;
+                    }
+                }
+                break;
+            case PEND_RU:
+                s.rr_true = tot;
+                s.n_ru += 1;
+                s.alpha = 0.0;
+                if (!finite(tot)) {
+                    s.mode = CG_FAILED;
+                } else if (tot <= s.stop_rr) {
+                    s.mode = CG_DONE;
+                } else if (s.mode == CG_MAXIT) {
+                    s.mode = CG_STOPPED;
+                } else {
+                    s.beta = tot / s.rr_prev;
+                    s.rr = tot;
+                    s.mode = CG_ACTIVE;
+                }
+                break;
+        }
+        s.pending = PEND_NONE;
+    }
+    __syncthreads();
+    S = sh;
+    __syncthreads();
+}
+
+// Workgroup 0 of a right-hand side publishes the record for the next kernel.
+__device__ __forceinline__ void cg_publish(const CgCtl& c, int k, int blk, const CgState& S) {
+    if (blk == 0 && threadIdx.x == 0) c.st_out[k] = S;
+}
 
 // ------------------------------------------------------------------------------------
 // The stencil of Eq. (17) at one site.  Src(c, i) yields component c of the input at
@@ -173,7 +238,6 @@ __device__ __forceinline__ void dslash_site(const Src& src, const R* __restrict_
     }
     const R g = cf.cpl * R(nb.stag);
     const R q1 = g * phi[s], q2 = g * phi[vol + s], q3 = g * phi[2 * vol + s];
-    // (q1 - i q2) z and (q1 + i q2) z
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         const C2<R> u = cen[2 * (1 - a)], w = cen[2 * (1 - a) + 1];
@@ -206,16 +270,14 @@ struct SrcXpay {
 };
 
 // ------------------------------------------------------------------------------------
-// out_k = M in_k (or M^dagger), k < n.  When st is given, right-hand sides whose mode
-// is not in `filter` are skipped.
+// out_k = M in_k (or M^dagger), k < n, one tile per workgroup.
 template <typename R, bool DAG>
 __global__ __launch_bounds__(kBlock) void k_apply(const C2<R>* __restrict__ in,
                                                   C2<R>* __restrict__ out,
                                                   const R* __restrict__ phi, Lat lat, Coef<R> cf,
-                                                  int nblk, const CgState* st, int filter) {
+                                                  int nblk) {
     const int logical = xcd_remap(blockIdx.x, gridDim.x);
     const int k = logical / nblk, blk = logical - k * nblk;
-    if (st != nullptr && !((1 << st[k].mode) & filter)) return;
     const int s = blk * kBlock + threadIdx.x;
     if (s >= lat.vol) return;
     const size_t off = size_t(k) * 4 * lat.vol;
@@ -238,238 +300,254 @@ struct CgVecs {
     C2<R>* x;       // solution accumulated in R (the caller's x in FP64 mode)
 };
 
-// CG step A (iteration k):  x += alpha_{k-1} p_{k-1};  p_k = r_k + beta_{k-1} p_{k-1};
-// t = M p_k;  |t|^2 = <p_k, M^dagger M p_k>.  The last workgroup sets alpha_k = |r|^2/|t|^2.
-// p is double-buffered because neighbouring sites read the old direction.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_cg_a(CgVecs<R> v, const R* __restrict__ phi, Lat lat,
-                                                 Coef<R> cf, int nblk, CgState* st,
-                                                 double* partial, unsigned* cnt) {
+// Map the launch onto (right-hand side, workgroup) and the workgroup's tile range.
+struct CgPos {
+    int k, blk, t0, t1;
+};
+__device__ __forceinline__ CgPos cg_pos(const CgCtl& c) {
     const int logical = xcd_remap(blockIdx.x, gridDim.x);
-    const int k = logical / nblk, blk = logical - k * nblk;
-    CgState* S = st + k;
-    if (S->mode != CG_ACTIVE) return;
-    const R alpha = R(S->alpha), beta = R(S->beta);
-    const int pb = S->pbuf;
-    const size_t off = size_t(k) * 4 * lat.vol;
+    CgPos p;
+    p.k = logical / c.bpr;
+    p.blk = logical - p.k * c.bpr;
+    p.t0 = p.blk * c.tpb;
+    p.t1 = min(p.t0 + c.tpb, c.ntiles);
+    return p;
+}
+
+// Store this workgroup's partial (thread 0) after a block reduction.
+__device__ __forceinline__ void store_partial(const CgCtl& c, int kind, const CgPos& p, double v) {
+    double a[1] = {v};
+    block_reduce<1>(a);
+    if (threadIdx.x == 0) part_slot(c, kind, p.k)[p.blk] = a[0];
+}
+
+// CG step A (iteration k):  x += alpha_{k-1} p_{k-1};  p_k = r_k + beta_{k-1} p_{k-1};
+// t = M p_k;  partial |t|^2 = <p_k, M^dagger M p_k>.  p is double-buffered because
+// neighbouring sites read the old direction.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, CgVecs<R> v, const R* __restrict__ phi,
+                                                 Lat lat, Coef<R> cf) {
+    const CgPos pos = cg_pos(ctl);
+    CgState S;
+    cg_finalize(ctl, pos.k, S);
+    if (S.mode != CG_ACTIVE) {
+        cg_publish(ctl, pos.k, pos.blk, S);
+        return;
+    }
+    const R alpha = R(S.alpha), beta = R(S.beta);
+    const int pb = S.pbuf;
+    const size_t off = size_t(pos.k) * 4 * lat.vol;
     const C2<R>* pin = (pb ? v.p1 : v.p0) + off;
     C2<R>* pout = (pb ? v.p0 : v.p1) + off;
     const C2<R>* r = v.r + off;
-    const int s = blk * kBlock + threadIdx.x;
-    double part[1] = {0.0};
-    if (s < lat.vol) {
-        SrcXpay<R> src{r, pin, beta, lat.vol};
-        const Nbr nb = neighbours(lat, s);
-        C2<R> o[4], pn[4];
-        dslash_site<R, false>(src, phi, lat, cf, nb, s, o, pn);
-        C2<R>* x = v.x + off;
-        C2<R>* t = v.t + off;
-        R acc = R(0);
+    C2<R>* x = v.x + off;
+    C2<R>* t = v.t + off;
+    SrcXpay<R> src{r, pin, beta, lat.vol};
+    double part = 0.0;
+    for (int tile = pos.t0; tile < pos.t1; ++tile) {
+        const int s = tile * kBlock + threadIdx.x;
+        if (s < lat.vol) {
+            const Nbr nb = neighbours(lat, s);
+            C2<R> o[4], pn[4];
+            dslash_site<R, false>(src, phi, lat, cf, nb, s, o, pn);
+            R acc = R(0);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = c * lat.vol + s;
-            x[i] = axpy<R>(alpha, pin[i], x[i]);
-            pout[i] = pn[c];
-            t[i] = o[c];
-            acc += norm2<R>(o[c]);
-        }
-        part[0] = double(acc);
-    }
-    if (grid_reduce<1>(part, partial + size_t(k) * nblk, 0, nblk, blk, cnt + k)) {
-        if (threadIdx.x == 0) {
-            const double tt = part[0];
-            S->alpha = 0.0;
-            S->pbuf = 1 - pb;
-            if (!(tt > 0.0) || !finite(tt)) {
-                S->mode = CG_FAILED;
-            } else {
-                S->alpha_cur = S->rr / tt;
+            for (int c = 0; c < 4; ++c) {
+                const int i = c * lat.vol + s;
+                x[i] = axpy<R>(alpha, pin[i], x[i]);
+                pout[i] = pn[c];
+                t[i] = o[c];
+                acc += norm2<R>(o[c]);
             }
+            part += double(acc);
         }
     }
+    store_partial(ctl, PEND_TT, pos, part);
+    S.alpha = 0.0;
+    S.pbuf = 1 - pb;
+    S.pending = PEND_TT;
+    cg_publish(ctl, pos.k, pos.blk, S);
 }
 
-// CG step B:  r -= alpha_k M^dagger t;  |r|^2.  The last workgroup sets beta_k, checks the
-// iterated residual against tol^2 |b|^2 and the iteration cap.
+// CG step B:  r -= alpha_k M^dagger t;  partial |r|^2.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_cg_b(CgVecs<R> v, const R* __restrict__ phi, Lat lat,
-                                                 Coef<R> cf, int nblk, CgState* st,
-                                                 double* partial, unsigned* cnt) {
-    const int logical = xcd_remap(blockIdx.x, gridDim.x);
-    const int k = logical / nblk, blk = logical - k * nblk;
-    CgState* S = st + k;
-    if (S->mode != CG_ACTIVE) return;
-    const R alpha = R(S->alpha_cur);
-    const size_t off = size_t(k) * 4 * lat.vol;
-    const int s = blk * kBlock + threadIdx.x;
-    double part[1] = {0.0};
-    if (s < lat.vol) {
-        SrcPlain<R> src{v.t + off, lat.vol};
-        const Nbr nb = neighbours(lat, s);
-        C2<R> o[4], cen[4];
-        dslash_site<R, true>(src, phi, lat, cf, nb, s, o, cen);
-        C2<R>* r = v.r + off;
-        R acc = R(0);
+__global__ __launch_bounds__(kBlock) void k_cg_b(CgCtl ctl, CgVecs<R> v, const R* __restrict__ phi,
+                                                 Lat lat, Coef<R> cf) {
+    const CgPos pos = cg_pos(ctl);
+    CgState S;
+    cg_finalize(ctl, pos.k, S);
+    if (S.mode != CG_ACTIVE) {
+        cg_publish(ctl, pos.k, pos.blk, S);
+        return;
+    }
+    const R alpha = R(S.alpha_cur);
+    const size_t off = size_t(pos.k) * 4 * lat.vol;
+    SrcPlain<R> src{v.t + off, lat.vol};
+    C2<R>* r = v.r + off;
+    double part = 0.0;
+    for (int tile = pos.t0; tile < pos.t1; ++tile) {
+        const int s = tile * kBlock + threadIdx.x;
+        if (s < lat.vol) {
+            const Nbr nb = neighbours(lat, s);
+            C2<R> o[4], cen[4];
+            dslash_site<R, true>(src, phi, lat, cf, nb, s, o, cen);
+            R acc = R(0);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = c * lat.vol + s;
-            const C2<R> rn = axpy<R>(-alpha, o[c], r[i]);
-            r[i] = rn;
-            acc += norm2<R>(rn);
-        }
-        part[0] = double(acc);
-    }
-    if (grid_reduce<1>(part, partial + size_t(k) * nblk, 0, nblk, blk, cnt + k)) {
-        if (threadIdx.x == 0) {
-            const double rr = part[0];
-            if (!finite(rr)) {
-                S->mode = CG_FAILED;
-            } else {
-                S->rr_prev = S->rr;
-                S->beta = rr / S->rr;
-                S->rr = rr;
-                S->alpha = S->alpha_cur;
-                S->iters += 1;
-                if (rr <= S->stop_rr) S->mode = CG_CONV_ITER;
-                else if (S->iters >= S->maxit) S->mode = CG_MAXIT;
+            for (int c = 0; c < 4; ++c) {
+                const int i = c * lat.vol + s;
+                const C2<R> rn = axpy<R>(-alpha, o[c], r[i]);
+                r[i] = rn;
+                acc += norm2<R>(rn);
             }
+            part += double(acc);
         }
     }
+    store_partial(ctl, PEND_RR, pos, part);
+    S.pending = PEND_RR;
+    cg_publish(ctl, pos.k, pos.blk, S);
 }
 
 // Reliable update, part 1 (elementwise): fold the pending step into the FP64 solution,
-// x64 += x_lo + alpha p (mixed) or x64 += alpha p (FP64, x_lo == nullptr), and clear x_lo.
+// x64 += x_lo + alpha p (mixed) or x64 += alpha p (FP64, where v.x is x64), clear x_lo.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_ru_fold(double2* __restrict__ x64, CgVecs<R> v,
-                                                    Lat lat, int nblk, const CgState* st,
-                                                    int filter) {
-    const int logical = xcd_remap(blockIdx.x, gridDim.x);
-    const int k = logical / nblk, blk = logical - k * nblk;
-    const CgState* S = st + k;
-    if (!((1 << S->mode) & filter)) return;
-    const double alpha = S->alpha;
-    const size_t off = size_t(k) * 4 * lat.vol;
-    const C2<R>* p = (S->pbuf ? v.p1 : v.p0) + off;
-    const int s = blk * kBlock + threadIdx.x;
-    if (s >= lat.vol) return;
+__global__ __launch_bounds__(kBlock) void k_ru_fold(CgCtl ctl, double2* __restrict__ x64,
+                                                    CgVecs<R> v, Lat lat, int filter) {
+    const CgPos pos = cg_pos(ctl);
+    CgState S;
+    cg_finalize(ctl, pos.k, S);
+    if (!((1 << S.mode) & filter)) {
+        cg_publish(ctl, pos.k, pos.blk, S);
+        return;
+    }
+    const double alpha = S.alpha;
+    const size_t off = size_t(pos.k) * 4 * lat.vol;
+    const C2<R>* p = (S.pbuf ? v.p1 : v.p0) + off;
+    const bool separate = (void*)v.x != (void*)x64;
+    for (int tile = pos.t0; tile < pos.t1; ++tile) {
+        const int s = tile * kBlock + threadIdx.x;
+        if (s >= lat.vol) break;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const size_t i = off + size_t(c) * lat.vol + s;
-        const C2<R> pc = p[c * lat.vol + s];
-        double2 xv = x64[i];
-        xv.x += alpha * double(pc.x);
-        xv.y += alpha * double(pc.y);
-        if (v.x != nullptr && (void*)v.x != (void*)x64) {
-            const C2<R> xl = v.x[i];
-            xv.x += double(xl.x);
-            xv.y += double(xl.y);
-            v.x[i] = mk<R>(R(0), R(0));
+        for (int c = 0; c < 4; ++c) {
+            const size_t i = off + size_t(c) * lat.vol + s;
+            const C2<R> pc = p[c * lat.vol + s];
+            double2 xv = x64[i];
+            xv.x += alpha * double(pc.x);
+            xv.y += alpha * double(pc.y);
+            if (separate) {
+                const C2<R> xl = v.x[i];
+                xv.x += double(xl.x);
+                xv.y += double(xl.y);
+                v.x[i] = mk<R>(R(0), R(0));
+            }
+            x64[i] = xv;
         }
-        x64[i] = xv;
+    }
+    S.alpha = 0.0;
+    cg_publish(ctl, pos.k, pos.blk, S);
+}
+
+// Reliable update, part 2: t64 = M x64 (FP64) for right-hand sides in `filter`.
+__global__ __launch_bounds__(kBlock) void k_ru_apply(CgCtl ctl, const double2* __restrict__ x64,
+                                                     double2* __restrict__ t64,
+                                                     const double* __restrict__ phi, Lat lat,
+                                                     Coef<double> cf, int filter) {
+    const CgPos pos = cg_pos(ctl);
+    CgState S;
+    cg_finalize(ctl, pos.k, S);
+    cg_publish(ctl, pos.k, pos.blk, S);
+    if (!((1 << S.mode) & filter)) return;
+    const size_t off = size_t(pos.k) * 4 * lat.vol;
+    SrcPlain<double> src{x64 + off, lat.vol};
+    for (int tile = pos.t0; tile < pos.t1; ++tile) {
+        const int s = tile * kBlock + threadIdx.x;
+        if (s >= lat.vol) break;
+        const Nbr nb = neighbours(lat, s);
+        double2 o[4], cen[4];
+        dslash_site<double, false>(src, phi, lat, cf, nb, s, o, cen);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) t64[off + size_t(c) * lat.vol + s] = o[c];
     }
 }
 
-// Reliable update, part 3: r = b - M^dagger t64 in FP64 (t64 = M x64 from k_apply), stored
-// in the Krylov precision; |r|^2 in FP64.  The last workgroup records the true residual and
-// moves the right-hand side to DONE, STOPPED or back to ACTIVE (keeping p, with
-// beta = |r_true|^2 / |r_prev|^2).
+// Reliable update, part 3: r = b - M^dagger t64 in FP64, stored in the Krylov precision;
+// partial |r|^2 in FP64 (reduced by the next kernel: DONE, STOPPED or back to ACTIVE).
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_ru_resid(const double2* __restrict__ b,
+__global__ __launch_bounds__(kBlock) void k_ru_resid(CgCtl ctl, const double2* __restrict__ b,
                                                      const double2* __restrict__ t64,
                                                      const double* __restrict__ phi, Lat lat,
                                                      Coef<double> cf, C2<R>* __restrict__ r,
-                                                     int nblk, CgState* st, int filter,
-                                                     double* partial, unsigned* cnt) {
-    const int logical = xcd_remap(blockIdx.x, gridDim.x);
-    const int k = logical / nblk, blk = logical - k * nblk;
-    CgState* S = st + k;
-    const int mode = S->mode;
-    if (!((1 << mode) & filter)) return;
-    const size_t off = size_t(k) * 4 * lat.vol;
-    const int s = blk * kBlock + threadIdx.x;
-    double part[1] = {0.0};
-    if (s < lat.vol) {
-        SrcPlain<double> src{t64 + off, lat.vol};
-        const Nbr nb = neighbours(lat, s);
-        double2 o[4], cen[4];
-        dslash_site<double, true>(src, phi, lat, cf, nb, s, o, cen);
-        double acc = 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const size_t i = off + size_t(c) * lat.vol + s;
-            const double2 rv = sub<double>(b[i], o[c]);
-            acc += norm2<double>(rv);
-            r[i] = mk<R>(R(rv.x), R(rv.y));
-        }
-        part[0] = acc;
+                                                     int filter) {
+    const CgPos pos = cg_pos(ctl);
+    CgState S;
+    cg_finalize(ctl, pos.k, S);
+    if (!((1 << S.mode) & filter)) {
+        cg_publish(ctl, pos.k, pos.blk, S);
+        return;
     }
-    if (grid_reduce<1>(part, partial + size_t(k) * nblk, 0, nblk, blk, cnt + k)) {
-        if (threadIdx.x == 0) {
-            const double rr = part[0];
-            S->rr_true = rr;
-            S->n_ru += 1;
-            S->alpha = 0.0;
-            if (!finite(rr)) {
-                S->mode = CG_FAILED;
-            } else if (rr <= S->stop_rr) {
-                S->mode = CG_DONE;
-            } else if (mode == CG_MAXIT) {
-                S->mode = CG_STOPPED;
-            } else {
-                S->beta = rr / S->rr_prev;
-                S->rr = rr;
-                S->mode = CG_ACTIVE;
+    const size_t off = size_t(pos.k) * 4 * lat.vol;
+    SrcPlain<double> src{t64 + off, lat.vol};
+    double part = 0.0;
+    for (int tile = pos.t0; tile < pos.t1; ++tile) {
+        const int s = tile * kBlock + threadIdx.x;
+        if (s < lat.vol) {
+            const Nbr nb = neighbours(lat, s);
+            double2 o[4], cen[4];
+            dslash_site<double, true>(src, phi, lat, cf, nb, s, o, cen);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const size_t i = off + size_t(c) * lat.vol + s;
+                const double2 rv = sub<double>(b[i], o[c]);
+                part += norm2<double>(rv);
+                r[i] = mk<R>(R(rv.x), R(rv.y));
             }
         }
     }
+    store_partial(ctl, PEND_RU, pos, part);
+    S.pending = PEND_RU;
+    cg_publish(ctl, pos.k, pos.blk, S);
 }
 
-// CG start from x = 0: x64 = 0, r = b, both direction buffers and x_lo cleared, |b|^2.
+// CG start from x = 0: x64 = 0, r = b, both direction buffers and x_lo cleared, partial |b|^2.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_cg_init(const double2* __restrict__ b,
+__global__ __launch_bounds__(kBlock) void k_cg_init(CgCtl ctl, const double2* __restrict__ b,
                                                     double2* __restrict__ x64, CgVecs<R> v,
-                                                    Lat lat, int nblk, CgState* st,
-                                                    double tol2, int maxit, double* partial,
-                                                    unsigned* cnt) {
-    const int logical = xcd_remap(blockIdx.x, gridDim.x);
-    const int k = logical / nblk, blk = logical - k * nblk;
-    const int s = blk * kBlock + threadIdx.x;
-    double part[1] = {0.0};
-    if (s < lat.vol) {
-        const size_t off = size_t(k) * 4 * lat.vol;
-        double acc = 0.0;
+                                                    Lat lat, double tol2, int maxit) {
+    const CgPos pos = cg_pos(ctl);
+    const size_t off = size_t(pos.k) * 4 * lat.vol;
+    const bool separate = (void*)v.x != (void*)x64;
+    double part = 0.0;
+    for (int tile = pos.t0; tile < pos.t1; ++tile) {
+        const int s = tile * kBlock + threadIdx.x;
+        if (s < lat.vol) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const size_t i = off + size_t(c) * lat.vol + s;
-            const double2 bv = b[i];
-            acc += norm2<double>(bv);
-            x64[i] = make_double2(0.0, 0.0);
-            v.r[i] = mk<R>(R(bv.x), R(bv.y));
-            v.p0[i] = mk<R>(R(0), R(0));
-            v.p1[i] = mk<R>(R(0), R(0));
-            if ((void*)v.x != (void*)x64) v.x[i] = mk<R>(R(0), R(0));
-        }
-        part[0] = acc;
-    }
-    if (grid_reduce<1>(part, partial + size_t(k) * nblk, 0, nblk, blk, cnt + k)) {
-        if (threadIdx.x == 0) {
-            CgState* S = st + k;
-            const double bb = part[0];
-            S->bb = bb;
-            S->stop_rr = tol2 * bb;
-            S->rr = bb;
-            S->rr_prev = bb;
-            S->alpha = 0.0;
-            S->alpha_cur = 0.0;
-            S->beta = 0.0;
-            S->rr_true = bb;
-            S->iters = 0;
-            S->pbuf = 0;
-            S->n_ru = 0;
-            S->maxit = maxit;
-            S->mode = !finite(bb) ? CG_FAILED : (bb > 0.0 ? CG_ACTIVE : CG_DONE);
+            for (int c = 0; c < 4; ++c) {
+                const size_t i = off + size_t(c) * lat.vol + s;
+                const double2 bv = b[i];
+                part += norm2<double>(bv);
+                x64[i] = make_double2(0.0, 0.0);
+                v.r[i] = mk<R>(R(bv.x), R(bv.y));
+                v.p0[i] = mk<R>(R(0), R(0));
+                v.p1[i] = mk<R>(R(0), R(0));
+                if (separate) v.x[i] = mk<R>(R(0), R(0));
+            }
         }
     }
+    store_partial(ctl, PEND_BB, pos, part);
+    CgState S{};
+    S.tol2 = tol2;
+    S.maxit = maxit;
+    S.mode = CG_ACTIVE;
+    S.pending = PEND_BB;
+    cg_publish(ctl, pos.k, pos.blk, S);
+}
+
+// One workgroup per right-hand side: reduce whatever is pending and publish the record
+// (run before the host reads the status).
+__global__ __launch_bounds__(kBlock) void k_cg_finalize(CgCtl ctl) {
+    const int k = blockIdx.x;
+    CgState S;
+    cg_finalize(ctl, k, S);
+    if (threadIdx.x == 0) ctl.st_out[k] = S;
 }
 
 // ------------------------------------------------------------------------------------
@@ -540,14 +618,12 @@ __global__ __launch_bounds__(kBlock) void k_force(const double2* __restrict__ x,
     }
 }
 
-// Kinetic energy 1/2 |pi|^2 and boson action S_B (Eq. 2 on the lattice) in one pass.
-// Results: out[0] = K, out[1] = S_B (written by the last workgroup).
+// Kinetic energy 1/2 |pi|^2 and boson action S_B (Eq. 2 on the lattice): per-workgroup
+// partials part[0][blk] = K, part[1][blk] = S_B (reduced by k_sum_partials).
 __global__ __launch_bounds__(kBlock) void k_energy(const double* __restrict__ pi,
                                                    const double* __restrict__ phi, Lat lat,
-                                                   BosonCoef bc, double* out, double* partial,
-                                                   int stride, unsigned* cnt) {
+                                                   BosonCoef bc, double* part, int stride) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int nblk = gridDim.x;
     const int s = blk * kBlock + threadIdx.x;
     double v[2] = {0.0, 0.0};
     if (s < lat.vol) {
@@ -567,20 +643,18 @@ __global__ __launch_bounds__(kBlock) void k_energy(const double* __restrict__ pi
         v[0] = 0.5 * kin;
         v[1] = 0.5 * bc.kt * st + 0.5 * bc.ks * ss + 0.5 * bc.kr * p2 + 0.25 * bc.ku * p2 * p2;
     }
-    if (grid_reduce<2>(v, partial, stride, nblk, blk, cnt)) {
-        if (threadIdx.x == 0) {
-            out[0] = v[0];
-            out[1] = v[1];
-        }
+    block_reduce<2>(v);
+    if (threadIdx.x == 0) {
+        part[blk] = v[0];
+        part[stride + blk] = v[1];
     }
 }
 
-// sum_k Re <a_k, b_k> over n spinors (complex128).  out[0] receives the sum.
+// sum_k Re <a_k, b_k> over n spinors (complex128): per-workgroup partials in part[blk].
 __global__ __launch_bounds__(kBlock) void k_dot_re(const double2* __restrict__ a,
                                                    const double2* __restrict__ b, int n, Lat lat,
-                                                   double* out, double* partial, unsigned* cnt) {
+                                                   double* part) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int nblk = gridDim.x;
     const int s = blk * kBlock + threadIdx.x;
     double v[1] = {0.0};
     if (s < lat.vol) {
@@ -593,8 +667,16 @@ __global__ __launch_bounds__(kBlock) void k_dot_re(const double2* __restrict__ a
             }
         }
     }
-    if (grid_reduce<1>(v, partial, 0, nblk, blk, cnt)) {
-        if (threadIdx.x == 0) out[0] = v[0];
+    block_reduce<1>(v);
+    if (threadIdx.x == 0) part[blk] = v[0];
+}
+
+// One workgroup: out[q] = sum over n partials of row q (rows `stride` apart), q < nq.
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ part, int n,
+                                                         int nq, int stride, double* out) {
+    for (int q = 0; q < nq; ++q) {
+        const double t = sum_partials(part + size_t(q) * stride, n);
+        if (threadIdx.x == 0) out[q] = t;
     }
 }
 
@@ -611,13 +693,6 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ a,
                                                    float* __restrict__ b, int n) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) b[i] = float(a[i]);
-}
-
-// Zero a buffer of n 32-bit words (used instead of memset so the sequence stays
-// capturable).
-__global__ __launch_bounds__(kBlock) void k_zero_u32(unsigned* __restrict__ a, int n) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) a[i] = 0u;
 }
 
 }  // namespace hmc

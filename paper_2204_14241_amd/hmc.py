@@ -112,6 +112,22 @@ class HMC:
         except Exception:
             pass
 
+    # ---------------------------------------------------------------- timing
+    def set_kernel_timing(self, enable=True):
+        check(self.lib.hmc_set_kernel_timing(self._ctx, 1 if enable else 0), "hmc_set_kernel_timing")
+
+    def set_cg_workgroups(self, n):
+        """Workgroups per right-hand side of the CG kernels; returns the count in use."""
+        check(self.lib.hmc_set_cg_workgroups(self._ctx, int(n)), "hmc_set_cg_workgroups")
+        return self.lib.hmc_get_cg_workgroups(self._ctx)
+
+    def kernel_times(self):
+        """{name: (average ms, samples)} of the sampled CG kernels."""
+        kt = _lib.HmcKernelTimes()
+        check(self.lib.hmc_get_kernel_times(self._ctx, ctypes.byref(kt)), "hmc_get_kernel_times")
+        return {n: (kt.ms[i] / kt.count[i] if kt.count[i] else None, kt.count[i])
+                for i, n in enumerate(_lib.KT_NAMES)}
+
     # ---------------------------------------------------------------- checks
     def _phi(self, phi, dtype=torch.float64):
         if phi.dtype != dtype or phi.device != self.device or not phi.is_contiguous():
