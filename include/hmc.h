@@ -192,6 +192,16 @@ int hmc_boson_action(hmc_ctx* ctx, const double* phi, double* S, void* stream);
 int hmc_trajectory(hmc_ctx* ctx, double* phi_inout, const double* pi0, const void* eta,
                    int n_pf, double u_uniform, hmc_traj_stats* stats, void* stream);
 
+/* The molecular-dynamics part of a trajectory alone (Eq. 29): n_leap kick-drift-kick steps
+ * of size eps on (phi_inout, pi_inout) in place, with the pseudofermions chi (n_pf
+ * complex128 spinors, e.g. from hmc_heatbath) held fixed.  No heat-bath and no Metropolis
+ * decision; stats receives the energies at both ends (S_pf0 from the solve at the start,
+ * S_pf1 from the last one), dH and solver counts.  Leapfrog is reversible: running it again
+ * from (phi_out, -pi_out) returns (phi_in, -pi_in) up to rounding and solver tolerance.
+ * Synchronises the stream.  Errors: as hmc_cg_solve (phi and pi are then undefined). */
+int hmc_leapfrog(hmc_ctx* ctx, double* phi_inout, double* pi_inout, const void* chi, int n_pf,
+                 hmc_traj_stats* stats, void* stream);
+
 /* Sampled kernel timing, for measuring the solver kernels inside real work.  When
  * enabled, the CG driver brackets the first iteration of every status chunk in which all
  * right-hand sides are still iterating with HIP events on the caller's stream, and adds

@@ -27,7 +27,7 @@ EXPORTED = [
     "hmc_force_from_solution", "hmc_pf_action", "hmc_boson_action", "hmc_trajectory",
     "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap",
     "hmc_set_kernel_timing", "hmc_get_kernel_times", "hmc_set_cg_workgroups",
-    "hmc_get_cg_workgroups",
+    "hmc_get_cg_workgroups", "hmc_leapfrog",
 ]
 
 
@@ -115,6 +115,7 @@ def load():
         "hmc_pf_action": (I, [P, P, P, I, P, ctypes.POINTER(D), ctypes.POINTER(HmcCgStats), P]),
         "hmc_boson_action": (I, [P, P, ctypes.POINTER(D), P]),
         "hmc_trajectory": (I, [P, P, P, P, I, D, ctypes.POINTER(HmcTrajStats), P]),
+        "hmc_leapfrog": (I, [P, P, P, P, I, ctypes.POINTER(HmcTrajStats), P]),
         "hmc_strerror": (ctypes.c_char_p, [I]),
         "hmc_last_error": (ctypes.c_char_p, []),
         "hmc_test_site": (I, [I, I, I, ctypes.POINTER(ctypes.c_int)]),

@@ -67,9 +67,9 @@ struct hmc_ctx {
     double dtau = 0.0;
     hmc_params p{};
     int cap = 1;            // right-hand sides the workspace holds
-    int nblk = 0;           // 256-site tiles per right-hand side
+    int nblk = 0;           // 256-site tiles per right-hand side (one site per thread)
+    int nblk2 = 0;          // 512-site tiles per right-hand side (FP32 pair kernels)
     int bpr = 0;            // CG workgroups per right-hand side
-    int tpb = 0;            // tiles per CG workgroup
     int seq = 0;            // CG launch counter (selects the state record buffer)
     Lat lat{};
     Coef<double> cf64{};
@@ -183,15 +183,15 @@ template <> struct KrylovBufs<float> {
 static bool finished(int mode) { return mode == CG_DONE || mode == CG_STOPPED || mode == CG_FAILED; }
 
 // Control block for the next CG launch; advances the state-record parity.
-static CgCtl next_ctl(hmc_ctx* c) {
+static CgCtl next_ctl(hmc_ctx* c, int expect, int ntiles) {
     CgCtl k;
+    k.expect = expect;
+    k.ntiles = ntiles;
     k.st_in = c->st + size_t(c->seq & 1) * c->cap;
     k.st_out = c->st + size_t((c->seq + 1) & 1) * c->cap;
     k.part = c->part;
     k.cap = c->cap;
     k.bpr = c->bpr;
-    k.tpb = c->tpb;
-    k.ntiles = c->nblk;
     c->seq += 1;
     return k;
 }
@@ -205,15 +205,15 @@ static int enqueue_ru(hmc_ctx* c, const double* phi64, const double2* b, double2
                       int filter, hipStream_t s) {
     CgVecs<R> v = KrylovBufs<R>::get(c, x);
     const int g = c->bpr * n;
-    hipLaunchKernelGGL(k_ru_fold<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c), x, v, c->lat, filter);
+    hipLaunchKernelGGL(k_ru_fold<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c, PEND_RR, c->nblk), x, v, c->lat, filter);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_ru_apply, dim3(g), dim3(kBlock), 0, s, next_ctl(c), x, c->t64, phi64,
+    hipLaunchKernelGGL(k_ru_apply, dim3(g), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE, c->nblk), x, c->t64, phi64,
                        c->lat, c->cf64, filter);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_ru_resid<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c), b, c->t64, phi64,
+    hipLaunchKernelGGL(k_ru_resid<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE, c->nblk), b, c->t64, phi64,
                        c->lat, c->cf64, v.r, filter);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_cg_finalize, dim3(n), dim3(kBlock), 0, s, next_ctl(c));
+    hipLaunchKernelGGL(k_cg_finalize, dim3(n), dim3(kBlock), 0, s, next_ctl(c, PEND_RU, c->nblk));
     LAUNCHCHK();
     return HMC_OK;
 }
@@ -233,7 +233,7 @@ static int cg_run(hmc_ctx* c, const double* phi64, const double2* b, double2* x,
     }
     const double tol = c->p.cg_tol;
     c->seq = 0;
-    hipLaunchKernelGGL(k_cg_init<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c), b, x, v, c->lat,
+    hipLaunchKernelGGL(k_cg_init<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE, c->nblk), b, x, v, c->lat,
                        tol * tol, c->p.cg_maxit);
     LAUNCHCHK();
 
@@ -251,10 +251,22 @@ static int cg_run(hmc_ctx* c, const double* phi64, const double2* b, double2* x,
         for (int i = 0; i < chunk; ++i) {
             const bool sample = c->timing && i == chunk / 2;
             if (sample) HIPCHK(hipEventRecord(c->tev[k & 1][0], s));
-            hipLaunchKernelGGL(k_cg_a<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c), v, phik, c->lat, cf);
+            // the first step A of a solve reduces |b|^2; after a status chunk nothing is pending
+            const int expect_a = i > 0 ? PEND_RR : (k == 0 ? PEND_BB : PEND_NONE);
+            if constexpr (sizeof(R) == sizeof(float))
+                hipLaunchKernelGGL(k_cg_a2, dim3(g), dim3(kBlock), 0, s, next_ctl(c, expect_a, c->nblk2), v,
+                                   phik, c->lat, cf);
+            else
+                hipLaunchKernelGGL(k_cg_a<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c, expect_a, c->nblk), v,
+                                   phik, c->lat, cf);
             LAUNCHCHK();
             if (sample) HIPCHK(hipEventRecord(c->tev[k & 1][1], s));
-            hipLaunchKernelGGL(k_cg_b<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c), v, phik, c->lat, cf);
+            if constexpr (sizeof(R) == sizeof(float))
+                hipLaunchKernelGGL(k_cg_b2, dim3(g), dim3(kBlock), 0, s, next_ctl(c, PEND_TT, c->nblk2), v,
+                                   phik, c->lat, cf);
+            else
+                hipLaunchKernelGGL(k_cg_b<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c, PEND_TT, c->nblk), v,
+                                   phik, c->lat, cf);
             LAUNCHCHK();
             if (sample) HIPCHK(hipEventRecord(c->tev[k & 1][2], s));
         }
@@ -374,12 +386,10 @@ static size_t ws_layout(hmc_ctx* c, char* base) {
     return off;
 }
 
-// CG launch shape: at most kMaxBpr workgroups per right-hand side, each sweeping a
-// contiguous range of tiles (so every consumer reduces at most kMaxBpr partials).
+// CG launch shape: at most max_bpr workgroups per right-hand side; workgroup b takes
+// tiles b, b + bpr, ... (so every consumer reduces at most kMaxBpr partials).
 static void set_cg_shape(hmc_ctx* c, int max_bpr) {
-    const int bpr0 = c->nblk < max_bpr ? c->nblk : max_bpr;
-    c->tpb = (c->nblk + bpr0 - 1) / bpr0;
-    c->bpr = (c->nblk + c->tpb - 1) / c->tpb;
+    c->bpr = c->nblk2 < max_bpr ? c->nblk2 : max_bpr;
 }
 
 // --------------------------------------------------------------------------------------
@@ -436,6 +446,7 @@ int hmc_create(int L, int Lt, double dtau, const hmc_params* params, hmc_ctx** o
     c->cap = params->max_rhs > 0 ? params->max_rhs : (params->n_pf > 0 ? params->n_pf : 1);
     c->lat = make_lat(L, Lt);
     c->nblk = (c->vol + kBlock - 1) / kBlock;
+    c->nblk2 = (c->vol / 2 + kBlock - 1) / kBlock;
     set_coefs(c);
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
@@ -530,11 +541,15 @@ static int apply_impl(hmc_ctx* c, const R* phi, const void* in, void* out, int n
     if (!aligned16(phi) || !aligned16(in) || !aligned16(out)) return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
     if (in == out) return fail(HMC_ERR_INVALID_ARG, "in and out must not overlap");
     if ((long long)c->nblk * n >= (1LL << 31)) return fail(HMC_ERR_INVALID_ARG, "too many vectors");
-    const Coef<R>* cf;
-    if constexpr (sizeof(R) == sizeof(double)) cf = &c->cf64; else cf = &c->cf32;
-    hipLaunchKernelGGL((k_apply<R, DAG>), dim3(grid_for(c, n)), dim3(kBlock), 0, (hipStream_t)stream,
-                       static_cast<const C2<R>*>(in), static_cast<C2<R>*>(out), phi, c->lat, *cf,
-                       c->nblk);
+    if constexpr (sizeof(R) == sizeof(double)) {
+        hipLaunchKernelGGL((k_apply<double, DAG>), dim3(grid_for(c, n)), dim3(kBlock), 0,
+                           (hipStream_t)stream, static_cast<const double2*>(in),
+                           static_cast<double2*>(out), phi, c->lat, c->cf64, c->nblk);
+    } else {
+        hipLaunchKernelGGL(k_apply2<DAG>, dim3(c->nblk2 * n), dim3(kBlock), 0, (hipStream_t)stream,
+                           static_cast<const float2*>(in), static_cast<float2*>(out), phi, c->lat,
+                           c->cf32, c->nblk2);
+    }
     LAUNCHCHK();
     return HMC_OK;
 }
@@ -701,6 +716,61 @@ int hmc_boson_action(hmc_ctx* c, const double* phi, double* S, void* stream) {
 
 // ---- trajectory ----------------------------------------------------------------------
 
+// Leapfrog (kick-drift-kick) on (phi, pi) with pseudofermions chi fixed: n_leap steps of eps,
+// one CG solve per step plus the one at the start, the two half kicks of neighbouring steps
+// applied separately inside the gradient kernel.  Leaves sum_k Re<chi_k, x_k> of the last
+// solve in slot SL_SPF1 and, if first_action, that of the first solve in SL_SPF0.
+static int md_integrate(hmc_ctx* c, double* phi, double* pi, const double2* chi, int n_pf,
+                        bool first_action, hmc_traj_stats* stats, hipStream_t s) {
+    const double eps = c->p.eps, h = 0.5 * eps;
+    const int nl = c->p.n_leap;
+    const int flags = HMC_FORCE_BOSON | (n_pf > 0 ? HMC_FORCE_PF : 0);
+    auto solve = [&]() -> int {
+        if (n_pf == 0) return HMC_OK;
+        hmc_cg_stats cs;
+        int r = cg_dispatch(c, phi, chi, c->xsol, n_pf, &cs, s);
+        if (r == HMC_OK || r == HMC_ERR_NOT_CONVERGED || r == HMC_ERR_NONFINITE) merge_stats(stats, cs);
+        return r;
+    };
+    int rc = solve();
+    if (rc) return rc;
+    if (first_action && n_pf > 0) {
+        rc = dot_re(c, chi, c->xsol, n_pf, c->slots + SL_SPF0, s);
+        if (rc) return rc;
+    }
+    // first half kick with the force at the start
+    rc = launch_force(c, phi, c->xsol, n_pf, flags, nullptr, pi, h, nl > 0 ? 1 : 0, s);
+    if (rc) return rc;
+    for (int step = 0; step < nl; ++step) {
+        hipLaunchKernelGGL(k_drift, dim3(elem_grid(3LL * c->vol)), dim3(kBlock), 0, s, phi, pi, eps,
+                           3 * c->vol);
+        LAUNCHCHK();
+        rc = solve();
+        if (rc) return rc;
+        // closing half kick of this step, then the opening half kick of the next one
+        rc = launch_force(c, phi, c->xsol, n_pf, flags, nullptr, pi, h, step + 1 < nl ? 2 : 1, s);
+        if (rc) return rc;
+    }
+    if (n_pf > 0) {
+        rc = dot_re(c, chi, c->xsol, n_pf, c->slots + SL_SPF1, s);
+        if (rc) return rc;
+    }
+    return HMC_OK;
+}
+
+static void fill_energies(hmc_ctx* c, int n_pf, hmc_traj_stats* stats) {
+    const double* hs = c->h_slots;
+    stats->K0 = hs[SL_K0];
+    stats->S_b0 = hs[SL_SB0];
+    stats->S_pf0 = n_pf > 0 ? hs[SL_SPF0] : 0.0;
+    stats->K1 = hs[SL_K1];
+    stats->S_b1 = hs[SL_SB1];
+    stats->S_pf1 = n_pf > 0 ? hs[SL_SPF1] : 0.0;
+    stats->H0 = stats->K0 + stats->S_b0 + stats->S_pf0;
+    stats->H1 = stats->K1 + stats->S_b1 + stats->S_pf1;
+    stats->dH = stats->H1 - stats->H0;
+}
+
 int hmc_trajectory(hmc_ctx* c, double* phi, const double* pi0, const void* eta, int n_pf,
                    double u, hmc_traj_stats* stats, void* stream) {
     if (c == nullptr || phi == nullptr || pi0 == nullptr || stats == nullptr)
@@ -713,9 +783,6 @@ int hmc_trajectory(hmc_ctx* c, double* phi, const double* pi0, const void* eta, 
     hipStream_t s = (hipStream_t)stream;
     std::memset(stats, 0, sizeof(*stats));
     const size_t phib = 3 * size_t(c->vol) * sizeof(double);
-    const double eps = c->p.eps, h = 0.5 * eps;
-    const int nl = c->p.n_leap;
-    const int flags = HMC_FORCE_BOSON | (n_pf > 0 ? HMC_FORCE_PF : 0);
 
     // start: keep phi0, copy pi0, heat-bath chi = M^dagger eta, energies at phi0
     HIPCHK(hipMemcpyAsync(c->phi_save, phi, phib, hipMemcpyDeviceToDevice, s));
@@ -730,13 +797,6 @@ int hmc_trajectory(hmc_ctx* c, double* phi, const double* pi0, const void* eta, 
     rc = energy(c, c->pi, phi, c->slots + SL_K0, s);
     if (rc) return rc;
 
-    auto solve = [&]() -> int {
-        if (n_pf == 0) return HMC_OK;
-        hmc_cg_stats cs;
-        int r = cg_dispatch(c, phi, c->chi, c->xsol, n_pf, &cs, s);
-        if (r == HMC_OK || r == HMC_ERR_NOT_CONVERGED || r == HMC_ERR_NONFINITE) merge_stats(stats, cs);
-        return r;
-    };
     auto restore = [&](int code) -> int {
         (void)hipMemcpyAsync(phi, c->phi_save, phib, hipMemcpyDeviceToDevice, s);
         (void)hipStreamSynchronize(s);
@@ -744,40 +804,13 @@ int hmc_trajectory(hmc_ctx* c, double* phi, const double* pi0, const void* eta, 
         stats->status = code;
         return code;
     };
-
-    // first half kick with the force at phi0
-    rc = solve();
+    rc = md_integrate(c, phi, c->pi, c->chi, n_pf, false, stats, s);
     if (rc) return restore(rc);
-    rc = launch_force(c, phi, c->xsol, n_pf, flags, nullptr, c->pi, h, nl > 0 ? 1 : 0, s);
-    if (rc) return restore(rc);
-    for (int step = 0; step < nl; ++step) {
-        hipLaunchKernelGGL(k_drift, dim3(elem_grid(3LL * c->vol)), dim3(kBlock), 0, s, phi, c->pi,
-                           eps, 3 * c->vol);
-        if (hipGetLastError() != hipSuccess) return restore(fail(HMC_ERR_HIP, "drift launch failed"));
-        rc = solve();
-        if (rc) return restore(rc);
-        // closing half kick of this step, then the opening half kick of the next one
-        rc = launch_force(c, phi, c->xsol, n_pf, flags, nullptr, c->pi, h, step + 1 < nl ? 2 : 1, s);
-        if (rc) return restore(rc);
-    }
-    if (n_pf > 0) {
-        rc = dot_re(c, c->chi, c->xsol, n_pf, c->slots + SL_SPF1, s);
-        if (rc) return restore(rc);
-    }
     rc = energy(c, c->pi, phi, c->slots + SL_K1, s);
     if (rc) return restore(rc);
     rc = read_slots(c, s);
     if (rc) return restore(rc);
-    const double* hs = c->h_slots;
-    stats->K0 = hs[SL_K0];
-    stats->S_b0 = hs[SL_SB0];
-    stats->S_pf0 = n_pf > 0 ? hs[SL_SPF0] : 0.0;
-    stats->K1 = hs[SL_K1];
-    stats->S_b1 = hs[SL_SB1];
-    stats->S_pf1 = n_pf > 0 ? hs[SL_SPF1] : 0.0;
-    stats->H0 = stats->K0 + stats->S_b0 + stats->S_pf0;
-    stats->H1 = stats->K1 + stats->S_b1 + stats->S_pf1;
-    stats->dH = stats->H1 - stats->H0;
+    fill_energies(c, n_pf, stats);
     if (!std::isfinite(stats->dH)) return restore(fail(HMC_ERR_NONFINITE, "dH is not finite"));
     stats->accepted = (u < std::exp(-stats->dH)) ? 1 : 0;
     stats->status = HMC_OK;
@@ -785,6 +818,31 @@ int hmc_trajectory(hmc_ctx* c, double* phi, const double* pi0, const void* eta, 
         HIPCHK(hipMemcpyAsync(phi, c->phi_save, phib, hipMemcpyDeviceToDevice, s));
         HIPCHK(hipStreamSynchronize(s));
     }
+    return HMC_OK;
+}
+
+int hmc_leapfrog(hmc_ctx* c, double* phi, double* pi, const void* chi, int n_pf,
+                 hmc_traj_stats* stats, void* stream) {
+    if (c == nullptr || phi == nullptr || pi == nullptr || stats == nullptr)
+        return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    int rc = need_ws(c);
+    if (rc) return rc;
+    if (n_pf < 0 || n_pf > c->cap) return fail(HMC_ERR_INVALID_ARG, "n_pf %d outside [0, %d]", n_pf, c->cap);
+    if (n_pf > 0 && chi == nullptr) return fail(HMC_ERR_INVALID_ARG, "chi is NULL");
+    if (!aligned16(phi) || !aligned16(pi) || (chi && !aligned16(chi))) return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    std::memset(stats, 0, sizeof(*stats));
+    rc = energy(c, pi, phi, c->slots + SL_K0, s);
+    if (rc) return rc;
+    rc = md_integrate(c, phi, pi, static_cast<const double2*>(chi), n_pf, true, stats, s);
+    if (rc) { stats->status = rc; return rc; }
+    rc = energy(c, pi, phi, c->slots + SL_K1, s);
+    if (rc) return rc;
+    rc = read_slots(c, s);
+    if (rc) return rc;
+    fill_energies(c, n_pf, stats);
+    stats->accepted = 1;
+    stats->status = HMC_OK;
     return HMC_OK;
 }
 

@@ -130,27 +130,40 @@ struct CgCtl {
     CgState* st_out;
     double* part;       // partial sums [4 kinds][cap][bpr]
     int cap;            // right-hand sides the buffers hold
-    int bpr;            // workgroups per right-hand side
-    int tpb;            // 256-site tiles per workgroup
+    int bpr;            // workgroups per right-hand side; workgroup b takes tiles b, b+bpr, ...
     int ntiles;         // tiles per right-hand side
+    int expect;         // the only partial kind that can be pending at this launch
 };
 
 __device__ __forceinline__ double* part_slot(const CgCtl& c, int kind, int k) {
     return c.part + (size_t(kind - 1) * c.cap + k) * c.bpr;
 }
 
-// Reduce the pending partials of right-hand side k and advance its state machine.
-// Every workgroup computes the same record (deterministic order); returned in S.
-__device__ __forceinline__ void cg_finalize(const CgCtl& c, int k, CgState& S) {
+constexpr int kStateWords = int(sizeof(CgState) / 4);
+static_assert(sizeof(CgState) % 4 == 0 && kStateWords <= kBlock, "state record layout");
+
+// The workgroup's copy of its right-hand side's record (one per kernel).
+__device__ __forceinline__ CgState& cg_shared() {
     __shared__ CgState sh;
-    if (threadIdx.x == 0) sh = c.st_in[k];
-    __syncthreads();
-    const int pend = sh.pending;
+    return sh;
+}
+
+// Reduce the pending partials of right-hand side k and advance its state machine into
+// cg_shared().  Every workgroup computes the same record (deterministic order).  The record
+// (24 dwords, one per lane) and the partials the host expects to be pending are loaded in
+// the same memory round trip; the partials are used only if the record says so.
+__device__ __forceinline__ void cg_finalize(const CgCtl& c, int k) {
+    CgState& sh = cg_shared();
+    const int t = threadIdx.x;
+    unsigned w = 0u;
+    if (t < kStateWords) w = reinterpret_cast<const unsigned*>(c.st_in + k)[t];
     double tot = 0.0;
-    if (pend != PEND_NONE) tot = sum_partials(part_slot(c, pend, k), c.bpr);
-    if (threadIdx.x == 0 && pend != PEND_NONE) {
+    if (c.expect != PEND_NONE) tot = sum_partials(part_slot(c, c.expect, k), c.bpr);
+    if (t < kStateWords) reinterpret_cast<unsigned*>(&sh)[t] = w;
+    __syncthreads();
+    if (t == 0 && sh.pending != PEND_NONE) {
         CgState& s = sh;
-        switch (pend) {
+        switch (s.pending) {
             case PEND_BB:
                 s.bb = tot;
                 s.stop_rr = s.tol2 * tot;
@@ -198,13 +211,15 @@ __device__ __forceinline__ void cg_finalize(const CgCtl& c, int k, CgState& S) {
         s.pending = PEND_NONE;
     }
     __syncthreads();
-    S = sh;
-    __syncthreads();
 }
 
-// Workgroup 0 of a right-hand side publishes the record for the next kernel.
-__device__ __forceinline__ void cg_publish(const CgCtl& c, int k, int blk, const CgState& S) {
-    if (blk == 0 && threadIdx.x == 0) c.st_out[k] = S;
+// Workgroup 0 of a right-hand side publishes the record for the next kernel (all threads
+// of the workgroup call this; changes made by thread 0 before it are included).
+__device__ __forceinline__ void cg_publish(const CgCtl& c, int k, int blk) {
+    __syncthreads();
+    if (blk == 0 && threadIdx.x < kStateWords)
+        reinterpret_cast<unsigned*>(c.st_out + k)[threadIdx.x] =
+            reinterpret_cast<const unsigned*>(&cg_shared())[threadIdx.x];
 }
 
 // ------------------------------------------------------------------------------------
@@ -302,15 +317,13 @@ struct CgVecs {
 
 // Map the launch onto (right-hand side, workgroup) and the workgroup's tile range.
 struct CgPos {
-    int k, blk, t0, t1;
+    int k, blk;
 };
 __device__ __forceinline__ CgPos cg_pos(const CgCtl& c) {
     const int logical = xcd_remap(blockIdx.x, gridDim.x);
     CgPos p;
     p.k = logical / c.bpr;
     p.blk = logical - p.k * c.bpr;
-    p.t0 = p.blk * c.tpb;
-    p.t1 = min(p.t0 + c.tpb, c.ntiles);
     return p;
 }
 
@@ -328,10 +341,10 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, CgVecs<R> v, const R* __restrict__ phi,
                                                  Lat lat, Coef<R> cf) {
     const CgPos pos = cg_pos(ctl);
-    CgState S;
-    cg_finalize(ctl, pos.k, S);
+    cg_finalize(ctl, pos.k);
+    const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
-        cg_publish(ctl, pos.k, pos.blk, S);
+        cg_publish(ctl, pos.k, pos.blk);
         return;
     }
     const R alpha = R(S.alpha), beta = R(S.beta);
@@ -344,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, CgVecs<R> v, const R
     C2<R>* t = v.t + off;
     SrcXpay<R> src{r, pin, beta, lat.vol};
     double part = 0.0;
-    for (int tile = pos.t0; tile < pos.t1; ++tile) {
+    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
         const int s = tile * kBlock + threadIdx.x;
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
@@ -363,10 +376,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, CgVecs<R> v, const R
         }
     }
     store_partial(ctl, PEND_TT, pos, part);
-    S.alpha = 0.0;
-    S.pbuf = 1 - pb;
-    S.pending = PEND_TT;
-    cg_publish(ctl, pos.k, pos.blk, S);
+    if (threadIdx.x == 0) {
+        CgState& W = cg_shared();
+        W.alpha = 0.0;
+        W.pbuf = 1 - pb;
+        W.pending = PEND_TT;
+    }
+    cg_publish(ctl, pos.k, pos.blk);
 }
 
 // CG step B:  r -= alpha_k M^dagger t;  partial |r|^2.
@@ -374,10 +390,10 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_cg_b(CgCtl ctl, CgVecs<R> v, const R* __restrict__ phi,
                                                  Lat lat, Coef<R> cf) {
     const CgPos pos = cg_pos(ctl);
-    CgState S;
-    cg_finalize(ctl, pos.k, S);
+    cg_finalize(ctl, pos.k);
+    const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
-        cg_publish(ctl, pos.k, pos.blk, S);
+        cg_publish(ctl, pos.k, pos.blk);
         return;
     }
     const R alpha = R(S.alpha_cur);
@@ -385,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(CgCtl ctl, CgVecs<R> v, const R
     SrcPlain<R> src{v.t + off, lat.vol};
     C2<R>* r = v.r + off;
     double part = 0.0;
-    for (int tile = pos.t0; tile < pos.t1; ++tile) {
+    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
         const int s = tile * kBlock + threadIdx.x;
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
@@ -403,8 +419,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(CgCtl ctl, CgVecs<R> v, const R
         }
     }
     store_partial(ctl, PEND_RR, pos, part);
-    S.pending = PEND_RR;
-    cg_publish(ctl, pos.k, pos.blk, S);
+    if (threadIdx.x == 0) cg_shared().pending = PEND_RR;
+    cg_publish(ctl, pos.k, pos.blk);
 }
 
 // Reliable update, part 1 (elementwise): fold the pending step into the FP64 solution,
@@ -413,17 +429,17 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_ru_fold(CgCtl ctl, double2* __restrict__ x64,
                                                     CgVecs<R> v, Lat lat, int filter) {
     const CgPos pos = cg_pos(ctl);
-    CgState S;
-    cg_finalize(ctl, pos.k, S);
+    cg_finalize(ctl, pos.k);
+    const CgState& S = cg_shared();
     if (!((1 << S.mode) & filter)) {
-        cg_publish(ctl, pos.k, pos.blk, S);
+        cg_publish(ctl, pos.k, pos.blk);
         return;
     }
     const double alpha = S.alpha;
     const size_t off = size_t(pos.k) * 4 * lat.vol;
     const C2<R>* p = (S.pbuf ? v.p1 : v.p0) + off;
     const bool separate = (void*)v.x != (void*)x64;
-    for (int tile = pos.t0; tile < pos.t1; ++tile) {
+    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
         const int s = tile * kBlock + threadIdx.x;
         if (s >= lat.vol) break;
 #pragma unroll
@@ -442,8 +458,9 @@ __global__ __launch_bounds__(kBlock) void k_ru_fold(CgCtl ctl, double2* __restri
             x64[i] = xv;
         }
     }
-    S.alpha = 0.0;
-    cg_publish(ctl, pos.k, pos.blk, S);
+    __syncthreads();
+    if (threadIdx.x == 0) cg_shared().alpha = 0.0;
+    cg_publish(ctl, pos.k, pos.blk);
 }
 
 // Reliable update, part 2: t64 = M x64 (FP64) for right-hand sides in `filter`.
@@ -452,13 +469,13 @@ __global__ __launch_bounds__(kBlock) void k_ru_apply(CgCtl ctl, const double2* _
                                                      const double* __restrict__ phi, Lat lat,
                                                      Coef<double> cf, int filter) {
     const CgPos pos = cg_pos(ctl);
-    CgState S;
-    cg_finalize(ctl, pos.k, S);
-    cg_publish(ctl, pos.k, pos.blk, S);
-    if (!((1 << S.mode) & filter)) return;
+    cg_finalize(ctl, pos.k);
+    const int mode = cg_shared().mode;
+    cg_publish(ctl, pos.k, pos.blk);
+    if (!((1 << mode) & filter)) return;
     const size_t off = size_t(pos.k) * 4 * lat.vol;
     SrcPlain<double> src{x64 + off, lat.vol};
-    for (int tile = pos.t0; tile < pos.t1; ++tile) {
+    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
         const int s = tile * kBlock + threadIdx.x;
         if (s >= lat.vol) break;
         const Nbr nb = neighbours(lat, s);
@@ -478,16 +495,15 @@ __global__ __launch_bounds__(kBlock) void k_ru_resid(CgCtl ctl, const double2* _
                                                      Coef<double> cf, C2<R>* __restrict__ r,
                                                      int filter) {
     const CgPos pos = cg_pos(ctl);
-    CgState S;
-    cg_finalize(ctl, pos.k, S);
-    if (!((1 << S.mode) & filter)) {
-        cg_publish(ctl, pos.k, pos.blk, S);
+    cg_finalize(ctl, pos.k);
+    if (!((1 << cg_shared().mode) & filter)) {
+        cg_publish(ctl, pos.k, pos.blk);
         return;
     }
     const size_t off = size_t(pos.k) * 4 * lat.vol;
     SrcPlain<double> src{t64 + off, lat.vol};
     double part = 0.0;
-    for (int tile = pos.t0; tile < pos.t1; ++tile) {
+    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
         const int s = tile * kBlock + threadIdx.x;
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
@@ -503,8 +519,8 @@ __global__ __launch_bounds__(kBlock) void k_ru_resid(CgCtl ctl, const double2* _
         }
     }
     store_partial(ctl, PEND_RU, pos, part);
-    S.pending = PEND_RU;
-    cg_publish(ctl, pos.k, pos.blk, S);
+    if (threadIdx.x == 0) cg_shared().pending = PEND_RU;
+    cg_publish(ctl, pos.k, pos.blk);
 }
 
 // CG start from x = 0: x64 = 0, r = b, both direction buffers and x_lo cleared, partial |b|^2.
@@ -516,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgCtl ctl, const double2* __
     const size_t off = size_t(pos.k) * 4 * lat.vol;
     const bool separate = (void*)v.x != (void*)x64;
     double part = 0.0;
-    for (int tile = pos.t0; tile < pos.t1; ++tile) {
+    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
         const int s = tile * kBlock + threadIdx.x;
         if (s < lat.vol) {
 #pragma unroll
@@ -533,21 +549,210 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgCtl ctl, const double2* __
         }
     }
     store_partial(ctl, PEND_BB, pos, part);
-    CgState S{};
-    S.tol2 = tol2;
-    S.maxit = maxit;
-    S.mode = CG_ACTIVE;
-    S.pending = PEND_BB;
-    cg_publish(ctl, pos.k, pos.blk, S);
+    if (threadIdx.x == 0) {
+        CgState& S = cg_shared();
+        S = CgState{};
+        S.tol2 = tol2;
+        S.maxit = maxit;
+        S.mode = CG_ACTIVE;
+        S.pending = PEND_BB;
+    }
+    cg_publish(ctl, pos.k, pos.blk);
 }
 
 // One workgroup per right-hand side: reduce whatever is pending and publish the record
 // (run before the host reads the status).
 __global__ __launch_bounds__(kBlock) void k_cg_finalize(CgCtl ctl) {
     const int k = blockIdx.x;
-    CgState S;
-    cg_finalize(ctl, k, S);
-    if (threadIdx.x == 0) ctl.st_out[k] = S;
+    cg_finalize(ctl, k);
+    cg_publish(ctl, k, 0);
+}
+
+// ------------------------------------------------------------------------------------
+// FP32 forms with two sites per thread.  Sites s (even) and s + 1 share a row (L is even),
+// so each component plane of a pair, and of its x+-1 and tau+-1 neighbours, is one aligned
+// 16-byte load; only the two outer y neighbours are single 8-byte loads.  Half the load
+// instructions of the one-site form, twice the bytes per instruction.
+__device__ __forceinline__ float4 f4(float a, float b, float c, float d) { return make_float4(a, b, c, d); }
+__device__ __forceinline__ float4 f4add(float4 a, float4 b) { return f4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
+// a + s*b
+__device__ __forceinline__ float4 f4axpy(float s, float4 b, float4 a) {
+    return f4(a.x + s * b.x, a.y + s * b.y, a.z + s * b.z, a.w + s * b.w);
+}
+__device__ __forceinline__ float f4norm2(float4 a) { return a.x * a.x + a.y * a.y + a.z * a.z + a.w * a.w; }
+__device__ __forceinline__ float4 ld4(const float2* p, size_t i) { return *reinterpret_cast<const float4*>(p + i); }
+__device__ __forceinline__ void st4(float2* p, size_t i, float4 v) { *reinterpret_cast<float4*>(p + i) = v; }
+
+struct SrcPlain2 {
+    const float2* __restrict__ v;
+    int vol;
+    __device__ __forceinline__ float4 pair(int c, int i) const { return ld4(v, size_t(c) * vol + i); }
+    __device__ __forceinline__ float2 one(int c, int i) const { return v[size_t(c) * vol + i]; }
+};
+
+struct SrcXpay2 {      // r + beta p
+    const float2* __restrict__ r;
+    const float2* __restrict__ p;
+    float beta;
+    int vol;
+    __device__ __forceinline__ float4 pair(int c, int i) const {
+        return f4axpy(beta, ld4(p, size_t(c) * vol + i), ld4(r, size_t(c) * vol + i));
+    }
+    __device__ __forceinline__ float2 one(int c, int i) const {
+        return axpy<float>(beta, p[size_t(c) * vol + i], r[size_t(c) * vol + i]);
+    }
+};
+
+// The stencil of Eq. (17) at sites s (even) and s + 1 (lanes .x .y and .z .w of each float4).
+template <bool DAG, class Src>
+__device__ __forceinline__ void dslash_pair(const Src& src, const float* __restrict__ phi,
+                                            const Lat& lat, const Coef<float>& cf, const Nbr& nb,
+                                            int s, float4 (&out)[4], float4 (&cen)[4]) {
+    const int vol = lat.vol, L = lat.L;
+    const int yl = nb.ym;                                   // y - 1 of site s
+    const int yr = (nb.y + 2 == L) ? s + 2 - L : s + 2;     // y + 1 of site s + 1
+    const int st = DAG ? nb.tm : nb.tp;
+    const float ts = float(DAG ? nb.sbwd : nb.sfwd);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) cen[c] = src.pair(c, s);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int a = c >> 1;
+        const float4 xp = src.pair(c, nb.xp), xm = src.pair(c, nb.xm), tt = src.pair(c, st);
+        const float2 lo = src.one(c, yl), hi = src.one(c, yr);
+        const float4 ce = cen[c];
+        const float dg = cf.diag[a], h0 = cf.hop[a][0], h1 = cf.hop[a][1];
+        float4 o;
+        o.x = dg * ce.x + h0 * (xp.x + xm.x) + h1 * (lo.x + ce.z) + ts * tt.x;
+        o.y = dg * ce.y + h0 * (xp.y + xm.y) + h1 * (lo.y + ce.w) + ts * tt.y;
+        o.z = dg * ce.z + h0 * (xp.z + xm.z) + h1 * (ce.x + hi.x) + ts * tt.z;
+        o.w = dg * ce.w + h0 * (xp.w + xm.w) + h1 * (ce.y + hi.y) + ts * tt.w;
+        out[c] = o;
+    }
+    const float g0 = cf.cpl * float(nb.stag), g1 = -g0;     // (-1)^(x+y) flips between s, s+1
+    const float2 P1 = *reinterpret_cast<const float2*>(phi + s);
+    const float2 P2 = *reinterpret_cast<const float2*>(phi + vol + s);
+    const float2 P3 = *reinterpret_cast<const float2*>(phi + 2 * vol + s);
+    const float q1a = g0 * P1.x, q2a = g0 * P2.x, q3a = g0 * P3.x;
+    const float q1b = g1 * P1.y, q2b = g1 * P2.y, q3b = g1 * P3.y;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const float4 u = cen[2 * (1 - a)], w = cen[2 * (1 - a) + 1];
+        out[2 * a].x += q3a * u.x + q1a * w.x + q2a * w.y;
+        out[2 * a].y += q3a * u.y + q1a * w.y - q2a * w.x;
+        out[2 * a].z += q3b * u.z + q1b * w.z + q2b * w.w;
+        out[2 * a].w += q3b * u.w + q1b * w.w - q2b * w.z;
+        out[2 * a + 1].x += q1a * u.x - q2a * u.y - q3a * w.x;
+        out[2 * a + 1].y += q1a * u.y + q2a * u.x - q3a * w.y;
+        out[2 * a + 1].z += q1b * u.z - q2b * u.w - q3b * w.z;
+        out[2 * a + 1].w += q1b * u.w + q2b * u.z - q3b * w.w;
+    }
+}
+
+// out_k = M in_k (or M^dagger), FP32, one 512-site tile per workgroup.
+template <bool DAG>
+__global__ __launch_bounds__(kBlock) void k_apply2(const float2* __restrict__ in,
+                                                   float2* __restrict__ out,
+                                                   const float* __restrict__ phi, Lat lat,
+                                                   Coef<float> cf, int nblk) {
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const int k = logical / nblk, blk = logical - k * nblk;
+    const int s = 2 * (blk * kBlock + threadIdx.x);
+    if (s >= lat.vol) return;
+    const size_t off = size_t(k) * 4 * lat.vol;
+    SrcPlain2 src{in + off, lat.vol};
+    const Nbr nb = neighbours(lat, s);
+    float4 o[4], cen[4];
+    dslash_pair<DAG>(src, phi, lat, cf, nb, s, o, cen);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) st4(out + off, size_t(c) * lat.vol + s, o[c]);
+}
+
+// CG step A, FP32 pair form (same algebra as k_cg_a).
+__global__ __launch_bounds__(kBlock) void k_cg_a2(CgCtl ctl, CgVecs<float> v,
+                                                  const float* __restrict__ phi, Lat lat,
+                                                  Coef<float> cf) {
+    const CgPos pos = cg_pos(ctl);
+    cg_finalize(ctl, pos.k);
+    const CgState& S = cg_shared();
+    if (S.mode != CG_ACTIVE) {
+        cg_publish(ctl, pos.k, pos.blk);
+        return;
+    }
+    const float alpha = float(S.alpha), beta = float(S.beta);
+    const int pb = S.pbuf;
+    const size_t off = size_t(pos.k) * 4 * lat.vol;
+    const float2* pin = (pb ? v.p1 : v.p0) + off;
+    float2* pout = (pb ? v.p0 : v.p1) + off;
+    const float2* r = v.r + off;
+    float2* x = v.x + off;
+    float2* t = v.t + off;
+    SrcXpay2 src{r, pin, beta, lat.vol};
+    double part = 0.0;
+    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
+        const int s = 2 * (tile * kBlock + threadIdx.x);
+        if (s < lat.vol) {
+            const Nbr nb = neighbours(lat, s);
+            float4 o[4], pn[4];
+            dslash_pair<false>(src, phi, lat, cf, nb, s, o, pn);
+            float acc = 0.f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const size_t i = size_t(c) * lat.vol + s;
+                st4(x, i, f4axpy(alpha, ld4(pin, i), ld4(x, i)));
+                st4(pout, i, pn[c]);
+                st4(t, i, o[c]);
+                acc += f4norm2(o[c]);
+            }
+            part += double(acc);
+        }
+    }
+    store_partial(ctl, PEND_TT, pos, part);
+    if (threadIdx.x == 0) {
+        CgState& W = cg_shared();
+        W.alpha = 0.0;
+        W.pbuf = 1 - pb;
+        W.pending = PEND_TT;
+    }
+    cg_publish(ctl, pos.k, pos.blk);
+}
+
+// CG step B, FP32 pair form (same algebra as k_cg_b).
+__global__ __launch_bounds__(kBlock) void k_cg_b2(CgCtl ctl, CgVecs<float> v,
+                                                  const float* __restrict__ phi, Lat lat,
+                                                  Coef<float> cf) {
+    const CgPos pos = cg_pos(ctl);
+    cg_finalize(ctl, pos.k);
+    const CgState& S = cg_shared();
+    if (S.mode != CG_ACTIVE) {
+        cg_publish(ctl, pos.k, pos.blk);
+        return;
+    }
+    const float alpha = float(S.alpha_cur);
+    const size_t off = size_t(pos.k) * 4 * lat.vol;
+    SrcPlain2 src{v.t + off, lat.vol};
+    float2* r = v.r + off;
+    double part = 0.0;
+    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
+        const int s = 2 * (tile * kBlock + threadIdx.x);
+        if (s < lat.vol) {
+            const Nbr nb = neighbours(lat, s);
+            float4 o[4], cen[4];
+            dslash_pair<true>(src, phi, lat, cf, nb, s, o, cen);
+            float acc = 0.f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const size_t i = size_t(c) * lat.vol + s;
+                const float4 rn = f4axpy(-alpha, o[c], ld4(r, i));
+                st4(r, i, rn);
+                acc += f4norm2(rn);
+            }
+            part += double(acc);
+        }
+    }
+    store_partial(ctl, PEND_RR, pos, part);
+    if (threadIdx.x == 0) cg_shared().pending = PEND_RR;
+    cg_publish(ctl, pos.k, pos.blk);
 }
 
 // ------------------------------------------------------------------------------------

@@ -226,6 +226,19 @@ class HMC:
         self._call("hmc_boson_action", _ptr(phi), ctypes.byref(S), _stream())
         return S.value
 
+    def leapfrog(self, phi, pi, chi):
+        """Molecular dynamics only: phi and pi are updated in place; chi is held fixed."""
+        self._phi(phi)
+        self._phi(pi)
+        n = 0
+        if chi is not None and chi.numel() > 0:
+            chi, n = self._spinors(chi)
+        st = HmcTrajStats()
+        code = self.lib.hmc_leapfrog(self._ctx, _ptr(phi), _ptr(pi), _ptr(chi) if n else None, n,
+                                     ctypes.byref(st), _stream())
+        check(code, "hmc_leapfrog")
+        return _traj_dict(st, code)
+
     def trajectory(self, phi, pi0, eta, u):
         """One trajectory; phi is updated in place.  Returns the stats as a dict."""
         self._phi(phi)
@@ -241,6 +254,12 @@ class HMC:
         if code != _lib.HMC_OK:
             check(code, "hmc_trajectory")
         return out
+
+
+def _traj_dict(st, code):
+    out = {f: getattr(st, f) for f, _ in HmcTrajStats._fields_}
+    out["code"] = code
+    return out
 
 
 def test_site(L, Lt, s):
