@@ -215,12 +215,30 @@ typedef struct hmc_kernel_times {
 
 int hmc_set_kernel_timing(hmc_ctx* ctx, int enable);
 
-/* Launch shape of the CG kernels: at most max_per_rhs workgroups per right-hand side
- * (1..4096; default 1024), each sweeping a contiguous range of 256-site tiles.  Results
- * do not depend on it beyond the order of the FP64 partial sums.  hmc_get_cg_workgroups
- * returns the count in use (the request rounded so that no workgroup is idle). */
-int hmc_set_cg_workgroups(hmc_ctx* ctx, int max_per_rhs);
-int hmc_get_cg_workgroups(const hmc_ctx* ctx);
+/* Launch shape of the CG kernels for solves in `precision` (HMC_FP64, HMC_MIXED, or -1
+ * for both): at most max_per_rhs workgroups per right-hand side (1..4096; defaults 1024
+ * FP64, 512 mixed); workgroup b sweeps tiles b, b + count, ...  Results depend on it only
+ * through the order of the FP64 partial sums.  hmc_get_cg_workgroups returns the count in
+ * use for `precision` (the request capped at the number of tiles). */
+int hmc_set_cg_workgroups(hmc_ctx* ctx, int precision, int max_per_rhs);
+int hmc_get_cg_workgroups(const hmc_ctx* ctx, int precision);
+
+/* Result of hmc_autotune (host struct). */
+typedef struct hmc_tune_result {
+    int    cg_workgroups[2];   /* chosen workgroups per right-hand side: [0] FP64, [1] mixed  */
+    double us_per_iter[2];     /* measured time per CG iteration at the choice (microseconds) */
+    int    candidates;         /* launch shapes timed                                          */
+} hmc_tune_result;
+
+/* Autotuner of the CG launch shape.  For each precision, times 100 CG iterations on the
+ * caller's phi and right-hand sides b (n complex128 spinors, n <= max_rhs) at each
+ * candidate workgroup count (128 ... 4096, capped at the tile count) with HIP events on the
+ * stream, keeps the fastest, and records the choice process-wide so that later contexts of
+ * the same lattice, right-hand-side count and device start with it.  Uses the context's
+ * workspace (no other allocation); the run parameters are restored afterwards.
+ * Synchronises the stream.  Errors: as hmc_cg_solve. */
+int hmc_autotune(hmc_ctx* ctx, const double* phi, const void* b, int n, hmc_tune_result* out,
+                 void* stream);
 int hmc_get_kernel_times(const hmc_ctx* ctx, hmc_kernel_times* out);
 
 /* Text for an HMC_* code. */

@@ -27,7 +27,7 @@ EXPORTED = [
     "hmc_force_from_solution", "hmc_pf_action", "hmc_boson_action", "hmc_trajectory",
     "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap",
     "hmc_set_kernel_timing", "hmc_get_kernel_times", "hmc_set_cg_workgroups",
-    "hmc_get_cg_workgroups", "hmc_leapfrog",
+    "hmc_get_cg_workgroups", "hmc_leapfrog", "hmc_autotune",
 ]
 
 
@@ -73,6 +73,11 @@ class HmcTrajStats(ctypes.Structure):
         ("max_true_resid", ctypes.c_double),
         ("status", ctypes.c_int),
     ]
+
+
+class HmcTuneResult(ctypes.Structure):
+    _fields_ = [("cg_workgroups", ctypes.c_int * 2), ("us_per_iter", ctypes.c_double * 2),
+                ("candidates", ctypes.c_int)]
 
 
 class HmcKernelTimes(ctypes.Structure):
@@ -122,8 +127,9 @@ def load():
         "hmc_test_xcd_remap": (I, [I, I]),
         "hmc_set_kernel_timing": (I, [P, I]),
         "hmc_get_kernel_times": (I, [P, ctypes.POINTER(HmcKernelTimes)]),
-        "hmc_set_cg_workgroups": (I, [P, I]),
-        "hmc_get_cg_workgroups": (I, [P]),
+        "hmc_set_cg_workgroups": (I, [P, I, I]),
+        "hmc_get_cg_workgroups": (I, [P, I]),
+        "hmc_autotune": (I, [P, P, P, I, ctypes.POINTER(HmcTuneResult), P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

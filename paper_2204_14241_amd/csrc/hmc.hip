@@ -12,6 +12,9 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/hmc.h"
@@ -50,7 +53,8 @@ size_t align_up(size_t n, size_t a) { return (n + a - 1) / a * a; }
 
 constexpr int kCheckEvery = 32;     // FP64 CG: iterations between host status reads
 constexpr int kSlots = 32;          // device scalars (energies, actions)
-constexpr int kDefaultBpr = 1024;   // default CG workgroups per right-hand side
+constexpr int kDefaultBpr64 = 1024; // default CG workgroups per right-hand side, FP64
+constexpr int kDefaultBpr32 = 512;  // ... mixed precision (FP32 pair kernels)
 constexpr int kMaxBpr = 4096;       // largest accepted (sizes the partial-sum buffer)
 
 // Slot indices in the device scalar area.
@@ -69,7 +73,9 @@ struct hmc_ctx {
     int cap = 1;            // right-hand sides the workspace holds
     int nblk = 0;           // 256-site tiles per right-hand side (one site per thread)
     int nblk2 = 0;          // 512-site tiles per right-hand side (FP32 pair kernels)
-    int bpr = 0;            // CG workgroups per right-hand side
+    int bpr = 0;            // CG workgroups per right-hand side of the solve in flight
+    int bpr64 = 0;          // ... chosen for FP64 solves
+    int bpr32 = 0;          // ... chosen for mixed-precision solves
     int seq = 0;            // CG launch counter (selects the state record buffer)
     Lat lat{};
     Coef<double> cf64{};
@@ -225,6 +231,7 @@ static int cg_run(hmc_ctx* c, const double* phi64, const double2* b, double2* x,
     CgVecs<R> v = KrylovBufs<R>::get(c, x);
     const R* phik = KrylovBufs<R>::phi(c, phi64);
     const Coef<R> cf = KrylovBufs<R>::cf(c);
+    c->bpr = mixed ? c->bpr32 : c->bpr64;
     const int g = c->bpr * n;
     if (mixed) {
         hipLaunchKernelGGL(k_to_f32, dim3(elem_grid(3LL * c->vol)), dim3(kBlock), 0, s, phi64,
@@ -388,9 +395,22 @@ static size_t ws_layout(hmc_ctx* c, char* base) {
 
 // CG launch shape: at most max_bpr workgroups per right-hand side; workgroup b takes
 // tiles b, b + bpr, ... (so every consumer reduces at most kMaxBpr partials).
-static void set_cg_shape(hmc_ctx* c, int max_bpr) {
-    c->bpr = c->nblk2 < max_bpr ? c->nblk2 : max_bpr;
+static int clamp_bpr(const hmc_ctx* c, int max_bpr) { return c->nblk2 < max_bpr ? c->nblk2 : max_bpr; }
+
+static void set_cg_shape(hmc_ctx* c, int precision, int max_bpr) {
+    if (precision != HMC_MIXED) c->bpr64 = clamp_bpr(c, max_bpr);
+    if (precision != HMC_FP64) c->bpr32 = clamp_bpr(c, max_bpr);
 }
+
+// Process-wide memory of autotuned shapes, keyed by lattice, right-hand sides and device.
+struct TuneKey {
+    int L, Lt, n, dev;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(L, Lt, n, dev) < std::tie(o.L, o.Lt, o.n, o.dev);
+    }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, std::pair<int, int>> g_tuned;   // -> (bpr64, bpr32)
 
 // --------------------------------------------------------------------------------------
 // C ABI
@@ -452,7 +472,16 @@ int hmc_create(int L, int Lt, double dtau, const hmc_params* params, hmc_ctx** o
         delete c;
         return fail(HMC_ERR_HIP, "hipGetDevice failed");
     }
-    set_cg_shape(c, kDefaultBpr);
+    set_cg_shape(c, HMC_FP64, kDefaultBpr64);
+    set_cg_shape(c, HMC_MIXED, kDefaultBpr32);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(TuneKey{L, Lt, c->cap, c->device});
+        if (it != g_tuned.end()) {
+            c->bpr64 = it->second.first;
+            c->bpr32 = it->second.second;
+        }
+    }
     c->need = ws_layout(c, nullptr);
     if (hipHostMalloc((void**)&c->h_st, sizeof(CgState) * 2 * size_t(c->cap), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_slots, sizeof(double) * kSlots, hipHostMallocDefault) != hipSuccess ||
@@ -476,15 +505,81 @@ int hmc_set_kernel_timing(hmc_ctx* c, int enable) {
     return HMC_OK;
 }
 
-int hmc_set_cg_workgroups(hmc_ctx* c, int max_per_rhs) {
+int hmc_set_cg_workgroups(hmc_ctx* c, int precision, int max_per_rhs) {
     if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
+    if (precision != HMC_FP64 && precision != HMC_MIXED && precision != -1)
+        return fail(HMC_ERR_INVALID_ARG, "precision must be HMC_FP64, HMC_MIXED or -1");
     if (max_per_rhs < 1 || max_per_rhs > kMaxBpr)
         return fail(HMC_ERR_INVALID_ARG, "workgroups per right-hand side must lie in [1, %d]", kMaxBpr);
-    set_cg_shape(c, max_per_rhs);
+    set_cg_shape(c, precision, max_per_rhs);
     return HMC_OK;
 }
 
-int hmc_get_cg_workgroups(const hmc_ctx* c) { return c ? c->bpr : -1; }
+int hmc_get_cg_workgroups(const hmc_ctx* c, int precision) {
+    if (c == nullptr) return -1;
+    return precision == HMC_MIXED ? c->bpr32 : c->bpr64;
+}
+
+static int check_solve_args(hmc_ctx* c, const void* phi, const void* b, const void* x, int n);
+
+int hmc_autotune(hmc_ctx* c, const double* phi, const void* b, int n, hmc_tune_result* out,
+                 void* stream) {
+    int rc = check_solve_args(c, phi, b, c ? c->xsol : nullptr, n);
+    if (rc) return rc;
+    if (out == nullptr) return fail(HMC_ERR_INVALID_ARG, "out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    static const int cand[] = {128, 256, 384, 512, 768, 1024, 1536, 2048, 4096};
+    const hmc_params saved = c->p;
+    const int iters = 100;
+    std::memset(out, 0, sizeof(*out));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int result = HMC_OK;
+    for (int pi = 0; pi < 2 && result == HMC_OK; ++pi) {
+        const int prec = pi == 0 ? HMC_FP64 : HMC_MIXED;
+        c->p.precision = prec;
+        c->p.cg_tol = 1e-30;           // never converges: every candidate runs `iters` iterations
+        c->p.cg_maxit = iters;
+        if (prec == HMC_MIXED && c->p.reliable_every < 1) c->p.reliable_every = 50;
+        double best = 1e300;
+        int best_bpr = 0, last = -1;
+        for (int cb : cand) {
+            const int bpr = clamp_bpr(c, cb);
+            if (bpr == last) continue;
+            last = bpr;
+            set_cg_shape(c, prec, bpr);
+            float ms = 0.f;
+            for (int rep = 0; rep < 2; ++rep) {    // first run warms caches and code
+                if (hipEventRecord(e0, s) != hipSuccess) { result = HMC_ERR_HIP; break; }
+                const int r = cg_dispatch(c, phi, static_cast<const double2*>(b), c->xsol, n, nullptr, s);
+                if (r != HMC_OK && r != HMC_ERR_NOT_CONVERGED) { result = r; break; }
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { result = HMC_ERR_HIP; break; }
+            }
+            if (result != HMC_OK) break;
+            out->candidates += 1;
+            const double us = 1e3 * ms / iters;
+            if (us < best) { best = us; best_bpr = bpr; }
+        }
+        if (result == HMC_OK) {
+            set_cg_shape(c, prec, best_bpr);
+            out->cg_workgroups[pi] = best_bpr;
+            out->us_per_iter[pi] = best;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->p = saved;
+    if (result != HMC_OK) {
+        set_cg_shape(c, HMC_FP64, kDefaultBpr64);
+        set_cg_shape(c, HMC_MIXED, kDefaultBpr32);
+        return result == HMC_ERR_HIP ? fail(result, "autotune: HIP call failed") : result;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[TuneKey{c->L, c->Lt, c->cap, c->device}] = {c->bpr64, c->bpr32};
+    return HMC_OK;
+}
 
 int hmc_get_kernel_times(const hmc_ctx* c, hmc_kernel_times* out) {
     if (c == nullptr || out == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL argument");

@@ -116,10 +116,25 @@ class HMC:
     def set_kernel_timing(self, enable=True):
         check(self.lib.hmc_set_kernel_timing(self._ctx, 1 if enable else 0), "hmc_set_kernel_timing")
 
-    def set_cg_workgroups(self, n):
-        """Workgroups per right-hand side of the CG kernels; returns the count in use."""
-        check(self.lib.hmc_set_cg_workgroups(self._ctx, int(n)), "hmc_set_cg_workgroups")
-        return self.lib.hmc_get_cg_workgroups(self._ctx)
+    def set_cg_workgroups(self, n, precision=None):
+        """Workgroups per right-hand side of the CG kernels ("fp64", "mixed" or both);
+        returns {precision: count in use}."""
+        pr = {None: -1, "fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]
+        check(self.lib.hmc_set_cg_workgroups(self._ctx, pr, int(n)), "hmc_set_cg_workgroups")
+        return self.cg_workgroups()
+
+    def cg_workgroups(self):
+        return {"fp64": self.lib.hmc_get_cg_workgroups(self._ctx, HMC_FP64),
+                "mixed": self.lib.hmc_get_cg_workgroups(self._ctx, HMC_MIXED)}
+
+    def autotune(self, phi, b):
+        """Pick the CG launch shape for each precision by timing (see hmc_autotune)."""
+        self._phi(phi)
+        b, n = self._spinors(b)
+        r = _lib.HmcTuneResult()
+        self._call("hmc_autotune", _ptr(phi), _ptr(b), n, ctypes.byref(r), _stream())
+        return {"fp64": (r.cg_workgroups[0], r.us_per_iter[0]),
+                "mixed": (r.cg_workgroups[1], r.us_per_iter[1]), "candidates": r.candidates}
 
     def kernel_times(self):
         """{name: (average ms, samples)} of the sampled CG kernels."""

@@ -90,3 +90,27 @@ def test_mixed_matches_fp64_at_80x80x200(hip):
     assert rel <= 1e-10
     assert dS < 1e-9
     assert dF < 1e-7
+
+
+def test_autotune_then_solve(hip):
+    """The autotuner picks a launch shape per precision; solves stay correct with it, and a
+    new context of the same lattice starts from the remembered choice."""
+    L, Lt = 12, 40
+    m = O.Model(L=L, Lt=Lt)
+    g = S.rng(70)
+    phi = S.draw_phi(g, L, Lt, 0.5)
+    b = S.draw_spinor(g, L, Lt, 1)
+    h = hip.HMC(L, Lt, cg_tol=1e-10)
+    res = h.autotune(torch.from_numpy(phi).cuda(), torch.from_numpy(b).cuda())
+    say(f"autotune {L}x{L}x{Lt}: {res}")
+    ntiles2 = (L * L * Lt // 2 + 255) // 256
+    for prec in ("fp64", "mixed"):
+        wg, us = res[prec]
+        assert 1 <= wg <= ntiles2 and us > 0
+    assert h.cg_workgroups() == {"fp64": res["fp64"][0], "mixed": res["mixed"][0]}
+    h2 = hip.HMC(L, Lt, cg_tol=1e-10, precision="mixed")
+    assert h2.cg_workgroups() == h.cg_workgroups()
+    for hh in (h, h2):
+        x, st = hh.cg_solve(torch.from_numpy(phi).cuda(), torch.from_numpy(b).cuda())
+        r = b[0] - O.apply_MdagM(m, phi, x.cpu().numpy()[0])
+        assert np.linalg.norm(r) / np.linalg.norm(b[0]) <= 1e-10
