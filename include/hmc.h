@@ -241,6 +241,89 @@ int hmc_autotune(hmc_ctx* ctx, const double* phi, const void* b, int n, hmc_tune
                  void* stream);
 int hmc_get_kernel_times(const hmc_ctx* ctx, hmc_kernel_times* out);
 
+/* Replay the CG status chunks from HIP graphs (enable != 0) instead of launching each
+ * kernel.  A chunk (reliable_every FP32 iterations plus the FP64 reliable update in mixed
+ * precision, 32 iterations plus the residual check in FP64) is captured once per solve shape
+ * (precision, pointers, right-hand sides, launch shape, coefficients) and relaunched on the
+ * caller's stream; results are bitwise those of eager launches.  Capture uses a private
+ * stream of the context.  Default: off for a single lattice, on for a batch. */
+int hmc_set_graphs(hmc_ctx* ctx, int enable);
+
+/* -----------------------------------------------------------------------------------------
+ * Batch of independent lattices.
+ *
+ * The study of the phase diagram (Results, "Numerical results"; Supplementary Note 1) and
+ * the scaling studies (Supplementary Note 6) run many independent Markov chains at
+ * different L, L_tau and boson mass r.  A batch advances nchains such lattices together:
+ * every CG launch and every site kernel covers all of them, so small lattices still fill
+ * the GPU, and each chain keeps its own convergence test, energies and Metropolis
+ * decision.  All chains share dtau and every hmc_params field except r (per chain); each
+ * chain carries params.n_pf right-hand sides.
+ *
+ * Layouts (device, caller-owned, 16-byte aligned): the per-chain arrays of the single-
+ * lattice layout concatenated in chain order.
+ *   phi, pi   : double, chain i at elements [phi_offsets[i], phi_offsets[i+1]),
+ *               3 * L_tau_i * L_i^2 of them.
+ *   spinors   : complex128 (FP64) or complex64 (HMC_MIXED in hmc_batch_apply), chain i at
+ *               complex elements [spinor_offsets[i], spinor_offsets[i+1]) holding its n_pf
+ *               right-hand sides one after another.
+ * hmc_batch_layout() returns both offset tables.  A batch is not thread-safe; the library
+ * allocates no device memory (workspace as for one lattice). */
+typedef struct hmc_batch hmc_batch;
+
+/* L, L_tau, r: host arrays of nchains entries.  Each lattice obeys the rules of hmc_create;
+ * params->n_pf >= 1.  Errors: HMC_ERR_INVALID_ARG (geometry, parameters, or more than
+ * 16384 chain-right-hand-side pairs, or 2^31 complex elements), HMC_ERR_HIP. */
+int hmc_batch_create(int nchains, const int* L, const int* L_tau, const double* r, double dtau,
+                     const hmc_params* params, hmc_batch** out);
+int hmc_batch_destroy(hmc_batch* batch);
+size_t hmc_batch_workspace_bytes(const hmc_batch* batch);
+int hmc_batch_set_workspace(hmc_batch* batch, void* ptr, size_t bytes);
+
+/* phi_offsets, spinor_offsets: host arrays of nchains + 1 entries (element and complex
+ * offsets, see above; the last entry is the total). */
+int hmc_batch_layout(const hmc_batch* batch, long long* phi_offsets, long long* spinor_offsets);
+
+/* As hmc_set_cg_workgroups, per (chain, right-hand side); each is capped at the tile count
+ * of its lattice.  hmc_batch_get_cg_workgroups returns the requested maximum. */
+int hmc_batch_set_cg_workgroups(hmc_batch* batch, int precision, int max_per_unit);
+int hmc_batch_get_cg_workgroups(const hmc_batch* batch, int precision);
+int hmc_batch_set_graphs(hmc_batch* batch, int enable);
+
+/* Replace the run parameters; n_pf must equal the value given at creation. */
+int hmc_batch_set_params(hmc_batch* batch, const hmc_params* params);
+
+/* out = M in (dagger = 0) or M^dagger in (dagger != 0), Eq. (17), for every right-hand side
+ * of every chain.  precision HMC_FP64: phi double, in/out complex128; HMC_MIXED: phi float,
+ * in/out complex64.  Asynchronous on the stream. */
+int hmc_batch_apply(hmc_batch* batch, int dagger, int precision, const void* phi, const void* in,
+                    void* out, void* stream);
+
+/* Solve (M^dagger M) x = b for every right-hand side of every chain (Methods, "Solving the
+ * linear system"; Eq. 22), each to params.cg_tol relative residual with its own stopping
+ * test, in params.precision.  iterations (int) and true_resid (double, the FP64 relative
+ * residual at exit) are optional host arrays of nchains * n_pf entries in chain-major order.
+ * Synchronises the stream.  Errors: as hmc_cg_solve. */
+int hmc_batch_cg_solve(hmc_batch* batch, const double* phi, const void* b, void* x,
+                       int* iterations, double* true_resid, void* stream);
+
+/* As hmc_autotune for the whole batch (the launch shape is shared by all chains); the
+ * choice is kept by the batch only. */
+int hmc_batch_autotune(hmc_batch* batch, const double* phi, const void* b, hmc_tune_result* out,
+                       void* stream);
+
+/* One HMC trajectory of every chain (Methods, "HMC"; Eq. 27-29): heat-bath chi = M^dagger eta
+ * per chain, n_leap leapfrog steps of size eps on all chains at once, then a Metropolis
+ * decision per chain with its own uniform u[i] (host array): chain i is accepted iff
+ * u[i] < exp(-dH_i).  Rejected chains get phi back from the start of the trajectory.
+ * dH (double) and accepted (int): host arrays of nchains entries.  totals: solver counts over
+ * all chains and accepted = the number of accepted chains.  pi0 is not modified.
+ * Synchronises the stream.  Errors: as hmc_trajectory; on an error every chain is rejected
+ * and phi restored. */
+int hmc_batch_trajectory(hmc_batch* batch, double* phi, const double* pi0, const void* eta,
+                         const double* u, double* dH, int* accepted, hmc_traj_stats* totals,
+                         void* stream);
+
 /* Text for an HMC_* code. */
 const char* hmc_strerror(int code);
 

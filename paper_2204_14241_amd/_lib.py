@@ -27,7 +27,11 @@ EXPORTED = [
     "hmc_force_from_solution", "hmc_pf_action", "hmc_boson_action", "hmc_trajectory",
     "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap",
     "hmc_set_kernel_timing", "hmc_get_kernel_times", "hmc_set_cg_workgroups",
-    "hmc_get_cg_workgroups", "hmc_leapfrog", "hmc_autotune",
+    "hmc_get_cg_workgroups", "hmc_leapfrog", "hmc_autotune", "hmc_set_graphs",
+    "hmc_batch_create", "hmc_batch_destroy", "hmc_batch_workspace_bytes",
+    "hmc_batch_set_workspace", "hmc_batch_layout", "hmc_batch_set_cg_workgroups",
+    "hmc_batch_get_cg_workgroups", "hmc_batch_set_graphs", "hmc_batch_set_params",
+    "hmc_batch_apply", "hmc_batch_cg_solve", "hmc_batch_autotune", "hmc_batch_trajectory",
 ]
 
 
@@ -130,6 +134,23 @@ def load():
         "hmc_set_cg_workgroups": (I, [P, I, I]),
         "hmc_get_cg_workgroups": (I, [P, I]),
         "hmc_autotune": (I, [P, P, P, I, ctypes.POINTER(HmcTuneResult), P]),
+        "hmc_set_graphs": (I, [P, I]),
+        "hmc_batch_create": (I, [I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D), D,
+                                 ctypes.POINTER(HmcParams), ctx_pp]),
+        "hmc_batch_destroy": (I, [P]),
+        "hmc_batch_workspace_bytes": (S, [P]),
+        "hmc_batch_set_workspace": (I, [P, P, S]),
+        "hmc_batch_layout": (I, [P, ctypes.POINTER(ctypes.c_longlong),
+                                 ctypes.POINTER(ctypes.c_longlong)]),
+        "hmc_batch_set_cg_workgroups": (I, [P, I, I]),
+        "hmc_batch_get_cg_workgroups": (I, [P, I]),
+        "hmc_batch_set_graphs": (I, [P, I]),
+        "hmc_batch_set_params": (I, [P, ctypes.POINTER(HmcParams)]),
+        "hmc_batch_apply": (I, [P, I, I, P, P, P, P]),
+        "hmc_batch_cg_solve": (I, [P, P, P, P, ctypes.POINTER(I), ctypes.POINTER(D), P]),
+        "hmc_batch_autotune": (I, [P, P, P, ctypes.POINTER(HmcTuneResult), P]),
+        "hmc_batch_trajectory": (I, [P, P, P, P, ctypes.POINTER(D), ctypes.POINTER(D),
+                                     ctypes.POINTER(I), ctypes.POINTER(HmcTrajStats), P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -1,19 +1,22 @@
 // hmc.hip -- host side of libhmc: context and workspace management, the C ABI of
-// include/hmc.h, the conjugate-gradient driver (FP64 and mixed precision with FP64
-// reliable updates) and the HMC trajectory driver.
+// include/hmc.h, the conjugate-gradient engine (FP64 and mixed precision with FP64 reliable
+// updates, eager or replayed from HIP graphs) and the HMC trajectory drivers for one lattice
+// and for a ragged batch of independent lattices.
 //
 // Every step of the path runs in the kernels of kernels.h; the host only sequences
-// launches on the caller's stream and reads back per-solve status words (CG
+// launches on the caller's stream and reads back per-solve status records (CG
 // convergence) and the energies of a trajectory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <string>
+#include <initializer_list>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -53,43 +56,88 @@ size_t align_up(size_t n, size_t a) { return (n + a - 1) / a * a; }
 
 constexpr int kCheckEvery = 32;     // FP64 CG: iterations between host status reads
 constexpr int kSlots = 32;          // device scalars (energies, actions)
+constexpr int kChainSlots = 8;      // per-lattice scalars in batch mode
 constexpr int kDefaultBpr64 = 1024; // default CG workgroups per right-hand side, FP64
 constexpr int kDefaultBpr32 = 512;  // ... mixed precision (FP32 pair kernels)
 constexpr int kMaxBpr = 4096;       // largest accepted (sizes the partial-sum buffer)
+// Mixed precision: an FP64 reliable update is due once the FP32 iterated |r| has fallen by
+// 1e-4 since the last true residual.  Beyond that the FP32 recurrence no longer tracks the
+// true residual, and the direction kept across the update would be stale.
+constexpr double kRuDrop2 = 1e-8;
 
-// Slot indices in the device scalar area.
+// Slot indices in the device scalar area (and in each lattice's block in batch mode).
 enum Slot : int {
     SL_K0 = 0, SL_SB0 = 1, SL_K1 = 2, SL_SB1 = 3, SL_SPF0 = 4, SL_SPF1 = 5, SL_TMP = 6,
     SL_TMP2 = 7,
 };
 
+int tiles1_host(int vol) { return (vol + kBlock - 1) / kBlock; }
+int tiles2_host(int vol) { return (vol / 2 + kBlock - 1) / kBlock; }
+
 }  // namespace
+
+// Batch-mode description: nchains independent lattices, nrhs right-hand sides each.
+struct BatchInfo {
+    int nchains = 0, nrhs = 0;
+    std::vector<Lat> lats;
+    std::vector<double> r;
+    std::vector<long long> phi_off;   // nchains + 1 prefix offsets (elements) of the boson fields
+    std::vector<long long> sp_off;    // nchains + 1 prefix offsets (complex) of the spinor blocks
+    std::vector<int> cfirst;          // nchains + 1 prefix of 256-site tiles (site kernels)
+    // device tables in the workspace; index 0: FP64 launch shape, 1: mixed precision
+    UnitDesc* units[2] = {nullptr, nullptr};
+    int2* blocks[2] = {nullptr, nullptr};
+    int nblocks[2] = {0, 0};
+    ChainDesc* chains = nullptr;
+    int2* cblocks = nullptr;
+    int* cfirst_dev = nullptr;
+    double* cslots = nullptr;         // nchains * kChainSlots
+    double* h_cslots = nullptr;       // pinned copy
+};
+
+// Graph-replay cache of the two status chunks of a solve (see cg_run).
+struct CgGraphs {
+    hipGraphExec_t exec[2] = {nullptr, nullptr};   // [0] first chunk, [1] later chunks
+    std::tuple<int, const void*, const void*, const void*, const void*, int, int, int, int, long>
+        key{};
+};
 
 struct hmc_ctx {
     int device = 0;
     int L = 0, Lt = 0, vol = 0;
     double dtau = 0.0;
     hmc_params p{};
-    int cap = 1;            // right-hand sides the workspace holds
+    int cap = 1;            // right-hand sides the workspace holds (one lattice)
     int nblk = 0;           // 256-site tiles per right-hand side (one site per thread)
     int nblk2 = 0;          // 512-site tiles per right-hand side (FP32 pair kernels)
-    int bpr = 0;            // CG workgroups per right-hand side of the solve in flight
-    int bpr64 = 0;          // ... chosen for FP64 solves
-    int bpr32 = 0;          // ... chosen for mixed-precision solves
+    int bpr64 = 0;          // CG workgroups per right-hand side, FP64 solves
+    int bpr32 = 0;          // ... mixed-precision solves
     int seq = 0;            // CG launch counter (selects the state record buffer)
+    long generation = 0;    // bumped when coefficients, workspace or launch shapes change
     Lat lat{};
     Coef<double> cf64{};
     Coef<float> cf32{};
     BosonCoef bc{};
+
+    // sizes of the workspace carve
+    long long vec_sites = 0;   // sites of one full set of right-hand sides
+    long long phi_sites = 0;   // sites of the boson field(s)
+    int nunits = 1;            // CG state records
+    int pslots = 0;            // CG partial-sum slots per kind (sum over units of the largest
+                               // workgroup count the unit can be given)
+    int ngblk = 0;             // 256-site tiles of the site-parallel kernels
+
+    bool is_batch = false;
+    BatchInfo bi;
 
     // workspace (caller-owned)
     char* ws = nullptr;
     size_t ws_bytes = 0;
     size_t need = 0;
     // carved pointers
-    CgState* st = nullptr;       // 2 * cap records (double-buffered by launch parity)
-    double* part = nullptr;      // CG partial sums: 4 kinds * cap * bpr
-    double* gpart = nullptr;     // generic reductions: 2 * nblk
+    CgState* st = nullptr;       // 2 * nunits records (double-buffered by launch parity)
+    double* part = nullptr;      // CG partial sums: 4 kinds * nunits * kMaxBpr
+    double* gpart = nullptr;     // site-kernel partial sums: 2 * ngblk
     double* slots = nullptr;
     double2 *r64 = nullptr, *p064 = nullptr, *p164 = nullptr, *t64 = nullptr;
     float2 *r32 = nullptr, *p032 = nullptr, *p132 = nullptr, *t32 = nullptr, *x32 = nullptr;
@@ -98,7 +146,7 @@ struct hmc_ctx {
     float* phi32 = nullptr;
 
     // pinned host status area
-    CgState* h_st = nullptr;     // 2 * cap records (double buffer)
+    CgState* h_st = nullptr;     // 2 * nunits records (double buffer)
     double* h_slots = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
 
@@ -106,10 +154,29 @@ struct hmc_ctx {
     bool timing = false;
     hipEvent_t tev[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     hmc_kernel_times kt{};
+
+    // graph replay of CG chunks
+    bool graphs = false;
+    hipStream_t cap_stream = nullptr;
+    CgGraphs cgg[2];             // [0] FP64, [1] mixed
+};
+
+// The batch handle is the same engine configured for ragged lattices.
+struct hmc_batch {
+    hmc_ctx c;
 };
 
 // --------------------------------------------------------------------------------------
 // helpers
+
+static BosonCoef boson_coef_of(double dt, double cv, double r, double u) {
+    BosonCoef b;
+    b.kt = 1.0 / (cv * cv * dt);
+    b.ks = dt;
+    b.kr = dt * r;
+    b.ku = dt * u;
+    return b;
+}
 
 static void set_coefs(hmc_ctx* c) {
     const double dt = c->dtau;
@@ -124,10 +191,8 @@ static void set_coefs(hmc_ctx* c) {
         for (int d = 0; d < 2; ++d) c->cf32.hop[a][d] = float(c->cf64.hop[a][d]);
     }
     c->cf32.cpl = float(c->cf64.cpl);
-    c->bc.kt = 1.0 / (p.c * p.c * dt);
-    c->bc.ks = dt;
-    c->bc.kr = dt * p.r;
-    c->bc.ku = dt * p.u;
+    c->bc = boson_coef_of(dt, p.c, p.r, p.u);
+    c->generation += 1;
 }
 
 static int check_params(const hmc_params* p) {
@@ -163,16 +228,152 @@ static int geometry_ok(int L, int Lt) {
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 static int need_ws(const hmc_ctx* c) {
-    if (c->ws == nullptr) return fail(HMC_ERR_WORKSPACE, "workspace not set (hmc_set_workspace)");
+    if (c->ws == nullptr) return fail(HMC_ERR_WORKSPACE, "workspace not set");
     return HMC_OK;
 }
 
-static int grid_for(const hmc_ctx* c, int n) { return c->nblk * n; }
-
 static int elem_grid(long long n) { return int((n + kBlock - 1) / kBlock); }
 
+// Workspace layout: one walk that either only measures (base == nullptr) or also
+// assigns the carved pointers.  Returns the bytes needed.
+static size_t ws_layout(hmc_ctx* c, char* base) {
+    const size_t VS = size_t(c->vec_sites), PS = size_t(c->phi_sites);
+    const size_t sp64 = 4 * VS * sizeof(double2), sp32 = 4 * VS * sizeof(float2);
+    const size_t nu = size_t(c->nunits);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off = align_up(off + bytes, 256);
+        return p;
+    };
+    char* st = take(sizeof(CgState) * 2 * nu);
+    char* part = take(sizeof(double) * 4 * size_t(c->pslots));
+    char* gpart = take(sizeof(double) * 2 * size_t(c->ngblk));
+    char* slots = take(sizeof(double) * kSlots);
+    char* v64 = take(4 * sp64);
+    char* v32 = take(5 * sp32);
+    char* tr = take(2 * sp64);
+    char* bos = take(2 * 3 * PS * sizeof(double));
+    char* f32 = take(3 * PS * sizeof(float));
+    char *un0 = nullptr, *un1 = nullptr, *bl0 = nullptr, *bl1 = nullptr, *ch = nullptr,
+         *cb = nullptr, *cf = nullptr, *cs = nullptr;
+    if (c->is_batch) {
+        const size_t nch = size_t(c->bi.nchains);
+        un0 = take(sizeof(UnitDesc) * nu);
+        un1 = take(sizeof(UnitDesc) * nu);
+        bl0 = take(sizeof(int2) * size_t(c->pslots));
+        bl1 = take(sizeof(int2) * size_t(c->pslots));
+        ch = take(sizeof(ChainDesc) * nch);
+        cb = take(sizeof(int2) * size_t(c->ngblk));
+        cf = take(sizeof(int) * (nch + 1));
+        cs = take(sizeof(double) * kChainSlots * nch);
+    }
+    if (base) {
+        c->st = reinterpret_cast<CgState*>(st);
+        c->part = reinterpret_cast<double*>(part);
+        c->gpart = reinterpret_cast<double*>(gpart);
+        c->slots = reinterpret_cast<double*>(slots);
+        c->r64 = reinterpret_cast<double2*>(v64);
+        c->p064 = reinterpret_cast<double2*>(v64 + sp64);
+        c->p164 = reinterpret_cast<double2*>(v64 + 2 * sp64);
+        c->t64 = reinterpret_cast<double2*>(v64 + 3 * sp64);
+        c->r32 = reinterpret_cast<float2*>(v32);
+        c->p032 = reinterpret_cast<float2*>(v32 + sp32);
+        c->p132 = reinterpret_cast<float2*>(v32 + 2 * sp32);
+        c->t32 = reinterpret_cast<float2*>(v32 + 3 * sp32);
+        c->x32 = reinterpret_cast<float2*>(v32 + 4 * sp32);
+        c->chi = reinterpret_cast<double2*>(tr);
+        c->xsol = reinterpret_cast<double2*>(tr + sp64);
+        c->pi = reinterpret_cast<double*>(bos);
+        c->phi_save = reinterpret_cast<double*>(bos + 3 * PS * sizeof(double));
+        c->phi32 = reinterpret_cast<float*>(f32);
+        if (c->is_batch) {
+            c->bi.units[0] = reinterpret_cast<UnitDesc*>(un0);
+            c->bi.units[1] = reinterpret_cast<UnitDesc*>(un1);
+            c->bi.blocks[0] = reinterpret_cast<int2*>(bl0);
+            c->bi.blocks[1] = reinterpret_cast<int2*>(bl1);
+            c->bi.chains = reinterpret_cast<ChainDesc*>(ch);
+            c->bi.cblocks = reinterpret_cast<int2*>(cb);
+            c->bi.cfirst_dev = reinterpret_cast<int*>(cf);
+            c->bi.cslots = reinterpret_cast<double*>(cs);
+        }
+    }
+    return off;
+}
+
+// CG launch shape: at most max_bpr workgroups per right-hand side (unit); workgroup b of a
+// unit takes tiles b, b + bpr, ... (so every consumer reduces at most kMaxBpr partials).
+static int clamp_bpr(int ntiles2, int max_bpr) { return ntiles2 < max_bpr ? ntiles2 : max_bpr; }
+
+// Batch: (re)write the unit and block tables of one precision's launch shape.
+static int upload_batch_shape(hmc_ctx* c, int pi, int max_bpr) {
+    BatchInfo& b = c->bi;
+    std::vector<UnitDesc> units(size_t(c->nunits));
+    std::vector<int2> blocks;
+    int part = 0;
+    for (int ch = 0; ch < b.nchains; ++ch) {
+        const Lat& lat = b.lats[size_t(ch)];
+        for (int k = 0; k < b.nrhs; ++k) {
+            const int u = ch * b.nrhs + k;
+            UnitDesc& d = units[size_t(u)];
+            d.lat = lat;
+            d.voff = b.sp_off[size_t(ch)] + 4LL * k * lat.vol;
+            d.phioff = b.phi_off[size_t(ch)];
+            d.bpr = clamp_bpr(tiles2_host(lat.vol), max_bpr);
+            d.part = part;
+            part += clamp_bpr(tiles2_host(lat.vol), kMaxBpr);
+            d.chain = ch;
+            d.pad = 0;
+            for (int w = 0; w < d.bpr; ++w) blocks.push_back(make_int2(u, w));
+        }
+    }
+    b.nblocks[pi] = int(blocks.size());
+    if (c->ws != nullptr) {
+        // launches already queued may still read the old tables
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(b.units[pi], units.data(), sizeof(UnitDesc) * units.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b.blocks[pi], blocks.data(), sizeof(int2) * blocks.size(), hipMemcpyHostToDevice));
+    }
+    return HMC_OK;
+}
+
+static int set_cg_shape(hmc_ctx* c, int precision, int max_bpr) {
+    if (precision != HMC_MIXED) c->bpr64 = c->is_batch ? max_bpr : clamp_bpr(c->nblk2, max_bpr);
+    if (precision != HMC_FP64) c->bpr32 = c->is_batch ? max_bpr : clamp_bpr(c->nblk2, max_bpr);
+    c->generation += 1;
+    if (c->is_batch) {
+        if (precision != HMC_MIXED) {
+            int rc = upload_batch_shape(c, 0, c->bpr64);
+            if (rc) return rc;
+        }
+        if (precision != HMC_FP64) {
+            int rc = upload_batch_shape(c, 1, c->bpr32);
+            if (rc) return rc;
+        }
+    }
+    return HMC_OK;
+}
+
+// Process-wide memory of autotuned shapes, keyed by lattice, right-hand sides and device.
+struct TuneKey {
+    int L, Lt, n, dev;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(L, Lt, n, dev) < std::tie(o.L, o.Lt, o.n, o.dev);
+    }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, std::pair<int, int>> g_tuned;   // -> (bpr64, bpr32)
+
 // --------------------------------------------------------------------------------------
-// conjugate gradient driver
+// geometry of a launch
+
+static GeoOne geo_one(const hmc_ctx* c, int bpr) { return GeoOne{c->lat, bpr}; }
+static GeoBatch geo_batch(const hmc_ctx* c, int pi) { return GeoBatch{c->bi.units[pi], c->bi.blocks[pi]}; }
+static CGeoOne cgeo_one(const hmc_ctx* c, int npf) { return CGeoOne{c->lat, c->bc, npf}; }
+static CGeoBatch cgeo_batch(const hmc_ctx* c) { return CGeoBatch{c->bi.chains, c->bi.cblocks}; }
+
+// --------------------------------------------------------------------------------------
+// conjugate-gradient engine
 
 template <typename R> struct KrylovBufs;
 template <> struct KrylovBufs<double> {
@@ -189,111 +390,164 @@ template <> struct KrylovBufs<float> {
 static bool finished(int mode) { return mode == CG_DONE || mode == CG_STOPPED || mode == CG_FAILED; }
 
 // Control block for the next CG launch; advances the state-record parity.
-static CgCtl next_ctl(hmc_ctx* c, int expect, int ntiles) {
+static CgCtl next_ctl(hmc_ctx* c, int expect) {
     CgCtl k;
-    k.expect = expect;
-    k.ntiles = ntiles;
-    k.st_in = c->st + size_t(c->seq & 1) * c->cap;
-    k.st_out = c->st + size_t((c->seq + 1) & 1) * c->cap;
+    k.st_in = c->st + size_t(c->seq & 1) * c->nunits;
+    k.st_out = c->st + size_t((c->seq + 1) & 1) * c->nunits;
     k.part = c->part;
-    k.cap = c->cap;
-    k.bpr = c->bpr;
+    k.nslots = c->pslots;
+    k.expect = expect;
     c->seq += 1;
     return k;
 }
 
-static const CgState* current_states(const hmc_ctx* c) { return c->st + size_t(c->seq & 1) * c->cap; }
+static const CgState* current_states(const hmc_ctx* c) { return c->st + size_t(c->seq & 1) * c->nunits; }
 
-// Enqueue the reliable-update / true-residual sequence for right-hand sides in `filter`,
-// then reduce what is pending so the published records are complete.
-template <typename R>
-static int enqueue_ru(hmc_ctx* c, const double* phi64, const double2* b, double2* x, int n,
-                      int filter, hipStream_t s) {
+// One status chunk: `chunk` iterations (steps A and B), then the reliable-update /
+// true-residual sequence for units in `filter`, then the reduction of what is pending so the
+// published records are complete.  An even number of launches, so every chunk starts at
+// the same record parity.  first: the first chunk of a solve (step A then reduces |b|^2).
+template <typename R, class Geo>
+static int enqueue_chunk(hmc_ctx* c, Geo geo, int grid, int n, const double* phi64,
+                         const double2* b, double2* x, int chunk, int filter, bool first,
+                         bool sample, int kslot, hipStream_t s) {
     CgVecs<R> v = KrylovBufs<R>::get(c, x);
-    const int g = c->bpr * n;
-    hipLaunchKernelGGL(k_ru_fold<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c, PEND_RR, c->nblk), x, v, c->lat, filter);
+    const R* phik = KrylovBufs<R>::phi(c, phi64);
+    const Coef<R> cf = KrylovBufs<R>::cf(c);
+    for (int i = 0; i < chunk; ++i) {
+        const bool smp = sample && i == chunk / 2;
+        if (smp) HIPCHK(hipEventRecord(c->tev[kslot][0], s));
+        const int expect_a = i > 0 ? PEND_RR : (first ? PEND_BB : PEND_NONE);
+        if constexpr (sizeof(R) == sizeof(float))
+            hipLaunchKernelGGL(k_cg_a2<Geo>, dim3(grid), dim3(kBlock), 0, s, next_ctl(c, expect_a), geo, v, phik, cf);
+        else
+            hipLaunchKernelGGL((k_cg_a<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, expect_a), geo, v, phik, cf);
+        LAUNCHCHK();
+        if (smp) HIPCHK(hipEventRecord(c->tev[kslot][1], s));
+        if constexpr (sizeof(R) == sizeof(float))
+            hipLaunchKernelGGL(k_cg_b2<Geo>, dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_TT), geo, v, phik, cf);
+        else
+            hipLaunchKernelGGL((k_cg_b<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_TT), geo, v, phik, cf);
+        LAUNCHCHK();
+        if (smp) HIPCHK(hipEventRecord(c->tev[kslot][2], s));
+    }
+    hipLaunchKernelGGL((k_ru_fold<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_RR), geo, x, v, filter);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_ru_apply, dim3(g), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE, c->nblk), x, c->t64, phi64,
-                       c->lat, c->cf64, filter);
+    hipLaunchKernelGGL(k_ru_apply<Geo>, dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), geo, x,
+                       c->t64, phi64, c->cf64, filter);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_ru_resid<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE, c->nblk), b, c->t64, phi64,
-                       c->lat, c->cf64, v.r, filter);
+    hipLaunchKernelGGL((k_ru_resid<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), geo,
+                       b, c->t64, phi64, c->cf64, v.r, filter);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_cg_finalize, dim3(n), dim3(kBlock), 0, s, next_ctl(c, PEND_RU, c->nblk));
+    hipLaunchKernelGGL(k_cg_finalize<Geo>, dim3(n), dim3(kBlock), 0, s, next_ctl(c, PEND_RU), geo);
     LAUNCHCHK();
     return HMC_OK;
 }
 
-template <typename R>
-static int cg_run(hmc_ctx* c, const double* phi64, const double2* b, double2* x, int n,
-                  hmc_cg_stats* stats, hipStream_t s) {
+// Capture the two kinds of status chunk of this solve shape into executable graphs, unless
+// the cached ones match.  Capture happens on the context's own (idle) stream; the graphs
+// are launched on the caller's stream.
+template <typename R, class Geo>
+static int prepare_graphs(hmc_ctx* c, Geo geo, int grid, int n, const double* phi64,
+                          const double2* b, double2* x, int chunk, int filter) {
+    const int pi = sizeof(R) == sizeof(float) ? 1 : 0;
+    CgGraphs& G = c->cgg[pi];
+    const auto key = std::make_tuple(grid, (const void*)phi64, (const void*)b, (const void*)x,
+                                     (const void*)c->st, n, chunk, filter, c->nunits, c->generation);
+    if (G.exec[0] != nullptr && G.key == key) return HMC_OK;
+    for (int g = 0; g < 2; ++g) {
+        if (G.exec[g]) (void)hipGraphExecDestroy(G.exec[g]);
+        G.exec[g] = nullptr;
+    }
+    if (c->cap_stream == nullptr) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const int saved = c->seq;
+    for (int g = 0; g < 2; ++g) {
+        hipGraph_t graph = nullptr;
+        c->seq = 1;                                   // every chunk starts at odd parity
+        HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_chunk<R, Geo>(c, geo, grid, n, phi64, b, x, chunk, filter, g == 0, false, 0,
+                                             c->cap_stream);
+        const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            c->seq = saved;
+            return rc;
+        }
+        if (e != hipSuccess) {
+            c->seq = saved;
+            return fail(HMC_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+        }
+        const hipError_t ei = hipGraphInstantiate(&G.exec[g], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            c->seq = saved;
+            return fail(HMC_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(ei));
+        }
+    }
+    c->seq = saved;
+    G.key = key;
+    return HMC_OK;
+}
+
+// Solve (M^dagger M) x_u = b_u for the n units of `geo` (grid workgroups).  Final records
+// are left in c->h_st[0 .. n).  Returns HMC_OK, HMC_ERR_NOT_CONVERGED or HMC_ERR_NONFINITE.
+template <typename R, class Geo>
+static int cg_run(hmc_ctx* c, Geo geo, int grid, int n, const double* phi64, const double2* b,
+                  double2* x, hipStream_t s) {
     const bool mixed = sizeof(R) == sizeof(float);
     CgVecs<R> v = KrylovBufs<R>::get(c, x);
-    const R* phik = KrylovBufs<R>::phi(c, phi64);
-    const Coef<R> cf = KrylovBufs<R>::cf(c);
-    c->bpr = mixed ? c->bpr32 : c->bpr64;
-    const int g = c->bpr * n;
     if (mixed) {
-        hipLaunchKernelGGL(k_to_f32, dim3(elem_grid(3LL * c->vol)), dim3(kBlock), 0, s, phi64,
-                           c->phi32, 3 * c->vol);
+        hipLaunchKernelGGL(k_to_f32, dim3(elem_grid(3LL * c->phi_sites)), dim3(kBlock), 0, s, phi64,
+                           c->phi32, int(3 * c->phi_sites));
         LAUNCHCHK();
     }
     const double tol = c->p.cg_tol;
-    c->seq = 0;
-    hipLaunchKernelGGL(k_cg_init<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE, c->nblk), b, x, v, c->lat,
-                       tol * tol, c->p.cg_maxit);
-    LAUNCHCHK();
-
     const int chunk = mixed ? c->p.reliable_every : kCheckEvery;
     const int ru_filter = mixed ? (F_ACTIVE | F_CONV_ITER | F_MAXIT) : (F_CONV_ITER | F_MAXIT);
+    const bool use_graphs = c->graphs;
+    if (use_graphs) {
+        int rc = prepare_graphs<R, Geo>(c, geo, grid, n, phi64, b, x, chunk, ru_filter);
+        if (rc) return rc;
+    }
+    c->seq = 0;
+    hipLaunchKernelGGL((k_cg_init<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), geo, b, x,
+                       v, tol * tol, mixed ? kRuDrop2 : 0.0, c->p.cg_maxit);
+    LAUNCHCHK();
+
     const size_t st_bytes = sizeof(CgState) * size_t(n);
+    const int chunk_launches = 2 * chunk + 4;
     int issued = 0;
     int k = 0;
     bool have_prev = false;
     const int kt_a = mixed ? 0 : 2;
-    bool start_active_prev = true;   // were all right-hand sides iterating when chunk k-1 began
+    const bool sample = c->timing && !use_graphs;
+    bool start_active_prev = true;   // were all units iterating when chunk k-1 began
     // Chunks are issued one ahead of the status read, so the GPU never idles on the host;
-    // once every right-hand side is finished the remaining launches return at once.
+    // once every unit is finished the remaining launches return at once.
     for (;;) {
-        for (int i = 0; i < chunk; ++i) {
-            const bool sample = c->timing && i == chunk / 2;
-            if (sample) HIPCHK(hipEventRecord(c->tev[k & 1][0], s));
-            // the first step A of a solve reduces |b|^2; after a status chunk nothing is pending
-            const int expect_a = i > 0 ? PEND_RR : (k == 0 ? PEND_BB : PEND_NONE);
-            if constexpr (sizeof(R) == sizeof(float))
-                hipLaunchKernelGGL(k_cg_a2, dim3(g), dim3(kBlock), 0, s, next_ctl(c, expect_a, c->nblk2), v,
-                                   phik, c->lat, cf);
-            else
-                hipLaunchKernelGGL(k_cg_a<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c, expect_a, c->nblk), v,
-                                   phik, c->lat, cf);
-            LAUNCHCHK();
-            if (sample) HIPCHK(hipEventRecord(c->tev[k & 1][1], s));
-            if constexpr (sizeof(R) == sizeof(float))
-                hipLaunchKernelGGL(k_cg_b2, dim3(g), dim3(kBlock), 0, s, next_ctl(c, PEND_TT, c->nblk2), v,
-                                   phik, c->lat, cf);
-            else
-                hipLaunchKernelGGL(k_cg_b<R>, dim3(g), dim3(kBlock), 0, s, next_ctl(c, PEND_TT, c->nblk), v,
-                                   phik, c->lat, cf);
-            LAUNCHCHK();
-            if (sample) HIPCHK(hipEventRecord(c->tev[k & 1][2], s));
+        if (use_graphs) {
+            HIPCHK(hipGraphLaunch(c->cgg[mixed ? 1 : 0].exec[k == 0 ? 0 : 1], s));
+            c->seq += chunk_launches;
+        } else {
+            int rc = enqueue_chunk<R, Geo>(c, geo, grid, n, phi64, b, x, chunk, ru_filter, k == 0, sample,
+                                           k & 1, s);
+            if (rc) return rc;
         }
         issued += chunk;
-        int rc = enqueue_ru<R>(c, phi64, b, x, n, ru_filter, s);
-        if (rc) return rc;
-        HIPCHK(hipMemcpyAsync(c->h_st + (k & 1) * c->cap, current_states(c), st_bytes,
+        HIPCHK(hipMemcpyAsync(c->h_st + size_t(k & 1) * c->nunits, current_states(c), st_bytes,
                               hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(c->ev[k & 1], s));
         if (have_prev) {
             HIPCHK(hipEventSynchronize(c->ev[(k - 1) & 1]));
-            const CgState* hs = c->h_st + ((k - 1) & 1) * c->cap;
+            const CgState* hs = c->h_st + size_t((k - 1) & 1) * c->nunits;
             bool all = true, all_active = true;
             for (int j = 0; j < n; ++j) {
                 all = all && finished(hs[j].mode);
                 all_active = all_active && hs[j].mode == CG_ACTIVE;
             }
-            // chunk k-1 began in the state chunk k-2 ended in; if every right-hand side was
-            // iterating then and is still iterating at its end, its mid-chunk sample did full work
-            if (c->timing && start_active_prev && all_active) {
+            // chunk k-1 began in the state chunk k-2 ended in; if every unit was iterating
+            // then and is still iterating at its end, its mid-chunk sample did full work
+            if (sample && start_active_prev && all_active) {
                 float ta = 0.f, tb = 0.f;
                 HIPCHK(hipEventElapsedTime(&ta, c->tev[(k - 1) & 1][0], c->tev[(k - 1) & 1][1]));
                 HIPCHK(hipEventElapsedTime(&tb, c->tev[(k - 1) & 1][1], c->tev[(k - 1) & 1][2]));
@@ -318,27 +572,44 @@ static int cg_run(hmc_ctx* c, const double* phi64, const double2* b, double2* x,
         if (h.mode == CG_FAILED) status = HMC_ERR_NONFINITE;
         else if (h.mode != CG_DONE && status == HMC_OK) status = HMC_ERR_NOT_CONVERGED;
     }
-    if (stats != nullptr) {
-        std::memset(stats, 0, sizeof(*stats));
-        stats->n = n;
-        stats->status = status;
-        for (int j = 0; j < n; ++j) {
-            const CgState& h = c->h_st[j];
-            stats->iterations[j] = h.iters;
-            stats->reliable_updates[j] = h.n_ru;
-            stats->true_resid[j] = h.bb > 0.0 ? std::sqrt(h.rr_true / h.bb) : 0.0;
-        }
-    }
     if (status == HMC_ERR_NONFINITE) return fail(status, "CG met a non-finite value");
     if (status == HMC_ERR_NOT_CONVERGED)
         return fail(status, "CG did not reach tol %.3g within %d iterations", tol, c->p.cg_maxit);
     return HMC_OK;
 }
 
+static double true_resid_of(const CgState& h) { return h.bb > 0.0 ? std::sqrt(h.rr_true / h.bb) : 0.0; }
+
+static void fill_cg_stats(const hmc_ctx* c, int n, int status, hmc_cg_stats* stats) {
+    if (stats == nullptr) return;
+    std::memset(stats, 0, sizeof(*stats));
+    stats->n = n;
+    stats->status = status;
+    for (int j = 0; j < n; ++j) {
+        const CgState& h = c->h_st[j];
+        stats->iterations[j] = h.iters;
+        stats->reliable_updates[j] = h.n_ru;
+        stats->true_resid[j] = true_resid_of(h);
+    }
+}
+
+// One lattice, n right-hand sides.
 static int cg_dispatch(hmc_ctx* c, const double* phi, const double2* b, double2* x, int n,
                        hmc_cg_stats* stats, hipStream_t s) {
-    if (c->p.precision == HMC_MIXED) return cg_run<float>(c, phi, b, x, n, stats, s);
-    return cg_run<double>(c, phi, b, x, n, stats, s);
+    int rc;
+    if (c->p.precision == HMC_MIXED)
+        rc = cg_run<float>(c, geo_one(c, c->bpr32), c->bpr32 * n, n, phi, b, x, s);
+    else
+        rc = cg_run<double>(c, geo_one(c, c->bpr64), c->bpr64 * n, n, phi, b, x, s);
+    if (rc == HMC_OK || rc == HMC_ERR_NOT_CONVERGED || rc == HMC_ERR_NONFINITE) fill_cg_stats(c, n, rc, stats);
+    return rc;
+}
+
+// A batch: every (lattice, right-hand side) unit.
+static int cg_dispatch_batch(hmc_ctx* c, const double* phi, const double2* b, double2* x, hipStream_t s) {
+    if (c->p.precision == HMC_MIXED)
+        return cg_run<float>(c, geo_batch(c, 1), c->bi.nblocks[1], c->nunits, phi, b, x, s);
+    return cg_run<double>(c, geo_batch(c, 0), c->bi.nblocks[0], c->nunits, phi, b, x, s);
 }
 
 static void merge_stats(hmc_traj_stats* t, const hmc_cg_stats& cs) {
@@ -349,71 +620,338 @@ static void merge_stats(hmc_traj_stats* t, const hmc_cg_stats& cs) {
     }
 }
 
-// Workspace layout: one walk that either only measures (base == nullptr) or also
-// assigns the carved pointers.  Returns the bytes needed.
-static size_t ws_layout(hmc_ctx* c, char* base) {
-    const size_t V = size_t(c->vol);
-    const size_t sp64 = 4 * V * sizeof(double2), sp32 = 4 * V * sizeof(float2);
-    const size_t cap = size_t(c->cap);
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        char* p = base ? base + off : nullptr;
-        off = align_up(off + bytes, 256);
-        return p;
+// --------------------------------------------------------------------------------------
+// site-parallel pieces shared by both modes
+
+// Applies M (DAG false) or M^dagger to every unit; FP64 or FP32 pair kernels.
+template <typename R, bool DAG>
+static int launch_apply(hmc_ctx* c, const R* phi, const void* in, void* out, int n, hipStream_t s) {
+    if constexpr (sizeof(R) == sizeof(double)) {
+        if (c->is_batch)
+            hipLaunchKernelGGL((k_apply<double, DAG, GeoBatch>), dim3(c->bi.nblocks[0]), dim3(kBlock), 0, s,
+                               geo_batch(c, 0), static_cast<const double2*>(in), static_cast<double2*>(out),
+                               phi, c->cf64);
+        else
+            hipLaunchKernelGGL((k_apply<double, DAG, GeoOne>), dim3(c->nblk * n), dim3(kBlock), 0, s,
+                               geo_one(c, c->nblk), static_cast<const double2*>(in),
+                               static_cast<double2*>(out), phi, c->cf64);
+    } else {
+        if (c->is_batch)
+            hipLaunchKernelGGL((k_apply2<DAG, GeoBatch>), dim3(c->bi.nblocks[1]), dim3(kBlock), 0, s,
+                               geo_batch(c, 1), static_cast<const float2*>(in), static_cast<float2*>(out),
+                               phi, c->cf32);
+        else
+            hipLaunchKernelGGL((k_apply2<DAG, GeoOne>), dim3(c->nblk2 * n), dim3(kBlock), 0, s,
+                               geo_one(c, c->nblk2), static_cast<const float2*>(in),
+                               static_cast<float2*>(out), phi, c->cf32);
+    }
+    LAUNCHCHK();
+    return HMC_OK;
+}
+
+static int launch_force(hmc_ctx* c, const double* phi, const double2* x, int npf, int flags,
+                        double* force, double* pi, double h, int nkick, hipStream_t s) {
+    const int do_pf = (flags & HMC_FORCE_PF) ? 1 : 0, do_b = (flags & HMC_FORCE_BOSON) ? 1 : 0;
+    if (c->is_batch)
+        hipLaunchKernelGGL(k_force<CGeoBatch>, dim3(c->ngblk), dim3(kBlock), 0, s, cgeo_batch(c), x, phi,
+                           c->cf64, do_pf, do_b, force, pi, h, nkick);
+    else
+        hipLaunchKernelGGL(k_force<CGeoOne>, dim3(c->nblk), dim3(kBlock), 0, s, cgeo_one(c, npf), x, phi,
+                           c->cf64, do_pf, do_b, force, pi, h, nkick);
+    LAUNCHCHK();
+    return HMC_OK;
+}
+
+// sum_k Re<a_k, b_k>: one lattice -> slots[slot_index]; batch -> per lattice, slot_index of
+// its block of kChainSlots.
+static int dot_re(hmc_ctx* c, const double2* a, const double2* b, int n, int slot_index, hipStream_t s) {
+    if (c->is_batch) {
+        hipLaunchKernelGGL(k_dot_re<CGeoBatch>, dim3(c->ngblk), dim3(kBlock), 0, s, cgeo_batch(c), a, b, c->gpart);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_sum_chains, dim3(c->bi.nchains), dim3(kBlock), 0, s, c->gpart, 0, 1,
+                           c->bi.cfirst_dev, c->bi.cslots + slot_index, kChainSlots);
+    } else {
+        hipLaunchKernelGGL(k_dot_re<CGeoOne>, dim3(c->nblk), dim3(kBlock), 0, s, cgeo_one(c, n), a, b, c->gpart);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, c->gpart, c->nblk, 1, 0,
+                           c->slots + slot_index);
+    }
+    LAUNCHCHK();
+    return HMC_OK;
+}
+
+// K = |pi|^2 / 2 (pi may be NULL) and S_B into slots [slot_index, slot_index + 1].
+static int energy(hmc_ctx* c, const double* pi, const double* phi, int slot_index, hipStream_t s) {
+    if (c->is_batch) {
+        hipLaunchKernelGGL(k_energy<CGeoBatch>, dim3(c->ngblk), dim3(kBlock), 0, s, cgeo_batch(c), pi, phi,
+                           c->gpart, c->ngblk);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_sum_chains, dim3(c->bi.nchains), dim3(kBlock), 0, s, c->gpart, c->ngblk, 2,
+                           c->bi.cfirst_dev, c->bi.cslots + slot_index, kChainSlots);
+    } else {
+        hipLaunchKernelGGL(k_energy<CGeoOne>, dim3(c->nblk), dim3(kBlock), 0, s, cgeo_one(c, 0), pi, phi,
+                           c->gpart, c->nblk);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, c->gpart, c->nblk, 2, c->nblk,
+                           c->slots + slot_index);
+    }
+    LAUNCHCHK();
+    return HMC_OK;
+}
+
+static int read_slots(hmc_ctx* c, hipStream_t s) {
+    if (c->is_batch)
+        HIPCHK(hipMemcpyAsync(c->bi.h_cslots, c->bi.cslots, sizeof(double) * kChainSlots * c->bi.nchains,
+                              hipMemcpyDeviceToHost, s));
+    else
+        HIPCHK(hipMemcpyAsync(c->h_slots, c->slots, sizeof(double) * kSlots, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HMC_OK;
+}
+
+// Leapfrog (kick-drift-kick) on (phi, pi) with pseudofermions chi fixed: n_leap steps of eps,
+// one CG solve per step plus the one at the start, the two half kicks of neighbouring steps
+// applied separately inside the gradient kernel.  Leaves sum_k Re<chi_k, x_k> of the last
+// solve in slot SL_SPF1 and, if first_action, that of the first solve in SL_SPF0.
+static int md_integrate(hmc_ctx* c, double* phi, double* pi, const double2* chi, int n_pf,
+                        bool first_action, hmc_traj_stats* stats, hipStream_t s) {
+    const double eps = c->p.eps, h = 0.5 * eps;
+    const int nl = c->p.n_leap;
+    const int flags = HMC_FORCE_BOSON | (n_pf > 0 ? HMC_FORCE_PF : 0);
+    auto solve = [&]() -> int {
+        if (n_pf == 0) return HMC_OK;
+        if (c->is_batch) {
+            const int r = cg_dispatch_batch(c, phi, chi, c->xsol, s);
+            if (r == HMC_OK || r == HMC_ERR_NOT_CONVERGED || r == HMC_ERR_NONFINITE) {
+                stats->cg_solves += 1;
+                for (int j = 0; j < c->nunits; ++j) {
+                    stats->cg_iterations += c->h_st[j].iters;
+                    const double tr = true_resid_of(c->h_st[j]);
+                    if (tr > stats->max_true_resid) stats->max_true_resid = tr;
+                }
+            }
+            return r;
+        }
+        hmc_cg_stats cs;
+        const int r = cg_dispatch(c, phi, chi, c->xsol, n_pf, &cs, s);
+        if (r == HMC_OK || r == HMC_ERR_NOT_CONVERGED || r == HMC_ERR_NONFINITE) merge_stats(stats, cs);
+        return r;
     };
-    char* st = take(sizeof(CgState) * 2 * cap);
-    char* part = take(sizeof(double) * 4 * cap * size_t(kMaxBpr));
-    char* gpart = take(sizeof(double) * 2 * size_t(c->nblk));
-    char* slots = take(sizeof(double) * kSlots);
-    char* v64 = take(4 * cap * sp64);
-    char* v32 = take(5 * cap * sp32);
-    char* tr = take(2 * cap * sp64);
-    char* bos = take(2 * 3 * V * sizeof(double));
-    char* f32 = take(3 * V * sizeof(float));
-    if (base) {
-        c->st = reinterpret_cast<CgState*>(st);
-        c->part = reinterpret_cast<double*>(part);
-        c->gpart = reinterpret_cast<double*>(gpart);
-        c->slots = reinterpret_cast<double*>(slots);
-        c->r64 = reinterpret_cast<double2*>(v64);
-        c->p064 = reinterpret_cast<double2*>(v64 + cap * sp64);
-        c->p164 = reinterpret_cast<double2*>(v64 + 2 * cap * sp64);
-        c->t64 = reinterpret_cast<double2*>(v64 + 3 * cap * sp64);
-        c->r32 = reinterpret_cast<float2*>(v32);
-        c->p032 = reinterpret_cast<float2*>(v32 + cap * sp32);
-        c->p132 = reinterpret_cast<float2*>(v32 + 2 * cap * sp32);
-        c->t32 = reinterpret_cast<float2*>(v32 + 3 * cap * sp32);
-        c->x32 = reinterpret_cast<float2*>(v32 + 4 * cap * sp32);
-        c->chi = reinterpret_cast<double2*>(tr);
-        c->xsol = reinterpret_cast<double2*>(tr + cap * sp64);
-        c->pi = reinterpret_cast<double*>(bos);
-        c->phi_save = reinterpret_cast<double*>(bos + 3 * V * sizeof(double));
-        c->phi32 = reinterpret_cast<float*>(f32);
+    int rc = solve();
+    if (rc) return rc;
+    if (first_action && n_pf > 0) {
+        rc = dot_re(c, chi, c->xsol, n_pf, SL_SPF0, s);
+        if (rc) return rc;
     }
-    return off;
+    // first half kick with the force at the start
+    rc = launch_force(c, phi, c->xsol, n_pf, flags, nullptr, pi, h, nl > 0 ? 1 : 0, s);
+    if (rc) return rc;
+    for (int step = 0; step < nl; ++step) {
+        hipLaunchKernelGGL(k_drift, dim3(elem_grid(3LL * c->phi_sites)), dim3(kBlock), 0, s, phi, pi, eps,
+                           int(3 * c->phi_sites));
+        LAUNCHCHK();
+        rc = solve();
+        if (rc) return rc;
+        // closing half kick of this step, then the opening half kick of the next one
+        rc = launch_force(c, phi, c->xsol, n_pf, flags, nullptr, pi, h, step + 1 < nl ? 2 : 1, s);
+        if (rc) return rc;
+    }
+    if (n_pf > 0) {
+        rc = dot_re(c, chi, c->xsol, n_pf, SL_SPF1, s);
+        if (rc) return rc;
+    }
+    return HMC_OK;
 }
 
-// CG launch shape: at most max_bpr workgroups per right-hand side; workgroup b takes
-// tiles b, b + bpr, ... (so every consumer reduces at most kMaxBpr partials).
-static int clamp_bpr(const hmc_ctx* c, int max_bpr) { return c->nblk2 < max_bpr ? c->nblk2 : max_bpr; }
-
-static void set_cg_shape(hmc_ctx* c, int precision, int max_bpr) {
-    if (precision != HMC_MIXED) c->bpr64 = clamp_bpr(c, max_bpr);
-    if (precision != HMC_FP64) c->bpr32 = clamp_bpr(c, max_bpr);
+static void fill_energies(const double* hs, int n_pf, hmc_traj_stats* stats) {
+    stats->K0 = hs[SL_K0];
+    stats->S_b0 = hs[SL_SB0];
+    stats->S_pf0 = n_pf > 0 ? hs[SL_SPF0] : 0.0;
+    stats->K1 = hs[SL_K1];
+    stats->S_b1 = hs[SL_SB1];
+    stats->S_pf1 = n_pf > 0 ? hs[SL_SPF1] : 0.0;
+    stats->H0 = stats->K0 + stats->S_b0 + stats->S_pf0;
+    stats->H1 = stats->K1 + stats->S_b1 + stats->S_pf1;
+    stats->dH = stats->H1 - stats->H0;
 }
 
-// Process-wide memory of autotuned shapes, keyed by lattice, right-hand sides and device.
-struct TuneKey {
-    int L, Lt, n, dev;
-    bool operator<(const TuneKey& o) const {
-        return std::tie(L, Lt, n, dev) < std::tie(o.L, o.Lt, o.n, o.dev);
+static int create_common(hmc_ctx* c) {
+    if (hipGetDevice(&c->device) != hipSuccess) return fail(HMC_ERR_HIP, "hipGetDevice failed");
+    if (hipHostMalloc((void**)&c->h_st, sizeof(CgState) * 2 * size_t(c->nunits), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_slots, sizeof(double) * kSlots, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess)
+        return fail(HMC_ERR_HIP, "pinned status buffer or event creation failed");
+    if (c->is_batch &&
+        hipHostMalloc((void**)&c->bi.h_cslots, sizeof(double) * kChainSlots * size_t(c->bi.nchains),
+                      hipHostMallocDefault) != hipSuccess)
+        return fail(HMC_ERR_HIP, "pinned status buffer creation failed");
+    return HMC_OK;
+}
+
+static void destroy_common(hmc_ctx* c) {
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j)
+            if (c->tev[i][j]) (void)hipEventDestroy(c->tev[i][j]);
+    for (int p = 0; p < 2; ++p)
+        for (int g = 0; g < 2; ++g)
+            if (c->cgg[p].exec[g]) (void)hipGraphExecDestroy(c->cgg[p].exec[g]);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->h_st) (void)hipHostFree(c->h_st);
+    if (c->h_slots) (void)hipHostFree(c->h_slots);
+    if (c->bi.h_cslots) (void)hipHostFree(c->bi.h_cslots);
+    for (int i = 0; i < 2; ++i)
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+}
+
+// Batch: per-lattice descriptors of the site-parallel kernels (geometry, offsets, boson
+// coefficients with the lattice's own r) and the tile prefix of the per-lattice sums.
+static int upload_chains(hmc_ctx* c) {
+    BatchInfo& b = c->bi;
+    HIPCHK(hipDeviceSynchronize());     // launches already queued may still read the tables
+    std::vector<ChainDesc> chains(size_t(b.nchains));
+    std::vector<int2> cblocks;
+    for (int ch = 0; ch < b.nchains; ++ch) {
+        ChainDesc& d = chains[size_t(ch)];
+        d.lat = b.lats[size_t(ch)];
+        d.voff = b.sp_off[size_t(ch)];
+        d.phioff = b.phi_off[size_t(ch)];
+        d.bc = boson_coef_of(c->dtau, c->p.c, b.r[size_t(ch)], c->p.u);
+        d.npf = b.nrhs;
+        d.pad = 0;
+        for (int t = 0; t < tiles1_host(d.lat.vol); ++t) cblocks.push_back(make_int2(ch, t));
     }
-};
-static std::mutex g_tune_mu;
-static std::map<TuneKey, std::pair<int, int>> g_tuned;   // -> (bpr64, bpr32)
+    HIPCHK(hipMemcpy(b.chains, chains.data(), sizeof(ChainDesc) * chains.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b.cblocks, cblocks.data(), sizeof(int2) * cblocks.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b.cfirst_dev, b.cfirst.data(), sizeof(int) * b.cfirst.size(), hipMemcpyHostToDevice));
+    return HMC_OK;
+}
+
+static int set_workspace_common(hmc_ctx* c, void* ptr, size_t bytes) {
+    if (c == nullptr || ptr == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL handle or workspace");
+    if ((reinterpret_cast<uintptr_t>(ptr) & 255u) != 0) return fail(HMC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (bytes < c->need) return fail(HMC_ERR_WORKSPACE, "workspace of %zu bytes < %zu needed", bytes, c->need);
+    char* base = static_cast<char*>(ptr);
+    (void)ws_layout(c, base);
+    c->ws = base;
+    c->ws_bytes = bytes;
+    c->generation += 1;
+    if (c->is_batch) {
+        int rc = upload_chains(c);
+        if (rc) return rc;
+        rc = set_cg_shape(c, HMC_FP64, c->bpr64);
+        if (rc) return rc;
+        rc = set_cg_shape(c, HMC_MIXED, c->bpr32);
+        if (rc) return rc;
+    }
+    return HMC_OK;
+}
+
+// Autotuner core: time `iters` CG iterations per candidate shape and keep the fastest.
+static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int n, hmc_tune_result* out,
+                           hipStream_t s) {
+    static const int cand[] = {128, 256, 384, 512, 768, 1024, 1536, 2048, 4096};
+    const hmc_params saved = c->p;
+    const int iters = 100;
+    std::memset(out, 0, sizeof(*out));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int result = HMC_OK;
+    int maxt = c->nblk2;
+    if (c->is_batch)
+        for (const Lat& l : c->bi.lats) maxt = std::max(maxt, tiles2_host(l.vol));
+    for (int pi = 0; pi < 2 && result == HMC_OK; ++pi) {
+        const int prec = pi == 0 ? HMC_FP64 : HMC_MIXED;
+        c->p.precision = prec;
+        c->p.cg_tol = 1e-30;           // never converges: every candidate runs `iters` iterations
+        c->p.cg_maxit = iters;
+        if (prec == HMC_MIXED && c->p.reliable_every < 1) c->p.reliable_every = 50;
+        double best = 1e300;
+        int best_bpr = 0, last = -1;
+        for (int cb : cand) {
+            const int bpr = clamp_bpr(maxt, cb);
+            if (bpr == last) continue;
+            last = bpr;
+            result = set_cg_shape(c, prec, bpr);
+            if (result) break;
+            float ms = 0.f;
+            for (int rep = 0; rep < 2; ++rep) {    // first run warms caches, code and graphs
+                if (hipEventRecord(e0, s) != hipSuccess) { result = HMC_ERR_HIP; break; }
+                const int r = c->is_batch ? cg_dispatch_batch(c, phi, b, c->xsol, s)
+                                          : cg_dispatch(c, phi, b, c->xsol, n, nullptr, s);
+                if (r != HMC_OK && r != HMC_ERR_NOT_CONVERGED) { result = r; break; }
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { result = HMC_ERR_HIP; break; }
+            }
+            if (result != HMC_OK) break;
+            out->candidates += 1;
+            const double us = 1e3 * ms / iters;
+            if (us < best) { best = us; best_bpr = bpr; }
+        }
+        if (result == HMC_OK) {
+            result = set_cg_shape(c, prec, best_bpr);
+            out->cg_workgroups[pi] = best_bpr;
+            out->us_per_iter[pi] = best;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->p = saved;
+    if (result != HMC_OK) {
+        (void)set_cg_shape(c, HMC_FP64, kDefaultBpr64);
+        (void)set_cg_shape(c, HMC_MIXED, kDefaultBpr32);
+        return result == HMC_ERR_HIP ? fail(result, "autotune: HIP call failed") : result;
+    }
+    return HMC_OK;
+}
+
+static int check_solve_args(hmc_ctx* c, const void* phi, const void* b, const void* x, int n) {
+    if (c == nullptr || phi == nullptr || b == nullptr || x == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    int rc = need_ws(c);
+    if (rc) return rc;
+    if (n < 1 || n > c->cap) return fail(HMC_ERR_INVALID_ARG, "n = %d outside [1, %d]", n, c->cap);
+    if (!aligned16(phi) || !aligned16(b) || !aligned16(x)) return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
+    if (b == x) return fail(HMC_ERR_INVALID_ARG, "b and x must not alias");
+    return HMC_OK;
+}
+
+template <typename R, bool DAG>
+static int apply_impl(hmc_ctx* c, const R* phi, const void* in, void* out, int n, void* stream) {
+    if (c == nullptr || phi == nullptr || in == nullptr || out == nullptr)
+        return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    if (n < 1) return fail(HMC_ERR_INVALID_ARG, "n must be >= 1");
+    if (!aligned16(phi) || !aligned16(in) || !aligned16(out)) return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
+    if (in == out) return fail(HMC_ERR_INVALID_ARG, "in and out must not overlap");
+    if ((long long)c->nblk * n >= (1LL << 31)) return fail(HMC_ERR_INVALID_ARG, "too many vectors");
+    return launch_apply<R, DAG>(c, phi, in, out, n, (hipStream_t)stream);
+}
+
+template <typename R>
+static int apply_normal_impl(hmc_ctx* c, const R* phi, const void* in, void* out, int n, void* stream) {
+    if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
+    int rc = need_ws(c);
+    if (rc) return rc;
+    if (n < 1 || n > c->cap) return fail(HMC_ERR_INVALID_ARG, "n must lie in [1, %d]", c->cap);
+    void* tmp;
+    if constexpr (sizeof(R) == sizeof(double)) tmp = c->t64; else tmp = c->t32;
+    if (tmp == in || tmp == out) return fail(HMC_ERR_INVALID_ARG, "in/out alias the workspace");
+    rc = apply_impl<R, false>(c, phi, in, tmp, n, stream);
+    if (rc) return rc;
+    return apply_impl<R, true>(c, phi, tmp, out, n, stream);
+}
+
+static int check_batch(hmc_batch* hb, std::initializer_list<const void*> ptrs) {
+    if (hb == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL batch");
+    for (const void* p : ptrs) {
+        if (p == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+        if (!aligned16(p)) return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
+    }
+    return need_ws(&hb->c);
+}
 
 // --------------------------------------------------------------------------------------
-// C ABI
+// C ABI: one lattice
 
 extern "C" {
 
@@ -465,15 +1003,22 @@ int hmc_create(int L, int Lt, double dtau, const hmc_params* params, hmc_ctx** o
     c->p = *params;
     c->cap = params->max_rhs > 0 ? params->max_rhs : (params->n_pf > 0 ? params->n_pf : 1);
     c->lat = make_lat(L, Lt);
-    c->nblk = (c->vol + kBlock - 1) / kBlock;
-    c->nblk2 = (c->vol / 2 + kBlock - 1) / kBlock;
+    c->nblk = tiles1_host(c->vol);
+    c->nblk2 = tiles2_host(c->vol);
+    c->vec_sites = (long long)c->cap * c->vol;
+    c->phi_sites = c->vol;
+    c->nunits = c->cap;
+    c->pslots = c->cap * clamp_bpr(c->nblk2, kMaxBpr);
+    c->ngblk = c->nblk;
     set_coefs(c);
-    if (hipGetDevice(&c->device) != hipSuccess) {
+    rc = create_common(c);
+    if (rc) {
+        destroy_common(c);
         delete c;
-        return fail(HMC_ERR_HIP, "hipGetDevice failed");
+        return rc;
     }
-    set_cg_shape(c, HMC_FP64, kDefaultBpr64);
-    set_cg_shape(c, HMC_MIXED, kDefaultBpr32);
+    (void)set_cg_shape(c, HMC_FP64, kDefaultBpr64);
+    (void)set_cg_shape(c, HMC_MIXED, kDefaultBpr32);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(TuneKey{L, Lt, c->cap, c->device});
@@ -483,13 +1028,6 @@ int hmc_create(int L, int Lt, double dtau, const hmc_params* params, hmc_ctx** o
         }
     }
     c->need = ws_layout(c, nullptr);
-    if (hipHostMalloc((void**)&c->h_st, sizeof(CgState) * 2 * size_t(c->cap), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_slots, sizeof(double) * kSlots, hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess) {
-        hmc_destroy(c);
-        return fail(HMC_ERR_HIP, "pinned status buffer or event creation failed");
-    }
     *out = c;
     return HMC_OK;
 }
@@ -505,14 +1043,19 @@ int hmc_set_kernel_timing(hmc_ctx* c, int enable) {
     return HMC_OK;
 }
 
+int hmc_set_graphs(hmc_ctx* c, int enable) {
+    if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
+    c->graphs = enable != 0;
+    return HMC_OK;
+}
+
 int hmc_set_cg_workgroups(hmc_ctx* c, int precision, int max_per_rhs) {
     if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
     if (precision != HMC_FP64 && precision != HMC_MIXED && precision != -1)
         return fail(HMC_ERR_INVALID_ARG, "precision must be HMC_FP64, HMC_MIXED or -1");
     if (max_per_rhs < 1 || max_per_rhs > kMaxBpr)
         return fail(HMC_ERR_INVALID_ARG, "workgroups per right-hand side must lie in [1, %d]", kMaxBpr);
-    set_cg_shape(c, precision, max_per_rhs);
-    return HMC_OK;
+    return set_cg_shape(c, precision, max_per_rhs);
 }
 
 int hmc_get_cg_workgroups(const hmc_ctx* c, int precision) {
@@ -520,62 +1063,13 @@ int hmc_get_cg_workgroups(const hmc_ctx* c, int precision) {
     return precision == HMC_MIXED ? c->bpr32 : c->bpr64;
 }
 
-static int check_solve_args(hmc_ctx* c, const void* phi, const void* b, const void* x, int n);
-
 int hmc_autotune(hmc_ctx* c, const double* phi, const void* b, int n, hmc_tune_result* out,
                  void* stream) {
     int rc = check_solve_args(c, phi, b, c ? c->xsol : nullptr, n);
     if (rc) return rc;
     if (out == nullptr) return fail(HMC_ERR_INVALID_ARG, "out is NULL");
-    hipStream_t s = (hipStream_t)stream;
-    static const int cand[] = {128, 256, 384, 512, 768, 1024, 1536, 2048, 4096};
-    const hmc_params saved = c->p;
-    const int iters = 100;
-    std::memset(out, 0, sizeof(*out));
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    int result = HMC_OK;
-    for (int pi = 0; pi < 2 && result == HMC_OK; ++pi) {
-        const int prec = pi == 0 ? HMC_FP64 : HMC_MIXED;
-        c->p.precision = prec;
-        c->p.cg_tol = 1e-30;           // never converges: every candidate runs `iters` iterations
-        c->p.cg_maxit = iters;
-        if (prec == HMC_MIXED && c->p.reliable_every < 1) c->p.reliable_every = 50;
-        double best = 1e300;
-        int best_bpr = 0, last = -1;
-        for (int cb : cand) {
-            const int bpr = clamp_bpr(c, cb);
-            if (bpr == last) continue;
-            last = bpr;
-            set_cg_shape(c, prec, bpr);
-            float ms = 0.f;
-            for (int rep = 0; rep < 2; ++rep) {    // first run warms caches and code
-                if (hipEventRecord(e0, s) != hipSuccess) { result = HMC_ERR_HIP; break; }
-                const int r = cg_dispatch(c, phi, static_cast<const double2*>(b), c->xsol, n, nullptr, s);
-                if (r != HMC_OK && r != HMC_ERR_NOT_CONVERGED) { result = r; break; }
-                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { result = HMC_ERR_HIP; break; }
-            }
-            if (result != HMC_OK) break;
-            out->candidates += 1;
-            const double us = 1e3 * ms / iters;
-            if (us < best) { best = us; best_bpr = bpr; }
-        }
-        if (result == HMC_OK) {
-            set_cg_shape(c, prec, best_bpr);
-            out->cg_workgroups[pi] = best_bpr;
-            out->us_per_iter[pi] = best;
-        }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    c->p = saved;
-    if (result != HMC_OK) {
-        set_cg_shape(c, HMC_FP64, kDefaultBpr64);
-        set_cg_shape(c, HMC_MIXED, kDefaultBpr32);
-        return result == HMC_ERR_HIP ? fail(result, "autotune: HIP call failed") : result;
-    }
+    rc = autotune_common(c, phi, static_cast<const double2*>(b), n, out, (hipStream_t)stream);
+    if (rc) return rc;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[TuneKey{c->L, c->Lt, c->cap, c->device}] = {c->bpr64, c->bpr32};
     return HMC_OK;
@@ -589,13 +1083,7 @@ int hmc_get_kernel_times(const hmc_ctx* c, hmc_kernel_times* out) {
 
 int hmc_destroy(hmc_ctx* c) {
     if (c == nullptr) return HMC_OK;
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 3; ++j)
-            if (c->tev[i][j]) (void)hipEventDestroy(c->tev[i][j]);
-    if (c->h_st) (void)hipHostFree(c->h_st);
-    if (c->h_slots) (void)hipHostFree(c->h_slots);
-    for (int i = 0; i < 2; ++i)
-        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    destroy_common(c);
     delete c;
     return HMC_OK;
 }
@@ -614,56 +1102,9 @@ int hmc_set_params(hmc_ctx* c, const hmc_params* params) {
 size_t hmc_workspace_bytes(const hmc_ctx* c) { return c ? c->need : 0; }
 
 int hmc_set_workspace(hmc_ctx* c, void* ptr, size_t bytes) {
-    if (c == nullptr || ptr == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL ctx or workspace");
-    if ((reinterpret_cast<uintptr_t>(ptr) & 255u) != 0) return fail(HMC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-    if (bytes < c->need) return fail(HMC_ERR_WORKSPACE, "workspace of %zu bytes < %zu needed", bytes, c->need);
-    char* base = static_cast<char*>(ptr);
-    (void)ws_layout(c, base);
-    c->ws = base;
-    c->ws_bytes = bytes;
-    return HMC_OK;
+    if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL ctx");
+    return set_workspace_common(c, ptr, bytes);
 }
-
-}  // extern "C"
-
-// ---- operator applies -----------------------------------------------------------------
-
-template <typename R, bool DAG>
-static int apply_impl(hmc_ctx* c, const R* phi, const void* in, void* out, int n, void* stream) {
-    if (c == nullptr || phi == nullptr || in == nullptr || out == nullptr)
-        return fail(HMC_ERR_INVALID_ARG, "NULL argument");
-    if (n < 1) return fail(HMC_ERR_INVALID_ARG, "n must be >= 1");
-    if (!aligned16(phi) || !aligned16(in) || !aligned16(out)) return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
-    if (in == out) return fail(HMC_ERR_INVALID_ARG, "in and out must not overlap");
-    if ((long long)c->nblk * n >= (1LL << 31)) return fail(HMC_ERR_INVALID_ARG, "too many vectors");
-    if constexpr (sizeof(R) == sizeof(double)) {
-        hipLaunchKernelGGL((k_apply<double, DAG>), dim3(grid_for(c, n)), dim3(kBlock), 0,
-                           (hipStream_t)stream, static_cast<const double2*>(in),
-                           static_cast<double2*>(out), phi, c->lat, c->cf64, c->nblk);
-    } else {
-        hipLaunchKernelGGL(k_apply2<DAG>, dim3(c->nblk2 * n), dim3(kBlock), 0, (hipStream_t)stream,
-                           static_cast<const float2*>(in), static_cast<float2*>(out), phi, c->lat,
-                           c->cf32, c->nblk2);
-    }
-    LAUNCHCHK();
-    return HMC_OK;
-}
-
-template <typename R>
-static int apply_normal_impl(hmc_ctx* c, const R* phi, const void* in, void* out, int n, void* stream) {
-    if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
-    int rc = need_ws(c);
-    if (rc) return rc;
-    if (n < 1 || n > c->cap) return fail(HMC_ERR_INVALID_ARG, "n must lie in [1, %d]", c->cap);
-    void* tmp;
-    if constexpr (sizeof(R) == sizeof(double)) tmp = c->t64; else tmp = c->t32;
-    if (tmp == in || tmp == out) return fail(HMC_ERR_INVALID_ARG, "in/out alias the workspace");
-    rc = apply_impl<R, false>(c, phi, in, tmp, n, stream);
-    if (rc) return rc;
-    return apply_impl<R, true>(c, phi, tmp, out, n, stream);
-}
-
-extern "C" {
 
 int hmc_apply_M(hmc_ctx* c, const double* phi, const void* in, void* out, int n, void* stream) {
     return apply_impl<double, false>(c, phi, in, out, n, stream);
@@ -688,18 +1129,6 @@ int hmc_heatbath(hmc_ctx* c, const double* phi, const void* eta, void* chi, int 
     return apply_impl<double, true>(c, phi, eta, chi, n_pf, stream);
 }
 
-// ---- solver, actions, gradient --------------------------------------------------------
-
-static int check_solve_args(hmc_ctx* c, const void* phi, const void* b, const void* x, int n) {
-    if (c == nullptr || phi == nullptr || b == nullptr || x == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL argument");
-    int rc = need_ws(c);
-    if (rc) return rc;
-    if (n < 1 || n > c->cap) return fail(HMC_ERR_INVALID_ARG, "n = %d outside [1, %d]", n, c->cap);
-    if (!aligned16(phi) || !aligned16(b) || !aligned16(x)) return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
-    if (b == x) return fail(HMC_ERR_INVALID_ARG, "b and x must not alias");
-    return HMC_OK;
-}
-
 int hmc_cg_solve(hmc_ctx* c, const double* phi, const void* b, void* x, int n,
                  hmc_cg_stats* stats, void* stream) {
     int rc = check_solve_args(c, phi, b, x, n);
@@ -708,47 +1137,14 @@ int hmc_cg_solve(hmc_ctx* c, const double* phi, const void* b, void* x, int n,
                        (hipStream_t)stream);
 }
 
-static int launch_force(hmc_ctx* c, const double* phi, const double2* x, int npf, int flags,
-                        double* force, double* pi, double h, int nkick, hipStream_t s) {
-    hipLaunchKernelGGL(k_force, dim3(c->nblk), dim3(kBlock), 0, s, x, npf, phi, c->lat, c->cf64,
-                       c->bc, (flags & HMC_FORCE_PF) ? 1 : 0, (flags & HMC_FORCE_BOSON) ? 1 : 0,
-                       force, pi, h, nkick);
-    LAUNCHCHK();
-    return HMC_OK;
-}
-
-static int dot_re(hmc_ctx* c, const double2* a, const double2* b, int n, double* slot, hipStream_t s) {
-    hipLaunchKernelGGL(k_dot_re, dim3(c->nblk), dim3(kBlock), 0, s, a, b, n, c->lat, c->gpart);
-    LAUNCHCHK();
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, c->gpart, c->nblk, 1, 0, slot);
-    LAUNCHCHK();
-    return HMC_OK;
-}
-
-// K = |pi|^2 / 2 (pi may be NULL) and S_B into slot[0], slot[1].
-static int energy(hmc_ctx* c, const double* pi, const double* phi, double* slot, hipStream_t s) {
-    hipLaunchKernelGGL(k_energy, dim3(c->nblk), dim3(kBlock), 0, s, pi, phi, c->lat, c->bc,
-                       c->gpart, c->nblk);
-    LAUNCHCHK();
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, c->gpart, c->nblk, 2, c->nblk, slot);
-    LAUNCHCHK();
-    return HMC_OK;
-}
-
-static int read_slots(hmc_ctx* c, hipStream_t s) {
-    HIPCHK(hipMemcpyAsync(c->h_slots, c->slots, sizeof(double) * kSlots, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return HMC_OK;
-}
-
 int hmc_force_from_solution(hmc_ctx* c, const double* phi, const void* x, int n_pf,
                             double* force, int flags, void* stream) {
     if (c == nullptr || phi == nullptr || force == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL argument");
     if ((flags & HMC_FORCE_PF) && (x == nullptr || n_pf < 1)) return fail(HMC_ERR_INVALID_ARG, "pseudofermion force needs x and n_pf >= 1");
     if (n_pf < 0 || n_pf > HMC_MAX_RHS) return fail(HMC_ERR_INVALID_ARG, "n_pf out of range");
     if (!aligned16(phi) || !aligned16(force) || (x && !aligned16(x))) return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
-    return launch_force(c, phi, static_cast<const double2*>(x), n_pf, flags, force, nullptr, 0.0, 0,
-                        (hipStream_t)stream);
+    return launch_force(c, phi, static_cast<const double2*>(x), (flags & HMC_FORCE_PF) ? n_pf : 0, flags,
+                        force, nullptr, 0.0, 0, (hipStream_t)stream);
 }
 
 int hmc_pf_action(hmc_ctx* c, const double* phi, const void* chi, int n_pf, void* x, double* S,
@@ -760,7 +1156,7 @@ int hmc_pf_action(hmc_ctx* c, const double* phi, const void* chi, int n_pf, void
     hipStream_t s = (hipStream_t)stream;
     rc = cg_dispatch(c, phi, static_cast<const double2*>(chi), xs, n_pf, stats, s);
     if (rc && rc != HMC_ERR_NOT_CONVERGED) return rc;
-    int rc2 = dot_re(c, static_cast<const double2*>(chi), xs, n_pf, c->slots + SL_TMP, s);
+    int rc2 = dot_re(c, static_cast<const double2*>(chi), xs, n_pf, SL_TMP, s);
     if (rc2) return rc2;
     rc2 = read_slots(c, s);
     if (rc2) return rc2;
@@ -785,7 +1181,7 @@ int hmc_force(hmc_ctx* c, const double* phi, const void* chi, int n_pf, double* 
                            nullptr, 0.0, 0, s);
     if (rc2) return rc2;
     if ((flags & HMC_FORCE_PF) && S_pf) {
-        rc2 = dot_re(c, static_cast<const double2*>(chi), c->xsol, n_pf, c->slots + SL_TMP, s);
+        rc2 = dot_re(c, static_cast<const double2*>(chi), c->xsol, n_pf, SL_TMP, s);
         if (rc2) return rc2;
         rc2 = read_slots(c, s);
         if (rc2) return rc2;
@@ -801,69 +1197,12 @@ int hmc_boson_action(hmc_ctx* c, const double* phi, double* S, void* stream) {
     int rc = need_ws(c);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    rc = energy(c, nullptr, phi, c->slots + SL_TMP, s);
+    rc = energy(c, nullptr, phi, SL_TMP, s);
     if (rc) return rc;
     rc = read_slots(c, s);
     if (rc) return rc;
     *S = c->h_slots[SL_TMP + 1];
     return HMC_OK;
-}
-
-// ---- trajectory ----------------------------------------------------------------------
-
-// Leapfrog (kick-drift-kick) on (phi, pi) with pseudofermions chi fixed: n_leap steps of eps,
-// one CG solve per step plus the one at the start, the two half kicks of neighbouring steps
-// applied separately inside the gradient kernel.  Leaves sum_k Re<chi_k, x_k> of the last
-// solve in slot SL_SPF1 and, if first_action, that of the first solve in SL_SPF0.
-static int md_integrate(hmc_ctx* c, double* phi, double* pi, const double2* chi, int n_pf,
-                        bool first_action, hmc_traj_stats* stats, hipStream_t s) {
-    const double eps = c->p.eps, h = 0.5 * eps;
-    const int nl = c->p.n_leap;
-    const int flags = HMC_FORCE_BOSON | (n_pf > 0 ? HMC_FORCE_PF : 0);
-    auto solve = [&]() -> int {
-        if (n_pf == 0) return HMC_OK;
-        hmc_cg_stats cs;
-        int r = cg_dispatch(c, phi, chi, c->xsol, n_pf, &cs, s);
-        if (r == HMC_OK || r == HMC_ERR_NOT_CONVERGED || r == HMC_ERR_NONFINITE) merge_stats(stats, cs);
-        return r;
-    };
-    int rc = solve();
-    if (rc) return rc;
-    if (first_action && n_pf > 0) {
-        rc = dot_re(c, chi, c->xsol, n_pf, c->slots + SL_SPF0, s);
-        if (rc) return rc;
-    }
-    // first half kick with the force at the start
-    rc = launch_force(c, phi, c->xsol, n_pf, flags, nullptr, pi, h, nl > 0 ? 1 : 0, s);
-    if (rc) return rc;
-    for (int step = 0; step < nl; ++step) {
-        hipLaunchKernelGGL(k_drift, dim3(elem_grid(3LL * c->vol)), dim3(kBlock), 0, s, phi, pi, eps,
-                           3 * c->vol);
-        LAUNCHCHK();
-        rc = solve();
-        if (rc) return rc;
-        // closing half kick of this step, then the opening half kick of the next one
-        rc = launch_force(c, phi, c->xsol, n_pf, flags, nullptr, pi, h, step + 1 < nl ? 2 : 1, s);
-        if (rc) return rc;
-    }
-    if (n_pf > 0) {
-        rc = dot_re(c, chi, c->xsol, n_pf, c->slots + SL_SPF1, s);
-        if (rc) return rc;
-    }
-    return HMC_OK;
-}
-
-static void fill_energies(hmc_ctx* c, int n_pf, hmc_traj_stats* stats) {
-    const double* hs = c->h_slots;
-    stats->K0 = hs[SL_K0];
-    stats->S_b0 = hs[SL_SB0];
-    stats->S_pf0 = n_pf > 0 ? hs[SL_SPF0] : 0.0;
-    stats->K1 = hs[SL_K1];
-    stats->S_b1 = hs[SL_SB1];
-    stats->S_pf1 = n_pf > 0 ? hs[SL_SPF1] : 0.0;
-    stats->H0 = stats->K0 + stats->S_b0 + stats->S_pf0;
-    stats->H1 = stats->K1 + stats->S_b1 + stats->S_pf1;
-    stats->dH = stats->H1 - stats->H0;
 }
 
 int hmc_trajectory(hmc_ctx* c, double* phi, const double* pi0, const void* eta, int n_pf,
@@ -883,13 +1222,12 @@ int hmc_trajectory(hmc_ctx* c, double* phi, const double* pi0, const void* eta, 
     HIPCHK(hipMemcpyAsync(c->phi_save, phi, phib, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(c->pi, pi0, phib, hipMemcpyDeviceToDevice, s));
     if (n_pf > 0) {
-        rc = apply_impl<double, true>(c, phi, eta, c->chi, n_pf, s);
+        rc = launch_apply<double, true>(c, phi, eta, c->chi, n_pf, s);
         if (rc) return rc;
-        rc = dot_re(c, static_cast<const double2*>(eta), static_cast<const double2*>(eta), n_pf,
-                    c->slots + SL_SPF0, s);
+        rc = dot_re(c, static_cast<const double2*>(eta), static_cast<const double2*>(eta), n_pf, SL_SPF0, s);
         if (rc) return rc;
     }
-    rc = energy(c, c->pi, phi, c->slots + SL_K0, s);
+    rc = energy(c, c->pi, phi, SL_K0, s);
     if (rc) return rc;
 
     auto restore = [&](int code) -> int {
@@ -901,11 +1239,11 @@ int hmc_trajectory(hmc_ctx* c, double* phi, const double* pi0, const void* eta, 
     };
     rc = md_integrate(c, phi, c->pi, c->chi, n_pf, false, stats, s);
     if (rc) return restore(rc);
-    rc = energy(c, c->pi, phi, c->slots + SL_K1, s);
+    rc = energy(c, c->pi, phi, SL_K1, s);
     if (rc) return restore(rc);
     rc = read_slots(c, s);
     if (rc) return restore(rc);
-    fill_energies(c, n_pf, stats);
+    fill_energies(c->h_slots, n_pf, stats);
     if (!std::isfinite(stats->dH)) return restore(fail(HMC_ERR_NONFINITE, "dH is not finite"));
     stats->accepted = (u < std::exp(-stats->dH)) ? 1 : 0;
     stats->status = HMC_OK;
@@ -927,17 +1265,229 @@ int hmc_leapfrog(hmc_ctx* c, double* phi, double* pi, const void* chi, int n_pf,
     if (!aligned16(phi) || !aligned16(pi) || (chi && !aligned16(chi))) return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     std::memset(stats, 0, sizeof(*stats));
-    rc = energy(c, pi, phi, c->slots + SL_K0, s);
+    rc = energy(c, pi, phi, SL_K0, s);
     if (rc) return rc;
     rc = md_integrate(c, phi, pi, static_cast<const double2*>(chi), n_pf, true, stats, s);
     if (rc) { stats->status = rc; return rc; }
-    rc = energy(c, pi, phi, c->slots + SL_K1, s);
+    rc = energy(c, pi, phi, SL_K1, s);
     if (rc) return rc;
     rc = read_slots(c, s);
     if (rc) return rc;
-    fill_energies(c, n_pf, stats);
+    fill_energies(c->h_slots, n_pf, stats);
     stats->accepted = 1;
     stats->status = HMC_OK;
+    return HMC_OK;
+}
+
+// --------------------------------------------------------------------------------------
+// C ABI: batch of independent lattices
+
+int hmc_batch_create(int nchains, const int* L, const int* L_tau, const double* r, double dtau,
+                     const hmc_params* params, hmc_batch** out) {
+    g_last_error.clear();
+    if (out == nullptr || L == nullptr || L_tau == nullptr || r == nullptr)
+        return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (nchains < 1) return fail(HMC_ERR_INVALID_ARG, "nchains must be >= 1");
+    if (!(dtau > 0.0) || !std::isfinite(dtau)) return fail(HMC_ERR_INVALID_ARG, "dtau must be > 0");
+    int rc = check_params(params);
+    if (rc) return rc;
+    if (params->n_pf < 1) return fail(HMC_ERR_INVALID_ARG, "batch mode needs n_pf >= 1");
+    long long tot_vol = 0;
+    for (int i = 0; i < nchains; ++i) {
+        if (!geometry_ok(L[i], L_tau[i]))
+            return fail(HMC_ERR_INVALID_ARG, "chain %d: bad lattice L=%d L_tau=%d", i, L[i], L_tau[i]);
+        if (!std::isfinite(r[i])) return fail(HMC_ERR_INVALID_ARG, "chain %d: r not finite", i);
+        tot_vol += (long long)L_tau[i] * L[i] * L[i];
+    }
+    const long long tot_units = (long long)nchains * params->n_pf;
+    if (tot_units > (1 << 14) || 4LL * params->n_pf * tot_vol >= (1LL << 31) || 3LL * tot_vol >= (1LL << 31))
+        return fail(HMC_ERR_INVALID_ARG, "batch too large");
+    hmc_batch* hb = new hmc_batch();
+    hmc_ctx* c = &hb->c;
+    c->is_batch = true;
+    c->dtau = dtau;
+    c->p = *params;
+    c->cap = params->n_pf;
+    BatchInfo& b = c->bi;
+    b.nchains = nchains;
+    b.nrhs = params->n_pf;
+    b.phi_off.push_back(0);
+    b.sp_off.push_back(0);
+    b.cfirst.push_back(0);
+    for (int i = 0; i < nchains; ++i) {
+        const Lat lat = make_lat(L[i], L_tau[i]);
+        b.lats.push_back(lat);
+        b.r.push_back(r[i]);
+        b.phi_off.push_back(b.phi_off.back() + 3LL * lat.vol);
+        b.sp_off.push_back(b.sp_off.back() + 4LL * b.nrhs * lat.vol);
+        b.cfirst.push_back(b.cfirst.back() + tiles1_host(lat.vol));
+    }
+    c->vec_sites = (long long)b.nrhs * tot_vol;
+    c->phi_sites = tot_vol;
+    c->nunits = int(tot_units);
+    c->pslots = 0;
+    for (const Lat& l : b.lats) c->pslots += b.nrhs * clamp_bpr(tiles2_host(l.vol), kMaxBpr);
+    c->ngblk = b.cfirst.back();
+    c->lat = b.lats[0];
+    c->nblk = tiles1_host(c->lat.vol);
+    c->nblk2 = tiles2_host(c->lat.vol);
+    set_coefs(c);
+    rc = create_common(c);
+    if (rc) {
+        destroy_common(c);
+        delete hb;
+        return rc;
+    }
+    c->bpr64 = kDefaultBpr64;
+    c->bpr32 = kDefaultBpr32;
+    (void)upload_batch_shape(c, 0, c->bpr64);    // counts only until the workspace is set
+    (void)upload_batch_shape(c, 1, c->bpr32);
+    c->need = ws_layout(c, nullptr);
+    c->graphs = true;
+    *out = hb;
+    return HMC_OK;
+}
+
+int hmc_batch_destroy(hmc_batch* hb) {
+    if (hb == nullptr) return HMC_OK;
+    destroy_common(&hb->c);
+    delete hb;
+    return HMC_OK;
+}
+
+size_t hmc_batch_workspace_bytes(const hmc_batch* hb) { return hb ? hb->c.need : 0; }
+
+int hmc_batch_set_workspace(hmc_batch* hb, void* ptr, size_t bytes) {
+    if (hb == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL batch");
+    return set_workspace_common(&hb->c, ptr, bytes);
+}
+
+int hmc_batch_layout(const hmc_batch* hb, long long* phi_offsets, long long* spinor_offsets) {
+    if (hb == nullptr || phi_offsets == nullptr || spinor_offsets == nullptr)
+        return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    const BatchInfo& b = hb->c.bi;
+    for (int i = 0; i <= b.nchains; ++i) {
+        phi_offsets[i] = b.phi_off[size_t(i)];
+        spinor_offsets[i] = b.sp_off[size_t(i)];
+    }
+    return HMC_OK;
+}
+
+int hmc_batch_set_cg_workgroups(hmc_batch* hb, int precision, int max_per_unit) {
+    if (hb == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL batch");
+    return hmc_set_cg_workgroups(&hb->c, precision, max_per_unit);
+}
+
+int hmc_batch_get_cg_workgroups(const hmc_batch* hb, int precision) {
+    return hb ? hmc_get_cg_workgroups(&hb->c, precision) : -1;
+}
+
+int hmc_batch_set_graphs(hmc_batch* hb, int enable) {
+    if (hb == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL batch");
+    hb->c.graphs = enable != 0;
+    return HMC_OK;
+}
+
+int hmc_batch_set_params(hmc_batch* hb, const hmc_params* params) {
+    if (hb == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL batch");
+    int rc = check_params(params);
+    if (rc) return rc;
+    if (params->n_pf != hb->c.bi.nrhs) return fail(HMC_ERR_INVALID_ARG, "n_pf is fixed at creation in batch mode");
+    hb->c.p = *params;
+    set_coefs(&hb->c);
+    if (hb->c.ws != nullptr) return upload_chains(&hb->c);
+    return HMC_OK;
+}
+
+int hmc_batch_apply(hmc_batch* hb, int dagger, int precision, const void* phi, const void* in, void* out,
+                    void* stream) {
+    int rc = check_batch(hb, {phi, in, out});
+    if (rc) return rc;
+    if (in == out) return fail(HMC_ERR_INVALID_ARG, "in and out must not overlap");
+    hmc_ctx* c = &hb->c;
+    hipStream_t s = (hipStream_t)stream;
+    if (precision == HMC_MIXED)
+        return dagger ? launch_apply<float, true>(c, static_cast<const float*>(phi), in, out, 1, s)
+                      : launch_apply<float, false>(c, static_cast<const float*>(phi), in, out, 1, s);
+    if (precision != HMC_FP64) return fail(HMC_ERR_INVALID_ARG, "precision must be HMC_FP64 or HMC_MIXED");
+    return dagger ? launch_apply<double, true>(c, static_cast<const double*>(phi), in, out, 1, s)
+                  : launch_apply<double, false>(c, static_cast<const double*>(phi), in, out, 1, s);
+}
+
+int hmc_batch_cg_solve(hmc_batch* hb, const double* phi, const void* b, void* x, int* iterations,
+                       double* true_resid, void* stream) {
+    int rc = check_batch(hb, {phi, b, x});
+    if (rc) return rc;
+    if (b == x) return fail(HMC_ERR_INVALID_ARG, "b and x must not alias");
+    hmc_ctx* c = &hb->c;
+    rc = cg_dispatch_batch(c, phi, static_cast<const double2*>(b), static_cast<double2*>(x), (hipStream_t)stream);
+    if (rc == HMC_OK || rc == HMC_ERR_NOT_CONVERGED || rc == HMC_ERR_NONFINITE) {
+        for (int j = 0; j < c->nunits; ++j) {
+            if (iterations) iterations[j] = c->h_st[j].iters;
+            if (true_resid) true_resid[j] = true_resid_of(c->h_st[j]);
+        }
+    }
+    return rc;
+}
+
+int hmc_batch_autotune(hmc_batch* hb, const double* phi, const void* b, hmc_tune_result* out, void* stream) {
+    int rc = check_batch(hb, {phi, b});
+    if (rc) return rc;
+    if (out == nullptr) return fail(HMC_ERR_INVALID_ARG, "out is NULL");
+    return autotune_common(&hb->c, phi, static_cast<const double2*>(b), hb->c.nunits, out, (hipStream_t)stream);
+}
+
+int hmc_batch_trajectory(hmc_batch* hb, double* phi, const double* pi0, const void* eta,
+                         const double* u, double* dH, int* accepted, hmc_traj_stats* totals,
+                         void* stream) {
+    int rc = check_batch(hb, {phi, pi0, eta});
+    if (rc) return rc;
+    if (u == nullptr || dH == nullptr || accepted == nullptr || totals == nullptr)
+        return fail(HMC_ERR_INVALID_ARG, "NULL host argument");
+    hmc_ctx* c = &hb->c;
+    BatchInfo& b = c->bi;
+    hipStream_t s = (hipStream_t)stream;
+    std::memset(totals, 0, sizeof(*totals));
+    const size_t phib = 3 * size_t(c->phi_sites) * sizeof(double);
+    const int npf = b.nrhs;
+    HIPCHK(hipMemcpyAsync(c->phi_save, phi, phib, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->pi, pi0, phib, hipMemcpyDeviceToDevice, s));
+    rc = launch_apply<double, true>(c, phi, eta, c->chi, 1, s);
+    if (rc) return rc;
+    rc = dot_re(c, static_cast<const double2*>(eta), static_cast<const double2*>(eta), npf, SL_SPF0, s);
+    if (rc) return rc;
+    rc = energy(c, c->pi, phi, SL_K0, s);
+    if (rc) return rc;
+    auto restore_all = [&](int code) -> int {
+        (void)hipMemcpyAsync(phi, c->phi_save, phib, hipMemcpyDeviceToDevice, s);
+        (void)hipStreamSynchronize(s);
+        for (int i = 0; i < b.nchains; ++i) accepted[i] = 0;
+        totals->status = code;
+        return code;
+    };
+    rc = md_integrate(c, phi, c->pi, c->chi, npf, false, totals, s);
+    if (rc) return restore_all(rc);
+    rc = energy(c, c->pi, phi, SL_K1, s);
+    if (rc) return restore_all(rc);
+    rc = read_slots(c, s);
+    if (rc) return restore_all(rc);
+    int nacc = 0;
+    for (int i = 0; i < b.nchains; ++i) {
+        hmc_traj_stats one{};
+        fill_energies(b.h_cslots + size_t(i) * kChainSlots, npf, &one);
+        dH[i] = one.dH;
+        accepted[i] = (std::isfinite(one.dH) && u[i] < std::exp(-one.dH)) ? 1 : 0;
+        nacc += accepted[i];
+        if (!accepted[i]) {
+            const size_t off = size_t(b.phi_off[size_t(i)]);
+            const size_t bytes = size_t(b.phi_off[size_t(i) + 1] - b.phi_off[size_t(i)]) * sizeof(double);
+            HIPCHK(hipMemcpyAsync(phi + off, c->phi_save + off, bytes, hipMemcpyDeviceToDevice, s));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    totals->accepted = nacc;
+    totals->status = HMC_OK;
     return HMC_OK;
 }
 

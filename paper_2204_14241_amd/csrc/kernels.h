@@ -92,7 +92,8 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
 // records[(s + 1) % 2], so no workgroup ever sees a record changed by its own launch.
 enum CgMode : int {
     CG_ACTIVE = 0,      // iterating
-    CG_CONV_ITER = 1,   // iterated residual passed; FP64 true residual not yet checked
+    CG_CONV_ITER = 1,   // iterated residual reached the stop, or fell by the factor that calls
+                        // for a reliable update; waits for the FP64 true residual
     CG_MAXIT = 2,       // iteration cap reached; x not yet finalised
     CG_DONE = 3,        // true residual passed
     CG_STOPPED = 4,     // iteration cap reached, x finalised
@@ -116,6 +117,9 @@ struct CgState {
     double alpha_cur;   // step of the iteration in flight
     double beta;        // coefficient of the next direction update p <- r + beta p
     double rr_true;     // last FP64 true residual |b - A x|^2
+    double drop2;       // reliable update once |r|^2 falls below drop2 times its value at the
+                        // last true residual (0: only at the stop)
+    double ru_rr;       // that threshold
     int mode;
     int iters;
     int pbuf;           // which of the two direction buffers holds the current p
@@ -124,19 +128,86 @@ struct CgState {
     int pending;        // CgPending
 };
 
-// Launch geometry and shared buffers of the CG kernels.
+// One right-hand side of one lattice: the unit the CG state machine tracks.  A solve on a
+// single lattice has one unit per right-hand side; a batch of independent lattices (chains)
+// of different sizes has one per (chain, right-hand side), all in one launch.
+struct UnitDesc {
+    Lat lat;            // geometry of the unit's lattice
+    long long voff;     // first complex element of the unit's vector in the spinor arrays
+    long long phioff;   // first element of its lattice's boson field
+    int bpr;            // workgroups on the unit; workgroup b takes tiles b, b + bpr, ...
+    int part;           // first partial-sum slot of the unit (within one kind)
+    int chain;          // lattice the unit belongs to
+    int pad;
+};
+
+// Where a workgroup works: its unit and its rank within the unit.
+struct UPos {
+    Lat lat;
+    size_t voff, phioff;
+    int k;              // unit (state record index)
+    int blk;            // workgroup within the unit
+    int bpr;            // workgroups on the unit
+    int part;           // first partial slot of the unit
+};
+
+// One lattice: unit k = right-hand side k, bpr workgroups each, in k-major order.
+struct GeoOne {
+    Lat lat;
+    int bpr;
+    __device__ __forceinline__ UPos unit(int k, int blk) const {
+        UPos p;
+        p.lat = lat;
+        p.voff = size_t(k) * 4 * lat.vol;
+        p.phioff = 0;
+        p.k = k;
+        p.blk = blk;
+        p.bpr = bpr;
+        p.part = k * bpr;
+        return p;
+    }
+    __device__ __forceinline__ UPos at(int logical) const {
+        const int k = logical / bpr;
+        return unit(k, logical - k * bpr);
+    }
+};
+
+// A ragged batch: blocks[logical] = (unit, workgroup within the unit).
+struct GeoBatch {
+    const UnitDesc* units;
+    const int2* blocks;
+    __device__ __forceinline__ UPos unit(int k, int blk) const {
+        const UnitDesc& u = units[k];
+        UPos p;
+        p.lat = u.lat;
+        p.voff = size_t(u.voff);
+        p.phioff = size_t(u.phioff);
+        p.k = k;
+        p.blk = blk;
+        p.bpr = u.bpr;
+        p.part = u.part;
+        return p;
+    }
+    __device__ __forceinline__ UPos at(int logical) const {
+        const int2 e = blocks[logical];
+        return unit(e.x, e.y);
+    }
+};
+
+__device__ __forceinline__ int tiles1(const Lat& l) { return (l.vol + kBlock - 1) / kBlock; }
+__device__ __forceinline__ int tiles2(const Lat& l) { return (l.vol / 2 + kBlock - 1) / kBlock; }
+
+// State records and partial sums of the CG kernels.
 struct CgCtl {
     const CgState* st_in;
     CgState* st_out;
-    double* part;       // partial sums [4 kinds][cap][bpr]
-    int cap;            // right-hand sides the buffers hold
-    int bpr;            // workgroups per right-hand side; workgroup b takes tiles b, b+bpr, ...
-    int ntiles;         // tiles per right-hand side
+    double* part;       // partial sums [4 kinds][nslots]
+    int nslots;         // partial slots per kind
     int expect;         // the only partial kind that can be pending at this launch
 };
 
-__device__ __forceinline__ double* part_slot(const CgCtl& c, int kind, int k) {
-    return c.part + (size_t(kind - 1) * c.cap + k) * c.bpr;
+__device__ __forceinline__ double* part_slot(const CgCtl& c, int kind, const UPos& p) {
+    return c.part + size_t(kind - 1) * c.nslots + p.part;
 }
 
 constexpr int kStateWords = int(sizeof(CgState) / 4);
@@ -152,13 +223,14 @@ __device__ __forceinline__ CgState& cg_shared() {
 // cg_shared().  Every workgroup computes the same record (deterministic order).  The record
 // (24 dwords, one per lane) and the partials the host expects to be pending are loaded in
 // the same memory round trip; the partials are used only if the record says so.
-__device__ __forceinline__ void cg_finalize(const CgCtl& c, int k) {
+__device__ __forceinline__ void cg_finalize(const CgCtl& c, const UPos& pos) {
+    const int k = pos.k;
     CgState& sh = cg_shared();
     const int t = threadIdx.x;
     unsigned w = 0u;
     if (t < kStateWords) w = reinterpret_cast<const unsigned*>(c.st_in + k)[t];
     double tot = 0.0;
-    if (c.expect != PEND_NONE) tot = sum_partials(part_slot(c, c.expect, k), c.bpr);
+    if (c.expect != PEND_NONE) tot = sum_partials(part_slot(c, c.expect, pos), pos.bpr);
     if (t < kStateWords) reinterpret_cast<unsigned*>(&sh)[t] = w;
     __syncthreads();
     if (t == 0 && sh.pending != PEND_NONE) {
@@ -168,6 +240,7 @@ __device__ __forceinline__ void cg_finalize(const CgCtl& c, int k) {
                 s.bb = tot;
                 s.stop_rr = s.tol2 * tot;
                 s.rr = s.rr_prev = s.rr_true = tot;
+                s.ru_rr = s.drop2 * tot;
                 s.mode = !finite(tot) ? CG_FAILED : (tot > 0.0 ? CG_ACTIVE : CG_DONE);
                 break;
             case PEND_TT:
@@ -186,7 +259,7 @@ __device__ __forceinline__ void cg_finalize(const CgCtl& c, int k) {
                         s.rr = tot;
                         s.alpha = s.alpha_cur;
                         s.iters += 1;
-                        if (tot <= s.stop_rr) s.mode = CG_CONV_ITER;
+                        if (tot <= s.stop_rr || tot <= s.ru_rr) s.mode = CG_CONV_ITER;
                         else if (s.iters >= s.maxit) s.mode = CG_MAXIT;
                     }
                 }
@@ -204,6 +277,7 @@ __device__ __forceinline__ void cg_finalize(const CgCtl& c, int k) {
                 } else {
                     s.beta = tot / s.rr_prev;
                     s.rr = tot;
+                    s.ru_rr = s.drop2 * tot;
                     s.mode = CG_ACTIVE;
                 }
                 break;
@@ -215,10 +289,10 @@ __device__ __forceinline__ void cg_finalize(const CgCtl& c, int k) {
 
 // Workgroup 0 of a right-hand side publishes the record for the next kernel (all threads
 // of the workgroup call this; changes made by thread 0 before it are included).
-__device__ __forceinline__ void cg_publish(const CgCtl& c, int k, int blk) {
+__device__ __forceinline__ void cg_publish(const CgCtl& c, const UPos& pos) {
     __syncthreads();
-    if (blk == 0 && threadIdx.x < kStateWords)
-        reinterpret_cast<unsigned*>(c.st_out + k)[threadIdx.x] =
+    if (pos.blk == 0 && threadIdx.x < kStateWords)
+        reinterpret_cast<unsigned*>(c.st_out + pos.k)[threadIdx.x] =
             reinterpret_cast<const unsigned*>(&cg_shared())[threadIdx.x];
 }
 
@@ -285,24 +359,27 @@ struct SrcXpay {
 };
 
 // ------------------------------------------------------------------------------------
-// out_k = M in_k (or M^dagger), k < n, one tile per workgroup.
-template <typename R, bool DAG>
-__global__ __launch_bounds__(kBlock) void k_apply(const C2<R>* __restrict__ in,
+// out = M in (or M^dagger) for every unit of the geometry; workgroup b of a unit takes its
+// 256-site tiles b, b + bpr, ...
+template <typename R, bool DAG, class Geo>
+__global__ __launch_bounds__(kBlock) void k_apply(Geo geo, const C2<R>* __restrict__ in,
                                                   C2<R>* __restrict__ out,
-                                                  const R* __restrict__ phi, Lat lat, Coef<R> cf,
-                                                  int nblk) {
-    const int logical = xcd_remap(blockIdx.x, gridDim.x);
-    const int k = logical / nblk, blk = logical - k * nblk;
-    const int s = blk * kBlock + threadIdx.x;
-    if (s >= lat.vol) return;
-    const size_t off = size_t(k) * 4 * lat.vol;
-    SrcPlain<R> src{in + off, lat.vol};
-    const Nbr nb = neighbours(lat, s);
-    C2<R> o[4], cen[4];
-    dslash_site<R, DAG>(src, phi, lat, cf, nb, s, o, cen);
-    C2<R>* dst = out + off;
+                                                  const R* __restrict__ phi_base, Coef<R> cf) {
+    const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = pos.lat;
+    const R* phi = phi_base + pos.phioff;
+    SrcPlain<R> src{in + pos.voff, lat.vol};
+    C2<R>* dst = out + pos.voff;
+    const int nt = tiles1(lat);
+    for (int tile = pos.blk; tile < nt; tile += pos.bpr) {
+        const int s = tile * kBlock + threadIdx.x;
+        if (s >= lat.vol) break;
+        const Nbr nb = neighbours(lat, s);
+        C2<R> o[4], cen[4];
+        dslash_site<R, DAG>(src, phi, lat, cf, nb, s, o, cen);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) dst[c * lat.vol + s] = o[c];
+        for (int c = 0; c < 4; ++c) dst[c * lat.vol + s] = o[c];
+    }
 }
 
 // Vectors of one conjugate-gradient solve in the Krylov precision R.
@@ -315,41 +392,31 @@ struct CgVecs {
     C2<R>* x;       // solution accumulated in R (the caller's x in FP64 mode)
 };
 
-// Map the launch onto (right-hand side, workgroup) and the workgroup's tile range.
-struct CgPos {
-    int k, blk;
-};
-__device__ __forceinline__ CgPos cg_pos(const CgCtl& c) {
-    const int logical = xcd_remap(blockIdx.x, gridDim.x);
-    CgPos p;
-    p.k = logical / c.bpr;
-    p.blk = logical - p.k * c.bpr;
-    return p;
-}
-
 // Store this workgroup's partial (thread 0) after a block reduction.
-__device__ __forceinline__ void store_partial(const CgCtl& c, int kind, const CgPos& p, double v) {
+__device__ __forceinline__ void store_partial(const CgCtl& c, int kind, const UPos& p, double v) {
     double a[1] = {v};
     block_reduce<1>(a);
-    if (threadIdx.x == 0) part_slot(c, kind, p.k)[p.blk] = a[0];
+    if (threadIdx.x == 0) part_slot(c, kind, p)[p.blk] = a[0];
 }
 
 // CG step A (iteration k):  x += alpha_{k-1} p_{k-1};  p_k = r_k + beta_{k-1} p_{k-1};
 // t = M p_k;  partial |t|^2 = <p_k, M^dagger M p_k>.  p is double-buffered because
 // neighbouring sites read the old direction.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, CgVecs<R> v, const R* __restrict__ phi,
-                                                 Lat lat, Coef<R> cf) {
-    const CgPos pos = cg_pos(ctl);
-    cg_finalize(ctl, pos.k);
+template <typename R, class Geo>
+__global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, Geo geo, CgVecs<R> v,
+                                                 const R* __restrict__ phi_base, Coef<R> cf) {
+    const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = pos.lat;
+    const R* phi = phi_base + pos.phioff;
+    cg_finalize(ctl, pos);
     const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
-        cg_publish(ctl, pos.k, pos.blk);
+        cg_publish(ctl, pos);
         return;
     }
     const R alpha = R(S.alpha), beta = R(S.beta);
     const int pb = S.pbuf;
-    const size_t off = size_t(pos.k) * 4 * lat.vol;
+    const size_t off = pos.voff;
     const C2<R>* pin = (pb ? v.p1 : v.p0) + off;
     C2<R>* pout = (pb ? v.p0 : v.p1) + off;
     const C2<R>* r = v.r + off;
@@ -357,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, CgVecs<R> v, const R
     C2<R>* t = v.t + off;
     SrcXpay<R> src{r, pin, beta, lat.vol};
     double part = 0.0;
-    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
+    for (int tile = pos.blk; tile < tiles1(lat); tile += pos.bpr) {
         const int s = tile * kBlock + threadIdx.x;
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
@@ -382,26 +449,28 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, CgVecs<R> v, const R
         W.pbuf = 1 - pb;
         W.pending = PEND_TT;
     }
-    cg_publish(ctl, pos.k, pos.blk);
+    cg_publish(ctl, pos);
 }
 
 // CG step B:  r -= alpha_k M^dagger t;  partial |r|^2.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_cg_b(CgCtl ctl, CgVecs<R> v, const R* __restrict__ phi,
-                                                 Lat lat, Coef<R> cf) {
-    const CgPos pos = cg_pos(ctl);
-    cg_finalize(ctl, pos.k);
+template <typename R, class Geo>
+__global__ __launch_bounds__(kBlock) void k_cg_b(CgCtl ctl, Geo geo, CgVecs<R> v,
+                                                 const R* __restrict__ phi_base, Coef<R> cf) {
+    const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = pos.lat;
+    const R* phi = phi_base + pos.phioff;
+    cg_finalize(ctl, pos);
     const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
-        cg_publish(ctl, pos.k, pos.blk);
+        cg_publish(ctl, pos);
         return;
     }
     const R alpha = R(S.alpha_cur);
-    const size_t off = size_t(pos.k) * 4 * lat.vol;
+    const size_t off = pos.voff;
     SrcPlain<R> src{v.t + off, lat.vol};
     C2<R>* r = v.r + off;
     double part = 0.0;
-    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
+    for (int tile = pos.blk; tile < tiles1(lat); tile += pos.bpr) {
         const int s = tile * kBlock + threadIdx.x;
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
@@ -420,26 +489,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(CgCtl ctl, CgVecs<R> v, const R
     }
     store_partial(ctl, PEND_RR, pos, part);
     if (threadIdx.x == 0) cg_shared().pending = PEND_RR;
-    cg_publish(ctl, pos.k, pos.blk);
+    cg_publish(ctl, pos);
 }
 
 // Reliable update, part 1 (elementwise): fold the pending step into the FP64 solution,
 // x64 += x_lo + alpha p (mixed) or x64 += alpha p (FP64, where v.x is x64), clear x_lo.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_ru_fold(CgCtl ctl, double2* __restrict__ x64,
-                                                    CgVecs<R> v, Lat lat, int filter) {
-    const CgPos pos = cg_pos(ctl);
-    cg_finalize(ctl, pos.k);
+template <typename R, class Geo>
+__global__ __launch_bounds__(kBlock) void k_ru_fold(CgCtl ctl, Geo geo, double2* __restrict__ x64,
+                                                    CgVecs<R> v, int filter) {
+    const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = pos.lat;
+    cg_finalize(ctl, pos);
     const CgState& S = cg_shared();
     if (!((1 << S.mode) & filter)) {
-        cg_publish(ctl, pos.k, pos.blk);
+        cg_publish(ctl, pos);
         return;
     }
     const double alpha = S.alpha;
-    const size_t off = size_t(pos.k) * 4 * lat.vol;
+    const size_t off = pos.voff;
     const C2<R>* p = (S.pbuf ? v.p1 : v.p0) + off;
     const bool separate = (void*)v.x != (void*)x64;
-    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
+    for (int tile = pos.blk; tile < tiles1(lat); tile += pos.bpr) {
         const int s = tile * kBlock + threadIdx.x;
         if (s >= lat.vol) break;
 #pragma unroll
@@ -460,22 +530,25 @@ __global__ __launch_bounds__(kBlock) void k_ru_fold(CgCtl ctl, double2* __restri
     }
     __syncthreads();
     if (threadIdx.x == 0) cg_shared().alpha = 0.0;
-    cg_publish(ctl, pos.k, pos.blk);
+    cg_publish(ctl, pos);
 }
 
 // Reliable update, part 2: t64 = M x64 (FP64) for right-hand sides in `filter`.
-__global__ __launch_bounds__(kBlock) void k_ru_apply(CgCtl ctl, const double2* __restrict__ x64,
+template <class Geo>
+__global__ __launch_bounds__(kBlock) void k_ru_apply(CgCtl ctl, Geo geo, const double2* __restrict__ x64,
                                                      double2* __restrict__ t64,
-                                                     const double* __restrict__ phi, Lat lat,
+                                                     const double* __restrict__ phi_base,
                                                      Coef<double> cf, int filter) {
-    const CgPos pos = cg_pos(ctl);
-    cg_finalize(ctl, pos.k);
+    const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = pos.lat;
+    const double* phi = phi_base + pos.phioff;
+    cg_finalize(ctl, pos);
     const int mode = cg_shared().mode;
-    cg_publish(ctl, pos.k, pos.blk);
+    cg_publish(ctl, pos);
     if (!((1 << mode) & filter)) return;
-    const size_t off = size_t(pos.k) * 4 * lat.vol;
+    const size_t off = pos.voff;
     SrcPlain<double> src{x64 + off, lat.vol};
-    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
+    for (int tile = pos.blk; tile < tiles1(lat); tile += pos.bpr) {
         const int s = tile * kBlock + threadIdx.x;
         if (s >= lat.vol) break;
         const Nbr nb = neighbours(lat, s);
@@ -488,22 +561,24 @@ __global__ __launch_bounds__(kBlock) void k_ru_apply(CgCtl ctl, const double2* _
 
 // Reliable update, part 3: r = b - M^dagger t64 in FP64, stored in the Krylov precision;
 // partial |r|^2 in FP64 (reduced by the next kernel: DONE, STOPPED or back to ACTIVE).
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_ru_resid(CgCtl ctl, const double2* __restrict__ b,
+template <typename R, class Geo>
+__global__ __launch_bounds__(kBlock) void k_ru_resid(CgCtl ctl, Geo geo, const double2* __restrict__ b,
                                                      const double2* __restrict__ t64,
-                                                     const double* __restrict__ phi, Lat lat,
+                                                     const double* __restrict__ phi_base,
                                                      Coef<double> cf, C2<R>* __restrict__ r,
                                                      int filter) {
-    const CgPos pos = cg_pos(ctl);
-    cg_finalize(ctl, pos.k);
+    const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = pos.lat;
+    const double* phi = phi_base + pos.phioff;
+    cg_finalize(ctl, pos);
     if (!((1 << cg_shared().mode) & filter)) {
-        cg_publish(ctl, pos.k, pos.blk);
+        cg_publish(ctl, pos);
         return;
     }
-    const size_t off = size_t(pos.k) * 4 * lat.vol;
+    const size_t off = pos.voff;
     SrcPlain<double> src{t64 + off, lat.vol};
     double part = 0.0;
-    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
+    for (int tile = pos.blk; tile < tiles1(lat); tile += pos.bpr) {
         const int s = tile * kBlock + threadIdx.x;
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
@@ -520,19 +595,20 @@ __global__ __launch_bounds__(kBlock) void k_ru_resid(CgCtl ctl, const double2* _
     }
     store_partial(ctl, PEND_RU, pos, part);
     if (threadIdx.x == 0) cg_shared().pending = PEND_RU;
-    cg_publish(ctl, pos.k, pos.blk);
+    cg_publish(ctl, pos);
 }
 
 // CG start from x = 0: x64 = 0, r = b, both direction buffers and x_lo cleared, partial |b|^2.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_cg_init(CgCtl ctl, const double2* __restrict__ b,
+template <typename R, class Geo>
+__global__ __launch_bounds__(kBlock) void k_cg_init(CgCtl ctl, Geo geo, const double2* __restrict__ b,
                                                     double2* __restrict__ x64, CgVecs<R> v,
-                                                    Lat lat, double tol2, int maxit) {
-    const CgPos pos = cg_pos(ctl);
-    const size_t off = size_t(pos.k) * 4 * lat.vol;
+                                                    double tol2, double drop2, int maxit) {
+    const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = pos.lat;
+    const size_t off = pos.voff;
     const bool separate = (void*)v.x != (void*)x64;
     double part = 0.0;
-    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
+    for (int tile = pos.blk; tile < tiles1(lat); tile += pos.bpr) {
         const int s = tile * kBlock + threadIdx.x;
         if (s < lat.vol) {
 #pragma unroll
@@ -553,19 +629,21 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgCtl ctl, const double2* __
         CgState& S = cg_shared();
         S = CgState{};
         S.tol2 = tol2;
+        S.drop2 = drop2;
         S.maxit = maxit;
         S.mode = CG_ACTIVE;
         S.pending = PEND_BB;
     }
-    cg_publish(ctl, pos.k, pos.blk);
+    cg_publish(ctl, pos);
 }
 
 // One workgroup per right-hand side: reduce whatever is pending and publish the record
 // (run before the host reads the status).
-__global__ __launch_bounds__(kBlock) void k_cg_finalize(CgCtl ctl) {
-    const int k = blockIdx.x;
-    cg_finalize(ctl, k);
-    cg_publish(ctl, k, 0);
+template <class Geo>
+__global__ __launch_bounds__(kBlock) void k_cg_finalize(CgCtl ctl, Geo geo) {
+    const UPos pos = geo.unit(blockIdx.x, 0);
+    cg_finalize(ctl, pos);
+    cg_publish(ctl, pos);
 }
 
 // ------------------------------------------------------------------------------------
@@ -650,38 +728,43 @@ __device__ __forceinline__ void dslash_pair(const Src& src, const float* __restr
 }
 
 // out_k = M in_k (or M^dagger), FP32, one 512-site tile per workgroup.
-template <bool DAG>
-__global__ __launch_bounds__(kBlock) void k_apply2(const float2* __restrict__ in,
+template <bool DAG, class Geo>
+__global__ __launch_bounds__(kBlock) void k_apply2(Geo geo, const float2* __restrict__ in,
                                                    float2* __restrict__ out,
-                                                   const float* __restrict__ phi, Lat lat,
-                                                   Coef<float> cf, int nblk) {
-    const int logical = xcd_remap(blockIdx.x, gridDim.x);
-    const int k = logical / nblk, blk = logical - k * nblk;
-    const int s = 2 * (blk * kBlock + threadIdx.x);
-    if (s >= lat.vol) return;
-    const size_t off = size_t(k) * 4 * lat.vol;
+                                                   const float* __restrict__ phi_base, Coef<float> cf) {
+    const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = pos.lat;
+    const float* phi = phi_base + pos.phioff;
+    const size_t off = pos.voff;
     SrcPlain2 src{in + off, lat.vol};
-    const Nbr nb = neighbours(lat, s);
-    float4 o[4], cen[4];
-    dslash_pair<DAG>(src, phi, lat, cf, nb, s, o, cen);
+    const int nt = tiles2(lat);
+    for (int tile = pos.blk; tile < nt; tile += pos.bpr) {
+        const int s = 2 * (tile * kBlock + threadIdx.x);
+        if (s >= lat.vol) break;
+        const Nbr nb = neighbours(lat, s);
+        float4 o[4], cen[4];
+        dslash_pair<DAG>(src, phi, lat, cf, nb, s, o, cen);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) st4(out + off, size_t(c) * lat.vol + s, o[c]);
+        for (int c = 0; c < 4; ++c) st4(out + off, size_t(c) * lat.vol + s, o[c]);
+    }
 }
 
 // CG step A, FP32 pair form (same algebra as k_cg_a).
-__global__ __launch_bounds__(kBlock) void k_cg_a2(CgCtl ctl, CgVecs<float> v,
-                                                  const float* __restrict__ phi, Lat lat,
-                                                  Coef<float> cf) {
-    const CgPos pos = cg_pos(ctl);
-    cg_finalize(ctl, pos.k);
+template <class Geo>
+__global__ __launch_bounds__(kBlock) void k_cg_a2(CgCtl ctl, Geo geo, CgVecs<float> v,
+                                                  const float* __restrict__ phi_base, Coef<float> cf) {
+    const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = pos.lat;
+    const float* phi = phi_base + pos.phioff;
+    cg_finalize(ctl, pos);
     const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
-        cg_publish(ctl, pos.k, pos.blk);
+        cg_publish(ctl, pos);
         return;
     }
     const float alpha = float(S.alpha), beta = float(S.beta);
     const int pb = S.pbuf;
-    const size_t off = size_t(pos.k) * 4 * lat.vol;
+    const size_t off = pos.voff;
     const float2* pin = (pb ? v.p1 : v.p0) + off;
     float2* pout = (pb ? v.p0 : v.p1) + off;
     const float2* r = v.r + off;
@@ -689,7 +772,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a2(CgCtl ctl, CgVecs<float> v,
     float2* t = v.t + off;
     SrcXpay2 src{r, pin, beta, lat.vol};
     double part = 0.0;
-    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
+    for (int tile = pos.blk; tile < tiles2(lat); tile += pos.bpr) {
         const int s = 2 * (tile * kBlock + threadIdx.x);
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
@@ -714,26 +797,28 @@ __global__ __launch_bounds__(kBlock) void k_cg_a2(CgCtl ctl, CgVecs<float> v,
         W.pbuf = 1 - pb;
         W.pending = PEND_TT;
     }
-    cg_publish(ctl, pos.k, pos.blk);
+    cg_publish(ctl, pos);
 }
 
 // CG step B, FP32 pair form (same algebra as k_cg_b).
-__global__ __launch_bounds__(kBlock) void k_cg_b2(CgCtl ctl, CgVecs<float> v,
-                                                  const float* __restrict__ phi, Lat lat,
-                                                  Coef<float> cf) {
-    const CgPos pos = cg_pos(ctl);
-    cg_finalize(ctl, pos.k);
+template <class Geo>
+__global__ __launch_bounds__(kBlock) void k_cg_b2(CgCtl ctl, Geo geo, CgVecs<float> v,
+                                                  const float* __restrict__ phi_base, Coef<float> cf) {
+    const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = pos.lat;
+    const float* phi = phi_base + pos.phioff;
+    cg_finalize(ctl, pos);
     const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
-        cg_publish(ctl, pos.k, pos.blk);
+        cg_publish(ctl, pos);
         return;
     }
     const float alpha = float(S.alpha_cur);
-    const size_t off = size_t(pos.k) * 4 * lat.vol;
+    const size_t off = pos.voff;
     SrcPlain2 src{v.t + off, lat.vol};
     float2* r = v.r + off;
     double part = 0.0;
-    for (int tile = pos.blk; tile < ctl.ntiles; tile += ctl.bpr) {
+    for (int tile = pos.blk; tile < tiles2(lat); tile += pos.bpr) {
         const int s = 2 * (tile * kBlock + threadIdx.x);
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
@@ -752,7 +837,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_b2(CgCtl ctl, CgVecs<float> v,
     }
     store_partial(ctl, PEND_RR, pos, part);
     if (threadIdx.x == 0) cg_shared().pending = PEND_RR;
-    cg_publish(ctl, pos.k, pos.blk);
+    cg_publish(ctl, pos);
 }
 
 // ------------------------------------------------------------------------------------
@@ -774,21 +859,74 @@ __device__ __forceinline__ void pauli_contract(double2 u0, double2 u1, double2 v
     f3 += re00 - re11;     // Pauli z
 }
 
-__global__ __launch_bounds__(kBlock) void k_force(const double2* __restrict__ x, int npf,
-                                                  const double* __restrict__ phi, Lat lat,
-                                                  Coef<double> cf, BosonCoef bc, int do_pf,
-                                                  int do_boson, double* __restrict__ force,
-                                                  double* __restrict__ pi, double h, int nkick) {
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int s = blk * kBlock + threadIdx.x;
+// Where a site-parallel (not CG) workgroup works: one 256-site tile of one lattice.
+struct ChainDesc {
+    Lat lat;
+    long long voff;     // first complex element of the lattice's first right-hand side
+    long long phioff;   // first element of its boson field
+    BosonCoef bc;
+    int npf;            // right-hand sides (consecutive vectors) of the lattice
+    int pad;
+};
+struct CPos {
+    Lat lat;
+    size_t voff, phioff;
+    BosonCoef bc;
+    int npf, tile;
+};
+// One lattice: workgroup = tile.
+struct CGeoOne {
+    Lat lat;
+    BosonCoef bc;
+    int npf;
+    __device__ __forceinline__ CPos at(int logical) const {
+        CPos p;
+        p.lat = lat;
+        p.voff = 0;
+        p.phioff = 0;
+        p.bc = bc;
+        p.npf = npf;
+        p.tile = logical;
+        return p;
+    }
+};
+// A ragged batch: blocks[logical] = (lattice, tile).
+struct CGeoBatch {
+    const ChainDesc* chains;
+    const int2* blocks;
+    __device__ __forceinline__ CPos at(int logical) const {
+        const int2 e = blocks[logical];
+        const ChainDesc& c = chains[e.x];
+        CPos p;
+        p.lat = c.lat;
+        p.voff = size_t(c.voff);
+        p.phioff = size_t(c.phioff);
+        p.bc = c.bc;
+        p.npf = c.npf;
+        p.tile = e.y;
+        return p;
+    }
+};
+
+template <class CGeo>
+__global__ __launch_bounds__(kBlock) void k_force(CGeo geo, const double2* __restrict__ x_base,
+                                                  const double* __restrict__ phi_base,
+                                                  Coef<double> cf, int do_pf, int do_boson,
+                                                  double* __restrict__ force_base,
+                                                  double* __restrict__ pi_base, double h, int nkick) {
+    const CPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = pos.lat;
+    const int s = pos.tile * kBlock + threadIdx.x;
     if (s >= lat.vol) return;
     const int vol = lat.vol;
+    const double* phi = phi_base + pos.phioff;
+    const BosonCoef& bc = pos.bc;
     const Nbr nb = neighbours(lat, s);
     double F[3] = {0.0, 0.0, 0.0};
     if (do_pf) {
         double f1 = 0.0, f2 = 0.0, f3 = 0.0;
-        for (int k = 0; k < npf; ++k) {
-            SrcPlain<double> src{x + size_t(k) * 4 * vol, vol};
+        for (int k = 0; k < pos.npf; ++k) {
+            SrcPlain<double> src{x_base + pos.voff + size_t(k) * 4 * vol, vol};
             double2 Y[4], X[4];
             dslash_site<double, false>(src, phi, lat, cf, nb, s, Y, X);
             pauli_contract(Y[0], Y[1], X[2], X[3], f1, f2, f3);
@@ -814,8 +952,9 @@ __global__ __launch_bounds__(kBlock) void k_force(const double2* __restrict__ x,
     }
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-        if (force != nullptr) force[l * vol + s] = F[l];
-        if (pi != nullptr) {
+        if (force_base != nullptr) force_base[pos.phioff + l * vol + s] = F[l];
+        if (pi_base != nullptr) {
+            double* pi = pi_base + pos.phioff;
             double pv = pi[l * vol + s];
             for (int j = 0; j < nkick; ++j) pv = pv - h * F[l];
             pi[l * vol + s] = pv;
@@ -824,15 +963,21 @@ __global__ __launch_bounds__(kBlock) void k_force(const double2* __restrict__ x,
 }
 
 // Kinetic energy 1/2 |pi|^2 and boson action S_B (Eq. 2 on the lattice): per-workgroup
-// partials part[0][blk] = K, part[1][blk] = S_B (reduced by k_sum_partials).
-__global__ __launch_bounds__(kBlock) void k_energy(const double* __restrict__ pi,
-                                                   const double* __restrict__ phi, Lat lat,
-                                                   BosonCoef bc, double* part, int stride) {
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int s = blk * kBlock + threadIdx.x;
+// partials part[0][logical] = K, part[stride + logical] = S_B.
+template <class CGeo>
+__global__ __launch_bounds__(kBlock) void k_energy(CGeo geo, const double* __restrict__ pi_base,
+                                                   const double* __restrict__ phi_base,
+                                                   double* part, int stride) {
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const CPos pos = geo.at(logical);
+    const Lat& lat = pos.lat;
+    const int s = pos.tile * kBlock + threadIdx.x;
     double v[2] = {0.0, 0.0};
     if (s < lat.vol) {
         const int vol = lat.vol;
+        const double* phi = phi_base + pos.phioff;
+        const double* pi = pi_base ? pi_base + pos.phioff : nullptr;
+        const BosonCoef& bc = pos.bc;
         const Nbr nb = neighbours(lat, s);
         double kin = 0.0, st = 0.0, ss = 0.0, p2 = 0.0;
 #pragma unroll
@@ -850,30 +995,46 @@ __global__ __launch_bounds__(kBlock) void k_energy(const double* __restrict__ pi
     }
     block_reduce<2>(v);
     if (threadIdx.x == 0) {
-        part[blk] = v[0];
-        part[stride + blk] = v[1];
+        part[logical] = v[0];
+        part[stride + logical] = v[1];
     }
 }
 
-// sum_k Re <a_k, b_k> over n spinors (complex128): per-workgroup partials in part[blk].
-__global__ __launch_bounds__(kBlock) void k_dot_re(const double2* __restrict__ a,
-                                                   const double2* __restrict__ b, int n, Lat lat,
-                                                   double* part) {
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int s = blk * kBlock + threadIdx.x;
+// sum_k Re <a_k, b_k> over the npf spinors of the workgroup's lattice (complex128):
+// per-workgroup partials in part[logical].
+template <class CGeo>
+__global__ __launch_bounds__(kBlock) void k_dot_re(CGeo geo, const double2* __restrict__ a,
+                                                   const double2* __restrict__ b, double* part) {
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const CPos pos = geo.at(logical);
+    const Lat& lat = pos.lat;
+    const int s = pos.tile * kBlock + threadIdx.x;
     double v[1] = {0.0};
     if (s < lat.vol) {
-        for (int k = 0; k < n; ++k) {
+        for (int k = 0; k < pos.npf; ++k) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const size_t i = (size_t(k) * 4 + c) * lat.vol + s;
+                const size_t i = pos.voff + (size_t(k) * 4 + c) * lat.vol + s;
                 const double2 u = a[i], w = b[i];
                 v[0] += u.x * w.x + u.y * w.y;
             }
         }
     }
     block_reduce<1>(v);
-    if (threadIdx.x == 0) part[blk] = v[0];
+    if (threadIdx.x == 0) part[logical] = v[0];
+}
+
+// One workgroup per lattice c: out[c * out_stride + q] = sum of part[q * stride + j] over the
+// lattice's workgroups j in [first[c], first[c + 1]), q < nq, in index order.
+__global__ __launch_bounds__(kBlock) void k_sum_chains(const double* __restrict__ part, int stride,
+                                                       int nq, const int* __restrict__ first,
+                                                       double* out, int out_stride) {
+    const int c = blockIdx.x;
+    const int j0 = first[c], j1 = first[c + 1];
+    for (int q = 0; q < nq; ++q) {
+        const double t = sum_partials(part + size_t(q) * stride + j0, j1 - j0);
+        if (threadIdx.x == 0) out[size_t(c) * out_stride + q] = t;
+    }
 }
 
 // One workgroup: out[q] = sum over n partials of row q (rows `stride` apart), q < nq.

@@ -116,6 +116,10 @@ class HMC:
     def set_kernel_timing(self, enable=True):
         check(self.lib.hmc_set_kernel_timing(self._ctx, 1 if enable else 0), "hmc_set_kernel_timing")
 
+    def set_graphs(self, enable=True):
+        """Replay the CG status chunks from HIP graphs (see hmc_set_graphs)."""
+        check(self.lib.hmc_set_graphs(self._ctx, 1 if enable else 0), "hmc_set_graphs")
+
     def set_cg_workgroups(self, n, precision=None):
         """Workgroups per right-hand side of the CG kernels ("fp64", "mixed" or both);
         returns {precision: count in use}."""
@@ -268,6 +272,155 @@ class HMC:
         out["code"] = code
         if code != _lib.HMC_OK:
             check(code, "hmc_trajectory")
+        return out
+
+
+class Batch:
+    """Independent lattices advanced together (include/hmc.h, "Batch of independent
+    lattices").  chains: sequence of (L, L_tau, r).  Fields of all chains are concatenated
+    flat tensors: phi/pi float64 of phi_offsets[-1] elements, spinors complex128 of
+    spinor_offsets[-1] elements (each chain's n_pf vectors one after another)."""
+
+    def __init__(self, chains, dtau=0.1, model=None, eps=0.01, n_leap=10, n_pf=1, cg_tol=1e-10,
+                 cg_maxit=20000, precision="fp64", reliable_every=50, device=None):
+        self.lib = _lib.load()
+        self.chains = [(int(L), int(Lt), float(r)) for L, Lt, r in chains]
+        self.nchains = len(self.chains)
+        self.dtau = float(dtau)
+        self.n_pf = int(n_pf)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.model = dict(DEFAULT_MODEL, **(model or {}))
+        self._p = HmcParams()
+        HMC._fill(self, eps=eps, n_leap=n_leap, n_pf=n_pf, cg_tol=cg_tol, cg_maxit=cg_maxit,
+                  precision=precision, reliable_every=reliable_every, max_rhs=0)
+        n = self.nchains
+        Ls = (ctypes.c_int * n)(*[c[0] for c in self.chains])
+        Lts = (ctypes.c_int * n)(*[c[1] for c in self.chains])
+        rs = (ctypes.c_double * n)(*[c[2] for c in self.chains])
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(self.lib.hmc_batch_create(n, Ls, Lts, rs, self.dtau, ctypes.byref(self._p),
+                                            ctypes.byref(self._h)), "hmc_batch_create")
+            nbytes = int(self.lib.hmc_batch_workspace_bytes(self._h))
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+            check(self.lib.hmc_batch_set_workspace(self._h, ctypes.c_void_p(aligned), nbytes),
+                  "hmc_batch_set_workspace")
+        po = (ctypes.c_longlong * (n + 1))()
+        so = (ctypes.c_longlong * (n + 1))()
+        check(self.lib.hmc_batch_layout(self._h, po, so), "hmc_batch_layout")
+        self.phi_offsets = list(po)
+        self.spinor_offsets = list(so)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.hmc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, name, *args):
+        check(getattr(self.lib, name)(self._h, *args), name)
+
+    # ---------------------------------------------------------------- layout helpers
+    def pack_phi(self, fields):
+        """Concatenate per-chain (3, L_tau, L, L) tensors into the flat batch layout."""
+        return torch.cat([f.reshape(-1) for f in fields]).contiguous()
+
+    def unpack_phi(self, flat):
+        o = self.phi_offsets
+        return [flat[o[i]:o[i + 1]].view(3, Lt, L, L) for i, (L, Lt, _) in enumerate(self.chains)]
+
+    def pack_spinors(self, vecs):
+        """Concatenate per-chain (n_pf, 4, L_tau, L, L) tensors into the flat batch layout."""
+        return torch.cat([v.reshape(-1) for v in vecs]).contiguous()
+
+    def unpack_spinors(self, flat):
+        o = self.spinor_offsets
+        return [flat[o[i]:o[i + 1]].view(self.n_pf, 4, Lt, L, L)
+                for i, (L, Lt, _) in enumerate(self.chains)]
+
+    def _check(self, t, dtype, n, what):
+        if t.dtype != dtype or t.device != self.device or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{what} must be a contiguous {dtype} tensor of {n} elements on {self.device}")
+
+    # ---------------------------------------------------------------- controls
+    def set_graphs(self, enable=True):
+        self._call("hmc_batch_set_graphs", 1 if enable else 0)
+
+    def set_cg_workgroups(self, n, precision=None):
+        pr = {None: -1, "fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]
+        self._call("hmc_batch_set_cg_workgroups", pr, int(n))
+        return self.cg_workgroups()
+
+    def cg_workgroups(self):
+        return {"fp64": self.lib.hmc_batch_get_cg_workgroups(self._h, HMC_FP64),
+                "mixed": self.lib.hmc_batch_get_cg_workgroups(self._h, HMC_MIXED)}
+
+    def set_params(self, **kw):
+        p = self._p
+        cur = dict(eps=p.eps, n_leap=p.n_leap, n_pf=p.n_pf, cg_tol=p.cg_tol, cg_maxit=p.cg_maxit,
+                   precision={HMC_FP64: "fp64", HMC_MIXED: "mixed"}[p.precision],
+                   reliable_every=p.reliable_every, max_rhs=0)
+        model = kw.pop("model", None)
+        if model:
+            self.model = dict(self.model, **model)
+        cur.update(kw)
+        HMC._fill(self, **cur)
+        self._call("hmc_batch_set_params", ctypes.byref(self._p))
+
+    # ---------------------------------------------------------------- operators and HMC
+    def apply(self, phi, psi, dagger=False, precision="fp64"):
+        f32 = precision == "mixed"
+        self._check(phi, torch.float32 if f32 else torch.float64, self.phi_offsets[-1], "phi")
+        self._check(psi, torch.complex64 if f32 else torch.complex128, self.spinor_offsets[-1], "psi")
+        out = torch.empty_like(psi)
+        self._call("hmc_batch_apply", 1 if dagger else 0, HMC_MIXED if f32 else HMC_FP64,
+                   _ptr(phi), _ptr(psi), _ptr(out), _stream())
+        return out
+
+    def cg_solve(self, phi, b, x=None):
+        self._check(phi, torch.float64, self.phi_offsets[-1], "phi")
+        self._check(b, torch.complex128, self.spinor_offsets[-1], "b")
+        if x is None:
+            x = torch.empty_like(b)
+        nu = self.nchains * self.n_pf
+        it = (ctypes.c_int * nu)()
+        tr = (ctypes.c_double * nu)()
+        code = self.lib.hmc_batch_cg_solve(self._h, _ptr(phi), _ptr(b), _ptr(x), it, tr, _stream())
+        if code not in (_lib.HMC_OK, _lib.HMC_ERR_NOT_CONVERGED):
+            check(code, "hmc_batch_cg_solve")
+        return x, {"iterations": list(it), "true_resid": list(tr), "status": code}
+
+    def autotune(self, phi, b):
+        self._check(phi, torch.float64, self.phi_offsets[-1], "phi")
+        self._check(b, torch.complex128, self.spinor_offsets[-1], "b")
+        r = _lib.HmcTuneResult()
+        self._call("hmc_batch_autotune", _ptr(phi), _ptr(b), ctypes.byref(r), _stream())
+        return {"fp64": (r.cg_workgroups[0], r.us_per_iter[0]),
+                "mixed": (r.cg_workgroups[1], r.us_per_iter[1]), "candidates": r.candidates}
+
+    def trajectory(self, phi, pi0, eta, u):
+        """One trajectory of every chain; phi is updated in place.  u: nchains uniforms."""
+        self._check(phi, torch.float64, self.phi_offsets[-1], "phi")
+        self._check(pi0, torch.float64, self.phi_offsets[-1], "pi0")
+        self._check(eta, torch.complex128, self.spinor_offsets[-1], "eta")
+        n = self.nchains
+        if len(u) != n:
+            raise ValueError(f"u must hold {n} values")
+        uu = (ctypes.c_double * n)(*[float(v) for v in u])
+        dH = (ctypes.c_double * n)()
+        acc = (ctypes.c_int * n)()
+        st = HmcTrajStats()
+        self._call("hmc_batch_trajectory", _ptr(phi), _ptr(pi0), _ptr(eta), uu, dH, acc,
+                   ctypes.byref(st), _stream())
+        out = _traj_dict(st, _lib.HMC_OK)
+        out["dH_chains"] = list(dH)
+        out["accepted_chains"] = list(acc)
         return out
 
 

@@ -29,6 +29,11 @@ WORKLOADS = {
 }
 
 
+# batched workload: independent chains of uneven size and boson mass, 4 pseudofermions each
+BATCH_WORKLOAD = dict(nchains=64, L_choices=(12, 16, 24, 32, 48), Lt_choices=(40, 80, 120),
+                      r_range=(-1.0, 1.0), phi_var=0.5, n_pf=4, n_leap=20, eps=0.01)
+
+
 def rng(seed):
     return np.random.Generator(np.random.PCG64(seed))
 
@@ -67,3 +72,30 @@ def hmc_inputs(seed, L, Lt, phi_var, n_pf, n_traj=1):
         u = float(g.uniform())
         trajs.append((pi, etas, u))
     return phi0, trajs
+
+
+def batch_chains(seed, nchains, L_choices=BATCH_WORKLOAD["L_choices"],
+                 Lt_choices=BATCH_WORKLOAD["Lt_choices"], r_range=BATCH_WORKLOAD["r_range"]):
+    """(L, L_tau, r) per chain: L and L_tau uniform over the choices, r uniform in r_range."""
+    g = rng(seed)
+    out = []
+    for _ in range(nchains):
+        L = int(g.choice(L_choices))
+        Lt = int(g.choice(Lt_choices))
+        r = float(g.uniform(*r_range))
+        out.append((L, Lt, r))
+    return out
+
+
+def batch_inputs(seed, chains, phi_var, n_pf):
+    """Per chain, in chain order: phi_0, pi, etas (n_pf, 2, 2, Lt, L, L), u (the draw order of
+    hmc_inputs, chain after chain, from one generator)."""
+    g = rng(seed)
+    out = []
+    for L, Lt, _ in chains:
+        phi0 = draw_phi(g, L, Lt, phi_var)
+        pi = draw_momentum(g, L, Lt)
+        etas = draw_eta(g, L, Lt, n_pf)
+        u = float(g.uniform())
+        out.append((phi0, pi, etas, u))
+    return out

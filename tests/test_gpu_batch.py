@@ -1,0 +1,274 @@
+"""Batches of independent lattices (uneven L, L_tau and r) against the oracle and against
+one-lattice contexts.
+
+A batch runs every chain's stencil, solve, force and energies in shared launches.  Per chain
+the arithmetic is the one-lattice arithmetic: the same per-site expressions, the same tile
+assignment for a given workgroup count, and the same order of the FP64 partial sums.  So a
+chain of a batch must reproduce a one-lattice context with that workgroup count bit for
+bit, and graph replay must reproduce eager launches bit for bit.  Against the oracle the
+bars are those of the one-lattice tests: 1e-14 (FP64) and 2e-6 (FP32) relative error of an
+apply, FP64 residual <= 1e-10 |b| of a solve, and dH to 1e-7 of a trajectory.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth_inputs as S
+
+pytestmark = pytest.mark.gpu
+
+# ragged: volumes 128, 360, 1152, 96 and 5760 sites (tails in both tile sizes), r of both signs
+SMALL = [(4, 8, 0.3), (6, 10, -0.7), (8, 18, 0.0), (4, 6, 1.0), (12, 40, -0.25)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return (t.to(dtype) if dtype is not None else t).cuda()
+
+
+def model_of(L, Lt, r):
+    return O.Model(L=L, Lt=Lt, r=r)
+
+
+def packed(bt, arrays, spinor=False):
+    ts = [dev(a) for a in arrays]
+    return bt.pack_spinors(ts) if spinor else bt.pack_phi(ts)
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_batch_layout(hip):
+    bt = hip.Batch(SMALL, n_pf=2)
+    vols = [Lt * L * L for L, Lt, _ in SMALL]
+    assert bt.phi_offsets == [0] + list(np.cumsum([3 * v for v in vols]))
+    assert bt.spinor_offsets == [0] + list(np.cumsum([2 * 4 * v for v in vols]))
+    bt.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_apply_matches_oracle(hip, precision):
+    say(f"batch apply {precision}")
+    g = S.rng(300)
+    phis = [S.draw_phi(g, L, Lt, 0.5) for L, Lt, _ in SMALL]
+    psis = [S.draw_spinor(g, L, Lt, 2) for L, Lt, _ in SMALL]
+    bt = hip.Batch(SMALL, n_pf=2)
+    f32 = precision == "mixed"
+    phi = packed(bt, phis)
+    psi = packed(bt, psis, spinor=True)
+    if f32:
+        phi, psi = phi.float(), psi.to(torch.complex64)
+    for dag in (False, True):
+        out = bt.unpack_spinors(bt.apply(phi, psi, dagger=dag, precision=precision))
+        for i, (L, Lt, r) in enumerate(SMALL):
+            m = model_of(L, Lt, r)
+            ph = phis[i].astype(np.float32).astype(np.float64) if f32 else phis[i]
+            for k in range(2):
+                x = psis[i][k].astype(np.complex64).astype(np.complex128) if f32 else psis[i][k]
+                ref = (O.apply_Mdag if dag else O.apply_M)(m, ph, x).reshape(4, Lt, L, L)
+                got = out[i][k].cpu().numpy().astype(np.complex128)
+                e = rel(got, ref)
+                assert e < (2e-6 if f32 else 1e-14), (i, k, dag, e)
+    bt.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_cg_matches_oracle(hip, precision):
+    say(f"batch cg {precision}")
+    g = S.rng(301)
+    phis = [S.draw_phi(g, L, Lt, 0.5) for L, Lt, _ in SMALL]
+    bs = [S.draw_spinor(g, L, Lt, 2) for L, Lt, _ in SMALL]
+    bt = hip.Batch(SMALL, n_pf=2, cg_tol=1e-10, precision=precision)
+    x, st = bt.cg_solve(packed(bt, phis), packed(bt, bs, spinor=True))
+    say(f"  iterations {st['iterations']}; true residuals {st['true_resid']}")
+    assert st["status"] == 0
+    xs = bt.unpack_spinors(x)
+    for i, (L, Lt, r) in enumerate(SMALL):
+        m = model_of(L, Lt, r)
+        for k in range(2):
+            res = bs[i][k] - O.apply_MdagM(m, phis[i], xs[i][k].cpu().numpy())
+            e = np.linalg.norm(res) / np.linalg.norm(bs[i][k])
+            assert e <= 1e-10, (i, k, e)
+            assert st["true_resid"][2 * i + k] <= 1e-10
+            assert st["iterations"][2 * i + k] > 0
+    bt.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_chain_equals_single_context(hip, precision):
+    """Chain i of a batch reproduces a one-lattice context bit for bit (same launch shape)."""
+    g = S.rng(302)
+    phis = [S.draw_phi(g, L, Lt, 0.5) for L, Lt, _ in SMALL]
+    bs = [S.draw_spinor(g, L, Lt, 2) for L, Lt, _ in SMALL]
+    wg = 8     # below every lattice's tile count except the smallest: strided tiles in use
+    bt = hip.Batch(SMALL, n_pf=2, cg_tol=1e-10, precision=precision)
+    bt.set_cg_workgroups(wg)
+    x, st = bt.cg_solve(packed(bt, phis), packed(bt, bs, spinor=True))
+    xs = bt.unpack_spinors(x)
+    for i, (L, Lt, r) in enumerate(SMALL):
+        h = hip.HMC(L, Lt, n_pf=2, cg_tol=1e-10, precision=precision, model=dict(r=r))
+        h.set_cg_workgroups(wg)
+        x1, st1 = h.cg_solve(dev(phis[i]), dev(bs[i]))
+        say(f"  chain {i} {L}x{L}x{Lt}: batch iters {st['iterations'][2 * i:2 * i + 2]} "
+            f"single {st1.iterations}")
+        assert st1.iterations == st["iterations"][2 * i:2 * i + 2]
+        assert torch.equal(x1.reshape(xs[i].shape), xs[i]), i
+        h.close()
+    bt.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_graph_replay_bitwise(hip, precision):
+    """Graph replay equals eager launches, also on a replay after other work on the stream."""
+    g = S.rng(303)
+    phis = [S.draw_phi(g, L, Lt, 0.5) for L, Lt, _ in SMALL]
+    bs = [S.draw_spinor(g, L, Lt, 2) for L, Lt, _ in SMALL]
+    bt = hip.Batch(SMALL, n_pf=2, cg_tol=1e-10, precision=precision)
+    phi, b = packed(bt, phis), packed(bt, bs, spinor=True)
+    bt.set_graphs(False)
+    x0, st0 = bt.cg_solve(phi, b)
+    bt.set_graphs(True)
+    for rep in range(3):
+        x1, st1 = bt.cg_solve(phi, b)
+        assert st1["iterations"] == st0["iterations"], rep
+        assert torch.equal(x1, x0), rep
+        # unrelated eager work and a synchronisation between replays
+        bt.apply(phi, b)
+        torch.cuda.synchronize()
+    # a second right-hand side through the same cached graphs (b changes -> recapture)
+    b2 = b.flip(0).contiguous()
+    bt.set_graphs(False)
+    y0, _ = bt.cg_solve(phi, b2)
+    bt.set_graphs(True)
+    y1, _ = bt.cg_solve(phi, b2)
+    assert torch.equal(y0, y1)
+    bt.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_trajectory_matches_single_and_oracle(hip, precision):
+    chains = SMALL[:4]
+    n_pf, eps, n_leap = 2, 0.02, 4
+    ins = S.batch_inputs(304, chains, 0.5, n_pf)
+    u = [ins[0][3], np.inf, 0.0, ins[3][3]]          # chain 1 always rejects, chain 2 always accepts
+    bt = hip.Batch(chains, n_pf=n_pf, eps=eps, n_leap=n_leap, cg_tol=1e-12, precision=precision)
+    bt.set_cg_workgroups(8)
+    phi = packed(bt, [a[0] for a in ins])
+    pi0 = packed(bt, [a[1] for a in ins])
+    eta = packed(bt, [a[2] for a in ins], spinor=True)
+    pi_before = pi0.clone()
+    st = bt.trajectory(phi, pi0, eta, u)
+    say(f"batch trajectory {precision}: dH {st['dH_chains']} accepted {st['accepted_chains']} "
+        f"cg solves {st['cg_solves']} iterations {st['cg_iterations']}")
+    assert torch.equal(pi0, pi_before)
+    assert st["cg_solves"] == n_leap + 1
+    assert st["accepted"] == sum(st["accepted_chains"])
+    assert st["accepted_chains"][1] == 0 and st["accepted_chains"][2] == 1
+    phis = bt.unpack_phi(phi)
+    for i, (L, Lt, r) in enumerate(chains):
+        dH = st["dH_chains"][i]
+        assert st["accepted_chains"][i] == int(u[i] < np.exp(-dH))
+        # one-lattice context, same launch shape: bit-identical
+        h = hip.HMC(L, Lt, n_pf=n_pf, eps=eps, n_leap=n_leap, cg_tol=1e-12, precision=precision,
+                    model=dict(r=r))
+        h.set_cg_workgroups(8)
+        p1 = dev(ins[i][0])
+        s1 = h.trajectory(p1, dev(ins[i][1]), dev(ins[i][2]), u[i])
+        assert s1["dH"] == dH, (i, s1["dH"], dH)
+        assert torch.equal(p1, phis[i]), i
+        h.close()
+        # oracle
+        ref = O.trajectory(model_of(L, Lt, r), ins[i][0], ins[i][1], list(ins[i][2]), u[i], eps,
+                           n_leap, tol=1e-12)
+        say(f"  chain {i}: dH {dH:.12e} oracle {ref['dH']:.12e}")
+        assert abs(dH - ref["dH"]) < 1e-7 * max(1.0, abs(ref["dH"]))
+        assert bool(st["accepted_chains"][i]) == ref["accepted"]
+        assert np.abs(phis[i].cpu().numpy() - ref["phi"]).max() < 1e-9
+    bt.close()
+
+
+def test_batch_autotune(hip):
+    g = S.rng(305)
+    phis = [S.draw_phi(g, L, Lt, 0.5) for L, Lt, _ in SMALL]
+    bs = [S.draw_spinor(g, L, Lt, 2) for L, Lt, _ in SMALL]
+    bt = hip.Batch(SMALL, n_pf=2, cg_tol=1e-10, precision="mixed")
+    phi, b = packed(bt, phis), packed(bt, bs, spinor=True)
+    res = bt.autotune(phi, b)
+    say(f"batch autotune: {res}")
+    for prec in ("fp64", "mixed"):
+        assert res[prec][0] >= 1 and res[prec][1] > 0
+    assert bt.cg_workgroups() == {"fp64": res["fp64"][0], "mixed": res["mixed"][0]}
+    x, st = bt.cg_solve(phi, b)
+    assert st["status"] == 0 and max(st["true_resid"]) <= 1e-10
+    bt.close()
+
+
+def test_batch_rejects_bad_input(hip):
+    from paper_2204_14241_amd._lib import HmcError
+    with pytest.raises(HmcError):
+        hip.Batch([(5, 8, 0.0)])                    # odd L
+    with pytest.raises(HmcError):
+        hip.Batch([(4, 8, float("nan"))])           # r not finite
+    with pytest.raises(HmcError):
+        hip.Batch([(4, 8, 0.0)], n_pf=0)            # a batch solves at least one rhs
+    bt = hip.Batch([(4, 8, 0.0), (6, 6, 0.0)], n_pf=1)
+    with pytest.raises(HmcError):
+        bt.set_params(n_pf=2)                      # n_pf fixed at creation
+    bt.close()
+
+
+def test_batch_full_workload(hip):
+    """64 chains of the batched recipe, mixed precision: autotune, a solve whose sampled units
+    the oracle confirms to 1e-10, and a short trajectory whose smallest chain a one-lattice
+    context reproduces bit for bit."""
+    cfg = S.BATCH_WORKLOAD
+    chains = S.batch_chains(4, cfg["nchains"])
+    n_pf = cfg["n_pf"]
+    ins = S.batch_inputs(5, chains, cfg["phi_var"], n_pf)
+    bt = hip.Batch(chains, n_pf=n_pf, eps=cfg["eps"], n_leap=2, cg_tol=1e-10, precision="mixed")
+    say(f"full batch: {len(chains)} chains, {bt.phi_offsets[-1] // 3} sites")
+    phi = packed(bt, [a[0] for a in ins])
+    eta = packed(bt, [a[2] for a in ins], spinor=True)
+    res = bt.autotune(phi, eta)
+    say(f"  autotune {res}")
+    x, st = bt.cg_solve(phi, eta)
+    say(f"  solve: iterations min {min(st['iterations'])} max {max(st['iterations'])}, "
+        f"max true residual {max(st['true_resid']):.3e}")
+    assert st["status"] == 0 and max(st["true_resid"]) <= 1e-10
+    vols = [Lt * L * L for L, Lt, _ in chains]
+    xs = bt.unpack_spinors(x)
+    for i in sorted({0, int(np.argmax(vols)), int(np.argmin(vols))}):
+        L, Lt, r = chains[i]
+        m = model_of(L, Lt, r)
+        for k in (0, n_pf - 1):
+            b = ins[i][2][k]
+            e = np.linalg.norm(b - O.apply_MdagM(m, ins[i][0], xs[i][k].cpu().numpy())) / np.linalg.norm(b)
+            say(f"  chain {i} ({L}x{L}x{Lt}) rhs {k}: oracle residual {e:.3e}")
+            assert e <= 1e-10
+    pi0 = packed(bt, [a[1] for a in ins])
+    u = [a[3] for a in ins]
+    st = bt.trajectory(phi, pi0, eta, u)
+    say(f"  trajectory: accepted {st['accepted']}/{len(chains)}, |dH| max "
+        f"{max(abs(d) for d in st['dH_chains']):.3e}, cg iterations {st['cg_iterations']}")
+    assert all(np.isfinite(st["dH_chains"]))
+    i = int(np.argmin(vols))
+    L, Lt, r = chains[i]
+    wg = bt.cg_workgroups()["mixed"]
+    h = hip.HMC(L, Lt, n_pf=n_pf, eps=cfg["eps"], n_leap=2, cg_tol=1e-10, precision="mixed",
+                model=dict(r=r))
+    h.set_cg_workgroups(wg, "mixed")
+    h.set_cg_workgroups(bt.cg_workgroups()["fp64"], "fp64")
+    p1 = dev(ins[i][0])
+    s1 = h.trajectory(p1, dev(ins[i][1]), dev(ins[i][2]), u[i])
+    assert s1["dH"] == st["dH_chains"][i]
+    assert torch.equal(p1, bt.unpack_phi(phi)[i])
+    bt.close()

@@ -143,6 +143,24 @@ def test_cg_medium_true_residual(hip, precision):
         assert rel <= 1e-10
 
 
+def test_cg_mixed_well_conditioned_converges(hip):
+    """A lattice whose normal operator has condition number ~30 (4 x 4 x 6): FP32 CG reaches
+    FP32 precision in ~15 iterations, so the reliable update must come as soon as the iterated
+    residual has fallen by the trigger factor, not only after a fixed number of iterations
+    (otherwise the FP32 recurrence drifts from the true residual and the solve stagnates)."""
+    L, Lt = 4, 6
+    m = O.Model(L=L, Lt=Lt)
+    g = S.rng(301)
+    phi = S.draw_phi(g, L, Lt, 0.5)
+    b = S.draw_spinor(g, L, Lt, 1)
+    h = make(hip, L, Lt, precision="mixed", cg_tol=1e-10, cg_maxit=2000)
+    x, st = h.cg_solve(to_dev(phi), to_dev(b))
+    say(f"cg 4x4x6 mixed: iters {st.iterations} ru {st.reliable_updates} resid {st.true_resid}")
+    assert st.status == 0 and st.iterations[0] < 200
+    r = b[0] - O.apply_MdagM(m, phi, to_np(x)[0])
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b[0])
+
+
 def test_cg_deterministic(hip):
     L, Lt = 12, 40
     g = S.rng(8)
