@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--apply-reps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default CG launch shapes")
+    ap.add_argument("--batch-steps", type=int, default=1,
+                    help="timed trajectories of the 64-chain batched workload (0 skips it)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed mixed trajectories (for profiler runs)")
     ap.add_argument("--profile-kernels", action="store_true",
@@ -164,6 +166,67 @@ def apply_bench(hmcmod, torch, L, Lt, f32, reps, seed):
     bps = 2 * BYTES_PER_SITE["apply_f32" if f32 else "apply_f64"] * vol
     h.close()
     return 1e3 / ms, bps / (ms * 1e-3) / 1e9, ms, nsets
+
+
+def batch_bench(hmcmod, torch, seed, steps, warmup):
+    """The batched workload: independent chains of uneven L, L_tau and r, 4 pseudofermions
+    each, mixed precision.  Autotunes the shared CG launch shape, times one batched CG solve
+    per launch mode (eager kernels, HIP-graph replay), then `steps` batched trajectories
+    (the momenta and noise of the one drawn set are reused each step)."""
+    import numpy as np
+    import synth_inputs as S
+    cfg = S.BATCH_WORKLOAD
+    chains = S.batch_chains(seed + 4, cfg["nchains"])
+    ins = S.batch_inputs(seed + 5, chains, cfg["phi_var"], cfg["n_pf"])
+    dev = torch.device("cuda")
+    bt = hmcmod.Batch(chains, n_pf=cfg["n_pf"], eps=cfg["eps"], n_leap=cfg["n_leap"], cg_tol=1e-10,
+                      cg_maxit=20000, precision="mixed", reliable_every=50)
+    phi = bt.pack_phi([torch.from_numpy(a[0]).to(dev) for a in ins])
+    pi0 = bt.pack_phi([torch.from_numpy(a[1]).to(dev) for a in ins])
+    eta = bt.pack_spinors([torch.from_numpy(a[2]).to(dev) for a in ins])
+    u = [a[3] for a in ins]
+    del ins
+    vols = [Lt * L * L for L, Lt, _ in chains]
+    out = {"chains": len(chains), "sites": int(sum(vols)), "n_pf": cfg["n_pf"],
+           "L_set": sorted({c[0] for c in chains}), "L_tau_set": sorted({c[1] for c in chains})}
+    out["autotune"] = bt.autotune(phi, eta)
+    log(f"batch: {len(chains)} chains, {sum(vols)} sites, autotune {out['autotune']}")
+    chi = bt.apply(phi, eta, dagger=True)
+    for graphs in (False, True):
+        bt.set_graphs(graphs)
+        bt.cg_solve(phi, chi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = bt.cg_solve(phi, chi)
+        el = time.perf_counter() - t0
+        site_it = sum(it * vols[j // cfg["n_pf"]] for j, it in enumerate(st["iterations"]))
+        b_it = BYTES_PER_SITE["cg_a_f32"] + BYTES_PER_SITE["cg_b_f32"]
+        out["cg_solve_" + ("graph" if graphs else "eager")] = {
+            "s": el, "max_iterations": max(st["iterations"]), "unit_iterations": sum(st["iterations"]),
+            "site_iterations_per_s": site_it / el, "effective_GB/s": site_it * b_it / el / 1e9,
+            "max_true_resid": max(st["true_resid"])}
+        log(f"batch cg ({'graph' if graphs else 'eager'}): {el:.3f} s, max iterations "
+            f"{max(st['iterations'])}, effective {site_it * b_it / el / 1e9:.0f} GB/s")
+    bt.set_graphs(True)
+    for _ in range(warmup):
+        bt.trajectory(phi, pi0, eta, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc, its = 0, 0
+    for i in range(steps):
+        st = bt.trajectory(phi, pi0, eta, u)
+        acc += st["accepted"]
+        its += st["cg_iterations"]
+        log(f"batch trajectory {i}: accepted {st['accepted']}/{len(chains)}, unit CG iterations "
+            f"{st['cg_iterations']}, max |dH| {max(abs(d) for d in st['dH_chains']):.3g}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out.update({"batch_trajectories": steps, "s_per_batch_trajectory": el / steps,
+                "chain_trajectories_per_hour": 3600.0 * steps * len(chains) / el,
+                "acceptance": acc / (steps * len(chains)),
+                "unit_cg_iterations_per_s": its / el})
+    bt.close()
+    return out
 
 
 def cpu_baseline(L, Lt, seed, budget_s=15.0):
@@ -305,6 +368,8 @@ def main():
                 "applies_per_s": aps, "GB/s": gbs, "ms": ms, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
                 "buffer_sets": nsets, "bytes_per_site": 2 * BYTES_PER_SITE["apply_f32" if f32 else "apply_f64"]}
             log(f"isolated M^dag M {'f32' if f32 else 'f64'}: {aps:.0f} applies/s, {gbs:.0f} GB/s")
+        if args.batch_steps > 0:
+            extras["batch_64_chains"] = batch_bench(hmcmod, torch, args.seed, args.batch_steps, 1)
         if not args.no_cpu:
             model, ncpu = cpu_info()
             result["cpu_baseline"] = cpu_baseline(L, Lt, args.seed)

@@ -203,9 +203,11 @@ int hmc_leapfrog(hmc_ctx* ctx, double* phi_inout, double* pi_inout, const void* 
                  hmc_traj_stats* stats, void* stream);
 
 /* Sampled kernel timing, for measuring the solver kernels inside real work.  When
- * enabled, the CG driver brackets the first iteration of every status chunk in which all
- * right-hand sides are still iterating with HIP events on the caller's stream, and adds
- * the two kernel durations to the accumulators below.  Enabling resets them.
+ * enabled, the CG driver times the middle iteration of every status chunk in which all
+ * right-hand sides are iterating (start and stop timestamps taken by the two kernels'
+ * own dispatches, hipExtLaunchKernel events, so nothing is inserted between kernels) and
+ * adds the two kernel durations to the accumulators below.  Eager launches only (no
+ * samples while CG chunks replay from graphs).  Enabling resets them.
  * Index: [0] CG step A (t = M p with the fused x and p updates), FP32 Krylov precision;
  * [1] CG step B (r -= alpha M^dagger t), FP32; [2] step A, FP64; [3] step B, FP64. */
 typedef struct hmc_kernel_times {
@@ -223,16 +225,20 @@ int hmc_set_kernel_timing(hmc_ctx* ctx, int enable);
 int hmc_set_cg_workgroups(hmc_ctx* ctx, int precision, int max_per_rhs);
 int hmc_get_cg_workgroups(const hmc_ctx* ctx, int precision);
 
-/* Result of hmc_autotune (host struct). */
+/* Result of hmc_autotune (host struct).  Index [0] FP64, [1] mixed precision. */
+#define HMC_TUNE_MAX 12
 typedef struct hmc_tune_result {
-    int    cg_workgroups[2];   /* chosen workgroups per right-hand side: [0] FP64, [1] mixed  */
+    int    cg_workgroups[2];   /* chosen workgroups per right-hand side                       */
     double us_per_iter[2];     /* measured time per CG iteration at the choice (microseconds) */
-    int    candidates;         /* launch shapes timed                                          */
+    int    candidates;         /* launch shapes timed, both precisions                         */
+    int    tried[2];           /* launch shapes timed per precision (<= HMC_TUNE_MAX)          */
+    int    tried_workgroups[2][HMC_TUNE_MAX];  /* each shape timed ...                         */
+    double tried_us[2][HMC_TUNE_MAX];          /* ... and its time per CG iteration (us)       */
 } hmc_tune_result;
 
 /* Autotuner of the CG launch shape.  For each precision, times 100 CG iterations on the
  * caller's phi and right-hand sides b (n complex128 spinors, n <= max_rhs) at each
- * candidate workgroup count (128 ... 4096, capped at the tile count) with HIP events on the
+ * candidate workgroup count (12 multiples of 8 from 128 to 4096, capped at the tile count) with HIP events on the
  * stream, keeps the fastest, and records the choice process-wide so that later contexts of
  * the same lattice, right-hand-side count and device start with it.  Uses the context's
  * workspace (no other allocation); the run parameters are restored afterwards.

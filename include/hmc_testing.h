@@ -27,6 +27,12 @@ int hmc_test_site(int L, int L_tau, int s, int out[12]);
  * XCDs) to a logical tile id.  A bijection on [0, nblocks). */
 int hmc_test_xcd_remap(int bid, int nblocks);
 
+/* The tiles a CG or apply workgroup works on: workgroup blk of the bpr workgroups of one
+ * right-hand side, over nt tiles, takes tiles out[0], out[0] + out[2], ... below out[1].
+ * Over blk in [0, bpr) these sets partition [0, nt).  Returns 0, or -1 for blk outside
+ * [0, bpr), bpr < 1 or nt < 0. */
+int hmc_test_tile_span(int blk, int bpr, int nt, int out[3]);
+
 #ifdef __cplusplus
 }
 #endif

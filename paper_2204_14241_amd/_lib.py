@@ -25,7 +25,7 @@ EXPORTED = [
     "hmc_apply_M", "hmc_apply_Mdag", "hmc_apply_MdagM", "hmc_apply_M_f32", "hmc_apply_Mdag_f32",
     "hmc_apply_MdagM_f32", "hmc_cg_solve", "hmc_heatbath", "hmc_force",
     "hmc_force_from_solution", "hmc_pf_action", "hmc_boson_action", "hmc_trajectory",
-    "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap",
+    "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap", "hmc_test_tile_span",
     "hmc_set_kernel_timing", "hmc_get_kernel_times", "hmc_set_cg_workgroups",
     "hmc_get_cg_workgroups", "hmc_leapfrog", "hmc_autotune", "hmc_set_graphs",
     "hmc_batch_create", "hmc_batch_destroy", "hmc_batch_workspace_bytes",
@@ -79,9 +79,25 @@ class HmcTrajStats(ctypes.Structure):
     ]
 
 
+HMC_TUNE_MAX = 12
+
+
 class HmcTuneResult(ctypes.Structure):
     _fields_ = [("cg_workgroups", ctypes.c_int * 2), ("us_per_iter", ctypes.c_double * 2),
-                ("candidates", ctypes.c_int)]
+                ("candidates", ctypes.c_int), ("tried", ctypes.c_int * 2),
+                ("tried_workgroups", (ctypes.c_int * HMC_TUNE_MAX) * 2),
+                ("tried_us", (ctypes.c_double * HMC_TUNE_MAX) * 2)]
+
+
+def tune_dict(r):
+    """hmc_tune_result as {"fp64": (workgroups, us), "mixed": ..., "candidates": n,
+    "tried": {"fp64": [(workgroups, us), ...], "mixed": [...]}}."""
+    names = ("fp64", "mixed")
+    out = {names[i]: (r.cg_workgroups[i], r.us_per_iter[i]) for i in range(2)}
+    out["candidates"] = r.candidates
+    out["tried"] = {names[i]: [(r.tried_workgroups[i][j], r.tried_us[i][j]) for j in range(r.tried[i])]
+                    for i in range(2)}
+    return out
 
 
 class HmcKernelTimes(ctypes.Structure):
@@ -129,6 +145,7 @@ def load():
         "hmc_last_error": (ctypes.c_char_p, []),
         "hmc_test_site": (I, [I, I, I, ctypes.POINTER(ctypes.c_int)]),
         "hmc_test_xcd_remap": (I, [I, I]),
+        "hmc_test_tile_span": (I, [I, I, I, ctypes.POINTER(ctypes.c_int)]),
         "hmc_set_kernel_timing": (I, [P, I]),
         "hmc_get_kernel_times": (I, [P, ctypes.POINTER(HmcKernelTimes)]),
         "hmc_set_cg_workgroups": (I, [P, I, I]),

@@ -6,6 +6,7 @@
 // Every step of the path runs in the kernels of kernels.h; the host only sequences
 // launches on the caller's stream and reads back per-solve status records (CG
 // convergence) and the energies of a trajectory.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -150,9 +151,10 @@ struct hmc_ctx {
     double* h_slots = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
 
-    // sampled kernel timing (timing-enabled events, one triple per status slot)
+    // sampled kernel timing: start/stop events of steps A and B, taken by the dispatch of the
+    // kernel itself (no marker packets between kernels), one set per status slot
     bool timing = false;
-    hipEvent_t tev[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    hipEvent_t tev[2][4] = {{nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr}};
     hmc_kernel_times kt{};
 
     // graph replay of CG chunks
@@ -415,21 +417,33 @@ static int enqueue_chunk(hmc_ctx* c, Geo geo, int grid, int n, const double* phi
     const R* phik = KrylovBufs<R>::phi(c, phi64);
     const Coef<R> cf = KrylovBufs<R>::cf(c);
     for (int i = 0; i < chunk; ++i) {
-        const bool smp = sample && i == chunk / 2;
-        if (smp) HIPCHK(hipEventRecord(c->tev[kslot][0], s));
         const int expect_a = i > 0 ? PEND_RR : (first ? PEND_BB : PEND_NONE);
-        if constexpr (sizeof(R) == sizeof(float))
-            hipLaunchKernelGGL(k_cg_a2<Geo>, dim3(grid), dim3(kBlock), 0, s, next_ctl(c, expect_a), geo, v, phik, cf);
-        else
-            hipLaunchKernelGGL((k_cg_a<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, expect_a), geo, v, phik, cf);
+        const CgCtl ka = next_ctl(c, expect_a), kb = next_ctl(c, PEND_TT);
+        if (sample && i == chunk / 2) {
+            // timestamps from the dispatches themselves (not captured into graphs)
+            hipEvent_t* e = c->tev[kslot];
+            if constexpr (sizeof(R) == sizeof(float)) {
+                hipExtLaunchKernelGGL(k_cg_a2<Geo>, dim3(grid), dim3(kBlock), 0, s, e[0], e[1], 0, ka, geo, v, phik, cf);
+                LAUNCHCHK();
+                hipExtLaunchKernelGGL(k_cg_b2<Geo>, dim3(grid), dim3(kBlock), 0, s, e[2], e[3], 0, kb, geo, v, phik, cf);
+            } else {
+                hipExtLaunchKernelGGL(k_cg_a<R, Geo>, dim3(grid), dim3(kBlock), 0, s, e[0], e[1], 0, ka, geo, v, phik, cf);
+                LAUNCHCHK();
+                hipExtLaunchKernelGGL(k_cg_b<R, Geo>, dim3(grid), dim3(kBlock), 0, s, e[2], e[3], 0, kb, geo, v, phik, cf);
+            }
+            LAUNCHCHK();
+            continue;
+        }
+        if constexpr (sizeof(R) == sizeof(float)) {
+            hipLaunchKernelGGL(k_cg_a2<Geo>, dim3(grid), dim3(kBlock), 0, s, ka, geo, v, phik, cf);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_cg_b2<Geo>, dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
+        } else {
+            hipLaunchKernelGGL((k_cg_a<R, Geo>), dim3(grid), dim3(kBlock), 0, s, ka, geo, v, phik, cf);
+            LAUNCHCHK();
+            hipLaunchKernelGGL((k_cg_b<R, Geo>), dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
+        }
         LAUNCHCHK();
-        if (smp) HIPCHK(hipEventRecord(c->tev[kslot][1], s));
-        if constexpr (sizeof(R) == sizeof(float))
-            hipLaunchKernelGGL(k_cg_b2<Geo>, dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_TT), geo, v, phik, cf);
-        else
-            hipLaunchKernelGGL((k_cg_b<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_TT), geo, v, phik, cf);
-        LAUNCHCHK();
-        if (smp) HIPCHK(hipEventRecord(c->tev[kslot][2], s));
     }
     hipLaunchKernelGGL((k_ru_fold<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_RR), geo, x, v, filter);
     LAUNCHCHK();
@@ -550,7 +564,7 @@ static int cg_run(hmc_ctx* c, Geo geo, int grid, int n, const double* phi64, con
             if (sample && start_active_prev && all_active) {
                 float ta = 0.f, tb = 0.f;
                 HIPCHK(hipEventElapsedTime(&ta, c->tev[(k - 1) & 1][0], c->tev[(k - 1) & 1][1]));
-                HIPCHK(hipEventElapsedTime(&tb, c->tev[(k - 1) & 1][1], c->tev[(k - 1) & 1][2]));
+                HIPCHK(hipEventElapsedTime(&tb, c->tev[(k - 1) & 1][2], c->tev[(k - 1) & 1][3]));
                 c->kt.ms[kt_a] += ta;
                 c->kt.ms[kt_a + 1] += tb;
                 c->kt.count[kt_a] += 1;
@@ -791,7 +805,7 @@ static int create_common(hmc_ctx* c) {
 
 static void destroy_common(hmc_ctx* c) {
     for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < 4; ++j)
             if (c->tev[i][j]) (void)hipEventDestroy(c->tev[i][j]);
     for (int p = 0; p < 2; ++p)
         for (int g = 0; g < 2; ++g)
@@ -850,7 +864,7 @@ static int set_workspace_common(hmc_ctx* c, void* ptr, size_t bytes) {
 // Autotuner core: time `iters` CG iterations per candidate shape and keep the fastest.
 static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int n, hmc_tune_result* out,
                            hipStream_t s) {
-    static const int cand[] = {128, 256, 384, 512, 768, 1024, 1536, 2048, 4096};
+    static const int cand[HMC_TUNE_MAX] = {128, 256, 384, 512, 640, 768, 1024, 1280, 1536, 2048, 3072, 4096};
     const hmc_params saved = c->p;
     const int iters = 100;
     std::memset(out, 0, sizeof(*out));
@@ -887,6 +901,9 @@ static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int 
             if (result != HMC_OK) break;
             out->candidates += 1;
             const double us = 1e3 * ms / iters;
+            out->tried_workgroups[pi][out->tried[pi]] = bpr;
+            out->tried_us[pi][out->tried[pi]] = us;
+            out->tried[pi] += 1;
             if (us < best) { best = us; best_bpr = bpr; }
         }
         if (result == HMC_OK) {
@@ -984,6 +1001,15 @@ int hmc_test_xcd_remap(int bid, int nb) {
     return xcd_remap(bid, nb);
 }
 
+int hmc_test_tile_span(int blk, int bpr, int nt, int out[3]) {
+    if (out == nullptr || bpr < 1 || blk < 0 || blk >= bpr || nt < 0) return -1;
+    const TileSpan t = tile_span(blk, bpr, nt);
+    out[0] = t.first;
+    out[1] = t.end;
+    out[2] = t.step;
+    return 0;
+}
+
 int hmc_create(int L, int Lt, double dtau, const hmc_params* params, hmc_ctx** out) {
     g_last_error.clear();
     if (out == nullptr) return fail(HMC_ERR_INVALID_ARG, "out is NULL");
@@ -1036,7 +1062,7 @@ int hmc_set_kernel_timing(hmc_ctx* c, int enable) {
     if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
     if (enable && c->tev[0][0] == nullptr) {
         for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 3; ++j) HIPCHK(hipEventCreate(&c->tev[i][j]));
+            for (int j = 0; j < 4; ++j) HIPCHK(hipEventCreate(&c->tev[i][j]));
     }
     c->timing = enable != 0;
     std::memset(&c->kt, 0, sizeof(c->kt));

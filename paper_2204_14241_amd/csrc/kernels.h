@@ -194,6 +194,33 @@ struct GeoBatch {
     }
 };
 
+// Tiles of workgroup blk among the bpr workgroups of a unit with nt tiles.  When bpr is a
+// multiple of the XCD count, the tiles are cut into kNumXcd contiguous regions and the
+// bpr / kNumXcd workgroups of region g stride through it together (with the XCD remap, the
+// workgroups of a region share an XCD when the unit's workgroups are XCD-aligned): the
+// time-slice neighbours of the tiles a region is working on are then the tiles it has just
+// done or does next, still in that XCD's L2.  Otherwise workgroup b takes tiles b, b + bpr, ...
+// Either way the workgroups partition [0, nt).
+struct TileSpan {
+    int first, end, step;
+};
+__host__ __device__ __forceinline__ TileSpan tile_span(int blk, int bpr, int nt) {
+    TileSpan t;
+    if (bpr % kNumXcd == 0) {
+        const int per = bpr / kNumXcd;
+        const int g = blk / per, m = blk - g * per;
+        const int lo = int((long long)g * nt / kNumXcd), hi = int((long long)(g + 1) * nt / kNumXcd);
+        t.first = lo + m;
+        t.end = hi;
+        t.step = per;
+    } else {
+        t.first = blk;
+        t.end = nt;
+        t.step = bpr;
+    }
+    return t;
+}
+
 __device__ __forceinline__ int tiles1(const Lat& l) { return (l.vol + kBlock - 1) / kBlock; }
 __device__ __forceinline__ int tiles2(const Lat& l) { return (l.vol / 2 + kBlock - 1) / kBlock; }
 
@@ -371,7 +398,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo geo, const C2<R>* __restri
     SrcPlain<R> src{in + pos.voff, lat.vol};
     C2<R>* dst = out + pos.voff;
     const int nt = tiles1(lat);
-    for (int tile = pos.blk; tile < nt; tile += pos.bpr) {
+    for (TileSpan sp = tile_span(pos.blk, pos.bpr, nt); sp.first < sp.end; sp.first += sp.step) {
+        const int tile = sp.first;
         const int s = tile * kBlock + threadIdx.x;
         if (s >= lat.vol) break;
         const Nbr nb = neighbours(lat, s);
@@ -424,7 +452,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, Geo geo, CgVecs<R> v
     C2<R>* t = v.t + off;
     SrcXpay<R> src{r, pin, beta, lat.vol};
     double part = 0.0;
-    for (int tile = pos.blk; tile < tiles1(lat); tile += pos.bpr) {
+    for (TileSpan sp = tile_span(pos.blk, pos.bpr, tiles1(lat)); sp.first < sp.end; sp.first += sp.step) {
+        const int tile = sp.first;
         const int s = tile * kBlock + threadIdx.x;
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
@@ -470,7 +499,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(CgCtl ctl, Geo geo, CgVecs<R> v
     SrcPlain<R> src{v.t + off, lat.vol};
     C2<R>* r = v.r + off;
     double part = 0.0;
-    for (int tile = pos.blk; tile < tiles1(lat); tile += pos.bpr) {
+    for (TileSpan sp = tile_span(pos.blk, pos.bpr, tiles1(lat)); sp.first < sp.end; sp.first += sp.step) {
+        const int tile = sp.first;
         const int s = tile * kBlock + threadIdx.x;
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
@@ -509,7 +539,8 @@ __global__ __launch_bounds__(kBlock) void k_ru_fold(CgCtl ctl, Geo geo, double2*
     const size_t off = pos.voff;
     const C2<R>* p = (S.pbuf ? v.p1 : v.p0) + off;
     const bool separate = (void*)v.x != (void*)x64;
-    for (int tile = pos.blk; tile < tiles1(lat); tile += pos.bpr) {
+    for (TileSpan sp = tile_span(pos.blk, pos.bpr, tiles1(lat)); sp.first < sp.end; sp.first += sp.step) {
+        const int tile = sp.first;
         const int s = tile * kBlock + threadIdx.x;
         if (s >= lat.vol) break;
 #pragma unroll
@@ -548,7 +579,8 @@ __global__ __launch_bounds__(kBlock) void k_ru_apply(CgCtl ctl, Geo geo, const d
     if (!((1 << mode) & filter)) return;
     const size_t off = pos.voff;
     SrcPlain<double> src{x64 + off, lat.vol};
-    for (int tile = pos.blk; tile < tiles1(lat); tile += pos.bpr) {
+    for (TileSpan sp = tile_span(pos.blk, pos.bpr, tiles1(lat)); sp.first < sp.end; sp.first += sp.step) {
+        const int tile = sp.first;
         const int s = tile * kBlock + threadIdx.x;
         if (s >= lat.vol) break;
         const Nbr nb = neighbours(lat, s);
@@ -578,7 +610,8 @@ __global__ __launch_bounds__(kBlock) void k_ru_resid(CgCtl ctl, Geo geo, const d
     const size_t off = pos.voff;
     SrcPlain<double> src{t64 + off, lat.vol};
     double part = 0.0;
-    for (int tile = pos.blk; tile < tiles1(lat); tile += pos.bpr) {
+    for (TileSpan sp = tile_span(pos.blk, pos.bpr, tiles1(lat)); sp.first < sp.end; sp.first += sp.step) {
+        const int tile = sp.first;
         const int s = tile * kBlock + threadIdx.x;
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
@@ -608,7 +641,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgCtl ctl, Geo geo, const do
     const size_t off = pos.voff;
     const bool separate = (void*)v.x != (void*)x64;
     double part = 0.0;
-    for (int tile = pos.blk; tile < tiles1(lat); tile += pos.bpr) {
+    for (TileSpan sp = tile_span(pos.blk, pos.bpr, tiles1(lat)); sp.first < sp.end; sp.first += sp.step) {
+        const int tile = sp.first;
         const int s = tile * kBlock + threadIdx.x;
         if (s < lat.vol) {
 #pragma unroll
@@ -738,7 +772,8 @@ __global__ __launch_bounds__(kBlock) void k_apply2(Geo geo, const float2* __rest
     const size_t off = pos.voff;
     SrcPlain2 src{in + off, lat.vol};
     const int nt = tiles2(lat);
-    for (int tile = pos.blk; tile < nt; tile += pos.bpr) {
+    for (TileSpan sp = tile_span(pos.blk, pos.bpr, nt); sp.first < sp.end; sp.first += sp.step) {
+        const int tile = sp.first;
         const int s = 2 * (tile * kBlock + threadIdx.x);
         if (s >= lat.vol) break;
         const Nbr nb = neighbours(lat, s);
@@ -772,7 +807,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_a2(CgCtl ctl, Geo geo, CgVecs<flo
     float2* t = v.t + off;
     SrcXpay2 src{r, pin, beta, lat.vol};
     double part = 0.0;
-    for (int tile = pos.blk; tile < tiles2(lat); tile += pos.bpr) {
+    for (TileSpan sp = tile_span(pos.blk, pos.bpr, tiles2(lat)); sp.first < sp.end; sp.first += sp.step) {
+        const int tile = sp.first;
         const int s = 2 * (tile * kBlock + threadIdx.x);
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
@@ -818,7 +854,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_b2(CgCtl ctl, Geo geo, CgVecs<flo
     SrcPlain2 src{v.t + off, lat.vol};
     float2* r = v.r + off;
     double part = 0.0;
-    for (int tile = pos.blk; tile < tiles2(lat); tile += pos.bpr) {
+    for (TileSpan sp = tile_span(pos.blk, pos.bpr, tiles2(lat)); sp.first < sp.end; sp.first += sp.step) {
+        const int tile = sp.first;
         const int s = 2 * (tile * kBlock + threadIdx.x);
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);

@@ -137,8 +137,7 @@ class HMC:
         b, n = self._spinors(b)
         r = _lib.HmcTuneResult()
         self._call("hmc_autotune", _ptr(phi), _ptr(b), n, ctypes.byref(r), _stream())
-        return {"fp64": (r.cg_workgroups[0], r.us_per_iter[0]),
-                "mixed": (r.cg_workgroups[1], r.us_per_iter[1]), "candidates": r.candidates}
+        return _lib.tune_dict(r)
 
     def kernel_times(self):
         """{name: (average ms, samples)} of the sampled CG kernels."""
@@ -401,8 +400,7 @@ class Batch:
         self._check(b, torch.complex128, self.spinor_offsets[-1], "b")
         r = _lib.HmcTuneResult()
         self._call("hmc_batch_autotune", _ptr(phi), _ptr(b), ctypes.byref(r), _stream())
-        return {"fp64": (r.cg_workgroups[0], r.us_per_iter[0]),
-                "mixed": (r.cg_workgroups[1], r.us_per_iter[1]), "candidates": r.candidates}
+        return _lib.tune_dict(r)
 
     def trajectory(self, phi, pi0, eta, u):
         """One trajectory of every chain; phi is updated in place.  u: nchains uniforms."""
@@ -440,3 +438,10 @@ def test_site(L, Lt, s):
 
 def test_xcd_remap(bid, nb):
     return _lib.load().hmc_test_xcd_remap(bid, nb)
+
+
+def test_tile_span(blk, bpr, nt):
+    """(first, end, step) of the tiles workgroup blk of bpr works on (no GPU needed)."""
+    out = (ctypes.c_int * 3)()
+    rc = _lib.load().hmc_test_tile_span(blk, bpr, nt, out)
+    return None if rc else tuple(out)

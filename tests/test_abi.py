@@ -39,16 +39,20 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_c(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "hmc.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(hmc_params), '
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(hmc_params), '
                    'sizeof(hmc_cg_stats), sizeof(hmc_traj_stats), offsetof(hmc_params, cg_tol), '
-                   'offsetof(hmc_cg_stats, true_resid), offsetof(hmc_traj_stats, max_true_resid));'
+                   'offsetof(hmc_cg_stats, true_resid), offsetof(hmc_traj_stats, max_true_resid), '
+                   'sizeof(hmc_tune_result), offsetof(hmc_tune_result, tried_us), '
+                   'sizeof(hmc_kernel_times), offsetof(hmc_kernel_times, count));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     P, C, T = _lib.HmcParams, _lib.HmcCgStats, _lib.HmcTrajStats
+    U, K = _lib.HmcTuneResult, _lib.HmcKernelTimes
     assert got == [ctypes.sizeof(P), ctypes.sizeof(C), ctypes.sizeof(T), P.cg_tol.offset,
-                   C.true_resid.offset, T.max_true_resid.offset]
+                   C.true_resid.offset, T.max_true_resid.offset, ctypes.sizeof(U),
+                   U.tried_us.offset, ctypes.sizeof(K), K.count.offset]
 
 
 def test_error_strings():
@@ -100,6 +104,26 @@ def test_xcd_remap_is_bijection(nb):
     for x in range(8):
         tiles = sorted(hmc.test_xcd_remap(b, nb) for b in range(x, nb, 8))
         assert tiles == list(range(tiles[0], tiles[0] + len(tiles))) if tiles else True
+
+
+@pytest.mark.parametrize("bpr,nt", [(1, 5), (7, 100), (8, 8), (8, 3), (16, 2500), (512, 2500),
+                                    (1024, 2500), (1024, 5000), (24, 7), (4096, 12)])
+def test_tile_span_partitions(bpr, nt):
+    """Every tile is worked on by exactly one workgroup, in increasing order; with bpr a
+    multiple of 8 each eighth of the workgroups stays inside one contiguous eighth of the
+    tiles."""
+    seen = []
+    for blk in range(bpr):
+        first, end, step = hmc.test_tile_span(blk, bpr, nt)
+        assert step >= 1
+        tiles = list(range(first, end, step))
+        seen += tiles
+        if bpr % 8 == 0:
+            g = blk // (bpr // 8)
+            lo, hi = g * nt // 8, (g + 1) * nt // 8
+            assert all(lo <= t < hi for t in tiles)
+    assert sorted(seen) == list(range(nt))
+    assert hmc.test_tile_span(bpr, bpr, nt) is None
 
 
 def test_create_rejects_bad_arguments_without_gpu():

@@ -107,6 +107,9 @@ def test_autotune_then_solve(hip):
     for prec in ("fp64", "mixed"):
         wg, us = res[prec]
         assert 1 <= wg <= ntiles2 and us > 0
+        tried = res["tried"][prec]
+        assert (wg, us) in tried and us == min(t for _, t in tried)
+        assert len({w for w, _ in tried}) == len(tried)
     assert h.cg_workgroups() == {"fp64": res["fp64"][0], "mixed": res["mixed"][0]}
     h2 = hip.HMC(L, Lt, cg_tol=1e-10, precision="mixed")
     assert h2.cg_workgroups() == h.cg_workgroups()
