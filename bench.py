@@ -229,6 +229,28 @@ def batch_bench(hmcmod, torch, seed, steps, warmup):
     return out
 
 
+def copy_bench(torch, reps=20):
+    """Device-to-device copy of 1 GiB (torch's copy kernel), two buffer pairs alternated so the
+    256 MB MALL cannot serve them: the practical streaming rate of this GPU, read + write."""
+    n = 2 ** 30
+    bufs = [torch.empty(n, dtype=torch.uint8, device="cuda") for _ in range(4)]
+    for b_ in bufs:
+        b_.fill_(1)
+    for i in range(4):
+        bufs[2 * (i & 1) + 1].copy_(bufs[2 * (i & 1)])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        bufs[2 * (i & 1) + 1].copy_(bufs[2 * (i & 1)])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del bufs
+    torch.cuda.empty_cache()
+    return 2 * n / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(L, Lt, seed, budget_s=15.0):
     """The FP64 oracle's M^dagger M apply on the host (NumPy, one thread), bounded sample."""
     import oracle as O
@@ -368,6 +390,11 @@ def main():
                 "applies_per_s": aps, "GB/s": gbs, "ms": ms, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
                 "buffer_sets": nsets, "bytes_per_site": 2 * BYTES_PER_SITE["apply_f32" if f32 else "apply_f64"]}
             log(f"isolated M^dag M {'f32' if f32 else 'f64'}: {aps:.0f} applies/s, {gbs:.0f} GB/s")
+        cgbs = copy_bench(torch)
+        extras["copy_1GiB_GB/s"] = cgbs
+        if "roofline" in result:
+            result["roofline"]["frac_of_copy"] = result["roofline"]["achieved"] / cgbs
+        log(f"1 GiB device copy: {cgbs:.0f} GB/s (read + write)")
         if args.batch_steps > 0:
             extras["batch_64_chains"] = batch_bench(hmcmod, torch, args.seed, args.batch_steps, 1)
         if not args.no_cpu:

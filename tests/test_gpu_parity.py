@@ -49,6 +49,31 @@ def make(hip, L, Lt, **kw):
 GEOMS = [(4, 8), (6, 5), (10, 7), (12, 40), (40, 100)]
 
 
+@pytest.mark.parametrize("f32", [False, True])
+def test_apply_matches_hand_derived_eq17_entries(hip, f32):
+    """The GPU's M applied to unit vectors reproduces the entries of Eq. (17) worked out by
+    hand in tests/golden/eq17_entries.txt (FP64 to 1e-15; FP32 to 1e-7, the rounding of the
+    coefficients to single precision)."""
+    import golden_fixtures as G
+    cfg = G.EQ17_MODEL
+    L, Lt = cfg["L"], cfg["Lt"]
+    entries = G.eq17_entries()
+    cols = sorted({c for _, c, _, _ in entries})
+    e = np.zeros((len(cols), 2, 2, Lt, L, L), dtype=np.complex128)
+    for k, c in enumerate(cols):
+        e[(k,) + c] = 1.0
+    h = make(hip, L, Lt, dtau=cfg["dtau"], model=dict(t=cfg["t"], mu=cfg["mu"], lam=cfg["lam"]))
+    phi = to_dev(G.eq17_phi())
+    if f32:
+        cols_out = to_np(h.apply_M_f32(phi.float(), to_dev(e).to(torch.complex64))).astype(np.complex128)
+    else:
+        cols_out = to_np(h.apply_M(phi, to_dev(e)))
+    cols_out = cols_out.reshape(len(cols), 2, 2, Lt, L, L)
+    for row, col, val, note in entries:
+        got = cols_out[(cols.index(col),) + row]
+        assert abs(got - val) < (1e-7 if f32 else 1e-15), (row, col, got, val, note)
+
+
 @pytest.mark.parametrize("L,Lt", GEOMS)
 def test_apply_fp64_matches_oracle(hip, L, Lt):
     say(f"apply fp64 L={L} Lt={Lt}")

@@ -45,6 +45,21 @@ def test_index_map_is_row_major_alpha_s_tau_x_y():
     assert seen == set(range(m.dim))
 
 
+def test_dense_matrix_matches_hand_derived_eq17_entries():
+    """Entries of Eq. (17) worked out by hand (tests/golden/eq17_entries.txt): diagonal,
+    forward and antiperiodic time links, hopping per band and direction, the Yukawa block
+    with its staggered sign, and entries that must vanish."""
+    import golden_fixtures as G
+    cfg = G.EQ17_MODEL
+    m = O.Model(L=cfg["L"], Lt=cfg["Lt"], dtau=cfg["dtau"], t=cfg["t"], mu=cfg["mu"], lam=cfg["lam"])
+    D = O.dense_M(m, G.eq17_phi())
+    entries = G.eq17_entries()
+    assert len(entries) >= 15
+    for row, col, val, note in entries:
+        got = D[O.spinor_index(m, *row), O.spinor_index(m, *col)]
+        assert abs(got - val) < 1e-15, (row, col, got, val, note)
+
+
 def test_dense_matches_matrix_free(tiny_inputs):
     phi = tiny_inputs[0]
     m = tiny()
