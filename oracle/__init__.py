@@ -19,6 +19,7 @@ action        pseudofermion heat-bath and action (Eq. 19-21, Methods D), its
 hmc           Hamiltonian of Eq. (28), leapfrog for Eq. (29), Metropolis step
 closed_forms  free-fermion (lambda = 0) determinant and spectrum, the BSS form of
               Eq. (18), the uniform-field determinant, free-boson leapfrog per mode
+precond       the twisted-Fourier preconditioner of Eq. (23)-(26) and preconditioned CG
 
 Every function is plain NumPy in float64/complex128, written for readability,
 not speed.
@@ -30,6 +31,7 @@ from .solver import cg_solve
 from .action import (heatbath, pf_action, pf_action_dense, pf_force, boson_action,
                      boson_force, total_force)
 from .hmc import hamiltonian, leapfrog, trajectory, metropolis_accept
+from .precond import kinetic_symbol, apply_precond, pcg_solve
 from . import closed_forms
 
 __all__ = [
@@ -37,5 +39,6 @@ __all__ = [
     "dense_M", "apply_M", "apply_Mdag", "apply_MdagM", "dense_MdagM",
     "time_slice_block", "cg_solve", "heatbath", "pf_action", "pf_action_dense",
     "pf_force", "boson_action", "boson_force", "total_force", "hamiltonian",
-    "leapfrog", "trajectory", "metropolis_accept", "closed_forms",
+    "leapfrog", "trajectory", "metropolis_accept", "closed_forms", "kinetic_symbol",
+    "apply_precond", "pcg_solve",
 ]

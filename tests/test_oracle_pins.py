@@ -259,3 +259,68 @@ def test_metropolis_rule():
     assert O.metropolis_accept(0.5, np.exp(-0.5) - 1e-12)
     assert not O.metropolis_accept(0.5, np.exp(-0.5))
     assert not O.metropolis_accept(np.inf, 0.0)
+
+
+# ---------------------------------------------------------------------------------------------
+# Fourier preconditioner (Methods C, Eq. 23-26)
+
+def _plane_wave(m, band, spin, n, kx, ky):
+    """The twisted plane wave exp(i w_n tau + 2 pi i (kx x + ky y)/L) in one (band, spin)."""
+    v = np.zeros(m.spinor_shape(), dtype=complex)
+    w = np.pi * (2 * n + 1) / m.Lt
+    tau = np.arange(m.Lt)[:, None, None]
+    x = np.arange(m.L)[None, :, None]
+    y = np.arange(m.L)[None, None, :]
+    v[band, spin] = np.exp(1j * (w * tau + 2 * np.pi * (kx * x + ky * y) / m.L))
+    return v
+
+
+def test_kinetic_symbol_is_the_eigenvalue_of_dense_K():
+    """K = M at phi = 0 (Eq. 23).  Each twisted plane wave is an eigenvector of the dense K
+    built entry by entry from Eq. (17), with eigenvalue K_hat."""
+    m = O.Model(L=6, Lt=5, mu=(0.5, 0.3))
+    K = O.dense_M(m, np.zeros(m.phi_shape()))
+    Kh = O.kinetic_symbol(m)
+    for band, spin, n, kx, ky in [(0, 0, 0, 0, 0), (1, 1, 4, 2, 5), (0, 1, 2, 3, 1), (1, 0, 1, 5, 3)]:
+        v = _plane_wave(m, band, spin, n, kx, ky).ravel()
+        assert np.allclose(K @ v, Kh[band, n, kx, ky] * v, atol=1e-13)
+
+
+def test_precond_inverts_dense_kinetic_normal_operator():
+    """P (K^dagger K) = 1 (Eq. 26) with K the dense phi = 0 matrix of Eq. (17)."""
+    m = O.Model(L=4, Lt=6, mu=(0.5, 0.3))
+    K = O.dense_M(m, np.zeros(m.phi_shape()))
+    KK = K.conj().T @ K
+    PK = np.stack([O.apply_precond(m, KK[:, j]).ravel() for j in range(m.dim)], axis=1)
+    assert np.abs(PK - np.eye(m.dim)).max() < 1e-12
+
+
+def test_precond_is_hermitian_positive_definite():
+    m = tiny()
+    g = S.rng(41)
+    u, v = S.draw_spinor(g, 4, 8, 2)
+    Pu, Pv = O.apply_precond(m, u), O.apply_precond(m, v)
+    assert abs(np.vdot(u.ravel(), Pv.ravel()) - np.conj(np.vdot(v.ravel(), Pu.ravel()))) < 1e-12
+    assert np.vdot(v.ravel(), Pv.ravel()).real > 0
+
+
+def test_pcg_exact_at_zero_coupling():
+    """At lambda = 0, P is the inverse of the normal operator: one iteration (Methods C)."""
+    m = O.Model(L=6, Lt=10, lam=0.0)
+    g = S.rng(42)
+    phi = S.draw_phi(g, 6, 10, 1.0)
+    b = S.draw_spinor(g, 6, 10, 1)[0]
+    x, it, rel = O.pcg_solve(m, phi, b, tol=1e-12)
+    assert it == 1 and rel <= 1e-12
+
+
+def test_pcg_matches_dense_solve_in_fewer_iterations(tiny_inputs):
+    phi0, _, etas, _ = tiny_inputs
+    m = tiny()
+    b = O.heatbath(m, phi0, etas[0])
+    x, it, rel = O.pcg_solve(m, phi0, b, tol=1e-11)
+    xd = np.linalg.solve(O.dense_MdagM(m, phi0), b.ravel())
+    assert rel <= 1e-11
+    assert np.linalg.norm(x.ravel() - xd) <= 1e-9 * np.linalg.norm(xd)
+    _, it_cg, _ = O.cg_solve(m, phi0, b, tol=1e-11)
+    assert it < it_cg
