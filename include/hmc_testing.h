@@ -1,12 +1,14 @@
 /*
- * hmc_testing.h -- host-callable integer helpers of libhmc, exported so that the lattice
- * indexing the kernels use can be checked bit for bit on a machine without a GPU.
+ * hmc_testing.h -- host-callable helpers of libhmc, exported so that the lattice indexing and
+ * the FFT the kernels use can be checked on a machine without a GPU.
  *
- * They are the same __host__ __device__ functions the kernels call, compiled for the
- * host.  All arguments are plain integers; nothing here touches a device.
+ * They run the same __host__ __device__ functions the kernels call, compiled for the host.
+ * Arguments are plain integers and host arrays; nothing here touches a device.
  */
 #ifndef HMC_TESTING_H
 #define HMC_TESTING_H
+
+#include "hmc.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -32,6 +34,21 @@ int hmc_test_xcd_remap(int bid, int nblocks);
  * Over blk in [0, bpr) these sets partition [0, nt).  Returns 0, or -1 for blk outside
  * [0, bpr), bpr < 1 or nt < 0. */
 int hmc_test_tile_span(int blk, int bpr, int nt, int out[3]);
+
+/* The in-place mixed-radix FFT of the preconditioner (fft.h), run on the host in FP64 on one
+ * line of n complex numbers (interleaved re, im).  Forward (inverse = 0): the unnormalised
+ * transform sum_m x_m exp(-2 pi i m k / n), frequency k left at the position p with
+ * hmc_test_fft_freq(n, p) = k.  Inverse: the conjugate transpose of the forward map, so that
+ * inverse(forward(x)) = n x.  Returns 0, or -1 if n has a prime factor above 13. */
+int hmc_test_fft(int n, int inverse, const double* in, double* out);
+int hmc_test_fft_freq(int n, int pos);
+
+/* The Fourier preconditioner P = (K K^dagger)^{-1} of Methods C (Eq. 26) applied on the host
+ * in FP64 to one spinor (complex128, [4][L_tau][L][L]) by the same three passes the kernels
+ * run (2-D transforms per slice, twisted tau transform with the symbol, inverse 2-D).  rz
+ * (optional) receives <in, P in> from the Fourier-space sum.  Returns 0 or -1. */
+int hmc_test_precond(int L, int L_tau, double dtau, const hmc_params* params, const double* in,
+                     double* out, double* rz);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,8 @@ EXPORTED = [
     "hmc_apply_M", "hmc_apply_Mdag", "hmc_apply_MdagM", "hmc_apply_M_f32", "hmc_apply_Mdag_f32",
     "hmc_apply_MdagM_f32", "hmc_cg_solve", "hmc_heatbath", "hmc_force",
     "hmc_force_from_solution", "hmc_pf_action", "hmc_boson_action", "hmc_trajectory",
-    "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap", "hmc_test_tile_span",
+    "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap", "hmc_test_tile_span", "hmc_test_fft",
+    "hmc_test_fft_freq", "hmc_test_precond",
     "hmc_set_kernel_timing", "hmc_get_kernel_times", "hmc_set_cg_workgroups",
     "hmc_get_cg_workgroups", "hmc_leapfrog", "hmc_autotune", "hmc_set_graphs",
     "hmc_batch_create", "hmc_batch_destroy", "hmc_batch_workspace_bytes",
@@ -146,6 +147,10 @@ def load():
         "hmc_test_site": (I, [I, I, I, ctypes.POINTER(ctypes.c_int)]),
         "hmc_test_xcd_remap": (I, [I, I]),
         "hmc_test_tile_span": (I, [I, I, I, ctypes.POINTER(ctypes.c_int)]),
+        "hmc_test_fft": (I, [I, I, ctypes.POINTER(D), ctypes.POINTER(D)]),
+        "hmc_test_fft_freq": (I, [I, I]),
+        "hmc_test_precond": (I, [I, I, D, ctypes.POINTER(HmcParams), ctypes.POINTER(D),
+                                 ctypes.POINTER(D), ctypes.POINTER(D)]),
         "hmc_set_kernel_timing": (I, [P, I]),
         "hmc_get_kernel_times": (I, [P, ctypes.POINTER(HmcKernelTimes)]),
         "hmc_set_cg_workgroups": (I, [P, I, I]),

@@ -23,6 +23,7 @@
 
 #include "../../include/hmc.h"
 #include "../../include/hmc_testing.h"
+#include "fft.h"
 #include "kernels.h"
 #include "lattice.h"
 
@@ -180,14 +181,50 @@ static BosonCoef boson_coef_of(double dt, double cv, double r, double u) {
     return b;
 }
 
+// exp(-2 pi i j / n) in FP64
+static double2 twiddle_host(int j, int n) {
+    const double a = -2.0 * M_PI * double(j) / double(n);
+    return make_double2(std::cos(a), std::sin(a));
+}
+
+// The preconditioner's per-lattice tables (layout pc_blob_layout).
+static std::vector<double> pc_table_blob(const FftPlan& pl, const FftPlan& pt) {
+    const int L = pl.n, Lt = pt.n;
+    const PcBlob b = pc_blob_layout(L, Lt);
+    std::vector<double> v(static_cast<size_t>(b.size));
+    for (int j = 0; j < L; ++j) {
+        const double2 w = twiddle_host(j, L);
+        v[size_t(b.twl + 2 * j)] = w.x;
+        v[size_t(b.twl + 2 * j + 1)] = w.y;
+        v[size_t(b.cosx + j)] = std::cos(2.0 * M_PI * double(fft_freq(pl, j)) / double(L));
+    }
+    for (int j = 0; j < Lt; ++j) {
+        const double2 w = twiddle_host(j, Lt);
+        v[size_t(b.twT + 2 * j)] = w.x;
+        v[size_t(b.twT + 2 * j + 1)] = w.y;
+        const double a = -M_PI * double(j) / double(Lt);
+        v[size_t(b.twt + 2 * j)] = std::cos(a);
+        v[size_t(b.twt + 2 * j + 1)] = std::sin(a);
+        const double sh = std::sin(M_PI * double(2 * fft_freq(pt, j) + 1) / double(2 * Lt));
+        v[size_t(b.s2 + j)] = sh * sh;
+    }
+    return v;
+}
+
+static Coef<double> coef64_of(double dt, const hmc_params& p) {
+    Coef<double> cf;
+    for (int a = 0; a < 2; ++a) {
+        cf.diag[a] = -1.0 - dt * p.mu[a];
+        for (int d = 0; d < 2; ++d) cf.hop[a][d] = -dt * p.t[a][d];
+    }
+    cf.cpl = dt * p.lambda;
+    return cf;
+}
+
 static void set_coefs(hmc_ctx* c) {
     const double dt = c->dtau;
     const hmc_params& p = c->p;
-    for (int a = 0; a < 2; ++a) {
-        c->cf64.diag[a] = -1.0 - dt * p.mu[a];
-        for (int d = 0; d < 2; ++d) c->cf64.hop[a][d] = -dt * p.t[a][d];
-    }
-    c->cf64.cpl = dt * p.lambda;
+    c->cf64 = coef64_of(dt, p);
     for (int a = 0; a < 2; ++a) {
         c->cf32.diag[a] = float(c->cf64.diag[a]);
         for (int d = 0; d < 2; ++d) c->cf32.hop[a][d] = float(c->cf64.hop[a][d]);
@@ -999,6 +1036,71 @@ int hmc_test_site(int L, int Lt, int s, int out[12]) {
 int hmc_test_xcd_remap(int bid, int nb) {
     if (nb <= 0 || bid < 0 || bid >= nb) return -1;
     return xcd_remap(bid, nb);
+}
+
+int hmc_test_fft(int n, int inverse, const double* in, double* out) {
+    FftPlan pl;
+    if (in == nullptr || out == nullptr || !make_fft_plan(n, pl)) return -1;
+    std::vector<double2> buf(static_cast<size_t>(n)), tw(static_cast<size_t>(n));
+    for (int i = 0; i < n; ++i) {
+        buf[size_t(i)] = make_double2(in[2 * i], in[2 * i + 1]);
+        tw[size_t(i)] = twiddle_host(i, n);
+    }
+    if (inverse) fft_lines<double, true>(ExHost(), buf.data(), 1, n, 1, pl, tw.data());
+    else fft_lines<double, false>(ExHost(), buf.data(), 1, n, 1, pl, tw.data());
+    for (int i = 0; i < n; ++i) {
+        out[2 * i] = buf[size_t(i)].x;
+        out[2 * i + 1] = buf[size_t(i)].y;
+    }
+    return 0;
+}
+
+int hmc_test_fft_freq(int n, int pos) {
+    FftPlan pl;
+    if (!make_fft_plan(n, pl) || pos < 0 || pos >= n) return -1;
+    return fft_freq(pl, pos);
+}
+
+int hmc_test_precond(int L, int Lt, double dtau, const hmc_params* params, const double* in, double* out,
+                     double* rz) {
+    FftPlan pl, pt;
+    if (params == nullptr || in == nullptr || out == nullptr || !geometry_ok(L, Lt) ||
+        !make_fft_plan(L, pl) || !make_fft_plan(Lt, pt))
+        return -1;
+    const Coef<double> cf = coef64_of(dtau, *params);
+    const int LL = L * L, vol = Lt * LL;
+    std::vector<double2> w(size_t(4) * vol);
+    for (size_t i = 0; i < w.size(); ++i) w[i] = make_double2(in[2 * i], in[2 * i + 1]);
+    std::vector<double> blob = pc_table_blob(pl, pt);
+    const PcBlob bl = pc_blob_layout(L, Lt);
+    double* B = blob.data();
+    const PcTables<double> t{reinterpret_cast<double2*>(B + bl.twt), B + bl.s2, B + bl.cosx,
+                             reinterpret_cast<double2*>(B + bl.twl), reinterpret_cast<double2*>(B + bl.twT)};
+    const double2* twl = t.twl;
+    const ExHost ex;
+    for (int sl = 0; sl < 4 * Lt; ++sl) fft_slice<double, false>(ex, w.data() + size_t(sl) * LL, pl, twl);
+    const int ncol_max = 16;          // columns per tau-pass group (any positive count works)
+    std::vector<double2> buf(size_t(Lt) * ncol_max);
+    double acc = 0.0;
+    for (int c = 0; c < 4; ++c) {
+        for (int col0 = 0; col0 < LL; col0 += ncol_max) {
+            const int ncol = std::min(ncol_max, LL - col0);
+            for (int tau = 0; tau < Lt; ++tau)
+                for (int j = 0; j < ncol; ++j)
+                    buf[size_t(tau) * ncol + j] = w[size_t(c) * vol + size_t(tau) * LL + col0 + j];
+            acc += pc_tau_pass<double>(ex, buf.data(), ncol, col0, c >> 1, t, pt, pl, cf);
+            for (int tau = 0; tau < Lt; ++tau)
+                for (int j = 0; j < ncol; ++j)
+                    w[size_t(c) * vol + size_t(tau) * LL + col0 + j] = buf[size_t(tau) * ncol + j];
+        }
+    }
+    for (int sl = 0; sl < 4 * Lt; ++sl) fft_slice<double, true>(ex, w.data() + size_t(sl) * LL, pl, twl);
+    for (size_t i = 0; i < w.size(); ++i) {
+        out[2 * i] = w[i].x;
+        out[2 * i + 1] = w[i].y;
+    }
+    if (rz) *rz = acc;
+    return 0;
 }
 
 int hmc_test_tile_span(int blk, int bpr, int nt, int out[3]) {

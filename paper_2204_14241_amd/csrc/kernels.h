@@ -25,27 +25,6 @@ namespace hmc {
 
 constexpr int kBlock = 256;
 
-// ------------------------------------------------------------------------------------
-// complex helpers (interleaved re, im)
-template <typename R> struct CT;
-template <> struct CT<double> { using T = double2; };
-template <> struct CT<float> { using T = float2; };
-template <typename R> using C2 = typename CT<R>::T;
-
-template <typename R>
-__device__ __forceinline__ C2<R> mk(R re, R im) { C2<R> z; z.x = re; z.y = im; return z; }
-template <typename R>
-__device__ __forceinline__ C2<R> add(C2<R> a, C2<R> b) { return mk<R>(a.x + b.x, a.y + b.y); }
-template <typename R>
-__device__ __forceinline__ C2<R> sub(C2<R> a, C2<R> b) { return mk<R>(a.x - b.x, a.y - b.y); }
-template <typename R>
-__device__ __forceinline__ C2<R> scl(R s, C2<R> a) { return mk<R>(s * a.x, s * a.y); }
-// a + s*b
-template <typename R>
-__device__ __forceinline__ C2<R> axpy(R s, C2<R> b, C2<R> a) { return mk<R>(a.x + s * b.x, a.y + s * b.y); }
-template <typename R>
-__device__ __forceinline__ R norm2(C2<R> a) { return a.x * a.x + a.y * a.y; }
-
 __device__ __forceinline__ bool finite(double x) { return x - x == 0.0; }
 
 // ------------------------------------------------------------------------------------

@@ -85,6 +85,32 @@ __host__ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
     return base + local;
 }
 
+// ------------------------------------------------------------------------------------
+// complex helpers (interleaved re, im), usable on the host and the device
+template <typename R> struct CT;
+template <> struct CT<double> { using T = double2; };
+template <> struct CT<float> { using T = float2; };
+template <typename R> using C2 = typename CT<R>::T;
+
+template <typename R>
+__host__ __device__ __forceinline__ C2<R> mk(R re, R im) { C2<R> z; z.x = re; z.y = im; return z; }
+template <typename R>
+__host__ __device__ __forceinline__ C2<R> add(C2<R> a, C2<R> b) { return mk<R>(a.x + b.x, a.y + b.y); }
+template <typename R>
+__host__ __device__ __forceinline__ C2<R> sub(C2<R> a, C2<R> b) { return mk<R>(a.x - b.x, a.y - b.y); }
+template <typename R>
+__host__ __device__ __forceinline__ C2<R> scl(R s, C2<R> a) { return mk<R>(s * a.x, s * a.y); }
+// a + s*b
+template <typename R>
+__host__ __device__ __forceinline__ C2<R> axpy(R s, C2<R> b, C2<R> a) { return mk<R>(a.x + s * b.x, a.y + s * b.y); }
+template <typename R>
+__host__ __device__ __forceinline__ R norm2(C2<R> a) { return a.x * a.x + a.y * a.y; }
+// a * b and a * conj(b)
+template <typename R>
+__host__ __device__ __forceinline__ C2<R> cmul(C2<R> a, C2<R> b) { return mk<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+template <typename R>
+__host__ __device__ __forceinline__ C2<R> cmulc(C2<R> a, C2<R> b) { return mk<R>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
+
 // Coefficients of M in the arithmetic precision R (Eq. 17).
 template <typename R>
 struct Coef {

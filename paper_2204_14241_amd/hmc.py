@@ -445,3 +445,38 @@ def test_tile_span(blk, bpr, nt):
     out = (ctypes.c_int * 3)()
     rc = _lib.load().hmc_test_tile_span(blk, bpr, nt, out)
     return None if rc else tuple(out)
+
+
+def test_fft(x, inverse=False):
+    """The kernels' in-place FFT run on the host in FP64 (no GPU needed).  x: complex128 1-D.
+    Forward output is in the FFT's own order (see test_fft_freq)."""
+    import numpy as np
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    out = np.empty_like(x)
+    P = ctypes.POINTER(ctypes.c_double)
+    rc = _lib.load().hmc_test_fft(x.size, 1 if inverse else 0, x.ctypes.data_as(P), out.ctypes.data_as(P))
+    return None if rc else out
+
+
+def test_fft_freq(n, pos):
+    return _lib.load().hmc_test_fft_freq(n, pos)
+
+
+def test_precond(L, Lt, v, dtau=0.1, model=None):
+    """The kernels' three-pass Fourier preconditioner run on the host in FP64 on one spinor
+    (complex128, 4 * L_tau * L * L values).  Returns (P v, <v, P v>)."""
+    import numpy as np
+    m = dict(DEFAULT_MODEL, **(model or {}))
+    p = HmcParams()
+    for a in range(2):
+        for d in range(2):
+            p.t[a][d] = float(m["t"][a][d])
+        p.mu[a] = float(m["mu"][a])
+    p.lambda_, p.r, p.c, p.u = float(m["lam"]), float(m["r"]), float(m["c"]), float(m["u"])
+    v = np.ascontiguousarray(v, dtype=np.complex128)
+    out = np.empty_like(v)
+    rz = ctypes.c_double(0.0)
+    P = ctypes.POINTER(ctypes.c_double)
+    rc = _lib.load().hmc_test_precond(L, Lt, float(dtau), ctypes.byref(p), v.ctypes.data_as(P),
+                                     out.ctypes.data_as(P), ctypes.byref(rz))
+    return None if rc else (out, rz.value)
