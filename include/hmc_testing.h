@@ -39,7 +39,7 @@ int hmc_test_tile_span(int blk, int bpr, int nt, int out[3]);
  * line of n complex numbers (interleaved re, im).  Forward (inverse = 0): the unnormalised
  * transform sum_m x_m exp(-2 pi i m k / n), frequency k left at the position p with
  * hmc_test_fft_freq(n, p) = k.  Inverse: the conjugate transpose of the forward map, so that
- * inverse(forward(x)) = n x.  Returns 0, or -1 if n has a prime factor above 13. */
+ * inverse(forward(x)) = n x.  Returns 0, or -1 if n has a prime factor above 7. */
 int hmc_test_fft(int n, int inverse, const double* in, double* out);
 int hmc_test_fft_freq(int n, int pos);
 

@@ -19,6 +19,8 @@ HMC_MIXED = 1
 HMC_MAX_RHS = 16
 HMC_FORCE_PF = 1
 HMC_FORCE_BOSON = 2
+HMC_PRECOND_NONE = 0
+HMC_PRECOND_FOURIER = 1
 
 EXPORTED = [
     "hmc_create", "hmc_destroy", "hmc_set_params", "hmc_workspace_bytes", "hmc_set_workspace",
@@ -52,6 +54,7 @@ class HmcParams(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("reliable_every", ctypes.c_int),
         ("max_rhs", ctypes.c_int),
+        ("precond", ctypes.c_int),
     ]
 
 

@@ -18,7 +18,7 @@
 // the inverse applies the conjugate transposes of the same stages in reverse order, which
 // takes that order back to natural order.  No permutation pass is ever needed: the symbol is
 // applied at permuted positions, and every position knows its frequency.  Radices 4, 2, 3,
-// 5, 7, 11, 13; lengths with a larger prime factor are rejected.  The functions are
+// 5, 7; lengths with a larger prime factor are rejected.  The functions are
 // __host__ __device__: the host build serves the CPU tests of this code.
 #pragma once
 
@@ -28,13 +28,16 @@
 
 namespace hmc {
 
-constexpr int kFftMaxStages = 24;
-constexpr int kFftMaxRadix = 13;
+constexpr int kFftMaxStages = 12;   // 4^12 > any lattice extent accepted
+constexpr int kFftMaxRadix = 7;
 
 struct FftPlan {
     int n;                      // transform length
     int nst;                    // number of radix stages
     int radix[kFftMaxStages];   // radix of stage 0 (outermost) ... nst - 1
+    int ni[kFftMaxStages];      // sub-length a stage works on (n for stage 0)
+    FastDiv dM[kFftMaxStages];  // division by ni / radix (butterfly -> block, offset)
+    FastDiv dnb[kFftMaxStages]; // division by n / radix (work item -> line, butterfly)
 };
 
 __host__ __device__ inline bool make_fft_plan(int n, FftPlan& p) {
@@ -47,13 +50,22 @@ __host__ __device__ inline bool make_fft_plan(int n, FftPlan& p) {
         p.radix[p.nst++] = 4;
         m /= 4;
     }
-    const int primes[6] = {2, 3, 5, 7, 11, 13};
-    for (int f : primes) {
+    const int primes[4] = {2, 3, 5, 7};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int f = primes[i];
         while (m % f == 0) {
             if (p.nst == kFftMaxStages) return false;
             p.radix[p.nst++] = f;
             m /= f;
         }
+    }
+    int len = n;
+    for (int st = 0; st < p.nst; ++st) {
+        p.ni[st] = len;
+        p.dM[st].init(uint32_t(len / p.radix[st]));
+        p.dnb[st].init(uint32_t(n / p.radix[st]));
+        len /= p.radix[st];
     }
     return m == 1;
 }
@@ -72,17 +84,16 @@ __host__ __device__ inline int fft_freq(const FftPlan& pl, int pos) {
     return k;
 }
 
-// Small DFT of radix r in place on v: v_k <- sum_m v_m W^{(+-) m k}, W = exp(-2 pi i / r)
-// read from the length-n table (W_r^e = tw[e * n / r]).
-template <typename R, bool INV>
-__host__ __device__ inline void small_dft(C2<R> (&v)[kFftMaxRadix], int r, const C2<R>* tw, int n) {
-    if (r == 2) {
+// Small DFT of radix 2, 3, 4 or 5 in place on v: v_k <- sum_m v_m W^{(+-) m k},
+// W = exp(-2 pi i / RAD).  Radix 2 and 4 exactly; radix 3 and 5 in their symmetric forms with
+// the powers of W read from the length-n table (W_RAD^e = tw[e * n / RAD]).
+template <typename R, bool INV, int RAD>
+__host__ __device__ __forceinline__ void small_dft(C2<R> (&v)[RAD], const C2<R>* tw, int n) {
+    if constexpr (RAD == 2) {
         const C2<R> a = v[0], b = v[1];
         v[0] = add<R>(a, b);
         v[1] = sub<R>(a, b);
-        return;
-    }
-    if (r == 4) {
+    } else if constexpr (RAD == 4) {
         const C2<R> a = v[0], b = v[1], c = v[2], d = v[3];
         const C2<R> s0 = add<R>(a, c), d0 = sub<R>(a, c), s1 = add<R>(b, d), d1 = sub<R>(b, d);
         // forward: -i * d1; inverse: +i * d1
@@ -91,50 +102,125 @@ __host__ __device__ inline void small_dft(C2<R> (&v)[kFftMaxRadix], int r, const
         v[1] = add<R>(d0, jd1);
         v[2] = sub<R>(s0, s1);
         v[3] = sub<R>(d0, jd1);
-        return;
+    } else if constexpr (RAD == 3) {
+        // W = c - i s with c = -1/2, s = sin(2 pi / 3), both taken from the table
+        const C2<R> w = tw[n / 3];
+        const R hs = INV ? -w.y : w.y;                    // -s forward, +s inverse
+        const C2<R> a = v[0], b = v[1], c = v[2];
+        const C2<R> t1 = add<R>(b, c);
+        const C2<R> t2 = axpy<R>(w.x, t1, a);             // a + c t1 (c = -1/2)
+        const C2<R> d = sub<R>(b, c);
+        const C2<R> t3 = mk<R>(-hs * d.y, hs * d.x);       // i * hs * (b - c)
+        v[0] = add<R>(a, t1);
+        v[1] = add<R>(t2, t3);
+        v[2] = sub<R>(t2, t3);
+    } else if constexpr (RAD == 5) {
+        // W = c1 - i s1, W^2 = c2 - i s2 from the table; the symmetric 5-point form
+        const C2<R> w1 = tw[n / 5], w2 = tw[2 * (n / 5)];
+        const R c1 = w1.x, s1 = -w1.y, c2 = w2.x, s2 = -w2.y;
+        const C2<R> t1 = add<R>(v[1], v[4]), t2 = add<R>(v[2], v[3]);
+        const C2<R> t3 = sub<R>(v[1], v[4]), t4 = sub<R>(v[2], v[3]);
+        const C2<R> a1 = axpy<R>(c2, t2, axpy<R>(c1, t1, v[0]));
+        const C2<R> a2 = axpy<R>(c1, t2, axpy<R>(c2, t1, v[0]));
+        const C2<R> b1 = axpy<R>(s2, t4, scl<R>(s1, t3));
+        const C2<R> b2 = axpy<R>(-s1, t4, scl<R>(s2, t3));
+        // forward: X1 = a1 - i b1, X4 = a1 + i b1, X2 = a2 - i b2, X3 = a2 + i b2; inverse: i -> -i
+        const R sg = INV ? R(-1) : R(1);
+        const C2<R> ib1 = mk<R>(-sg * b1.y, sg * b1.x), ib2 = mk<R>(-sg * b2.y, sg * b2.x);
+        v[0] = add<R>(v[0], add<R>(t1, t2));
+        v[1] = sub<R>(a1, ib1);
+        v[4] = add<R>(a1, ib1);
+        v[2] = sub<R>(a2, ib2);
+        v[3] = add<R>(a2, ib2);
     }
-    C2<R> o[kFftMaxRadix];
-    const int step = n / r;
-    for (int k = 0; k < r; ++k) {
-        C2<R> acc = v[0];
-        for (int m = 1; m < r; ++m) {
-            const C2<R> w = tw[((m * k) % r) * step];
-            acc = add<R>(acc, INV ? cmulc<R>(v[m], w) : cmul<R>(v[m], w));
-        }
-        o[k] = acc;
-    }
-    for (int k = 0; k < r; ++k) v[k] = o[k];
 }
 
-// One butterfly j of stage st (sub-length ni) on the line at `line`, element stride es.
-// Forward (DIF): v_q = x[base + M q]; small DFT; times W_N^{(N/ni) n1 k}; store in place.
-// Inverse: the conjugate transpose of that map.
-template <typename R, bool INV>
-__host__ __device__ inline void fft_butterfly(C2<R>* line, int es, const FftPlan& pl, int st, int ni,
-                                              int j, const C2<R>* tw) {
-    const int r = pl.radix[st];
-    const int M = ni / r;
-    const int b = j / M, n1 = j - b * M;
+// One butterfly j of a radix-RAD stage with sub-length ni, on the line at `line` (element
+// stride es), transform length n.  Forward (DIF): v_q = x[base + M q]; small DFT; times
+// W_n^{(n/ni) n1 k}; store in place.  Inverse: the conjugate transpose of that map.  The
+// twiddle exponent (n/ni) n1 k stays below n because n1 < ni/RAD and k < RAD.
+template <typename R, bool INV, int RAD>
+__host__ __device__ __forceinline__ void butterfly(C2<R>* line, int es, int n, int ni, const FastDiv& dM, int j,
+                                                   const C2<R>* tw) {
+    const int M = int(dM.d);
+    const int b = int(dM.div(uint32_t(j))), n1 = j - b * M;
     const int base = b * ni + n1;
-    const int s = pl.n / ni;
-    C2<R> v[kFftMaxRadix];
-    for (int q = 0; q < r; ++q) v[q] = line[(base + M * q) * es];
-    if (!INV) {
-        small_dft<R, false>(v, r, tw, pl.n);
-        for (int k = 1; k < r; ++k) v[k] = cmul<R>(v[k], tw[(s * n1 * k) % pl.n]);
+    const int e1 = (n / ni) * n1;
+    C2<R> v[RAD];
+#pragma unroll
+    for (int q = 0; q < RAD; ++q) v[q] = line[(base + M * q) * es];
+    if constexpr (RAD <= 5) {
+        if constexpr (!INV) {
+            small_dft<R, false, RAD>(v, tw, n);
+#pragma unroll
+            for (int k = 1; k < RAD; ++k) v[k] = cmul<R>(v[k], tw[e1 * k]);
+        } else {
+#pragma unroll
+            for (int k = 1; k < RAD; ++k) v[k] = cmulc<R>(v[k], tw[e1 * k]);
+            small_dft<R, true, RAD>(v, tw, n);
+        }
+#pragma unroll
+        for (int q = 0; q < RAD; ++q) line[(base + M * q) * es] = v[q];
     } else {
-        for (int k = 1; k < r; ++k) v[k] = cmulc<R>(v[k], tw[(s * n1 * k) % pl.n]);
-        small_dft<R, true>(v, r, tw, pl.n);
+        // radix 7: each output is summed from the inputs held in registers and stored at once
+        // (no output array), the powers of W read from the table as they are needed
+        const int step = n / RAD;
+        if constexpr (INV) {
+#pragma unroll
+            for (int k = 1; k < RAD; ++k) v[k] = cmulc<R>(v[k], tw[e1 * k]);
+        }
+#pragma unroll
+        for (int k = 0; k < RAD; ++k) {
+            C2<R> acc = v[0];
+#pragma unroll
+            for (int m = 1; m < RAD; ++m) {
+                const C2<R> w = tw[((m * k) % RAD) * step];
+                acc = add<R>(acc, INV ? cmulc<R>(v[m], w) : cmul<R>(v[m], w));
+            }
+            if constexpr (!INV) {
+                if (k > 0) acc = cmul<R>(acc, tw[e1 * k]);
+            }
+            line[(base + M * k) * es] = acc;
+        }
     }
-    for (int q = 0; q < r; ++q) line[(base + M * q) * es] = v[q];
+}
+
+// One radix-RAD stage on cnt lines: every butterfly of every line, spread over the executor.
+// Consecutive work items take consecutive lines when lines are closer together than the
+// elements of a line, consecutive butterflies otherwise (LDS bank spread).  Divisions by the
+// stage's counts use the plan's precomputed reciprocals.
+template <typename R, bool INV, int RAD, class Ex>
+__host__ __device__ __forceinline__ void fft_stage(const Ex& ex, C2<R>* buf, int es, int ls, int cnt,
+                                                   const FastDiv& dcnt, int n, int ni, const FastDiv& dM,
+                                                   const FastDiv& dnb, const C2<R>* tw) {
+    const int nb = n / RAD;
+    const bool lines_fast = ls < es;
+    ex.for_each(cnt * nb, [&](int j) {
+        int l, jj;
+        if (lines_fast) {
+            jj = int(dcnt.div(uint32_t(j)));
+            l = j - jj * cnt;
+        } else {
+            l = int(dnb.div(uint32_t(j)));
+            jj = j - l * nb;
+        }
+        butterfly<R, INV, RAD>(buf + l * ls, es, n, ni, dM, jj, tw);
+    });
 }
 
 // Execution policies: the device one spreads work over the workgroup and synchronises it; the
-// host one runs sequentially (CPU tests).
+// host one runs sequentially (CPU tests).  sum_each adds up what f returns, per thread.
 struct ExDevice {
     template <class F>
     __device__ __forceinline__ void for_each(int n, F f) const {
+#pragma unroll 1
         for (int i = threadIdx.x; i < n; i += blockDim.x) f(i);
+    }
+    template <class F>
+    __device__ __forceinline__ double sum_each(int n, F f) const {
+        double a = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) a += f(i);
+        return a;
     }
     __device__ __forceinline__ void sync() const { __syncthreads(); }
 };
@@ -143,43 +229,62 @@ struct ExHost {
     void for_each(int n, F f) const {
         for (int i = 0; i < n; ++i) f(i);
     }
+    template <class F>
+    double sum_each(int n, F f) const {
+        double a = 0.0;
+        for (int i = 0; i < n; ++i) a += f(i);
+        return a;
+    }
     void sync() const {}
 };
 
-// All stages on cnt lines (line l starts at buf + l * ls, element stride es).
-template <typename R, bool INV, class Ex>
-__host__ __device__ inline void fft_lines(const Ex& ex, C2<R>* buf, int es, int ls, int cnt,
+// All stages on cnt lines (line l starts at buf + l * ls, element stride es).  The plan may
+// live in LDS: it is only read, stage by stage.  MAXR is the largest radix compiled in (5 or
+// 7): a kernel's register allocation covers every stage it can reach, and the radix-7 stage
+// needs many more than the others, so kernels for lattices without a factor 7 leave it out.
+template <typename R, bool INV, int MAXR = 7, class Ex>
+__host__ __device__ __forceinline__ void fft_lines(const Ex& ex, C2<R>* buf, int es, int ls, int cnt,
                                           const FftPlan& pl, const C2<R>* tw) {
-    int ni[kFftMaxStages];
-    int len = pl.n;
-    for (int st = 0; st < pl.nst; ++st) {
-        ni[st] = len;
-        len /= pl.radix[st];
-    }
-    for (int q = 0; q < pl.nst; ++q) {
-        const int st = INV ? pl.nst - 1 - q : q;
-        const int nb = pl.n / pl.radix[st];
-        const int nist = ni[st];
-        ex.for_each(cnt * nb, [=](int j) {
-            const int l = j / nb;
-            fft_butterfly<R, INV>(buf + l * ls, es, pl, st, nist, j - l * nb, tw);
-        });
+    const int n = pl.n, nst = pl.nst;
+    FastDiv dcnt;
+    dcnt.init(uint32_t(cnt));
+    for (int q = 0; q < nst; ++q) {
+        const int st = INV ? nst - 1 - q : q;
+        const int ni = pl.ni[st];
+        const FastDiv& dM = pl.dM[st];
+        const FastDiv& dnb = pl.dnb[st];
+        switch (pl.radix[st]) {
+            case 4: fft_stage<R, INV, 4>(ex, buf, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
+            case 2: fft_stage<R, INV, 2>(ex, buf, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
+            case 3: fft_stage<R, INV, 3>(ex, buf, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
+            case 5: fft_stage<R, INV, 5>(ex, buf, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
+            default:
+                if constexpr (MAXR >= 7) fft_stage<R, INV, 7>(ex, buf, es, ls, cnt, dcnt, n, ni, dM, dnb, tw);
+                break;
+        }
         ex.sync();
     }
 }
 
 // 2-D transform of one L x L slice (row-major x, y) in place: forward along y then x; inverse
 // along x then y.
-template <typename R, bool INV, class Ex>
-__host__ __device__ inline void fft_slice(const Ex& ex, C2<R>* buf, const FftPlan& pl, const C2<R>* tw) {
+template <typename R, bool INV, int MAXR = 7, class Ex>
+__host__ __device__ __forceinline__ void fft_slice(const Ex& ex, C2<R>* buf, const FftPlan& pl, const C2<R>* tw) {
     const int L = pl.n;
     if (!INV) {
-        fft_lines<R, false>(ex, buf, 1, L, L, pl, tw);
-        fft_lines<R, false>(ex, buf, L, 1, L, pl, tw);
+        fft_lines<R, false, MAXR>(ex, buf, 1, L, L, pl, tw);
+        fft_lines<R, false, MAXR>(ex, buf, L, 1, L, pl, tw);
     } else {
-        fft_lines<R, true>(ex, buf, L, 1, L, pl, tw);
-        fft_lines<R, true>(ex, buf, 1, L, L, pl, tw);
+        fft_lines<R, true, MAXR>(ex, buf, L, 1, L, pl, tw);
+        fft_lines<R, true, MAXR>(ex, buf, 1, L, L, pl, tw);
     }
+}
+
+// Largest radix a plan uses.
+__host__ __device__ inline int fft_max_radix(const FftPlan& pl) {
+    int m = 1;
+    for (int i = 0; i < pl.nst; ++i) m = pl.radix[i] > m ? pl.radix[i] : m;
+    return m;
 }
 
 // Symbol 1/|K_hat|^2 of the preconditioner for one band, from b and sin^2(w_n / 2).
@@ -201,6 +306,7 @@ struct PcTables {
     double* cosx;
     C2<R>* twl;
     C2<R>* twT;
+    double* bcol;  // scratch: b of each column of the group being processed
 };
 
 // Offsets (in doubles) of the tables in the flat blob: twl, twT, twt (complex), s2, cosx.
@@ -224,35 +330,38 @@ __host__ __device__ __forceinline__ PcBlob pc_blob_layout(int L, int Lt) {
 // inverse tau transform and untwist, scaled by 1 / (N_tau L^2).  Returns the workgroup's share
 // of <r, P r> = (1 / N) sum |Y|^2 / |K_hat|^2 (Parseval), valid in every thread's own terms
 // (the caller reduces).
-template <typename R, class Ex>
-__host__ __device__ inline double pc_tau_pass(const Ex& ex, C2<R>* buf, int ncol, int col0, int band,
+template <typename R, int MAXR = 7, class Ex>
+__host__ __device__ __forceinline__ double pc_tau_pass(const Ex& ex, C2<R>* buf, int ncol, int col0, int band,
                                               const PcTables<R>& t, const FftPlan& pt, const FftPlan& pl,
                                               const Coef<double>& cf64) {
     const int Lt = pt.n, L = pl.n;
     const double inv_n = 1.0 / (double(Lt) * double(L) * double(L));
-    ex.for_each(Lt * ncol, [=](int i) {
-        const int tau = i / ncol;
+    FastDiv dc, dL;
+    dc.init(uint32_t(ncol));
+    dL.init(uint32_t(L));
+    // b = 1 + dtau (mu + 2 t_x cos kx + 2 t_y cos ky) per column (diag = -1 - dtau mu, hop = -dtau t)
+    ex.for_each(ncol, [&](int j) {
+        const int col = col0 + j;
+        const int px = int(dL.div(uint32_t(col))), py = col - px * L;
+        t.bcol[j] = -cf64.diag[band] - 2.0 * (cf64.hop[band][0] * t.cosx[px] + cf64.hop[band][1] * t.cosx[py]);
+    });
+    ex.for_each(Lt * ncol, [&](int i) {
+        const int tau = int(dc.div(uint32_t(i)));
         buf[i] = cmul<R>(buf[i], t.twt[tau]);
     });
     ex.sync();
-    fft_lines<R, false>(ex, buf, ncol, 1, ncol, pt, t.twT);
-    double part = 0.0;
-    double* pp = &part;
-    ex.for_each(Lt * ncol, [=](int i) {
-        const int p = i / ncol, j = i - p * ncol;
-        const int col = col0 + j;
-        const int px = col / L, py = col - px * L;
-        // b = 1 + dtau (mu + 2 t_x cos kx + 2 t_y cos ky), with diag = -1 - dtau mu, hop = -dtau t
-        const double b = -cf64.diag[band] - 2.0 * (cf64.hop[band][0] * t.cosx[px] + cf64.hop[band][1] * t.cosx[py]);
-        const double w = pc_symbol(b, t.s2[p]) * inv_n;
+    fft_lines<R, false, MAXR>(ex, buf, ncol, 1, ncol, pt, t.twT);
+    const double part = ex.sum_each(Lt * ncol, [&](int i) {
+        const int p = int(dc.div(uint32_t(i))), j = i - p * ncol;
+        const double w = pc_symbol(t.bcol[j], t.s2[p]) * inv_n;
         const C2<R> y = buf[i];
-        *pp += w * double(norm2<R>(y));
         buf[i] = scl<R>(R(w), y);
+        return w * double(norm2<R>(y));
     });
     ex.sync();
-    fft_lines<R, true>(ex, buf, ncol, 1, ncol, pt, t.twT);
-    ex.for_each(Lt * ncol, [=](int i) {
-        const int tau = i / ncol;
+    fft_lines<R, true, MAXR>(ex, buf, ncol, 1, ncol, pt, t.twT);
+    ex.for_each(Lt * ncol, [&](int i) {
+        const int tau = int(dc.div(uint32_t(i)));
         buf[i] = cmulc<R>(buf[i], t.twt[tau]);
     });
     ex.sync();

@@ -86,10 +86,15 @@ struct BatchInfo {
     std::vector<long long> phi_off;   // nchains + 1 prefix offsets (elements) of the boson fields
     std::vector<long long> sp_off;    // nchains + 1 prefix offsets (complex) of the spinor blocks
     std::vector<int> cfirst;          // nchains + 1 prefix of 256-site tiles (site kernels)
+    std::vector<long long> pcoff;     // nchains + 1 prefix offsets (doubles) of preconditioner tables
+    int nslices = 0;                  // sum over units of 4 L_tau (preconditioner slice workgroups)
+    int ngroups[2] = {0, 0};          // sum over units of the tau-pass workgroups [FP64, FP32]
     // device tables in the workspace; index 0: FP64 launch shape, 1: mixed precision
     UnitDesc* units[2] = {nullptr, nullptr};
     int2* blocks[2] = {nullptr, nullptr};
     int nblocks[2] = {0, 0};
+    int2* pxy_blocks = nullptr;       // preconditioner slice passes: (unit, slice)
+    int2* pt_blocks[2] = {nullptr, nullptr};   // tau pass: (unit, column group) [FP64, FP32]
     ChainDesc* chains = nullptr;
     int2* cblocks = nullptr;
     int* cfirst_dev = nullptr;
@@ -100,7 +105,7 @@ struct BatchInfo {
 // Graph-replay cache of the two status chunks of a solve (see cg_run).
 struct CgGraphs {
     hipGraphExec_t exec[2] = {nullptr, nullptr};   // [0] first chunk, [1] later chunks
-    std::tuple<int, const void*, const void*, const void*, const void*, int, int, int, int, long>
+    std::tuple<int, const void*, const void*, const void*, const void*, int, int, int, int, long, int>
         key{};
 };
 
@@ -126,7 +131,14 @@ struct hmc_ctx {
     long long phi_sites = 0;   // sites of the boson field(s)
     int nunits = 1;            // CG state records
     int pslots = 0;            // CG partial-sum slots per kind (sum over units of the largest
-                               // workgroup count the unit can be given)
+                               // workgroup count any kernel runs on the unit)
+    int pstride = 0;           // one lattice: partial slots per unit
+    bool pc_ok[2] = {false, false};   // the Fourier preconditioner supports these lattices on
+                                      // this GPU [FP64, FP32]
+    size_t lds_xy[2] = {0, 0}; // dynamic LDS of the preconditioner passes [FP64, FP32]
+    size_t lds_t[2] = {0, 0};
+    long long blob_doubles = 0;    // preconditioner tables of all lattices
+    bool pc_r7 = false;            // some lattice extent needs radix-7 FFT stages
     int ngblk = 0;             // 256-site tiles of the site-parallel kernels
 
     bool is_batch = false;
@@ -138,11 +150,12 @@ struct hmc_ctx {
     size_t need = 0;
     // carved pointers
     CgState* st = nullptr;       // 2 * nunits records (double-buffered by launch parity)
-    double* part = nullptr;      // CG partial sums: 4 kinds * nunits * kMaxBpr
+    double* part = nullptr;      // CG partial sums: kPendKinds * pslots
     double* gpart = nullptr;     // site-kernel partial sums: 2 * ngblk
     double* slots = nullptr;
-    double2 *r64 = nullptr, *p064 = nullptr, *p164 = nullptr, *t64 = nullptr;
-    float2 *r32 = nullptr, *p032 = nullptr, *p132 = nullptr, *t32 = nullptr, *x32 = nullptr;
+    double2 *r64 = nullptr, *p064 = nullptr, *p164 = nullptr, *t64 = nullptr, *z64 = nullptr;
+    float2 *r32 = nullptr, *p032 = nullptr, *p132 = nullptr, *t32 = nullptr, *x32 = nullptr, *z32 = nullptr;
+    double* blob = nullptr;      // preconditioner tables
     double2 *chi = nullptr, *xsol = nullptr;
     double *pi = nullptr, *phi_save = nullptr;
     float* phi32 = nullptr;
@@ -253,6 +266,8 @@ static int check_params(const hmc_params* p) {
         return fail(HMC_ERR_INVALID_ARG, "reliable_every must be >= 1 in mixed precision");
     if (p->n_leap < 0) return fail(HMC_ERR_INVALID_ARG, "n_leap must be >= 0");
     if (!std::isfinite(p->eps)) return fail(HMC_ERR_INVALID_ARG, "eps not finite");
+    if (p->precond != HMC_PRECOND_NONE && p->precond != HMC_PRECOND_FOURIER)
+        return fail(HMC_ERR_INVALID_ARG, "unknown preconditioner");
     return HMC_OK;
 }
 
@@ -286,16 +301,17 @@ static size_t ws_layout(hmc_ctx* c, char* base) {
         return p;
     };
     char* st = take(sizeof(CgState) * 2 * nu);
-    char* part = take(sizeof(double) * 4 * size_t(c->pslots));
+    char* part = take(sizeof(double) * kPendKinds * size_t(c->pslots));
     char* gpart = take(sizeof(double) * 2 * size_t(c->ngblk));
     char* slots = take(sizeof(double) * kSlots);
-    char* v64 = take(4 * sp64);
-    char* v32 = take(5 * sp32);
+    char* v64 = take(5 * sp64);
+    char* v32 = take(6 * sp32);
+    char* blob = take(sizeof(double) * size_t(c->blob_doubles));
     char* tr = take(2 * sp64);
     char* bos = take(2 * 3 * PS * sizeof(double));
     char* f32 = take(3 * PS * sizeof(float));
     char *un0 = nullptr, *un1 = nullptr, *bl0 = nullptr, *bl1 = nullptr, *ch = nullptr,
-         *cb = nullptr, *cf = nullptr, *cs = nullptr;
+         *cb = nullptr, *cf = nullptr, *cs = nullptr, *pxy = nullptr, *pt0 = nullptr, *pt1 = nullptr;
     if (c->is_batch) {
         const size_t nch = size_t(c->bi.nchains);
         un0 = take(sizeof(UnitDesc) * nu);
@@ -306,6 +322,9 @@ static size_t ws_layout(hmc_ctx* c, char* base) {
         cb = take(sizeof(int2) * size_t(c->ngblk));
         cf = take(sizeof(int) * (nch + 1));
         cs = take(sizeof(double) * kChainSlots * nch);
+        pxy = take(sizeof(int2) * size_t(c->bi.nslices));
+        pt0 = take(sizeof(int2) * size_t(c->bi.ngroups[0]));
+        pt1 = take(sizeof(int2) * size_t(c->bi.ngroups[1]));
     }
     if (base) {
         c->st = reinterpret_cast<CgState*>(st);
@@ -316,6 +335,9 @@ static size_t ws_layout(hmc_ctx* c, char* base) {
         c->p064 = reinterpret_cast<double2*>(v64 + sp64);
         c->p164 = reinterpret_cast<double2*>(v64 + 2 * sp64);
         c->t64 = reinterpret_cast<double2*>(v64 + 3 * sp64);
+        c->z64 = reinterpret_cast<double2*>(v64 + 4 * sp64);
+        c->z32 = reinterpret_cast<float2*>(v32 + 5 * sp32);
+        c->blob = reinterpret_cast<double*>(blob);
         c->r32 = reinterpret_cast<float2*>(v32);
         c->p032 = reinterpret_cast<float2*>(v32 + sp32);
         c->p132 = reinterpret_cast<float2*>(v32 + 2 * sp32);
@@ -335,6 +357,9 @@ static size_t ws_layout(hmc_ctx* c, char* base) {
             c->bi.cblocks = reinterpret_cast<int2*>(cb);
             c->bi.cfirst_dev = reinterpret_cast<int*>(cf);
             c->bi.cslots = reinterpret_cast<double*>(cs);
+            c->bi.pxy_blocks = reinterpret_cast<int2*>(pxy);
+            c->bi.pt_blocks[0] = reinterpret_cast<int2*>(pt0);
+            c->bi.pt_blocks[1] = reinterpret_cast<int2*>(pt1);
         }
     }
     return off;
@@ -343,6 +368,12 @@ static size_t ws_layout(hmc_ctx* c, char* base) {
 // CG launch shape: at most max_bpr workgroups per right-hand side (unit); workgroup b of a
 // unit takes tiles b, b + bpr, ... (so every consumer reduces at most kMaxBpr partials).
 static int clamp_bpr(int ntiles2, int max_bpr) { return ntiles2 < max_bpr ? ntiles2 : max_bpr; }
+
+// Partial slots a unit needs per kind: the most workgroups any kernel runs on it (the CG steps,
+// at most kMaxBpr; the preconditioner's tau pass, 4 column groups per FP64 group width).
+static int unit_slots(const Lat& l) {
+    return std::max(clamp_bpr(tiles2_host(l.vol), kMaxBpr), 4 * pc_groups(l.LL, pc_ncol<double>()));
+}
 
 // Batch: (re)write the unit and block tables of one precision's launch shape.
 static int upload_batch_shape(hmc_ctx* c, int pi, int max_bpr) {
@@ -360,9 +391,9 @@ static int upload_batch_shape(hmc_ctx* c, int pi, int max_bpr) {
             d.phioff = b.phi_off[size_t(ch)];
             d.bpr = clamp_bpr(tiles2_host(lat.vol), max_bpr);
             d.part = part;
-            part += clamp_bpr(tiles2_host(lat.vol), kMaxBpr);
+            part += unit_slots(lat);
             d.chain = ch;
-            d.pad = 0;
+            d.pcoff = int(b.pcoff[size_t(ch)]);
             for (int w = 0; w < d.bpr; ++w) blocks.push_back(make_int2(u, w));
         }
     }
@@ -406,22 +437,73 @@ static std::map<TuneKey, std::pair<int, int>> g_tuned;   // -> (bpr64, bpr32)
 // --------------------------------------------------------------------------------------
 // geometry of a launch
 
-static GeoOne geo_one(const hmc_ctx* c, int bpr) { return GeoOne{c->lat, bpr}; }
+static GeoOne geo_one(const hmc_ctx* c, int bpr) { return GeoOne{c->lat, bpr, bpr, c->pstride}; }
 static GeoBatch geo_batch(const hmc_ctx* c, int pi) { return GeoBatch{c->bi.units[pi], c->bi.blocks[pi]}; }
 static CGeoOne cgeo_one(const hmc_ctx* c, int npf) { return CGeoOne{c->lat, c->bc, npf}; }
 static CGeoBatch cgeo_batch(const hmc_ctx* c) { return CGeoBatch{c->bi.chains, c->bi.cblocks}; }
+
+// Everything a solve launches: the CG steps and, with the preconditioner, its slice passes and
+// its tau pass, each with its geometry and grid.
+template <class Geo>
+struct Launch {
+    Geo cg, pxy, pt;
+    int ncg = 0, npxy = 0, npt = 0;
+    size_t lds_xy = 0, lds_t = 0;
+    bool pc = false;
+    bool r7 = false;      // some lattice extent has a factor 7 (radix-7 FFT stages)
+};
+
+template <typename R>
+static Launch<GeoOne> launch_one(const hmc_ctx* c, int n) {
+    const int pi = sizeof(R) == sizeof(float) ? 1 : 0;
+    const int bpr = pi ? c->bpr32 : c->bpr64;
+    Launch<GeoOne> l;
+    l.cg = geo_one(c, bpr);
+    l.ncg = bpr * n;
+    l.pc = c->p.precond == HMC_PRECOND_FOURIER && c->pc_ok[pi];
+    const int nxy = 4 * c->Lt, nt = 4 * pc_groups(c->lat.LL, pc_ncol<R>());
+    l.pxy = GeoOne{c->lat, bpr, nxy, c->pstride};
+    l.pt = GeoOne{c->lat, bpr, nt, c->pstride};
+    l.npxy = nxy * n;
+    l.npt = nt * n;
+    l.lds_xy = c->lds_xy[pi];
+    l.lds_t = c->lds_t[pi];
+    l.r7 = c->pc_r7;
+    return l;
+}
+
+template <typename R>
+static Launch<GeoBatch> launch_batch(const hmc_ctx* c) {
+    const int pi = sizeof(R) == sizeof(float) ? 1 : 0;
+    Launch<GeoBatch> l;
+    l.cg = geo_batch(c, pi);
+    l.ncg = c->bi.nblocks[pi];
+    l.pc = c->p.precond == HMC_PRECOND_FOURIER && c->pc_ok[pi];
+    l.pxy = GeoBatch{c->bi.units[pi], c->bi.pxy_blocks};
+    l.pt = GeoBatch{c->bi.units[pi], c->bi.pt_blocks[pi]};
+    l.npxy = c->bi.nslices;
+    l.npt = c->bi.ngroups[pi];
+    l.lds_xy = c->lds_xy[pi];
+    l.lds_t = c->lds_t[pi];
+    l.r7 = c->pc_r7;
+    return l;
+}
 
 // --------------------------------------------------------------------------------------
 // conjugate-gradient engine
 
 template <typename R> struct KrylovBufs;
 template <> struct KrylovBufs<double> {
-    static CgVecs<double> get(hmc_ctx* c, double2* x) { return {c->r64, c->p064, c->p164, c->t64, x}; }
+    static CgVecs<double> get(hmc_ctx* c, double2* x, bool pc) {
+        return {c->r64, c->p064, c->p164, c->t64, x, pc ? c->z64 : c->r64};
+    }
     static const double* phi(hmc_ctx*, const double* phi64) { return phi64; }
     static Coef<double> cf(hmc_ctx* c) { return c->cf64; }
 };
 template <> struct KrylovBufs<float> {
-    static CgVecs<float> get(hmc_ctx* c, double2*) { return {c->r32, c->p032, c->p132, c->t32, c->x32}; }
+    static CgVecs<float> get(hmc_ctx* c, double2*, bool pc) {
+        return {c->r32, c->p032, c->p132, c->t32, c->x32, pc ? c->z32 : c->r32};
+    }
     static const float* phi(hmc_ctx* c, const double*) { return c->phi32; }
     static Coef<float> cf(hmc_ctx* c) { return c->cf32; }
 };
@@ -442,19 +524,50 @@ static CgCtl next_ctl(hmc_ctx* c, int expect) {
 
 static const CgState* current_states(const hmc_ctx* c) { return c->st + size_t(c->seq & 1) * c->nunits; }
 
-// One status chunk: `chunk` iterations (steps A and B), then the reliable-update /
-// true-residual sequence for units in `filter`, then the reduction of what is pending so the
-// published records are complete.  An even number of launches, so every chunk starts at
-// the same record parity.  first: the first chunk of a solve (step A then reduces |b|^2).
+// The three preconditioner passes, z = P r, for the units whose residual just changed; the
+// first consumes the pending kind `expect1` (a new |r|^2, the first |b|^2 or a true residual).
+template <typename R, class Geo, int MAXR>
+static int enqueue_pc_r(hmc_ctx* c, const Launch<Geo>& lc, const CgVecs<R>& v, int expect1, hipStream_t s) {
+    hipLaunchKernelGGL((k_pc_xy<R, false, Geo, MAXR>), dim3(lc.npxy), dim3(kPcBlock), lc.lds_xy, s,
+                       next_ctl(c, expect1), lc.pxy, v.r, v.z, c->blob);
+    LAUNCHCHK();
+    hipLaunchKernelGGL((k_pc_t<R, Geo, MAXR>), dim3(lc.npt), dim3(kPcBlock), lc.lds_t, s, next_ctl(c, PEND_NONE),
+                       lc.pt, v.z, c->blob, c->cf64);
+    LAUNCHCHK();
+    hipLaunchKernelGGL((k_pc_xy<R, true, Geo, MAXR>), dim3(lc.npxy), dim3(kPcBlock), lc.lds_xy, s,
+                       next_ctl(c, PEND_RZ), lc.pxy, v.z, v.z, c->blob);
+    LAUNCHCHK();
+    return HMC_OK;
+}
+
 template <typename R, class Geo>
-static int enqueue_chunk(hmc_ctx* c, Geo geo, int grid, int n, const double* phi64,
-                         const double2* b, double2* x, int chunk, int filter, bool first,
-                         bool sample, int kslot, hipStream_t s) {
-    CgVecs<R> v = KrylovBufs<R>::get(c, x);
+static int enqueue_pc(hmc_ctx* c, const Launch<Geo>& lc, const CgVecs<R>& v, int expect1, hipStream_t s) {
+    return lc.r7 ? enqueue_pc_r<R, Geo, 7>(c, lc, v, expect1, s) : enqueue_pc_r<R, Geo, 5>(c, lc, v, expect1, s);
+}
+
+// Launches of one status chunk (kept even, so that every chunk starts at the same record
+// parity): without preconditioner 2 per iteration + 4; with it 5 per iteration + 6, plus a
+// finalize if odd.
+static int chunk_launches(int chunk, bool pc) {
+    if (!pc) return 2 * chunk + 4;
+    const int n = 5 * chunk + 6;
+    return n + (n & 1);
+}
+
+// One status chunk: `chunk` iterations (steps A and B, and the preconditioner passes), then
+// the reliable-update / true-residual sequence for units in `filter`, then what makes the
+// published records complete.  first: the first chunk of an unpreconditioned solve (its
+// step A then reduces |b|^2).
+template <typename R, class Geo>
+static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double* phi64, const double2* b,
+                         double2* x, int chunk, int filter, bool first, bool sample, int kslot, hipStream_t s) {
+    CgVecs<R> v = KrylovBufs<R>::get(c, x, lc.pc);
     const R* phik = KrylovBufs<R>::phi(c, phi64);
     const Coef<R> cf = KrylovBufs<R>::cf(c);
+    const Geo geo = lc.cg;
+    const int grid = lc.ncg;
     for (int i = 0; i < chunk; ++i) {
-        const int expect_a = i > 0 ? PEND_RR : (first ? PEND_BB : PEND_NONE);
+        const int expect_a = lc.pc ? PEND_NONE : (i > 0 ? PEND_RR : (first ? PEND_BB : PEND_NONE));
         const CgCtl ka = next_ctl(c, expect_a), kb = next_ctl(c, PEND_TT);
         if (sample && i == chunk / 2) {
             // timestamps from the dispatches themselves (not captured into graphs)
@@ -469,20 +582,25 @@ static int enqueue_chunk(hmc_ctx* c, Geo geo, int grid, int n, const double* phi
                 hipExtLaunchKernelGGL(k_cg_b<R, Geo>, dim3(grid), dim3(kBlock), 0, s, e[2], e[3], 0, kb, geo, v, phik, cf);
             }
             LAUNCHCHK();
-            continue;
-        }
-        if constexpr (sizeof(R) == sizeof(float)) {
-            hipLaunchKernelGGL(k_cg_a2<Geo>, dim3(grid), dim3(kBlock), 0, s, ka, geo, v, phik, cf);
-            LAUNCHCHK();
-            hipLaunchKernelGGL(k_cg_b2<Geo>, dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
         } else {
-            hipLaunchKernelGGL((k_cg_a<R, Geo>), dim3(grid), dim3(kBlock), 0, s, ka, geo, v, phik, cf);
+            if constexpr (sizeof(R) == sizeof(float)) {
+                hipLaunchKernelGGL(k_cg_a2<Geo>, dim3(grid), dim3(kBlock), 0, s, ka, geo, v, phik, cf);
+                LAUNCHCHK();
+                hipLaunchKernelGGL(k_cg_b2<Geo>, dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
+            } else {
+                hipLaunchKernelGGL((k_cg_a<R, Geo>), dim3(grid), dim3(kBlock), 0, s, ka, geo, v, phik, cf);
+                LAUNCHCHK();
+                hipLaunchKernelGGL((k_cg_b<R, Geo>), dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
+            }
             LAUNCHCHK();
-            hipLaunchKernelGGL((k_cg_b<R, Geo>), dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
         }
-        LAUNCHCHK();
+        if (lc.pc) {
+            int rc = enqueue_pc<R, Geo>(c, lc, v, PEND_RR, s);
+            if (rc) return rc;
+        }
     }
-    hipLaunchKernelGGL((k_ru_fold<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_RR), geo, x, v, filter);
+    hipLaunchKernelGGL((k_ru_fold<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, lc.pc ? PEND_NONE : PEND_RR),
+                       geo, x, v, filter);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_ru_apply<Geo>, dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), geo, x,
                        c->t64, phi64, c->cf64, filter);
@@ -490,8 +608,17 @@ static int enqueue_chunk(hmc_ctx* c, Geo geo, int grid, int n, const double* phi
     hipLaunchKernelGGL((k_ru_resid<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), geo,
                        b, c->t64, phi64, c->cf64, v.r, filter);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_cg_finalize<Geo>, dim3(n), dim3(kBlock), 0, s, next_ctl(c, PEND_RU), geo);
-    LAUNCHCHK();
+    if (lc.pc) {
+        int rc = enqueue_pc<R, Geo>(c, lc, v, PEND_RU, s);
+        if (rc) return rc;
+        if ((5 * chunk + 6) & 1) {
+            hipLaunchKernelGGL(k_cg_finalize<Geo>, dim3(n), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), geo, 0);
+            LAUNCHCHK();
+        }
+    } else {
+        hipLaunchKernelGGL(k_cg_finalize<Geo>, dim3(n), dim3(kBlock), 0, s, next_ctl(c, PEND_RU), geo, 0);
+        LAUNCHCHK();
+    }
     return HMC_OK;
 }
 
@@ -499,12 +626,13 @@ static int enqueue_chunk(hmc_ctx* c, Geo geo, int grid, int n, const double* phi
 // the cached ones match.  Capture happens on the context's own (idle) stream; the graphs
 // are launched on the caller's stream.
 template <typename R, class Geo>
-static int prepare_graphs(hmc_ctx* c, Geo geo, int grid, int n, const double* phi64,
-                          const double2* b, double2* x, int chunk, int filter) {
+static int prepare_graphs(hmc_ctx* c, const Launch<Geo>& lc, int n, const double* phi64, const double2* b,
+                          double2* x, int chunk, int filter, int parity) {
     const int pi = sizeof(R) == sizeof(float) ? 1 : 0;
     CgGraphs& G = c->cgg[pi];
-    const auto key = std::make_tuple(grid, (const void*)phi64, (const void*)b, (const void*)x,
-                                     (const void*)c->st, n, chunk, filter, c->nunits, c->generation);
+    const auto key = std::make_tuple(lc.ncg, (const void*)phi64, (const void*)b, (const void*)x,
+                                     (const void*)c->st, n, chunk, filter, c->nunits, c->generation,
+                                     lc.pc ? 1 : 0);
     if (G.exec[0] != nullptr && G.key == key) return HMC_OK;
     for (int g = 0; g < 2; ++g) {
         if (G.exec[g]) (void)hipGraphExecDestroy(G.exec[g]);
@@ -514,10 +642,9 @@ static int prepare_graphs(hmc_ctx* c, Geo geo, int grid, int n, const double* ph
     const int saved = c->seq;
     for (int g = 0; g < 2; ++g) {
         hipGraph_t graph = nullptr;
-        c->seq = 1;                                   // every chunk starts at odd parity
+        c->seq = parity;                              // every chunk starts at this parity
         HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        const int rc = enqueue_chunk<R, Geo>(c, geo, grid, n, phi64, b, x, chunk, filter, g == 0, false, 0,
-                                             c->cap_stream);
+        const int rc = enqueue_chunk<R, Geo>(c, lc, n, phi64, b, x, chunk, filter, g == 0, false, 0, c->cap_stream);
         const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
         if (rc) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -540,13 +667,13 @@ static int prepare_graphs(hmc_ctx* c, Geo geo, int grid, int n, const double* ph
     return HMC_OK;
 }
 
-// Solve (M^dagger M) x_u = b_u for the n units of `geo` (grid workgroups).  Final records
-// are left in c->h_st[0 .. n).  Returns HMC_OK, HMC_ERR_NOT_CONVERGED or HMC_ERR_NONFINITE.
+// Solve (M^dagger M) x_u = b_u for the n units of the launch.  Final records are left in
+// c->h_st[0 .. n).  Returns HMC_OK, HMC_ERR_NOT_CONVERGED or HMC_ERR_NONFINITE.
 template <typename R, class Geo>
-static int cg_run(hmc_ctx* c, Geo geo, int grid, int n, const double* phi64, const double2* b,
+static int cg_run(hmc_ctx* c, const Launch<Geo>& lc, int n, const double* phi64, const double2* b,
                   double2* x, hipStream_t s) {
     const bool mixed = sizeof(R) == sizeof(float);
-    CgVecs<R> v = KrylovBufs<R>::get(c, x);
+    CgVecs<R> v = KrylovBufs<R>::get(c, x, lc.pc);
     if (mixed) {
         hipLaunchKernelGGL(k_to_f32, dim3(elem_grid(3LL * c->phi_sites)), dim3(kBlock), 0, s, phi64,
                            c->phi32, int(3 * c->phi_sites));
@@ -556,17 +683,23 @@ static int cg_run(hmc_ctx* c, Geo geo, int grid, int n, const double* phi64, con
     const int chunk = mixed ? c->p.reliable_every : kCheckEvery;
     const int ru_filter = mixed ? (F_ACTIVE | F_CONV_ITER | F_MAXIT) : (F_CONV_ITER | F_MAXIT);
     const bool use_graphs = c->graphs;
+    // launches before the first chunk: the start (1), and with the preconditioner z = P b (3)
+    const int parity = lc.pc ? 0 : 1;
     if (use_graphs) {
-        int rc = prepare_graphs<R, Geo>(c, geo, grid, n, phi64, b, x, chunk, ru_filter);
+        int rc = prepare_graphs<R, Geo>(c, lc, n, phi64, b, x, chunk, ru_filter, parity);
         if (rc) return rc;
     }
     c->seq = 0;
-    hipLaunchKernelGGL((k_cg_init<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), geo, b, x,
-                       v, tol * tol, mixed ? kRuDrop2 : 0.0, c->p.cg_maxit);
+    hipLaunchKernelGGL((k_cg_init<R, Geo>), dim3(lc.ncg), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), lc.cg, b, x,
+                       v, tol * tol, mixed ? kRuDrop2 : 0.0, c->p.cg_maxit, lc.pc ? 1 : 0);
     LAUNCHCHK();
+    if (lc.pc) {
+        int rc = enqueue_pc<R, Geo>(c, lc, v, PEND_BB, s);
+        if (rc) return rc;
+    }
 
     const size_t st_bytes = sizeof(CgState) * size_t(n);
-    const int chunk_launches = 2 * chunk + 4;
+    const int nlaunch = chunk_launches(chunk, lc.pc);
     int issued = 0;
     int k = 0;
     bool have_prev = false;
@@ -578,10 +711,9 @@ static int cg_run(hmc_ctx* c, Geo geo, int grid, int n, const double* phi64, con
     for (;;) {
         if (use_graphs) {
             HIPCHK(hipGraphLaunch(c->cgg[mixed ? 1 : 0].exec[k == 0 ? 0 : 1], s));
-            c->seq += chunk_launches;
+            c->seq += nlaunch;
         } else {
-            int rc = enqueue_chunk<R, Geo>(c, geo, grid, n, phi64, b, x, chunk, ru_filter, k == 0, sample,
-                                           k & 1, s);
+            int rc = enqueue_chunk<R, Geo>(c, lc, n, phi64, b, x, chunk, ru_filter, k == 0, sample, k & 1, s);
             if (rc) return rc;
         }
         issued += chunk;
@@ -649,18 +781,17 @@ static int cg_dispatch(hmc_ctx* c, const double* phi, const double2* b, double2*
                        hmc_cg_stats* stats, hipStream_t s) {
     int rc;
     if (c->p.precision == HMC_MIXED)
-        rc = cg_run<float>(c, geo_one(c, c->bpr32), c->bpr32 * n, n, phi, b, x, s);
+        rc = cg_run<float>(c, launch_one<float>(c, n), n, phi, b, x, s);
     else
-        rc = cg_run<double>(c, geo_one(c, c->bpr64), c->bpr64 * n, n, phi, b, x, s);
+        rc = cg_run<double>(c, launch_one<double>(c, n), n, phi, b, x, s);
     if (rc == HMC_OK || rc == HMC_ERR_NOT_CONVERGED || rc == HMC_ERR_NONFINITE) fill_cg_stats(c, n, rc, stats);
     return rc;
 }
 
 // A batch: every (lattice, right-hand side) unit.
 static int cg_dispatch_batch(hmc_ctx* c, const double* phi, const double2* b, double2* x, hipStream_t s) {
-    if (c->p.precision == HMC_MIXED)
-        return cg_run<float>(c, geo_batch(c, 1), c->bi.nblocks[1], c->nunits, phi, b, x, s);
-    return cg_run<double>(c, geo_batch(c, 0), c->bi.nblocks[0], c->nunits, phi, b, x, s);
+    if (c->p.precision == HMC_MIXED) return cg_run<float>(c, launch_batch<float>(c), c->nunits, phi, b, x, s);
+    return cg_run<double>(c, launch_batch<double>(c), c->nunits, phi, b, x, s);
 }
 
 static void merge_stats(hmc_traj_stats* t, const hmc_cg_stats& cs) {
@@ -826,6 +957,112 @@ static void fill_energies(const double* hs, int n_pf, hmc_traj_stats* stats) {
     stats->dH = stats->H1 - stats->H0;
 }
 
+// Preconditioner support and sizes for the lattices of the context: FFT plans for L and L_tau,
+// dynamic LDS of the three passes per precision against the device's per-workgroup limit,
+// table offsets; batch: the workgroup counts of the slice and tau passes.
+static void pc_setup(hmc_ctx* c) {
+    int maxlds = 0;
+    if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
+        maxlds = 0;
+    std::vector<Lat> lats;
+    if (c->is_batch) lats = c->bi.lats;
+    else lats.push_back(c->lat);
+    bool plans = true;
+    long long blob = 0;
+    c->pc_r7 = false;
+    c->bi.pcoff.assign(1, 0);
+    c->bi.nslices = 0;
+    c->bi.ngroups[0] = c->bi.ngroups[1] = 0;
+    for (int pi = 0; pi < 2; ++pi) c->lds_xy[pi] = c->lds_t[pi] = 0;
+    for (const Lat& l : lats) {
+        FftPlan pa, pb;
+        const bool ok = make_fft_plan(l.L, pa) && make_fft_plan(l.Lt, pb);
+        plans = plans && ok;
+        if (ok) c->pc_r7 = c->pc_r7 || fft_max_radix(pa) == 7 || fft_max_radix(pb) == 7;
+        blob += pc_blob_layout(l.L, l.Lt).size;
+        c->bi.pcoff.push_back(blob);
+        const int nrhs = c->is_batch ? c->bi.nrhs : 1;
+        c->bi.nslices += 4 * l.Lt * nrhs;
+        c->bi.ngroups[0] += 4 * pc_groups(l.LL, pc_ncol<double>()) * nrhs;
+        c->bi.ngroups[1] += 4 * pc_groups(l.LL, pc_ncol<float>()) * nrhs;
+        const size_t c64 = sizeof(double2), c32 = sizeof(float2);
+        c->lds_xy[0] = std::max(c->lds_xy[0], size_t(l.LL + l.L) * c64);
+        c->lds_xy[1] = std::max(c->lds_xy[1], size_t(l.LL + l.L) * c32);
+        c->lds_t[0] = std::max(c->lds_t[0], size_t(l.Lt * pc_ncol<double>() + 2 * l.Lt) * c64 +
+                                                size_t(l.Lt + l.L + pc_ncol<double>()) * 8);
+        c->lds_t[1] = std::max(c->lds_t[1], size_t(l.Lt * pc_ncol<float>() + 2 * l.Lt) * c32 +
+                                                size_t(l.Lt + l.L + pc_ncol<float>()) * 8);
+    }
+    c->blob_doubles = blob;
+    for (int pi = 0; pi < 2; ++pi)
+        c->pc_ok[pi] = plans && c->lds_xy[pi] <= size_t(maxlds) && c->lds_t[pi] <= size_t(maxlds);
+}
+
+static int check_precond(const hmc_ctx* c, const hmc_params* p) {
+    if (p->precond == HMC_PRECOND_FOURIER && !c->pc_ok[p->precision == HMC_MIXED ? 1 : 0])
+        return fail(HMC_ERR_INVALID_ARG,
+                    "Fourier preconditioner unavailable for this lattice and precision (L and L_tau need "
+                    "prime factors <= 7, and an L x L slice must fit the GPU's LDS)");
+    return HMC_OK;
+}
+
+// Allow the preconditioner passes their dynamic LDS (above the default per-workgroup amount).
+template <typename R, class Geo, int MAXR>
+static void pc_lds_attributes_r(size_t xy, size_t t) {
+    const hipFuncAttribute a = hipFuncAttributeMaxDynamicSharedMemorySize;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pc_xy<R, false, Geo, MAXR>), a, int(xy));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pc_xy<R, true, Geo, MAXR>), a, int(xy));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pc_t<R, Geo, MAXR>), a, int(t));
+}
+
+template <class Geo>
+static void pc_lds_attributes(const hmc_ctx* c) {
+    if (c->pc_ok[0]) {
+        if (c->pc_r7) pc_lds_attributes_r<double, Geo, 7>(c->lds_xy[0], c->lds_t[0]);
+        else pc_lds_attributes_r<double, Geo, 5>(c->lds_xy[0], c->lds_t[0]);
+    }
+    if (c->pc_ok[1]) {
+        if (c->pc_r7) pc_lds_attributes_r<float, Geo, 7>(c->lds_xy[1], c->lds_t[1]);
+        else pc_lds_attributes_r<float, Geo, 5>(c->lds_xy[1], c->lds_t[1]);
+    }
+    (void)hipGetLastError();
+}
+
+// Preconditioner tables of every lattice into the workspace; batch: the pass block tables.
+static int upload_pc(hmc_ctx* c) {
+    std::vector<Lat> lats;
+    if (c->is_batch) lats = c->bi.lats;
+    else lats.push_back(c->lat);
+    std::vector<double> all;
+    for (const Lat& l : lats) {
+        FftPlan pa, pb;
+        if (!make_fft_plan(l.L, pa) || !make_fft_plan(l.Lt, pb)) return HMC_OK;   // unsupported: no tables
+        const std::vector<double> b = pc_table_blob(pa, pb);
+        all.insert(all.end(), b.begin(), b.end());
+    }
+    if (!all.empty()) HIPCHK(hipMemcpy(c->blob, all.data(), sizeof(double) * all.size(), hipMemcpyHostToDevice));
+    if (c->is_batch) {
+        BatchInfo& b = c->bi;
+        std::vector<int2> xy, t[2];
+        for (int ch = 0; ch < b.nchains; ++ch) {
+            const Lat& l = b.lats[size_t(ch)];
+            for (int k = 0; k < b.nrhs; ++k) {
+                const int u = ch * b.nrhs + k;
+                for (int r = 0; r < 4 * l.Lt; ++r) xy.push_back(make_int2(u, r));
+                for (int r = 0; r < 4 * pc_groups(l.LL, pc_ncol<double>()); ++r) t[0].push_back(make_int2(u, r));
+                for (int r = 0; r < 4 * pc_groups(l.LL, pc_ncol<float>()); ++r) t[1].push_back(make_int2(u, r));
+            }
+        }
+        HIPCHK(hipMemcpy(b.pxy_blocks, xy.data(), sizeof(int2) * xy.size(), hipMemcpyHostToDevice));
+        for (int pi = 0; pi < 2; ++pi)
+            HIPCHK(hipMemcpy(b.pt_blocks[pi], t[pi].data(), sizeof(int2) * t[pi].size(), hipMemcpyHostToDevice));
+        pc_lds_attributes<GeoBatch>(c);
+    } else {
+        pc_lds_attributes<GeoOne>(c);
+    }
+    return HMC_OK;
+}
+
 static int create_common(hmc_ctx* c) {
     if (hipGetDevice(&c->device) != hipSuccess) return fail(HMC_ERR_HIP, "hipGetDevice failed");
     if (hipHostMalloc((void**)&c->h_st, sizeof(CgState) * 2 * size_t(c->nunits), hipHostMallocDefault) != hipSuccess ||
@@ -887,6 +1124,10 @@ static int set_workspace_common(hmc_ctx* c, void* ptr, size_t bytes) {
     c->ws = base;
     c->ws_bytes = bytes;
     c->generation += 1;
+    {
+        int rc = upload_pc(c);
+        if (rc) return rc;
+    }
     if (c->is_batch) {
         int rc = upload_chains(c);
         if (rc) return rc;
@@ -1074,8 +1315,10 @@ int hmc_test_precond(int L, int Lt, double dtau, const hmc_params* params, const
     std::vector<double> blob = pc_table_blob(pl, pt);
     const PcBlob bl = pc_blob_layout(L, Lt);
     double* B = blob.data();
+    std::vector<double> bcol(16);
     const PcTables<double> t{reinterpret_cast<double2*>(B + bl.twt), B + bl.s2, B + bl.cosx,
-                             reinterpret_cast<double2*>(B + bl.twl), reinterpret_cast<double2*>(B + bl.twT)};
+                             reinterpret_cast<double2*>(B + bl.twl), reinterpret_cast<double2*>(B + bl.twT),
+                             bcol.data()};
     const double2* twl = t.twl;
     const ExHost ex;
     for (int sl = 0; sl < 4 * Lt; ++sl) fft_slice<double, false>(ex, w.data() + size_t(sl) * LL, pl, twl);
@@ -1136,10 +1379,15 @@ int hmc_create(int L, int Lt, double dtau, const hmc_params* params, hmc_ctx** o
     c->vec_sites = (long long)c->cap * c->vol;
     c->phi_sites = c->vol;
     c->nunits = c->cap;
-    c->pslots = c->cap * clamp_bpr(c->nblk2, kMaxBpr);
+    c->pstride = unit_slots(c->lat);
+    c->pslots = c->cap * c->pstride;
     c->ngblk = c->nblk;
     set_coefs(c);
     rc = create_common(c);
+    if (rc == HMC_OK) {
+        pc_setup(c);
+        rc = check_precond(c, params);
+    }
     if (rc) {
         destroy_common(c);
         delete c;
@@ -1222,6 +1470,8 @@ int hmc_set_params(hmc_ctx* c, const hmc_params* params) {
     if (rc) return rc;
     const int want = params->max_rhs > 0 ? params->max_rhs : params->n_pf;
     if (want > c->cap) return fail(HMC_ERR_INVALID_ARG, "n_pf/max_rhs %d exceeds workspace capacity %d", want, c->cap);
+    rc = check_precond(c, params);
+    if (rc) return rc;
     c->p = *params;
     set_coefs(c);
     return HMC_OK;
@@ -1455,13 +1705,17 @@ int hmc_batch_create(int nchains, const int* L, const int* L_tau, const double* 
     c->phi_sites = tot_vol;
     c->nunits = int(tot_units);
     c->pslots = 0;
-    for (const Lat& l : b.lats) c->pslots += b.nrhs * clamp_bpr(tiles2_host(l.vol), kMaxBpr);
+    for (const Lat& l : b.lats) c->pslots += b.nrhs * unit_slots(l);
     c->ngblk = b.cfirst.back();
     c->lat = b.lats[0];
     c->nblk = tiles1_host(c->lat.vol);
     c->nblk2 = tiles2_host(c->lat.vol);
     set_coefs(c);
     rc = create_common(c);
+    if (rc == HMC_OK) {
+        pc_setup(c);
+        rc = check_precond(c, params);
+    }
     if (rc) {
         destroy_common(c);
         delete hb;
@@ -1522,6 +1776,8 @@ int hmc_batch_set_params(hmc_batch* hb, const hmc_params* params) {
     int rc = check_params(params);
     if (rc) return rc;
     if (params->n_pf != hb->c.bi.nrhs) return fail(HMC_ERR_INVALID_ARG, "n_pf is fixed at creation in batch mode");
+    rc = check_precond(&hb->c, params);
+    if (rc) return rc;
     hb->c.p = *params;
     set_coefs(&hb->c);
     if (hb->c.ws != nullptr) return upload_chains(&hb->c);

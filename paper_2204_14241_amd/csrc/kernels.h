@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fft.h"
 #include "lattice.h"
 
 namespace hmc {
@@ -84,7 +85,8 @@ enum : int {
     F_MAXIT = 1 << CG_MAXIT,
 };
 // Which partial sums the previous kernel left to be reduced.
-enum CgPending : int { PEND_NONE = 0, PEND_BB = 1, PEND_TT = 2, PEND_RR = 3, PEND_RU = 4 };
+enum CgPending : int { PEND_NONE = 0, PEND_BB = 1, PEND_TT = 2, PEND_RR = 3, PEND_RU = 4, PEND_RZ = 5 };
+constexpr int kPendKinds = 5;
 
 struct CgState {
     double bb;          // |b|^2
@@ -99,12 +101,18 @@ struct CgState {
     double drop2;       // reliable update once |r|^2 falls below drop2 times its value at the
                         // last true residual (0: only at the stop)
     double ru_rr;       // that threshold
+    double rz;          // <r, z> of the current residual, z = P r (z = r without preconditioner)
+    double rz_prev;     // <r, z> of the previous residual
     int mode;
     int iters;
     int pbuf;           // which of the two direction buffers holds the current p
     int n_ru;           // FP64 true-residual recomputations
     int maxit;
     int pending;        // CgPending
+    int pc;             // 1: Fourier-preconditioned (z = P r computed by the three pc passes)
+    int zstage;         // pc: 0 z current; 1 forward (x, y) transform done; 2 tau pass done
+    int zinit;          // pc: the next <r, z> is the first of the solve (no direction to keep)
+    int pad;
 };
 
 // One right-hand side of one lattice: the unit the CG state machine tracks.  A solve on a
@@ -117,7 +125,7 @@ struct UnitDesc {
     int bpr;            // workgroups on the unit; workgroup b takes tiles b, b + bpr, ...
     int part;           // first partial-sum slot of the unit (within one kind)
     int chain;          // lattice the unit belongs to
-    int pad;
+    int pcoff;          // first double of its lattice's preconditioner tables
 };
 
 // Where a workgroup works: its unit and its rank within the unit.
@@ -126,14 +134,19 @@ struct UPos {
     size_t voff, phioff;
     int k;              // unit (state record index)
     int blk;            // workgroup within the unit
-    int bpr;            // workgroups on the unit
+    int bpr;            // CG workgroups on the unit (the count of its step partials)
     int part;           // first partial slot of the unit
+    int pcoff;          // first double of the preconditioner tables of its lattice
 };
 
-// One lattice: unit k = right-hand side k, bpr workgroups each, in k-major order.
+// One lattice: unit k = right-hand side k; a launch runs nblk workgroups per unit in k-major
+// order (nblk = bpr for the CG steps, the slice or column-group count for the preconditioner
+// passes); each unit owns pstride partial slots per kind.
 struct GeoOne {
     Lat lat;
     int bpr;
+    int nblk;
+    int pstride;
     __device__ __forceinline__ UPos unit(int k, int blk) const {
         UPos p;
         p.lat = lat;
@@ -142,12 +155,13 @@ struct GeoOne {
         p.k = k;
         p.blk = blk;
         p.bpr = bpr;
-        p.part = k * bpr;
+        p.part = k * pstride;
+        p.pcoff = 0;
         return p;
     }
     __device__ __forceinline__ UPos at(int logical) const {
-        const int k = logical / bpr;
-        return unit(k, logical - k * bpr);
+        const int k = logical / nblk;
+        return unit(k, logical - k * nblk);
     }
 };
 
@@ -165,6 +179,7 @@ struct GeoBatch {
         p.blk = blk;
         p.bpr = u.bpr;
         p.part = u.part;
+        p.pcoff = u.pcoff;
         return p;
     }
     __device__ __forceinline__ UPos at(int logical) const {
@@ -207,7 +222,7 @@ __device__ __forceinline__ int tiles2(const Lat& l) { return (l.vol / 2 + kBlock
 struct CgCtl {
     const CgState* st_in;
     CgState* st_out;
-    double* part;       // partial sums [4 kinds][nslots]
+    double* part;       // partial sums [kPendKinds][nslots]
     int nslots;         // partial slots per kind
     int expect;         // the only partial kind that can be pending at this launch
 };
@@ -225,72 +240,107 @@ __device__ __forceinline__ CgState& cg_shared() {
     return sh;
 }
 
-// Reduce the pending partials of right-hand side k and advance its state machine into
-// cg_shared().  Every workgroup computes the same record (deterministic order).  The record
-// (24 dwords, one per lane) and the partials the host expects to be pending are loaded in
-// the same memory round trip; the partials are used only if the record says so.
-__device__ __forceinline__ void cg_finalize(const CgCtl& c, const UPos& pos) {
+// Reduce the pending partials of right-hand side k (nparts of them, as many as the producing
+// kernel ran workgroups on the unit) and advance its state machine into cg_shared().  Every
+// workgroup computes the same record (deterministic order).  The record (one dword per lane)
+// and the partials the host expects to be pending are loaded in the same memory round trip;
+// the partials are used only if the record says so.  Returns the kind consumed (PEND_NONE if
+// nothing was pending).  A pending kind other than the expected one (a sequencing error of
+// the host) fails the right-hand side instead of using foreign partials.
+__device__ __forceinline__ int cg_finalize(const CgCtl& c, const UPos& pos, int nparts) {
     const int k = pos.k;
     CgState& sh = cg_shared();
+    __shared__ int consumed;
     const int t = threadIdx.x;
     unsigned w = 0u;
     if (t < kStateWords) w = reinterpret_cast<const unsigned*>(c.st_in + k)[t];
     double tot = 0.0;
-    if (c.expect != PEND_NONE) tot = sum_partials(part_slot(c, c.expect, pos), pos.bpr);
+    if (c.expect != PEND_NONE) tot = sum_partials(part_slot(c, c.expect, pos), nparts);
     if (t < kStateWords) reinterpret_cast<unsigned*>(&sh)[t] = w;
     __syncthreads();
-    if (t == 0 && sh.pending != PEND_NONE) {
+    if (t == 0) {
         CgState& s = sh;
-        switch (s.pending) {
-            case PEND_BB:
-                s.bb = tot;
-                s.stop_rr = s.tol2 * tot;
-                s.rr = s.rr_prev = s.rr_true = tot;
-                s.ru_rr = s.drop2 * tot;
-                s.mode = !finite(tot) ? CG_FAILED : (tot > 0.0 ? CG_ACTIVE : CG_DONE);
-                break;
-            case PEND_TT:
-                if (s.mode == CG_ACTIVE) {
-                    if (!(tot > 0.0) || !finite(tot)) s.mode = CG_FAILED;
-                    else s.alpha_cur = s.rr / tot;
-                }
-                break;
-            case PEND_RR:
-                if (s.mode == CG_ACTIVE) {
+        consumed = s.pending;
+        if (s.pending != PEND_NONE && s.pending != c.expect) {
+            s.mode = CG_FAILED;
+        } else {
+            switch (s.pending) {
+                case PEND_BB:
+                    s.bb = tot;
+                    s.stop_rr = s.tol2 * tot;
+                    s.rr = s.rr_prev = s.rr_true = tot;
+                    s.rz = s.rz_prev = tot;
+                    s.ru_rr = s.drop2 * tot;
+                    s.zinit = 1;
+                    s.zstage = 0;
+                    s.mode = !finite(tot) ? CG_FAILED : (tot > 0.0 ? CG_ACTIVE : CG_DONE);
+                    break;
+                case PEND_TT:
+                    if (s.mode == CG_ACTIVE) {
+                        if (!(tot > 0.0) || !finite(tot)) s.mode = CG_FAILED;
+                        else s.alpha_cur = s.rz / tot;
+                    }
+                    break;
+                case PEND_RR:
+                    if (s.mode == CG_ACTIVE) {
+                        if (!finite(tot)) {
+                            s.mode = CG_FAILED;
+                        } else {
+                            s.rz_prev = s.rz;
+                            if (!s.pc) {
+                                s.beta = tot / s.rz;
+                                s.rz = tot;
+                            }
+                            s.rr_prev = s.rr;
+                            s.rr = tot;
+                            s.alpha = s.alpha_cur;
+                            s.iters += 1;
+                            if (tot <= s.stop_rr || tot <= s.ru_rr) s.mode = CG_CONV_ITER;
+                            else if (s.iters >= s.maxit) s.mode = CG_MAXIT;
+                        }
+                    }
+                    break;
+                case PEND_RU:
+                    s.rr_true = tot;
+                    s.n_ru += 1;
+                    s.alpha = 0.0;
                     if (!finite(tot)) {
                         s.mode = CG_FAILED;
+                    } else if (tot <= s.stop_rr) {
+                        s.mode = CG_DONE;
+                    } else if (s.mode == CG_MAXIT) {
+                        s.mode = CG_STOPPED;
                     } else {
-                        s.rr_prev = s.rr;
-                        s.beta = tot / s.rr;
+                        if (!s.pc) {
+                            s.beta = tot / s.rz_prev;
+                            s.rz = tot;
+                        }
                         s.rr = tot;
-                        s.alpha = s.alpha_cur;
-                        s.iters += 1;
-                        if (tot <= s.stop_rr || tot <= s.ru_rr) s.mode = CG_CONV_ITER;
-                        else if (s.iters >= s.maxit) s.mode = CG_MAXIT;
+                        s.ru_rr = s.drop2 * tot;
+                        s.mode = CG_ACTIVE;
                     }
-                }
-                break;
-            case PEND_RU:
-                s.rr_true = tot;
-                s.n_ru += 1;
-                s.alpha = 0.0;
-                if (!finite(tot)) {
-                    s.mode = CG_FAILED;
-                } else if (tot <= s.stop_rr) {
-                    s.mode = CG_DONE;
-                } else if (s.mode == CG_MAXIT) {
-                    s.mode = CG_STOPPED;
-                } else {
-                    s.beta = tot / s.rr_prev;
-                    s.rr = tot;
-                    s.ru_rr = s.drop2 * tot;
-                    s.mode = CG_ACTIVE;
-                }
-                break;
+                    break;
+                case PEND_RZ:
+                    if (s.mode == CG_ACTIVE) {
+                        if (!(tot > 0.0) || !finite(tot)) {
+                            s.mode = CG_FAILED;
+                        } else if (s.zinit) {
+                            s.beta = 0.0;
+                            s.rz = tot;
+                            s.zinit = 0;
+                        } else {
+                            s.beta = tot / s.rz_prev;
+                            s.rz = tot;
+                        }
+                    }
+                    s.zstage = 0;
+                    break;
+            }
         }
         s.pending = PEND_NONE;
     }
     __syncthreads();
+    return consumed;
 }
 
 // Workgroup 0 of a right-hand side publishes the record for the next kernel (all threads
@@ -397,6 +447,7 @@ struct CgVecs {
     C2<R>* p1;      // direction, buffer 1
     C2<R>* t;       // M p
     C2<R>* x;       // solution accumulated in R (the caller's x in FP64 mode)
+    C2<R>* z;       // preconditioned residual P r (the residual itself without preconditioner)
 };
 
 // Store this workgroup's partial (thread 0) after a block reduction.
@@ -415,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, Geo geo, CgVecs<R> v
     const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
     const Lat& lat = pos.lat;
     const R* phi = phi_base + pos.phioff;
-    cg_finalize(ctl, pos);
+    cg_finalize(ctl, pos, pos.bpr);
     const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
         cg_publish(ctl, pos);
@@ -426,10 +477,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, Geo geo, CgVecs<R> v
     const size_t off = pos.voff;
     const C2<R>* pin = (pb ? v.p1 : v.p0) + off;
     C2<R>* pout = (pb ? v.p0 : v.p1) + off;
-    const C2<R>* r = v.r + off;
     C2<R>* x = v.x + off;
     C2<R>* t = v.t + off;
-    SrcXpay<R> src{r, pin, beta, lat.vol};
+    SrcXpay<R> src{v.z + off, pin, beta, lat.vol};
     double part = 0.0;
     for (TileSpan sp = tile_span(pos.blk, pos.bpr, tiles1(lat)); sp.first < sp.end; sp.first += sp.step) {
         const int tile = sp.first;
@@ -467,7 +517,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(CgCtl ctl, Geo geo, CgVecs<R> v
     const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
     const Lat& lat = pos.lat;
     const R* phi = phi_base + pos.phioff;
-    cg_finalize(ctl, pos);
+    cg_finalize(ctl, pos, pos.bpr);
     const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
         cg_publish(ctl, pos);
@@ -508,7 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_fold(CgCtl ctl, Geo geo, double2*
                                                     CgVecs<R> v, int filter) {
     const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
     const Lat& lat = pos.lat;
-    cg_finalize(ctl, pos);
+    cg_finalize(ctl, pos, pos.bpr);
     const CgState& S = cg_shared();
     if (!((1 << S.mode) & filter)) {
         cg_publish(ctl, pos);
@@ -552,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_apply(CgCtl ctl, Geo geo, const d
     const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
     const Lat& lat = pos.lat;
     const double* phi = phi_base + pos.phioff;
-    cg_finalize(ctl, pos);
+    cg_finalize(ctl, pos, pos.bpr);
     const int mode = cg_shared().mode;
     cg_publish(ctl, pos);
     if (!((1 << mode) & filter)) return;
@@ -581,7 +631,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_resid(CgCtl ctl, Geo geo, const d
     const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
     const Lat& lat = pos.lat;
     const double* phi = phi_base + pos.phioff;
-    cg_finalize(ctl, pos);
+    cg_finalize(ctl, pos, pos.bpr);
     if (!((1 << cg_shared().mode) & filter)) {
         cg_publish(ctl, pos);
         return;
@@ -614,7 +664,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_resid(CgCtl ctl, Geo geo, const d
 template <typename R, class Geo>
 __global__ __launch_bounds__(kBlock) void k_cg_init(CgCtl ctl, Geo geo, const double2* __restrict__ b,
                                                     double2* __restrict__ x64, CgVecs<R> v,
-                                                    double tol2, double drop2, int maxit) {
+                                                    double tol2, double drop2, int maxit, int pc) {
     const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
     const Lat& lat = pos.lat;
     const size_t off = pos.voff;
@@ -644,18 +694,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgCtl ctl, Geo geo, const do
         S.tol2 = tol2;
         S.drop2 = drop2;
         S.maxit = maxit;
+        S.pc = pc;
         S.mode = CG_ACTIVE;
         S.pending = PEND_BB;
     }
     cg_publish(ctl, pos);
 }
 
-// One workgroup per right-hand side: reduce whatever is pending and publish the record
-// (run before the host reads the status).
+// One workgroup per right-hand side: reduce whatever is pending (nparts per unit: 0 selects
+// the unit's CG workgroup count) and publish the record.
 template <class Geo>
-__global__ __launch_bounds__(kBlock) void k_cg_finalize(CgCtl ctl, Geo geo) {
+__global__ __launch_bounds__(kBlock) void k_cg_finalize(CgCtl ctl, Geo geo, int nparts) {
     const UPos pos = geo.unit(blockIdx.x, 0);
-    cg_finalize(ctl, pos);
+    cg_finalize(ctl, pos, nparts > 0 ? nparts : pos.bpr);
     cg_publish(ctl, pos);
 }
 
@@ -770,7 +821,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a2(CgCtl ctl, Geo geo, CgVecs<flo
     const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
     const Lat& lat = pos.lat;
     const float* phi = phi_base + pos.phioff;
-    cg_finalize(ctl, pos);
+    cg_finalize(ctl, pos, pos.bpr);
     const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
         cg_publish(ctl, pos);
@@ -781,10 +832,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_a2(CgCtl ctl, Geo geo, CgVecs<flo
     const size_t off = pos.voff;
     const float2* pin = (pb ? v.p1 : v.p0) + off;
     float2* pout = (pb ? v.p0 : v.p1) + off;
-    const float2* r = v.r + off;
     float2* x = v.x + off;
     float2* t = v.t + off;
-    SrcXpay2 src{r, pin, beta, lat.vol};
+    SrcXpay2 src{v.z + off, pin, beta, lat.vol};
     double part = 0.0;
     for (TileSpan sp = tile_span(pos.blk, pos.bpr, tiles2(lat)); sp.first < sp.end; sp.first += sp.step) {
         const int tile = sp.first;
@@ -822,7 +872,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_b2(CgCtl ctl, Geo geo, CgVecs<flo
     const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
     const Lat& lat = pos.lat;
     const float* phi = phi_base + pos.phioff;
-    cg_finalize(ctl, pos);
+    cg_finalize(ctl, pos, pos.bpr);
     const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
         cg_publish(ctl, pos);
@@ -853,6 +903,164 @@ __global__ __launch_bounds__(kBlock) void k_cg_b2(CgCtl ctl, Geo geo, CgVecs<flo
     }
     store_partial(ctl, PEND_RR, pos, part);
     if (threadIdx.x == 0) cg_shared().pending = PEND_RR;
+    cg_publish(ctl, pos);
+}
+
+// ------------------------------------------------------------------------------------
+// Fourier preconditioner passes (Methods C, Eq. 26; transforms and symbol in fft.h), run for
+// the units whose residual has just changed, producing z = P r:
+//   pass 1 (k_pc_xy, forward): 2-D (x, y) transform of one (component, tau) slice, r -> z;
+//   pass 2 (k_pc_t): one group of (x, y) columns of one component: twist, tau transform,
+//          symbol, inverse tau transform, untwist, in place on z; partial <r, z> by Parseval;
+//   pass 3 (k_pc_xy, inverse): inverse 2-D transform of one slice, in place on z.
+// Pass 1 consumes the new residual norm (or the first |b|^2, or a true residual), pass 3 the
+// <r, z> partials of pass 2.  Each pass keeps its line set in LDS (dynamic shared memory the
+// host sizes per lattice).
+template <typename R>
+__host__ __device__ constexpr int pc_ncol() { return int(256 / sizeof(C2<R>)); }   // 32 FP32, 16 FP64
+
+__host__ __device__ __forceinline__ int pc_groups(int LL, int ncol) { return (LL + ncol - 1) / ncol; }
+
+// Workgroup size of the preconditioner passes: a slice or column group is one workgroup's LDS,
+// and only a few fit a CU, so each gets more threads (more loads in flight, shorter FFT phase).
+constexpr int kPcBlock = 512;
+
+// Stage n complex elements between global memory and LDS: element i of the set lives at g(i)
+// in global memory and at lds[i].  Up to 64 bytes of loads are in flight per thread before
+// their LDS writes (a plain loop would wait out the memory latency once per element).  The
+// components are kept in separate arrays so that they stay in registers.
+template <typename R, class G>
+__device__ __forceinline__ void stage_in(C2<R>* __restrict__ lds, int n, G g) {
+    constexpr int U = sizeof(R) == 4 ? 8 : 4;
+    const int nt = blockDim.x;
+    for (int i0 = threadIdx.x; i0 < n; i0 += nt * U) {
+        R vx[U], vy[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nt;
+            if (i < n) {
+                const C2<R> v = *g(i);
+                vx[u] = v.x;
+                vy[u] = v.y;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nt;
+            if (i < n) lds[i] = mk<R>(vx[u], vy[u]);
+        }
+    }
+}
+template <typename R, class G>
+__device__ __forceinline__ void stage_out(const C2<R>* __restrict__ lds, int n, G g) {
+    constexpr int U = sizeof(R) == 4 ? 8 : 4;
+    const int nt = blockDim.x;
+    for (int i0 = threadIdx.x; i0 < n; i0 += nt * U) {
+        R vx[U], vy[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nt;
+            if (i < n) {
+                const C2<R> v = lds[i];
+                vx[u] = v.x;
+                vy[u] = v.y;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nt;
+            if (i < n) *g(i) = mk<R>(vx[u], vy[u]);
+        }
+    }
+}
+
+template <typename R, bool INV, class Geo, int MAXR>
+__global__ __launch_bounds__(kPcBlock) void k_pc_xy(CgCtl ctl, Geo geo, const C2<R>* src, C2<R>* dst,
+                                                  const double* __restrict__ blob) {
+    extern __shared__ __align__(16) unsigned char pc_smem[];
+    const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = pos.lat;
+    const int L = lat.L, LL = lat.LL;
+    const int nparts = INV ? 4 * pc_groups(LL, pc_ncol<R>()) : pos.bpr;
+    const int got = cg_finalize(ctl, pos, nparts);
+    CgState& S = cg_shared();
+    const bool work = S.pc && S.mode == CG_ACTIVE &&
+                      (INV ? got == PEND_RZ : (got == PEND_RR || got == PEND_RU || got == PEND_BB));
+    if (!work) {
+        cg_publish(ctl, pos);
+        return;
+    }
+    if (!INV && threadIdx.x == 0) S.zstage = 1;
+    C2<R>* buf = reinterpret_cast<C2<R>*>(pc_smem);
+    C2<R>* tw = buf + LL;
+    const PcBlob bl = pc_blob_layout(L, lat.Lt);
+    const double* B = blob + pos.pcoff;
+    for (int i = threadIdx.x; i < L; i += kPcBlock) tw[i] = mk<R>(R(B[bl.twl + 2 * i]), R(B[bl.twl + 2 * i + 1]));
+    const int c = pos.blk / lat.Lt, tau = pos.blk - c * lat.Lt;
+    const size_t o = pos.voff + size_t(c) * lat.vol + size_t(tau) * LL;
+    __shared__ FftPlan pl;
+    if (threadIdx.x == 0) make_fft_plan(L, pl);
+    stage_in<R>(buf, LL, [&](int i) { return src + o + i; });
+    __syncthreads();
+    fft_slice<R, INV, MAXR>(ExDevice(), buf, pl, tw);
+    stage_out<R>(buf, LL, [&](int i) { return dst + o + i; });
+    cg_publish(ctl, pos);
+}
+
+template <typename R, class Geo, int MAXR>
+__global__ __launch_bounds__(kPcBlock) void k_pc_t(CgCtl ctl, Geo geo, C2<R>* z, const double* __restrict__ blob,
+                                                 Coef<double> cf) {
+    extern __shared__ __align__(16) unsigned char pc_smem[];
+    const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = pos.lat;
+    const int L = lat.L, Lt = lat.Lt, LL = lat.LL;
+    cg_finalize(ctl, pos, 0);
+    CgState& S = cg_shared();
+    const bool work = S.pc && S.mode == CG_ACTIVE && S.zstage == 1;
+    if (!work) {
+        cg_publish(ctl, pos);
+        return;
+    }
+    constexpr int NC = pc_ncol<R>();
+    const int ng = pc_groups(LL, NC);
+    const int c = pos.blk / ng, g = pos.blk - c * ng;
+    const int col0 = g * NC, ncol = min(NC, LL - col0);
+    C2<R>* buf = reinterpret_cast<C2<R>*>(pc_smem);
+    C2<R>* twT = buf + Lt * NC;
+    C2<R>* twt = twT + Lt;
+    double* s2 = reinterpret_cast<double*>(twt + Lt);
+    double* cosx = s2 + Lt;
+    double* bcol = cosx + L;
+    const PcBlob bl = pc_blob_layout(L, Lt);
+    const double* B = blob + pos.pcoff;
+    for (int i = threadIdx.x; i < Lt; i += kPcBlock) {
+        twT[i] = mk<R>(R(B[bl.twT + 2 * i]), R(B[bl.twT + 2 * i + 1]));
+        twt[i] = mk<R>(R(B[bl.twt + 2 * i]), R(B[bl.twt + 2 * i + 1]));
+        s2[i] = B[bl.s2 + i];
+    }
+    for (int i = threadIdx.x; i < L; i += kPcBlock) cosx[i] = B[bl.cosx + i];
+    const size_t o = pos.voff + size_t(c) * lat.vol + size_t(col0);
+    FastDiv dc;
+    dc.init(uint32_t(ncol));
+    stage_in<R>(buf, Lt * ncol, [&](int i) {
+        const int tau = int(dc.div(uint32_t(i)));
+        return z + o + size_t(tau) * LL + (i - tau * ncol);
+    });
+    __shared__ FftPlan pt, pl;
+    if (threadIdx.x == 0) make_fft_plan(Lt, pt);
+    if (threadIdx.x == 1) make_fft_plan(L, pl);
+    __syncthreads();
+    const PcTables<R> T{twt, s2, cosx, nullptr, twT, bcol};
+    const double part = pc_tau_pass<R, MAXR>(ExDevice(), buf, ncol, col0, c >> 1, T, pt, pl, cf);
+    stage_out<R>(buf, Lt * ncol, [&](int i) {
+        const int tau = int(dc.div(uint32_t(i)));
+        return z + o + size_t(tau) * LL + (i - tau * ncol);
+    });
+    store_partial(ctl, PEND_RZ, pos, part);
+    if (threadIdx.x == 0) {
+        S.zstage = 2;
+        S.pending = PEND_RZ;
+    }
     cg_publish(ctl, pos);
 }
 

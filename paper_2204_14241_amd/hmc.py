@@ -45,7 +45,8 @@ class HMC:
     """One lattice context on the current CUDA (HIP) device."""
 
     def __init__(self, L, Lt, dtau=0.1, model=None, eps=0.01, n_leap=10, n_pf=1, cg_tol=1e-10,
-                 cg_maxit=20000, precision="fp64", reliable_every=50, max_rhs=0, device=None):
+                 cg_maxit=20000, precision="fp64", reliable_every=50, max_rhs=0, precond=None,
+                 device=None):
         self.lib = _lib.load()
         self.L, self.Lt, self.dtau = int(L), int(Lt), float(dtau)
         self.vol = self.Lt * self.L * self.L
@@ -53,7 +54,8 @@ class HMC:
         self.model = dict(DEFAULT_MODEL, **(model or {}))
         self._p = HmcParams()
         self._fill(eps=eps, n_leap=n_leap, n_pf=n_pf, cg_tol=cg_tol, cg_maxit=cg_maxit,
-                   precision=precision, reliable_every=reliable_every, max_rhs=max_rhs)
+                   precision=precision, reliable_every=reliable_every, max_rhs=max_rhs,
+                   precond=precond)
         self._ctx = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(self.lib.hmc_create(self.L, self.Lt, self.dtau, ctypes.byref(self._p),
@@ -67,7 +69,8 @@ class HMC:
         self.capacity = self._p.max_rhs if self._p.max_rhs > 0 else max(self._p.n_pf, 1)
 
     # ---------------------------------------------------------------- parameters
-    def _fill(self, eps, n_leap, n_pf, cg_tol, cg_maxit, precision, reliable_every, max_rhs):
+    def _fill(self, eps, n_leap, n_pf, cg_tol, cg_maxit, precision, reliable_every, max_rhs,
+              precond=None):
         m = self.model
         p = self._p
         for a in range(2):
@@ -84,12 +87,15 @@ class HMC:
         p.precision = {"fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]
         p.reliable_every = int(reliable_every)
         p.max_rhs = int(max_rhs)
+        p.precond = {None: _lib.HMC_PRECOND_NONE, "none": _lib.HMC_PRECOND_NONE,
+                     "fourier": _lib.HMC_PRECOND_FOURIER}[precond]
 
     def set_params(self, **kw):
         p = self._p
         cur = dict(eps=p.eps, n_leap=p.n_leap, n_pf=p.n_pf, cg_tol=p.cg_tol, cg_maxit=p.cg_maxit,
                    precision={HMC_FP64: "fp64", HMC_MIXED: "mixed"}[p.precision],
-                   reliable_every=p.reliable_every, max_rhs=p.max_rhs)
+                   reliable_every=p.reliable_every, max_rhs=p.max_rhs,
+                   precond="fourier" if p.precond == _lib.HMC_PRECOND_FOURIER else None)
         model = kw.pop("model", None)
         if model:
             self.model = dict(self.model, **model)
@@ -281,7 +287,7 @@ class Batch:
     spinor_offsets[-1] elements (each chain's n_pf vectors one after another)."""
 
     def __init__(self, chains, dtau=0.1, model=None, eps=0.01, n_leap=10, n_pf=1, cg_tol=1e-10,
-                 cg_maxit=20000, precision="fp64", reliable_every=50, device=None):
+                 cg_maxit=20000, precision="fp64", reliable_every=50, precond=None, device=None):
         self.lib = _lib.load()
         self.chains = [(int(L), int(Lt), float(r)) for L, Lt, r in chains]
         self.nchains = len(self.chains)
@@ -291,7 +297,7 @@ class Batch:
         self.model = dict(DEFAULT_MODEL, **(model or {}))
         self._p = HmcParams()
         HMC._fill(self, eps=eps, n_leap=n_leap, n_pf=n_pf, cg_tol=cg_tol, cg_maxit=cg_maxit,
-                  precision=precision, reliable_every=reliable_every, max_rhs=0)
+                  precision=precision, reliable_every=reliable_every, max_rhs=0, precond=precond)
         n = self.nchains
         Ls = (ctypes.c_int * n)(*[c[0] for c in self.chains])
         Lts = (ctypes.c_int * n)(*[c[1] for c in self.chains])
@@ -364,7 +370,8 @@ class Batch:
         p = self._p
         cur = dict(eps=p.eps, n_leap=p.n_leap, n_pf=p.n_pf, cg_tol=p.cg_tol, cg_maxit=p.cg_maxit,
                    precision={HMC_FP64: "fp64", HMC_MIXED: "mixed"}[p.precision],
-                   reliable_every=p.reliable_every, max_rhs=0)
+                   reliable_every=p.reliable_every, max_rhs=0,
+                   precond="fourier" if p.precond == _lib.HMC_PRECOND_FOURIER else None)
         model = kw.pop("model", None)
         if model:
             self.model = dict(self.model, **model)

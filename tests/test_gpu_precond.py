@@ -1,0 +1,138 @@
+"""Fourier-preconditioned CG (Methods C, Eq. 23-26) on the GPU against the oracle.
+
+Bars: the FP64 true residual by the oracle's operator <= 1e-10 |b| (both precisions); at zero
+coupling the preconditioner inverts the normal operator, so FP64 PCG stops after one
+iteration; FP64 PCG takes the oracle PCG's iteration count to within 2 (the two differ only
+in rounding order); trajectories as for plain CG (dH to 1e-7).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth_inputs as S
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def resid(m, phi, b, x):
+    return np.linalg.norm(b - O.apply_MdagM(m, phi, x)) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("L,Lt", [(4, 8), (6, 10), (10, 7), (12, 40)])
+def test_pcg_matches_oracle(hip, precision, L, Lt):
+    say(f"pcg {precision} {L}x{L}x{Lt}")
+    m = O.Model(L=L, Lt=Lt)
+    g = S.rng(500 + L + Lt)
+    phi = S.draw_phi(g, L, Lt, 0.5)
+    b = S.draw_spinor(g, L, Lt, 2)
+    h = hip.HMC(L, Lt, n_pf=2, cg_tol=1e-10, precision=precision, precond="fourier")
+    x, st = h.cg_solve(dev(phi), dev(b))
+    hp = hip.HMC(L, Lt, n_pf=2, cg_tol=1e-10, precision=precision)
+    _, st0 = hp.cg_solve(dev(phi), dev(b))
+    say(f"  iterations pcg {st.iterations} cg {st0.iterations}; true residual {st.true_resid}")
+    assert st.status == 0
+    x = x.cpu().numpy()
+    for k in range(2):
+        assert resid(m, phi, b[k], x[k]) <= 1e-10
+        assert st.iterations[k] < st0.iterations[k]
+    if precision == "fp64":
+        for k in range(2):
+            _, it_ref, _ = O.pcg_solve(m, phi, b[k], tol=1e-10)
+            assert abs(st.iterations[k] - it_ref) <= 2, (st.iterations[k], it_ref)
+
+
+def test_pcg_exact_at_zero_coupling(hip):
+    L, Lt = 12, 40
+    g = S.rng(510)
+    phi = S.draw_phi(g, L, Lt, 1.0)
+    b = S.draw_spinor(g, L, Lt, 1)
+    h = hip.HMC(L, Lt, cg_tol=1e-12, precond="fourier", model=dict(lam=0.0))
+    x, st = h.cg_solve(dev(phi), dev(b))
+    say(f"pcg at lambda = 0: iterations {st.iterations}, residual {st.true_resid}")
+    assert st.status == 0 and st.iterations[0] == 1 and st.true_resid[0] <= 1e-12
+
+
+def test_pcg_medium_40x40x100(hip):
+    L, Lt = 40, 100
+    m = O.Model(L=L, Lt=Lt)
+    g = S.rng(511)
+    phi = S.draw_phi(g, L, Lt, 0.5)
+    b = S.draw_spinor(g, L, Lt, 1)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        h = hip.HMC(L, Lt, cg_tol=1e-10, precision=prec, precond="fourier", cg_maxit=20000)
+        x, st = h.cg_solve(dev(phi), dev(b))
+        e = resid(m, phi, b[0], x.cpu().numpy()[0])
+        say(f"pcg {prec} 40x40x100: iterations {st.iterations}, ru {st.reliable_updates}, oracle residual {e:.3e}")
+        assert st.status == 0 and e <= 1e-10
+        out[prec] = st.iterations[0]
+    _, it_ref, _ = O.pcg_solve(m, phi, b[0], tol=1e-10)
+    assert abs(out["fp64"] - it_ref) <= 2
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pcg_trajectory_matches_oracle(hip, precision):
+    L, Lt = 4, 8
+    cfg = S.WORKLOADS["tiny_4x4x8"]
+    m = O.Model(L=L, Lt=Lt)
+    phi0, trajs = S.hmc_inputs(3, L, Lt, cfg["phi_var"], 1)
+    pi, etas, u = trajs[0]
+    ref = O.trajectory(m, phi0, pi, list(etas), u, cfg["eps"], cfg["n_leap"], tol=1e-12)
+    h = hip.HMC(L, Lt, eps=cfg["eps"], n_leap=cfg["n_leap"], n_pf=1, cg_tol=1e-12, precision=precision,
+                precond="fourier")
+    phi = dev(phi0)
+    st = h.trajectory(phi, dev(pi), dev(etas), u)
+    say(f"pcg trajectory {precision}: dH {st['dH']} vs {ref['dH']}, cg iterations {st['cg_iterations']}")
+    assert st["accepted"] == ref["accepted"]
+    assert abs(st["dH"] - ref["dH"]) < 1e-7 * max(1.0, abs(ref["dH"]))
+    assert np.abs(phi.cpu().numpy() - ref["phi"]).max() < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pcg_batch_matches_oracle_and_single(hip, precision):
+    chains = [(4, 8, 0.3), (6, 10, -0.7), (8, 18, 0.0), (12, 40, -0.25)]
+    g = S.rng(512)
+    phis = [S.draw_phi(g, L, Lt, 0.5) for L, Lt, _ in chains]
+    bs = [S.draw_spinor(g, L, Lt, 2) for L, Lt, _ in chains]
+    bt = hip.Batch(chains, n_pf=2, cg_tol=1e-10, precision=precision, precond="fourier")
+    bt.set_cg_workgroups(8)
+    phi = bt.pack_phi([dev(p) for p in phis])
+    b = bt.pack_spinors([dev(v) for v in bs])
+    x, st = bt.cg_solve(phi, b)
+    say(f"pcg batch {precision}: iterations {st['iterations']}")
+    assert st["status"] == 0
+    xs = bt.unpack_spinors(x)
+    for i, (L, Lt, r) in enumerate(chains):
+        m = O.Model(L=L, Lt=Lt, r=r)
+        for k in range(2):
+            assert resid(m, phis[i], bs[i][k], xs[i][k].cpu().numpy()) <= 1e-10
+        h = hip.HMC(L, Lt, n_pf=2, cg_tol=1e-10, precision=precision, precond="fourier", model=dict(r=r))
+        h.set_cg_workgroups(8)
+        x1, st1 = h.cg_solve(dev(phis[i]), dev(bs[i]))
+        assert st1.iterations == st["iterations"][2 * i:2 * i + 2]
+        assert torch.equal(x1.reshape(xs[i].shape), xs[i])
+    # graph replay equals eager launches
+    bt.set_graphs(False)
+    x0, _ = bt.cg_solve(phi, b)
+    bt.set_graphs(True)
+    x2, _ = bt.cg_solve(phi, b)
+    assert torch.equal(x0, x2)
+
+
+def test_pcg_rejects_unsupported_lattice(hip):
+    from paper_2204_14241_amd._lib import HmcError
+    with pytest.raises(HmcError):
+        hip.HMC(4, 17, precond="fourier")
