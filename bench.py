@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--apply-reps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default CG launch shapes")
+    ap.add_argument("--pcg-steps", type=int, default=1,
+                    help="timed Fourier-preconditioned mixed trajectories (0: solves only)")
     ap.add_argument("--batch-steps", type=int, default=1,
                     help="timed trajectories of the 64-chain batched workload (0 skips it)")
     ap.add_argument("--no-extras", action="store_true",
@@ -207,6 +209,17 @@ def batch_bench(hmcmod, torch, seed, steps, warmup):
             "max_true_resid": max(st["true_resid"])}
         log(f"batch cg ({'graph' if graphs else 'eager'}): {el:.3f} s, max iterations "
             f"{max(st['iterations'])}, effective {site_it * b_it / el / 1e9:.0f} GB/s")
+    # the same solve with the Fourier preconditioner (Methods C)
+    bt.set_params(precond="fourier")
+    bt.cg_solve(phi, chi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = bt.cg_solve(phi, chi)
+    el = time.perf_counter() - t0
+    out["pcg_solve"] = {"s": el, "max_iterations": max(st["iterations"]),
+                        "unit_iterations": sum(st["iterations"]), "max_true_resid": max(st["true_resid"])}
+    log(f"batch pcg: {el:.3f} s, max iterations {max(st['iterations'])}")
+    bt.set_params(precond=None)
     bt.set_graphs(True)
     for _ in range(warmup):
         bt.trajectory(phi, pi0, eta, u)
@@ -226,6 +239,49 @@ def batch_bench(hmcmod, torch, seed, steps, warmup):
                 "acceptance": acc / (steps * len(chains)),
                 "unit_cg_iterations_per_s": its / el})
     bt.close()
+    return out
+
+
+def pcg_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, warmup, steps):
+    """Fourier-preconditioned CG (Methods C) against plain CG at the workload size: one mixed
+    solve of each on the first trajectory's pseudofermion (solves/s, iterations), then `steps`
+    preconditioned mixed trajectories on the same seeds as the plain ones."""
+    dev = torch.device("cuda")
+    out = {}
+    phi = torch.from_numpy(phi0).to(dev)
+    for pc in (None, "fourier"):
+        h = hmcmod.HMC(L, Lt, precision="mixed", precond=pc, **common)
+        chi = h.heatbath(phi, d_traj[0][1])
+        h.cg_solve(phi, chi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = h.cg_solve(phi, chi)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["solve_" + (pc or "plain")] = {"ms": 1e3 * el, "iterations": st.iterations[0],
+                                          "us_per_iteration": 1e6 * el / st.iterations[0],
+                                          "true_resid": st.true_resid[0]}
+        log(f"mixed solve precond={pc}: {1e3 * el:.1f} ms, {st.iterations[0]} iterations")
+        h.close()
+    if steps > 0:
+        h = hmcmod.HMC(L, Lt, precision="mixed", precond="fourier", **common)
+        phi = torch.from_numpy(phi0).to(dev)
+        for i in range(warmup):
+            p, e, u = d_traj[i]
+            h.trajectory(phi, p, e, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = 0
+        for i in range(warmup, warmup + steps):
+            p, e, u = d_traj[i]
+            st = h.trajectory(phi, p, e, u)
+            its += st["cg_iterations"]
+            log(f"[mixed, preconditioned] trajectory {i}: dH {st['dH']:.6g} cg iters {st['cg_iterations']}")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["traj_per_hour_mixed_pcg"] = 3600.0 * steps / el
+        out["cg_iterations_per_traj_mixed_pcg"] = its / steps
+        h.close()
     return out
 
 
@@ -384,6 +440,7 @@ def main():
             extras["cg_iterations_per_traj_fp64"] = sum(o["cg_iterations"] for o in out64) / args.fp64_steps
             extras["dH_fp64"] = [o["dH"] for o in out64]
             extras["mixed_vs_fp64_traj_speedup"] = extras["traj_per_hour_mixed"] / extras["traj_per_hour_fp64"]
+        extras["pcg_80x80x200"] = pcg_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, W, args.pcg_steps)
         for f32 in (True, False):
             aps, gbs, ms, nsets = apply_bench(hmcmod, torch, L, Lt, f32, args.apply_reps, args.seed + 1)
             extras["mdagm_apply_" + ("f32" if f32 else "f64")] = {

@@ -329,11 +329,12 @@ __host__ __device__ __forceinline__ PcBlob pc_blob_layout(int L, int Lt) {
 // Input: the (x, y)-transformed field; output: the same after twist, tau transform, symbol,
 // inverse tau transform and untwist, scaled by 1 / (N_tau L^2).  Returns the workgroup's share
 // of <r, P r> = (1 / N) sum |Y|^2 / |K_hat|^2 (Parseval), valid in every thread's own terms
-// (the caller reduces).
+// (the caller reduces).  pc_tau_core is the part between the twists (the kernels apply the
+// twists while staging the columns through LDS).
 template <typename R, int MAXR = 7, class Ex>
-__host__ __device__ __forceinline__ double pc_tau_pass(const Ex& ex, C2<R>* buf, int ncol, int col0, int band,
-                                              const PcTables<R>& t, const FftPlan& pt, const FftPlan& pl,
-                                              const Coef<double>& cf64) {
+__host__ __device__ __forceinline__ double pc_tau_core(const Ex& ex, C2<R>* buf, int ncol, int col0, int band,
+                                                       const PcTables<R>& t, const FftPlan& pt, const FftPlan& pl,
+                                                       const Coef<double>& cf64) {
     const int Lt = pt.n, L = pl.n;
     const double inv_n = 1.0 / (double(Lt) * double(L) * double(L));
     FastDiv dc, dL;
@@ -345,11 +346,6 @@ __host__ __device__ __forceinline__ double pc_tau_pass(const Ex& ex, C2<R>* buf,
         const int px = int(dL.div(uint32_t(col))), py = col - px * L;
         t.bcol[j] = -cf64.diag[band] - 2.0 * (cf64.hop[band][0] * t.cosx[px] + cf64.hop[band][1] * t.cosx[py]);
     });
-    ex.for_each(Lt * ncol, [&](int i) {
-        const int tau = int(dc.div(uint32_t(i)));
-        buf[i] = cmul<R>(buf[i], t.twt[tau]);
-    });
-    ex.sync();
     fft_lines<R, false, MAXR>(ex, buf, ncol, 1, ncol, pt, t.twT);
     const double part = ex.sum_each(Lt * ncol, [&](int i) {
         const int p = int(dc.div(uint32_t(i))), j = i - p * ncol;
@@ -360,6 +356,22 @@ __host__ __device__ __forceinline__ double pc_tau_pass(const Ex& ex, C2<R>* buf,
     });
     ex.sync();
     fft_lines<R, true, MAXR>(ex, buf, ncol, 1, ncol, pt, t.twT);
+    return part;
+}
+
+template <typename R, int MAXR = 7, class Ex>
+__host__ __device__ __forceinline__ double pc_tau_pass(const Ex& ex, C2<R>* buf, int ncol, int col0, int band,
+                                                       const PcTables<R>& t, const FftPlan& pt, const FftPlan& pl,
+                                                       const Coef<double>& cf64) {
+    const int Lt = pt.n;
+    FastDiv dc;
+    dc.init(uint32_t(ncol));
+    ex.for_each(Lt * ncol, [&](int i) {
+        const int tau = int(dc.div(uint32_t(i)));
+        buf[i] = cmul<R>(buf[i], t.twt[tau]);
+    });
+    ex.sync();
+    const double part = pc_tau_core<R, MAXR>(ex, buf, ncol, col0, band, t, pt, pl, cf64);
     ex.for_each(Lt * ncol, [&](int i) {
         const int tau = int(dc.div(uint32_t(i)));
         buf[i] = cmulc<R>(buf[i], t.twt[tau]);

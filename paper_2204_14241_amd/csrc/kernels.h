@@ -951,6 +951,52 @@ __device__ __forceinline__ void stage_in(C2<R>* __restrict__ lds, int n, G g) {
         }
     }
 }
+// As stage_in / stage_out with a value on the way: v(i, x) transforms element i.
+template <typename R, class G, class V>
+__device__ __forceinline__ void stage_in_v(C2<R>* __restrict__ lds, int n, G g, V v) {
+    constexpr int U = sizeof(R) == 4 ? 8 : 4;
+    const int nt = blockDim.x;
+    for (int i0 = threadIdx.x; i0 < n; i0 += nt * U) {
+        R vx[U], vy[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nt;
+            if (i < n) {
+                const C2<R> a = *g(i);
+                vx[u] = a.x;
+                vy[u] = a.y;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nt;
+            if (i < n) lds[i] = v(i, mk<R>(vx[u], vy[u]));
+        }
+    }
+}
+template <typename R, class G, class V>
+__device__ __forceinline__ void stage_out_v(const C2<R>* __restrict__ lds, int n, G g, V v) {
+    constexpr int U = sizeof(R) == 4 ? 8 : 4;
+    const int nt = blockDim.x;
+    for (int i0 = threadIdx.x; i0 < n; i0 += nt * U) {
+        R vx[U], vy[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nt;
+            if (i < n) {
+                const C2<R> a = v(i, lds[i]);
+                vx[u] = a.x;
+                vy[u] = a.y;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nt;
+            if (i < n) *g(i) = mk<R>(vx[u], vy[u]);
+        }
+    }
+}
+
 template <typename R, class G>
 __device__ __forceinline__ void stage_out(const C2<R>* __restrict__ lds, int n, G g) {
     constexpr int U = sizeof(R) == 4 ? 8 : 4;
@@ -1035,27 +1081,41 @@ __global__ __launch_bounds__(kPcBlock) void k_pc_t(CgCtl ctl, Geo geo, C2<R>* z,
     const double* B = blob + pos.pcoff;
     for (int i = threadIdx.x; i < Lt; i += kPcBlock) {
         twT[i] = mk<R>(R(B[bl.twT + 2 * i]), R(B[bl.twT + 2 * i + 1]));
-        twt[i] = mk<R>(R(B[bl.twt + 2 * i]), R(B[bl.twt + 2 * i + 1]));
         s2[i] = B[bl.s2 + i];
     }
     for (int i = threadIdx.x; i < L; i += kPcBlock) cosx[i] = B[bl.cosx + i];
     const size_t o = pos.voff + size_t(c) * lat.vol + size_t(col0);
     FastDiv dc;
     dc.init(uint32_t(ncol));
-    stage_in<R>(buf, Lt * ncol, [&](int i) {
-        const int tau = int(dc.div(uint32_t(i)));
-        return z + o + size_t(tau) * LL + (i - tau * ncol);
-    });
+    // the twist exp(-i pi tau / N_tau) on the way in, its conjugate on the way out (the table
+    // entries are read from global memory, where they stay cached)
+    const C2<double>* twg = reinterpret_cast<const C2<double>*>(B + bl.twt);
+    stage_in_v<R>(
+        buf, Lt * ncol,
+        [&](int i) {
+            const int tau = int(dc.div(uint32_t(i)));
+            return z + o + size_t(tau) * LL + (i - tau * ncol);
+        },
+        [&](int i, C2<R> a) {
+            const C2<double> w = twg[dc.div(uint32_t(i))];
+            return cmul<R>(a, mk<R>(R(w.x), R(w.y)));
+        });
     __shared__ FftPlan pt, pl;
     if (threadIdx.x == 0) make_fft_plan(Lt, pt);
     if (threadIdx.x == 1) make_fft_plan(L, pl);
     __syncthreads();
     const PcTables<R> T{twt, s2, cosx, nullptr, twT, bcol};
-    const double part = pc_tau_pass<R, MAXR>(ExDevice(), buf, ncol, col0, c >> 1, T, pt, pl, cf);
-    stage_out<R>(buf, Lt * ncol, [&](int i) {
-        const int tau = int(dc.div(uint32_t(i)));
-        return z + o + size_t(tau) * LL + (i - tau * ncol);
-    });
+    const double part = pc_tau_core<R, MAXR>(ExDevice(), buf, ncol, col0, c >> 1, T, pt, pl, cf);
+    stage_out_v<R>(
+        buf, Lt * ncol,
+        [&](int i) {
+            const int tau = int(dc.div(uint32_t(i)));
+            return z + o + size_t(tau) * LL + (i - tau * ncol);
+        },
+        [&](int i, C2<R> a) {
+            const C2<double> w = twg[dc.div(uint32_t(i))];
+            return cmulc<R>(a, mk<R>(R(w.x), R(w.y)));
+        });
     store_partial(ctl, PEND_RZ, pos, part);
     if (threadIdx.x == 0) {
         S.zstage = 2;
