@@ -63,11 +63,23 @@ def parse():
                     help="timed trajectories of the 64-chain batched workload (0 skips it)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed mixed trajectories (for profiler runs)")
+    ap.add_argument("--profile-pcg", action="store_true",
+                    help="short fixed sequence for profiler runs of the Fourier preconditioner: one "
+                         "mixed-precision and one FP64 preconditioned CG solve at the workload size")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="short fixed sequence for counter runs: a 512 MiB device copy (the "
                          "byte-counter calibration), FP32/FP64 M and M^dagger applies and 60 "
                          "mixed-precision CG iterations at the workload size")
     return ap.parse_args()
+
+
+def calibration_copy(torch):
+    """Three device copies of 512 MiB: the known byte count that scales the HBM counters."""
+    a = torch.empty(512 * 2 ** 20, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)                      # reads 512 MiB, writes 512 MiB
+    torch.cuda.synchronize()
 
 
 def profile_kernels(args):
@@ -78,11 +90,7 @@ def profile_kernels(args):
     cfg = S.WORKLOADS[args.workload]
     L, Lt = cfg["L"], cfg["Lt"]
     dev = torch.device("cuda")
-    a = torch.empty(512 * 2 ** 20, dtype=torch.uint8, device=dev).fill_(1)
-    b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)                      # reads 512 MiB, writes 512 MiB
-    del a, b
+    calibration_copy(torch)
     g = S.rng(args.seed)
     phi = torch.from_numpy(S.draw_phi(g, L, Lt, cfg["phi_var"])).to(dev)
     psi = torch.from_numpy(S.draw_spinor(g, L, Lt, 1)).to(dev)
@@ -97,6 +105,30 @@ def profile_kernels(args):
     x, st = h.cg_solve(phi, psi)
     torch.cuda.synchronize()
     log(f"profile sequence done: cg iterations {st.iterations}")
+
+
+def profile_pcg(args):
+    """One mixed and one FP64 Fourier-preconditioned solve (M^dag M x = M^dag eta), for
+    rocprofv3 kernel traces and counters of the preconditioner passes."""
+    import torch
+    import synth_inputs as S
+    from paper_2204_14241_amd import hmc as hmcmod
+    cfg = S.WORKLOADS[args.workload]
+    L, Lt = cfg["L"], cfg["Lt"]
+    dev = torch.device("cuda")
+    calibration_copy(torch)
+    g = S.rng(args.seed)
+    phi = torch.from_numpy(S.draw_phi(g, L, Lt, cfg["phi_var"])).to(dev)
+    eta = torch.from_numpy(S.draw_eta(g, L, Lt, 1)).to(dev)
+    for prec in ("mixed", "fp64"):
+        h = hmcmod.HMC(L, Lt, precision=prec, cg_tol=1e-10, cg_maxit=20000, reliable_every=50,
+                       precond="fourier")
+        chi = h.heatbath(phi, eta)
+        x, st = h.cg_solve(phi, chi)
+        torch.cuda.synchronize()
+        log(f"preconditioned {prec} solve at {L}x{L}x{Lt}: {st.iterations[0]} iterations, "
+            f"true residual {st.true_resid[0]:.2e}")
+        h.close()
 
 
 def measured_traffic(kname):
@@ -269,6 +301,7 @@ def pcg_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, warmup, steps):
         for i in range(warmup):
             p, e, u = d_traj[i]
             h.trajectory(phi, p, e, u)
+        h.set_kernel_timing(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         its = 0
@@ -281,6 +314,19 @@ def pcg_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, warmup, steps):
         el = time.perf_counter() - t0
         out["traj_per_hour_mixed_pcg"] = 3600.0 * steps / el
         out["cg_iterations_per_traj_mixed_pcg"] = its / steps
+        # live per-kernel samples of the preconditioned iteration (HIP events on the kernels'
+        # own dispatches); each preconditioner pass reads and writes one FP32 spinor
+        kt = h.kernel_times()
+        vol = Lt * L * L
+        passes = {}
+        for name, bps in (("cg_a_f32", BYTES_PER_SITE["cg_a_f32"]), ("cg_b_f32", BYTES_PER_SITE["cg_b_f32"]),
+                          ("pc_xy_fwd_f32", 64), ("pc_t_f32", 64), ("pc_xy_inv_f32", 64)):
+            ms, n = kt[name]
+            if ms:
+                gbs = bps * vol / (ms * 1e-3) / 1e9
+                passes[name] = {"avg_ms": ms, "samples": n, "bytes_per_launch": bps * vol, "GB/s": gbs,
+                                "frac_hbm_peak": gbs / HBM_PEAK_GBS}
+        out["kernels"] = passes
         h.close()
     return out
 
@@ -332,6 +378,9 @@ def main():
     if args.profile_kernels:
         profile_kernels(args)
         return
+    if args.profile_pcg:
+        profile_pcg(args)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the one-GPU build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
@@ -350,7 +399,7 @@ def main():
     vol = Lt * L * L
     dev = torch.device("cuda")
     K, W = args.steps, args.warmup
-    nt = W + max(K, args.fp64_steps)
+    nt = W + max(K, args.fp64_steps, args.pcg_steps)
     phi0, trajs = S.hmc_inputs(args.seed, L, Lt, cfg["phi_var"], n_pf, n_traj=nt)
     d_traj = [(torch.from_numpy(p).to(dev), torch.from_numpy(e).to(dev), u) for p, e, u in trajs]
     common = dict(eps=eps, n_leap=n_leap, n_pf=n_pf, cg_tol=1e-10, cg_maxit=20000,

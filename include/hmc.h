@@ -211,6 +211,102 @@ int hmc_trajectory(hmc_ctx* ctx, double* phi_inout, const double* pi0, const voi
 int hmc_leapfrog(hmc_ctx* ctx, double* phi_inout, double* pi_inout, const void* chi, int n_pf,
                  hmc_traj_stats* stats, void* stream);
 
+/* Fourier-diagonal HMC metric ("Scale-invariant sampling": Eq. 30 and the momentum draw
+ * and kinetic energy stated with it).  The metric of Eq. (28) is G = Sigma^{-1} with
+ * Sigma = F diag(sigma) F^*, F the unitary DFT over (tau, x, y) of each component of a
+ * boson-shaped field; sigma is a device array double[3][L_tau][L][L] indexed by frequency
+ * (component l, n_tau, k_x, k_y in natural order), positive and finite.  A real field's
+ * estimate (Eq. 30) is even in k; the operators use the even part of any table.
+ *
+ * hmc_set_metric keeps the pointer (NULL: the identity metric, the default): the caller keeps
+ * the array alive and unchanged while trajectories or the calls below run.  With a metric set,
+ * hmc_trajectory and hmc_leapfrog drift by dphi/dt = Sigma pi and report the kinetic energy
+ * 1/2 pi^T Sigma pi; their pi0 should then come from hmc_metric_momenta.  One-lattice contexts
+ * only; L and L_tau need prime factors <= 7 and an L x L FP64 slice must fit the LDS (L <= 100
+ * on gfx950).  Errors: HMC_ERR_INVALID_ARG. */
+int hmc_set_metric(hmc_ctx* ctx, const double* sigma);
+
+/* The metric operations on boson-shaped fields (device double[3][L_tau][L][L], 16-byte
+ * aligned), with the metric set on the context (sigma = 1 if none).  They use the FP64 CG
+ * scratch vector of the workspace, so they may not overlap a solve on another stream.
+ *   momenta:    pi = F(sigma^{-1/2} . F^* xi), for a real standard normal field xi: then
+ *               pi ~ N(0, G) (xi and pi may alias);
+ *   kinetic:    *K = 1/2 pi^T Sigma pi = 1/2 sum_k sigma(k) |(F pi)(k)|^2 (host double);
+ *   norm2:      *out = v^T G v = sum_k |(F v)(k)|^2 / sigma(k), the squared jump distance of
+ *               Eq. (32) for v = phi' - phi (host double);
+ *   accumulate: acc(k) += |(F phi)(k)|^2, one sample's term of the estimate of Eq. (30);
+ *               acc has sigma's layout (divide by the number of samples afterwards).
+ * kinetic and norm2 synchronise the stream.  Errors: HMC_ERR_INVALID_ARG, HMC_ERR_WORKSPACE,
+ * HMC_ERR_HIP. */
+int hmc_metric_momenta(hmc_ctx* ctx, const double* xi, double* pi, void* stream);
+int hmc_metric_kinetic(hmc_ctx* ctx, const double* pi, double* K, void* stream);
+int hmc_metric_norm2(hmc_ctx* ctx, const double* v, double* out, void* stream);
+int hmc_metric_accumulate(hmc_ctx* ctx, const double* phi, double* acc, void* stream);
+
+/* Warm-up tuning of the step size and trajectory length ("Online HMC hyperparameter
+ * tuning": Eq. 31 and Eq. 32).  Host state, owned by the caller; plain arithmetic, no GPU.
+ *
+ * Step size (Eq. 31, read from the explanation beside it: one step of eps is worth two of
+ * eps/2 per solve while alpha(eps/2)^2 <= 2 alpha(eps); violated when alpha(eps) = 0):
+ * hmc_tuner_add_step takes the energy errors dH of two single-step proposals (n_leap = 1) at
+ * eps and eps/2, adds alpha = min(1, exp(-dH)) of each to the window sums, and once `window`
+ * pairs are in, multiplies eps by `factor` if the rule holds for the window means and divides
+ * it otherwise, then restarts the window.
+ * Length (Eq. 32): hmc_tuner_add_jump adds ||phi' - phi||_G^2 alpha of a proposal of length
+ * n to that length's sums; hmc_tuner_best_length returns the n <= n_cap with the largest mean
+ * (the smallest on ties; 0 before any sample).  hmc_jitter(u, n_max) = 1 + min(floor(u n_max),
+ * n_max - 1), a length uniform on {1, ..., n_max} for u uniform on [0, 1) (0 if n_max < 1 or
+ * u is outside [0, 1)).
+ * Errors: HMC_ERR_INVALID_ARG (eps <= 0, window < 1, factor <= 1, n_cap outside
+ * [1, HMC_TUNER_MAX_LEN], n outside [1, n_cap], non-finite inputs). */
+#define HMC_TUNER_MAX_LEN 256
+typedef struct hmc_tuner {
+    double eps;             /* step size of the next warm-up iteration                     */
+    double factor;          /* multiplicative change of eps (> 1)                          */
+    int    window;          /* single-step pairs per decision (>= 1)                       */
+    int    n_cap;           /* warm-up trajectory lengths are drawn from {1, ..., n_cap}   */
+    int    count;           /* pairs in the current window                                 */
+    int    pad;
+    double sum_alpha_eps;   /* window sums of alpha(eps) and alpha(eps/2)                  */
+    double sum_alpha_half;
+    double esjd_sum[HMC_TUNER_MAX_LEN + 1];   /* per length: sum of ||dphi||_G^2 alpha     */
+    long   esjd_count[HMC_TUNER_MAX_LEN + 1]; /* per length: proposals                     */
+} hmc_tuner;
+
+int hmc_tuner_init(hmc_tuner* t, double eps, int window, double factor, int n_cap);
+int hmc_tuner_add_step(hmc_tuner* t, double dH_eps, double dH_half);
+int hmc_tuner_add_jump(hmc_tuner* t, int n, double sqdist, double dH);
+int hmc_tuner_best_length(const hmc_tuner* t);
+int hmc_jitter(double u, int n_max);
+
+/* Result of one warm-up iteration (host struct). */
+typedef struct hmc_warmup_stats {
+    double eps;             /* step size used by the three proposals                       */
+    double eps_next;        /* step size after the rule (t->eps on return)                  */
+    double dH_eps;          /* energy error of the single step of eps                      */
+    double dH_half;         /* ... and of eps/2                                             */
+    double dH;              /* energy error of the jittered proposal                       */
+    double sqdist;          /* ||phi' - phi||_G^2 of that proposal (G: the context's metric) */
+    int    n_leap;          /* its length, hmc_jitter(u_length, t->n_cap)                   */
+    int    accepted;        /* u_accept < exp(-dH)                                          */
+    long   cg_iterations;   /* Krylov iterations of the three proposals                     */
+    double max_true_resid;  /* largest final relative residual of their solves              */
+} hmc_warmup_stats;
+
+/* One warm-up iteration on a one-lattice context, in this order: momenta pi = F(sigma^{-1/2}
+ * . F^* xi) under the context's metric (pi = xi without one); two single-step proposals from
+ * (phi, pi) at t->eps and t->eps / 2, neither accepted, whose dH go to hmc_tuner_add_step
+ * after the third; a proposal of n_leap = hmc_jitter(u_length, t->n_cap) steps of t->eps,
+ * whose ||phi' - phi||_G^2 and dH go to hmc_tuner_add_jump; its Metropolis decision by
+ * u_accept (phi_inout becomes phi' or stays).  Each proposal is a full trajectory as in
+ * hmc_trajectory (heat-bath of the same eta, CG solves, energies); eps and n_leap of the
+ * context's parameters are untouched.  xi: a real standard normal field, phi's layout.
+ * Synchronises the stream.  Errors: as hmc_trajectory (phi_inout is then restored and the
+ * tuner unchanged); HMC_ERR_INVALID_ARG for an invalid tuner. */
+int hmc_warmup_iteration(hmc_ctx* ctx, hmc_tuner* t, double* phi_inout, const double* xi, const void* eta,
+                         int n_pf, double u_accept, double u_length, hmc_warmup_stats* stats,
+                         void* stream);
+
 /* Sampled kernel timing, for measuring the solver kernels inside real work.  When
  * enabled, the CG driver times the middle iteration of every status chunk in which all
  * right-hand sides are iterating (start and stop timestamps taken by the two kernels'
@@ -218,10 +314,14 @@ int hmc_leapfrog(hmc_ctx* ctx, double* phi_inout, double* pi_inout, const void* 
  * adds the two kernel durations to the accumulators below.  Eager launches only (no
  * samples while CG chunks replay from graphs).  Enabling resets them.
  * Index: [0] CG step A (t = M p with the fused x and p updates), FP32 Krylov precision;
- * [1] CG step B (r -= alpha M^dagger t), FP32; [2] step A, FP64; [3] step B, FP64. */
+ * [1] CG step B (r -= alpha M^dagger t), FP32; [2] step A, FP64; [3] step B, FP64.
+ * With the Fourier preconditioner the three passes of z = P r in the same sampled
+ * iteration: [4] forward slice FFT, [5] time-direction pass, [6] inverse slice FFT, FP32;
+ * [7], [8], [9] the same in FP64. */
+#define HMC_KT_SLOTS 10
 typedef struct hmc_kernel_times {
-    double ms[4];        /* summed durations in milliseconds                              */
-    long   count[4];     /* number of sampled launches                                    */
+    double ms[HMC_KT_SLOTS];     /* summed durations in milliseconds                      */
+    long   count[HMC_KT_SLOTS];  /* number of sampled launches                            */
 } hmc_kernel_times;
 
 int hmc_set_kernel_timing(hmc_ctx* ctx, int enable);

@@ -31,6 +31,9 @@ EXPORTED = [
     "hmc_test_fft_freq", "hmc_test_precond",
     "hmc_set_kernel_timing", "hmc_get_kernel_times", "hmc_set_cg_workgroups",
     "hmc_get_cg_workgroups", "hmc_leapfrog", "hmc_autotune", "hmc_set_graphs",
+    "hmc_set_metric", "hmc_metric_momenta", "hmc_metric_kinetic", "hmc_metric_norm2",
+    "hmc_metric_accumulate", "hmc_tuner_init", "hmc_tuner_add_step", "hmc_tuner_add_jump",
+    "hmc_tuner_best_length", "hmc_jitter", "hmc_warmup_iteration",
     "hmc_batch_create", "hmc_batch_destroy", "hmc_batch_workspace_bytes",
     "hmc_batch_set_workspace", "hmc_batch_layout", "hmc_batch_set_cg_workgroups",
     "hmc_batch_get_cg_workgroups", "hmc_batch_set_graphs", "hmc_batch_set_params",
@@ -104,11 +107,30 @@ def tune_dict(r):
     return out
 
 
+HMC_TUNER_MAX_LEN = 256
+
+
+class HmcTuner(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("factor", ctypes.c_double), ("window", ctypes.c_int),
+                ("n_cap", ctypes.c_int), ("count", ctypes.c_int), ("pad", ctypes.c_int),
+                ("sum_alpha_eps", ctypes.c_double), ("sum_alpha_half", ctypes.c_double),
+                ("esjd_sum", ctypes.c_double * (HMC_TUNER_MAX_LEN + 1)),
+                ("esjd_count", ctypes.c_long * (HMC_TUNER_MAX_LEN + 1))]
+
+
+class HmcWarmupStats(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("eps_next", ctypes.c_double), ("dH_eps", ctypes.c_double),
+                ("dH_half", ctypes.c_double), ("dH", ctypes.c_double), ("sqdist", ctypes.c_double),
+                ("n_leap", ctypes.c_int), ("accepted", ctypes.c_int), ("cg_iterations", ctypes.c_long),
+                ("max_true_resid", ctypes.c_double)]
+
+
 class HmcKernelTimes(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 4), ("count", ctypes.c_long * 4)]
+    _fields_ = [("ms", ctypes.c_double * 10), ("count", ctypes.c_long * 10)]
 
 
-KT_NAMES = ("cg_a_f32", "cg_b_f32", "cg_a_f64", "cg_b_f64")
+KT_NAMES = ("cg_a_f32", "cg_b_f32", "cg_a_f64", "cg_b_f64",
+            "pc_xy_fwd_f32", "pc_t_f32", "pc_xy_inv_f32", "pc_xy_fwd_f64", "pc_t_f64", "pc_xy_inv_f64")
 
 _lib = None
 
@@ -160,6 +182,18 @@ def load():
         "hmc_get_cg_workgroups": (I, [P, I]),
         "hmc_autotune": (I, [P, P, P, I, ctypes.POINTER(HmcTuneResult), P]),
         "hmc_set_graphs": (I, [P, I]),
+        "hmc_set_metric": (I, [P, P]),
+        "hmc_metric_momenta": (I, [P, P, P, P]),
+        "hmc_metric_kinetic": (I, [P, P, ctypes.POINTER(D), P]),
+        "hmc_metric_norm2": (I, [P, P, ctypes.POINTER(D), P]),
+        "hmc_metric_accumulate": (I, [P, P, P, P]),
+        "hmc_tuner_init": (I, [ctypes.POINTER(HmcTuner), D, I, D, I]),
+        "hmc_tuner_add_step": (I, [ctypes.POINTER(HmcTuner), D, D]),
+        "hmc_tuner_add_jump": (I, [ctypes.POINTER(HmcTuner), I, D, D]),
+        "hmc_tuner_best_length": (I, [ctypes.POINTER(HmcTuner)]),
+        "hmc_jitter": (I, [D, I]),
+        "hmc_warmup_iteration": (I, [P, ctypes.POINTER(HmcTuner), P, P, P, I, D, D,
+                                     ctypes.POINTER(HmcWarmupStats), P]),
         "hmc_batch_create": (I, [I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D), D,
                                  ctypes.POINTER(HmcParams), ctx_pp]),
         "hmc_batch_destroy": (I, [P]),

@@ -25,6 +25,7 @@
 #include "../../include/hmc_testing.h"
 #include "fft.h"
 #include "kernels.h"
+#include "metric.h"
 #include "lattice.h"
 
 using namespace hmc;
@@ -139,6 +140,14 @@ struct hmc_ctx {
     size_t lds_t[2] = {0, 0};
     long long blob_doubles = 0;    // preconditioner tables of all lattices
     bool pc_r7 = false;            // some lattice extent needs radix-7 FFT stages
+    // Fourier-diagonal HMC metric (one lattice): the caller's sigma table (null: identity,
+    // plain drift and kinetic energy), whether this lattice supports the metric passes, their
+    // tau-pass LDS and per-workgroup partial sums
+    const double* sigma = nullptr;
+    bool metric_ok = false;
+    size_t lds_mt_t = 0;
+    double* mpart = nullptr;
+    double* piw = nullptr;             // momenta of a warm-up iteration (one lattice)
     int ngblk = 0;             // 256-site tiles of the site-parallel kernels
 
     bool is_batch = false;
@@ -165,10 +174,12 @@ struct hmc_ctx {
     double* h_slots = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
 
-    // sampled kernel timing: start/stop events of steps A and B, taken by the dispatch of the
-    // kernel itself (no marker packets between kernels), one set per status slot
+    // sampled kernel timing: start/stop events of steps A and B and of the three
+    // preconditioner passes, taken by the dispatch of the kernel itself (no marker packets
+    // between kernels), one set per status slot
     bool timing = false;
-    hipEvent_t tev[2][4] = {{nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr}};
+    static constexpr int kEv = 10;
+    hipEvent_t tev[2][kEv] = {};
     hmc_kernel_times kt{};
 
     // graph replay of CG chunks
@@ -310,6 +321,8 @@ static size_t ws_layout(hmc_ctx* c, char* base) {
     char* tr = take(2 * sp64);
     char* bos = take(2 * 3 * PS * sizeof(double));
     char* f32 = take(3 * PS * sizeof(float));
+    char* mp = c->is_batch ? nullptr : take(sizeof(double) * 3 * size_t(pc_groups(c->lat.LL, pc_ncol<double>())));
+    char* pw = c->is_batch ? nullptr : take(3 * PS * sizeof(double));
     char *un0 = nullptr, *un1 = nullptr, *bl0 = nullptr, *bl1 = nullptr, *ch = nullptr,
          *cb = nullptr, *cf = nullptr, *cs = nullptr, *pxy = nullptr, *pt0 = nullptr, *pt1 = nullptr;
     if (c->is_batch) {
@@ -348,6 +361,8 @@ static size_t ws_layout(hmc_ctx* c, char* base) {
         c->pi = reinterpret_cast<double*>(bos);
         c->phi_save = reinterpret_cast<double*>(bos + 3 * PS * sizeof(double));
         c->phi32 = reinterpret_cast<float*>(f32);
+        c->mpart = reinterpret_cast<double*>(mp);
+        c->piw = reinterpret_cast<double*>(pw);
         if (c->is_batch) {
             c->bi.units[0] = reinterpret_cast<UnitDesc*>(un0);
             c->bi.units[1] = reinterpret_cast<UnitDesc*>(un1);
@@ -524,25 +539,36 @@ static CgCtl next_ctl(hmc_ctx* c, int expect) {
 
 static const CgState* current_states(const hmc_ctx* c) { return c->st + size_t(c->seq & 1) * c->nunits; }
 
+// Launch kernel k; with events e, start/stop timestamps of pass q come from its own dispatch.
+template <typename... P, typename... A>
+static void launch_timed(void (*k)(P...), int grid, int block, size_t lds, hipStream_t s, hipEvent_t* e, int q,
+                         A&&... a) {
+    if (e) hipExtLaunchKernelGGL(k, dim3(grid), dim3(block), lds, s, e[2 * q], e[2 * q + 1], 0, static_cast<P>(a)...);
+    else hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, s, static_cast<P>(a)...);
+}
+
 // The three preconditioner passes, z = P r, for the units whose residual just changed; the
 // first consumes the pending kind `expect1` (a new |r|^2, the first |b|^2 or a true residual).
 template <typename R, class Geo, int MAXR>
-static int enqueue_pc_r(hmc_ctx* c, const Launch<Geo>& lc, const CgVecs<R>& v, int expect1, hipStream_t s) {
-    hipLaunchKernelGGL((k_pc_xy<R, false, Geo, MAXR>), dim3(lc.npxy), dim3(kPcBlock), lc.lds_xy, s,
-                       next_ctl(c, expect1), lc.pxy, v.r, v.z, c->blob);
+static int enqueue_pc_r(hmc_ctx* c, const Launch<Geo>& lc, const CgVecs<R>& v, int expect1, hipStream_t s,
+                        hipEvent_t* e) {
+    // e: null, or the start/stop events of the three passes (timed by their own dispatches)
+    launch_timed(k_pc_xy<R, false, Geo, MAXR>, lc.npxy, kPcBlock, lc.lds_xy, s, e, 0,
+                 next_ctl(c, expect1), lc.pxy, v.r, v.z, c->blob);
     LAUNCHCHK();
-    hipLaunchKernelGGL((k_pc_t<R, Geo, MAXR>), dim3(lc.npt), dim3(kPcBlock), lc.lds_t, s, next_ctl(c, PEND_NONE),
-                       lc.pt, v.z, c->blob, c->cf64);
+    launch_timed(k_pc_t<R, Geo, MAXR>, lc.npt, kPcBlock, lc.lds_t, s, e, 1,
+                 next_ctl(c, PEND_NONE), lc.pt, v.z, c->blob, c->cf64);
     LAUNCHCHK();
-    hipLaunchKernelGGL((k_pc_xy<R, true, Geo, MAXR>), dim3(lc.npxy), dim3(kPcBlock), lc.lds_xy, s,
-                       next_ctl(c, PEND_RZ), lc.pxy, v.z, v.z, c->blob);
+    launch_timed(k_pc_xy<R, true, Geo, MAXR>, lc.npxy, kPcBlock, lc.lds_xy, s, e, 2,
+                 next_ctl(c, PEND_RZ), lc.pxy, v.z, v.z, c->blob);
     LAUNCHCHK();
     return HMC_OK;
 }
 
 template <typename R, class Geo>
-static int enqueue_pc(hmc_ctx* c, const Launch<Geo>& lc, const CgVecs<R>& v, int expect1, hipStream_t s) {
-    return lc.r7 ? enqueue_pc_r<R, Geo, 7>(c, lc, v, expect1, s) : enqueue_pc_r<R, Geo, 5>(c, lc, v, expect1, s);
+static int enqueue_pc(hmc_ctx* c, const Launch<Geo>& lc, const CgVecs<R>& v, int expect1, hipStream_t s,
+                      hipEvent_t* e = nullptr) {
+    return lc.r7 ? enqueue_pc_r<R, Geo, 7>(c, lc, v, expect1, s, e) : enqueue_pc_r<R, Geo, 5>(c, lc, v, expect1, s, e);
 }
 
 // Launches of one status chunk (kept even, so that every chunk starts at the same record
@@ -595,7 +621,7 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
             LAUNCHCHK();
         }
         if (lc.pc) {
-            int rc = enqueue_pc<R, Geo>(c, lc, v, PEND_RR, s);
+            int rc = enqueue_pc<R, Geo>(c, lc, v, PEND_RR, s, sample && i == chunk / 2 ? c->tev[kslot] + 4 : nullptr);
             if (rc) return rc;
         }
     }
@@ -731,13 +757,14 @@ static int cg_run(hmc_ctx* c, const Launch<Geo>& lc, int n, const double* phi64,
             // chunk k-1 began in the state chunk k-2 ended in; if every unit was iterating
             // then and is still iterating at its end, its mid-chunk sample did full work
             if (sample && start_active_prev && all_active) {
-                float ta = 0.f, tb = 0.f;
-                HIPCHK(hipEventElapsedTime(&ta, c->tev[(k - 1) & 1][0], c->tev[(k - 1) & 1][1]));
-                HIPCHK(hipEventElapsedTime(&tb, c->tev[(k - 1) & 1][2], c->tev[(k - 1) & 1][3]));
-                c->kt.ms[kt_a] += ta;
-                c->kt.ms[kt_a + 1] += tb;
-                c->kt.count[kt_a] += 1;
-                c->kt.count[kt_a + 1] += 1;
+                const hipEvent_t* ev = c->tev[(k - 1) & 1];
+                for (int q = 0; q < (lc.pc ? 5 : 2); ++q) {
+                    float t = 0.f;
+                    HIPCHK(hipEventElapsedTime(&t, ev[2 * q], ev[2 * q + 1]));
+                    const int slot = q < 2 ? kt_a + q : (mixed ? 4 : 7) + q - 2;
+                    c->kt.ms[slot] += t;
+                    c->kt.count[slot] += 1;
+                }
             }
             start_active_prev = all_active;
             if (all) break;
@@ -891,6 +918,58 @@ static int read_slots(hmc_ctx* c, hipStream_t s) {
     return HMC_OK;
 }
 
+// The metric passes on one lattice (FP64): forward slice FFT of `in` into the scratch field
+// (the FP64 CG vector t, idle outside solves), the tau pass (the reduction `red`, scaled by
+// rs, into slots[slot]; the accumulation into acc; the scaling `mul`), and with `mul` the
+// inverse slice FFT into out (add: out += h y; else out = y).  in may equal out.
+template <int MAXR>
+static int metric_passes_r(hmc_ctx* c, const double* in, double* out, int add, double h, int mul, int red,
+                           double rs, double* acc, int slot, hipStream_t s) {
+    const MetricGeo g{c->lat.L, c->lat.Lt, c->lat.LL, c->lat.vol};
+    double2* scr = c->t64;
+    const int nslice = 3 * g.Lt, ngrp = 3 * pc_groups(g.LL, pc_ncol<double>());
+    hipLaunchKernelGGL((k_mt_xy<false, MAXR>), dim3(nslice), dim3(kPcBlock), c->lds_xy[0], s, g, in, scr,
+                       static_cast<double*>(nullptr), 0, 0.0, c->blob);
+    LAUNCHCHK();
+    hipLaunchKernelGGL((k_mt_t<MAXR>), dim3(ngrp), dim3(kPcBlock), c->lds_mt_t, s, g, scr, c->sigma, mul, red, rs,
+                       acc, red ? c->mpart : static_cast<double*>(nullptr), c->blob);
+    LAUNCHCHK();
+    if (red) {
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, c->mpart, ngrp, 1, 0, c->slots + slot);
+        LAUNCHCHK();
+    }
+    if (mul) {
+        hipLaunchKernelGGL((k_mt_xy<true, MAXR>), dim3(nslice), dim3(kPcBlock), c->lds_xy[0], s, g,
+                           static_cast<const double*>(nullptr), scr, out, add, h, c->blob);
+        LAUNCHCHK();
+    }
+    return HMC_OK;
+}
+
+static int metric_passes(hmc_ctx* c, const double* in, double* out, int add, double h, int mul, int red,
+                         double rs, double* acc, int slot, hipStream_t s) {
+    return c->pc_r7 ? metric_passes_r<7>(c, in, out, add, h, mul, red, rs, acc, slot, s)
+                    : metric_passes_r<5>(c, in, out, add, h, mul, red, rs, acc, slot, s);
+}
+
+// The leapfrog drift phi += eps dphi/dt: eps pi (identity metric) or eps Sigma pi.
+static int drift(hmc_ctx* c, double* phi, const double* pi, double eps, hipStream_t s) {
+    if (c->sigma != nullptr) return metric_passes(c, pi, phi, 1, eps, MUL_SIGMA, RED_NONE, 1.0, nullptr, 0, s);
+    hipLaunchKernelGGL(k_drift, dim3(elem_grid(3LL * c->phi_sites)), dim3(kBlock), 0, s, phi, pi, eps,
+                       int(3 * c->phi_sites));
+    LAUNCHCHK();
+    return HMC_OK;
+}
+
+// Kinetic energy (1/2 |pi|^2, or 1/2 pi^T Sigma pi with the metric) and S_B into slots
+// [slot_index, slot_index + 1].
+static int energies(hmc_ctx* c, const double* pi, const double* phi, int slot_index, hipStream_t s) {
+    if (c->sigma == nullptr) return energy(c, pi, phi, slot_index, s);
+    int rc = energy(c, nullptr, phi, slot_index, s);
+    if (rc) return rc;
+    return metric_passes(c, pi, nullptr, 0, 0.0, 0, RED_SIGMA, 0.5, nullptr, slot_index, s);
+}
+
 // Leapfrog (kick-drift-kick) on (phi, pi) with pseudofermions chi fixed: n_leap steps of eps,
 // one CG solve per step plus the one at the start, the two half kicks of neighbouring steps
 // applied separately inside the gradient kernel.  Leaves sum_k Re<chi_k, x_k> of the last
@@ -929,9 +1008,8 @@ static int md_integrate(hmc_ctx* c, double* phi, double* pi, const double2* chi,
     rc = launch_force(c, phi, c->xsol, n_pf, flags, nullptr, pi, h, nl > 0 ? 1 : 0, s);
     if (rc) return rc;
     for (int step = 0; step < nl; ++step) {
-        hipLaunchKernelGGL(k_drift, dim3(elem_grid(3LL * c->phi_sites)), dim3(kBlock), 0, s, phi, pi, eps,
-                           int(3 * c->phi_sites));
-        LAUNCHCHK();
+        rc = drift(c, phi, pi, eps, s);
+        if (rc) return rc;
         rc = solve();
         if (rc) return rc;
         // closing half kick of this step, then the opening half kick of the next one
@@ -996,6 +1074,11 @@ static void pc_setup(hmc_ctx* c) {
     c->blob_doubles = blob;
     for (int pi = 0; pi < 2; ++pi)
         c->pc_ok[pi] = plans && c->lds_xy[pi] <= size_t(maxlds) && c->lds_t[pi] <= size_t(maxlds);
+    if (!c->is_batch) {
+        const Lat& l = c->lat;
+        c->lds_mt_t = size_t(l.Lt) * (pc_ncol<double>() + 1) * sizeof(double2) + size_t(l.Lt + l.L) * sizeof(int);
+        c->metric_ok = plans && c->lds_xy[0] <= size_t(maxlds) && c->lds_mt_t <= size_t(maxlds);
+    }
 }
 
 static int check_precond(const hmc_ctx* c, const hmc_params* p) {
@@ -1059,6 +1142,16 @@ static int upload_pc(hmc_ctx* c) {
         pc_lds_attributes<GeoBatch>(c);
     } else {
         pc_lds_attributes<GeoOne>(c);
+        if (c->metric_ok) {
+            const hipFuncAttribute a = hipFuncAttributeMaxDynamicSharedMemorySize;
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mt_xy<false, 5>), a, int(c->lds_xy[0]));
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mt_xy<true, 5>), a, int(c->lds_xy[0]));
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mt_t<5>), a, int(c->lds_mt_t));
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mt_xy<false, 7>), a, int(c->lds_xy[0]));
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mt_xy<true, 7>), a, int(c->lds_xy[0]));
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mt_t<7>), a, int(c->lds_mt_t));
+            (void)hipGetLastError();
+        }
     }
     return HMC_OK;
 }
@@ -1079,7 +1172,7 @@ static int create_common(hmc_ctx* c) {
 
 static void destroy_common(hmc_ctx* c) {
     for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < hmc_ctx::kEv; ++j)
             if (c->tev[i][j]) (void)hipEventDestroy(c->tev[i][j]);
     for (int p = 0; p < 2; ++p)
         for (int g = 0; g < 2; ++g)
@@ -1412,11 +1505,76 @@ int hmc_set_kernel_timing(hmc_ctx* c, int enable) {
     if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
     if (enable && c->tev[0][0] == nullptr) {
         for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 4; ++j) HIPCHK(hipEventCreate(&c->tev[i][j]));
+            for (int j = 0; j < hmc_ctx::kEv; ++j) HIPCHK(hipEventCreate(&c->tev[i][j]));
     }
     c->timing = enable != 0;
     std::memset(&c->kt, 0, sizeof(c->kt));
     return HMC_OK;
+}
+
+int hmc_set_metric(hmc_ctx* c, const double* sigma) {
+    if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
+    if (c->is_batch) return fail(HMC_ERR_INVALID_ARG, "the Fourier metric is for one-lattice contexts");
+    if (sigma != nullptr) {
+        if (!c->metric_ok)
+            return fail(HMC_ERR_INVALID_ARG,
+                        "Fourier metric unavailable for this lattice (L and L_tau need prime factors <= 7, "
+                        "and an L x L FP64 slice must fit the GPU's LDS)");
+        if (!aligned16(sigma)) return fail(HMC_ERR_INVALID_ARG, "sigma must be 16-byte aligned");
+    }
+    c->sigma = sigma;
+    return HMC_OK;
+}
+
+// Common checks of the metric entry points (two field pointers, either may be required).
+static int metric_check(hmc_ctx* c, const void* a, const void* b) {
+    if (c == nullptr || a == nullptr || b == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    if (c->is_batch) return fail(HMC_ERR_INVALID_ARG, "the Fourier metric is for one-lattice contexts");
+    int rc = need_ws(c);
+    if (rc) return rc;
+    if (!c->metric_ok)
+        return fail(HMC_ERR_INVALID_ARG,
+                    "Fourier metric unavailable for this lattice (L and L_tau need prime factors <= 7, "
+                    "and an L x L FP64 slice must fit the GPU's LDS)");
+    if (!aligned16(a) || !aligned16(b)) return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
+    return HMC_OK;
+}
+
+static int read_slot(hmc_ctx* c, int slot, double* out, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(c->h_slots + slot, c->slots + slot, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *out = c->h_slots[slot];
+    return HMC_OK;
+}
+
+int hmc_metric_momenta(hmc_ctx* c, const double* xi, double* pi, void* stream) {
+    int rc = metric_check(c, xi, pi);
+    if (rc) return rc;
+    return metric_passes(c, xi, pi, 0, 0.0, MUL_RSQRT, RED_NONE, 1.0, nullptr, 0, (hipStream_t)stream);
+}
+
+int hmc_metric_kinetic(hmc_ctx* c, const double* pi, double* K, void* stream) {
+    int rc = metric_check(c, pi, K);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    rc = metric_passes(c, pi, nullptr, 0, 0.0, 0, RED_SIGMA, 0.5, nullptr, SL_TMP, s);
+    if (rc) return rc;
+    return read_slot(c, SL_TMP, K, s);
+}
+
+int hmc_metric_norm2(hmc_ctx* c, const double* v, double* out, void* stream) {
+    int rc = metric_check(c, v, out);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    rc = metric_passes(c, v, nullptr, 0, 0.0, 0, RED_INV, 1.0, nullptr, SL_TMP, s);
+    if (rc) return rc;
+    return read_slot(c, SL_TMP, out, s);
+}
+
+int hmc_metric_accumulate(hmc_ctx* c, const double* phi, double* acc, void* stream) {
+    int rc = metric_check(c, phi, acc);
+    if (rc) return rc;
+    return metric_passes(c, phi, nullptr, 0, 0.0, 0, RED_NONE, 1.0, acc, 0, (hipStream_t)stream);
 }
 
 int hmc_set_graphs(hmc_ctx* c, int enable) {
@@ -1583,6 +1741,49 @@ int hmc_boson_action(hmc_ctx* c, const double* phi, double* S, void* stream) {
     return HMC_OK;
 }
 
+// The proposal of one trajectory from (phi, pi0): phi0 kept in c->phi_save, pi0 copied to
+// c->pi, heat-bath chi = M^dagger eta, energies at both ends and the molecular dynamics.
+// Leaves the proposal in phi and fills stats (no decision).  On an error phi is restored.
+static int traj_propose(hmc_ctx* c, double* phi, const double* pi0, const void* eta, int n_pf,
+                        hmc_traj_stats* stats, hipStream_t s) {
+    std::memset(stats, 0, sizeof(*stats));
+    const size_t phib = 3 * size_t(c->vol) * sizeof(double);
+    HIPCHK(hipMemcpyAsync(c->phi_save, phi, phib, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->pi, pi0, phib, hipMemcpyDeviceToDevice, s));
+    int rc;
+    if (n_pf > 0) {
+        rc = launch_apply<double, true>(c, phi, eta, c->chi, n_pf, s);
+        if (rc) return rc;
+        rc = dot_re(c, static_cast<const double2*>(eta), static_cast<const double2*>(eta), n_pf, SL_SPF0, s);
+        if (rc) return rc;
+    }
+    rc = energies(c, c->pi, phi, SL_K0, s);
+    if (rc) return rc;
+    auto restore = [&](int code) -> int {
+        (void)hipMemcpyAsync(phi, c->phi_save, phib, hipMemcpyDeviceToDevice, s);
+        (void)hipStreamSynchronize(s);
+        stats->accepted = 0;
+        stats->status = code;
+        return code;
+    };
+    rc = md_integrate(c, phi, c->pi, c->chi, n_pf, false, stats, s);
+    if (rc) return restore(rc);
+    rc = energies(c, c->pi, phi, SL_K1, s);
+    if (rc) return restore(rc);
+    rc = read_slots(c, s);
+    if (rc) return restore(rc);
+    fill_energies(c->h_slots, n_pf, stats);
+    if (!std::isfinite(stats->dH)) return restore(fail(HMC_ERR_NONFINITE, "dH is not finite"));
+    stats->status = HMC_OK;
+    return HMC_OK;
+}
+
+static int restore_phi(hmc_ctx* c, double* phi, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(phi, c->phi_save, 3 * size_t(c->vol) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HMC_OK;
+}
+
 int hmc_trajectory(hmc_ctx* c, double* phi, const double* pi0, const void* eta, int n_pf,
                    double u, hmc_traj_stats* stats, void* stream) {
     if (c == nullptr || phi == nullptr || pi0 == nullptr || stats == nullptr)
@@ -1593,43 +1794,163 @@ int hmc_trajectory(hmc_ctx* c, double* phi, const double* pi0, const void* eta, 
     if (n_pf > 0 && eta == nullptr) return fail(HMC_ERR_INVALID_ARG, "eta is NULL");
     if (!aligned16(phi) || !aligned16(pi0) || (eta && !aligned16(eta))) return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
-    std::memset(stats, 0, sizeof(*stats));
-    const size_t phib = 3 * size_t(c->vol) * sizeof(double);
-
-    // start: keep phi0, copy pi0, heat-bath chi = M^dagger eta, energies at phi0
-    HIPCHK(hipMemcpyAsync(c->phi_save, phi, phib, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(c->pi, pi0, phib, hipMemcpyDeviceToDevice, s));
-    if (n_pf > 0) {
-        rc = launch_apply<double, true>(c, phi, eta, c->chi, n_pf, s);
-        if (rc) return rc;
-        rc = dot_re(c, static_cast<const double2*>(eta), static_cast<const double2*>(eta), n_pf, SL_SPF0, s);
-        if (rc) return rc;
-    }
-    rc = energy(c, c->pi, phi, SL_K0, s);
+    rc = traj_propose(c, phi, pi0, eta, n_pf, stats, s);
     if (rc) return rc;
-
-    auto restore = [&](int code) -> int {
-        (void)hipMemcpyAsync(phi, c->phi_save, phib, hipMemcpyDeviceToDevice, s);
-        (void)hipStreamSynchronize(s);
-        stats->accepted = 0;
-        stats->status = code;
-        return code;
-    };
-    rc = md_integrate(c, phi, c->pi, c->chi, n_pf, false, stats, s);
-    if (rc) return restore(rc);
-    rc = energy(c, c->pi, phi, SL_K1, s);
-    if (rc) return restore(rc);
-    rc = read_slots(c, s);
-    if (rc) return restore(rc);
-    fill_energies(c->h_slots, n_pf, stats);
-    if (!std::isfinite(stats->dH)) return restore(fail(HMC_ERR_NONFINITE, "dH is not finite"));
     stats->accepted = (u < std::exp(-stats->dH)) ? 1 : 0;
-    stats->status = HMC_OK;
-    if (!stats->accepted) {
-        HIPCHK(hipMemcpyAsync(phi, c->phi_save, phib, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
+    if (!stats->accepted) return restore_phi(c, phi, s);
+    return HMC_OK;
+}
+
+// --------------------------------------------------------------------------------------
+// Warm-up tuning (Eq. 31, Eq. 32): host arithmetic
+
+static double accept_prob(double dH) { return dH <= 0.0 ? 1.0 : std::exp(-dH); }
+
+int hmc_tuner_init(hmc_tuner* t, double eps, int window, double factor, int n_cap) {
+    if (t == nullptr) return fail(HMC_ERR_INVALID_ARG, "tuner is NULL");
+    if (!(eps > 0.0) || !std::isfinite(eps) || window < 1 || !(factor > 1.0) || !std::isfinite(factor) ||
+        n_cap < 1 || n_cap > HMC_TUNER_MAX_LEN)
+        return fail(HMC_ERR_INVALID_ARG, "tuner needs eps > 0, window >= 1, factor > 1, 1 <= n_cap <= %d",
+                    HMC_TUNER_MAX_LEN);
+    std::memset(t, 0, sizeof(*t));
+    t->eps = eps;
+    t->factor = factor;
+    t->window = window;
+    t->n_cap = n_cap;
+    return HMC_OK;
+}
+
+static bool tuner_valid(const hmc_tuner* t) {
+    return t != nullptr && t->eps > 0.0 && std::isfinite(t->eps) && t->window >= 1 && t->factor > 1.0 &&
+           t->n_cap >= 1 && t->n_cap <= HMC_TUNER_MAX_LEN && t->count >= 0 && t->count < t->window;
+}
+
+int hmc_tuner_add_step(hmc_tuner* t, double dH_eps, double dH_half) {
+    if (!tuner_valid(t)) return fail(HMC_ERR_INVALID_ARG, "invalid tuner");
+    if (std::isnan(dH_eps) || std::isnan(dH_half)) return fail(HMC_ERR_INVALID_ARG, "dH is NaN");
+    t->sum_alpha_eps += accept_prob(dH_eps);
+    t->sum_alpha_half += accept_prob(dH_half);
+    t->count += 1;
+    if (t->count >= t->window) {
+        const double ae = t->sum_alpha_eps / t->count, ah = t->sum_alpha_half / t->count;
+        const bool holds = ae > 0.0 && ah * ah <= 2.0 * ae;
+        t->eps = holds ? t->eps * t->factor : t->eps / t->factor;
+        t->count = 0;
+        t->sum_alpha_eps = t->sum_alpha_half = 0.0;
     }
     return HMC_OK;
+}
+
+int hmc_tuner_add_jump(hmc_tuner* t, int n, double sqdist, double dH) {
+    if (!tuner_valid(t)) return fail(HMC_ERR_INVALID_ARG, "invalid tuner");
+    if (n < 1 || n > t->n_cap) return fail(HMC_ERR_INVALID_ARG, "length %d outside [1, %d]", n, t->n_cap);
+    if (!std::isfinite(sqdist) || std::isnan(dH)) return fail(HMC_ERR_INVALID_ARG, "non-finite jump sample");
+    t->esjd_sum[n] += sqdist * accept_prob(dH);
+    t->esjd_count[n] += 1;
+    return HMC_OK;
+}
+
+int hmc_tuner_best_length(const hmc_tuner* t) {
+    if (t == nullptr || t->n_cap < 1 || t->n_cap > HMC_TUNER_MAX_LEN) return 0;
+    int best = 0;
+    double bv = 0.0;
+    for (int n = 1; n <= t->n_cap; ++n) {
+        if (t->esjd_count[n] == 0) continue;
+        const double v = t->esjd_sum[n] / double(t->esjd_count[n]);
+        if (best == 0 || v > bv) {
+            best = n;
+            bv = v;
+        }
+    }
+    return best;
+}
+
+int hmc_jitter(double u, int n_max) {
+    if (n_max < 1 || !(u >= 0.0 && u < 1.0)) return 0;
+    const double k = std::floor(u * double(n_max));
+    return 1 + (k > double(n_max - 1) ? n_max - 1 : int(k));
+}
+
+int hmc_warmup_iteration(hmc_ctx* c, hmc_tuner* t, double* phi, const double* xi, const void* eta, int n_pf,
+                         double u_accept, double u_length, hmc_warmup_stats* out, void* stream) {
+    if (c == nullptr || t == nullptr || phi == nullptr || xi == nullptr || out == nullptr)
+        return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    if (c->is_batch) return fail(HMC_ERR_INVALID_ARG, "warm-up iterations are for one-lattice contexts");
+    if (!tuner_valid(t)) return fail(HMC_ERR_INVALID_ARG, "invalid tuner");
+    int rc = need_ws(c);
+    if (rc) return rc;
+    if (n_pf < 0 || n_pf > c->cap) return fail(HMC_ERR_INVALID_ARG, "n_pf %d outside [0, %d]", n_pf, c->cap);
+    if (n_pf > 0 && eta == nullptr) return fail(HMC_ERR_INVALID_ARG, "eta is NULL");
+    if (!aligned16(phi) || !aligned16(xi) || (eta && !aligned16(eta)))
+        return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
+    const int n = hmc_jitter(u_length, t->n_cap);
+    if (n == 0) return fail(HMC_ERR_INVALID_ARG, "u_length must lie in [0, 1)");
+    hipStream_t s = (hipStream_t)stream;
+    std::memset(out, 0, sizeof(*out));
+    const size_t phib = 3 * size_t(c->vol) * sizeof(double);
+    const double eps = t->eps;
+    const double saved_eps = c->p.eps;
+    const int saved_nl = c->p.n_leap;
+    auto done = [&](int code) {
+        c->p.eps = saved_eps;
+        c->p.n_leap = saved_nl;
+        return code;
+    };
+    // momenta under the metric, kept for all three proposals
+    if (c->sigma != nullptr) rc = metric_passes(c, xi, c->piw, 0, 0.0, MUL_RSQRT, RED_NONE, 1.0, nullptr, 0, s);
+    else rc = hipMemcpyAsync(c->piw, xi, phib, hipMemcpyDeviceToDevice, s) == hipSuccess
+                  ? HMC_OK : fail(HMC_ERR_HIP, "copy failed");
+    if (rc) return done(rc);
+    hmc_traj_stats st[3];
+    const double eps_of[3] = {eps, 0.5 * eps, eps};
+    const int len_of[3] = {1, 1, n};
+    for (int k = 0; k < 3; ++k) {
+        c->p.eps = eps_of[k];
+        c->p.n_leap = len_of[k];
+        rc = traj_propose(c, phi, c->piw, eta, n_pf, &st[k], s);
+        if (rc) return done(rc);
+        out->cg_iterations += st[k].cg_iterations;
+        out->max_true_resid = std::max(out->max_true_resid, st[k].max_true_resid);
+        if (k < 2) {
+            rc = restore_phi(c, phi, s);
+            if (rc) return done(rc);
+        }
+    }
+    // squared jump distance of the proposal: dphi = phi' - phi0 in the (idle) CG residual
+    double* dphi = reinterpret_cast<double*>(c->r64);
+    double sq = 0.0;
+    rc = hipMemcpyAsync(dphi, phi, phib, hipMemcpyDeviceToDevice, s) == hipSuccess ? HMC_OK
+                                                                                : fail(HMC_ERR_HIP, "copy failed");
+    if (!rc) {
+        hipLaunchKernelGGL(k_drift, dim3(elem_grid(3LL * c->phi_sites)), dim3(kBlock), 0, s, dphi,
+                           static_cast<const double*>(c->phi_save), -1.0, int(3 * c->phi_sites));
+        rc = hipGetLastError() == hipSuccess ? HMC_OK : fail(HMC_ERR_HIP, "kernel launch failed");
+    }
+    if (!rc) {
+        if (c->sigma != nullptr) rc = metric_passes(c, dphi, nullptr, 0, 0.0, 0, RED_INV, 1.0, nullptr, SL_TMP, s);
+        else rc = energy(c, dphi, phi, SL_TMP, s);      // slot SL_TMP: |dphi|^2 / 2
+    }
+    if (!rc) rc = read_slot(c, SL_TMP, &sq, s);
+    if (rc) {
+        (void)restore_phi(c, phi, s);
+        return done(rc);
+    }
+    if (c->sigma == nullptr) sq *= 2.0;
+    out->eps = eps;
+    out->dH_eps = st[0].dH;
+    out->dH_half = st[1].dH;
+    out->dH = st[2].dH;
+    out->n_leap = n;
+    out->sqdist = sq;
+    out->accepted = (u_accept < std::exp(-st[2].dH)) ? 1 : 0;
+    if (!out->accepted) {
+        rc = restore_phi(c, phi, s);
+        if (rc) return done(rc);
+    }
+    (void)hmc_tuner_add_jump(t, n, sq, st[2].dH);
+    (void)hmc_tuner_add_step(t, st[0].dH, st[1].dH);
+    out->eps_next = t->eps;
+    return done(HMC_OK);
 }
 
 int hmc_leapfrog(hmc_ctx* c, double* phi, double* pi, const void* chi, int n_pf,
@@ -1643,11 +1964,11 @@ int hmc_leapfrog(hmc_ctx* c, double* phi, double* pi, const void* chi, int n_pf,
     if (!aligned16(phi) || !aligned16(pi) || (chi && !aligned16(chi))) return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     std::memset(stats, 0, sizeof(*stats));
-    rc = energy(c, pi, phi, SL_K0, s);
+    rc = energies(c, pi, phi, SL_K0, s);
     if (rc) return rc;
     rc = md_integrate(c, phi, pi, static_cast<const double2*>(chi), n_pf, true, stats, s);
     if (rc) { stats->status = rc; return rc; }
-    rc = energy(c, pi, phi, SL_K1, s);
+    rc = energies(c, pi, phi, SL_K1, s);
     if (rc) return rc;
     rc = read_slots(c, s);
     if (rc) return rc;

@@ -145,6 +145,57 @@ class HMC:
         self._call("hmc_autotune", _ptr(phi), _ptr(b), n, ctypes.byref(r), _stream())
         return _lib.tune_dict(r)
 
+    # ---------------------------------------------------------------- Fourier metric
+    def set_metric(self, sigma):
+        """Fourier-diagonal metric (hmc_set_metric): sigma is a float64 tensor of phi's shape
+        indexed by frequency, or None for the identity.  The context keeps a reference."""
+        if sigma is not None:
+            self._phi(sigma)
+        check(self.lib.hmc_set_metric(self._ctx, _ptr(sigma) if sigma is not None else None), "hmc_set_metric")
+        self._sigma = sigma
+
+    def metric_momenta(self, xi, out=None):
+        """pi = F(sigma^{-1/2} . F^* xi) for a real standard normal field xi."""
+        self._phi(xi)
+        out = torch.empty_like(xi) if out is None else self._phi(out)
+        self._call("hmc_metric_momenta", _ptr(xi), _ptr(out), _stream())
+        return out
+
+    def metric_kinetic(self, pi):
+        """1/2 pi^T Sigma pi."""
+        self._phi(pi)
+        K = ctypes.c_double(0.0)
+        self._call("hmc_metric_kinetic", _ptr(pi), ctypes.byref(K), _stream())
+        return K.value
+
+    def metric_norm2(self, v):
+        """v^T Sigma^{-1} v (the squared jump distance of Eq. 32 for v = phi' - phi)."""
+        self._phi(v)
+        out = ctypes.c_double(0.0)
+        self._call("hmc_metric_norm2", _ptr(v), ctypes.byref(out), _stream())
+        return out.value
+
+    def metric_accumulate(self, phi, acc):
+        """acc += |F phi|^2 (one term of Eq. 30), in place."""
+        self._phi(phi)
+        self._phi(acc)
+        self._call("hmc_metric_accumulate", _ptr(phi), _ptr(acc), _stream())
+        return acc
+
+    def warmup_iteration(self, tuner, phi, xi, eta, u_accept, u_length):
+        """One warm-up iteration (hmc_warmup_iteration); phi is updated in place and the
+        tuner's state advances.  Returns the stats as a dict."""
+        self._phi(phi)
+        self._phi(xi)
+        n = 0
+        if eta is not None and eta.numel() > 0:
+            eta, n = self._spinors(eta)
+        st = _lib.HmcWarmupStats()
+        self._call("hmc_warmup_iteration", ctypes.byref(tuner.state), _ptr(phi), _ptr(xi),
+                   _ptr(eta) if n else None, n, float(u_accept), float(u_length), ctypes.byref(st),
+                   _stream())
+        return {f: getattr(st, f) for f, _ in _lib.HmcWarmupStats._fields_}
+
     def kernel_times(self):
         """{name: (average ms, samples)} of the sampled CG kernels."""
         kt = _lib.HmcKernelTimes()
@@ -278,6 +329,49 @@ class HMC:
         if code != _lib.HMC_OK:
             check(code, "hmc_trajectory")
         return out
+
+
+class Tuner:
+    """Warm-up state of the step size (Eq. 31) and trajectory length (Eq. 32) rules
+    (hmc_tuner_*); host arithmetic in the library."""
+
+    def __init__(self, eps, window=10, factor=1.2, n_cap=20):
+        self.lib = _lib.load()
+        self.state = _lib.HmcTuner()
+        check(self.lib.hmc_tuner_init(ctypes.byref(self.state), float(eps), int(window), float(factor),
+                                      int(n_cap)), "hmc_tuner_init")
+
+    @property
+    def eps(self):
+        return self.state.eps
+
+    @property
+    def n_cap(self):
+        return self.state.n_cap
+
+    def add_step(self, dH_eps, dH_half):
+        check(self.lib.hmc_tuner_add_step(ctypes.byref(self.state), float(dH_eps), float(dH_half)),
+              "hmc_tuner_add_step")
+        return self.state.eps
+
+    def add_jump(self, n, sqdist, dH):
+        check(self.lib.hmc_tuner_add_jump(ctypes.byref(self.state), int(n), float(sqdist), float(dH)),
+              "hmc_tuner_add_jump")
+
+    def esjd(self, n):
+        c = self.state.esjd_count[n]
+        return self.state.esjd_sum[n] / c if c else None
+
+    def best_length(self):
+        return self.lib.hmc_tuner_best_length(ctypes.byref(self.state)) or None
+
+
+def jitter(u, n_max):
+    """A trajectory length uniform on {1, ..., n_max} from a uniform u in [0, 1)."""
+    n = _lib.load().hmc_jitter(float(u), int(n_max))
+    if n == 0:
+        raise ValueError("jitter needs n_max >= 1 and u in [0, 1)")
+    return n
 
 
 class Batch:

@@ -99,3 +99,14 @@ def batch_inputs(seed, chains, phi_var, n_pf):
         u = float(g.uniform())
         out.append((phi0, pi, etas, u))
     return out
+
+
+def draw_metric_table(g, L, Lt, lo=0.2, hi=2.0, even=True):
+    """A positive table of a boson-shaped field's shape, indexed by frequency (l, n, kx, ky):
+    uniform in [lo, hi], and with even=True averaged with its reflection k -> -k (indices
+    taken mod N_tau and L), the symmetry of a real field's power spectrum."""
+    t = g.uniform(lo, hi, size=(3, Lt, L, L))
+    if not even:
+        return t
+    nt, nx = (-np.arange(Lt)) % Lt, (-np.arange(L)) % L
+    return 0.5 * (t + t[:, nt][:, :, nx][:, :, :, nx])

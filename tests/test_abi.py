@@ -44,15 +44,19 @@ def test_struct_layouts_match_c(tmp_path):
                    'offsetof(hmc_cg_stats, true_resid), offsetof(hmc_traj_stats, max_true_resid), '
                    'sizeof(hmc_tune_result), offsetof(hmc_tune_result, tried_us), '
                    'sizeof(hmc_kernel_times), offsetof(hmc_kernel_times, count));'
+                   'printf("%zu %zu %zu %zu\\n", sizeof(hmc_tuner), offsetof(hmc_tuner, esjd_count), '
+                   'sizeof(hmc_warmup_stats), offsetof(hmc_warmup_stats, max_true_resid));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     P, C, T = _lib.HmcParams, _lib.HmcCgStats, _lib.HmcTrajStats
     U, K = _lib.HmcTuneResult, _lib.HmcKernelTimes
+    Tu, W = _lib.HmcTuner, _lib.HmcWarmupStats
     assert got == [ctypes.sizeof(P), ctypes.sizeof(C), ctypes.sizeof(T), P.cg_tol.offset,
                    C.true_resid.offset, T.max_true_resid.offset, ctypes.sizeof(U),
-                   U.tried_us.offset, ctypes.sizeof(K), K.count.offset]
+                   U.tried_us.offset, ctypes.sizeof(K), K.count.offset,
+                   ctypes.sizeof(Tu), Tu.esjd_count.offset, ctypes.sizeof(W), W.max_true_resid.offset]
 
 
 def test_error_strings():

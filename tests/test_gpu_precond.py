@@ -136,3 +136,31 @@ def test_pcg_rejects_unsupported_lattice(hip):
     from paper_2204_14241_amd._lib import HmcError
     with pytest.raises(HmcError):
         hip.HMC(4, 17, precond="fourier")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pcg_kernel_timing_samples_every_pass(hip, precision):
+    """Sampled kernel timing covers steps A and B and the three preconditioner passes of the
+    same iterations; graph replay takes no samples."""
+    L, Lt = 24, 40
+    say(f"pcg kernel timing {precision} {L}x{L}x{Lt}")
+    g = S.rng(520)
+    phi = dev(S.draw_phi(g, L, Lt, 0.5))
+    b = dev(S.draw_spinor(g, L, Lt, 1))
+    h = hip.HMC(L, Lt, n_pf=1, cg_tol=1e-10, precision=precision, precond="fourier")
+    h.set_kernel_timing(True)
+    _, st = h.cg_solve(phi, b)
+    kt = h.kernel_times()
+    suf = "f32" if precision == "mixed" else "f64"
+    names = [f"cg_a_{suf}", f"cg_b_{suf}", f"pc_xy_fwd_{suf}", f"pc_t_{suf}", f"pc_xy_inv_{suf}"]
+    counts = {kt[n][1] for n in names}
+    say(f"  iterations {st.iterations}; samples {[(n, kt[n]) for n in names]}")
+    assert len(counts) == 1 and counts.pop() >= 1
+    for n in names:
+        assert 0.0 < kt[n][0] < 50.0
+    other = "f64" if suf == "f32" else "f32"
+    assert all(kt[n][1] == 0 for n in kt if n.endswith(other))
+    h.set_kernel_timing(True)
+    h.set_graphs(True)
+    h.cg_solve(phi, b)
+    assert all(v[1] == 0 for v in h.kernel_times().values())
