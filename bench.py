@@ -163,6 +163,49 @@ def cpu_info():
     return model, os.cpu_count()
 
 
+def metric_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, seed, reps=20):
+    """The Fourier-diagonal metric at the workload size: the metric estimated (Eq. 30) from
+    the starting field and the first momenta, the momentum draw and the kinetic energy timed
+    with HIP events, and one mixed-precision warm-up iteration (Eq. 31-32; lengths 1..4)."""
+    import synth_inputs as S
+    dev = torch.device("cuda")
+    out = {}
+    h = hmcmod.HMC(L, Lt, precision="mixed", **common)
+    phi = torch.from_numpy(phi0).to(dev)
+    acc = torch.zeros_like(phi)
+    h.metric_accumulate(phi, acc)
+    h.metric_accumulate(d_traj[0][0], acc)
+    sigma = acc / 2
+    h.set_metric(sigma)
+    xi = torch.from_numpy(S.draw_momentum(S.rng(seed + 7), L, Lt)).to(dev)
+    pi = torch.empty_like(xi)
+    vol = Lt * L * L
+    for name, fn, bps in (("momenta", lambda: h.metric_momenta(xi, out=pi), 264),
+                          ("kinetic", lambda: h.metric_kinetic(pi), 144)):
+        fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        ms = sorted(a.elapsed_time(b) for a, b in ev)[reps // 2]
+        out[name] = {"ms": ms, "bytes_per_site": bps, "GB/s": bps * vol / (ms * 1e-3) / 1e9}
+        log(f"metric {name}: {ms:.3f} ms, {out[name]['GB/s']:.0f} GB/s")
+    tuner = hmcmod.Tuner(common["eps"], window=2, factor=1.2, n_cap=4)
+    p, e, u = d_traj[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = h.warmup_iteration(tuner, phi, xi, e, u, 0.6)
+    torch.cuda.synchronize()
+    out["warmup_iteration"] = {"s": time.perf_counter() - t0, "n_leap": st["n_leap"], "dH_eps": st["dH_eps"],
+                               "dH_half": st["dH_half"], "dH": st["dH"], "sqdist": st["sqdist"],
+                               "cg_iterations": st["cg_iterations"], "accepted": st["accepted"]}
+    log(f"warm-up iteration: {out['warmup_iteration']['s']:.2f} s, n_leap {st['n_leap']}, dH {st['dH']:.4g}")
+    h.close()
+    return out
+
+
 def apply_bench(hmcmod, torch, L, Lt, f32, reps, seed):
     """Isolated two-pass M^dagger M: M then M^dagger through the C ABI, buffer sets rotated
     so their combined footprint exceeds 512 MB.  Returns (applies/s, GB/s, ms/apply)."""
@@ -490,6 +533,7 @@ def main():
             extras["dH_fp64"] = [o["dH"] for o in out64]
             extras["mixed_vs_fp64_traj_speedup"] = extras["traj_per_hour_mixed"] / extras["traj_per_hour_fp64"]
         extras["pcg_80x80x200"] = pcg_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, W, args.pcg_steps)
+        extras["metric_80x80x200"] = metric_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, args.seed)
         for f32 in (True, False):
             aps, gbs, ms, nsets = apply_bench(hmcmod, torch, L, Lt, f32, args.apply_reps, args.seed + 1)
             extras["mdagm_apply_" + ("f32" if f32 else "f64")] = {

@@ -54,8 +54,9 @@ extern "C" {
 
 #define HMC_PRECOND_NONE    0      /* plain CG on M^dagger M                             */
 #define HMC_PRECOND_FOURIER 1      /* CG preconditioned with P = (K K^dagger)^{-1}, K the
-                                      phi-independent part of M, applied by twisted FFTs
-                                      (Methods C, Eq. 23-26)                             */
+                                      phi-independent part of M (Methods C, Eq. 23-26):
+                                      (x, y) FFTs, and along tau the exact inverse of K
+                                      per frequency (what the twisted tau FFT diagonalises) */
 
 /* Model and run parameters.  Eq. (17) for the fermion terms, Eq. (2) for the boson. */
 typedef struct hmc_params {
@@ -73,9 +74,10 @@ typedef struct hmc_params {
     int    reliable_every; /* mixed precision: FP64 reliable update every k iterations    */
     int    max_rhs;      /* right-hand sides the workspace is sized for (0: n_pf)        */
     int    precond;      /* HMC_PRECOND_NONE or HMC_PRECOND_FOURIER.  The Fourier form
-                            needs L and L_tau whose prime factors are <= 7 and an L x L
+                            needs L and L_tau whose prime factors are <= 7, an L x L
                             slice (FP64 in FP64 solves) that fits the GPU's LDS
-                            (L <= 100 on gfx950); otherwise HMC_ERR_INVALID_ARG          */
+                            (L <= 100 on gfx950) and L_tau <= 320 (mixed) or 256 (FP64);
+                            otherwise HMC_ERR_INVALID_ARG                                */
 } hmc_params;
 
 /* Per-solve statistics (host struct filled by the solver entry points). */

@@ -45,8 +45,9 @@ int hmc_test_fft_freq(int n, int pos);
 
 /* The Fourier preconditioner P = (K K^dagger)^{-1} of Methods C (Eq. 26) applied on the host
  * in FP64 to one spinor (complex128, [4][L_tau][L][L]) by the same three passes the kernels
- * run (2-D transforms per slice, twisted tau transform with the symbol, inverse 2-D).  rz
- * (optional) receives <in, P in> from the Fourier-space sum.  Returns 0 or -1. */
+ * run (2-D transforms per slice; per frequency column the two tau recurrences, chunked as the
+ * FP64 kernel chunks them; inverse 2-D).  rz (optional) receives <in, P in> = sum |K^{-1} r|^2.
+ * Returns 0, or -1 for a lattice the preconditioner does not support. */
 int hmc_test_precond(int L, int L_tau, double dtau, const hmc_params* params, const double* in,
                      double* out, double* rz);
 

@@ -287,97 +287,22 @@ __host__ __device__ inline int fft_max_radix(const FftPlan& pl) {
     return m;
 }
 
-// Symbol 1/|K_hat|^2 of the preconditioner for one band, from b and sin^2(w_n / 2).
-__host__ __device__ __forceinline__ double pc_symbol(double b, double s2) {
-    const double d = 1.0 - b;
-    return 1.0 / (d * d + 4.0 * b * s2);
-}
-
-// Per-lattice tables, computed once on the host in FP64 (pc_table_blob) and read by every pass:
+// Per-lattice tables, computed once on the host in FP64 (pc_table_blob) and read by the
+// passes of the preconditioner and of the metric:
 //   twl[j]   = exp(-2 pi i j / L)          FFT twiddles of length L
 //   twT[j]   = exp(-2 pi i j / N_tau)      FFT twiddles of length N_tau
-//   twt[tau] = exp(-i pi tau / N_tau)      the conjugate twist
-//   s2[p]    = sin^2(w_n / 2) for the frequency n held at tau-position p
 //   cosx[p]  = cos(2 pi k / L) for the frequency k held at x (or y) position p
-template <typename R>
-struct PcTables {
-    C2<R>* twt;
-    double* s2;
-    double* cosx;
-    C2<R>* twl;
-    C2<R>* twT;
-    double* bcol;  // scratch: b of each column of the group being processed
-};
-
-// Offsets (in doubles) of the tables in the flat blob: twl, twT, twt (complex), s2, cosx.
+// Offsets (in doubles) of the tables in the flat blob.
 struct PcBlob {
-    int twl, twT, twt, s2, cosx, size;
+    int twl, twT, cosx, size;
 };
 __host__ __device__ __forceinline__ PcBlob pc_blob_layout(int L, int Lt) {
     PcBlob b;
     b.twl = 0;
     b.twT = 2 * L;
-    b.twt = b.twT + 2 * Lt;
-    b.s2 = b.twt + 2 * Lt;
-    b.cosx = b.s2 + Lt;
+    b.cosx = b.twT + 2 * Lt;
     b.size = b.cosx + L;
     return b;
-}
-
-// The tau pass on one group of `ncol` (x, y) columns of one component of band `band`, held in
-// buf as [N_tau][ncol] (column j at buf + j, stride ncol), starting at xy-position col0.
-// Input: the (x, y)-transformed field; output: the same after twist, tau transform, symbol,
-// inverse tau transform and untwist, scaled by 1 / (N_tau L^2).  Returns the workgroup's share
-// of <r, P r> = (1 / N) sum |Y|^2 / |K_hat|^2 (Parseval), valid in every thread's own terms
-// (the caller reduces).  pc_tau_core is the part between the twists (the kernels apply the
-// twists while staging the columns through LDS).
-template <typename R, int MAXR = 7, class Ex>
-__host__ __device__ __forceinline__ double pc_tau_core(const Ex& ex, C2<R>* buf, int ncol, int col0, int band,
-                                                       const PcTables<R>& t, const FftPlan& pt, const FftPlan& pl,
-                                                       const Coef<double>& cf64) {
-    const int Lt = pt.n, L = pl.n;
-    const double inv_n = 1.0 / (double(Lt) * double(L) * double(L));
-    FastDiv dc, dL;
-    dc.init(uint32_t(ncol));
-    dL.init(uint32_t(L));
-    // b = 1 + dtau (mu + 2 t_x cos kx + 2 t_y cos ky) per column (diag = -1 - dtau mu, hop = -dtau t)
-    ex.for_each(ncol, [&](int j) {
-        const int col = col0 + j;
-        const int px = int(dL.div(uint32_t(col))), py = col - px * L;
-        t.bcol[j] = -cf64.diag[band] - 2.0 * (cf64.hop[band][0] * t.cosx[px] + cf64.hop[band][1] * t.cosx[py]);
-    });
-    fft_lines<R, false, MAXR>(ex, buf, ncol, 1, ncol, pt, t.twT);
-    const double part = ex.sum_each(Lt * ncol, [&](int i) {
-        const int p = int(dc.div(uint32_t(i))), j = i - p * ncol;
-        const double w = pc_symbol(t.bcol[j], t.s2[p]) * inv_n;
-        const C2<R> y = buf[i];
-        buf[i] = scl<R>(R(w), y);
-        return w * double(norm2<R>(y));
-    });
-    ex.sync();
-    fft_lines<R, true, MAXR>(ex, buf, ncol, 1, ncol, pt, t.twT);
-    return part;
-}
-
-template <typename R, int MAXR = 7, class Ex>
-__host__ __device__ __forceinline__ double pc_tau_pass(const Ex& ex, C2<R>* buf, int ncol, int col0, int band,
-                                                       const PcTables<R>& t, const FftPlan& pt, const FftPlan& pl,
-                                                       const Coef<double>& cf64) {
-    const int Lt = pt.n;
-    FastDiv dc;
-    dc.init(uint32_t(ncol));
-    ex.for_each(Lt * ncol, [&](int i) {
-        const int tau = int(dc.div(uint32_t(i)));
-        buf[i] = cmul<R>(buf[i], t.twt[tau]);
-    });
-    ex.sync();
-    const double part = pc_tau_core<R, MAXR>(ex, buf, ncol, col0, band, t, pt, pl, cf64);
-    ex.for_each(Lt * ncol, [&](int i) {
-        const int tau = int(dc.div(uint32_t(i)));
-        buf[i] = cmulc<R>(buf[i], t.twt[tau]);
-    });
-    ex.sync();
-    return part;
 }
 
 }  // namespace hmc

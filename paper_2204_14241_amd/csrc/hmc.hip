@@ -25,6 +25,7 @@
 #include "../../include/hmc_testing.h"
 #include "fft.h"
 #include "kernels.h"
+#include "precond.h"
 #include "metric.h"
 #include "lattice.h"
 
@@ -138,6 +139,7 @@ struct hmc_ctx {
                                       // this GPU [FP64, FP32]
     size_t lds_xy[2] = {0, 0}; // dynamic LDS of the preconditioner passes [FP64, FP32]
     size_t lds_t[2] = {0, 0};
+    int pc_q[2] = {0, 0};      // chunks per column of the tau pass [FP64, FP32]
     long long blob_doubles = 0;    // preconditioner tables of all lattices
     bool pc_r7 = false;            // some lattice extent needs radix-7 FFT stages
     // Fourier-diagonal HMC metric (one lattice): the caller's sigma table (null: identity,
@@ -226,11 +228,6 @@ static std::vector<double> pc_table_blob(const FftPlan& pl, const FftPlan& pt) {
         const double2 w = twiddle_host(j, Lt);
         v[size_t(b.twT + 2 * j)] = w.x;
         v[size_t(b.twT + 2 * j + 1)] = w.y;
-        const double a = -M_PI * double(j) / double(Lt);
-        v[size_t(b.twt + 2 * j)] = std::cos(a);
-        v[size_t(b.twt + 2 * j + 1)] = std::sin(a);
-        const double sh = std::sin(M_PI * double(2 * fft_freq(pt, j) + 1) / double(2 * Lt));
-        v[size_t(b.s2 + j)] = sh * sh;
     }
     return v;
 }
@@ -387,7 +384,7 @@ static int clamp_bpr(int ntiles2, int max_bpr) { return ntiles2 < max_bpr ? ntil
 // Partial slots a unit needs per kind: the most workgroups any kernel runs on it (the CG steps,
 // at most kMaxBpr; the preconditioner's tau pass, 4 column groups per FP64 group width).
 static int unit_slots(const Lat& l) {
-    return std::max(clamp_bpr(tiles2_host(l.vol), kMaxBpr), 4 * pc_groups(l.LL, pc_ncol<double>()));
+    return std::max(clamp_bpr(tiles2_host(l.vol), kMaxBpr), 4 * pc_groups(l.LL, kPcCols));
 }
 
 // Batch: (re)write the unit and block tables of one precision's launch shape.
@@ -464,6 +461,7 @@ struct Launch {
     Geo cg, pxy, pt;
     int ncg = 0, npxy = 0, npt = 0;
     size_t lds_xy = 0, lds_t = 0;
+    int pt_threads = 0;   // tau-pass workgroup size (64 columns x chunks per column)
     bool pc = false;
     bool r7 = false;      // some lattice extent has a factor 7 (radix-7 FFT stages)
 };
@@ -476,13 +474,14 @@ static Launch<GeoOne> launch_one(const hmc_ctx* c, int n) {
     l.cg = geo_one(c, bpr);
     l.ncg = bpr * n;
     l.pc = c->p.precond == HMC_PRECOND_FOURIER && c->pc_ok[pi];
-    const int nxy = 4 * c->Lt, nt = 4 * pc_groups(c->lat.LL, pc_ncol<R>());
+    const int nxy = 4 * c->Lt, nt = 4 * pc_groups(c->lat.LL, kPcCols);
     l.pxy = GeoOne{c->lat, bpr, nxy, c->pstride};
     l.pt = GeoOne{c->lat, bpr, nt, c->pstride};
     l.npxy = nxy * n;
     l.npt = nt * n;
     l.lds_xy = c->lds_xy[pi];
     l.lds_t = c->lds_t[pi];
+    l.pt_threads = kPcCols * c->pc_q[pi];
     l.r7 = c->pc_r7;
     return l;
 }
@@ -500,6 +499,7 @@ static Launch<GeoBatch> launch_batch(const hmc_ctx* c) {
     l.npt = c->bi.ngroups[pi];
     l.lds_xy = c->lds_xy[pi];
     l.lds_t = c->lds_t[pi];
+    l.pt_threads = kPcCols * c->pc_q[pi];
     l.r7 = c->pc_r7;
     return l;
 }
@@ -556,7 +556,7 @@ static int enqueue_pc_r(hmc_ctx* c, const Launch<Geo>& lc, const CgVecs<R>& v, i
     launch_timed(k_pc_xy<R, false, Geo, MAXR>, lc.npxy, kPcBlock, lc.lds_xy, s, e, 0,
                  next_ctl(c, expect1), lc.pxy, v.r, v.z, c->blob);
     LAUNCHCHK();
-    launch_timed(k_pc_t<R, Geo, MAXR>, lc.npt, kPcBlock, lc.lds_t, s, e, 1,
+    launch_timed(k_pc_t<R, Geo>, lc.npt, lc.pt_threads, lc.lds_t, s, e, 1,
                  next_ctl(c, PEND_NONE), lc.pt, v.z, c->blob, c->cf64);
     LAUNCHCHK();
     launch_timed(k_pc_xy<R, true, Geo, MAXR>, lc.npxy, kPcBlock, lc.lds_xy, s, e, 2,
@@ -1051,7 +1051,7 @@ static void pc_setup(hmc_ctx* c) {
     c->bi.pcoff.assign(1, 0);
     c->bi.nslices = 0;
     c->bi.ngroups[0] = c->bi.ngroups[1] = 0;
-    for (int pi = 0; pi < 2; ++pi) c->lds_xy[pi] = c->lds_t[pi] = 0;
+    for (int pi = 0; pi < 2; ++pi) c->lds_xy[pi] = c->lds_t[pi] = 0, c->pc_q[pi] = 0;
     for (const Lat& l : lats) {
         FftPlan pa, pb;
         const bool ok = make_fft_plan(l.L, pa) && make_fft_plan(l.Lt, pb);
@@ -1061,19 +1061,21 @@ static void pc_setup(hmc_ctx* c) {
         c->bi.pcoff.push_back(blob);
         const int nrhs = c->is_batch ? c->bi.nrhs : 1;
         c->bi.nslices += 4 * l.Lt * nrhs;
-        c->bi.ngroups[0] += 4 * pc_groups(l.LL, pc_ncol<double>()) * nrhs;
-        c->bi.ngroups[1] += 4 * pc_groups(l.LL, pc_ncol<float>()) * nrhs;
+        c->bi.ngroups[0] += 4 * pc_groups(l.LL, kPcCols) * nrhs;
+        c->bi.ngroups[1] += 4 * pc_groups(l.LL, kPcCols) * nrhs;
         const size_t c64 = sizeof(double2), c32 = sizeof(float2);
         c->lds_xy[0] = std::max(c->lds_xy[0], size_t(l.LL + l.L) * c64);
         c->lds_xy[1] = std::max(c->lds_xy[1], size_t(l.LL + l.L) * c32);
-        c->lds_t[0] = std::max(c->lds_t[0], size_t(l.Lt * pc_ncol<double>() + 2 * l.Lt) * c64 +
-                                                size_t(l.Lt + l.L + pc_ncol<double>()) * 8);
-        c->lds_t[1] = std::max(c->lds_t[1], size_t(l.Lt * pc_ncol<float>() + 2 * l.Lt) * c32 +
-                                                size_t(l.Lt + l.L + pc_ncol<float>()) * 8);
+        const int q64 = pc_chunks<double>(l.Lt), q32 = pc_chunks<float>(l.Lt);
+        c->pc_q[0] = (q64 == 0 || c->pc_q[0] < 0) ? -1 : std::max(c->pc_q[0], q64);
+        c->pc_q[1] = (q32 == 0 || c->pc_q[1] < 0) ? -1 : std::max(c->pc_q[1], q32);
     }
     c->blob_doubles = blob;
+    c->lds_t[0] = c->pc_q[0] > 0 ? pc_tau_lds<double>(c->pc_q[0]) : 0;
+    c->lds_t[1] = c->pc_q[1] > 0 ? pc_tau_lds<float>(c->pc_q[1]) : 0;
     for (int pi = 0; pi < 2; ++pi)
-        c->pc_ok[pi] = plans && c->lds_xy[pi] <= size_t(maxlds) && c->lds_t[pi] <= size_t(maxlds);
+        c->pc_ok[pi] = plans && c->pc_q[pi] > 0 && c->lds_xy[pi] <= size_t(maxlds) &&
+                       c->lds_t[pi] <= size_t(maxlds);
     if (!c->is_batch) {
         const Lat& l = c->lat;
         c->lds_mt_t = size_t(l.Lt) * (pc_ncol<double>() + 1) * sizeof(double2) + size_t(l.Lt + l.L) * sizeof(int);
@@ -1095,7 +1097,7 @@ static void pc_lds_attributes_r(size_t xy, size_t t) {
     const hipFuncAttribute a = hipFuncAttributeMaxDynamicSharedMemorySize;
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pc_xy<R, false, Geo, MAXR>), a, int(xy));
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pc_xy<R, true, Geo, MAXR>), a, int(xy));
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pc_t<R, Geo, MAXR>), a, int(t));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pc_t<R, Geo>), a, int(t));
 }
 
 template <class Geo>
@@ -1132,8 +1134,8 @@ static int upload_pc(hmc_ctx* c) {
             for (int k = 0; k < b.nrhs; ++k) {
                 const int u = ch * b.nrhs + k;
                 for (int r = 0; r < 4 * l.Lt; ++r) xy.push_back(make_int2(u, r));
-                for (int r = 0; r < 4 * pc_groups(l.LL, pc_ncol<double>()); ++r) t[0].push_back(make_int2(u, r));
-                for (int r = 0; r < 4 * pc_groups(l.LL, pc_ncol<float>()); ++r) t[1].push_back(make_int2(u, r));
+                for (int r = 0; r < 4 * pc_groups(l.LL, kPcCols); ++r) t[0].push_back(make_int2(u, r));
+                for (int r = 0; r < 4 * pc_groups(l.LL, kPcCols); ++r) t[1].push_back(make_int2(u, r));
             }
         }
         HIPCHK(hipMemcpy(b.pxy_blocks, xy.data(), sizeof(int2) * xy.size(), hipMemcpyHostToDevice));
@@ -1398,36 +1400,55 @@ int hmc_test_fft_freq(int n, int pos) {
 int hmc_test_precond(int L, int Lt, double dtau, const hmc_params* params, const double* in, double* out,
                      double* rz) {
     FftPlan pl, pt;
+    constexpr int MC = pc_chunk_max<double>();
+    const int Q = pc_chunks<double>(Lt);
     if (params == nullptr || in == nullptr || out == nullptr || !geometry_ok(L, Lt) ||
-        !make_fft_plan(L, pl) || !make_fft_plan(Lt, pt))
+        !make_fft_plan(L, pl) || !make_fft_plan(Lt, pt) || Q == 0)
         return -1;
     const Coef<double> cf = coef64_of(dtau, *params);
     const int LL = L * L, vol = Lt * LL;
     std::vector<double2> w(size_t(4) * vol);
     for (size_t i = 0; i < w.size(); ++i) w[i] = make_double2(in[2 * i], in[2 * i + 1]);
-    std::vector<double> blob = pc_table_blob(pl, pt);
+    const std::vector<double> blob = pc_table_blob(pl, pt);
     const PcBlob bl = pc_blob_layout(L, Lt);
-    double* B = blob.data();
-    std::vector<double> bcol(16);
-    const PcTables<double> t{reinterpret_cast<double2*>(B + bl.twt), B + bl.s2, B + bl.cosx,
-                             reinterpret_cast<double2*>(B + bl.twl), reinterpret_cast<double2*>(B + bl.twT),
-                             bcol.data()};
-    const double2* twl = t.twl;
+    const double2* twl = reinterpret_cast<const double2*>(blob.data() + bl.twl);
     const ExHost ex;
     for (int sl = 0; sl < 4 * Lt; ++sl) fft_slice<double, false>(ex, w.data() + size_t(sl) * LL, pl, twl);
-    const int ncol_max = 16;          // columns per tau-pass group (any positive count works)
-    std::vector<double2> buf(size_t(Lt) * ncol_max);
+    // the tau pass as the kernel runs it: Q chunks per column, each reduced to an affine map,
+    // the maps closed around the cycle, the chunks rerun from their entering values
+    const int m = (Lt + Q - 1) / Q;
     double acc = 0.0;
     for (int c = 0; c < 4; ++c) {
-        for (int col0 = 0; col0 < LL; col0 += ncol_max) {
-            const int ncol = std::min(ncol_max, LL - col0);
-            for (int tau = 0; tau < Lt; ++tau)
-                for (int j = 0; j < ncol; ++j)
-                    buf[size_t(tau) * ncol + j] = w[size_t(c) * vol + size_t(tau) * LL + col0 + j];
-            acc += pc_tau_pass<double>(ex, buf.data(), ncol, col0, c >> 1, t, pt, pl, cf);
-            for (int tau = 0; tau < Lt; ++tau)
-                for (int j = 0; j < ncol; ++j)
-                    w[size_t(c) * vol + size_t(tau) * LL + col0 + j] = buf[size_t(tau) * ncol + j];
+        for (int col = 0; col < LL; ++col) {
+            const double b = pc_column_b(col, L, c >> 1, blob.data() + bl.cosx, cf), ib = 1.0 / b;
+            const bool small = b <= 1.0 && b >= -1.0;
+            constexpr int QM = pc_max_chunks<double>();
+            double2 ch[QM][MC], sc[QM], sx[QM + 1];
+            double sa[QM];
+            int t0[QM], n[QM];
+            const bool rev = !small;   // chunks held in the order K^{-1} walks them
+            auto at = [&](int q, int j) { return size_t(c) * vol + size_t(t0[q] + (rev ? n[q] - 1 - j : j)) * LL + col; };
+            for (int q = 0; q < Q; ++q) {
+                t0[q] = std::min(q * m, Lt);
+                n[q] = std::min(m, Lt - t0[q]);
+                for (int j = 0; j < MC; ++j) ch[q][j] = j < n[q] ? w[at(q, j)] : make_double2(0.0, 0.0);
+            }
+            const SignK sk{Lt};
+            const SignKd skd{};
+            for (int q = 0; q < Q; ++q)
+                chunk_map<double, MC, true>(ch[q], n[q], t0[q], rev, b, ib, sk, small, sa[q], sc[q]);
+            chunk_close<double>(sa, sc, sx, Q, 1, small);
+            for (int q = 0; q < Q; ++q) {
+                chunk_apply<double, MC, true>(ch[q], n[q], t0[q], rev, b, ib, sk, small, sx[small ? q : q + 1]);
+                for (int j = 0; j < n[q]; ++j) acc += (ch[q][j].x * ch[q][j].x + ch[q][j].y * ch[q][j].y) / LL;
+            }
+            for (int q = 0; q < Q; ++q)
+                chunk_map<double, MC, false>(ch[q], n[q], t0[q], rev, b, ib, skd, small, sa[q], sc[q]);
+            chunk_close<double>(sa, sc, sx, Q, 1, !small);
+            for (int q = 0; q < Q; ++q) {
+                chunk_apply<double, MC, false>(ch[q], n[q], t0[q], rev, b, ib, skd, small, sx[small ? q + 1 : q]);
+                for (int j = 0; j < n[q]; ++j) w[at(q, j)] = make_double2(ch[q][j].x / LL, ch[q][j].y / LL);
+            }
         }
     }
     for (int sl = 0; sl < 4 * Lt; ++sl) fft_slice<double, true>(ex, w.data() + size_t(sl) * LL, pl, twl);

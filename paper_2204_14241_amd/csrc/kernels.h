@@ -19,7 +19,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "fft.h"
 #include "lattice.h"
 
 namespace hmc {
@@ -903,224 +902,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_b2(CgCtl ctl, Geo geo, CgVecs<flo
     }
     store_partial(ctl, PEND_RR, pos, part);
     if (threadIdx.x == 0) cg_shared().pending = PEND_RR;
-    cg_publish(ctl, pos);
-}
-
-// ------------------------------------------------------------------------------------
-// Fourier preconditioner passes (Methods C, Eq. 26; transforms and symbol in fft.h), run for
-// the units whose residual has just changed, producing z = P r:
-//   pass 1 (k_pc_xy, forward): 2-D (x, y) transform of one (component, tau) slice, r -> z;
-//   pass 2 (k_pc_t): one group of (x, y) columns of one component: twist, tau transform,
-//          symbol, inverse tau transform, untwist, in place on z; partial <r, z> by Parseval;
-//   pass 3 (k_pc_xy, inverse): inverse 2-D transform of one slice, in place on z.
-// Pass 1 consumes the new residual norm (or the first |b|^2, or a true residual), pass 3 the
-// <r, z> partials of pass 2.  Each pass keeps its line set in LDS (dynamic shared memory the
-// host sizes per lattice).
-template <typename R>
-__host__ __device__ constexpr int pc_ncol() { return int(256 / sizeof(C2<R>)); }   // 32 FP32, 16 FP64
-
-__host__ __device__ __forceinline__ int pc_groups(int LL, int ncol) { return (LL + ncol - 1) / ncol; }
-
-// Workgroup size of the preconditioner passes: a slice or column group is one workgroup's LDS,
-// and only a few fit a CU, so each gets more threads (more loads in flight, shorter FFT phase).
-constexpr int kPcBlock = 512;
-
-// Stage n complex elements between global memory and LDS: element i of the set lives at g(i)
-// in global memory and at lds[i].  Up to 64 bytes of loads are in flight per thread before
-// their LDS writes (a plain loop would wait out the memory latency once per element).  The
-// components are kept in separate arrays so that they stay in registers.
-template <typename R, class G>
-__device__ __forceinline__ void stage_in(C2<R>* __restrict__ lds, int n, G g) {
-    constexpr int U = sizeof(R) == 4 ? 8 : 4;
-    const int nt = blockDim.x;
-    for (int i0 = threadIdx.x; i0 < n; i0 += nt * U) {
-        R vx[U], vy[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * nt;
-            if (i < n) {
-                const C2<R> v = *g(i);
-                vx[u] = v.x;
-                vy[u] = v.y;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * nt;
-            if (i < n) lds[i] = mk<R>(vx[u], vy[u]);
-        }
-    }
-}
-// As stage_in / stage_out with a value on the way: v(i, x) transforms element i.
-template <typename R, class G, class V>
-__device__ __forceinline__ void stage_in_v(C2<R>* __restrict__ lds, int n, G g, V v) {
-    constexpr int U = sizeof(R) == 4 ? 8 : 4;
-    const int nt = blockDim.x;
-    for (int i0 = threadIdx.x; i0 < n; i0 += nt * U) {
-        R vx[U], vy[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * nt;
-            if (i < n) {
-                const C2<R> a = *g(i);
-                vx[u] = a.x;
-                vy[u] = a.y;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * nt;
-            if (i < n) lds[i] = v(i, mk<R>(vx[u], vy[u]));
-        }
-    }
-}
-template <typename R, class G, class V>
-__device__ __forceinline__ void stage_out_v(const C2<R>* __restrict__ lds, int n, G g, V v) {
-    constexpr int U = sizeof(R) == 4 ? 8 : 4;
-    const int nt = blockDim.x;
-    for (int i0 = threadIdx.x; i0 < n; i0 += nt * U) {
-        R vx[U], vy[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * nt;
-            if (i < n) {
-                const C2<R> a = v(i, lds[i]);
-                vx[u] = a.x;
-                vy[u] = a.y;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * nt;
-            if (i < n) *g(i) = mk<R>(vx[u], vy[u]);
-        }
-    }
-}
-
-template <typename R, class G>
-__device__ __forceinline__ void stage_out(const C2<R>* __restrict__ lds, int n, G g) {
-    constexpr int U = sizeof(R) == 4 ? 8 : 4;
-    const int nt = blockDim.x;
-    for (int i0 = threadIdx.x; i0 < n; i0 += nt * U) {
-        R vx[U], vy[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * nt;
-            if (i < n) {
-                const C2<R> v = lds[i];
-                vx[u] = v.x;
-                vy[u] = v.y;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * nt;
-            if (i < n) *g(i) = mk<R>(vx[u], vy[u]);
-        }
-    }
-}
-
-template <typename R, bool INV, class Geo, int MAXR>
-__global__ __launch_bounds__(kPcBlock) void k_pc_xy(CgCtl ctl, Geo geo, const C2<R>* src, C2<R>* dst,
-                                                  const double* __restrict__ blob) {
-    extern __shared__ __align__(16) unsigned char pc_smem[];
-    const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
-    const Lat& lat = pos.lat;
-    const int L = lat.L, LL = lat.LL;
-    const int nparts = INV ? 4 * pc_groups(LL, pc_ncol<R>()) : pos.bpr;
-    const int got = cg_finalize(ctl, pos, nparts);
-    CgState& S = cg_shared();
-    const bool work = S.pc && S.mode == CG_ACTIVE &&
-                      (INV ? got == PEND_RZ : (got == PEND_RR || got == PEND_RU || got == PEND_BB));
-    if (!work) {
-        cg_publish(ctl, pos);
-        return;
-    }
-    if (!INV && threadIdx.x == 0) S.zstage = 1;
-    C2<R>* buf = reinterpret_cast<C2<R>*>(pc_smem);
-    C2<R>* tw = buf + LL;
-    const PcBlob bl = pc_blob_layout(L, lat.Lt);
-    const double* B = blob + pos.pcoff;
-    for (int i = threadIdx.x; i < L; i += kPcBlock) tw[i] = mk<R>(R(B[bl.twl + 2 * i]), R(B[bl.twl + 2 * i + 1]));
-    const int c = pos.blk / lat.Lt, tau = pos.blk - c * lat.Lt;
-    const size_t o = pos.voff + size_t(c) * lat.vol + size_t(tau) * LL;
-    __shared__ FftPlan pl;
-    if (threadIdx.x == 0) make_fft_plan(L, pl);
-    stage_in<R>(buf, LL, [&](int i) { return src + o + i; });
-    __syncthreads();
-    fft_slice<R, INV, MAXR>(ExDevice(), buf, pl, tw);
-    stage_out<R>(buf, LL, [&](int i) { return dst + o + i; });
-    cg_publish(ctl, pos);
-}
-
-template <typename R, class Geo, int MAXR>
-__global__ __launch_bounds__(kPcBlock) void k_pc_t(CgCtl ctl, Geo geo, C2<R>* z, const double* __restrict__ blob,
-                                                 Coef<double> cf) {
-    extern __shared__ __align__(16) unsigned char pc_smem[];
-    const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
-    const Lat& lat = pos.lat;
-    const int L = lat.L, Lt = lat.Lt, LL = lat.LL;
-    cg_finalize(ctl, pos, 0);
-    CgState& S = cg_shared();
-    const bool work = S.pc && S.mode == CG_ACTIVE && S.zstage == 1;
-    if (!work) {
-        cg_publish(ctl, pos);
-        return;
-    }
-    constexpr int NC = pc_ncol<R>();
-    const int ng = pc_groups(LL, NC);
-    const int c = pos.blk / ng, g = pos.blk - c * ng;
-    const int col0 = g * NC, ncol = min(NC, LL - col0);
-    C2<R>* buf = reinterpret_cast<C2<R>*>(pc_smem);
-    C2<R>* twT = buf + Lt * NC;
-    C2<R>* twt = twT + Lt;
-    double* s2 = reinterpret_cast<double*>(twt + Lt);
-    double* cosx = s2 + Lt;
-    double* bcol = cosx + L;
-    const PcBlob bl = pc_blob_layout(L, Lt);
-    const double* B = blob + pos.pcoff;
-    for (int i = threadIdx.x; i < Lt; i += kPcBlock) {
-        twT[i] = mk<R>(R(B[bl.twT + 2 * i]), R(B[bl.twT + 2 * i + 1]));
-        s2[i] = B[bl.s2 + i];
-    }
-    for (int i = threadIdx.x; i < L; i += kPcBlock) cosx[i] = B[bl.cosx + i];
-    const size_t o = pos.voff + size_t(c) * lat.vol + size_t(col0);
-    FastDiv dc;
-    dc.init(uint32_t(ncol));
-    // the twist exp(-i pi tau / N_tau) on the way in, its conjugate on the way out (the table
-    // entries are read from global memory, where they stay cached)
-    const C2<double>* twg = reinterpret_cast<const C2<double>*>(B + bl.twt);
-    stage_in_v<R>(
-        buf, Lt * ncol,
-        [&](int i) {
-            const int tau = int(dc.div(uint32_t(i)));
-            return z + o + size_t(tau) * LL + (i - tau * ncol);
-        },
-        [&](int i, C2<R> a) {
-            const C2<double> w = twg[dc.div(uint32_t(i))];
-            return cmul<R>(a, mk<R>(R(w.x), R(w.y)));
-        });
-    __shared__ FftPlan pt, pl;
-    if (threadIdx.x == 0) make_fft_plan(Lt, pt);
-    if (threadIdx.x == 1) make_fft_plan(L, pl);
-    __syncthreads();
-    const PcTables<R> T{twt, s2, cosx, nullptr, twT, bcol};
-    const double part = pc_tau_core<R, MAXR>(ExDevice(), buf, ncol, col0, c >> 1, T, pt, pl, cf);
-    stage_out_v<R>(
-        buf, Lt * ncol,
-        [&](int i) {
-            const int tau = int(dc.div(uint32_t(i)));
-            return z + o + size_t(tau) * LL + (i - tau * ncol);
-        },
-        [&](int i, C2<R> a) {
-            const C2<double> w = twg[dc.div(uint32_t(i))];
-            return cmulc<R>(a, mk<R>(R(w.x), R(w.y)));
-        });
-    store_partial(ctl, PEND_RZ, pos, part);
-    if (threadIdx.x == 0) {
-        S.zstage = 2;
-        S.pending = PEND_RZ;
-    }
     cg_publish(ctl, pos);
 }
 

@@ -12,7 +12,7 @@
 // or adds the real part.
 #pragma once
 
-#include "kernels.h"
+#include "precond.h"
 
 namespace hmc {
 

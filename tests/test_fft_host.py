@@ -31,7 +31,7 @@ def test_fft_rejects_unsupported_lengths(n):
     assert hmc.test_fft(np.zeros(n, dtype=complex)) is None
 
 
-@pytest.mark.parametrize("L,Lt", [(4, 6), (6, 5), (10, 7), (8, 18), (12, 40)])
+@pytest.mark.parametrize("L,Lt", [(4, 6), (6, 5), (10, 7), (8, 18), (12, 40), (6, 35), (4, 200), (4, 256)])
 def test_precond_matches_oracle(L, Lt):
     model = dict(mu=(0.5, 0.3), t=((1.0, 0.5), (0.5, 1.0)))
     m = O.Model(L=L, Lt=Lt, mu=model["mu"], t=model["t"])
@@ -45,4 +45,6 @@ def test_precond_matches_oracle(L, Lt):
 
 def test_precond_rejects_unsupported_lattice():
     v = np.zeros(4 * 17 * 4 * 4, dtype=complex)
-    assert hmc.test_precond(4, 17, v) is None
+    assert hmc.test_precond(4, 17, v) is None          # no FFT plan for 17
+    w = np.zeros(4 * 260 * 4 * 4, dtype=complex)
+    assert hmc.test_precond(4, 260, w) is None         # more than 16 chunks of 16 per column

@@ -132,6 +132,41 @@ def test_pcg_batch_matches_oracle_and_single(hip, precision):
     assert torch.equal(x0, x2)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pcg_batch_uneven_time_extents(hip, precision):
+    """A long and a short time extent in one batch: the short lattice's columns use fewer
+    chunks than the launch has wavefronts (the rest are empty), and still equal a context of
+    their own bit for bit."""
+    chains = [(4, 256, 0.2), (4, 8, -0.4), (6, 30, 0.0)]
+    g = S.rng(530)
+    phis = [S.draw_phi(g, L, Lt, 0.5) for L, Lt, _ in chains]
+    bs = [S.draw_spinor(g, L, Lt, 1) for L, Lt, _ in chains]
+    bt = hip.Batch(chains, n_pf=1, cg_tol=1e-10, precision=precision, precond="fourier")
+    bt.set_cg_workgroups(8)
+    x, st = bt.cg_solve(bt.pack_phi([dev(p) for p in phis]), bt.pack_spinors([dev(v) for v in bs]))
+    say(f"pcg batch uneven {precision}: iterations {st['iterations']}")
+    assert st["status"] == 0
+    xs = bt.unpack_spinors(x)
+    for i, (L, Lt, r) in enumerate(chains):
+        m = O.Model(L=L, Lt=Lt, r=r)
+        assert resid(m, phis[i], bs[i][0], xs[i][0].cpu().numpy()) <= 1e-10
+        h = hip.HMC(L, Lt, n_pf=1, cg_tol=1e-10, precision=precision, precond="fourier", model=dict(r=r))
+        h.set_cg_workgroups(8)
+        x1, st1 = h.cg_solve(dev(phis[i]), dev(bs[i]))
+        assert st1.iterations == st["iterations"][i:i + 1]
+        assert torch.equal(x1.reshape(xs[i].shape), xs[i])
+
+
+def test_pcg_time_extent_limits(hip):
+    from paper_2204_14241_amd._lib import HmcError
+    hip.HMC(4, 320, precision="mixed", precond="fourier")        # 8 chunks of 40
+    hip.HMC(4, 256, precision="fp64", precond="fourier")         # 8 chunks of 32
+    with pytest.raises(HmcError):
+        hip.HMC(4, 324, precision="mixed", precond="fourier")
+    with pytest.raises(HmcError):
+        hip.HMC(4, 270, precision="fp64", precond="fourier")
+
+
 def test_pcg_rejects_unsupported_lattice(hip):
     from paper_2204_14241_amd._lib import HmcError
     with pytest.raises(HmcError):
