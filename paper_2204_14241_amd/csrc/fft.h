@@ -135,20 +135,21 @@ __host__ __device__ __forceinline__ void small_dft(C2<R> (&v)[RAD], const C2<R>*
     }
 }
 
-// One butterfly j of a radix-RAD stage with sub-length ni, on the line at `line` (element
+// One butterfly j of a radix-RAD stage with sub-length ni, on the line at `src` (element
 // stride es), transform length n.  Forward (DIF): v_q = x[base + M q]; small DFT; times
-// W_n^{(n/ni) n1 k}; store in place.  Inverse: the conjugate transpose of that map.  The
-// twiddle exponent (n/ni) n1 k stays below n because n1 < ni/RAD and k < RAD.
+// W_n^{(n/ni) n1 k}; store at the same positions of the line at `dst` (in place when dst is
+// src).  Inverse: the conjugate transpose of that map.  The twiddle exponent (n/ni) n1 k
+// stays below n because n1 < ni/RAD and k < RAD.
 template <typename R, bool INV, int RAD>
-__host__ __device__ __forceinline__ void butterfly(C2<R>* line, int es, int n, int ni, const FastDiv& dM, int j,
-                                                   const C2<R>* tw) {
+__host__ __device__ __forceinline__ void butterfly(const C2<R>* src, C2<R>* line, int es, int n, int ni,
+                                                   const FastDiv& dM, int j, const C2<R>* tw) {
     const int M = int(dM.d);
     const int b = int(dM.div(uint32_t(j))), n1 = j - b * M;
     const int base = b * ni + n1;
     const int e1 = (n / ni) * n1;
     C2<R> v[RAD];
 #pragma unroll
-    for (int q = 0; q < RAD; ++q) v[q] = line[(base + M * q) * es];
+    for (int q = 0; q < RAD; ++q) v[q] = src[(base + M * q) * es];
     if constexpr (RAD <= 5) {
         if constexpr (!INV) {
             small_dft<R, false, RAD>(v, tw, n);
@@ -185,13 +186,14 @@ __host__ __device__ __forceinline__ void butterfly(C2<R>* line, int es, int n, i
     }
 }
 
-// One radix-RAD stage on cnt lines: every butterfly of every line, spread over the executor.
-// Consecutive work items take consecutive lines when lines are closer together than the
-// elements of a line, consecutive butterflies otherwise (LDS bank spread).  Divisions by the
-// stage's counts use the plan's precomputed reciprocals.
+// One radix-RAD stage on cnt lines: every butterfly of every line, spread over the executor,
+// from the lines at src to the same positions at dst.  Consecutive work items take
+// consecutive lines when lines are closer together than the elements of a line, consecutive
+// butterflies otherwise (LDS bank spread, and whole rows of a slice when src or dst is in
+// global memory).  Divisions by the stage's counts use the plan's precomputed reciprocals.
 template <typename R, bool INV, int RAD, class Ex>
-__host__ __device__ __forceinline__ void fft_stage(const Ex& ex, C2<R>* buf, int es, int ls, int cnt,
-                                                   const FastDiv& dcnt, int n, int ni, const FastDiv& dM,
+__host__ __device__ __forceinline__ void fft_stage(const Ex& ex, const C2<R>* src, C2<R>* buf, int es, int ls,
+                                                   int cnt, const FastDiv& dcnt, int n, int ni, const FastDiv& dM,
                                                    const FastDiv& dnb, const C2<R>* tw) {
     const int nb = n / RAD;
     const bool lines_fast = ls < es;
@@ -204,7 +206,7 @@ __host__ __device__ __forceinline__ void fft_stage(const Ex& ex, C2<R>* buf, int
             l = int(dnb.div(uint32_t(j)));
             jj = j - l * nb;
         }
-        butterfly<R, INV, RAD>(buf + l * ls, es, n, ni, dM, jj, tw);
+        butterfly<R, INV, RAD>(src + l * ls, buf + l * ls, es, n, ni, dM, jj, tw);
     });
 }
 
@@ -238,30 +240,40 @@ struct ExHost {
     void sync() const {}
 };
 
-// All stages on cnt lines (line l starts at buf + l * ls, element stride es).  The plan may
-// live in LDS: it is only read, stage by stage.  MAXR is the largest radix compiled in (5 or
-// 7): a kernel's register allocation covers every stage it can reach, and the radix-7 stage
-// needs many more than the others, so kernels for lattices without a factor 7 leave it out.
+// Stage st of the plan on cnt lines (line l starts at src + l * ls and dst + l * ls, element
+// stride es), no synchronisation.  MAXR is the largest radix compiled in (5 or 7): a kernel's
+// register allocation covers every stage it can reach, and the radix-7 stage needs many more
+// than the others, so kernels for lattices without a factor 7 leave it out.
+template <typename R, bool INV, int MAXR = 7, class Ex>
+__host__ __device__ __forceinline__ void fft_one_stage(const Ex& ex, const C2<R>* src, C2<R>* dst, int es, int ls,
+                                                       int cnt, const FastDiv& dcnt, const FftPlan& pl, int st,
+                                                       const C2<R>* tw) {
+    const int n = pl.n, ni = pl.ni[st];
+    const FastDiv& dM = pl.dM[st];
+    const FastDiv& dnb = pl.dnb[st];
+    switch (pl.radix[st]) {
+        case 4: fft_stage<R, INV, 4>(ex, src, dst, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
+        case 2: fft_stage<R, INV, 2>(ex, src, dst, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
+        case 3: fft_stage<R, INV, 3>(ex, src, dst, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
+        case 5: fft_stage<R, INV, 5>(ex, src, dst, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
+        default:
+            if constexpr (MAXR >= 7) fft_stage<R, INV, 7>(ex, src, dst, es, ls, cnt, dcnt, n, ni, dM, dnb, tw);
+            break;
+    }
+}
+
+// Stages in place on cnt lines of buf, in transform order (stage 0 first forward, last first
+// inverse), leaving out the first `skip0` and the last `skip1` of that order; each followed by
+// a synchronisation.  The plan may live in LDS: it is only read, stage by stage.
 template <typename R, bool INV, int MAXR = 7, class Ex>
 __host__ __device__ __forceinline__ void fft_lines(const Ex& ex, C2<R>* buf, int es, int ls, int cnt,
-                                          const FftPlan& pl, const C2<R>* tw) {
-    const int n = pl.n, nst = pl.nst;
+                                                   const FftPlan& pl, const C2<R>* tw, int skip0 = 0,
+                                                   int skip1 = 0) {
+    const int nst = pl.nst;
     FastDiv dcnt;
     dcnt.init(uint32_t(cnt));
-    for (int q = 0; q < nst; ++q) {
-        const int st = INV ? nst - 1 - q : q;
-        const int ni = pl.ni[st];
-        const FastDiv& dM = pl.dM[st];
-        const FastDiv& dnb = pl.dnb[st];
-        switch (pl.radix[st]) {
-            case 4: fft_stage<R, INV, 4>(ex, buf, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
-            case 2: fft_stage<R, INV, 2>(ex, buf, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
-            case 3: fft_stage<R, INV, 3>(ex, buf, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
-            case 5: fft_stage<R, INV, 5>(ex, buf, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
-            default:
-                if constexpr (MAXR >= 7) fft_stage<R, INV, 7>(ex, buf, es, ls, cnt, dcnt, n, ni, dM, dnb, tw);
-                break;
-        }
+    for (int q = skip0; q < nst - skip1; ++q) {
+        fft_one_stage<R, INV, MAXR>(ex, buf, buf, es, ls, cnt, dcnt, pl, INV ? nst - 1 - q : q, tw);
         ex.sync();
     }
 }
@@ -278,6 +290,25 @@ __host__ __device__ __forceinline__ void fft_slice(const Ex& ex, C2<R>* buf, con
         fft_lines<R, true, MAXR>(ex, buf, L, 1, L, pl, tw);
         fft_lines<R, true, MAXR>(ex, buf, 1, L, L, pl, tw);
     }
+}
+
+// The same 2-D transform from the slice at src to the slice at dst, with buf (the size of a
+// slice) as the working copy: the first stage reads src and writes buf, the last reads buf and
+// writes dst, so src and dst (which may coincide) are each touched once, by a stage, with no
+// separate copy in or out.
+template <typename R, bool INV, int MAXR = 7, class Ex>
+__host__ __device__ __forceinline__ void fft_slice_io(const Ex& ex, const C2<R>* src, C2<R>* buf, C2<R>* dst,
+                                                      const FftPlan& pl, const C2<R>* tw) {
+    const int L = pl.n, nst = pl.nst;
+    FastDiv dL;
+    dL.init(uint32_t(L));
+    // forward: rows (es 1, ls L) then columns (es L, ls 1); inverse: columns then rows
+    const int es0 = INV ? L : 1, ls0 = INV ? 1 : L;
+    fft_one_stage<R, INV, MAXR>(ex, src, buf, es0, ls0, L, dL, pl, INV ? nst - 1 : 0, tw);
+    ex.sync();
+    fft_lines<R, INV, MAXR>(ex, buf, es0, ls0, L, pl, tw, 1, 0);
+    fft_lines<R, INV, MAXR>(ex, buf, ls0, es0, L, pl, tw, 0, 1);
+    fft_one_stage<R, INV, MAXR>(ex, buf, dst, ls0, es0, L, dL, pl, INV ? 0 : nst - 1, tw);
 }
 
 // Largest radix a plan uses.

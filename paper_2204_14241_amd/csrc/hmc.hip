@@ -1413,7 +1413,11 @@ int hmc_test_precond(int L, int Lt, double dtau, const hmc_params* params, const
     const PcBlob bl = pc_blob_layout(L, Lt);
     const double2* twl = reinterpret_cast<const double2*>(blob.data() + bl.twl);
     const ExHost ex;
-    for (int sl = 0; sl < 4 * Lt; ++sl) fft_slice<double, false>(ex, w.data() + size_t(sl) * LL, pl, twl);
+    std::vector<double2> sbuf(static_cast<size_t>(LL));   // the kernels' LDS copy of a slice
+    for (int sl = 0; sl < 4 * Lt; ++sl) {
+        double2* slice = w.data() + size_t(sl) * LL;
+        fft_slice_io<double, false>(ex, slice, sbuf.data(), slice, pl, twl);
+    }
     // the tau pass as the kernel runs it: Q chunks per column, each reduced to an affine map,
     // the maps closed around the cycle, the chunks rerun from their entering values
     const int m = (Lt + Q - 1) / Q;
@@ -1451,7 +1455,10 @@ int hmc_test_precond(int L, int Lt, double dtau, const hmc_params* params, const
             }
         }
     }
-    for (int sl = 0; sl < 4 * Lt; ++sl) fft_slice<double, true>(ex, w.data() + size_t(sl) * LL, pl, twl);
+    for (int sl = 0; sl < 4 * Lt; ++sl) {
+        double2* slice = w.data() + size_t(sl) * LL;
+        fft_slice_io<double, true>(ex, slice, sbuf.data(), slice, pl, twl);
+    }
     for (size_t i = 0; i < w.size(); ++i) {
         out[2 * i] = w[i].x;
         out[2 * i + 1] = w[i].y;

@@ -119,10 +119,9 @@ __global__ __launch_bounds__(kPcBlock) void k_pc_xy(CgCtl ctl, Geo geo, const C2
     const size_t o = pos.voff + size_t(c) * lat.vol + size_t(tau) * LL;
     __shared__ FftPlan pl;
     if (threadIdx.x == 0) make_fft_plan(L, pl);
-    stage_in<R>(buf, LL, [&](int i) { return src + o + i; });
     __syncthreads();
-    fft_slice<R, INV, MAXR>(ExDevice(), buf, pl, tw);
-    stage_out<R>(buf, LL, [&](int i) { return dst + o + i; });
+    // the first stage reads the slice from src, the last writes it to dst
+    fft_slice_io<R, INV, MAXR>(ExDevice(), src + o, buf, dst + o, pl, tw);
     cg_publish(ctl, pos);
 }
 
