@@ -135,21 +135,29 @@ __host__ __device__ __forceinline__ void small_dft(C2<R> (&v)[RAD], const C2<R>*
     }
 }
 
-// One butterfly j of a radix-RAD stage with sub-length ni, on the line at `src` (element
-// stride es), transform length n.  Forward (DIF): v_q = x[base + M q]; small DFT; times
-// W_n^{(n/ni) n1 k}; store at the same positions of the line at `dst` (in place when dst is
-// src).  Inverse: the conjugate transpose of that map.  The twiddle exponent (n/ni) n1 k
-// stays below n because n1 < ni/RAD and k < RAD.
-template <typename R, bool INV, int RAD>
-__host__ __device__ __forceinline__ void butterfly(const C2<R>* src, C2<R>* line, int es, int n, int ni,
-                                                   const FastDiv& dM, int j, const C2<R>* tw) {
+// Butterfly j of a radix-RAD stage with sub-length ni, transform length n: its inputs sit at
+// positions base + M q (q < RAD) of the line, and its twiddles are W_n^{e1 k}.
+struct BflyPos {
+    int base, M, e1;
+};
+__host__ __device__ __forceinline__ BflyPos bfly_pos(int n, int ni, const FastDiv& dM, int j) {
     const int M = int(dM.d);
     const int b = int(dM.div(uint32_t(j))), n1 = j - b * M;
-    const int base = b * ni + n1;
-    const int e1 = (n / ni) * n1;
-    C2<R> v[RAD];
+    return BflyPos{b * ni + n1, M, (n / ni) * n1};
+}
+template <typename R, int RAD>
+__host__ __device__ __forceinline__ void bfly_load(const C2<R>* src, int es, const BflyPos& p, C2<R> (&v)[RAD]) {
 #pragma unroll
-    for (int q = 0; q < RAD; ++q) v[q] = src[(base + M * q) * es];
+    for (int q = 0; q < RAD; ++q) v[q] = src[(p.base + p.M * q) * es];
+}
+
+// The butterfly on its loaded inputs v, stored at the same positions of the line at `line`.
+// Forward (DIF): small DFT, then times W_n^{e1 k}.  Inverse: the conjugate transpose of that
+// map.  The twiddle exponent e1 k stays below n because n1 < ni/RAD and k < RAD.
+template <typename R, bool INV, int RAD>
+__host__ __device__ __forceinline__ void bfly_store(C2<R>* line, int es, int n, const BflyPos& p, C2<R> (&v)[RAD],
+                                                    const C2<R>* tw) {
+    const int base = p.base, M = p.M, e1 = p.e1;
     if constexpr (RAD <= 5) {
         if constexpr (!INV) {
             small_dft<R, false, RAD>(v, tw, n);
@@ -186,6 +194,18 @@ __host__ __device__ __forceinline__ void butterfly(const C2<R>* src, C2<R>* line
     }
 }
 
+
+// One butterfly j, from the line at `src` to the same positions of the line at `line` (in
+// place when they coincide).
+template <typename R, bool INV, int RAD>
+__host__ __device__ __forceinline__ void butterfly(const C2<R>* src, C2<R>* line, int es, int n, int ni,
+                                                   const FastDiv& dM, int j, const C2<R>* tw) {
+    const BflyPos p = bfly_pos(n, ni, dM, j);
+    C2<R> v[RAD];
+    bfly_load<R, RAD>(src, es, p, v);
+    bfly_store<R, INV, RAD>(line, es, n, p, v, tw);
+}
+
 // One radix-RAD stage on cnt lines: every butterfly of every line, spread over the executor,
 // from the lines at src to the same positions at dst.  Consecutive work items take
 // consecutive lines when lines are closer together than the elements of a line, consecutive
@@ -210,9 +230,47 @@ __host__ __device__ __forceinline__ void fft_stage(const Ex& ex, const C2<R>* sr
     });
 }
 
+// The same stage with the inputs of NB butterflies per thread loaded before any is computed,
+// for a stage that reads global memory (more loads in flight than one butterfly's).
+template <typename R, bool INV, int RAD, int NB, class Ex>
+__host__ __device__ __forceinline__ void fft_stage_nb(const Ex& ex, const C2<R>* src, C2<R>* buf, int es, int ls,
+                                                      int cnt, const FastDiv& dcnt, int n, int ni, const FastDiv& dM,
+                                                      const FastDiv& dnb, const C2<R>* tw) {
+    const int nb = n / RAD, total = cnt * nb, stride = ex.stride();
+    const bool lines_fast = ls < es;
+#pragma unroll 1
+    for (int j0 = ex.first(); j0 < total; j0 += NB * stride) {
+        C2<R> v[NB][RAD];
+        BflyPos p[NB];
+        int lo[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = j0 + u * stride;
+            if (j < total) {
+                int l, jj;
+                if (lines_fast) {
+                    jj = int(dcnt.div(uint32_t(j)));
+                    l = j - jj * cnt;
+                } else {
+                    l = int(dnb.div(uint32_t(j)));
+                    jj = j - l * nb;
+                }
+                lo[u] = l * ls;
+                p[u] = bfly_pos(n, ni, dM, jj);
+                bfly_load<R, RAD>(src + lo[u], es, p[u], v[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+            if (j0 + u * stride < total) bfly_store<R, INV, RAD>(buf + lo[u], es, n, p[u], v[u], tw);
+    }
+}
+
 // Execution policies: the device one spreads work over the workgroup and synchronises it; the
 // host one runs sequentially (CPU tests).  sum_each adds up what f returns, per thread.
 struct ExDevice {
+    __device__ __forceinline__ int first() const { return int(threadIdx.x); }
+    __device__ __forceinline__ int stride() const { return int(blockDim.x); }
     template <class F>
     __device__ __forceinline__ void for_each(int n, F f) const {
 #pragma unroll 1
@@ -227,6 +285,8 @@ struct ExDevice {
     __device__ __forceinline__ void sync() const { __syncthreads(); }
 };
 struct ExHost {
+    int first() const { return 0; }
+    int stride() const { return 1; }
     template <class F>
     void for_each(int n, F f) const {
         for (int i = 0; i < n; ++i) f(i);
@@ -244,22 +304,26 @@ struct ExHost {
 // stride es), no synchronisation.  MAXR is the largest radix compiled in (5 or 7): a kernel's
 // register allocation covers every stage it can reach, and the radix-7 stage needs many more
 // than the others, so kernels for lattices without a factor 7 leave it out.
-template <typename R, bool INV, int MAXR = 7, class Ex>
+template <typename R, bool INV, int MAXR = 7, int NB = 1, class Ex>
 __host__ __device__ __forceinline__ void fft_one_stage(const Ex& ex, const C2<R>* src, C2<R>* dst, int es, int ls,
                                                        int cnt, const FastDiv& dcnt, const FftPlan& pl, int st,
                                                        const C2<R>* tw) {
     const int n = pl.n, ni = pl.ni[st];
     const FastDiv& dM = pl.dM[st];
     const FastDiv& dnb = pl.dnb[st];
+#define HMC_FFT_STAGE(RAD)                                                                       \
+    if constexpr (NB > 1) fft_stage_nb<R, INV, RAD, NB>(ex, src, dst, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); \
+    else fft_stage<R, INV, RAD>(ex, src, dst, es, ls, cnt, dcnt, n, ni, dM, dnb, tw);
     switch (pl.radix[st]) {
-        case 4: fft_stage<R, INV, 4>(ex, src, dst, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
-        case 2: fft_stage<R, INV, 2>(ex, src, dst, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
-        case 3: fft_stage<R, INV, 3>(ex, src, dst, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
-        case 5: fft_stage<R, INV, 5>(ex, src, dst, es, ls, cnt, dcnt, n, ni, dM, dnb, tw); break;
+        case 4: { HMC_FFT_STAGE(4) } break;
+        case 2: { HMC_FFT_STAGE(2) } break;
+        case 3: { HMC_FFT_STAGE(3) } break;
+        case 5: { HMC_FFT_STAGE(5) } break;
         default:
-            if constexpr (MAXR >= 7) fft_stage<R, INV, 7>(ex, src, dst, es, ls, cnt, dcnt, n, ni, dM, dnb, tw);
+            if constexpr (MAXR >= 7) { HMC_FFT_STAGE(7) }
             break;
     }
+#undef HMC_FFT_STAGE
 }
 
 // Stages in place on cnt lines of buf, in transform order (stage 0 first forward, last first
@@ -304,7 +368,9 @@ __host__ __device__ __forceinline__ void fft_slice_io(const Ex& ex, const C2<R>*
     dL.init(uint32_t(L));
     // forward: rows (es 1, ls L) then columns (es L, ls 1); inverse: columns then rows
     const int es0 = INV ? L : 1, ls0 = INV ? 1 : L;
-    fft_one_stage<R, INV, MAXR>(ex, src, buf, es0, ls0, L, dL, pl, INV ? nst - 1 : 0, tw);
+    // the stage that reads src keeps several butterflies' loads in flight per thread (2 FP32,
+    // which keeps three slice workgroups per CU; 4 FP64, where one slice fills the LDS anyway)
+    fft_one_stage<R, INV, MAXR, sizeof(R) == 4 ? 2 : 4>(ex, src, buf, es0, ls0, L, dL, pl, INV ? nst - 1 : 0, tw);
     ex.sync();
     fft_lines<R, INV, MAXR>(ex, buf, es0, ls0, L, pl, tw, 1, 0);
     fft_lines<R, INV, MAXR>(ex, buf, ls0, es0, L, pl, tw, 0, 1);
