@@ -22,6 +22,7 @@ closed_forms  free-fermion (lambda = 0) determinant and spectrum, the BSS form o
 precond       the twisted-Fourier preconditioner of Eq. (23)-(26) and preconditioned CG
 metric        the Fourier-diagonal HMC metric (Eq. 30, momenta, kinetic energy), the
               step-size rule of Eq. (31), the jump-distance estimate of Eq. (32), jitter
+observables   SDW susceptibility (Eq. 34), order parameter and Binder cumulant
 
 Every function is plain NumPy in float64/complex128, written for readability,
 not speed.
@@ -34,7 +35,7 @@ from .action import (heatbath, pf_action, pf_action_dense, pf_force, boson_actio
                      boson_force, total_force)
 from .hmc import hamiltonian, leapfrog, trajectory, metropolis_accept
 from .precond import kinetic_symbol, apply_precond, pcg_solve
-from . import closed_forms, metric
+from . import closed_forms, metric, observables
 
 __all__ = [
     "Model", "spinor_index", "phi_index", "stagger",
@@ -42,5 +43,5 @@ __all__ = [
     "time_slice_block", "cg_solve", "heatbath", "pf_action", "pf_action_dense",
     "pf_force", "boson_action", "boson_force", "total_force", "hamiltonian",
     "leapfrog", "trajectory", "metropolis_accept", "closed_forms", "kinetic_symbol",
-    "apply_precond", "pcg_solve", "metric",
+    "apply_precond", "pcg_solve", "metric", "observables",
 ]
