@@ -165,8 +165,9 @@ def cpu_info():
 
 def metric_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, seed, reps=20):
     """The Fourier-diagonal metric at the workload size: the metric estimated (Eq. 30) from
-    the starting field and the first momenta, the momentum draw and the kinetic energy timed
-    with HIP events, and one mixed-precision warm-up iteration (Eq. 31-32; lengths 1..4)."""
+    the starting field and the first momenta, the momentum draw, the kinetic energy and one
+    term of the SDW susceptibility (Eq. 34) timed with HIP events, and one mixed-precision
+    warm-up iteration (Eq. 31-32; lengths 1..4)."""
     import synth_inputs as S
     dev = torch.device("cuda")
     out = {}
@@ -180,8 +181,11 @@ def metric_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, seed, reps=20):
     xi = torch.from_numpy(S.draw_momentum(S.rng(seed + 7), L, Lt)).to(dev)
     pi = torch.empty_like(xi)
     vol = Lt * L * L
+    chi = torch.zeros(Lt, L, L, dtype=torch.float64, device=dev)
+    # bytes per site: slice pass 24 + 48, tau pass 48 + 24 (spectra), sum 24 + 8 + 8
     for name, fn, bps in (("momenta", lambda: h.metric_momenta(xi, out=pi), 264),
-                          ("kinetic", lambda: h.metric_kinetic(pi), 144)):
+                          ("kinetic", lambda: h.metric_kinetic(pi), 144),
+                          ("sdw_accumulate", lambda: h.sdw_accumulate(phi, chi), 184)):
         fn()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
         for a, b in ev:

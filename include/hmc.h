@@ -245,6 +245,20 @@ int hmc_metric_kinetic(hmc_ctx* ctx, const double* pi, double* K, void* stream);
 int hmc_metric_norm2(hmc_ctx* ctx, const double* v, double* out, void* stream);
 int hmc_metric_accumulate(hmc_ctx* ctx, const double* phi, double* acc, void* stream);
 
+/* Bosonic observables ("Estimation of observables", Eq. 33-34; Supplementary Note 1).
+ *   hmc_sdw_accumulate: chi_acc(n, kx, ky) += dtau sum_l |(F phi_l)(n, kx, ky)|^2, F the unitary
+ *     space-time DFT: one sample's term of the SDW susceptibility of Eq. (34) (divide by the
+ *     number of samples afterwards).  chi_acc: device double[L_tau][L][L] indexed by frequency.
+ *     Needs the lattices the metric supports (factors <= 7, L <= 100); uses the FP64 CG
+ *     residual of the workspace as scratch.
+ *   hmc_order_parameter: Phi[l] = sum over all sites of phi_l (host double[3]); synchronises.
+ *   hmc_binder: B = 1 - 3 <|Phi|^4> / (5 <|Phi|^2>^2) over S samples Phi[S][3] (host arrays;
+ *     NaN for S < 1 or a NULL array).  0 for an isotropic Gaussian Phi, 2/5 at fixed |Phi|.
+ * Errors: HMC_ERR_INVALID_ARG, HMC_ERR_WORKSPACE, HMC_ERR_HIP. */
+int hmc_sdw_accumulate(hmc_ctx* ctx, const double* phi, double* chi_acc, void* stream);
+int hmc_order_parameter(hmc_ctx* ctx, const double* phi, double* Phi, void* stream);
+double hmc_binder(const double* Phi, int S);
+
 /* Warm-up tuning of the step size and trajectory length ("Online HMC hyperparameter
  * tuning": Eq. 31 and Eq. 32).  Host state, owned by the caller; plain arithmetic, no GPU.
  *

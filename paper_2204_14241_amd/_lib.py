@@ -33,7 +33,8 @@ EXPORTED = [
     "hmc_get_cg_workgroups", "hmc_leapfrog", "hmc_autotune", "hmc_set_graphs",
     "hmc_set_metric", "hmc_metric_momenta", "hmc_metric_kinetic", "hmc_metric_norm2",
     "hmc_metric_accumulate", "hmc_tuner_init", "hmc_tuner_add_step", "hmc_tuner_add_jump",
-    "hmc_tuner_best_length", "hmc_jitter", "hmc_warmup_iteration",
+    "hmc_tuner_best_length", "hmc_jitter", "hmc_warmup_iteration", "hmc_sdw_accumulate",
+    "hmc_order_parameter", "hmc_binder",
     "hmc_batch_create", "hmc_batch_destroy", "hmc_batch_workspace_bytes",
     "hmc_batch_set_workspace", "hmc_batch_layout", "hmc_batch_set_cg_workgroups",
     "hmc_batch_get_cg_workgroups", "hmc_batch_set_graphs", "hmc_batch_set_params",
@@ -192,6 +193,9 @@ def load():
         "hmc_tuner_add_jump": (I, [ctypes.POINTER(HmcTuner), I, D, D]),
         "hmc_tuner_best_length": (I, [ctypes.POINTER(HmcTuner)]),
         "hmc_jitter": (I, [D, I]),
+        "hmc_sdw_accumulate": (I, [P, P, P, P]),
+        "hmc_order_parameter": (I, [P, P, ctypes.POINTER(D), P]),
+        "hmc_binder": (D, [ctypes.POINTER(D), I]),
         "hmc_warmup_iteration": (I, [P, ctypes.POINTER(HmcTuner), P, P, P, I, D, D,
                                      ctypes.POINTER(HmcWarmupStats), P]),
         "hmc_batch_create": (I, [I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D), D,

@@ -148,7 +148,7 @@ struct hmc_ctx {
     const double* sigma = nullptr;
     bool metric_ok = false;
     size_t lds_mt_t = 0;
-    double* mpart = nullptr;
+    double* mpart = nullptr;           // 3 x max(tau-pass groups, 256) partial sums
     double* piw = nullptr;             // momenta of a warm-up iteration (one lattice)
     int ngblk = 0;             // 256-site tiles of the site-parallel kernels
 
@@ -318,7 +318,7 @@ static size_t ws_layout(hmc_ctx* c, char* base) {
     char* tr = take(2 * sp64);
     char* bos = take(2 * 3 * PS * sizeof(double));
     char* f32 = take(3 * PS * sizeof(float));
-    char* mp = c->is_batch ? nullptr : take(sizeof(double) * 3 * size_t(pc_groups(c->lat.LL, pc_ncol<double>())));
+    char* mp = c->is_batch ? nullptr : take(sizeof(double) * 3 * size_t(std::max(pc_groups(c->lat.LL, pc_ncol<double>()), 256)));
     char* pw = c->is_batch ? nullptr : take(3 * PS * sizeof(double));
     char *un0 = nullptr, *un1 = nullptr, *bl0 = nullptr, *bl1 = nullptr, *ch = nullptr,
          *cb = nullptr, *cf = nullptr, *cs = nullptr, *pxy = nullptr, *pt0 = nullptr, *pt1 = nullptr;
@@ -924,7 +924,7 @@ static int read_slots(hmc_ctx* c, hipStream_t s) {
 // inverse slice FFT into out (add: out += h y; else out = y).  in may equal out.
 template <int MAXR>
 static int metric_passes_r(hmc_ctx* c, const double* in, double* out, int add, double h, int mul, int red,
-                           double rs, double* acc, int slot, hipStream_t s) {
+                           double rs, double* acc, int slot, hipStream_t s, int acc_add) {
     const MetricGeo g{c->lat.L, c->lat.Lt, c->lat.LL, c->lat.vol};
     double2* scr = c->t64;
     const int nslice = 3 * g.Lt, ngrp = 3 * pc_groups(g.LL, pc_ncol<double>());
@@ -932,7 +932,7 @@ static int metric_passes_r(hmc_ctx* c, const double* in, double* out, int add, d
                        static_cast<double*>(nullptr), 0, 0.0, c->blob);
     LAUNCHCHK();
     hipLaunchKernelGGL((k_mt_t<MAXR>), dim3(ngrp), dim3(kPcBlock), c->lds_mt_t, s, g, scr, c->sigma, mul, red, rs,
-                       acc, red ? c->mpart : static_cast<double*>(nullptr), c->blob);
+                       acc, acc_add, red ? c->mpart : static_cast<double*>(nullptr), c->blob);
     LAUNCHCHK();
     if (red) {
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, c->mpart, ngrp, 1, 0, c->slots + slot);
@@ -947,9 +947,9 @@ static int metric_passes_r(hmc_ctx* c, const double* in, double* out, int add, d
 }
 
 static int metric_passes(hmc_ctx* c, const double* in, double* out, int add, double h, int mul, int red,
-                         double rs, double* acc, int slot, hipStream_t s) {
-    return c->pc_r7 ? metric_passes_r<7>(c, in, out, add, h, mul, red, rs, acc, slot, s)
-                    : metric_passes_r<5>(c, in, out, add, h, mul, red, rs, acc, slot, s);
+                         double rs, double* acc, int slot, hipStream_t s, int acc_add = 1) {
+    return c->pc_r7 ? metric_passes_r<7>(c, in, out, add, h, mul, red, rs, acc, slot, s, acc_add)
+                    : metric_passes_r<5>(c, in, out, add, h, mul, red, rs, acc, slot, s, acc_add);
 }
 
 // The leapfrog drift phi += eps dphi/dt: eps pi (identity metric) or eps Sigma pi.
@@ -1603,6 +1603,54 @@ int hmc_metric_accumulate(hmc_ctx* c, const double* phi, double* acc, void* stre
     int rc = metric_check(c, phi, acc);
     if (rc) return rc;
     return metric_passes(c, phi, nullptr, 0, 0.0, 0, RED_NONE, 1.0, acc, 0, (hipStream_t)stream);
+}
+
+int hmc_sdw_accumulate(hmc_ctx* c, const double* phi, double* chi, void* stream) {
+    int rc = metric_check(c, phi, chi);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    // per-component spectra into the idle FP64 CG residual, then summed into chi
+    double* t = reinterpret_cast<double*>(c->r64);
+    const double* sg = c->sigma;
+    c->sigma = nullptr;
+    rc = metric_passes(c, phi, nullptr, 0, 0.0, 0, RED_NONE, 1.0, t, 0, s, 0);
+    c->sigma = sg;
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_mt_sum3, dim3(elem_grid(c->vol)), dim3(kBlock), 0, s, static_cast<const double*>(t), chi,
+                       c->dtau, int(c->vol));
+    LAUNCHCHK();
+    return HMC_OK;
+}
+
+int hmc_order_parameter(hmc_ctx* c, const double* phi, double* Phi, void* stream) {
+    if (c == nullptr || phi == nullptr || Phi == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    if (c->is_batch) return fail(HMC_ERR_INVALID_ARG, "the order parameter is for one-lattice contexts");
+    int rc = need_ws(c);
+    if (rc) return rc;
+    if (!aligned16(phi)) return fail(HMC_ERR_INVALID_ARG, "phi must be 16-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = std::min(256, elem_grid(c->vol));
+    hipLaunchKernelGGL(k_mt_csum, dim3(3 * nb), dim3(kBlock), 0, s, phi, c->mpart, int(c->vol), nb);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, static_cast<const double*>(c->mpart), nb, 3, nb,
+                       c->slots + SL_TMP);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(c->h_slots + SL_TMP, c->slots + SL_TMP, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int l = 0; l < 3; ++l) Phi[l] = c->h_slots[SL_TMP + l];
+    return HMC_OK;
+}
+
+double hmc_binder(const double* Phi, int S) {
+    if (Phi == nullptr || S < 1) return std::nan("");
+    double s2 = 0.0, s4 = 0.0;
+    for (int i = 0; i < S; ++i) {
+        const double n2 = Phi[3 * i] * Phi[3 * i] + Phi[3 * i + 1] * Phi[3 * i + 1] + Phi[3 * i + 2] * Phi[3 * i + 2];
+        s2 += n2;
+        s4 += n2 * n2;
+    }
+    const double m2 = s2 / S, m4 = s4 / S;
+    return 1.0 - 3.0 * m4 / (5.0 * m2 * m2);
 }
 
 int hmc_set_graphs(hmc_ctx* c, int enable) {

@@ -58,11 +58,12 @@ __global__ __launch_bounds__(kPcBlock) void k_mt_xy(MetricGeo g, const double* _
 // One workgroup per (component, group of 16 consecutive positions of a slice): the tau FFT
 // of the group's columns of scr, the per-frequency work (positions are in digit-reversed
 // order; each knows its frequency), and with `mul` != 0 the scaling by s / V and the inverse
-// tau FFT back into scr.  part[workgroup] receives rs times the workgroup's share of the sum.
+// tau FFT back into scr.  part[workgroup] receives rs times the workgroup's share of the sum;
+// acc(k) receives |(F v)(k)|^2, added (acc_add) or stored.
 template <int MAXR>
 __global__ __launch_bounds__(kPcBlock) void k_mt_t(MetricGeo g, double2* __restrict__ scr,
                                                  const double* __restrict__ sigma, int mul, int red, double rs,
-                                                 double* __restrict__ acc, double* __restrict__ part,
+                                                 double* __restrict__ acc, int acc_add, double* __restrict__ part,
                                                  const double* __restrict__ blob) {
     extern __shared__ __align__(16) unsigned char pc_smem[];
     constexpr int NC = pc_ncol<double>();
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(kPcBlock) void k_mt_t(MetricGeo g, double2* __restr
         if (red == RED_SIGMA) sum[0] += sv * n2;
         else if (red == RED_INV) sum[0] += n2 / sv;
         else if (red == RED_PLAIN) sum[0] += n2;
-        if (ac) ac[k] += n2;
+        if (ac) ac[k] = acc_add ? ac[k] + n2 : n2;
         if (mul) {
             const double m = (mul == MUL_SIGMA ? sv : 1.0 / sqrt(sv)) * inv_v;
             buf[i] = make_double2(m * y.x, m * y.y);
@@ -121,6 +122,25 @@ __global__ __launch_bounds__(kPcBlock) void k_mt_t(MetricGeo g, double2* __restr
         fft_lines<double, true, MAXR>(ExDevice(), buf, ncol, 1, ncol, pt, twT);
         stage_out<double>(buf, Lt * ncol, at);
     }
+}
+
+// chi(k) += scale ((t0(k) + t1(k)) + t2(k)) for the three component planes of t (each vol
+// long): one term of the SDW susceptibility of Eq. (34) from the per-component spectra.
+__global__ __launch_bounds__(kBlock) void k_mt_sum3(const double* __restrict__ t, double* __restrict__ chi,
+                                                    double scale, int vol) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < vol) chi[i] = chi[i] + scale * ((t[i] + t[vol + i]) + t[2 * vol + i]);
+}
+
+// Per-workgroup partial sums of each component of a boson-shaped field: part[l * nb + b] for
+// component l and workgroup b of nb (the order parameter Phi = sum over sites of phi).
+__global__ __launch_bounds__(kBlock) void k_mt_csum(const double* __restrict__ phi, double* __restrict__ part,
+                                                    int vol, int nb) {
+    const int l = blockIdx.x / nb, b = blockIdx.x - l * nb;
+    double v[1] = {0.0};
+    for (int i = b * kBlock + threadIdx.x; i < vol; i += nb * kBlock) v[0] += phi[size_t(l) * vol + i];
+    block_reduce<1>(v);
+    if (threadIdx.x == 0) part[size_t(l) * nb + b] = v[0];
 }
 
 }  // namespace hmc

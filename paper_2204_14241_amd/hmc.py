@@ -182,6 +182,24 @@ class HMC:
         self._call("hmc_metric_accumulate", _ptr(phi), _ptr(acc), _stream())
         return acc
 
+    # ---------------------------------------------------------------- observables
+    def sdw_accumulate(self, phi, chi_acc):
+        """chi_acc += dtau sum_l |F phi_l|^2 (one term of Eq. 34), in place; chi_acc is a
+        float64 tensor of shape (L_tau, L, L)."""
+        self._phi(phi)
+        if (chi_acc.dtype != torch.float64 or chi_acc.device != self.device or not chi_acc.is_contiguous()
+                or tuple(chi_acc.shape) != (self.Lt, self.L, self.L)):
+            raise ValueError(f"chi_acc must be a contiguous float64 ({self.Lt}, {self.L}, {self.L}) tensor")
+        self._call("hmc_sdw_accumulate", _ptr(phi), _ptr(chi_acc), _stream())
+        return chi_acc
+
+    def order_parameter(self, phi):
+        """Phi = sum over sites of phi (three floats)."""
+        self._phi(phi)
+        out = (ctypes.c_double * 3)()
+        self._call("hmc_order_parameter", _ptr(phi), out, _stream())
+        return list(out)
+
     def warmup_iteration(self, tuner, phi, xi, eta, u_accept, u_length):
         """One warm-up iteration (hmc_warmup_iteration); phi is updated in place and the
         tuner's state advances.  Returns the stats as a dict."""
@@ -364,6 +382,13 @@ class Tuner:
 
     def best_length(self):
         return self.lib.hmc_tuner_best_length(ctypes.byref(self.state)) or None
+
+
+def binder(Phis):
+    """B = 1 - 3 <|Phi|^4> / (5 <|Phi|^2>^2) over order-parameter samples (sequence of 3-vectors)."""
+    flat = [float(v) for P in Phis for v in P]
+    arr = (ctypes.c_double * len(flat))(*flat)
+    return _lib.load().hmc_binder(arr, len(flat) // 3)
 
 
 def jitter(u, n_max):

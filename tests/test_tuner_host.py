@@ -57,3 +57,15 @@ def test_tuner_rejects_invalid_settings():
         t.add_jump(5, 1.0, 0.0)
     with pytest.raises(RuntimeError):
         t.add_step(float("nan"), 0.0)
+
+
+def test_binder_matches_oracle():
+    from oracle import observables as Ob
+    rng = np.random.default_rng(21)
+    for S in (1, 2, 17, 1000):
+        P = rng.standard_normal((S, 3)) * rng.uniform(0.5, 2.0, (S, 1))
+        assert hmc.binder(P) == pytest.approx(Ob.binder(P), rel=1e-13, abs=1e-15)
+    fixed = rng.standard_normal((50, 3))
+    fixed *= 3.0 / np.linalg.norm(fixed, axis=1, keepdims=True)
+    assert hmc.binder(fixed) == pytest.approx(0.4, abs=1e-13)
+    assert math.isnan(hmc.binder([]))
