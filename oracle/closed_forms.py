@@ -6,7 +6,7 @@ Eq. (17) by hand derivation.
 Free fermions (g = 0).  M is then block diagonal in band alpha, spin s and spatial
 momentum k = 2 pi (m_x, m_y) / L (translation invariance, Eq. 23-25).  Each block is the
 N_tau x N_tau matrix -b 1 + S, where b = 1 + dtau (mu_alpha + 2 t_{alpha,x} cos k_x +
-2 t_{alpha,y} cos k_y) and S is the antiperiodic forward shift (S^N_tau = -1).  The
+2 t_{alpha,y} cos k_y + 2 tn_{alpha,x} cos 2k_x + 2 tn_{alpha,y} cos 2k_y) and S is the antiperiodic forward shift (S^N_tau = -1).  The
 eigenvalues of S are z_n = exp(i w_n) with w_n = pi (2n + 1) / N_tau, so the block has
 eigenvalues z_n - b and determinant (-1)^N_tau (1 + b^N_tau): the BSS form of Eq. (18)
 for this linear-in-dtau discretisation.  The blocks are normal, so the spectrum of
@@ -31,7 +31,8 @@ import numpy as np
 
 
 def _band_b(m, a, kx, ky):
-    return 1.0 + m.dtau * (m.mu[a] + 2 * m.t[a][0] * np.cos(kx) + 2 * m.t[a][1] * np.cos(ky))
+    return 1.0 + m.dtau * (m.mu[a] + 2 * m.t[a][0] * np.cos(kx) + 2 * m.t[a][1] * np.cos(ky)
+                           + 2 * m.tn[a][0] * np.cos(2 * kx) + 2 * m.tn[a][1] * np.cos(2 * ky))
 
 
 def _momenta(m):

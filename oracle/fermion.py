@@ -57,6 +57,9 @@ def dense_M(m, phi):
                         for dx, dy, d in neighbours:
                             col = spinor_index(m, a, s, tau, (x + dx) % L, (y + dy) % L)
                             D[row, col] += -dt * m.t[a][d]
+                            # the same for the site two steps along the axis (tn)
+                            col = spinor_index(m, a, s, tau, (x + 2 * dx) % L, (y + 2 * dy) % L)
+                            D[row, col] += -dt * m.tn[a][d]
                         # dtau g e^{i Q.r} phi . tau_{s s'} sigma^x_{alpha alpha'}
                         coup = dt * m.lam * stag[x, y] * _phi_dot_tau(phi[:, tau, x, y])
                         for s2 in range(2):
@@ -71,10 +74,14 @@ def dense_MdagM(m, phi):
 
 
 def _hop(m, a, psi_a):
-    """sum over the four nearest neighbours r' of t_{a,d} psi(r'); psi_a has axes (s, tau, x, y)."""
+    """sum over the four nearest neighbours r' of t_{a,d} psi(r') and over the four sites two
+    steps away along an axis of tn_{a,d} psi(r'); psi_a has axes (s, tau, x, y)."""
     tx, ty = m.t[a]
+    ux, uy = m.tn[a]
     return (tx * (np.roll(psi_a, -1, axis=2) + np.roll(psi_a, 1, axis=2))
-            + ty * (np.roll(psi_a, -1, axis=3) + np.roll(psi_a, 1, axis=3)))
+            + ty * (np.roll(psi_a, -1, axis=3) + np.roll(psi_a, 1, axis=3))
+            + ux * (np.roll(psi_a, -2, axis=2) + np.roll(psi_a, 2, axis=2))
+            + uy * (np.roll(psi_a, -2, axis=3) + np.roll(psi_a, 2, axis=3)))
 
 
 def _yukawa(m, phi, psi):

@@ -8,8 +8,11 @@ The boson field is an array of shape 3 x N_tau x L x L (Methods B).
 
 Readings where the paper leaves a choice open:
   * band alpha = 0 is the paper's band "x", alpha = 1 is band "y"; spin s = 0 is up;
-  * hopping is nearest-neighbour only, t[alpha][d] for direction d = 0 (the slower
-    spatial index x) and d = 1 (the faster index y);
+  * hopping t[alpha][d] to the nearest neighbours along direction d = 0 (the slower
+    spatial index x) and d = 1 (the faster index y), and tn[alpha][d] to the sites two steps
+    away along the same axis: the next-nearest-neighbour amplitudes of the production model
+    (t_tilde_{h,alpha} along x, t_tilde_{v,alpha} along y), read as on-axis hops because the
+    paper names them by direction (horizontal, vertical); zero by default;
   * mu[alpha] is a per-band chemical potential;
   * lam is the Yukawa coefficient g of Eq. (17) (no 1/sqrt(N_f));
   * the ordering-vector phase exp(i Q_AF . r) with Q_AF = (pi, pi) is (-1)^(x+y),
@@ -28,6 +31,7 @@ class Model:
     dtau: float = 0.1
     t: tuple = ((1.0, 0.5), (0.5, 1.0))   # t[band][direction]
     mu: tuple = (0.5, 0.5)                # mu[band]
+    tn: tuple = ((0.0, 0.0), (0.0, 0.0))  # tn[band][direction]: hop by two sites
     lam: float = 1.0                      # Yukawa coefficient g of Eq. (17)
     r: float = 0.0                        # boson mass squared, Eq. (2)
     c: float = 1.0                        # boson velocity, Eq. (2)

@@ -26,14 +26,15 @@ def kinetic_symbol(m):
     exp(i w_n tau) exp(2 pi i (kx x + ky y) / L), w_n = pi (2 n + 1) / N_tau.
 
     On that wave the diagonal gives -(1 + dtau mu_band), the time link (with its sign on the
-    wrap) gives exp(i w_n), and the hopping gives -2 dtau sum_d t[band][d] cos(k_d):
-    K_hat = exp(i w_n) - b,  b = 1 + dtau (mu_band + 2 t[band][0] cos k_x + 2 t[band][1] cos k_y).
+    wrap) gives exp(i w_n), and the hopping gives -2 dtau sum_d (t[band][d] cos(k_d) +
+    tn[band][d] cos(2 k_d)): K_hat = exp(i w_n) - b, b = 1 + dtau (mu_band + those sums).
     """
     w = np.pi * (2 * np.arange(m.Lt) + 1) / m.Lt
     k = 2 * np.pi * np.arange(m.L) / m.L
     out = np.empty((2, m.Lt, m.L, m.L), dtype=complex)
     for a in range(2):
-        eps = 2 * m.t[a][0] * np.cos(k)[:, None] + 2 * m.t[a][1] * np.cos(k)[None, :]
+        eps = (2 * m.t[a][0] * np.cos(k)[:, None] + 2 * m.t[a][1] * np.cos(k)[None, :]
+               + 2 * m.tn[a][0] * np.cos(2 * k)[:, None] + 2 * m.tn[a][1] * np.cos(2 * k)[None, :])
         b = 1.0 + m.dtau * (m.mu[a] + eps)
         out[a] = np.exp(1j * w)[:, None, None] - b[None, :, :]
     return out

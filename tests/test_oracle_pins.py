@@ -324,3 +324,79 @@ def test_pcg_matches_dense_solve_in_fewer_iterations(tiny_inputs):
     assert np.linalg.norm(x.ravel() - xd) <= 1e-9 * np.linalg.norm(xd)
     _, it_cg, _ = O.cg_solve(m, phi0, b, tol=1e-11)
     assert it < it_cg
+
+
+# ---------------------------------------------------------------- production model (NNN hopping)
+# The nesting-parameter set v_1 of the paper's production runs: nearest-neighbour hopping only
+# horizontal for band x and vertical for band y, next-nearest-neighbour (two sites along an
+# axis) t_tilde_{v,x} = -t_tilde_{h,y} = 0.45, mu_x = -mu_y = -0.47.
+PROD = dict(t=((1.0, 0.0), (0.0, 1.0)), tn=((0.0, 0.45), (-0.45, 0.0)), mu=(-0.47, 0.47))
+
+
+@pytest.mark.parametrize("L", [4, 6])
+def test_nnn_entries_by_hand(L):
+    """The hop by two sites along y of band x is -dtau * 0.45, and -dtau * 0.45 twice over
+    when L = 4 (where y + 2 and y - 2 are the same site); along x it is zero for band x."""
+    m = O.Model(L=L, Lt=3, lam=0.0, **PROD)
+    D = O.dense_M(m, np.zeros(m.phi_shape()))
+    idx = O.spinor_index
+    twice = 2.0 if L == 4 else 1.0
+    row = idx(m, 0, 1, 1, 2, 1)
+    assert D[row, idx(m, 0, 1, 1, 2, 3)] == pytest.approx(-m.dtau * 0.45 * twice, abs=1e-16)
+    assert D[row, idx(m, 0, 1, 1, 2, (1 - 2) % L)] == pytest.approx(-m.dtau * 0.45 * twice, abs=1e-16)
+    assert D[row, idx(m, 0, 1, 1, (2 + 2) % L, 1)] == 0.0
+    assert D[row, idx(m, 0, 1, 1, 3, 1)] == pytest.approx(-m.dtau * 1.0, abs=1e-16)
+    assert D[row, idx(m, 0, 1, 1, 2, 2)] == 0.0                       # no vertical NN for band x
+    row = idx(m, 1, 0, 2, 1, 1)
+    assert D[row, idx(m, 1, 0, 2, 3, 1)] == pytest.approx(+m.dtau * 0.45 * twice, abs=1e-16)
+    assert D[row, idx(m, 1, 0, 2, 1, 2)] == pytest.approx(-m.dtau * 1.0, abs=1e-16)
+    assert D[row, row] == pytest.approx(-1.0 - m.dtau * 0.47, abs=1e-16)
+
+
+def test_nnn_dense_matches_matrix_free_and_free_limit():
+    m = O.Model(L=6, Lt=4, lam=0.7 * np.sqrt(2), **PROD)
+    g = S.rng(61)
+    phi = S.draw_phi(g, 6, 4, 1.0)
+    D = O.dense_M(m, phi)
+    for v in S.draw_spinor(g, 6, 4, 2):
+        assert np.abs(D @ v.ravel() - O.apply_M(m, phi, v).ravel()).max() < 1e-13
+        assert np.abs(D.conj().T @ v.ravel() - O.apply_Mdag(m, phi, v).ravel()).max() < 1e-13
+    m0 = O.Model(L=6, Lt=4, lam=0.0, **PROD)
+    A = O.dense_MdagM(m0, np.zeros(m0.phi_shape()))
+    assert abs(np.linalg.slogdet(A)[1] - C.free_logdet_MdagM(m0)) < 1e-10
+    assert np.abs(np.sort(np.linalg.eigvalsh(A)) - C.free_spectrum_MdagM(m0)).max() < 1e-12
+
+
+def test_nnn_kinetic_symbol_and_preconditioner():
+    m = O.Model(L=6, Lt=5, **PROD)
+    K = O.dense_M(m, np.zeros(m.phi_shape()))
+    Kh = O.kinetic_symbol(m)
+    for band, spin, n, kx, ky in [(0, 0, 0, 0, 0), (1, 1, 4, 2, 5), (0, 1, 2, 3, 1), (1, 0, 1, 5, 3)]:
+        v = _plane_wave(m, band, spin, n, kx, ky).ravel()
+        assert np.allclose(K @ v, Kh[band, n, kx, ky] * v, atol=1e-13)
+    m = O.Model(L=4, Lt=6, **PROD)
+    K = O.dense_M(m, np.zeros(m.phi_shape()))
+    KK = K.conj().T @ K
+    PK = np.stack([O.apply_precond(m, KK[:, j]).ravel() for j in range(m.dim)], axis=1)
+    assert np.abs(PK - np.eye(m.dim)).max() < 1e-12
+
+
+def test_nnn_determinant_real_positive_and_force_fd():
+    """The inter-band anti-unitary symmetry keeps det M real and positive with these
+    hoppings too (they are real and band-symmetric in the way the symmetry needs); the
+    gradient matches central differences."""
+    m = O.Model(L=4, Lt=4, lam=0.7 * np.sqrt(2), **PROD)
+    g = S.rng(62)
+    phi = S.draw_phi(g, 4, 4, 1.0)
+    sign, logabs = np.linalg.slogdet(O.dense_M(m, phi))
+    assert abs(sign.imag) < 1e-10 and sign.real > 0
+    eta = S.draw_eta(g, 4, 4, 1)[0]
+    chi = O.heatbath(m, phi, eta)
+    F, xs, _ = O.total_force(m, phi, [chi])
+    h = 1e-5
+    for (l, t, x, y) in [(0, 1, 2, 3), (2, 3, 0, 1)]:
+        e = np.zeros_like(phi)
+        e[l, t, x, y] = h
+        Sp = O.pf_action_dense(m, phi + e, [chi]) + O.boson_action(m, phi + e)
+        Sm = O.pf_action_dense(m, phi - e, [chi]) + O.boson_action(m, phi - e)
+        assert F[l, t, x, y] == pytest.approx((Sp - Sm) / (2 * h), rel=1e-6, abs=1e-8)
