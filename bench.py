@@ -163,6 +163,43 @@ def cpu_info():
     return model, os.cpu_count()
 
 
+# The paper's production model, nesting set v_1 (hops by two sites along an axis).
+PROD_MODEL = dict(t=((1.0, 0.0), (0.0, 1.0)), tn=((0.0, 0.45), (-0.45, 0.0)), mu=(-0.47, 0.47),
+                  lam=0.7 * 2 ** 0.5, c=3.0, r=1.26, u=0.0)
+
+
+def prod_bench(hmcmod, torch, L, Lt, common, phi0, d_traj):
+    """The production model at the workload size: one mixed solve of M^dag M x = M^dag eta
+    plain and Fourier-preconditioned, with the sampled kernel times of the instantiations
+    that read the sites two steps away (same algorithmic bytes as the nearest-neighbour
+    kernels: the extra neighbours are re-reads)."""
+    dev = torch.device("cuda")
+    out = {}
+    phi = torch.from_numpy(phi0).to(dev)
+    vol = Lt * L * L
+    for pc in (None, "fourier"):
+        h = hmcmod.HMC(L, Lt, precision="mixed", precond=pc, model=PROD_MODEL, **common)
+        chi = h.heatbath(phi, d_traj[0][1])
+        h.cg_solve(phi, chi)
+        h.set_kernel_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = h.cg_solve(phi, chi)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kt = h.kernel_times()
+        rec = {"ms": 1e3 * el, "iterations": st.iterations[0], "true_resid": st.true_resid[0]}
+        for name in ("cg_a_f32", "cg_b_f32"):
+            ms, n = kt[name]
+            if ms:
+                bps = BYTES_PER_SITE[name]
+                rec[name] = {"avg_ms": ms, "samples": n, "GB/s": bps * vol / (ms * 1e-3) / 1e9}
+        out["solve_" + (pc or "plain")] = rec
+        log(f"production model, mixed solve precond={pc}: {1e3 * el:.1f} ms, {st.iterations[0]} iterations")
+        h.close()
+    return out
+
+
 def metric_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, seed, reps=20):
     """The Fourier-diagonal metric at the workload size: the metric estimated (Eq. 30) from
     the starting field and the first momenta, the momentum draw, the kinetic energy and one
@@ -538,6 +575,7 @@ def main():
             extras["mixed_vs_fp64_traj_speedup"] = extras["traj_per_hour_mixed"] / extras["traj_per_hour_fp64"]
         extras["pcg_80x80x200"] = pcg_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, W, args.pcg_steps)
         extras["metric_80x80x200"] = metric_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, args.seed)
+        extras["production_model_80x80x200"] = prod_bench(hmcmod, torch, L, Lt, common, phi0, d_traj)
         for f32 in (True, False):
             aps, gbs, ms, nsets = apply_bench(hmcmod, torch, L, Lt, f32, args.apply_reps, args.seed + 1)
             extras["mdagm_apply_" + ("f32" if f32 else "f64")] = {

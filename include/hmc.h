@@ -78,6 +78,10 @@ typedef struct hmc_params {
                             slice (FP64 in FP64 solves) that fits the GPU's LDS
                             (L <= 100 on gfx950) and L_tau <= 320 (mixed) or 256 (FP64);
                             otherwise HMC_ERR_INVALID_ARG                                */
+    double tn[2][2];     /* hopping by two sites along direction d, tn[band][d]: the
+                            next-nearest-neighbour terms of the production model (the
+                            paper's t_tilde_{h,alpha} along x, t_tilde_{v,alpha} along y);
+                            zero for the nearest-neighbour model                         */
 } hmc_params;
 
 /* Per-solve statistics (host struct filled by the solver entry points). */

@@ -59,6 +59,7 @@ class HmcParams(ctypes.Structure):
         ("reliable_every", ctypes.c_int),
         ("max_rhs", ctypes.c_int),
         ("precond", ctypes.c_int),
+        ("tn", (ctypes.c_double * 2) * 2),
     ]
 
 

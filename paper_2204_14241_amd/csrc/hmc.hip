@@ -239,6 +239,12 @@ static Coef<double> coef64_of(double dt, const hmc_params& p) {
         for (int d = 0; d < 2; ++d) cf.hop[a][d] = -dt * p.t[a][d];
     }
     cf.cpl = dt * p.lambda;
+    cf.nn2 = 0;
+    for (int a = 0; a < 2; ++a)
+        for (int d = 0; d < 2; ++d) {
+            cf.hop2[a][d] = -dt * p.tn[a][d];
+            if (p.tn[a][d] != 0.0) cf.nn2 = 1;
+        }
     return cf;
 }
 
@@ -248,9 +254,13 @@ static void set_coefs(hmc_ctx* c) {
     c->cf64 = coef64_of(dt, p);
     for (int a = 0; a < 2; ++a) {
         c->cf32.diag[a] = float(c->cf64.diag[a]);
-        for (int d = 0; d < 2; ++d) c->cf32.hop[a][d] = float(c->cf64.hop[a][d]);
+        for (int d = 0; d < 2; ++d) {
+            c->cf32.hop[a][d] = float(c->cf64.hop[a][d]);
+            c->cf32.hop2[a][d] = float(c->cf64.hop2[a][d]);
+        }
     }
     c->cf32.cpl = float(c->cf64.cpl);
+    c->cf32.nn2 = c->cf64.nn2;
     c->bc = boson_coef_of(dt, p.c, p.r, p.u);
     c->generation += 1;
 }
@@ -263,7 +273,8 @@ static int check_params(const hmc_params* p) {
     for (int a = 0; a < 2; ++a) {
         if (!std::isfinite(p->mu[a])) return fail(HMC_ERR_INVALID_ARG, "non-finite mu");
         for (int d = 0; d < 2; ++d)
-            if (!std::isfinite(p->t[a][d])) return fail(HMC_ERR_INVALID_ARG, "non-finite hopping");
+            if (!std::isfinite(p->t[a][d]) || !std::isfinite(p->tn[a][d]))
+                return fail(HMC_ERR_INVALID_ARG, "non-finite hopping");
     }
     if (p->n_pf < 0 || p->n_pf > HMC_MAX_RHS) return fail(HMC_ERR_INVALID_ARG, "n_pf out of range [0, %d]", HMC_MAX_RHS);
     if (p->max_rhs < 0 || p->max_rhs > HMC_MAX_RHS) return fail(HMC_ERR_INVALID_ARG, "max_rhs out of range");
@@ -462,6 +473,7 @@ struct Launch {
     int ncg = 0, npxy = 0, npt = 0;
     size_t lds_xy = 0, lds_t = 0;
     int pt_threads = 0;   // tau-pass workgroup size (64 columns x chunks per column)
+    bool nn2 = false;     // the operator hops by two sites (the instantiations with those terms)
     bool pc = false;
     bool r7 = false;      // some lattice extent has a factor 7 (radix-7 FFT stages)
 };
@@ -482,6 +494,7 @@ static Launch<GeoOne> launch_one(const hmc_ctx* c, int n) {
     l.lds_xy = c->lds_xy[pi];
     l.lds_t = c->lds_t[pi];
     l.pt_threads = kPcCols * c->pc_q[pi];
+    l.nn2 = c->cf64.nn2 != 0;
     l.r7 = c->pc_r7;
     return l;
 }
@@ -500,6 +513,7 @@ static Launch<GeoBatch> launch_batch(const hmc_ctx* c) {
     l.lds_xy = c->lds_xy[pi];
     l.lds_t = c->lds_t[pi];
     l.pt_threads = kPcCols * c->pc_q[pi];
+    l.nn2 = c->cf64.nn2 != 0;
     l.r7 = c->pc_r7;
     return l;
 }
@@ -538,6 +552,18 @@ static CgCtl next_ctl(hmc_ctx* c, int expect) {
 }
 
 static const CgState* current_states(const hmc_ctx* c) { return c->st + size_t(c->seq & 1) * c->nunits; }
+
+// Launch the instantiation of a stencil kernel with or without the hops by two sites.
+#define HMC_LAUNCH_NN2(nn2, KT, KF, ...)           \
+    do {                                          \
+        if (nn2) hipLaunchKernelGGL(KT, __VA_ARGS__); \
+        else hipLaunchKernelGGL(KF, __VA_ARGS__);     \
+    } while (0)
+#define HMC_EXT_LAUNCH_NN2(nn2, KT, KF, ...)           \
+    do {                                              \
+        if (nn2) hipExtLaunchKernelGGL(KT, __VA_ARGS__); \
+        else hipExtLaunchKernelGGL(KF, __VA_ARGS__);     \
+    } while (0)
 
 // Launch kernel k; with events e, start/stop timestamps of pass q come from its own dispatch.
 template <typename... P, typename... A>
@@ -599,24 +625,32 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
             // timestamps from the dispatches themselves (not captured into graphs)
             hipEvent_t* e = c->tev[kslot];
             if constexpr (sizeof(R) == sizeof(float)) {
-                hipExtLaunchKernelGGL(k_cg_a2<Geo>, dim3(grid), dim3(kBlock), 0, s, e[0], e[1], 0, ka, geo, v, phik, cf);
+                HMC_EXT_LAUNCH_NN2(lc.nn2, (k_cg_a2<Geo, true>), (k_cg_a2<Geo, false>), dim3(grid), dim3(kBlock), 0, s,
+                                   e[0], e[1], 0, ka, geo, v, phik, cf);
                 LAUNCHCHK();
-                hipExtLaunchKernelGGL(k_cg_b2<Geo>, dim3(grid), dim3(kBlock), 0, s, e[2], e[3], 0, kb, geo, v, phik, cf);
+                HMC_EXT_LAUNCH_NN2(lc.nn2, (k_cg_b2<Geo, true>), (k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0, s,
+                                   e[2], e[3], 0, kb, geo, v, phik, cf);
             } else {
-                hipExtLaunchKernelGGL(k_cg_a<R, Geo>, dim3(grid), dim3(kBlock), 0, s, e[0], e[1], 0, ka, geo, v, phik, cf);
+                HMC_EXT_LAUNCH_NN2(lc.nn2, (k_cg_a<R, Geo, true>), (k_cg_a<R, Geo, false>), dim3(grid), dim3(kBlock), 0,
+                                   s, e[0], e[1], 0, ka, geo, v, phik, cf);
                 LAUNCHCHK();
-                hipExtLaunchKernelGGL(k_cg_b<R, Geo>, dim3(grid), dim3(kBlock), 0, s, e[2], e[3], 0, kb, geo, v, phik, cf);
+                HMC_EXT_LAUNCH_NN2(lc.nn2, (k_cg_b<R, Geo, true>), (k_cg_b<R, Geo, false>), dim3(grid), dim3(kBlock), 0,
+                                   s, e[2], e[3], 0, kb, geo, v, phik, cf);
             }
             LAUNCHCHK();
         } else {
             if constexpr (sizeof(R) == sizeof(float)) {
-                hipLaunchKernelGGL(k_cg_a2<Geo>, dim3(grid), dim3(kBlock), 0, s, ka, geo, v, phik, cf);
+                HMC_LAUNCH_NN2(lc.nn2, (k_cg_a2<Geo, true>), (k_cg_a2<Geo, false>), dim3(grid), dim3(kBlock), 0, s, ka,
+                               geo, v, phik, cf);
                 LAUNCHCHK();
-                hipLaunchKernelGGL(k_cg_b2<Geo>, dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
+                HMC_LAUNCH_NN2(lc.nn2, (k_cg_b2<Geo, true>), (k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0, s, kb,
+                               geo, v, phik, cf);
             } else {
-                hipLaunchKernelGGL((k_cg_a<R, Geo>), dim3(grid), dim3(kBlock), 0, s, ka, geo, v, phik, cf);
+                HMC_LAUNCH_NN2(lc.nn2, (k_cg_a<R, Geo, true>), (k_cg_a<R, Geo, false>), dim3(grid), dim3(kBlock), 0, s,
+                               ka, geo, v, phik, cf);
                 LAUNCHCHK();
-                hipLaunchKernelGGL((k_cg_b<R, Geo>), dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
+                HMC_LAUNCH_NN2(lc.nn2, (k_cg_b<R, Geo, true>), (k_cg_b<R, Geo, false>), dim3(grid), dim3(kBlock), 0, s,
+                               kb, geo, v, phik, cf);
             }
             LAUNCHCHK();
         }
@@ -628,11 +662,11 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
     hipLaunchKernelGGL((k_ru_fold<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, lc.pc ? PEND_NONE : PEND_RR),
                        geo, x, v, filter);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_ru_apply<Geo>, dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), geo, x,
-                       c->t64, phi64, c->cf64, filter);
+    HMC_LAUNCH_NN2(lc.nn2, (k_ru_apply<Geo, true>), (k_ru_apply<Geo, false>), dim3(grid), dim3(kBlock), 0, s,
+                   next_ctl(c, PEND_NONE), geo, x, c->t64, phi64, c->cf64, filter);
     LAUNCHCHK();
-    hipLaunchKernelGGL((k_ru_resid<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), geo,
-                       b, c->t64, phi64, c->cf64, v.r, filter);
+    HMC_LAUNCH_NN2(lc.nn2, (k_ru_resid<R, Geo, true>), (k_ru_resid<R, Geo, false>), dim3(grid), dim3(kBlock), 0,
+                   s, next_ctl(c, PEND_NONE), geo, b, c->t64, phi64, c->cf64, v.r, filter);
     LAUNCHCHK();
     if (lc.pc) {
         int rc = enqueue_pc<R, Geo>(c, lc, v, PEND_RU, s);
@@ -835,24 +869,25 @@ static void merge_stats(hmc_traj_stats* t, const hmc_cg_stats& cs) {
 // Applies M (DAG false) or M^dagger to every unit; FP64 or FP32 pair kernels.
 template <typename R, bool DAG>
 static int launch_apply(hmc_ctx* c, const R* phi, const void* in, void* out, int n, hipStream_t s) {
+    const bool nn2 = c->cf64.nn2 != 0;
     if constexpr (sizeof(R) == sizeof(double)) {
         if (c->is_batch)
-            hipLaunchKernelGGL((k_apply<double, DAG, GeoBatch>), dim3(c->bi.nblocks[0]), dim3(kBlock), 0, s,
-                               geo_batch(c, 0), static_cast<const double2*>(in), static_cast<double2*>(out),
-                               phi, c->cf64);
+            HMC_LAUNCH_NN2(nn2, (k_apply<double, DAG, GeoBatch, true>), (k_apply<double, DAG, GeoBatch, false>),
+                           dim3(c->bi.nblocks[0]), dim3(kBlock), 0, s, geo_batch(c, 0),
+                           static_cast<const double2*>(in), static_cast<double2*>(out), phi, c->cf64);
         else
-            hipLaunchKernelGGL((k_apply<double, DAG, GeoOne>), dim3(c->nblk * n), dim3(kBlock), 0, s,
-                               geo_one(c, c->nblk), static_cast<const double2*>(in),
-                               static_cast<double2*>(out), phi, c->cf64);
+            HMC_LAUNCH_NN2(nn2, (k_apply<double, DAG, GeoOne, true>), (k_apply<double, DAG, GeoOne, false>),
+                           dim3(c->nblk * n), dim3(kBlock), 0, s, geo_one(c, c->nblk),
+                           static_cast<const double2*>(in), static_cast<double2*>(out), phi, c->cf64);
     } else {
         if (c->is_batch)
-            hipLaunchKernelGGL((k_apply2<DAG, GeoBatch>), dim3(c->bi.nblocks[1]), dim3(kBlock), 0, s,
-                               geo_batch(c, 1), static_cast<const float2*>(in), static_cast<float2*>(out),
-                               phi, c->cf32);
+            HMC_LAUNCH_NN2(nn2, (k_apply2<DAG, GeoBatch, true>), (k_apply2<DAG, GeoBatch, false>),
+                           dim3(c->bi.nblocks[1]), dim3(kBlock), 0, s, geo_batch(c, 1),
+                           static_cast<const float2*>(in), static_cast<float2*>(out), phi, c->cf32);
         else
-            hipLaunchKernelGGL((k_apply2<DAG, GeoOne>), dim3(c->nblk2 * n), dim3(kBlock), 0, s,
-                               geo_one(c, c->nblk2), static_cast<const float2*>(in),
-                               static_cast<float2*>(out), phi, c->cf32);
+            HMC_LAUNCH_NN2(nn2, (k_apply2<DAG, GeoOne, true>), (k_apply2<DAG, GeoOne, false>),
+                           dim3(c->nblk2 * n), dim3(kBlock), 0, s, geo_one(c, c->nblk2),
+                           static_cast<const float2*>(in), static_cast<float2*>(out), phi, c->cf32);
     }
     LAUNCHCHK();
     return HMC_OK;
@@ -862,11 +897,11 @@ static int launch_force(hmc_ctx* c, const double* phi, const double2* x, int npf
                         double* force, double* pi, double h, int nkick, hipStream_t s) {
     const int do_pf = (flags & HMC_FORCE_PF) ? 1 : 0, do_b = (flags & HMC_FORCE_BOSON) ? 1 : 0;
     if (c->is_batch)
-        hipLaunchKernelGGL(k_force<CGeoBatch>, dim3(c->ngblk), dim3(kBlock), 0, s, cgeo_batch(c), x, phi,
-                           c->cf64, do_pf, do_b, force, pi, h, nkick);
+        HMC_LAUNCH_NN2(c->cf64.nn2, (k_force<CGeoBatch, true>), (k_force<CGeoBatch, false>), dim3(c->ngblk),
+                       dim3(kBlock), 0, s, cgeo_batch(c), x, phi, c->cf64, do_pf, do_b, force, pi, h, nkick);
     else
-        hipLaunchKernelGGL(k_force<CGeoOne>, dim3(c->nblk), dim3(kBlock), 0, s, cgeo_one(c, npf), x, phi,
-                           c->cf64, do_pf, do_b, force, pi, h, nkick);
+        HMC_LAUNCH_NN2(c->cf64.nn2, (k_force<CGeoOne, true>), (k_force<CGeoOne, false>), dim3(c->nblk),
+                       dim3(kBlock), 0, s, cgeo_one(c, npf), x, phi, c->cf64, do_pf, do_b, force, pi, h, nkick);
     LAUNCHCHK();
     return HMC_OK;
 }

@@ -359,7 +359,7 @@ __device__ __forceinline__ void cg_publish(const CgCtl& c, const UPos& pos) {
 //   (M^+ psi)_c   = the same with sbwd psi_c(tau-1)
 //   Yukawa (band a, spin s) = dtau lambda (-1)^(x+y) sum_s' (phi . Pauli)_{s s'} psi_{other band, s'}
 // with phi . Pauli = [[phi3, phi1 - i phi2], [phi1 + i phi2, -phi3]].
-template <typename R, bool DAG, class Src>
+template <typename R, bool DAG, bool NN2, class Src>
 __device__ __forceinline__ void dslash_site(const Src& src, const R* __restrict__ phi,
                                             const Lat& lat, const Coef<R>& cf, const Nbr& nb,
                                             int s, C2<R> (&out)[4], C2<R> (&cen)[4]) {
@@ -379,6 +379,15 @@ __device__ __forceinline__ void dslash_site(const Src& src, const R* __restrict_
         o = axpy<R>(cf.hop[a][1], hy, o);
         o = axpy<R>(ts, tt, o);
         out[c] = o;
+    }
+    if constexpr (NN2) {   // hops by two sites along each axis (the production model's NNN terms)
+        const Nbr2 n2 = neighbours2(lat, nb, s);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int a = c >> 1;
+            out[c] = axpy<R>(cf.hop2[a][0], add<R>(src(c, n2.xpp), src(c, n2.xmm)), out[c]);
+            out[c] = axpy<R>(cf.hop2[a][1], add<R>(src(c, n2.ypp), src(c, n2.ymm)), out[c]);
+        }
     }
     const R g = cf.cpl * R(nb.stag);
     const R q1 = g * phi[s], q2 = g * phi[vol + s], q3 = g * phi[2 * vol + s];
@@ -416,7 +425,7 @@ struct SrcXpay {
 // ------------------------------------------------------------------------------------
 // out = M in (or M^dagger) for every unit of the geometry; workgroup b of a unit takes its
 // 256-site tiles b, b + bpr, ...
-template <typename R, bool DAG, class Geo>
+template <typename R, bool DAG, class Geo, bool NN2>
 __global__ __launch_bounds__(kBlock) void k_apply(Geo geo, const C2<R>* __restrict__ in,
                                                   C2<R>* __restrict__ out,
                                                   const R* __restrict__ phi_base, Coef<R> cf) {
@@ -432,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo geo, const C2<R>* __restri
         if (s >= lat.vol) break;
         const Nbr nb = neighbours(lat, s);
         C2<R> o[4], cen[4];
-        dslash_site<R, DAG>(src, phi, lat, cf, nb, s, o, cen);
+        dslash_site<R, DAG, NN2>(src, phi, lat, cf, nb, s, o, cen);
 #pragma unroll
         for (int c = 0; c < 4; ++c) dst[c * lat.vol + s] = o[c];
     }
@@ -459,7 +468,7 @@ __device__ __forceinline__ void store_partial(const CgCtl& c, int kind, const UP
 // CG step A (iteration k):  x += alpha_{k-1} p_{k-1};  p_k = r_k + beta_{k-1} p_{k-1};
 // t = M p_k;  partial |t|^2 = <p_k, M^dagger M p_k>.  p is double-buffered because
 // neighbouring sites read the old direction.
-template <typename R, class Geo>
+template <typename R, class Geo, bool NN2>
 __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, Geo geo, CgVecs<R> v,
                                                  const R* __restrict__ phi_base, Coef<R> cf) {
     const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
@@ -486,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, Geo geo, CgVecs<R> v
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
             C2<R> o[4], pn[4];
-            dslash_site<R, false>(src, phi, lat, cf, nb, s, o, pn);
+            dslash_site<R, false, NN2>(src, phi, lat, cf, nb, s, o, pn);
             R acc = R(0);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -510,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, Geo geo, CgVecs<R> v
 }
 
 // CG step B:  r -= alpha_k M^dagger t;  partial |r|^2.
-template <typename R, class Geo>
+template <typename R, class Geo, bool NN2>
 __global__ __launch_bounds__(kBlock) void k_cg_b(CgCtl ctl, Geo geo, CgVecs<R> v,
                                                  const R* __restrict__ phi_base, Coef<R> cf) {
     const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
@@ -533,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(CgCtl ctl, Geo geo, CgVecs<R> v
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
             C2<R> o[4], cen[4];
-            dslash_site<R, true>(src, phi, lat, cf, nb, s, o, cen);
+            dslash_site<R, true, NN2>(src, phi, lat, cf, nb, s, o, cen);
             R acc = R(0);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -593,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_fold(CgCtl ctl, Geo geo, double2*
 }
 
 // Reliable update, part 2: t64 = M x64 (FP64) for right-hand sides in `filter`.
-template <class Geo>
+template <class Geo, bool NN2>
 __global__ __launch_bounds__(kBlock) void k_ru_apply(CgCtl ctl, Geo geo, const double2* __restrict__ x64,
                                                      double2* __restrict__ t64,
                                                      const double* __restrict__ phi_base,
@@ -613,7 +622,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_apply(CgCtl ctl, Geo geo, const d
         if (s >= lat.vol) break;
         const Nbr nb = neighbours(lat, s);
         double2 o[4], cen[4];
-        dslash_site<double, false>(src, phi, lat, cf, nb, s, o, cen);
+        dslash_site<double, false, NN2>(src, phi, lat, cf, nb, s, o, cen);
 #pragma unroll
         for (int c = 0; c < 4; ++c) t64[off + size_t(c) * lat.vol + s] = o[c];
     }
@@ -621,7 +630,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_apply(CgCtl ctl, Geo geo, const d
 
 // Reliable update, part 3: r = b - M^dagger t64 in FP64, stored in the Krylov precision;
 // partial |r|^2 in FP64 (reduced by the next kernel: DONE, STOPPED or back to ACTIVE).
-template <typename R, class Geo>
+template <typename R, class Geo, bool NN2>
 __global__ __launch_bounds__(kBlock) void k_ru_resid(CgCtl ctl, Geo geo, const double2* __restrict__ b,
                                                      const double2* __restrict__ t64,
                                                      const double* __restrict__ phi_base,
@@ -644,7 +653,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_resid(CgCtl ctl, Geo geo, const d
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
             double2 o[4], cen[4];
-            dslash_site<double, true>(src, phi, lat, cf, nb, s, o, cen);
+            dslash_site<double, true, NN2>(src, phi, lat, cf, nb, s, o, cen);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const size_t i = off + size_t(c) * lat.vol + s;
@@ -745,7 +754,7 @@ struct SrcXpay2 {      // r + beta p
 };
 
 // The stencil of Eq. (17) at sites s (even) and s + 1 (lanes .x .y and .z .w of each float4).
-template <bool DAG, class Src>
+template <bool DAG, bool NN2, class Src>
 __device__ __forceinline__ void dslash_pair(const Src& src, const float* __restrict__ phi,
                                             const Lat& lat, const Coef<float>& cf, const Nbr& nb,
                                             int s, float4 (&out)[4], float4 (&cen)[4]) {
@@ -770,6 +779,22 @@ __device__ __forceinline__ void dslash_pair(const Src& src, const float* __restr
         o.w = dg * ce.w + h0 * (xp.w + xm.w) + h1 * (ce.y + hi.y) + ts * tt.w;
         out[c] = o;
     }
+    if constexpr (NN2) {
+        // hops by two sites: rows x +- 2 at the same pair, and the pairs (y - 2, y - 1) and
+        // (y + 2, y + 3), all aligned (y is even and so is L)
+        const Nbr2 n2 = neighbours2(lat, nb, s);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int a = c >> 1;
+            const float4 xx = f4add(src.pair(c, n2.xpp), src.pair(c, n2.xmm));
+            const float4 yy = f4add(src.pair(c, n2.ymm), src.pair(c, n2.ypp));
+            const float u0 = cf.hop2[a][0], u1 = cf.hop2[a][1];
+            out[c].x += u0 * xx.x + u1 * yy.x;
+            out[c].y += u0 * xx.y + u1 * yy.y;
+            out[c].z += u0 * xx.z + u1 * yy.z;
+            out[c].w += u0 * xx.w + u1 * yy.w;
+        }
+    }
     const float g0 = cf.cpl * float(nb.stag), g1 = -g0;     // (-1)^(x+y) flips between s, s+1
     const float2 P1 = *reinterpret_cast<const float2*>(phi + s);
     const float2 P2 = *reinterpret_cast<const float2*>(phi + vol + s);
@@ -791,7 +816,7 @@ __device__ __forceinline__ void dslash_pair(const Src& src, const float* __restr
 }
 
 // out_k = M in_k (or M^dagger), FP32, one 512-site tile per workgroup.
-template <bool DAG, class Geo>
+template <bool DAG, class Geo, bool NN2>
 __global__ __launch_bounds__(kBlock) void k_apply2(Geo geo, const float2* __restrict__ in,
                                                    float2* __restrict__ out,
                                                    const float* __restrict__ phi_base, Coef<float> cf) {
@@ -807,14 +832,14 @@ __global__ __launch_bounds__(kBlock) void k_apply2(Geo geo, const float2* __rest
         if (s >= lat.vol) break;
         const Nbr nb = neighbours(lat, s);
         float4 o[4], cen[4];
-        dslash_pair<DAG>(src, phi, lat, cf, nb, s, o, cen);
+        dslash_pair<DAG, NN2>(src, phi, lat, cf, nb, s, o, cen);
 #pragma unroll
         for (int c = 0; c < 4; ++c) st4(out + off, size_t(c) * lat.vol + s, o[c]);
     }
 }
 
 // CG step A, FP32 pair form (same algebra as k_cg_a).
-template <class Geo>
+template <class Geo, bool NN2>
 __global__ __launch_bounds__(kBlock) void k_cg_a2(CgCtl ctl, Geo geo, CgVecs<float> v,
                                                   const float* __restrict__ phi_base, Coef<float> cf) {
     const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
@@ -841,7 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a2(CgCtl ctl, Geo geo, CgVecs<flo
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
             float4 o[4], pn[4];
-            dslash_pair<false>(src, phi, lat, cf, nb, s, o, pn);
+            dslash_pair<false, NN2>(src, phi, lat, cf, nb, s, o, pn);
             float acc = 0.f;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -865,7 +890,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a2(CgCtl ctl, Geo geo, CgVecs<flo
 }
 
 // CG step B, FP32 pair form (same algebra as k_cg_b).
-template <class Geo>
+template <class Geo, bool NN2>
 __global__ __launch_bounds__(kBlock) void k_cg_b2(CgCtl ctl, Geo geo, CgVecs<float> v,
                                                   const float* __restrict__ phi_base, Coef<float> cf) {
     const UPos pos = geo.at(xcd_remap(blockIdx.x, gridDim.x));
@@ -888,7 +913,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_b2(CgCtl ctl, Geo geo, CgVecs<flo
         if (s < lat.vol) {
             const Nbr nb = neighbours(lat, s);
             float4 o[4], cen[4];
-            dslash_pair<true>(src, phi, lat, cf, nb, s, o, cen);
+            dslash_pair<true, NN2>(src, phi, lat, cf, nb, s, o, cen);
             float acc = 0.f;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -973,7 +998,7 @@ struct CGeoBatch {
     }
 };
 
-template <class CGeo>
+template <class CGeo, bool NN2>
 __global__ __launch_bounds__(kBlock) void k_force(CGeo geo, const double2* __restrict__ x_base,
                                                   const double* __restrict__ phi_base,
                                                   Coef<double> cf, int do_pf, int do_boson,
@@ -993,7 +1018,7 @@ __global__ __launch_bounds__(kBlock) void k_force(CGeo geo, const double2* __res
         for (int k = 0; k < pos.npf; ++k) {
             SrcPlain<double> src{x_base + pos.voff + size_t(k) * 4 * vol, vol};
             double2 Y[4], X[4];
-            dslash_site<double, false>(src, phi, lat, cf, nb, s, Y, X);
+            dslash_site<double, false, NN2>(src, phi, lat, cf, nb, s, Y, X);
             pauli_contract(Y[0], Y[1], X[2], X[3], f1, f2, f3);
             pauli_contract(Y[2], Y[3], X[0], X[1], f1, f2, f3);
         }

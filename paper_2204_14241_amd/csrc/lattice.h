@@ -74,6 +74,20 @@ __host__ __device__ __forceinline__ Nbr neighbours(const Lat& lat, int s) {
     return n;
 }
 
+// Sites two steps along each spatial axis (periodic): x +- 2 and y +- 2.
+struct Nbr2 {
+    int xpp, xmm, ypp, ymm;
+};
+__host__ __device__ __forceinline__ Nbr2 neighbours2(const Lat& lat, const Nbr& nb, int s) {
+    const int L = lat.L;
+    Nbr2 n;
+    n.xpp = nb.x + 2 < L ? s + 2 * L : s + 2 * L - L * L;
+    n.xmm = nb.x >= 2 ? s - 2 * L : s - 2 * L + L * L;
+    n.ypp = nb.y + 2 < L ? s + 2 : s + 2 - L;
+    n.ymm = nb.y >= 2 ? s - 2 : s - 2 + L;
+    return n;
+}
+
 // Hardware workgroup id -> logical tile id.  Workgroups go round-robin to the 8 XCDs
 // (bid % 8); this hands XCD j a contiguous range of logical tiles so that stencil
 // neighbours (the rows above/below and the next/previous time slice) are read through
@@ -117,6 +131,8 @@ struct Coef {
     R diag[2];      // -(1 + dtau mu_band)
     R hop[2][2];    // -dtau t[band][direction]
     R cpl;          // dtau * lambda (Yukawa)
+    R hop2[2][2];   // -dtau tn[band][direction]: hop by two sites along the axis
+    int nn2;        // some hop2 is nonzero (the stencils then read the distance-2 sites)
 };
 
 // Boson-action coefficients (Eq. 2, time term 1/(2 c^2)).

@@ -231,7 +231,9 @@ __host__ __device__ inline void chunk_close(const R* a, const C2<R>* c, C2<R>* x
 // cosx is indexed by position).
 __host__ __device__ inline double pc_column_b(int col, int L, int band, const double* cosx, const Coef<double>& cf) {
     const int px = col / L, py = col - px * L;
-    return -cf.diag[band] - 2.0 * (cf.hop[band][0] * cosx[px] + cf.hop[band][1] * cosx[py]);
+    const double cx = cosx[px], cy = cosx[py];
+    return -cf.diag[band] - 2.0 * (cf.hop[band][0] * cx + cf.hop[band][1] * cy) -
+           2.0 * (cf.hop2[band][0] * (2.0 * cx * cx - 1.0) + cf.hop2[band][1] * (2.0 * cy * cy - 1.0));
 }
 
 // Both recurrences on one thread's chunk, with the workgroup's map exchange in LDS (a, c, x:

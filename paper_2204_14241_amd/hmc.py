@@ -17,7 +17,8 @@ from . import _lib
 from ._lib import (HMC_FORCE_BOSON, HMC_FORCE_PF, HMC_FP64, HMC_MIXED, HmcCgStats, HmcParams,
                    HmcTrajStats, check)
 
-DEFAULT_MODEL = dict(t=((1.0, 0.5), (0.5, 1.0)), mu=(0.5, 0.5), lam=1.0, r=0.0, c=1.0, u=0.0)
+DEFAULT_MODEL = dict(t=((1.0, 0.5), (0.5, 1.0)), mu=(0.5, 0.5), lam=1.0, r=0.0, c=1.0, u=0.0,
+                     tn=((0.0, 0.0), (0.0, 0.0)))
 
 
 def _stream():
@@ -76,6 +77,7 @@ class HMC:
         for a in range(2):
             for d in range(2):
                 p.t[a][d] = float(m["t"][a][d])
+                p.tn[a][d] = float(m["tn"][a][d])
             p.mu[a] = float(m["mu"][a])
         p.lambda_ = float(m["lam"])
         p.r, p.c, p.u = float(m["r"]), float(m["c"]), float(m["u"])
@@ -597,6 +599,7 @@ def test_precond(L, Lt, v, dtau=0.1, model=None):
     for a in range(2):
         for d in range(2):
             p.t[a][d] = float(m["t"][a][d])
+            p.tn[a][d] = float(m["tn"][a][d])
         p.mu[a] = float(m["mu"][a])
     p.lambda_, p.r, p.c, p.u = float(m["lam"]), float(m["r"]), float(m["c"]), float(m["u"])
     v = np.ascontiguousarray(v, dtype=np.complex128)

@@ -48,3 +48,15 @@ def test_precond_rejects_unsupported_lattice():
     assert hmc.test_precond(4, 17, v) is None          # no FFT plan for 17
     w = np.zeros(4 * 260 * 4 * 4, dtype=complex)
     assert hmc.test_precond(4, 260, w) is None         # more than 16 chunks of 16 per column
+
+
+@pytest.mark.parametrize("L,Lt", [(6, 10), (8, 40)])
+def test_precond_with_nnn_hopping_matches_oracle(L, Lt):
+    """The production model's hops by two sites enter the per-column b of the tau pass."""
+    model = dict(t=((1.0, 0.0), (0.0, 1.0)), tn=((0.0, 0.45), (-0.45, 0.0)), mu=(-0.47, 0.47))
+    m = O.Model(L=L, Lt=Lt, **model)
+    v = S.draw_spinor(S.rng(9 * L + Lt), L, Lt, 1)[0]
+    out, rz = hmc.test_precond(L, Lt, v.ravel(), model=model)
+    ref = O.apply_precond(m, v).ravel()
+    assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert abs(rz - np.vdot(v.ravel(), ref).real) <= 1e-12 * abs(rz)
