@@ -68,6 +68,27 @@ def dense_M(m, phi):
     return D
 
 
+def apply_M_site(m, phi, psi, a, s, tau, x, y, dagger=False):
+    """One entry of M[phi] psi (or M^dagger psi): the row (a, s, tau, x, y) of Eq. (17) summed
+    term by term against psi (shape (2, 2, N_tau, L, L)).  For checks of very large lattices
+    at sampled sites, where the matrix-free operator over the whole lattice is too costly."""
+    L, Lt, dt = m.L, m.Lt, m.dtau
+    out = (-1.0 - dt * m.mu[a]) * psi[a, s, tau, x, y]
+    if not dagger:
+        sign = 1.0 - 2.0 * (tau == Lt - 1)
+        out += sign * psi[a, s, (tau + 1) % Lt, x, y]
+    else:
+        sign = 1.0 - 2.0 * (tau == 0)          # the link (tau - 1 -> tau), -1 on the wrap
+        out += sign * psi[a, s, (tau - 1) % Lt, x, y]
+    for dx, dy, d in ((1, 0, 0), (-1, 0, 0), (0, 1, 1), (0, -1, 1)):
+        out += -dt * m.t[a][d] * psi[a, s, tau, (x + dx) % L, (y + dy) % L]
+        out += -dt * m.tn[a][d] * psi[a, s, tau, (x + 2 * dx) % L, (y + 2 * dy) % L]
+    coup = dt * m.lam * (1.0 if (x + y) % 2 == 0 else -1.0) * _phi_dot_tau(phi[:, tau, x, y])
+    for s2 in range(2):
+        out += coup[s, s2] * psi[1 - a, s2, tau, x, y]
+    return out
+
+
 def dense_MdagM(m, phi):
     D = dense_M(m, phi)
     return D.conj().T @ D

@@ -400,3 +400,19 @@ def test_nnn_determinant_real_positive_and_force_fd():
         Sp = O.pf_action_dense(m, phi + e, [chi]) + O.boson_action(m, phi + e)
         Sm = O.pf_action_dense(m, phi - e, [chi]) + O.boson_action(m, phi - e)
         assert F[l, t, x, y] == pytest.approx((Sp - Sm) / (2 * h), rel=1e-6, abs=1e-8)
+
+
+def test_site_apply_matches_dense_rows():
+    """The one-row evaluator used at sampled sites of very large lattices equals the dense
+    matrix's rows (and its adjoint's), also with the production model's hops by two sites."""
+    for kw in [dict(), PROD]:
+        m = O.Model(L=6, Lt=4, lam=0.9, **kw)
+        g = S.rng(71)
+        phi = S.draw_phi(g, 6, 4, 1.0)
+        psi = S.draw_spinor(g, 6, 4, 1)[0]
+        D = O.dense_M(m, phi)
+        Mv, Mdv = D @ psi.ravel(), D.conj().T @ psi.ravel()
+        for (a, s, t, x, y) in [(0, 0, 0, 0, 0), (1, 1, 3, 5, 2), (0, 1, 2, 1, 5), (1, 0, 1, 4, 4)]:
+            row = O.spinor_index(m, a, s, t, x, y)
+            assert abs(O.fermion.apply_M_site(m, phi, psi, a, s, t, x, y) - Mv[row]) < 1e-14
+            assert abs(O.fermion.apply_M_site(m, phi, psi, a, s, t, x, y, dagger=True) - Mdv[row]) < 1e-14
