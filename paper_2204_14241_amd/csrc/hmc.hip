@@ -140,6 +140,7 @@ struct hmc_ctx {
     size_t lds_xy[2] = {0, 0}; // dynamic LDS of the preconditioner passes [FP64, FP32]
     size_t lds_t[2] = {0, 0};
     int pc_q[2] = {0, 0};      // chunks per column of the tau pass [FP64, FP32]
+    bool pc_full[2] = {false, false};   // every lattice's columns are pc_q full chunks
     long long blob_doubles = 0;    // preconditioner tables of all lattices
     bool pc_r7 = false;            // some lattice extent needs radix-7 FFT stages
     // Fourier-diagonal HMC metric (one lattice): the caller's sigma table (null: identity,
@@ -473,6 +474,8 @@ struct Launch {
     int ncg = 0, npxy = 0, npt = 0;
     size_t lds_xy = 0, lds_t = 0;
     int pt_threads = 0;   // tau-pass workgroup size (64 columns x chunks per column)
+    bool pt_full = false; // every chunk of the tau pass is full (the instantiation without
+                          // per-step predicates)
     bool nn2 = false;     // the operator hops by two sites (the instantiations with those terms)
     bool pc = false;
     bool r7 = false;      // some lattice extent has a factor 7 (radix-7 FFT stages)
@@ -494,6 +497,7 @@ static Launch<GeoOne> launch_one(const hmc_ctx* c, int n) {
     l.lds_xy = c->lds_xy[pi];
     l.lds_t = c->lds_t[pi];
     l.pt_threads = kPcCols * c->pc_q[pi];
+    l.pt_full = c->pc_full[pi];
     l.nn2 = c->cf64.nn2 != 0;
     l.r7 = c->pc_r7;
     return l;
@@ -513,6 +517,7 @@ static Launch<GeoBatch> launch_batch(const hmc_ctx* c) {
     l.lds_xy = c->lds_xy[pi];
     l.lds_t = c->lds_t[pi];
     l.pt_threads = kPcCols * c->pc_q[pi];
+    l.pt_full = c->pc_full[pi];
     l.nn2 = c->cf64.nn2 != 0;
     l.r7 = c->pc_r7;
     return l;
@@ -582,8 +587,12 @@ static int enqueue_pc_r(hmc_ctx* c, const Launch<Geo>& lc, const CgVecs<R>& v, i
     launch_timed(k_pc_xy<R, false, Geo, MAXR>, lc.npxy, kPcBlock, lc.lds_xy, s, e, 0,
                  next_ctl(c, expect1), lc.pxy, v.r, v.z, c->blob);
     LAUNCHCHK();
-    launch_timed(k_pc_t<R, Geo>, lc.npt, lc.pt_threads, lc.lds_t, s, e, 1,
-                 next_ctl(c, PEND_NONE), lc.pt, v.z, c->blob, c->cf64);
+    if (lc.pt_full)
+        launch_timed(k_pc_t<R, Geo, true>, lc.npt, lc.pt_threads, lc.lds_t, s, e, 1,
+                     next_ctl(c, PEND_NONE), lc.pt, v.z, c->blob, c->cf64);
+    else
+        launch_timed(k_pc_t<R, Geo, false>, lc.npt, lc.pt_threads, lc.lds_t, s, e, 1,
+                     next_ctl(c, PEND_NONE), lc.pt, v.z, c->blob, c->cf64);
     LAUNCHCHK();
     launch_timed(k_pc_xy<R, true, Geo, MAXR>, lc.npxy, kPcBlock, lc.lds_xy, s, e, 2,
                  next_ctl(c, PEND_RZ), lc.pxy, v.z, v.z, c->blob);
@@ -1086,7 +1095,7 @@ static void pc_setup(hmc_ctx* c) {
     c->bi.pcoff.assign(1, 0);
     c->bi.nslices = 0;
     c->bi.ngroups[0] = c->bi.ngroups[1] = 0;
-    for (int pi = 0; pi < 2; ++pi) c->lds_xy[pi] = c->lds_t[pi] = 0, c->pc_q[pi] = 0;
+    for (int pi = 0; pi < 2; ++pi) c->lds_xy[pi] = c->lds_t[pi] = 0, c->pc_q[pi] = 0, c->pc_full[pi] = false;
     for (const Lat& l : lats) {
         FftPlan pa, pb;
         const bool ok = make_fft_plan(l.L, pa) && make_fft_plan(l.Lt, pb);
@@ -1106,6 +1115,12 @@ static void pc_setup(hmc_ctx* c) {
         c->pc_q[1] = (q32 == 0 || c->pc_q[1] < 0) ? -1 : std::max(c->pc_q[1], q32);
     }
     c->blob_doubles = blob;
+    c->pc_full[0] = c->pc_q[0] > 0;
+    c->pc_full[1] = c->pc_q[1] > 0;
+    for (const Lat& l : lats) {
+        c->pc_full[0] = c->pc_full[0] && l.Lt == c->pc_q[0] * pc_chunk_max<double>();
+        c->pc_full[1] = c->pc_full[1] && l.Lt == c->pc_q[1] * pc_chunk_max<float>();
+    }
     c->lds_t[0] = c->pc_q[0] > 0 ? pc_tau_lds<double>(c->pc_q[0]) : 0;
     c->lds_t[1] = c->pc_q[1] > 0 ? pc_tau_lds<float>(c->pc_q[1]) : 0;
     for (int pi = 0; pi < 2; ++pi)
@@ -1132,7 +1147,8 @@ static void pc_lds_attributes_r(size_t xy, size_t t) {
     const hipFuncAttribute a = hipFuncAttributeMaxDynamicSharedMemorySize;
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pc_xy<R, false, Geo, MAXR>), a, int(xy));
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pc_xy<R, true, Geo, MAXR>), a, int(xy));
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pc_t<R, Geo>), a, int(t));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pc_t<R, Geo, false>), a, int(t));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pc_t<R, Geo, true>), a, int(t));
 }
 
 template <class Geo>
@@ -1455,38 +1471,44 @@ int hmc_test_precond(int L, int Lt, double dtau, const hmc_params* params, const
     }
     // the tau pass as the kernel runs it: Q chunks per column, each reduced to an affine map,
     // the maps closed around the cycle, the chunks rerun from their entering values
-    const int m = (Lt + Q - 1) / Q;
     double acc = 0.0;
     for (int c = 0; c < 4; ++c) {
         for (int col = 0; col < LL; ++col) {
-            const double b = pc_column_b(col, L, c >> 1, blob.data() + bl.cosx, cf), ib = 1.0 / b;
-            const bool small = b <= 1.0 && b >= -1.0;
+            const double b = pc_column_b(col, L, c >> 1, blob.data() + bl.cosx, cf);
+            const RecCoef<double> k = rec_coef(b);
             constexpr int QM = pc_max_chunks<double>();
             double2 ch[QM][MC], sc[QM], sx[QM + 1];
             double sa[QM];
-            int t0[QM], n[QM];
-            const bool rev = !small;   // chunks held in the order K^{-1} walks them
-            auto at = [&](int q, int j) { return size_t(c) * vol + size_t(t0[q] + (rev ? n[q] - 1 - j : j)) * LL + col; };
+            ChunkSpan sp[QM];
+            const bool rev = !k.before;   // chunks held in the order K^{-1} walks them
+            auto at = [&](int q, int j) {
+                return size_t(c) * vol + size_t(sp[q].t0 + (rev ? sp[q].n - 1 - j : j)) * LL + col;
+            };
             for (int q = 0; q < Q; ++q) {
-                t0[q] = std::min(q * m, Lt);
-                n[q] = std::min(m, Lt - t0[q]);
-                for (int j = 0; j < MC; ++j) ch[q][j] = j < n[q] ? w[at(q, j)] : make_double2(0.0, 0.0);
+                sp[q] = pc_chunk_span<double>(q, Lt);
+                for (int j = 0; j < MC; ++j) ch[q][j] = j < sp[q].n ? w[at(q, j)] : make_double2(0.0, 0.0);
             }
-            const SignK sk{Lt};
-            const SignKd skd{};
-            for (int q = 0; q < Q; ++q)
-                chunk_map<double, MC, true>(ch[q], n[q], t0[q], rev, b, ib, sk, small, sa[q], sc[q]);
-            chunk_close<double>(sa, sc, sx, Q, 1, small);
+            auto wk = [&](int q) { return sp[q].n > 0 && sp[q].t0 + sp[q].n == Lt; };
+            auto wkd = [&](int q) { return sp[q].n > 0 && sp[q].t0 == 0; };
             for (int q = 0; q < Q; ++q) {
-                chunk_apply<double, MC, true>(ch[q], n[q], t0[q], rev, b, ib, sk, small, sx[small ? q : q + 1]);
-                for (int j = 0; j < n[q]; ++j) acc += (ch[q][j].x * ch[q][j].x + ch[q][j].y * ch[q][j].y) / LL;
+                chunk_scale<double, MC>(ch[q], k.B);
+                chunk_map<double, MC, true>(ch[q], sp[q].n, k, sa[q], sc[q]);
+                wrap_map<double>(wk(q), k.before, sa[q], sc[q]);
             }
-            for (int q = 0; q < Q; ++q)
-                chunk_map<double, MC, false>(ch[q], n[q], t0[q], rev, b, ib, skd, small, sa[q], sc[q]);
-            chunk_close<double>(sa, sc, sx, Q, 1, !small);
+            chunk_close<double>(sa, sc, sx, Q, 1, k.before);
             for (int q = 0; q < Q; ++q) {
-                chunk_apply<double, MC, false>(ch[q], n[q], t0[q], rev, b, ib, skd, small, sx[small ? q + 1 : q]);
-                for (int j = 0; j < n[q]; ++j) w[at(q, j)] = make_double2(ch[q][j].x / LL, ch[q][j].y / LL);
+                chunk_apply<double, MC, true>(ch[q], sp[q].n, k, wrap_entry<double>(wk(q), k.before, sx[k.before ? q : q + 1]));
+                acc += chunk_norm2<double, MC>(ch[q], sp[q].n) / LL;
+            }
+            for (int q = 0; q < Q; ++q) {
+                chunk_scale<double, MC>(ch[q], k.B * (1.0 / LL));   // z with the 1 / L^2
+                chunk_map<double, MC, false>(ch[q], sp[q].n, k, sa[q], sc[q]);
+                wrap_map<double>(wkd(q), k.before, sa[q], sc[q]);
+            }
+            chunk_close<double>(sa, sc, sx, Q, 1, !k.before);
+            for (int q = 0; q < Q; ++q) {
+                chunk_apply<double, MC, false>(ch[q], sp[q].n, k, wrap_entry<double>(wkd(q), k.before, sx[k.before ? q + 1 : q]));
+                for (int j = 0; j < sp[q].n; ++j) w[at(q, j)] = ch[q][j];
             }
         }
     }

@@ -2,6 +2,8 @@
 // z = P r inside CG (transforms and tables in fft.h).
 #pragma once
 
+#include <type_traits>
+
 #include "fft.h"
 #include "kernels.h"
 
@@ -140,66 +142,110 @@ __global__ __launch_bounds__(kPcBlock) void k_pc_xy(CgCtl ctl, Geo geo, const C2
 // an affine map of the value entering it, one lane per column composes the Q maps around the
 // cycle (closing it through the wrap) and hands each chunk its entering value, and the
 // threads rerun their chunks from it.
-// Signs of the two recurrences at tau: s_tau (K) and s_{tau-1} (K^dagger).
-struct SignK {
-    int Lt;
-    __host__ __device__ int operator()(int t) const { return t == Lt - 1 ? -1 : 1; }
-};
-struct SignKd {
-    __host__ __device__ int operator()(int t) const { return t == 0 ? -1 : 1; }
-};
-
 // A thread's chunk: positions t0 .. t0 + n - 1 of its column in registers, v[j] holding
 // t0 + j, or t0 + n - 1 - j when rev (a lane whose K^{-1} runs backward keeps its chunk in
 // that order).  Both recurrences then walk the registers in a fixed order, K^{-1} up and
-// K^{-dagger} down, with compile-time register positions: the direction never depends on
-// the lane (a per-lane choice of register would put the chunk in scratch memory).
-// One step at position t with entering value x: before, x' = sg(t) (b x + v(t)) and the value
-// kept at t is x (K^{-1} forward, K^{-dagger} backward); else x' = (sg(t) x - v(t)) / b and the
-// value kept is x' (K^{-1} backward, K^{-dagger} forward).
-// chunk_map: the chunk as the affine map x_out = a x_in + c.
-// One step; the sign is applied to chain values only (a select on the chunk's own values
-// could be hoisted ahead of the chain and hold a second copy of the chunk).
+// K^{-dagger} down, with compile-time register positions (a per-lane choice of register would
+// put the chunk in scratch memory).
+// Away from the wrap, every step of either recurrence is x' = A x + B v(t) with the lane's own
+// A and B.  A lane with |b| <= 1 runs both "before": the step keeps its entering value x
+// (K^{-1} forward, K^{-dagger} backward), A = b, B = 1.  Otherwise the step keeps x' (K^{-1}
+// backward, K^{-dagger} forward), A = 1/b, B = -1/b.  The wrap's sign s = -1 falls on one step
+// of one chunk (tau = N_tau - 1 for K^{-1}, tau = 0 for K^{-dagger}): the last step a before-lane
+// takes there, whose leaving value it negates, or the first step of any other lane, whose
+// entering value it negates.  It is therefore applied to that chunk's map and entering value
+// (wrap_map, wrap_entry) rather than inside the loop.
 template <typename R>
-__host__ __device__ __forceinline__ C2<R> rec_step(C2<R> x, C2<R> v, R b, R ib, bool neg, bool before) {
-    if (before) {   // sg (b x + v)
-        const C2<R> w = mk<R>(b * x.x + v.x, b * x.y + v.y);
-        return neg ? mk<R>(-w.x, -w.y) : w;
-    }
-    const C2<R> xs = neg ? mk<R>(-x.x, -x.y) : x;   // (sg x - v) / b
-    return mk<R>(ib * (xs.x - v.x), ib * (xs.y - v.y));
+struct RecCoef {
+    R A, B;
+    bool before;
+};
+template <typename R>
+__host__ __device__ __forceinline__ RecCoef<R> rec_coef(R b) {
+    const bool before = b <= R(1) && b >= R(-1);
+    const R ib = R(1) / b;
+    return {before ? b : ib, before ? R(1) : -ib, before};
 }
-template <typename R, int MC, bool ASC, class Sg>
-__host__ __device__ __forceinline__ void chunk_map(const C2<R> (&v)[MC], int n, int t0, bool rev, R b, R ib, Sg sg,
-                                                   bool before, R& a, C2<R>& c) {
-    // a: the product of the steps' multipliers (b or 1/b, signed); c: the chunk run from 0
-    a = R(1);
+
+// Chunk q of a column of N_tau positions: chunks of pc_chunk_max from tau = 0, the last one
+// shorter, the ones beyond the column empty (n = 0).  Full chunks make a reversed lane's rows
+// the mirror image of a forward lane's, so loads and stores can be issued in mirrored pairs.
+struct ChunkSpan {
+    int t0, n;
+};
+template <typename R>
+__host__ __device__ __forceinline__ ChunkSpan pc_chunk_span(int q, int Lt) {
+    constexpr int MC = pc_chunk_max<R>();
+    const int t0 = q * MC < Lt ? q * MC : Lt;
+    return {t0, Lt - t0 < MC ? Lt - t0 : MC};
+}
+
+// A chunk's length: the runtime count, or FixedLen when every chunk of the launch is full, so
+// that the walks carry no per-step predicates.
+template <int N>
+struct FixedLen {
+    __host__ __device__ constexpr FixedLen() {}
+    __host__ __device__ constexpr explicit FixedLen(int) {}   // the runtime count, known to be N
+    __host__ __device__ constexpr operator int() const { return N; }
+};
+
+// x^n by repeated squaring (n >= 0).
+template <typename R>
+__host__ __device__ __forceinline__ R ipow(R x, int n) {
+    R r = R(1);
+    for (; n > 0; n >>= 1) {
+        if (n & 1) r *= x;
+        x *= x;
+    }
+    return r;
+}
+
+// The chunk's values are scaled by B once (chunk_scale), so that each step is one multiply-add
+// per component, x' = A x + u(t) with u = B v.  (Computing B v inside the steps lets the
+// compiler keep those products live from one walk to the next: a second copy of the chunk.)
+// Registers beyond the chunk hold zeros, which scaling keeps, so it needs no predicate.
+template <typename R, int MC>
+__host__ __device__ __forceinline__ void chunk_scale(C2<R> (&v)[MC], R B) {
+#pragma unroll
+    for (int j = 0; j < MC; ++j) v[j] = mk<R>(B * v[j].x, B * v[j].y);
+}
+// chunk_map: the chunk (scaled values u) as the affine map x_out = a x_in + c (a = A^n, c the
+// chunk run from 0).
+template <typename R, int MC, bool ASC, class N>
+__host__ __device__ __forceinline__ void chunk_map(const C2<R> (&u)[MC], N n, RecCoef<R> k, R& a, C2<R>& c) {
+    a = ipow(k.A, int(n));
     c = mk<R>(R(0), R(0));
-    const R mb = before ? b : ib;
 #pragma unroll
-    for (int k = 0; k < MC; ++k) {
-        const int j = ASC ? k : MC - 1 - k;
-        if (j < n) {
-            const bool neg = sg(rev ? t0 + n - 1 - j : t0 + j) < 0;
-            a = neg ? -(mb * a) : mb * a;
-            c = rec_step<R>(c, v[j], b, ib, neg, before);
-        }
+    for (int s = 0; s < MC; ++s) {
+        const int j = ASC ? s : MC - 1 - s;
+        if (j < n) c = mk<R>(k.A * c.x + u[j].x, k.A * c.y + u[j].y);
     }
 }
-// The same chunk run from the entering value x, replacing v by the recurrence's values.
-template <typename R, int MC, bool ASC, class Sg>
-__host__ __device__ __forceinline__ void chunk_apply(C2<R> (&v)[MC], int n, int t0, bool rev, R b, R ib, Sg sg,
-                                                     bool before, C2<R> x) {
+// The same chunk run from the entering value x, replacing u by the recurrence's values.
+template <typename R, int MC, bool ASC, class N>
+__host__ __device__ __forceinline__ void chunk_apply(C2<R> (&u)[MC], N n, RecCoef<R> k, C2<R> x) {
 #pragma unroll
-    for (int k = 0; k < MC; ++k) {
-        const int j = ASC ? k : MC - 1 - k;
+    for (int s = 0; s < MC; ++s) {
+        const int j = ASC ? s : MC - 1 - s;
         if (j < n) {
-            const bool neg = sg(rev ? t0 + n - 1 - j : t0 + j) < 0;
-            const C2<R> y = rec_step<R>(x, v[j], b, ib, neg, before);
-            v[j] = before ? x : y;
+            const C2<R> y = mk<R>(k.A * x.x + u[j].x, k.A * x.y + u[j].y);
+            u[j] = mk<R>(k.before ? x.x : y.x, k.before ? x.y : y.y);
             x = y;
         }
     }
+}
+// The wrap's sign on the chunk that holds it: a before-lane's leaving value is negated
+// (a, c -> -a, -c), another lane's entering value (a -> -a, and x_in -> -x_in on the rerun).
+template <typename R>
+__host__ __device__ __forceinline__ void wrap_map(bool wrap, bool before, R& a, C2<R>& c) {
+    a = wrap ? -a : a;
+    const bool nc = wrap && before;
+    c = mk<R>(nc ? -c.x : c.x, nc ? -c.y : c.y);
+}
+template <typename R>
+__host__ __device__ __forceinline__ C2<R> wrap_entry(bool wrap, bool before, C2<R> x) {
+    const bool nx = wrap && !before;
+    return mk<R>(nx ? -x.x : x.x, nx ? -x.y : x.y);
 }
 // Compose the Q chunk maps of one column (a[q * st], c[q * st]) around the cycle and write
 // the value entering each chunk: ascending chunks map x_q -> x_{q+1}, descending ones
@@ -236,40 +282,67 @@ __host__ __device__ inline double pc_column_b(int col, int L, int band, const do
            2.0 * (cf.hop2[band][0] * (2.0 * cx * cx - 1.0) + cf.hop2[band][1] * (2.0 * cy * cy - 1.0));
 }
 
-// Both recurrences on one thread's chunk, with the workgroup's map exchange in LDS (a, c, x:
-// Q x 64 entries, x one row more).  Returns sum |y|^2 over the chunk (y = K^{-1} r).
-template <typename R, int MC>
-__device__ __forceinline__ double pc_tau_solve(C2<R> (&v)[MC], int n, int t0, int Lt, R b, R* sa, C2<R>* sc,
-                                               C2<R>* sx, int q, int lane, int Q) {
-    const R ib = R(1) / b;
-    const bool small = b <= R(1) && b >= R(-1);
-    const SignK sk{Lt};
-    const SignKd skd{};
+// sum |v|^2 over a chunk, accumulated in R.
+template <typename R, int MC, class N>
+__host__ __device__ __forceinline__ R chunk_norm2(const C2<R> (&v)[MC], N n) {
+    R s = R(0);
+#pragma unroll
+    for (int j = 0; j < MC; ++j)
+        if (j < n) s += v[j].x * v[j].x + v[j].y * v[j].y;
+    return s;
+}
+// Makes b available only after a has been computed (an empty asm that takes and returns both).
+template <typename R>
+__host__ __device__ __forceinline__ void order_pin(R& a, R& b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+v"(a), "+v"(b));
+#else
+    (void)a;
+    (void)b;
+#endif
+}
+
+// Both recurrences on one thread's chunk (n values from tau = sp.t0), with the workgroup's map
+// exchange in LDS (a, c, x: Q x 64 entries, x one row more).  z comes out scaled by `scale`.
+// Returns sum |y|^2 over the chunk (y = K^{-1} r).  Between the barriers: the maps are written
+// before the first, read by the closing wave before the second; the entering values are read
+// after the second, and the next closing wave writes them only after the third, which every
+// wave reaches after its reads.
+template <typename R, int MC, class N>
+__device__ __forceinline__ double pc_tau_solve(C2<R> (&v)[MC], N n, ChunkSpan sp, int Lt, R b, R scale, R* sa,
+                                               C2<R>* sc, C2<R>* sx, int q, int lane, int Q) {
+    const RecCoef<R> k = rec_coef(b);
+    const bool wk = sp.n > 0 && sp.t0 + sp.n == Lt;   // holds tau = N_tau - 1 (K's wrap)
+    const bool wkd = sp.n > 0 && sp.t0 == 0;          // holds tau = 0 (K^dagger's wrap)
     R a;
     C2<R> c;
-    // y = K^{-1} r: forward (kept value entering each step) for |b| <= 1, else backward; the
-    // registers hold the chunk in the order this recurrence walks it (rev = !small)
-    chunk_map<R, MC, true>(v, n, t0, !small, b, ib, sk, small, a, c);
+    // y = K^{-1} r: the registers walked up
+    chunk_scale<R, MC>(v, k.B);
+    chunk_map<R, MC, true>(v, n, k, a, c);
+    wrap_map<R>(wk, k.before, a, c);
     sa[q * kPcCols + lane] = a;
     sc[q * kPcCols + lane] = c;
     __syncthreads();
-    if (q == 0) chunk_close<R>(sa + lane, sc + lane, sx + lane, Q, kPcCols, small);
+    if (q == 0) chunk_close<R>(sa + lane, sc + lane, sx + lane, Q, kPcCols, k.before);
     __syncthreads();
-    chunk_apply<R, MC, true>(v, n, t0, !small, b, ib, sk, small, sx[(small ? q : q + 1) * kPcCols + lane]);
-    double part = 0.0;
-#pragma unroll
-    for (int i = 0; i < MC; ++i)
-        if (i < n) part += double(v[i].x) * double(v[i].x) + double(v[i].y) * double(v[i].y);
-    __syncthreads();   // the exchange arrays are reused
-    // z = K^{-dagger} y: backward for |b| <= 1, else forward, i.e. the registers walked down
-    chunk_map<R, MC, false>(v, n, t0, !small, b, ib, skd, small, a, c);
+    const C2<R> x1 = wrap_entry<R>(wk, k.before, sx[(k.before ? q : q + 1) * kPcCols + lane]);
+    chunk_apply<R, MC, true>(v, n, k, x1);
+    // then z = K^{-dagger} y, scaled: the registers walked down.  The norm is taken before the
+    // values are scaled (deferred, it would hold y and B y at once).
+    R nrm = chunk_norm2<R, MC>(v, n);
+    R B2 = k.B * scale;
+    order_pin(nrm, B2);
+    chunk_scale<R, MC>(v, B2);
+    chunk_map<R, MC, false>(v, n, k, a, c);
+    wrap_map<R>(wkd, k.before, a, c);
     sa[q * kPcCols + lane] = a;
     sc[q * kPcCols + lane] = c;
     __syncthreads();
-    if (q == 0) chunk_close<R>(sa + lane, sc + lane, sx + lane, Q, kPcCols, !small);
+    if (q == 0) chunk_close<R>(sa + lane, sc + lane, sx + lane, Q, kPcCols, !k.before);
     __syncthreads();
-    chunk_apply<R, MC, false>(v, n, t0, !small, b, ib, skd, small, sx[(small ? q + 1 : q) * kPcCols + lane]);
-    return part;
+    const C2<R> x2 = wrap_entry<R>(wkd, k.before, sx[(k.before ? q + 1 : q) * kPcCols + lane]);
+    chunk_apply<R, MC, false>(v, n, k, x2);
+    return double(nrm);
 }
 
 // Dynamic LDS of the tau pass for Q chunks per column.
@@ -279,8 +352,9 @@ __host__ __device__ inline size_t pc_tau_lds(int Q) {
 }
 
 // Pass 2: one workgroup per (component, group of 64 columns) of a unit, 64 Q threads (lane:
-// column, wavefront: chunk), Q = blockDim / 64 at least each lattice's pc_chunks.
-template <typename R, class Geo>
+// column, wavefront: chunk), Q = blockDim / 64 at least each lattice's pc_chunks.  FULL: every
+// lattice of the launch has N_tau = Q pc_chunk_max, so every chunk is full.
+template <typename R, class Geo, bool FULL>
 __global__ __launch_bounds__(kPcCols * pc_max_chunks<R>()) void k_pc_t(CgCtl ctl, Geo geo, C2<R>* z,
                                                             const double* __restrict__ blob, Coef<double> cf) {
     extern __shared__ __align__(16) unsigned char pc_smem[];
@@ -302,31 +376,46 @@ __global__ __launch_bounds__(kPcCols * pc_max_chunks<R>()) void k_pc_t(CgCtl ctl
     const int q = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kPcCols);
     const int col = grp * kPcCols + lane;
     const bool on = col < LL;
-    // the lattice's own chunk count (a batch launch has the largest of its lattices; chunks
-    // beyond a lattice's count are empty, identity maps, so each lattice is cut the same way
-    // in a batch as on its own)
-    const int ql = pc_chunks<R>(Lt), m = (Lt + ql - 1) / ql;
-    const int t0 = min(q * m, Lt), n = min(m, Lt - t0);
+    // the lattice's own chunks (a batch launch has as many as the longest of its lattices needs;
+    // chunks beyond a lattice's own are empty, identity maps, so each lattice is cut the same
+    // way in a batch as on its own)
+    const ChunkSpan sp = pc_chunk_span<R>(q, Lt);
+    using N = typename std::conditional<FULL, FixedLen<MC>, int>::type;
+    const N n = N(sp.n);
     const PcBlob bl = pc_blob_layout(L, Lt);
     const R b = on ? R(pc_column_b(col, L, comp >> 1, blob + pos.pcoff + bl.cosx, cf)) : R(1);
     const bool rev = !(b <= R(1) && b >= R(-1));   // K^{-1} runs backward: chunk held reversed
-    // element j of the chunk at zc + j * st (one pointer and one stride per lane)
-    C2<R>* zc = z + pos.voff + size_t(comp) * lat.vol + size_t(t0) * LL + size_t(col) +
-                (rev && n > 0 ? ptrdiff_t(n - 1) * LL : ptrdiff_t(0));
-    ptrdiff_t st = rev ? -ptrdiff_t(LL) : ptrdiff_t(LL);
+    // Element j of the chunk at byte offset o0 + j * ob from the chunk's first row (a base shared
+    // by the wavefront), in 32 bits: at most pc_chunk_max rows of an L x L slice.
+    const char* zb = reinterpret_cast<const char*>(z + pos.voff + size_t(comp) * lat.vol + size_t(sp.t0) * LL);
+    const int rowb = LL * int(sizeof(C2<R>));
+    // a lane past the slice's last column runs a copy of that column (b = 1; its results are
+    // neither stored nor counted), so that the loads need no lane mask
+    const unsigned o0 = unsigned(on ? col : LL - 1) * unsigned(sizeof(C2<R>)) +
+                        (rev && n > 0 ? unsigned(int(n) - 1) * unsigned(rowb) : 0u);
+    int ob = rev ? -rowb : rowb;
+    auto at = [&](int j) { return reinterpret_cast<C2<R>*>(const_cast<char*>(zb) + (o0 + unsigned(j * ob))); };
+    // Registers j and MC - 1 - j are loaded and stored back to back: in a full chunk they cover
+    // the same two rows between the forward and the reversed lanes, so each pair writes whole
+    // cache lines while they are still in L2.
     C2<R> v[MC];
 #pragma unroll
-    for (int j = 0; j < MC; ++j) v[j] = (j < n && on) ? zc[j * st] : mk<R>(R(0), R(0));
+    for (int i = 0; i < MC; ++i) {
+        const int j = (i & 1) ? MC - 1 - (i >> 1) : (i >> 1);
+        v[j] = j < n ? *at(j) : mk<R>(R(0), R(0));
+    }
     // the stores recompute their addresses rather than keep the loads' live through the solve
-    asm volatile("" : "+v"(st));
+    asm volatile("" : "+v"(ob));
     R* sa = reinterpret_cast<R*>(pc_smem);
     C2<R>* sc = reinterpret_cast<C2<R>*>(sa + Q * kPcCols);
     C2<R>* sx = sc + Q * kPcCols;
-    const double part = pc_tau_solve<R, MC>(v, n, t0, Lt, b, sa, sc, sx, q, lane, Q);
-    const R inv = R(1) / R(LL);
+    // z is stored with the inverse transform's 1 / L^2
+    const double part = pc_tau_solve<R, MC>(v, n, sp, Lt, b, R(1) / R(LL), sa, sc, sx, q, lane, Q) * (on ? 1.0 : 0.0);
 #pragma unroll
-    for (int j = 0; j < MC; ++j)
-        if (j < n && on) zc[j * st] = mk<R>(v[j].x * inv, v[j].y * inv);
+    for (int i = 0; i < MC; ++i) {
+        const int j = (i & 1) ? MC - 1 - (i >> 1) : (i >> 1);
+        if (j < n && on) *at(j) = v[j];
+    }
     store_partial(ctl, PEND_RZ, pos, part / double(LL));
     if (threadIdx.x == 0) {
         S.zstage = 2;
