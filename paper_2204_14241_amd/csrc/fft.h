@@ -159,13 +159,24 @@ __host__ __device__ __forceinline__ void bfly_store(C2<R>* line, int es, int n, 
                                                     const C2<R>* tw) {
     const int base = p.base, M = p.M, e1 = p.e1;
     if constexpr (RAD <= 5) {
+        // W^{e1 k} as powers of the one table entry W^{e1} (one LDS read per butterfly instead
+        // of RAD - 1, whose per-lane addresses also collide in the banks)
+        const C2<R> w1 = tw[e1];
         if constexpr (!INV) {
             small_dft<R, false, RAD>(v, tw, n);
+            C2<R> w = w1;
 #pragma unroll
-            for (int k = 1; k < RAD; ++k) v[k] = cmul<R>(v[k], tw[e1 * k]);
+            for (int k = 1; k < RAD; ++k) {
+                v[k] = cmul<R>(v[k], w);
+                if (k + 1 < RAD) w = cmul<R>(w, w1);
+            }
         } else {
+            C2<R> w = w1;
 #pragma unroll
-            for (int k = 1; k < RAD; ++k) v[k] = cmulc<R>(v[k], tw[e1 * k]);
+            for (int k = 1; k < RAD; ++k) {
+                v[k] = cmulc<R>(v[k], w);
+                if (k + 1 < RAD) w = cmul<R>(w, w1);
+            }
             small_dft<R, true, RAD>(v, tw, n);
         }
 #pragma unroll
