@@ -410,7 +410,8 @@ __global__ __launch_bounds__(kPcCols * pc_max_chunks<R>()) void k_pc_t(CgCtl ctl
     C2<R>* sc = reinterpret_cast<C2<R>*>(sa + Q * kPcCols);
     C2<R>* sx = sc + Q * kPcCols;
     // z is stored with the inverse transform's 1 / L^2
-    const double part = pc_tau_solve<R, MC>(v, n, sp, Lt, b, R(1) / R(LL), sa, sc, sx, q, lane, Q) * (on ? 1.0 : 0.0);
+    const double pl = pc_tau_solve<R, MC>(v, n, sp, Lt, b, R(1) / R(LL), sa, sc, sx, q, lane, Q);
+    const double part = on ? pl : 0.0;
 #pragma unroll
     for (int i = 0; i < MC; ++i) {
         const int j = (i & 1) ? MC - 1 - (i >> 1) : (i >> 1);

@@ -31,7 +31,9 @@ def resid(m, phi, b, x):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("L,Lt", [(4, 8), (6, 10), (10, 7), (12, 40)])
+# N_tau = 40 and 80 cut every column into full FP32 chunks (the predicate-free tau pass), 64 into
+# full FP64 chunks; the others leave a short last chunk
+@pytest.mark.parametrize("L,Lt", [(4, 8), (6, 10), (10, 7), (12, 40), (6, 64), (6, 80)])
 def test_pcg_matches_oracle(hip, precision, L, Lt):
     say(f"pcg {precision} {L}x{L}x{Lt}")
     m = O.Model(L=L, Lt=Lt)
@@ -54,8 +56,9 @@ def test_pcg_matches_oracle(hip, precision, L, Lt):
             assert abs(st.iterations[k] - it_ref) <= 2, (st.iterations[k], it_ref)
 
 
-def test_pcg_exact_at_zero_coupling(hip):
-    L, Lt = 12, 40
+@pytest.mark.parametrize("Lt", [40, 64])
+def test_pcg_exact_at_zero_coupling(hip, Lt):
+    L = 12
     g = S.rng(510)
     phi = S.draw_phi(g, L, Lt, 1.0)
     b = S.draw_spinor(g, L, Lt, 1)
@@ -130,6 +133,30 @@ def test_pcg_batch_matches_oracle_and_single(hip, precision):
     bt.set_graphs(True)
     x2, _ = bt.cg_solve(phi, b)
     assert torch.equal(x0, x2)
+
+
+@pytest.mark.parametrize("precision,Lt", [("fp64", 64), ("mixed", 80)])
+def test_pcg_batch_full_chunks(hip, precision, Lt):
+    """Every chain's time extent a multiple of the chunk length (the predicate-free tau pass in
+    the batch launch): per chain equal to its own context bit for bit, and to the oracle."""
+    chains = [(4, Lt, 0.1), (6, Lt, -0.5), (8, Lt, 0.0)]
+    g = S.rng(531)
+    phis = [S.draw_phi(g, L, Lt_, 0.5) for L, Lt_, _ in chains]
+    bs = [S.draw_spinor(g, L, Lt_, 1) for L, Lt_, _ in chains]
+    bt = hip.Batch(chains, n_pf=1, cg_tol=1e-10, precision=precision, precond="fourier")
+    bt.set_cg_workgroups(8)
+    x, st = bt.cg_solve(bt.pack_phi([dev(p) for p in phis]), bt.pack_spinors([dev(v) for v in bs]))
+    say(f"pcg batch full chunks {precision} N_tau {Lt}: iterations {st['iterations']}")
+    assert st["status"] == 0
+    xs = bt.unpack_spinors(x)
+    for i, (L, Lt_, r) in enumerate(chains):
+        m = O.Model(L=L, Lt=Lt_, r=r)
+        assert resid(m, phis[i], bs[i][0], xs[i][0].cpu().numpy()) <= 1e-10
+        h = hip.HMC(L, Lt_, n_pf=1, cg_tol=1e-10, precision=precision, precond="fourier", model=dict(r=r))
+        h.set_cg_workgroups(8)
+        x1, st1 = h.cg_solve(dev(phis[i]), dev(bs[i]))
+        assert st1.iterations == st["iterations"][i:i + 1]
+        assert torch.equal(x1.reshape(xs[i].shape), xs[i])
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
