@@ -763,13 +763,28 @@ __device__ __forceinline__ void dslash_pair(const Src& src, const float* __restr
     const int yr = (nb.y + 2 == L) ? s + 2 - L : s + 2;     // y + 1 of site s + 1
     const int st = DAG ? nb.tm : nb.tp;
     const float ts = float(DAG ? nb.sbwd : nb.sfwd);
+    // hops by two sites: rows x +- 2 at the same pair, and the pairs (y - 2, y - 1) and
+    // (y + 2, y + 3), all aligned (y is even and so is L); the latter two also hold the y - 1
+    // and y + 2 values of the nearest-neighbour terms
+    Nbr2 n2{};
+    if constexpr (NN2) n2 = neighbours2(lat, nb, s);
 #pragma unroll
     for (int c = 0; c < 4; ++c) cen[c] = src.pair(c, s);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int a = c >> 1;
         const float4 xp = src.pair(c, nb.xp), xm = src.pair(c, nb.xm), tt = src.pair(c, st);
-        const float2 lo = src.one(c, yl), hi = src.one(c, yr);
+        float2 lo, hi;
+        float4 ym2, yp2;
+        if constexpr (NN2) {
+            ym2 = src.pair(c, n2.ymm);
+            yp2 = src.pair(c, n2.ypp);
+            lo = make_float2(ym2.z, ym2.w);
+            hi = make_float2(yp2.x, yp2.y);
+        } else {
+            lo = src.one(c, yl);
+            hi = src.one(c, yr);
+        }
         const float4 ce = cen[c];
         const float dg = cf.diag[a], h0 = cf.hop[a][0], h1 = cf.hop[a][1];
         float4 o;
@@ -777,23 +792,16 @@ __device__ __forceinline__ void dslash_pair(const Src& src, const float* __restr
         o.y = dg * ce.y + h0 * (xp.y + xm.y) + h1 * (lo.y + ce.w) + ts * tt.y;
         o.z = dg * ce.z + h0 * (xp.z + xm.z) + h1 * (ce.x + hi.x) + ts * tt.z;
         o.w = dg * ce.w + h0 * (xp.w + xm.w) + h1 * (ce.y + hi.y) + ts * tt.w;
-        out[c] = o;
-    }
-    if constexpr (NN2) {
-        // hops by two sites: rows x +- 2 at the same pair, and the pairs (y - 2, y - 1) and
-        // (y + 2, y + 3), all aligned (y is even and so is L)
-        const Nbr2 n2 = neighbours2(lat, nb, s);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int a = c >> 1;
+        if constexpr (NN2) {
             const float4 xx = f4add(src.pair(c, n2.xpp), src.pair(c, n2.xmm));
-            const float4 yy = f4add(src.pair(c, n2.ymm), src.pair(c, n2.ypp));
+            const float4 yy = f4add(ym2, yp2);
             const float u0 = cf.hop2[a][0], u1 = cf.hop2[a][1];
-            out[c].x += u0 * xx.x + u1 * yy.x;
-            out[c].y += u0 * xx.y + u1 * yy.y;
-            out[c].z += u0 * xx.z + u1 * yy.z;
-            out[c].w += u0 * xx.w + u1 * yy.w;
+            o.x += u0 * xx.x + u1 * yy.x;
+            o.y += u0 * xx.y + u1 * yy.y;
+            o.z += u0 * xx.z + u1 * yy.z;
+            o.w += u0 * xx.w + u1 * yy.w;
         }
+        out[c] = o;
     }
     const float g0 = cf.cpl * float(nb.stag), g1 = -g0;     // (-1)^(x+y) flips between s, s+1
     const float2 P1 = *reinterpret_cast<const float2*>(phi + s);
