@@ -31,12 +31,15 @@ constexpr int kPcBlock = 512;
 
 constexpr int kPcCols = 64;     // columns per tau-pass workgroup
 
-// Longest chunk a thread holds in registers (40 FP32, 32 FP64 values) and most chunks per
-// column, i.e. wavefronts of a 512-thread workgroup: N_tau <= 320 (FP32) or 256 (FP64).
+// Longest chunk a thread holds in registers (20 FP32, 32 FP64 values) and most chunks per
+// column, i.e. wavefronts of a workgroup (1024 or 512 threads): N_tau <= 320 (FP32) or 256
+// (FP64).  Short FP32 chunks give a column more wavefronts and each a shorter chain (at
+// 80x80x200 the pass takes 19 us with chunks of 20 against 26 us with 40); FP64 chunks of 20
+// would spill under the 1024-thread bound.
 template <typename R>
-__host__ __device__ constexpr int pc_chunk_max() { return sizeof(R) == 4 ? 40 : 32; }
+__host__ __device__ constexpr int pc_chunk_max() { return sizeof(R) == 4 ? 20 : 32; }
 template <typename R>
-__host__ __device__ constexpr int pc_max_chunks() { return 8; }
+__host__ __device__ constexpr int pc_max_chunks() { return sizeof(R) == 4 ? 16 : 8; }
 
 // Chunks per column for N_tau (the fewest that keep chunks within pc_chunk_max); 0 if more
 // than pc_max_chunks would be needed.

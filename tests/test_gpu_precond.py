@@ -32,7 +32,7 @@ def resid(m, phi, b, x):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 # N_tau = 40 and 80 cut every column into full FP32 chunks (the predicate-free tau pass), 64 into
-# full FP64 chunks; the others leave a short last chunk
+# full FP64 chunks; the others leave a short last chunk (10 and 7 in FP32, all but 64 in FP64)
 @pytest.mark.parametrize("L,Lt", [(4, 8), (6, 10), (10, 7), (12, 40), (6, 64), (6, 80)])
 def test_pcg_matches_oracle(hip, precision, L, Lt):
     say(f"pcg {precision} {L}x{L}x{Lt}")
@@ -186,7 +186,7 @@ def test_pcg_batch_uneven_time_extents(hip, precision):
 
 def test_pcg_time_extent_limits(hip):
     from paper_2204_14241_amd._lib import HmcError
-    hip.HMC(4, 320, precision="mixed", precond="fourier")        # 8 chunks of 40
+    hip.HMC(4, 320, precision="mixed", precond="fourier")        # 16 chunks of 20
     hip.HMC(4, 256, precision="fp64", precond="fourier")         # 8 chunks of 32
     with pytest.raises(HmcError):
         hip.HMC(4, 324, precision="mixed", precond="fourier")
