@@ -200,6 +200,80 @@ def prod_bench(hmcmod, torch, L, Lt, common, phi0, d_traj):
     return out
 
 
+def fp64_configs_bench(hmcmod, torch, seed, cpu):
+    """The plain FP64 workloads beside the headline one: 40x40x100 with two pseudofermions (one
+    CG solve with its sampled kernel times, one 20-step trajectory, and the oracle's M^dag M on
+    the host for comparison) and 60x60x160 with one (the differentiable action's forward and
+    backward, recomputing the solution, and one 20-step trajectory)."""
+    import synth_inputs as S
+    from paper_2204_14241_amd.autograd import pf_action
+    dev = torch.device("cuda")
+    out = {}
+    for name, extra in (("medium_40x40x100", 6), ("grad_60x60x160", 7)):
+        cfg = S.WORKLOADS[name]
+        L, Lt, n_pf = cfg["L"], cfg["Lt"], cfg["n_pf"]
+        vol = Lt * L * L
+        phi0, trajs = S.hmc_inputs(seed + extra, L, Lt, cfg["phi_var"], n_pf, n_traj=1)
+        p0, e0, u0 = (torch.from_numpy(trajs[0][0]).to(dev), torch.from_numpy(trajs[0][1]).to(dev),
+                      trajs[0][2])
+        h = hmcmod.HMC(L, Lt, precision="fp64", eps=cfg["eps"], n_leap=cfg["n_leap"], n_pf=n_pf,
+                       cg_tol=1e-10, cg_maxit=40000, max_rhs=n_pf)
+        phi = torch.from_numpy(phi0).to(dev)
+        chi = h.heatbath(phi, e0)
+        rec = {"L": L, "L_tau": Lt, "n_pf": n_pf}
+        if name.startswith("medium"):
+            h.cg_solve(phi, chi)
+            h.set_kernel_timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = h.cg_solve(phi, chi)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            kt = h.kernel_times()
+            h.set_kernel_timing(False)
+            its = sum(st.iterations)
+            rec["cg_solve"] = {"ms": 1e3 * el, "iterations": list(st.iterations),
+                               "mdagm_applies_per_s": its / el,
+                               "max_true_resid": max(st.true_resid)}
+            for kname in ("cg_a_f64", "cg_b_f64"):
+                ms, n = kt[kname]
+                if ms:
+                    gbs = BYTES_PER_SITE[kname] * vol / (ms * 1e-3) / 1e9
+                    rec["cg_solve"][kname] = {"avg_ms": ms, "samples": n, "GB/s": gbs,
+                                              "frac_hbm_peak": gbs / HBM_PEAK_GBS}
+            if cpu:
+                cb = cpu_baseline(L, Lt, seed + extra, budget_s=5.0)
+                rec["cpu_oracle_mdagm_applies_per_s"] = cb["value"]
+                rec["cpu_oracle_sample"] = cb["sample"]
+                rec["gpu_vs_cpu_oracle"] = rec["cg_solve"]["mdagm_applies_per_s"] / cb["value"]
+        else:
+            pv = phi.clone().requires_grad_(True)
+            pf_action(pv, chi, h)                     # warm-up
+            pv.grad = None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S_ = pf_action(pv, chi, h)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            S_.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            rec["autograd"] = {"forward_ms": 1e3 * (t1 - t0), "backward_ms": 1e3 * (t2 - t1),
+                               "policy": "recompute", "S": S_.item()}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr = h.trajectory(phi, p0, e0, u0)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rec["trajectory"] = {"s": el, "traj_per_hour": 3600.0 / el, "n_leap": cfg["n_leap"],
+                             "dH": tr["dH"], "accepted": tr["accepted"],
+                             "cg_iterations": tr["cg_iterations"], "max_true_resid": tr["max_true_resid"]}
+        log(f"FP64 {name}: trajectory {el:.2f} s, cg iterations {tr['cg_iterations']}")
+        h.close()
+        out[name] = rec
+    return out
+
+
 def metric_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, seed, reps=20):
     """The Fourier-diagonal metric at the workload size: the metric estimated (Eq. 30) from
     the starting field and the first momenta, the momentum draw, the kinetic energy and one
@@ -576,6 +650,7 @@ def main():
         extras["pcg_80x80x200"] = pcg_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, W, args.pcg_steps)
         extras["metric_80x80x200"] = metric_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, args.seed)
         extras["production_model_80x80x200"] = prod_bench(hmcmod, torch, L, Lt, common, phi0, d_traj)
+        extras["fp64_workloads"] = fp64_configs_bench(hmcmod, torch, args.seed, not args.no_cpu)
         for f32 in (True, False):
             aps, gbs, ms, nsets = apply_bench(hmcmod, torch, L, Lt, f32, args.apply_reps, args.seed + 1)
             extras["mdagm_apply_" + ("f32" if f32 else "f64")] = {
