@@ -201,10 +201,11 @@ def prod_bench(hmcmod, torch, L, Lt, common, phi0, d_traj):
 
 
 def fp64_configs_bench(hmcmod, torch, seed, cpu):
-    """The plain FP64 workloads beside the headline one: 40x40x100 with two pseudofermions (one
-    CG solve with its sampled kernel times, one 20-step trajectory, and the oracle's M^dag M on
-    the host for comparison) and 60x60x160 with one (the differentiable action's forward and
-    backward, recomputing the solution, and one 20-step trajectory)."""
+    """The plain FP64 workloads beside the headline one: 40x40x100 with two pseudofermions (the
+    autotuned launch shape, one CG solve with its sampled kernel times, one 20-step trajectory,
+    and the oracle's M^dag M on the host for comparison) and 60x60x160 with one (the
+    differentiable action's forward and backward, recomputing the solution, and one 20-step
+    trajectory)."""
     import synth_inputs as S
     from paper_2204_14241_amd.autograd import pf_action
     dev = torch.device("cuda")
@@ -222,6 +223,7 @@ def fp64_configs_bench(hmcmod, torch, seed, cpu):
         chi = h.heatbath(phi, e0)
         rec = {"L": L, "L_tau": Lt, "n_pf": n_pf}
         if name.startswith("medium"):
+            rec["autotune"] = h.autotune(phi, chi)
             h.cg_solve(phi, chi)
             h.set_kernel_timing(True)
             torch.cuda.synchronize()

@@ -184,6 +184,23 @@ def test_pcg_batch_uneven_time_extents(hip, precision):
         assert torch.equal(x1.reshape(xs[i].shape), xs[i])
 
 
+@pytest.mark.parametrize("precision,Lt", [("mixed", 320), ("fp64", 256)])
+def test_pcg_at_the_longest_time_extent(hip, precision, Lt):
+    """The largest N_tau each precision accepts (16 chunks of 20 FP32 values, 8 of 32 FP64): a
+    full workgroup of chunk wavefronts, solved to the oracle's residual bar."""
+    L = 4
+    say(f"pcg {precision} {L}x{L}x{Lt}")
+    m = O.Model(L=L, Lt=Lt)
+    g = S.rng(540 + Lt)
+    phi = S.draw_phi(g, L, Lt, 0.5)
+    b = S.draw_spinor(g, L, Lt, 1)
+    h = hip.HMC(L, Lt, cg_tol=1e-10, precision=precision, precond="fourier")
+    x, st = h.cg_solve(dev(phi), dev(b))
+    say(f"  iterations {st.iterations}, true residual {st.true_resid}")
+    assert st.status == 0
+    assert resid(m, phi, b[0], x.cpu().numpy()[0]) <= 1e-10
+
+
 def test_pcg_time_extent_limits(hip):
     from paper_2204_14241_amd._lib import HmcError
     hip.HMC(4, 320, precision="mixed", precond="fourier")        # 16 chunks of 20
