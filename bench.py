@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--profile-pcg", action="store_true",
                     help="short fixed sequence for profiler runs of the Fourier preconditioner: one "
                          "mixed-precision and one FP64 preconditioned CG solve at the workload size")
+    ap.add_argument("--profile-shapes", action="store_true",
+                    help="counter runs over launch shapes: a 512 MiB device copy, then 150 CG "
+                         "iterations per precision at 256, 512, 1024 and 2048 workgroups")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="short fixed sequence for counter runs: a 512 MiB device copy (the "
                          "byte-counter calibration), FP32/FP64 M and M^dagger applies and 60 "
@@ -105,6 +108,47 @@ def profile_kernels(args):
     x, st = h.cg_solve(phi, psi)
     torch.cuda.synchronize()
     log(f"profile sequence done: cg iterations {st.iterations}")
+
+
+def profile_shapes(args):
+    """CG steps A and B of both precisions at several launch shapes (workgroups per right-hand
+    side), 150 iterations each, with their live kernel times: for counter runs that show how
+    the HBM re-read of step A grows with the number of workgroups in flight."""
+    import torch
+    import synth_inputs as S
+    from paper_2204_14241_amd import hmc as hmcmod
+    from paper_2204_14241_amd._lib import HmcError, HMC_ERR_NOT_CONVERGED
+    cfg = S.WORKLOADS[args.workload]
+    L, Lt = cfg["L"], cfg["Lt"]
+    dev = torch.device("cuda")
+    calibration_copy(torch)
+    g = S.rng(args.seed)
+    phi = torch.from_numpy(S.draw_phi(g, L, Lt, cfg["phi_var"])).to(dev)
+    eta = torch.from_numpy(S.draw_eta(g, L, Lt, 1)).to(dev)
+    out = {}
+    for prec, suf in (("fp64", "f64"), ("mixed", "f32")):
+        h = hmcmod.HMC(L, Lt, precision=prec, cg_tol=1e-30, cg_maxit=150, reliable_every=50)
+        chi = h.heatbath(phi, eta)
+
+        def solve():
+            try:
+                h.cg_solve(phi, chi)
+            except HmcError as e:          # the tolerance is never met: 150 iterations run
+                if e.code != HMC_ERR_NOT_CONVERGED:
+                    raise
+        for bpr in (256, 512, 1024, 2048):
+            h.set_cg_workgroups(bpr, prec)
+            solve()
+            h.set_kernel_timing(True)
+            solve()
+            torch.cuda.synchronize()
+            kt = h.kernel_times()
+            h.set_kernel_timing(False)
+            out[f"{prec}_{bpr}"] = {"cg_a_us": 1e3 * kt["cg_a_" + suf][0], "cg_b_us": 1e3 * kt["cg_b_" + suf][0]}
+            log(f"{prec} {bpr} workgroups: step A {1e3 * kt['cg_a_' + suf][0]:.1f} us, "
+                f"step B {1e3 * kt['cg_b_' + suf][0]:.1f} us")
+        h.close()
+    print(json.dumps(out))
 
 
 def profile_pcg(args):
@@ -540,6 +584,9 @@ def main():
         return
     if args.profile_pcg:
         profile_pcg(args)
+        return
+    if args.profile_shapes:
+        profile_shapes(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the one-GPU build has no multi-GPU path "
