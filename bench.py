@@ -409,7 +409,8 @@ def batch_bench(hmcmod, torch, seed, steps, warmup):
     """The batched workload: independent chains of uneven L, L_tau and r, 4 pseudofermions
     each, mixed precision.  Autotunes the shared CG launch shape, times one batched CG solve
     per launch mode (eager kernels, HIP-graph replay), then `steps` batched trajectories
-    (the momenta and noise of the one drawn set are reused each step)."""
+    (the momenta and noise of the one drawn set are reused each step), plain and then
+    Fourier-preconditioned from the same field (the one the warm-up trajectories leave)."""
     import numpy as np
     import synth_inputs as S
     cfg = S.BATCH_WORKLOAD
@@ -454,25 +455,34 @@ def batch_bench(hmcmod, torch, seed, steps, warmup):
     out["pcg_solve"] = {"s": el, "max_iterations": max(st["iterations"]),
                         "unit_iterations": sum(st["iterations"]), "max_true_resid": max(st["true_resid"])}
     log(f"batch pcg: {el:.3f} s, max iterations {max(st['iterations'])}")
-    bt.set_params(precond=None)
     bt.set_graphs(True)
+    bt.set_params(precond=None)
     for _ in range(warmup):
         bt.trajectory(phi, pi0, eta, u)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    acc, its = 0, 0
-    for i in range(steps):
-        st = bt.trajectory(phi, pi0, eta, u)
-        acc += st["accepted"]
-        its += st["cg_iterations"]
-        log(f"batch trajectory {i}: accepted {st['accepted']}/{len(chains)}, unit CG iterations "
-            f"{st['cg_iterations']}, max |dH| {max(abs(d) for d in st['dH_chains']):.3g}")
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    out.update({"batch_trajectories": steps, "s_per_batch_trajectory": el / steps,
-                "chain_trajectories_per_hour": 3600.0 * steps * len(chains) / el,
-                "acceptance": acc / (steps * len(chains)),
-                "unit_cg_iterations_per_s": its / el})
+    phi_start = phi.clone()
+    for pc in (None, "fourier"):
+        # the same starting field, momenta and noise for the plain and the preconditioned runs
+        phi.copy_(phi_start)
+        bt.set_params(precond=pc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        acc, its = 0, 0
+        for i in range(steps):
+            st = bt.trajectory(phi, pi0, eta, u)
+            acc += st["accepted"]
+            its += st["cg_iterations"]
+            log(f"batch trajectory {i} (precond={pc}): accepted {st['accepted']}/{len(chains)}, unit CG "
+                f"iterations {st['cg_iterations']}, max |dH| {max(abs(d) for d in st['dH_chains']):.3g}")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rec = {"batch_trajectories": steps, "s_per_batch_trajectory": el / steps,
+               "chain_trajectories_per_hour": 3600.0 * steps * len(chains) / el,
+               "acceptance": acc / (steps * len(chains)),
+               "unit_cg_iterations_per_s": its / el, "unit_cg_iterations": its}
+        if pc is None:
+            out.update(rec)
+        else:
+            out["pcg_trajectories"] = rec
     bt.close()
     return out
 
