@@ -30,20 +30,33 @@ sys.path.insert(0, ROOT)
 METRIC = "M^dag M applies/s + HBM GB/s at 80x80x200; HMC traj/h mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic HBM bytes per lattice site of each kernel (each vector counted once per pass).
-# A spinor is 4 complex numbers per site (64 B in FP64, 32 B in FP32); phi is 3 reals.
-BYTES_PER_SITE = {
+# Algorithmic HBM traffic of each kernel per lattice site (each vector counted once per pass):
+# (spinor streams per right-hand side, boson-field streams per launch).  A spinor is 4 complex
+# numbers per site (64 B in FP64, 32 B in FP32); phi is 3 reals (24 B / 12 B), read once per
+# launch however many right-hand sides the launch covers.
+KERNEL_STREAMS = {
     # t = M p_new with p_new = r + beta p_old, x += alpha p_old: reads r, p_old, x, phi;
     # writes p_new, t, x
-    "cg_a_f32": 6 * 32 + 12,
-    "cg_a_f64": 6 * 64 + 24,
+    "cg_a": (6, 1),
     # r -= alpha M^dagger t: reads t, r, phi; writes r
-    "cg_b_f32": 3 * 32 + 12,
-    "cg_b_f64": 3 * 64 + 24,
+    "cg_b": (3, 1),
     # one M or M^dagger apply: reads psi, phi; writes psi
-    "apply_f32": 2 * 32 + 12,
-    "apply_f64": 2 * 64 + 24,
+    "apply": (2, 1),
 }
+SPINOR_BYTES = {"f32": 32, "f64": 64}
+PHI_BYTES = {"f32": 12, "f64": 24}
+
+
+def launch_bytes(name, vol, nrhs=1):
+    """Algorithmic HBM bytes of one launch of kernel `name` ("cg_a_f32", ...) over nrhs
+    right-hand sides of a vol-site lattice."""
+    kern, prec = name.rsplit("_", 1)
+    ns, nphi = KERNEL_STREAMS[kern]
+    return vol * (nrhs * ns * SPINOR_BYTES[prec] + nphi * PHI_BYTES[prec])
+
+
+# per site of one right-hand side
+BYTES_PER_SITE = {f"{k}_{p}": launch_bytes(f"{k}_{p}", 1) for k in KERNEL_STREAMS for p in SPINOR_BYTES}
 
 
 def parse():
@@ -51,7 +64,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=3,
+                    help="timed plain FP64 trajectories, on the first indices the mixed run times")
     ap.add_argument("--workload", default="large_80x80x200")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--apply-reps", type=int, default=40)
@@ -69,6 +83,10 @@ def parse():
     ap.add_argument("--profile-shapes", action="store_true",
                     help="counter runs over launch shapes: a 512 MiB device copy, then 150 CG "
                          "iterations per precision at 256, 512, 1024 and 2048 workgroups")
+    ap.add_argument("--profile-mall", action="store_true",
+                    help="short fixed sequence for counter runs with a working set above the MALL: a "
+                         "512 MiB device copy, then 60 mixed-precision CG iterations on 4 right-hand "
+                         "sides at once at the workload size")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="short fixed sequence for counter runs: a 512 MiB device copy (the "
                          "byte-counter calibration), FP32/FP64 M and M^dagger applies and 60 "
@@ -108,6 +126,30 @@ def profile_kernels(args):
     x, st = h.cg_solve(phi, psi)
     torch.cuda.synchronize()
     log(f"profile sequence done: cg iterations {st.iterations}")
+
+
+def profile_mall(args):
+    """Counter-run sequence of the in-CG kernels with a working set the MALL cannot hold."""
+    import torch
+    import synth_inputs as S
+    from paper_2204_14241_amd import hmc as hmcmod
+    from paper_2204_14241_amd._lib import HmcError, HMC_ERR_NOT_CONVERGED
+    cfg = S.WORKLOADS[args.workload]
+    L, Lt = cfg["L"], cfg["Lt"]
+    dev = torch.device("cuda")
+    calibration_copy(torch)
+    g = S.rng(args.seed)
+    phi = torch.from_numpy(S.draw_phi(g, L, Lt, cfg["phi_var"])).to(dev)
+    eta = torch.from_numpy(S.draw_eta(g, L, Lt, 4)).to(dev)
+    h = hmcmod.HMC(L, Lt, precision="mixed", n_pf=4, max_rhs=4, cg_tol=1e-30, cg_maxit=60, reliable_every=50)
+    chi = h.heatbath(phi, eta)
+    try:
+        h.cg_solve(phi, chi)
+    except HmcError as e:          # the tolerance is never met: 60 iterations run
+        if e.code != HMC_ERR_NOT_CONVERGED:
+            raise
+    torch.cuda.synchronize()
+    log("profile sequence done: 60 mixed CG iterations on 4 right-hand sides")
 
 
 def profile_shapes(args):
@@ -284,8 +326,12 @@ def fp64_configs_bench(hmcmod, torch, seed, cpu):
             for kname in ("cg_a_f64", "cg_b_f64"):
                 ms, n = kt[kname]
                 if ms:
-                    gbs = BYTES_PER_SITE[kname] * vol / (ms * 1e-3) / 1e9
-                    rec["cg_solve"][kname] = {"avg_ms": ms, "samples": n, "GB/s": gbs,
+                    # one launch covers every right-hand side (samples are taken only while
+                    # all of them iterate)
+                    nb = launch_bytes(kname, vol, n_pf)
+                    gbs = nb / (ms * 1e-3) / 1e9
+                    rec["cg_solve"][kname] = {"avg_ms": ms, "samples": n, "rhs_per_launch": n_pf,
+                                              "bytes_per_launch": nb, "GB/s": gbs,
                                               "frac_hbm_peak": gbs / HBM_PEAK_GBS}
             if cpu:
                 # the same CPU-baseline leg as the headline's, at this workload
@@ -438,7 +484,8 @@ def batch_bench(hmcmod, torch, seed, steps, warmup):
         _, st = bt.cg_solve(phi, chi)
         el = time.perf_counter() - t0
         site_it = sum(it * vols[j // cfg["n_pf"]] for j, it in enumerate(st["iterations"]))
-        b_it = BYTES_PER_SITE["cg_a_f32"] + BYTES_PER_SITE["cg_b_f32"]
+        # per unit (chain, right-hand side) and site; a chain's phi is shared by its n_pf units
+        b_it = (launch_bytes("cg_a_f32", 1, cfg["n_pf"]) + launch_bytes("cg_b_f32", 1, cfg["n_pf"])) / cfg["n_pf"]
         out["cg_solve_" + ("graph" if graphs else "eager")] = {
             "s": el, "max_iterations": max(st["iterations"]), "unit_iterations": sum(st["iterations"]),
             "site_iterations_per_s": site_it / el, "effective_GB/s": site_it * b_it / el / 1e9,
@@ -566,6 +613,81 @@ def copy_bench(torch, reps=20):
     return 2 * n / (ms * 1e-3) / 1e9
 
 
+def probe_bench(hmcmod, torch, reps=10, grids=(1024, 2048, 4096, 8192)):
+    """The library's streaming reference kernels (hmc_stream_probe) on buffers far larger than
+    the 256 MB MALL, two buffer sets alternated: read-only, write-only, copy (1 GiB per stream)
+    and three reads with three writes (512 MiB per stream, the mix of one fused CG step).
+    Each is timed at several grid sizes with HIP events; the fastest is kept.  These are the
+    rates this GPU sustains for plain streams: the achievable reference beside the nominal
+    8 TB/s."""
+    GiB = 2 ** 30
+    kinds = {"read": (1, 0, GiB), "write": (0, 1, GiB), "copy": (1, 1, GiB), "3r3w": (3, 3, GiB // 2)}
+    out = {}
+    for kind, (nr, nw, nb) in kinds.items():
+        sets = []
+        for _ in range(2):
+            src = torch.ones(nr * nb // 4, dtype=torch.float32, device="cuda") if nr else None
+            dst = (torch.empty(nw * nb, dtype=torch.uint8, device="cuda") if nw
+                   else torch.empty(max(grids), dtype=torch.float64, device="cuda"))
+            sets.append((src, dst))
+        tried = {}
+        for grid in grids:
+            for i in range(2):
+                hmcmod.stream_probe(kind, sets[i][0], sets[i][1], nb, grid)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for i in range(reps):
+                hmcmod.stream_probe(kind, sets[i & 1][0], sets[i & 1][1], nb, grid)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            tried[grid] = (nr + nw) * nb / (ms * 1e-3) / 1e9
+        best = max(tried, key=tried.get)
+        out[kind] = {"GB/s": tried[best], "grid": best, "bytes_per_stream": nb, "streams": [nr, nw],
+                     "tried": tried}
+        log(f"stream probe {kind}: {tried[best]:.0f} GB/s (grid {best})")
+        del sets
+        torch.cuda.empty_cache()
+    return out
+
+
+def mall_controlled_bench(hmcmod, torch, L, Lt, phi0, seed, nrhs=4):
+    """The in-CG kernels with a working set the 256 MB MALL cannot hold: one mixed solve of
+    nrhs right-hand sides at once (FP32 r, p0, p1, t, x per right-hand side and the FP32 phi:
+    about 835 MB at 80x80x200 and nrhs = 4), with the live samples of steps A and B; one launch
+    covers all right-hand sides."""
+    import synth_inputs as S
+    dev = torch.device("cuda")
+    vol = Lt * L * L
+    h = hmcmod.HMC(L, Lt, precision="mixed", n_pf=nrhs, max_rhs=nrhs, cg_tol=1e-10, cg_maxit=20000,
+                   reliable_every=50)
+    phi = torch.from_numpy(phi0).to(dev)
+    eta = torch.from_numpy(S.draw_eta(S.rng(seed + 11), L, Lt, nrhs)).to(dev)
+    chi = h.heatbath(phi, eta)
+    h.cg_solve(phi, chi)
+    h.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = h.cg_solve(phi, chi)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = h.kernel_times()
+    ws = vol * (5 * nrhs * SPINOR_BYTES["f32"] + PHI_BYTES["f32"])
+    rec = {"rhs": nrhs, "working_set_bytes": ws, "solve_s": el, "iterations": list(st.iterations),
+           "max_true_resid": max(st.true_resid), "bpr": h.cg_workgroups()["mixed"]}
+    for name in ("cg_a_f32", "cg_b_f32"):
+        ms, n = kt[name]
+        if ms:
+            nb = launch_bytes(name, vol, nrhs)
+            gbs = nb / (ms * 1e-3) / 1e9
+            rec[name] = {"avg_ms": ms, "samples": n, "bytes_per_launch": nb, "GB/s": gbs,
+                         "frac_hbm_peak": gbs / HBM_PEAK_GBS}
+            log(f"MALL-controlled {name} ({nrhs} right-hand sides, {ws / 1e6:.0f} MB working set): "
+                f"{1e3 * ms:.1f} us, {gbs:.0f} GB/s")
+    h.close()
+    return rec
+
+
 def cpu_baseline(L, Lt, seed, budget_s=15.0):
     """The FP64 oracle's M^dagger M apply on the host (NumPy, one thread), bounded sample."""
     import oracle as O
@@ -594,6 +716,9 @@ def main():
     if args.profile_pcg:
         profile_pcg(args)
         return
+    if args.profile_mall:
+        profile_mall(args)
+        return
     if args.profile_shapes:
         profile_shapes(args)
         return
@@ -621,12 +746,16 @@ def main():
     common = dict(eps=eps, n_leap=n_leap, n_pf=n_pf, cg_tol=1e-10, cg_maxit=20000,
                   reliable_every=50, max_rhs=n_pf)
 
-    def run(precision, nsteps, nwarm, timing=False):
+    def run(precision, nsteps, nwarm, timing=False, phi_start=None):
+        """nwarm untimed then nsteps timed trajectories (indices nwarm ...) from phi_start (the
+        seed's phi_0 if None).  Returns (seconds, per-trajectory stats and seconds, kernel
+        times, the field at index nwarm)."""
         h = hmcmod.HMC(L, Lt, precision=precision, **common)
-        phi = torch.from_numpy(phi0).to(dev)
+        phi = torch.from_numpy(phi0).to(dev) if phi_start is None else phi_start.clone()
         for i in range(nwarm):
             p, e, u = d_traj[i]
             h.trajectory(phi, p, e, u)
+        phi_at = phi.clone()
         if timing:
             h.set_kernel_timing(True)
         torch.cuda.synchronize()
@@ -634,14 +763,16 @@ def main():
         out = []
         for i in range(nwarm, nwarm + nsteps):
             p, e, u = d_traj[i]
+            ti = time.perf_counter()
             out.append(h.trajectory(phi, p, e, u))
-            log(f"[{precision}] trajectory {i}: dH {out[-1]['dH']:.6g} acc {out[-1]['accepted']} "
-                f"cg iters {out[-1]['cg_iterations']} max resid {out[-1]['max_true_resid']:.2e}")
+            out[-1]["s"] = time.perf_counter() - ti      # each trajectory ends synchronised
+            log(f"[{precision}] trajectory {i}: {out[-1]['s']:.3f} s dH {out[-1]['dH']:.6g} acc "
+                f"{out[-1]['accepted']} cg iters {out[-1]['cg_iterations']} max resid {out[-1]['max_true_resid']:.2e}")
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         kt = h.kernel_times() if timing else None
         h.close()
-        return el, out, kt
+        return el, out, kt, phi_at
 
     # launch shapes from the project autotuner (remembered process-wide for this lattice)
     tuning = None
@@ -653,7 +784,7 @@ def main():
         log(f"autotuned CG workgroups per right-hand side: {tuning}")
 
     log(f"mixed-precision trajectories at {L}x{L}x{Lt}: warmup {W}, timed {K}")
-    el, out, kt = run("mixed", K, W, timing=True)
+    el, out, kt, phi_w = run("mixed", K, W, timing=True)
     iters = sum(o["cg_iterations"] for o in out)
     value = iters / el
     result = {
@@ -699,12 +830,32 @@ def main():
         extras["cg_iteration_f32"] = {"ms": it_ms, "GB/s": (BYTES_PER_SITE["cg_a_f32"] + BYTES_PER_SITE["cg_b_f32"]) * vol / (it_ms * 1e-3) / 1e9}
     if not args.no_extras:
         if args.fp64_steps > 0:
-            log("plain FP64 trajectories on the same seeds")
-            el64, out64, _ = run("fp64", args.fp64_steps, W)
-            extras["traj_per_hour_fp64"] = 3600.0 * args.fp64_steps / el64
-            extras["cg_iterations_per_traj_fp64"] = sum(o["cg_iterations"] for o in out64) / args.fp64_steps
+            # plain FP64 from the field the mixed run had at its first timed trajectory, with the
+            # same momenta, noise and uniforms: the same trajectory indices, so the comparison
+            # is of precision, not of how far the synthetic field has relaxed
+            nf = min(args.fp64_steps, K)
+            log(f"plain FP64 trajectories {W} .. {W + nf - 1} from the mixed run's field at {W}")
+            el64, out64, _, _ = run("fp64", nf, 0, phi_start=phi_w)
+            el_m = sum(o["s"] for o in out[:nf])
+            it_m = sum(o["cg_iterations"] for o in out[:nf])
+            it_64 = sum(o["cg_iterations"] for o in out64)
+            extras["traj_per_hour_fp64"] = 3600.0 * nf / el64
+            extras["cg_iterations_per_traj_fp64"] = it_64 / nf
             extras["dH_fp64"] = [o["dH"] for o in out64]
-            extras["mixed_vs_fp64_traj_speedup"] = extras["traj_per_hour_mixed"] / extras["traj_per_hour_fp64"]
+            extras["same_indices"] = {
+                "indices": [W, W + nf - 1],
+                "s_per_traj_mixed": [o["s"] for o in out[:nf]],
+                "s_per_traj_fp64": [o["s"] for o in out64],
+                "cg_iterations_mixed": [o["cg_iterations"] for o in out[:nf]],
+                "cg_iterations_fp64": [o["cg_iterations"] for o in out64],
+                "traj_per_hour_mixed": 3600.0 * nf / el_m,
+                "traj_per_hour_fp64": 3600.0 * nf / el64,
+                "ms_per_cg_iteration_mixed": 1e3 * el_m / it_m,
+                "ms_per_cg_iteration_fp64": 1e3 * el64 / it_64,
+                "mixed_vs_fp64_traj_speedup": el64 / el_m,
+                "mixed_vs_fp64_per_iteration_speedup": (el64 / it_64) / (el_m / it_m),
+            }
+            extras["mixed_vs_fp64_traj_speedup"] = el64 / el_m
         extras["pcg_80x80x200"] = pcg_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, W, args.pcg_steps)
         extras["metric_80x80x200"] = metric_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, args.seed)
         extras["production_model_80x80x200"] = prod_bench(hmcmod, torch, L, Lt, common, phi0, d_traj)
@@ -717,9 +868,19 @@ def main():
             log(f"isolated M^dag M {'f32' if f32 else 'f64'}: {aps:.0f} applies/s, {gbs:.0f} GB/s")
         cgbs = copy_bench(torch)
         extras["copy_1GiB_GB/s"] = cgbs
+        log(f"1 GiB device copy (torch): {cgbs:.0f} GB/s (read + write)")
+        extras["stream_probe"] = probe_bench(hmcmod, torch)
         if "roofline" in result:
             result["roofline"]["frac_of_copy"] = result["roofline"]["achieved"] / cgbs
-        log(f"1 GiB device copy: {cgbs:.0f} GB/s (read + write)")
+            result["roofline"]["frac_of_probe_3r3w"] = (result["roofline"]["achieved"]
+                                                        / extras["stream_probe"]["3r3w"]["GB/s"])
+        extras["mall_controlled_80x80x200_4rhs"] = mall_controlled_bench(hmcmod, torch, L, Lt, phi0, args.seed)
+        if "roofline" in result:
+            mc = extras["mall_controlled_80x80x200_4rhs"].get(dom)
+            if mc:
+                result["roofline"]["mall_controlled"] = {"achieved": mc["GB/s"], "frac": mc["frac_hbm_peak"],
+                                                         "avg_ms": mc["avg_ms"], "rhs_per_launch": 4,
+                                                         "bytes_per_launch": mc["bytes_per_launch"]}
         if args.batch_steps > 0:
             extras["batch_64_chains"] = batch_bench(hmcmod, torch, args.seed, args.batch_steps, 1)
         if not args.no_cpu:

@@ -459,6 +459,27 @@ int hmc_batch_trajectory(hmc_batch* batch, double* phi, const double* pi0, const
                          const double* u, double* dH, int* accepted, hmc_traj_stats* totals,
                          void* stream);
 
+/* -----------------------------------------------------------------------------------------
+ * Streaming reference (a measurement aid; no step of the method).
+ *
+ * The stencil kernels are bound by HBM bandwidth, and the rate an MI355X sustains depends
+ * on the mix of reads and writes.  hmc_stream_probe runs a plain grid-stride streaming
+ * kernel (16-byte vectors, 256-thread workgroups, `grid` workgroups; 0 = 2048) over
+ * `bytes` per stream (a positive multiple of 16), so that each kernel of the path can be
+ * compared with the streaming rate of its own mix:
+ *   HMC_PROBE_READ   reads src (bytes); writes one double per workgroup to dst (grid doubles);
+ *   HMC_PROBE_WRITE  writes dst (bytes); src unused (may be NULL);
+ *   HMC_PROBE_COPY   reads src, writes dst (bytes each);
+ *   HMC_PROBE_3R3W   reads three streams (src: 3 * bytes) and writes three (dst: 3 * bytes),
+ *                    the mix of one fused CG step.
+ * Device pointers, 16-byte aligned, caller-owned; asynchronous on the stream.  Errors:
+ * HMC_ERR_INVALID_ARG (kind, size, alignment, NULL, grid outside [1, 65536]), HMC_ERR_HIP. */
+#define HMC_PROBE_READ  0
+#define HMC_PROBE_WRITE 1
+#define HMC_PROBE_COPY  2
+#define HMC_PROBE_3R3W  3
+int hmc_stream_probe(int kind, const void* src, void* dst, size_t bytes, int grid, void* stream);
+
 /* Text for an HMC_* code. */
 const char* hmc_strerror(int code);
 

@@ -3,7 +3,8 @@
  * the FFT the kernels use can be checked on a machine without a GPU.
  *
  * They run the same __host__ __device__ functions the kernels call, compiled for the host.
- * Arguments are plain integers and host arrays; nothing here touches a device.
+ * Arguments are plain integers and host arrays; nothing here touches a device, except
+ * hmc_test_apply_precond (the preconditioner applied once on the GPU, for parity tests).
  */
 #ifndef HMC_TESTING_H
 #define HMC_TESTING_H
@@ -50,6 +51,19 @@ int hmc_test_fft_freq(int n, int pos);
  * Returns 0, or -1 for a lattice the preconditioner does not support. */
 int hmc_test_precond(int L, int L_tau, double dtau, const hmc_params* params, const double* in,
                      double* out, double* rz);
+
+/* One application z = P r of the Fourier preconditioner P = (K K^dagger)^{-1} of Methods C
+ * (Eq. 23-26) ON THE GPU, by the kernels a preconditioned solve runs (it is the only entry
+ * point here that touches a device).  ctx: a one-lattice context with its workspace set (its
+ * params need not ask for the preconditioner, but the lattice must support it in
+ * `precision`).  in: n <= max_rhs complex128 spinors (device); out: n spinors (device) in the
+ * Krylov precision of `precision`: complex128 for HMC_FP64, complex64 for HMC_MIXED (then r is
+ * in rounded to FP32 first, as the mixed solver holds it).  rz (optional, host, n doubles):
+ * <r, P r> reduced in FP64.  Uses the context's workspace; synchronises the stream.  Errors:
+ * HMC_ERR_INVALID_ARG (NULL, alignment, n, batch context, unsupported lattice),
+ * HMC_ERR_WORKSPACE, HMC_ERR_NONFINITE, HMC_ERR_HIP. */
+int hmc_test_apply_precond(hmc_ctx* ctx, int precision, const void* in, void* out, int n, double* rz,
+                           void* stream);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,7 @@ observables   SDW susceptibility (Eq. 34), order parameter and Binder cumulant
 Every function is plain NumPy in float64/complex128, written for readability,
 not speed.
 """
-from .model import Model, spinor_index, phi_index, stagger
+from .model import Model, spinor_index, stagger
 from .fermion import (dense_M, apply_M, apply_Mdag, apply_MdagM, dense_MdagM,
                       time_slice_block)
 from .solver import cg_solve
@@ -38,7 +38,7 @@ from .precond import kinetic_symbol, apply_precond, pcg_solve
 from . import closed_forms, metric, observables
 
 __all__ = [
-    "Model", "spinor_index", "phi_index", "stagger",
+    "Model", "spinor_index", "stagger",
     "dense_M", "apply_M", "apply_Mdag", "apply_MdagM", "dense_MdagM",
     "time_slice_block", "cg_solve", "heatbath", "pf_action", "pf_action_dense",
     "pf_force", "boson_action", "boson_force", "total_force", "hamiltonian",

@@ -66,11 +66,6 @@ def spinor_index(m, alpha, s, tau, x, y):
     return (((alpha * 2 + s) * m.Lt + tau) * m.L + x) * m.L + y
 
 
-def phi_index(m, l, tau, x, y):
-    """Flat position of component l of phi(tau, x, y) in a 3 x N_tau x L x L array."""
-    return ((l * m.Lt + tau) * m.L + x) * m.L + y
-
-
 def stagger(m):
     """exp(i Q_AF . r) with Q_AF = (pi, pi): the real sign (-1)^(x+y), shape (L, L)."""
     x = np.arange(m.L)[:, None]

@@ -21,6 +21,10 @@ HMC_FORCE_PF = 1
 HMC_FORCE_BOSON = 2
 HMC_PRECOND_NONE = 0
 HMC_PRECOND_FOURIER = 1
+HMC_PROBE_READ = 0
+HMC_PROBE_WRITE = 1
+HMC_PROBE_COPY = 2
+HMC_PROBE_3R3W = 3
 
 EXPORTED = [
     "hmc_create", "hmc_destroy", "hmc_set_params", "hmc_workspace_bytes", "hmc_set_workspace",
@@ -28,7 +32,7 @@ EXPORTED = [
     "hmc_apply_MdagM_f32", "hmc_cg_solve", "hmc_heatbath", "hmc_force",
     "hmc_force_from_solution", "hmc_pf_action", "hmc_boson_action", "hmc_trajectory",
     "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap", "hmc_test_tile_span", "hmc_test_fft",
-    "hmc_test_fft_freq", "hmc_test_precond",
+    "hmc_test_fft_freq", "hmc_test_precond", "hmc_test_apply_precond", "hmc_stream_probe",
     "hmc_set_kernel_timing", "hmc_get_kernel_times", "hmc_set_cg_workgroups",
     "hmc_get_cg_workgroups", "hmc_leapfrog", "hmc_autotune", "hmc_set_graphs",
     "hmc_set_metric", "hmc_metric_momenta", "hmc_metric_kinetic", "hmc_metric_norm2",
@@ -178,6 +182,8 @@ def load():
         "hmc_test_fft_freq": (I, [I, I]),
         "hmc_test_precond": (I, [I, I, D, ctypes.POINTER(HmcParams), ctypes.POINTER(D),
                                  ctypes.POINTER(D), ctypes.POINTER(D)]),
+        "hmc_test_apply_precond": (I, [P, I, P, P, I, ctypes.POINTER(D), P]),
+        "hmc_stream_probe": (I, [I, P, P, S, I, P]),
         "hmc_set_kernel_timing": (I, [P, I]),
         "hmc_get_kernel_times": (I, [P, ctypes.POINTER(HmcKernelTimes)]),
         "hmc_set_cg_workgroups": (I, [P, I, I]),

@@ -28,6 +28,7 @@
 #include "precond.h"
 #include "metric.h"
 #include "lattice.h"
+#include "probe.h"
 
 using namespace hmc;
 
@@ -1391,6 +1392,32 @@ static int check_batch(hmc_batch* hb, std::initializer_list<const void*> ptrs) {
     return need_ws(&hb->c);
 }
 
+// One application z = P r of the Fourier preconditioner on the GPU, through the same launches
+// a preconditioned solve makes: the CG start (r = b, |b|^2), then the three passes; the last
+// reduces the <r, z> partials of the second into the state records.
+template <typename R>
+static int apply_precond_impl(hmc_ctx* c, const double2* in, void* out, int n, double* rz, hipStream_t s) {
+    Launch<GeoOne> lc = launch_one<R>(c, n);
+    lc.pc = true;
+    CgVecs<R> v = KrylovBufs<R>::get(c, c->xsol, true);
+    const size_t bytes = size_t(n) * 4 * size_t(c->vol) * sizeof(C2<R>);
+    HIPCHK(hipMemsetAsync(v.z, 0, bytes, s));   // P 0 = 0: a zero input leaves z untouched
+    c->seq = 0;
+    hipLaunchKernelGGL((k_cg_init<R, GeoOne>), dim3(lc.ncg), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), lc.cg,
+                       in, c->xsol, v, 0.0, 0.0, 1, 1);
+    LAUNCHCHK();
+    int rc = enqueue_pc<R, GeoOne>(c, lc, v, PEND_BB, s);   // the last pass consumes <r, z>
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(out, v.z, bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->h_st, current_states(c), sizeof(CgState) * size_t(n), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int j = 0; j < n; ++j) {
+        if (c->h_st[j].mode == CG_FAILED) return fail(HMC_ERR_NONFINITE, "preconditioner met a non-finite value");
+        if (rz) rz[j] = c->h_st[j].mode == CG_DONE ? 0.0 : c->h_st[j].rz;
+    }
+    return HMC_OK;
+}
+
 // --------------------------------------------------------------------------------------
 // C ABI: one lattice
 
@@ -1522,6 +1549,51 @@ int hmc_test_precond(int L, int Lt, double dtau, const hmc_params* params, const
     }
     if (rz) *rz = acc;
     return 0;
+}
+
+int hmc_test_apply_precond(hmc_ctx* c, int precision, const void* in, void* out, int n, double* rz, void* stream) {
+    if (c == nullptr || in == nullptr || out == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    int rc = need_ws(c);
+    if (rc) return rc;
+    if (c->is_batch) return fail(HMC_ERR_INVALID_ARG, "one-lattice contexts only");
+    if (precision != HMC_FP64 && precision != HMC_MIXED) return fail(HMC_ERR_INVALID_ARG, "unknown precision");
+    if (n < 1 || n > c->cap) return fail(HMC_ERR_INVALID_ARG, "n = %d outside [1, %d]", n, c->cap);
+    if (!aligned16(in) || !aligned16(out)) return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
+    const int pi = precision == HMC_MIXED ? 1 : 0;
+    if (!c->pc_ok[pi]) return fail(HMC_ERR_INVALID_ARG, "Fourier preconditioner unavailable for this lattice");
+    const hipStream_t s = (hipStream_t)stream;
+    return pi ? apply_precond_impl<float>(c, static_cast<const double2*>(in), out, n, rz, s)
+              : apply_precond_impl<double>(c, static_cast<const double2*>(in), out, n, rz, s);
+}
+
+int hmc_stream_probe(int kind, const void* src, void* dst, size_t bytes, int grid, void* stream) {
+    if (dst == nullptr || (kind != HMC_PROBE_WRITE && src == nullptr)) return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    if (bytes == 0 || bytes % 16 != 0) return fail(HMC_ERR_INVALID_ARG, "bytes must be a positive multiple of 16");
+    if (!aligned16(dst) || (src != nullptr && !aligned16(src))) return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
+    if (grid == 0) grid = 2048;
+    if (grid < 1 || grid > 65536) return fail(HMC_ERR_INVALID_ARG, "grid outside [1, 65536]");
+    const size_t n4 = bytes / 16;
+    const float4* a = static_cast<const float4*>(src);
+    float4* b = static_cast<float4*>(dst);
+    const hipStream_t s = (hipStream_t)stream;
+    switch (kind) {
+        case HMC_PROBE_READ:
+            hipLaunchKernelGGL((k_stream<1, 0>), dim3(grid), dim3(kBlock), 0, s, a, nullptr, n4, static_cast<double*>(dst));
+            break;
+        case HMC_PROBE_WRITE:
+            hipLaunchKernelGGL((k_stream<0, 1>), dim3(grid), dim3(kBlock), 0, s, nullptr, b, n4, nullptr);
+            break;
+        case HMC_PROBE_COPY:
+            hipLaunchKernelGGL((k_stream<1, 1>), dim3(grid), dim3(kBlock), 0, s, a, b, n4, nullptr);
+            break;
+        case HMC_PROBE_3R3W:
+            hipLaunchKernelGGL((k_stream<3, 3>), dim3(grid), dim3(kBlock), 0, s, a, b, n4, nullptr);
+            break;
+        default:
+            return fail(HMC_ERR_INVALID_ARG, "unknown probe kind %d", kind);
+    }
+    LAUNCHCHK();
+    return HMC_OK;
 }
 
 int hmc_test_tile_span(int blk, int bpr, int nt, int out[3]) {

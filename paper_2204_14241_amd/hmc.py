@@ -268,6 +268,18 @@ class HMC:
     def apply_MdagM_f32(self, phi32, psi):
         return self._apply("hmc_apply_MdagM_f32", phi32, psi, True)
 
+    def apply_precond(self, r, precision="fp64"):
+        """z = P r (Methods C, Eq. 26) once, by the GPU kernels of a preconditioned solve
+        (hmc_test_apply_precond).  r: complex128 spinors; z comes back in the Krylov precision
+        (complex128 for "fp64", complex64 for "mixed").  Returns (z, [<r, P r>, ...])."""
+        r, n = self._spinors(r)
+        z = torch.empty(r.shape, dtype=torch.complex64 if precision == "mixed" else torch.complex128,
+                        device=self.device)
+        rz = (ctypes.c_double * n)()
+        self._call("hmc_test_apply_precond", {"fp64": HMC_FP64, "mixed": HMC_MIXED}[precision], _ptr(r),
+                   _ptr(z), n, rz, _stream())
+        return z, list(rz)
+
     def apply_into(self, name, phi, psi, out, n):
         """Raw launch for benchmarks: no allocation, no checks beyond the library's."""
         self._call(name, _ptr(phi), _ptr(psi), _ptr(out), n, _stream())
@@ -554,6 +566,16 @@ def _traj_dict(st, code):
     out = {f: getattr(st, f) for f, _ in HmcTrajStats._fields_}
     out["code"] = code
     return out
+
+
+def stream_probe(kind, src, dst, nbytes, grid=0):
+    """One launch of the library's streaming reference kernel (hmc_stream_probe) on the current
+    stream: kind "read", "write", "copy" or "3r3w"; src/dst: device tensors (src may be None for
+    "write"); nbytes: bytes per stream."""
+    k = {"read": _lib.HMC_PROBE_READ, "write": _lib.HMC_PROBE_WRITE, "copy": _lib.HMC_PROBE_COPY,
+         "3r3w": _lib.HMC_PROBE_3R3W}[kind]
+    check(_lib.load().hmc_stream_probe(k, _ptr(src), _ptr(dst), int(nbytes), int(grid), _stream()),
+          "hmc_stream_probe")
 
 
 def test_site(L, Lt, s):

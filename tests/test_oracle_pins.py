@@ -156,6 +156,23 @@ def test_heatbath_action_equals_eta_norm(tiny_inputs):
     assert abs(O.pf_action_dense(m, phi, chis) - ref) < 1e-12 * ref
 
 
+def test_pf_action_cg_form_matches_dense_and_eta_norm(tiny_inputs):
+    """The CG form of S_PF (Eq. 21) against a dense linear solve at 4x4x8, and at 8x8x16 against
+    the heat-bath identity S_PF(M^dagger eta) = |eta|^2, which no solver enters."""
+    m = tiny()
+    phi, _, etas, _ = tiny_inputs
+    chis = [O.heatbath(m, phi, e) for e in etas]
+    dense = O.pf_action_dense(m, phi, chis)
+    assert abs(O.pf_action(m, phi, chis, tol=1e-12) - dense) < 1e-10 * dense
+    m8 = O.Model(L=8, Lt=16)
+    g = S.rng(33)
+    phi8 = S.draw_phi(g, 8, 16, 0.5)
+    eta8 = S.draw_eta(g, 8, 16, 2)
+    ref = float((np.abs(eta8) ** 2).sum())
+    got = O.pf_action(m8, phi8, [O.heatbath(m8, phi8, e) for e in eta8], tol=1e-12)
+    assert abs(got - ref) < 1e-9 * ref
+
+
 def test_pf_force_central_differences(tiny_inputs):
     m = tiny()
     phi, _, etas, _ = tiny_inputs
