@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--profile-shapes", action="store_true",
                     help="counter runs over launch shapes: a 512 MiB device copy, then 150 CG "
                          "iterations per precision at 256, 512, 1024 and 2048 workgroups")
+    ap.add_argument("--applies-only", action="store_true",
+                    help="only the isolated M^dagger M legs (two-pass and one-pass, both precisions)")
     ap.add_argument("--profile-mall", action="store_true",
                     help="short fixed sequence for counter runs with a working set above the MALL: a "
                          "512 MiB device copy, then 60 mixed-precision CG iterations on 4 right-hand "
@@ -126,6 +128,22 @@ def profile_kernels(args):
     x, st = h.cg_solve(phi, psi)
     torch.cuda.synchronize()
     log(f"profile sequence done: cg iterations {st.iterations}")
+
+
+def applies_only(args):
+    """The isolated M^dagger M legs alone (two-pass and one-pass, FP32 and FP64), as JSON."""
+    import torch
+    import synth_inputs as S
+    from paper_2204_14241_amd import hmc as hmcmod
+    cfg = S.WORKLOADS[args.workload]
+    L, Lt = cfg["L"], cfg["Lt"]
+    out = {}
+    for f32 in (True, False):
+        aps, gbs, ms, nsets = apply_bench(hmcmod, torch, L, Lt, f32, args.apply_reps, args.seed + 1)
+        out["two_pass_" + ("f32" if f32 else "f64")] = {"applies_per_s": aps, "GB/s": gbs, "ms": ms}
+        out["fused_" + ("f32" if f32 else "f64")] = fused_apply_bench(hmcmod, torch, L, Lt, f32, args.apply_reps,
+                                                                      args.seed + 1)
+    print(json.dumps(out), flush=True)
 
 
 def profile_mall(args):
@@ -451,6 +469,53 @@ def apply_bench(hmcmod, torch, L, Lt, f32, reps, seed):
     return 1e3 / ms, bps / (ms * 1e-3) / 1e9, ms, nsets
 
 
+def fused_apply_bench(hmcmod, torch, L, Lt, f32, reps, seed, rows_set=(2, 4, 6, 8, 12, 16), slices_set=(1, 2, 4)):
+    """The one-pass M^dagger M (hmc_apply_MdagM / _f32) with buffer sets rotated through more than
+    512 MB, at each launch shape (rows per band, slices per segment); 76 B (FP32) or 152 B (FP64)
+    per site.  Returns the fastest shape's rate and every shape's time."""
+    import numpy as np
+    import synth_inputs as S
+    dev = torch.device("cuda")
+    vol = Lt * L * L
+    cdt, rdt = (torch.complex64, torch.float32) if f32 else (torch.complex128, torch.float64)
+    prec = "mixed" if f32 else "fp64"
+    set_bytes = vol * (2 * 4 * (8 if f32 else 16) + 3 * (4 if f32 else 8))
+    nsets = max(3, int(np.ceil(600e6 / set_bytes)))
+    h = hmcmod.HMC(L, Lt)
+    g = S.rng(seed)
+    sets = []
+    for _ in range(nsets):
+        phi = torch.from_numpy(S.draw_phi(g, L, Lt, 0.5)).to(dev, rdt)
+        psi = torch.from_numpy(S.draw_spinor(g, L, Lt, 1)).to(dev, cdt)
+        sets.append((phi, psi, torch.empty_like(psi)))
+    name = "hmc_apply_MdagM_f32" if f32 else "hmc_apply_MdagM"
+    bps = launch_bytes("apply_f32" if f32 else "apply_f64", vol)
+    tried = []
+    for rows in rows_set:
+        for sl in slices_set:
+            h.set_mdm_shape(rows, sl, prec)
+            shape = h.mdm_shape(prec, 1)
+            for i in range(nsets):
+                h.apply_into(name, sets[i][0], sets[i][1], sets[i][2], 1)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for i in range(reps):
+                phi, psi, out = sets[i % nsets]
+                h.apply_into(name, phi, psi, out, 1)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            tried.append({"rows": shape[0], "slices": shape[1], "workgroups": shape[2], "ms": ms,
+                          "GB/s": bps / (ms * 1e-3) / 1e9})
+    h.close()
+    best = min(tried, key=lambda t: t["ms"])
+    log(f"fused M^dag M {prec}: best {1e3 / best['ms']:.0f} applies/s, {best['GB/s']:.0f} GB/s at rows "
+        f"{best['rows']} slices {best['slices']}")
+    return {"applies_per_s": 1e3 / best["ms"], "GB/s": best["GB/s"], "ms": best["ms"],
+            "frac_hbm_peak": best["GB/s"] / HBM_PEAK_GBS, "bytes_per_site": bps // vol, "buffer_sets": nsets,
+            "rows": best["rows"], "slices": best["slices"], "workgroups": best["workgroups"], "tried": tried}
+
+
 def batch_bench(hmcmod, torch, seed, steps, warmup):
     """The batched workload: independent chains of uneven L, L_tau and r, 4 pseudofermions
     each, mixed precision.  Autotunes the shared CG launch shape, times one batched CG solve
@@ -719,6 +784,9 @@ def main():
     if args.profile_mall:
         profile_mall(args)
         return
+    if args.applies_only:
+        applies_only(args)
+        return
     if args.profile_shapes:
         profile_shapes(args)
         return
@@ -865,7 +933,9 @@ def main():
             extras["mdagm_apply_" + ("f32" if f32 else "f64")] = {
                 "applies_per_s": aps, "GB/s": gbs, "ms": ms, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
                 "buffer_sets": nsets, "bytes_per_site": 2 * BYTES_PER_SITE["apply_f32" if f32 else "apply_f64"]}
-            log(f"isolated M^dag M {'f32' if f32 else 'f64'}: {aps:.0f} applies/s, {gbs:.0f} GB/s")
+            log(f"isolated two-pass M^dag M {'f32' if f32 else 'f64'}: {aps:.0f} applies/s, {gbs:.0f} GB/s")
+            extras["mdagm_fused_" + ("f32" if f32 else "f64")] = fused_apply_bench(
+                hmcmod, torch, L, Lt, f32, args.apply_reps, args.seed + 1)
         cgbs = copy_bench(torch)
         extras["copy_1GiB_GB/s"] = cgbs
         log(f"1 GiB device copy (torch): {cgbs:.0f} GB/s (read + write)")

@@ -142,8 +142,12 @@ int hmc_apply_M(hmc_ctx* ctx, const double* phi, const void* in, void* out, int 
  * backward time link from tau - 1 with the sign of that link. */
 int hmc_apply_Mdag(hmc_ctx* ctx, const double* phi, const void* in, void* out, int n, void* stream);
 
-/* out_k = M^dagger M in_k, the normal operator of Eq. (22).  Uses the workspace for the
- * intermediate M in_k (n <= max_rhs).  Errors as above plus HMC_ERR_WORKSPACE. */
+/* out_k = M^dagger M in_k, the normal operator of Eq. (22) (n <= max_rhs).  The
+ * nearest-neighbour operator is applied in one pass over memory: M in_k is formed band by
+ * band in LDS and never stored (read in and phi, write out; see hmc_set_mdm_shape).  With
+ * the two-site hops (params.tn nonzero) two passes, the intermediate M in_k in the
+ * workspace.  The workspace must be set either way.  in and out must not overlap.  Errors as
+ * above plus HMC_ERR_WORKSPACE. */
 int hmc_apply_MdagM(hmc_ctx* ctx, const double* phi, const void* in, void* out, int n, void* stream);
 
 /* FP32 forms of the three applies: phi is float[3][L_tau][L][L], spinors complex64.
@@ -353,6 +357,17 @@ int hmc_set_kernel_timing(hmc_ctx* ctx, int enable);
  * use for `precision` (the request capped at the number of tiles). */
 int hmc_set_cg_workgroups(hmc_ctx* ctx, int precision, int max_per_rhs);
 int hmc_get_cg_workgroups(const hmc_ctx* ctx, int precision);
+
+/* Launch shape of the one-pass M^dagger M (hmc_apply_MdagM and hmc_apply_MdagM_f32 on the
+ * nearest-neighbour operator): each workgroup owns a band of `rows` lattice rows of one vector
+ * and marches through `slices` consecutive time slices, holding M in for its rows and the rows
+ * beside them in LDS; with slices = 1 each workgroup takes one slice of its band and forms
+ * M in at the previous slice itself.  0 selects the default (12 rows FP32, 6 rows FP64, one
+ * slice; rows are capped so that the band's M in fits 64 KB of LDS).  precision: HMC_FP64,
+ * HMC_MIXED or -1 for both.  Results do not depend on the shape.  hmc_get_mdm_shape reports the
+ * shape an apply of n vectors uses: rows, slices and the workgroup count (host ints). */
+int hmc_set_mdm_shape(hmc_ctx* ctx, int precision, int rows, int slices);
+int hmc_get_mdm_shape(const hmc_ctx* ctx, int precision, int n, int* rows, int* slices, int* workgroups);
 
 /* Result of hmc_autotune (host struct).  Index [0] FP64, [1] mixed precision. */
 #define HMC_TUNE_MAX 12

@@ -34,7 +34,7 @@ EXPORTED = [
     "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap", "hmc_test_tile_span", "hmc_test_fft",
     "hmc_test_fft_freq", "hmc_test_precond", "hmc_test_apply_precond", "hmc_stream_probe",
     "hmc_set_kernel_timing", "hmc_get_kernel_times", "hmc_set_cg_workgroups",
-    "hmc_get_cg_workgroups", "hmc_leapfrog", "hmc_autotune", "hmc_set_graphs",
+    "hmc_get_cg_workgroups", "hmc_set_mdm_shape", "hmc_get_mdm_shape", "hmc_leapfrog", "hmc_autotune", "hmc_set_graphs",
     "hmc_set_metric", "hmc_metric_momenta", "hmc_metric_kinetic", "hmc_metric_norm2",
     "hmc_metric_accumulate", "hmc_tuner_init", "hmc_tuner_add_step", "hmc_tuner_add_jump",
     "hmc_tuner_best_length", "hmc_jitter", "hmc_warmup_iteration", "hmc_sdw_accumulate",
@@ -188,6 +188,8 @@ def load():
         "hmc_get_kernel_times": (I, [P, ctypes.POINTER(HmcKernelTimes)]),
         "hmc_set_cg_workgroups": (I, [P, I, I]),
         "hmc_get_cg_workgroups": (I, [P, I]),
+        "hmc_set_mdm_shape": (I, [P, I, I, I]),
+        "hmc_get_mdm_shape": (I, [P, I, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "hmc_autotune": (I, [P, P, P, I, ctypes.POINTER(HmcTuneResult), P]),
         "hmc_set_graphs": (I, [P, I]),
         "hmc_set_metric": (I, [P, P]),

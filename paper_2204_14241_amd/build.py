@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhmc.so")
 SOURCES = [os.path.join(CSRC, "hmc.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("kernels.h", "lattice.h", "fft.h", "precond.h", "metric.h", "probe.h")] + [
+DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("kernels.h", "lattice.h", "fft.h", "precond.h", "metric.h", "probe.h", "march.h")] + [
     os.path.join(ROOT, "include", f) for f in ("hmc.h", "hmc_testing.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

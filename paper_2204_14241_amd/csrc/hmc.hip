@@ -29,6 +29,7 @@
 #include "metric.h"
 #include "lattice.h"
 #include "probe.h"
+#include "march.h"
 
 using namespace hmc;
 
@@ -185,6 +186,11 @@ struct hmc_ctx {
     static constexpr int kEv = 10;
     hipEvent_t tev[2][kEv] = {};
     hmc_kernel_times kt{};
+
+    // fused M^dagger M (march.h): rows per band and slices per segment [FP64, FP32]; 0 = the
+    // default for the lattice
+    int mdm_rows[2] = {0, 0};
+    int mdm_seg[2] = {0, 0};
 
     // graph replay of CG chunks
     bool graphs = false;
@@ -1369,12 +1375,96 @@ static int apply_impl(hmc_ctx* c, const R* phi, const void* in, void* out, int n
     return launch_apply<R, DAG>(c, phi, in, out, n, (hipStream_t)stream);
 }
 
+// Launch shape of the fused M^dagger M for n vectors: rows per band (so that the chi rows fit
+// 64 KB of LDS), slices per segment (1: one workgroup per slice and band, k_mdm*_tile; more:
+// the march), threads (one per element of the band, at most 512) and elements per thread (at
+// most 4).  The shape does not depend on n.
+struct MdmShape {
+    MarchPlan plan;
+    int threads, ept;
+    size_t lds;
+    bool tile;   // one slice per workgroup (k_mdm*_tile), else the march
+};
+template <typename R>
+static MdmShape mdm_shape(const hmc_ctx* c, int n) {
+    const int pi = sizeof(R) == sizeof(float) ? 1 : 0;
+    const int L = c->L, Lt = c->Lt, per_row = pi ? L / 2 : L;
+    // defaults: the fastest shapes at 80 x 80 x 200 (one slice per workgroup; 12 rows FP32, 6 FP64)
+    int rows = c->mdm_rows[pi] > 0 ? c->mdm_rows[pi] : (pi ? 12 : 6);
+    const int rows_lds = int((size_t(64) << 10) / (4 * size_t(L) * sizeof(C2<R>))) - 2;
+    rows = std::max(1, std::min({rows, rows_lds, 4 * kMarchMaxThreads / per_row}));
+    const int seg = c->mdm_seg[pi] > 0 ? c->mdm_seg[pi] : 1;
+    (void)n;
+    MdmShape m;
+    m.tile = seg == 1;
+    if (m.tile) rows = std::max(1, std::min(rows, kMarchMaxThreads / per_row));
+    m.plan = make_march_plan(L, Lt, rows, seg);
+    const int elems = m.plan.R * per_row;
+    if (m.tile) {
+        // one element of the band per thread, and the rows beside it on the first 2 rows' worth
+        m.threads = (std::max(elems, 2 * per_row) + 63) / 64 * 64;
+        m.ept = 1;
+    } else {
+        m.threads = std::min(kMarchMaxThreads, (elems + 63) / 64 * 64);
+        m.ept = (elems + m.threads - 1) / m.threads;
+    }
+    m.lds = march_lds<R>(m.plan.R, L);
+    return m;
+}
+
+template <typename R, int EPT>
+static void launch_mdm_ept(const hmc_ctx* c, const MdmShape& m, int grid, const R* phi, const void* in,
+                           void* out, hipStream_t s) {
+    if constexpr (sizeof(R) == sizeof(float))
+        hipLaunchKernelGGL((k_mdm2<EPT>), dim3(grid), dim3(m.threads), m.lds, s, c->lat, m.plan,
+                           static_cast<const float2*>(in), static_cast<float2*>(out), phi, c->cf32);
+    else
+        hipLaunchKernelGGL((k_mdm<EPT>), dim3(grid), dim3(m.threads), m.lds, s, c->lat, m.plan,
+                           static_cast<const double2*>(in), static_cast<double2*>(out), phi, c->cf64);
+}
+
+// out = M^dagger M in, one pass (nearest-neighbour operator, one lattice).
+template <typename R>
+static int launch_mdm(hmc_ctx* c, const R* phi, const void* in, void* out, int n, hipStream_t s) {
+    const MdmShape m = mdm_shape<R>(c, n);
+    const long long grid = (long long)n * m.plan.nband * m.plan.nseg;
+    if (grid >= (1LL << 31)) return fail(HMC_ERR_INVALID_ARG, "too many vectors");
+    if (m.tile) {
+        if constexpr (sizeof(R) == sizeof(float))
+            hipLaunchKernelGGL(k_mdm2_tile, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat, m.plan,
+                               static_cast<const float2*>(in), static_cast<float2*>(out), phi, c->cf32);
+        else
+            hipLaunchKernelGGL(k_mdm_tile, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat, m.plan,
+                               static_cast<const double2*>(in), static_cast<double2*>(out), phi, c->cf64);
+        LAUNCHCHK();
+        return HMC_OK;
+    }
+    switch (m.ept) {
+        case 1: launch_mdm_ept<R, 1>(c, m, int(grid), phi, in, out, s); break;
+        case 2: launch_mdm_ept<R, 2>(c, m, int(grid), phi, in, out, s); break;
+        case 3: launch_mdm_ept<R, 3>(c, m, int(grid), phi, in, out, s); break;
+        case 4: launch_mdm_ept<R, 4>(c, m, int(grid), phi, in, out, s); break;
+        default: return fail(HMC_ERR_INVALID_ARG, "fused M^dagger M shape needs %d elements per thread", m.ept);
+    }
+    LAUNCHCHK();
+    return HMC_OK;
+}
+
 template <typename R>
 static int apply_normal_impl(hmc_ctx* c, const R* phi, const void* in, void* out, int n, void* stream) {
     if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
     int rc = need_ws(c);
     if (rc) return rc;
     if (n < 1 || n > c->cap) return fail(HMC_ERR_INVALID_ARG, "n must lie in [1, %d]", c->cap);
+    if (!c->cf64.nn2) {
+        // one pass: M^dagger (M in) with M in held on chip
+        if (phi == nullptr || in == nullptr || out == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+        if (!aligned16(phi) || !aligned16(in) || !aligned16(out))
+            return fail(HMC_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
+        if (in == out) return fail(HMC_ERR_INVALID_ARG, "in and out must not overlap");
+        return launch_mdm<R>(c, phi, in, out, n, (hipStream_t)stream);
+    }
+    // the two-site hops: two passes through the workspace
     void* tmp;
     if constexpr (sizeof(R) == sizeof(double)) tmp = c->t64; else tmp = c->t32;
     if (tmp == in || tmp == out) return fail(HMC_ERR_INVALID_ARG, "in/out alias the workspace");
@@ -1795,6 +1885,32 @@ int hmc_set_cg_workgroups(hmc_ctx* c, int precision, int max_per_rhs) {
     if (max_per_rhs < 1 || max_per_rhs > kMaxBpr)
         return fail(HMC_ERR_INVALID_ARG, "workgroups per right-hand side must lie in [1, %d]", kMaxBpr);
     return set_cg_shape(c, precision, max_per_rhs);
+}
+
+int hmc_set_mdm_shape(hmc_ctx* c, int precision, int rows, int slices) {
+    if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
+    if (precision != HMC_FP64 && precision != HMC_MIXED && precision != -1)
+        return fail(HMC_ERR_INVALID_ARG, "unknown precision");
+    if (rows < 0 || rows > 256 || slices < 0 || slices > 1 << 20)
+        return fail(HMC_ERR_INVALID_ARG, "rows must lie in [0, 256] and slices be >= 0");
+    for (int pi = 0; pi < 2; ++pi)
+        if (precision == -1 || precision == (pi ? HMC_MIXED : HMC_FP64)) {
+            c->mdm_rows[pi] = rows;
+            c->mdm_seg[pi] = slices;
+        }
+    return HMC_OK;
+}
+
+int hmc_get_mdm_shape(const hmc_ctx* c, int precision, int n, int* rows, int* slices, int* workgroups) {
+    if (c == nullptr || rows == nullptr || slices == nullptr || workgroups == nullptr)
+        return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    if (precision != HMC_FP64 && precision != HMC_MIXED) return fail(HMC_ERR_INVALID_ARG, "unknown precision");
+    if (n < 1) return fail(HMC_ERR_INVALID_ARG, "n must be >= 1");
+    const MdmShape m = precision == HMC_MIXED ? mdm_shape<float>(c, n) : mdm_shape<double>(c, n);
+    *rows = m.plan.R;
+    *slices = m.plan.seglen;
+    *workgroups = n * m.plan.nband * m.plan.nseg;
+    return HMC_OK;
 }
 
 int hmc_get_cg_workgroups(const hmc_ctx* c, int precision) {

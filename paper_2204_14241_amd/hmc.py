@@ -135,6 +135,18 @@ class HMC:
         check(self.lib.hmc_set_cg_workgroups(self._ctx, pr, int(n)), "hmc_set_cg_workgroups")
         return self.cg_workgroups()
 
+    def set_mdm_shape(self, rows=0, slices=0, precision=None):
+        """Launch shape of the one-pass M^dagger M (hmc_set_mdm_shape); 0 = default."""
+        pr = {None: -1, "fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]
+        check(self.lib.hmc_set_mdm_shape(self._ctx, pr, int(rows), int(slices)), "hmc_set_mdm_shape")
+
+    def mdm_shape(self, precision="fp64", n=1):
+        """(rows per band, slices per segment, workgroups) of a one-pass M^dagger M of n vectors."""
+        r, t, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self._call("hmc_get_mdm_shape", {"fp64": HMC_FP64, "mixed": HMC_MIXED}[precision], int(n),
+                   ctypes.byref(r), ctypes.byref(t), ctypes.byref(w))
+        return r.value, t.value, w.value
+
     def cg_workgroups(self):
         return {"fp64": self.lib.hmc_get_cg_workgroups(self._ctx, HMC_FP64),
                 "mixed": self.lib.hmc_get_cg_workgroups(self._ctx, HMC_MIXED)}
