@@ -4,14 +4,16 @@
 // K, the phi-independent part of the fermion matrix, is diagonal on twisted plane waves
 // exp(i w_n tau + 2 pi i (kx x + ky y) / L) with w_n = pi (2 n + 1) / N_tau (the twist
 // exp(i pi tau / N_tau) turns periodic functions of tau into antiperiodic ones).  Its eigenvalue
-// is exp(i w_n) - b with b = 1 + dtau (mu_band + 2 t[band][0] cos k_x + 2 t[band][1] cos k_y),
-// so P multiplies each Fourier coefficient of the untwisted field by
-// 1 / |exp(i w_n) - b|^2 = 1 / ((1 - b)^2 + 4 b sin^2(w_n / 2)).
+// is exp(i w_n) - b with b = 1 + dtau (mu_band + 2 t[band][0] cos k_x + 2 t[band][1] cos k_y
+// + 2 tn[band][0] cos 2k_x + 2 tn[band][1] cos 2k_y), the tn terms being the hops by two
+// sites of the production model, so P multiplies each Fourier coefficient of the untwisted
+// field by 1 / |exp(i w_n) - b|^2 = 1 / ((1 - b)^2 + 4 b sin^2(w_n / 2)).
 //
-// The transforms are split into three passes over a spinor so that each pass holds a whole
-// line set in LDS: (1) the 2-D (x, y) transform of every (component, tau) slice; (2) per group
-// of (x, y) columns of one component, twist, transform along tau, multiply by the symbol,
-// inverse along tau, untwist; (3) the inverse 2-D transform of every slice.
+// The preconditioner runs in three passes over a spinor: (1) the 2-D (x, y) transform of
+// every (component, tau) slice, held in LDS; (2) per (x, y) frequency column, the exact
+// inverse of K K^dagger along tau as two first-order recurrences in registers (precond.h),
+// which is what the twisted tau transform and the symbol compute; (3) the inverse 2-D
+// transform of every slice.  This header holds the transforms and the tables.
 //
 // FFT: forward is a decimation-in-frequency sequence of radix stages done in place, so its
 // output sits in mixed-radix digit-reversed order (position p holds frequency fft_freq(p));
