@@ -156,6 +156,20 @@ int hmc_apply_M_f32(hmc_ctx* ctx, const float* phi, const void* in, void* out, i
 int hmc_apply_Mdag_f32(hmc_ctx* ctx, const float* phi, const void* in, void* out, int n, void* stream);
 int hmc_apply_MdagM_f32(hmc_ctx* ctx, const float* phi, const void* in, void* out, int n, void* stream);
 
+/* hmc_apply_MdagM (FP64, two passes) for callers that cannot allocate device memory or use a
+ * workspace: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The intermediate M in lives in a static device buffer of the library
+ * (HMC_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends) instead of the workspace;
+ * the context's workspace need not be set.  Nothing is allocated, freed or synchronised.
+ * n * 4 * L_tau * L^2 * 16 bytes must fit the buffer (n = 1 up to 1,048,576 sites, e.g.
+ * 40 x 40 x 100 with n <= 6), else HMC_ERR_INVALID_ARG.  Every call on one GPU shares that
+ * GPU's buffer and leaves its intermediate there: calls that overlap on one GPU (two streams,
+ * two threads) race and must be serialised by the caller.  One-lattice contexts only.
+ * Results are bitwise those of hmc_apply_M followed by hmc_apply_Mdag.  Errors:
+ * HMC_ERR_INVALID_ARG, HMC_ERR_HIP. */
+#define HMC_NOALLOC_SCRATCH_BYTES (64u << 20)
+int hmc_apply_MdagM_noalloc(hmc_ctx* ctx, const double* phi, const void* in, void* out, int n, void* stream);
+
 /* Solve (M^dagger M) x_k = b_k, k < n <= max_rhs, by conjugate gradient from x = 0
  * (Methods C).  b, x: complex128 spinors.  Convergence: the FP64 true residual
  * ||b - A x|| / ||b|| <= cg_tol, evaluated once the iterated residual passes that bound

@@ -21,6 +21,7 @@ HMC_FORCE_PF = 1
 HMC_FORCE_BOSON = 2
 HMC_PRECOND_NONE = 0
 HMC_PRECOND_FOURIER = 1
+HMC_NOALLOC_SCRATCH_BYTES = 64 << 20
 HMC_PROBE_READ = 0
 HMC_PROBE_WRITE = 1
 HMC_PROBE_COPY = 2
@@ -29,7 +30,7 @@ HMC_PROBE_3R3W = 3
 EXPORTED = [
     "hmc_create", "hmc_destroy", "hmc_set_params", "hmc_workspace_bytes", "hmc_set_workspace",
     "hmc_apply_M", "hmc_apply_Mdag", "hmc_apply_MdagM", "hmc_apply_M_f32", "hmc_apply_Mdag_f32",
-    "hmc_apply_MdagM_f32", "hmc_cg_solve", "hmc_heatbath", "hmc_force",
+    "hmc_apply_MdagM_f32", "hmc_apply_MdagM_noalloc", "hmc_cg_solve", "hmc_heatbath", "hmc_force",
     "hmc_force_from_solution", "hmc_pf_action", "hmc_boson_action", "hmc_trajectory",
     "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap", "hmc_test_tile_span", "hmc_test_fft",
     "hmc_test_fft_freq", "hmc_test_precond", "hmc_test_apply_precond", "hmc_stream_probe",
@@ -165,6 +166,7 @@ def load():
         "hmc_apply_M_f32": (I, [P, P, P, P, I, P]),
         "hmc_apply_Mdag_f32": (I, [P, P, P, P, I, P]),
         "hmc_apply_MdagM_f32": (I, [P, P, P, P, I, P]),
+        "hmc_apply_MdagM_noalloc": (I, [P, P, P, P, I, P]),
         "hmc_cg_solve": (I, [P, P, P, P, I, ctypes.POINTER(HmcCgStats), P]),
         "hmc_heatbath": (I, [P, P, P, P, I, P]),
         "hmc_force": (I, [P, P, P, I, P, ctypes.POINTER(D), I, ctypes.POINTER(HmcCgStats), P]),

@@ -82,6 +82,16 @@ int tiles2_host(int vol) { return (vol / 2 + kBlock - 1) / kBlock; }
 
 }  // namespace
 
+// Device scratch for the entry point that must not allocate (hmc_apply_MdagM_noalloc): the
+// intermediate M in of its two passes.  Each GPU holds its own copy for the life of the
+// process.  In host code the name stands for a host-side symbol, not a device address: the
+// address comes from hipGetSymbolAddress, taken once per device when a context is created on
+// it (scratch_for_device) and kept in the context.
+constexpr size_t kStaticScratchBytes = size_t(HMC_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_addr;   // device -> device address of `scratch`
+
 // Batch-mode description: nchains independent lattices, nrhs right-hand sides each.
 struct BatchInfo {
     int nchains = 0, nrhs = 0;
@@ -191,6 +201,10 @@ struct hmc_ctx {
     // default for the lattice
     int mdm_rows[2] = {0, 0};
     int mdm_seg[2] = {0, 0};
+
+    // device address of the static scratch on this context's GPU (null if it could not be
+    // resolved; only hmc_apply_MdagM_noalloc uses it)
+    void* scratch = nullptr;
 
     // graph replay of CG chunks
     bool graphs = false;
@@ -1216,8 +1230,26 @@ static int upload_pc(hmc_ctx* c) {
     return HMC_OK;
 }
 
+// The device address of `scratch` on `device` (current), resolved once per device.  Returns
+// null, with the failure left in hmc_last_error, if the runtime cannot resolve it.
+static void* scratch_for_device(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it != g_scratch_addr.end()) return it->second;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(HMC_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        return nullptr;
+    }
+    g_scratch_addr[device] = p;
+    return p;
+}
+
 static int create_common(hmc_ctx* c) {
     if (hipGetDevice(&c->device) != hipSuccess) return fail(HMC_ERR_HIP, "hipGetDevice failed");
+    c->scratch = scratch_for_device(c->device);
     if (hipHostMalloc((void**)&c->h_st, sizeof(CgState) * 2 * size_t(c->nunits), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_slots, sizeof(double) * kSlots, hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) != hipSuccess ||
@@ -1980,6 +2012,22 @@ int hmc_apply_Mdag_f32(hmc_ctx* c, const float* phi, const void* in, void* out, 
 }
 int hmc_apply_MdagM_f32(hmc_ctx* c, const float* phi, const void* in, void* out, int n, void* stream) {
     return apply_normal_impl<float>(c, phi, in, out, n, stream);
+}
+
+int hmc_apply_MdagM_noalloc(hmc_ctx* c, const double* phi, const void* in, void* out, int n, void* stream) {
+    if (c == nullptr || phi == nullptr || in == nullptr || out == nullptr)
+        return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    if (c->is_batch) return fail(HMC_ERR_INVALID_ARG, "one-lattice contexts only");
+    if (n < 1) return fail(HMC_ERR_INVALID_ARG, "n must be >= 1");
+    const size_t need = size_t(n) * 4 * size_t(c->vol) * sizeof(double2);
+    if (need > kStaticScratchBytes)
+        return fail(HMC_ERR_INVALID_ARG, "n = %d vectors of this lattice need %zu bytes of scratch, above the %zu "
+                    "of the static buffer", n, need, kStaticScratchBytes);
+    if (c->scratch == nullptr) return fail(HMC_ERR_HIP, "the static scratch has no device address on this GPU");
+    if (in == c->scratch || out == c->scratch) return fail(HMC_ERR_INVALID_ARG, "in/out alias the static scratch");
+    int rc = apply_impl<double, false>(c, phi, in, c->scratch, n, stream);
+    if (rc) return rc;
+    return apply_impl<double, true>(c, phi, c->scratch, out, n, stream);
 }
 
 int hmc_heatbath(hmc_ctx* c, const double* phi, const void* eta, void* chi, int n_pf, void* stream) {

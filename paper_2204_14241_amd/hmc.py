@@ -271,6 +271,15 @@ class HMC:
     def apply_MdagM(self, phi, psi):
         return self._apply("hmc_apply_MdagM", phi, psi)
 
+    def apply_MdagM_noalloc(self, phi, psi, out=None):
+        """M^dagger M psi through the entry point that allocates nothing (its intermediate in
+        the library's static device buffer).  out: an optional preallocated result."""
+        self._phi(phi)
+        psi, n = self._spinors(psi)
+        out = torch.empty_like(psi) if out is None else self._spinors(out)[0]
+        self._call("hmc_apply_MdagM_noalloc", _ptr(phi), _ptr(psi), _ptr(out), n, _stream())
+        return out
+
     def apply_M_f32(self, phi32, psi):
         return self._apply("hmc_apply_M_f32", phi32, psi, True)
 
