@@ -85,13 +85,19 @@ def parse():
                          "iterations per precision at 256, 512, 1024 and 2048 workgroups")
     ap.add_argument("--applies-only", action="store_true",
                     help="only the isolated M^dagger M legs (two-pass and one-pass, both precisions)")
+    ap.add_argument("--mall-bpr", type=int, default=0,
+                    help="--profile-mall: CG workgroups per right-hand side (0: the default)")
+    ap.add_argument("--profile-fused", action="store_true",
+                    help="short fixed sequence for counter runs of the one-pass M^dagger M: a 512 MiB "
+                         "device copy, then three FP32 and three FP64 applies at the workload size")
     ap.add_argument("--profile-mall", action="store_true",
                     help="short fixed sequence for counter runs with a working set above the MALL: a "
                          "512 MiB device copy, then 60 mixed-precision CG iterations on 4 right-hand "
                          "sides at once at the workload size")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="short fixed sequence for counter runs: a 512 MiB device copy (the "
-                         "byte-counter calibration), FP32/FP64 M and M^dagger applies and 60 "
+                         "byte-counter calibration), the autotuner (the benchmark's launch shape; "
+                         "--no-tune skips it), FP32/FP64 M and M^dagger applies and 60 "
                          "mixed-precision CG iterations at the workload size")
     return ap.parse_args()
 
@@ -118,6 +124,8 @@ def profile_kernels(args):
     phi = torch.from_numpy(S.draw_phi(g, L, Lt, cfg["phi_var"])).to(dev)
     psi = torch.from_numpy(S.draw_spinor(g, L, Lt, 1)).to(dev)
     h = hmcmod.HMC(L, Lt, precision="mixed", cg_maxit=60, reliable_every=50)
+    if not args.no_tune:
+        log(f"autotune: {h.autotune(phi, h.heatbath(phi, psi))}")   # the benchmark's launch shape
     phi32, psi32 = phi.float(), psi.to(torch.complex64)
     out32, out64 = torch.empty_like(psi32), torch.empty_like(psi)
     for _ in range(3):
@@ -146,6 +154,29 @@ def applies_only(args):
     print(json.dumps(out), flush=True)
 
 
+def profile_fused(args):
+    """Counter-run sequence of the one-pass M^dagger M at its default launch shape."""
+    import torch
+    import synth_inputs as S
+    from paper_2204_14241_amd import hmc as hmcmod
+    cfg = S.WORKLOADS[args.workload]
+    L, Lt = cfg["L"], cfg["Lt"]
+    dev = torch.device("cuda")
+    calibration_copy(torch)
+    g = S.rng(args.seed)
+    phi = torch.from_numpy(S.draw_phi(g, L, Lt, cfg["phi_var"])).to(dev)
+    psi = torch.from_numpy(S.draw_spinor(g, L, Lt, 1)).to(dev)
+    h = hmcmod.HMC(L, Lt)
+    phi32, psi32 = phi.float(), psi.to(torch.complex64)
+    out32, out64 = torch.empty_like(psi32), torch.empty_like(psi)
+    for _ in range(3):
+        h.apply_into("hmc_apply_MdagM_f32", phi32, psi32, out32, 1)
+    for _ in range(3):
+        h.apply_into("hmc_apply_MdagM", phi, psi, out64, 1)
+    torch.cuda.synchronize()
+    log(f"profile sequence done: shapes f32 {h.mdm_shape('mixed')}, f64 {h.mdm_shape('fp64')}")
+
+
 def profile_mall(args):
     """Counter-run sequence of the in-CG kernels with a working set the MALL cannot hold."""
     import torch
@@ -161,6 +192,8 @@ def profile_mall(args):
     eta = torch.from_numpy(S.draw_eta(g, L, Lt, 4)).to(dev)
     h = hmcmod.HMC(L, Lt, precision="mixed", n_pf=4, max_rhs=4, cg_tol=1e-30, cg_maxit=60, reliable_every=50)
     chi = h.heatbath(phi, eta)
+    if args.mall_bpr > 0:
+        h.set_cg_workgroups(args.mall_bpr, "mixed")
     try:
         h.cg_solve(phi, chi)
     except HmcError as e:          # the tolerance is never met: 60 iterations run
@@ -235,6 +268,18 @@ def profile_pcg(args):
         h.close()
 
 
+KERNEL_SOURCES = ("kernels.h", "march.h", "lattice.h")
+
+
+def kernel_sources_sha256():
+    """SHA-256 over the sources of the CG kernels (the counters are void once they change)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2204_14241_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(kname):
     """HBM bytes per launch (read + write) from the committed rocprofv3 counter summary,
     or None if the kernel source changed since the counters were taken."""
@@ -244,8 +289,7 @@ def measured_traffic(kname):
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    src = open(os.path.join(ROOT, "paper_2204_14241_amd", "csrc", "kernels.h"), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec.get("kernels_h_sha256"):
+    if kernel_sources_sha256() != rec.get("kernel_sources_sha256"):
         return None
     t = rec.get("per_launch", {}).get(kname)
     return None if t is None else t["read_bytes"] + t["write_bytes"]
@@ -729,6 +773,7 @@ def mall_controlled_bench(hmcmod, torch, L, Lt, phi0, seed, nrhs=4):
     phi = torch.from_numpy(phi0).to(dev)
     eta = torch.from_numpy(S.draw_eta(S.rng(seed + 11), L, Lt, nrhs)).to(dev)
     chi = h.heatbath(phi, eta)
+    tune = h.autotune(phi, chi)         # the launch shape for nrhs right-hand sides per launch
     h.cg_solve(phi, chi)
     h.set_kernel_timing(True)
     torch.cuda.synchronize()
@@ -739,7 +784,7 @@ def mall_controlled_bench(hmcmod, torch, L, Lt, phi0, seed, nrhs=4):
     kt = h.kernel_times()
     ws = vol * (5 * nrhs * SPINOR_BYTES["f32"] + PHI_BYTES["f32"])
     rec = {"rhs": nrhs, "working_set_bytes": ws, "solve_s": el, "iterations": list(st.iterations),
-           "max_true_resid": max(st.true_resid), "bpr": h.cg_workgroups()["mixed"]}
+           "max_true_resid": max(st.true_resid), "bpr": h.cg_workgroups()["mixed"], "autotune": tune}
     for name in ("cg_a_f32", "cg_b_f32"):
         ms, n = kt[name]
         if ms:
@@ -783,6 +828,9 @@ def main():
         return
     if args.profile_mall:
         profile_mall(args)
+        return
+    if args.profile_fused:
+        profile_fused(args)
         return
     if args.applies_only:
         applies_only(args)
@@ -878,7 +926,10 @@ def main():
     if ms_dom:
         bytes_launch = BYTES_PER_SITE[dom] * vol
         ach = bytes_launch / (ms_dom * 1e-3) / 1e9
-        kname = {"cg_a_f32": "k_cg_a2", "cg_b_f32": "k_cg_b2"}[dom]
+        hq = hmcmod.HMC(L, Lt, **common)            # the launch shape the trajectories used
+        marching = hq.cg_march("mixed")[0] > 0
+        hq.close()
+        kname = {"cg_a_f32": "k_cg_a2_march" if marching else "k_cg_a2", "cg_b_f32": "k_cg_b2"}[dom]
         result["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": ach / HBM_PEAK_GBS,
                               "traffic": measured_traffic(kname) if args.workload == "large_80x80x200" else None,

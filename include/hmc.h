@@ -383,24 +383,53 @@ int hmc_get_cg_workgroups(const hmc_ctx* ctx, int precision);
 int hmc_set_mdm_shape(hmc_ctx* ctx, int precision, int rows, int slices);
 int hmc_get_mdm_shape(const hmc_ctx* ctx, int precision, int n, int* rows, int* slices, int* workgroups);
 
+/* CG step A (the direction update, t = M p and the fused x update) as a march (one lattice,
+ * nearest-neighbour operator): each workgroup owns a band of `rows` lattice rows of one
+ * right-hand side and walks `slices` consecutive time slices, holding the new direction of two
+ * consecutive slices in LDS and loading the next slice while it computes the current one, so
+ * that every value of r (z), p, x and phi leaves HBM once.  rows = 0 switches back to the tile
+ * kernels; slices = 0 picks about one workgroup per compute unit.  Default for one-lattice
+ * contexts: 8 rows (FP32) / 4 rows (FP64), 8 slices, or the autotuner's choice.  precision:
+ * HMC_FP64, HMC_MIXED or -1 for both.  The algebra is that of the tile kernels; only the order
+ * of the FP64 partial sums differs.  One-lattice contexts only (HMC_ERR_INVALID_ARG on a
+ * batch); lattices whose band does not fit (rows + 2 rows of one thread per element, at most
+ * 512 threads) keep the tile kernels. */
+int hmc_set_cg_march(hmc_ctx* ctx, int precision, int rows, int slices);
+/* The setting in use for `precision` (host ints; rows 0: the tile kernels). */
+int hmc_get_cg_march(const hmc_ctx* ctx, int precision, int* rows, int* slices);
+
 /* Result of hmc_autotune (host struct).  Index [0] FP64, [1] mixed precision. */
 #define HMC_TUNE_MAX 12
+#define HMC_TUNE_MARCH_MAX 16
 typedef struct hmc_tune_result {
     int    cg_workgroups[2];   /* chosen workgroups per right-hand side                       */
     double us_per_iter[2];     /* measured time per CG iteration at the choice (microseconds) */
     int    candidates;         /* launch shapes timed, both precisions                         */
-    int    tried[2];           /* launch shapes timed per precision (<= HMC_TUNE_MAX)          */
-    int    tried_workgroups[2][HMC_TUNE_MAX];  /* each shape timed ...                         */
+    int    tried[2];           /* workgroup counts timed per precision (<= HMC_TUNE_MAX)       */
+    int    tried_workgroups[2][HMC_TUNE_MAX];  /* each count timed ...                         */
     double tried_us[2][HMC_TUNE_MAX];          /* ... and its time per CG iteration (us)       */
+    int    march_rows[2];      /* chosen step-A march (hmc_set_cg_march): rows, 0 = tile kernels */
+    int    march_slices[2];    /* ... and slices per segment                                   */
+    int    mtried[2];          /* march shapes timed per precision (<= HMC_TUNE_MARCH_MAX)     */
+    int    mtried_rows[2][HMC_TUNE_MARCH_MAX];
+    int    mtried_slices[2][HMC_TUNE_MARCH_MAX];
+    double mtried_us[2][HMC_TUNE_MARCH_MAX];
+    int    from_cache;         /* 1: the shapes came from the on-disk cache, nothing was timed */
 } hmc_tune_result;
 
 /* Autotuner of the CG launch shape.  For each precision, times 100 CG iterations on the
- * caller's phi and right-hand sides b (n complex128 spinors, n <= max_rhs) at each
- * candidate workgroup count (12 multiples of 8 from 128 to 4096, capped at the tile count) with HIP events on the
- * stream, keeps the fastest, and records the choice process-wide so that later contexts of
- * the same lattice, right-hand-side count and device start with it.  Uses the context's
- * workspace (no other allocation); the run parameters are restored afterwards.
- * Synchronises the stream.  Errors: as hmc_cg_solve. */
+ * caller's phi and right-hand sides b (n complex128 spinors, n <= max_rhs) with HIP events on
+ * the stream: first at each candidate workgroup count of the tile kernels (12 multiples of 8
+ * from 128 to 4096, capped at the tile count), then, for a one-lattice nearest-neighbour
+ * context, at each step-A march shape (rows per band x slices per segment, up to 16 that fit)
+ * with the chosen count; keeps the fastest.  The choice is remembered process-wide for later
+ * contexts of the same lattice, right-hand-side count and device, and written to an on-disk
+ * cache keyed by (L, L_tau, right-hand sides, device, kernel-source hash): the file named by
+ * the environment variable HMC_TUNE_CACHE, else $XDG_CACHE_HOME/hmc/tune.txt, else
+ * $HOME/.cache/hmc/tune.txt (HMC_TUNE_CACHE=off disables it).  hmc_create applies a cached
+ * choice; hmc_autotune with the variable HMC_TUNE_REUSE=1 returns a cached choice without
+ * timing.  Uses the context's workspace (no other allocation); the run parameters are restored
+ * afterwards.  Synchronises the stream.  Errors: as hmc_cg_solve. */
 int hmc_autotune(hmc_ctx* ctx, const double* phi, const void* b, int n, hmc_tune_result* out,
                  void* stream);
 int hmc_get_kernel_times(const hmc_ctx* ctx, hmc_kernel_times* out);

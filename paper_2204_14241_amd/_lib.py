@@ -35,7 +35,7 @@ EXPORTED = [
     "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap", "hmc_test_tile_span", "hmc_test_fft",
     "hmc_test_fft_freq", "hmc_test_precond", "hmc_test_apply_precond", "hmc_stream_probe",
     "hmc_set_kernel_timing", "hmc_get_kernel_times", "hmc_set_cg_workgroups",
-    "hmc_get_cg_workgroups", "hmc_set_mdm_shape", "hmc_get_mdm_shape", "hmc_leapfrog", "hmc_autotune", "hmc_set_graphs",
+    "hmc_get_cg_workgroups", "hmc_set_mdm_shape", "hmc_get_mdm_shape", "hmc_set_cg_march", "hmc_get_cg_march", "hmc_leapfrog", "hmc_autotune", "hmc_set_graphs",
     "hmc_set_metric", "hmc_metric_momenta", "hmc_metric_kinetic", "hmc_metric_norm2",
     "hmc_metric_accumulate", "hmc_tuner_init", "hmc_tuner_add_step", "hmc_tuner_add_jump",
     "hmc_tuner_best_length", "hmc_jitter", "hmc_warmup_iteration", "hmc_sdw_accumulate",
@@ -96,11 +96,20 @@ class HmcTrajStats(ctypes.Structure):
 HMC_TUNE_MAX = 12
 
 
+HMC_TUNE_MARCH_MAX = 16
+
+
 class HmcTuneResult(ctypes.Structure):
     _fields_ = [("cg_workgroups", ctypes.c_int * 2), ("us_per_iter", ctypes.c_double * 2),
                 ("candidates", ctypes.c_int), ("tried", ctypes.c_int * 2),
                 ("tried_workgroups", (ctypes.c_int * HMC_TUNE_MAX) * 2),
-                ("tried_us", (ctypes.c_double * HMC_TUNE_MAX) * 2)]
+                ("tried_us", (ctypes.c_double * HMC_TUNE_MAX) * 2),
+                ("march_rows", ctypes.c_int * 2), ("march_slices", ctypes.c_int * 2),
+                ("mtried", ctypes.c_int * 2),
+                ("mtried_rows", (ctypes.c_int * HMC_TUNE_MARCH_MAX) * 2),
+                ("mtried_slices", (ctypes.c_int * HMC_TUNE_MARCH_MAX) * 2),
+                ("mtried_us", (ctypes.c_double * HMC_TUNE_MARCH_MAX) * 2),
+                ("from_cache", ctypes.c_int)]
 
 
 def tune_dict(r):
@@ -111,6 +120,10 @@ def tune_dict(r):
     out["candidates"] = r.candidates
     out["tried"] = {names[i]: [(r.tried_workgroups[i][j], r.tried_us[i][j]) for j in range(r.tried[i])]
                     for i in range(2)}
+    out["march"] = {names[i]: (r.march_rows[i], r.march_slices[i]) for i in range(2)}
+    out["march_tried"] = {names[i]: [(r.mtried_rows[i][j], r.mtried_slices[i][j], r.mtried_us[i][j])
+                                     for j in range(r.mtried[i])] for i in range(2)}
+    out["from_cache"] = r.from_cache
     return out
 
 
@@ -191,6 +204,8 @@ def load():
         "hmc_set_cg_workgroups": (I, [P, I, I]),
         "hmc_get_cg_workgroups": (I, [P, I]),
         "hmc_set_mdm_shape": (I, [P, I, I, I]),
+        "hmc_set_cg_march": (I, [P, I, I, I]),
+        "hmc_get_cg_march": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "hmc_get_mdm_shape": (I, [P, I, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "hmc_autotune": (I, [P, P, P, I, ctypes.POINTER(HmcTuneResult), P]),
         "hmc_set_graphs": (I, [P, I]),

@@ -30,10 +30,22 @@ FLAGS = [
 ]
 
 
+def source_hash():
+    """First 16 hex digits of the SHA-256 of every source and header the library is built from
+    (keys the autotuner's on-disk cache to the kernels it timed)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in DEPS:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build_library(verbose=False):
     """Compile every HIP source into paper_2204_14241_amd/libhmc.so (always rebuilds)."""
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *SOURCES, "-o", tmp]
+    cmd = [HIPCC, *FLAGS, f'-DHMC_SOURCE_HASH="{source_hash()}"', *SOURCES, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -13,13 +13,18 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <initializer_list>
 #include <map>
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
+
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include "../../include/hmc.h"
 #include "../../include/hmc_testing.h"
@@ -201,6 +206,10 @@ struct hmc_ctx {
     // default for the lattice
     int mdm_rows[2] = {0, 0};
     int mdm_seg[2] = {0, 0};
+    // CG step A as a march (march.h) [FP64, FP32]: rows per band (0: the tile kernels) and slices
+    // per segment (0: the default)
+    int cgm_rows[2] = {0, 0};
+    int cgm_seg[2] = {0, 0};
 
     // device address of the static scratch on this context's GPU (null if it could not be
     // resolved; only hmc_apply_MdagM_noalloc uses it)
@@ -216,6 +225,35 @@ struct hmc_ctx {
 struct hmc_batch {
     hmc_ctx c;
 };
+
+static std::string device_tag(int dev);
+
+// Cache key of a context: one lattice "one L Lt n", a batch "batch <hash of the chain list>",
+// then the device and the kernel-source hash.
+static std::string tune_key(const hmc_ctx* c) {
+    std::string k;
+    if (c->is_batch) {
+        uint64_t h = 1469598103934665603ULL;   // FNV-1a over the chain geometry
+        auto mix = [&](long long v) {
+            for (int i = 0; i < 8; ++i) {
+                h ^= uint64_t((v >> (8 * i)) & 0xff);
+                h *= 1099511628211ULL;
+            }
+        };
+        mix(c->bi.nchains);
+        mix(c->bi.nrhs);
+        for (const Lat& l : c->bi.lats) {
+            mix(l.L);
+            mix(l.Lt);
+        }
+        char buf[64];
+        std::snprintf(buf, sizeof(buf), "batch %016llx", (unsigned long long)h);
+        k = buf;
+    } else {
+        k = "one " + std::to_string(c->L) + " " + std::to_string(c->Lt) + " " + std::to_string(c->cap);
+    }
+    return k + " " + device_tag(c->device) + " " + HMC_SOURCE_HASH;
+}
 
 // --------------------------------------------------------------------------------------
 // helpers
@@ -469,7 +507,13 @@ static int set_cg_shape(hmc_ctx* c, int precision, int max_bpr) {
     return HMC_OK;
 }
 
-// Process-wide memory of autotuned shapes, keyed by lattice, right-hand sides and device.
+// Autotuned launch shapes: CG workgroups per right-hand side and the step-A march, per
+// precision.  Kept process-wide per (lattice, right-hand sides, device) and on disk.
+struct TuneChoice {
+    int bpr[2] = {0, 0};    // [FP64, FP32]
+    int mrows[2] = {0, 0};
+    int mseg[2] = {0, 0};
+};
 struct TuneKey {
     int L, Lt, n, dev;
     bool operator<(const TuneKey& o) const {
@@ -477,7 +521,85 @@ struct TuneKey {
     }
 };
 static std::mutex g_tune_mu;
-static std::map<TuneKey, std::pair<int, int>> g_tuned;   // -> (bpr64, bpr32)
+static std::map<TuneKey, TuneChoice> g_tuned;
+
+#ifndef HMC_SOURCE_HASH
+#define HMC_SOURCE_HASH "unknown"
+#endif
+
+// The on-disk cache: one line per key, "<key> bpr64 bpr32 rows64 slices64 rows32 slices32".
+static std::string tune_cache_path() {
+    const char* e = std::getenv("HMC_TUNE_CACHE");
+    if (e != nullptr) return (*e == 0 || std::strcmp(e, "off") == 0) ? std::string() : std::string(e);
+    const char* x = std::getenv("XDG_CACHE_HOME");
+    if (x != nullptr && *x) return std::string(x) + "/hmc/tune.txt";
+    const char* h = std::getenv("HOME");
+    if (h != nullptr && *h) return std::string(h) + "/.cache/hmc/tune.txt";
+    return std::string();
+}
+
+// Device identity in a cache key: architecture and compute-unit count.
+static std::string device_tag(int dev) {
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, dev) != hipSuccess) return "unknown";
+    std::string t = std::string(pr.gcnArchName) + "/" + std::to_string(pr.multiProcessorCount);
+    for (char& ch : t)
+        if (ch == ' ' || ch == '\t') ch = '_';
+    return t;
+}
+
+static bool tune_cache_lookup(const std::string& key, TuneChoice& out) {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return false;
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (f == nullptr) return false;
+    char line[1024];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        const size_t kl = key.size();
+        if (std::strncmp(line, key.c_str(), kl) != 0 || line[kl] != ' ') continue;
+        TuneChoice c;
+        if (std::sscanf(line + kl, "%d %d %d %d %d %d", &c.bpr[0], &c.bpr[1], &c.mrows[0], &c.mseg[0], &c.mrows[1],
+                        &c.mseg[1]) == 6 &&
+            c.bpr[0] >= 1 && c.bpr[1] >= 1) {
+            out = c;
+            found = true;   // the last matching line wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void make_parent_dirs(const std::string& path) {
+    for (size_t i = 1; i < path.size(); ++i)
+        if (path[i] == '/') (void)mkdir(path.substr(0, i).c_str(), 0755);
+}
+
+// Replace (or add) the key's line; written to a temporary file and renamed into place.
+static void tune_cache_store(const std::string& key, const TuneChoice& c) {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    make_parent_dirs(path);
+    std::vector<std::string> keep;
+    if (FILE* f = std::fopen(path.c_str(), "r")) {
+        char line[1024];
+        while (std::fgets(line, sizeof(line), f)) {
+            const size_t kl = key.size();
+            if (std::strncmp(line, key.c_str(), kl) == 0 && line[kl] == ' ') continue;
+            keep.emplace_back(line);
+        }
+        std::fclose(f);
+    }
+    const std::string tmp = path + ".tmp" + std::to_string(long(getpid()));
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (f == nullptr) return;
+    for (const std::string& l : keep) std::fputs(l.c_str(), f);
+    std::fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), c.bpr[0], c.bpr[1], c.mrows[0], c.mseg[0], c.mrows[1],
+                 c.mseg[1]);
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) (void)std::remove(tmp.c_str());
+}
+
 
 // --------------------------------------------------------------------------------------
 // geometry of a launch
@@ -500,6 +622,11 @@ struct Launch {
     bool nn2 = false;     // the operator hops by two sites (the instantiations with those terms)
     bool pc = false;
     bool r7 = false;      // some lattice extent has a factor 7 (radix-7 FFT stages)
+    // CG step A as a march (one lattice, nearest-neighbour operator): plan, threads, LDS and
+    // workgroups per unit (0: the tile kernels k_cg_a / k_cg_a2)
+    MarchPlan cgm{};
+    int cgm_threads = 0, cgm_per_unit = 0;
+    size_t cgm_lds = 0;
 };
 
 template <typename R>
@@ -521,6 +648,24 @@ static Launch<GeoOne> launch_one(const hmc_ctx* c, int n) {
     l.pt_full = c->pc_full[pi];
     l.nn2 = c->cf64.nn2 != 0;
     l.r7 = c->pc_r7;
+    // step A as a march: rows per band so that the band and its two neighbour rows have one
+    // thread each (at most kMarchCgThreads); slices per segment for about one workgroup per
+    // compute unit over all right-hand sides (at least 2)
+    if (c->cgm_rows[pi] > 0 && !l.nn2) {
+        const int per_row = pi ? c->L / 2 : c->L;
+        const int rows = std::max(1, std::min(c->cgm_rows[pi], kMarchCgThreads / per_row - 2));
+        const size_t lds = march_cg_lds<R>(rows, c->L);
+        if (rows >= 1 && (rows + 2) * per_row <= kMarchCgThreads && lds <= (size_t(64) << 10)) {
+            const int nband = (c->L + std::min(rows, c->L) - 1) / std::min(rows, c->L);
+            int seg = c->cgm_seg[pi];
+            if (seg <= 0) seg = std::max(2, (c->Lt * nband * n + 255) / 256);
+            l.cgm = make_march_plan(c->L, c->Lt, rows, seg);
+            l.cgm_per_unit = l.cgm.nband * l.cgm.nseg;
+            if (l.cgm_per_unit > c->pstride) l.cgm_per_unit = 0;   // partial slots: keep the tile kernels
+            l.cgm_threads = ((std::min(rows, c->L) + 2) * per_row + 63) / 64 * 64;
+            l.cgm_lds = lds;
+        }
+    }
     return l;
 }
 
@@ -573,6 +718,7 @@ static CgCtl next_ctl(hmc_ctx* c, int expect) {
     k.part = c->part;
     k.nslots = c->pslots;
     k.expect = expect;
+    k.nparts = 0;
     c->seq += 1;
     return k;
 }
@@ -650,7 +796,41 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
     const int grid = lc.ncg;
     for (int i = 0; i < chunk; ++i) {
         const int expect_a = lc.pc ? PEND_NONE : (i > 0 ? PEND_RR : (first ? PEND_BB : PEND_NONE));
-        const CgCtl ka = next_ctl(c, expect_a), kb = next_ctl(c, PEND_TT);
+        const CgCtl ka = next_ctl(c, expect_a);
+        CgCtl kb = next_ctl(c, PEND_TT);
+        if constexpr (std::is_same<Geo, GeoOne>::value) {
+            if (lc.cgm_per_unit > 0) {
+                // step A as a march; step B then reduces the march's partials
+                kb.nparts = lc.cgm_per_unit;
+                const hipEvent_t* e = (sample && i == chunk / 2) ? c->tev[kslot] : nullptr;
+                const int g = lc.cgm_per_unit * n;
+                if constexpr (sizeof(R) == sizeof(float)) {
+                    if (e) hipExtLaunchKernelGGL(k_cg_a2_march, dim3(g), dim3(lc.cgm_threads), lc.cgm_lds, s, e[0], e[1], 0,
+                                                 ka, geo.lat, lc.cgm, geo.bpr, c->pstride, v, phik, cf);
+                    else hipLaunchKernelGGL(k_cg_a2_march, dim3(g), dim3(lc.cgm_threads), lc.cgm_lds, s, ka, geo.lat,
+                                            lc.cgm, geo.bpr, c->pstride, v, phik, cf);
+                    LAUNCHCHK();
+                    if (e) hipExtLaunchKernelGGL((k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0, s, e[2], e[3], 0, kb,
+                                                 geo, v, phik, cf);
+                    else hipLaunchKernelGGL((k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
+                } else {
+                    if (e) hipExtLaunchKernelGGL(k_cg_a_march, dim3(g), dim3(lc.cgm_threads), lc.cgm_lds, s, e[0], e[1], 0,
+                                                 ka, geo.lat, lc.cgm, geo.bpr, c->pstride, v, phik, cf);
+                    else hipLaunchKernelGGL(k_cg_a_march, dim3(g), dim3(lc.cgm_threads), lc.cgm_lds, s, ka, geo.lat,
+                                            lc.cgm, geo.bpr, c->pstride, v, phik, cf);
+                    LAUNCHCHK();
+                    if (e) hipExtLaunchKernelGGL((k_cg_b<R, Geo, false>), dim3(grid), dim3(kBlock), 0, s, e[2], e[3], 0,
+                                                 kb, geo, v, phik, cf);
+                    else hipLaunchKernelGGL((k_cg_b<R, Geo, false>), dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
+                }
+                LAUNCHCHK();
+                if (lc.pc) {
+                    int rc = enqueue_pc<R, Geo>(c, lc, v, PEND_RR, s, e ? c->tev[kslot] + 4 : nullptr);
+                    if (rc) return rc;
+                }
+                continue;
+            }
+        }
         if (sample && i == chunk / 2) {
             // timestamps from the dispatches themselves (not captured into graphs)
             hipEvent_t* e = c->tev[kslot];
@@ -1324,6 +1504,29 @@ static int set_workspace_common(hmc_ctx* c, void* ptr, size_t bytes) {
     return HMC_OK;
 }
 
+// Launch shapes of a tuning choice (clamped as the setters clamp them).
+static void apply_choice(hmc_ctx* c, const TuneChoice& ch) {
+    c->bpr64 = c->is_batch ? ch.bpr[0] : clamp_bpr(c->nblk2, ch.bpr[0]);
+    c->bpr32 = c->is_batch ? ch.bpr[1] : clamp_bpr(c->nblk2, ch.bpr[1]);
+    if (!c->is_batch)
+        for (int pi = 0; pi < 2; ++pi) {
+            c->cgm_rows[pi] = ch.mrows[pi];
+            c->cgm_seg[pi] = ch.mseg[pi];
+        }
+    c->generation += 1;
+}
+
+static TuneChoice current_choice(const hmc_ctx* c) {
+    TuneChoice ch;
+    ch.bpr[0] = c->bpr64;
+    ch.bpr[1] = c->bpr32;
+    for (int pi = 0; pi < 2; ++pi) {
+        ch.mrows[pi] = c->cgm_rows[pi];
+        ch.mseg[pi] = c->cgm_seg[pi];
+    }
+    return ch;
+}
+
 // Autotuner core: time `iters` CG iterations per candidate shape and keep the fastest.
 static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int n, hmc_tune_result* out,
                            hipStream_t s) {
@@ -1346,6 +1549,9 @@ static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int 
         if (prec == HMC_MIXED && c->p.reliable_every < 1) c->p.reliable_every = 50;
         double best = 1e300;
         int best_bpr = 0, last = -1;
+        // the workgroup count is tuned on the tile kernels, then the march shapes with it
+        c->cgm_rows[pi] = 0;
+        c->generation += 1;
         for (int cb : cand) {
             const int bpr = clamp_bpr(maxt, cb);
             if (bpr == last) continue;
@@ -1374,6 +1580,51 @@ static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int 
             out->cg_workgroups[pi] = best_bpr;
             out->us_per_iter[pi] = best;
         }
+        // step A as a march (one lattice, nearest neighbours): rows per band x slices per segment
+        if (result == HMC_OK && !c->is_batch && !c->cf64.nn2) {
+            static const int rows32[] = {4, 6, 8, 10}, rows64[] = {2, 3, 4};
+            static const int segs32[] = {4, 6, 8}, segs64[] = {4, 6, 8, 12};
+            const int per_row = pi ? c->L / 2 : c->L;
+            int best_r = 0, best_s = 0;
+            const int* rows = pi ? rows32 : rows64;
+            const int* segs = pi ? segs32 : segs64;
+            const int nr = pi ? 4 : 3, ns = pi ? 3 : 4;
+            for (int a = 0; a < nr && result == HMC_OK; ++a) {
+                if ((rows[a] + 2) * per_row > kMarchCgThreads || rows[a] > c->L) continue;
+                for (int q = 0; q < ns && result == HMC_OK; ++q) {
+                    if (out->mtried[pi] >= HMC_TUNE_MARCH_MAX) break;
+                    c->cgm_rows[pi] = rows[a];
+                    c->cgm_seg[pi] = segs[q];
+                    c->generation += 1;
+                    float ms = 0.f;
+                    for (int rep = 0; rep < 2; ++rep) {
+                        if (hipEventRecord(e0, s) != hipSuccess) { result = HMC_ERR_HIP; break; }
+                        const int r = cg_dispatch(c, phi, b, c->xsol, n, nullptr, s);
+                        if (r != HMC_OK && r != HMC_ERR_NOT_CONVERGED) { result = r; break; }
+                        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { result = HMC_ERR_HIP; break; }
+                    }
+                    if (result != HMC_OK) break;
+                    out->candidates += 1;
+                    const double us = 1e3 * ms / iters;
+                    const int j = out->mtried[pi]++;
+                    out->mtried_rows[pi][j] = rows[a];
+                    out->mtried_slices[pi][j] = segs[q];
+                    out->mtried_us[pi][j] = us;
+                    if (us < best) {
+                        best = us;
+                        best_r = rows[a];
+                        best_s = segs[q];
+                    }
+                }
+            }
+            c->cgm_rows[pi] = best_r;
+            c->cgm_seg[pi] = best_s;
+            c->generation += 1;
+            out->march_rows[pi] = best_r;
+            out->march_slices[pi] = best_s;
+            out->us_per_iter[pi] = best;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1381,9 +1632,30 @@ static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int 
     if (result != HMC_OK) {
         (void)set_cg_shape(c, HMC_FP64, kDefaultBpr64);
         (void)set_cg_shape(c, HMC_MIXED, kDefaultBpr32);
+        if (!c->is_batch) {
+            c->cgm_rows[0] = 4;
+            c->cgm_rows[1] = 8;
+            c->cgm_seg[0] = c->cgm_seg[1] = 8;
+        }
         return result == HMC_ERR_HIP ? fail(result, "autotune: HIP call failed") : result;
     }
     return HMC_OK;
+}
+
+// A cached choice as the tuner's result (nothing timed).
+static void choice_result(const TuneChoice& ch, hmc_tune_result* out) {
+    std::memset(out, 0, sizeof(*out));
+    for (int pi = 0; pi < 2; ++pi) {
+        out->cg_workgroups[pi] = ch.bpr[pi];
+        out->march_rows[pi] = ch.mrows[pi];
+        out->march_slices[pi] = ch.mseg[pi];
+    }
+    out->from_cache = 1;
+}
+
+static bool reuse_cached() {
+    const char* e = std::getenv("HMC_TUNE_REUSE");
+    return e != nullptr && std::strcmp(e, "1") == 0;
 }
 
 static int check_solve_args(hmc_ctx* c, const void* phi, const void* b, const void* x, int n) {
@@ -1767,13 +2039,18 @@ int hmc_create(int L, int Lt, double dtau, const hmc_params* params, hmc_ctx** o
     }
     (void)set_cg_shape(c, HMC_FP64, kDefaultBpr64);
     (void)set_cg_shape(c, HMC_MIXED, kDefaultBpr32);
+    // step A marches by default (the tile kernels where a lattice's band does not fit)
+    c->cgm_rows[0] = 4;
+    c->cgm_rows[1] = 8;
+    c->cgm_seg[0] = c->cgm_seg[1] = 8;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(TuneKey{L, Lt, c->cap, c->device});
-        if (it != g_tuned.end()) {
-            c->bpr64 = it->second.first;
-            c->bpr32 = it->second.second;
-        }
+        TuneChoice ch;
+        bool have = it != g_tuned.end();
+        if (have) ch = it->second;
+        else have = tune_cache_lookup(tune_key(c), ch);
+        if (have) apply_choice(c, ch);
     }
     c->need = ws_layout(c, nullptr);
     *out = c;
@@ -1933,6 +2210,31 @@ int hmc_set_mdm_shape(hmc_ctx* c, int precision, int rows, int slices) {
     return HMC_OK;
 }
 
+int hmc_set_cg_march(hmc_ctx* c, int precision, int rows, int slices) {
+    if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
+    if (c->is_batch) return fail(HMC_ERR_INVALID_ARG, "one-lattice contexts only");
+    if (precision != HMC_FP64 && precision != HMC_MIXED && precision != -1)
+        return fail(HMC_ERR_INVALID_ARG, "unknown precision");
+    if (rows < 0 || rows > 256 || slices < 0 || slices > 1 << 20)
+        return fail(HMC_ERR_INVALID_ARG, "rows must lie in [0, 256] and slices be >= 0");
+    for (int pi = 0; pi < 2; ++pi)
+        if (precision == -1 || precision == (pi ? HMC_MIXED : HMC_FP64)) {
+            c->cgm_rows[pi] = rows;
+            c->cgm_seg[pi] = slices;
+        }
+    c->generation += 1;   // captured graphs hold the launch shape
+    return HMC_OK;
+}
+
+int hmc_get_cg_march(const hmc_ctx* c, int precision, int* rows, int* slices) {
+    if (c == nullptr || rows == nullptr || slices == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    if (precision != HMC_FP64 && precision != HMC_MIXED) return fail(HMC_ERR_INVALID_ARG, "unknown precision");
+    const int pi = precision == HMC_MIXED ? 1 : 0;
+    *rows = c->cgm_rows[pi];
+    *slices = c->cgm_seg[pi];
+    return HMC_OK;
+}
+
 int hmc_get_mdm_shape(const hmc_ctx* c, int precision, int n, int* rows, int* slices, int* workgroups) {
     if (c == nullptr || rows == nullptr || slices == nullptr || workgroups == nullptr)
         return fail(HMC_ERR_INVALID_ARG, "NULL argument");
@@ -1955,10 +2257,22 @@ int hmc_autotune(hmc_ctx* c, const double* phi, const void* b, int n, hmc_tune_r
     int rc = check_solve_args(c, phi, b, c ? c->xsol : nullptr, n);
     if (rc) return rc;
     if (out == nullptr) return fail(HMC_ERR_INVALID_ARG, "out is NULL");
+    if (reuse_cached()) {
+        TuneChoice ch;
+        if (tune_cache_lookup(tune_key(c), ch)) {
+            apply_choice(c, ch);
+            choice_result(ch, out);
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tuned[TuneKey{c->L, c->Lt, c->cap, c->device}] = ch;
+            return HMC_OK;
+        }
+    }
     rc = autotune_common(c, phi, static_cast<const double2*>(b), n, out, (hipStream_t)stream);
     if (rc) return rc;
+    const TuneChoice ch = current_choice(c);
+    tune_cache_store(tune_key(c), ch);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[TuneKey{c->L, c->Lt, c->cap, c->device}] = {c->bpr64, c->bpr32};
+    g_tuned[TuneKey{c->L, c->Lt, c->cap, c->device}] = ch;
     return HMC_OK;
 }
 
@@ -2413,6 +2727,13 @@ int hmc_batch_create(int nchains, const int* L, const int* L_tau, const double* 
     }
     c->bpr64 = kDefaultBpr64;
     c->bpr32 = kDefaultBpr32;
+    {
+        TuneChoice ch;
+        if (tune_cache_lookup(tune_key(c), ch)) {
+            c->bpr64 = ch.bpr[0];
+            c->bpr32 = ch.bpr[1];
+        }
+    }
     (void)upload_batch_shape(c, 0, c->bpr64);    // counts only until the workspace is set
     (void)upload_batch_shape(c, 1, c->bpr32);
     c->need = ws_layout(c, nullptr);
@@ -2509,7 +2830,21 @@ int hmc_batch_autotune(hmc_batch* hb, const double* phi, const void* b, hmc_tune
     int rc = check_batch(hb, {phi, b});
     if (rc) return rc;
     if (out == nullptr) return fail(HMC_ERR_INVALID_ARG, "out is NULL");
-    return autotune_common(&hb->c, phi, static_cast<const double2*>(b), hb->c.nunits, out, (hipStream_t)stream);
+    hmc_ctx* c = &hb->c;
+    if (reuse_cached()) {
+        TuneChoice ch;
+        if (tune_cache_lookup(tune_key(c), ch)) {
+            rc = set_cg_shape(c, HMC_FP64, ch.bpr[0]);
+            if (rc == HMC_OK) rc = set_cg_shape(c, HMC_MIXED, ch.bpr[1]);
+            if (rc) return rc;
+            choice_result(ch, out);
+            return HMC_OK;
+        }
+    }
+    rc = autotune_common(c, phi, static_cast<const double2*>(b), c->nunits, out, (hipStream_t)stream);
+    if (rc) return rc;
+    tune_cache_store(tune_key(c), current_choice(c));
+    return HMC_OK;
 }
 
 int hmc_batch_trajectory(hmc_batch* hb, double* phi, const double* pi0, const void* eta,

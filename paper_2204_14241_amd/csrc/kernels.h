@@ -224,6 +224,8 @@ struct CgCtl {
     double* part;       // partial sums [kPendKinds][nslots]
     int nslots;         // partial slots per kind
     int expect;         // the only partial kind that can be pending at this launch
+    int nparts;         // > 0: partials the previous kernel left per unit (when its workgroup
+                        // count differs from the caller's default)
 };
 
 __device__ __forceinline__ double* part_slot(const CgCtl& c, int kind, const UPos& p) {
@@ -254,7 +256,7 @@ __device__ __forceinline__ int cg_finalize(const CgCtl& c, const UPos& pos, int 
     unsigned w = 0u;
     if (t < kStateWords) w = reinterpret_cast<const unsigned*>(c.st_in + k)[t];
     double tot = 0.0;
-    if (c.expect != PEND_NONE) tot = sum_partials(part_slot(c, c.expect, pos), nparts);
+    if (c.expect != PEND_NONE) tot = sum_partials(part_slot(c, c.expect, pos), c.nparts > 0 ? c.nparts : nparts);
     if (t < kStateWords) reinterpret_cast<unsigned*>(&sh)[t] = w;
     __syncthreads();
     if (t == 0) {

@@ -72,15 +72,16 @@ __host__ __device__ inline size_t march_lds(int Rrows, int L) {
     return size_t(Rrows + 2) * 4 * size_t(L) * sizeof(C2<R>);
 }
 
-// M^dagger at the pair (x, y) of slice tau (flat index s) from chi(tau) in LDS (row r of the
-// band buffer, [row][component][y]) and chi(tau - 1) in registers (tt), with the time link's
-// sign ts: the stencil arithmetic of the two-pass kernels in their order.  cen receives
-// chi(tau) at the pair.
-__device__ __forceinline__ void mdag_pair_lds(const float2* __restrict__ chi, int r, int x, int y, int s,
-                                              const Lat& lat, const float* __restrict__ phi,
-                                              const Coef<float>& cf, float ts, const float4 (&tt)[4],
-                                              float4 (&o)[4], float4 (&cen)[4]) {
-    const int L = lat.L, vol = lat.vol, rowc = 4 * L;
+// A_tau v + ts tt at the pair (x, y), y even: the time-local part of M (diagonal, hopping,
+// Yukawa coupling) from v(tau) in LDS (row r of a band buffer, [row][component][y]), plus the
+// time link ts tt, with phi(tau) at the pair given as (P1, P2, P3), each holding a component at
+// the two sites.  The arithmetic of the two-pass pair stencil (dslash_pair) in its order, so
+// both M (tt = v(tau + 1), ts = s_tau) and M^dagger (tt = v(tau - 1), ts = s_{tau-1}) come out
+// as the separate passes compute them.  cen receives v(tau) at the pair.
+__device__ __forceinline__ void stencil_pair_lds(const float2* __restrict__ chi, int r, int x, int y, int L,
+                                                 float2 P1, float2 P2, float2 P3, const Coef<float>& cf, float ts,
+                                                 const float4 (&tt)[4], float4 (&o)[4], float4 (&cen)[4]) {
+    const int rowc = 4 * L;
     auto lds4 = [&](int rr, int c, int yy) { return *reinterpret_cast<const float4*>(chi + rr * rowc + c * L + yy); };
     const int yl = y == 0 ? L - 1 : y - 1, yr = y + 2 == L ? 0 : y + 2;
 #pragma unroll
@@ -100,9 +101,6 @@ __device__ __forceinline__ void mdag_pair_lds(const float2* __restrict__ chi, in
         o[c] = v;
     }
     const float g0 = cf.cpl * float((x & 1) ? -1 : 1), g1 = -g0;   // (-1)^(x+y), y even
-    const float2 P1 = *reinterpret_cast<const float2*>(phi + s);
-    const float2 P2 = *reinterpret_cast<const float2*>(phi + vol + s);
-    const float2 P3 = *reinterpret_cast<const float2*>(phi + 2 * vol + s);
     const float q1a = g0 * P1.x, q2a = g0 * P2.x, q3a = g0 * P3.x;
     const float q1b = g1 * P1.y, q2b = g1 * P2.y, q3b = g1 * P3.y;
 #pragma unroll
@@ -117,6 +115,19 @@ __device__ __forceinline__ void mdag_pair_lds(const float2* __restrict__ chi, in
         o[2 * a + 1].z += q1b * u.z - q2b * u.w - q3b * w.z;
         o[2 * a + 1].w += q1b * u.w + q2b * u.z - q3b * w.w;
     }
+}
+
+// M^dagger at the pair (x, y) of slice tau (flat index s) from chi(tau) in LDS and chi(tau - 1)
+// in registers (tt), with the time link's sign ts.
+__device__ __forceinline__ void mdag_pair_lds(const float2* __restrict__ chi, int r, int x, int y, int s,
+                                              const Lat& lat, const float* __restrict__ phi,
+                                              const Coef<float>& cf, float ts, const float4 (&tt)[4],
+                                              float4 (&o)[4], float4 (&cen)[4]) {
+    const int vol = lat.vol;
+    const float2 P1 = *reinterpret_cast<const float2*>(phi + s);
+    const float2 P2 = *reinterpret_cast<const float2*>(phi + vol + s);
+    const float2 P3 = *reinterpret_cast<const float2*>(phi + 2 * vol + s);
+    stencil_pair_lds(chi, r, x, y, lat.L, P1, P2, P3, cf, ts, tt, o, cen);
 }
 
 // FP32: an element is a pair of neighbouring sites (y even), as in the pair kernels.
@@ -183,12 +194,13 @@ __global__ __launch_bounds__(kMarchMaxThreads) void k_mdm2(Lat lat, MarchPlan mp
     }
 }
 
-// FP64 form of mdag_pair_lds at the site (x, y).
-__device__ __forceinline__ void mdag_site_lds(const double2* __restrict__ chi, int r, int x, int y, int s,
-                                              const Lat& lat, const double* __restrict__ phi,
-                                              const Coef<double>& cf, double ts, const double2 (&tt)[4],
-                                              double2 (&o)[4], double2 (&cen)[4]) {
-    const int L = lat.L, vol = lat.vol, rowc = 4 * L;
+// FP64 form of stencil_pair_lds at the site (x, y), phi(tau) there given as (q1, q2, q3) before
+// the coupling and the staggered sign are applied.
+__device__ __forceinline__ void stencil_site_lds(const double2* __restrict__ chi, int r, int x, int y, int L,
+                                                 double f1, double f2, double f3, const Coef<double>& cf,
+                                                 double ts, const double2 (&tt)[4], double2 (&o)[4],
+                                                 double2 (&cen)[4]) {
+    const int rowc = 4 * L;
     const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
 #pragma unroll
     for (int c = 0; c < 4; ++c) cen[c] = chi[r * rowc + c * L + y];
@@ -204,7 +216,7 @@ __device__ __forceinline__ void mdag_site_lds(const double2* __restrict__ chi, i
         o[c] = v;
     }
     const double g = cf.cpl * double(((x + y) & 1) ? -1 : 1);
-    const double q1 = g * phi[s], q2 = g * phi[vol + s], q3 = g * phi[2 * vol + s];
+    const double q1 = g * f1, q2 = g * f2, q3 = g * f3;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         const double2 u = cen[2 * (1 - a)], w = cen[2 * (1 - a) + 1];
@@ -213,6 +225,14 @@ __device__ __forceinline__ void mdag_site_lds(const double2* __restrict__ chi, i
         o[2 * a + 1].x += q1 * u.x - q2 * u.y - q3 * w.x;
         o[2 * a + 1].y += q1 * u.y + q2 * u.x - q3 * w.y;
     }
+}
+
+__device__ __forceinline__ void mdag_site_lds(const double2* __restrict__ chi, int r, int x, int y, int s,
+                                              const Lat& lat, const double* __restrict__ phi,
+                                              const Coef<double>& cf, double ts, const double2 (&tt)[4],
+                                              double2 (&o)[4], double2 (&cen)[4]) {
+    const int vol = lat.vol;
+    stencil_site_lds(chi, r, x, y, lat.L, phi[s], phi[vol + s], phi[2 * vol + s], cf, ts, tt, o, cen);
 }
 
 // FP64: an element is one site.
@@ -371,6 +391,268 @@ __global__ __launch_bounds__(kMarchMaxThreads) void k_mdm_tile(Lat lat, MarchPla
 #pragma unroll
         for (int c = 0; c < 4; ++c) out[voff + size_t(c) * vol + s] = o[c];
     }
+}
+
+// ------------------------------------------------------------------------------------
+// CG step A as a march (one lattice, nearest-neighbour operator): the algebra of k_cg_a /
+// k_cg_a2 (x += alpha p_old; p_new = z + beta p_old; t = M p_new; partial |t|^2), with the
+// reuse along tau held on chip.  A workgroup owns a band of rows of one right-hand side and a
+// segment of slices; one thread per element of the band and of the row on either side.  At
+// each slice tau it forms p_new(tau + 1) on those rows from the z and p_old it loaded during
+// the previous slice (so every value of z, p_old and x leaves HBM once, and the loads of the
+// next slice are in flight while the current one is computed), writes p_new and x for its own
+// rows, and forms t(tau) = A_tau p_new(tau) + s_tau p_new(tau + 1) from p_new(tau) in LDS
+// (the spatial neighbours) and p_new(tau + 1) in registers (the time link).  The slice after a
+// segment is formed again, not stored, by the segment before it.  Partials: one per workgroup
+// (the consumer is told the count through CgCtl::nparts).
+template <typename R>
+__host__ __device__ inline size_t march_cg_lds(int Rrows, int L) {
+    return 2 * size_t(Rrows + 2) * 4 * size_t(L) * sizeof(C2<R>);
+}
+
+// Most threads of a CG march workgroup (the band's elements and the two rows beside it).
+constexpr int kMarchCgThreads = 512;
+
+// The unit record of a march workgroup.
+__device__ __forceinline__ UPos march_unit(const Lat& lat, int k, int blk, int nparts_in, int pstride) {
+    UPos p;
+    p.lat = lat;
+    p.voff = size_t(k) * 4 * lat.vol;
+    p.phioff = 0;
+    p.k = k;
+    p.blk = blk;
+    p.bpr = nparts_in;
+    p.part = k * pstride;
+    p.pcoff = 0;
+    return p;
+}
+
+__global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, Lat lat, MarchPlan mp, int nparts_in,
+                                                                 int pstride, CgVecs<float> v,
+                                                                 const float* __restrict__ phi, Coef<float> cf) {
+    extern __shared__ __align__(16) unsigned char march_smem[];
+    const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, P = L / 2, rowc = 4 * L;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x), per_vec = mp.nseg * mp.nband;
+    const MarchPos mpos = march_pos(lat, mp, wg);
+    const UPos pos = march_unit(lat, mpos.k, wg - mpos.k * per_vec, nparts_in, pstride);
+    cg_finalize(ctl, pos, nparts_in);
+    const CgState& S = cg_shared();
+    if (S.mode != CG_ACTIVE) {
+        cg_publish(ctl, pos);
+        return;
+    }
+    const float alpha = float(S.alpha), beta = float(S.beta);
+    const int pb = S.pbuf;
+    const size_t off = pos.voff;
+    const float2* pin = (pb ? v.p1 : v.p0) + off;
+    float2* pout = (pb ? v.p0 : v.p1) + off;
+    float2* x = v.x + off;
+    float2* t = v.t + off;
+    const float2* z = v.z + off;
+    float2* cur = reinterpret_cast<float2*>(march_smem);
+    float2* nxt = cur + size_t(mp.R + 2) * rowc;
+    // this thread's element: row lr of the band buffer (0 and nr + 1 are the rows beside the band)
+    const int e = threadIdx.x, nh = (mpos.nr + 2) * P;
+    const bool act = e < nh;
+    const int lr = act ? e / P : 0, py = act ? e - lr * P : 0, y = 2 * py;
+    const int xrow = wrap_row(mpos.x0 - 1 + lr, L);
+    const bool inner = act && lr >= 1 && lr <= mpos.nr;
+    const int ro = xrow * L + y;                      // offset of the element within a slice
+    float4 rz[4], rp[4], rx[4];
+    float2 f1 = make_float2(0.f, 0.f), f2 = f1, f3 = f1;
+    auto load_slab = [&](int tq) {
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const size_t i = size_t(c) * vol + size_t(tq) * LL + ro;
+                rz[c] = ld4(z, i);
+                rp[c] = ld4(pin, i);
+            }
+        }
+        if (inner) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rx[c] = ld4(x, size_t(c) * vol + size_t(tq) * LL + ro);
+        }
+    };
+    auto load_phi = [&](int tq) {
+        if (inner) {
+            const size_t i = size_t(tq) * LL + ro;
+            f1 = *reinterpret_cast<const float2*>(phi + i);
+            f2 = *reinterpret_cast<const float2*>(phi + vol + i);
+            f3 = *reinterpret_cast<const float2*>(phi + 2 * vol + i);
+        }
+    };
+    // p_new at slice tq from the loaded z, p_old (into buf, and stored with the x update when own)
+    auto form = [&](int tq, float2* buf, bool own, float4 (&pn)[4]) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pn[c] = f4axpy(beta, rp[c], rz[c]);
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) *reinterpret_cast<float4*>(buf + lr * rowc + c * L + y) = pn[c];
+        }
+        if (inner && own) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const size_t i = size_t(c) * vol + size_t(tq) * LL + ro;
+                st4(pout, i, pn[c]);
+                st4(x, i, f4axpy(alpha, rp[c], rx[c]));
+            }
+        }
+    };
+    const int t0 = mpos.t0, t1 = mpos.t1;
+    float4 pn[4];
+    load_slab(t0);
+    form(t0, cur, true, pn);
+    load_slab(t0 + 1 == Lt ? 0 : t0 + 1);
+    load_phi(t0);
+    double part = 0.0;
+    for (int tau = t0; tau < t1; ++tau) {
+        const int tn = tau + 1 == Lt ? 0 : tau + 1;
+        const bool own_next = tau + 1 < t1;
+        float4 pnx[4];
+        form(tn, nxt, own_next, pnx);
+        const float2 g1 = f1, g2 = f2, g3 = f3;
+        if (own_next) {
+            load_slab(tn + 1 == Lt ? 0 : tn + 1);
+            load_phi(tn);
+        }
+        __syncthreads();
+        if (inner) {
+            float4 o[4], cen[4];
+            stencil_pair_lds(cur, lr, xrow, y, L, g1, g2, g3, cf, tau == Lt - 1 ? -1.f : 1.f, pnx, o, cen);
+            float acc = 0.f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                st4(t, size_t(c) * vol + size_t(tau) * LL + ro, o[c]);
+                acc += f4norm2(o[c]);
+            }
+            part += double(acc);
+        }
+        __syncthreads();
+        float2* sw = cur;
+        cur = nxt;
+        nxt = sw;
+    }
+    store_partial(ctl, PEND_TT, pos, part);
+    if (threadIdx.x == 0) {
+        CgState& W = cg_shared();
+        W.alpha = 0.0;
+        W.pbuf = 1 - pb;
+        W.pending = PEND_TT;
+    }
+    cg_publish(ctl, pos);
+}
+
+__global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, Lat lat, MarchPlan mp, int nparts_in,
+                                                                int pstride, CgVecs<double> v,
+                                                                const double* __restrict__ phi, Coef<double> cf) {
+    extern __shared__ __align__(16) unsigned char march_smem[];
+    const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, rowc = 4 * L;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x), per_vec = mp.nseg * mp.nband;
+    const MarchPos mpos = march_pos(lat, mp, wg);
+    const UPos pos = march_unit(lat, mpos.k, wg - mpos.k * per_vec, nparts_in, pstride);
+    cg_finalize(ctl, pos, nparts_in);
+    const CgState& S = cg_shared();
+    if (S.mode != CG_ACTIVE) {
+        cg_publish(ctl, pos);
+        return;
+    }
+    const double alpha = S.alpha, beta = S.beta;
+    const int pb = S.pbuf;
+    const size_t off = pos.voff;
+    const double2* pin = (pb ? v.p1 : v.p0) + off;
+    double2* pout = (pb ? v.p0 : v.p1) + off;
+    double2* x = v.x + off;
+    double2* t = v.t + off;
+    const double2* z = v.z + off;
+    double2* cur = reinterpret_cast<double2*>(march_smem);
+    double2* nxt = cur + size_t(mp.R + 2) * rowc;
+    const int e = threadIdx.x, nh = (mpos.nr + 2) * L;
+    const bool act = e < nh;
+    const int lr = act ? e / L : 0, y = act ? e - lr * L : 0;
+    const int xrow = wrap_row(mpos.x0 - 1 + lr, L);
+    const bool inner = act && lr >= 1 && lr <= mpos.nr;
+    const int ro = xrow * L + y;
+    double2 rz[4], rp[4], rx[4];
+    double f1 = 0.0, f2 = 0.0, f3 = 0.0;
+    auto load_slab = [&](int tq) {
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const size_t i = size_t(c) * vol + size_t(tq) * LL + ro;
+                rz[c] = z[i];
+                rp[c] = pin[i];
+            }
+        }
+        if (inner) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rx[c] = x[size_t(c) * vol + size_t(tq) * LL + ro];
+        }
+    };
+    auto load_phi = [&](int tq) {
+        if (inner) {
+            const size_t i = size_t(tq) * LL + ro;
+            f1 = phi[i];
+            f2 = phi[vol + i];
+            f3 = phi[2 * vol + i];
+        }
+    };
+    auto form = [&](int tq, double2* buf, bool own, double2 (&pn)[4]) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pn[c] = axpy<double>(beta, rp[c], rz[c]);
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) buf[lr * rowc + c * L + y] = pn[c];
+        }
+        if (inner && own) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const size_t i = size_t(c) * vol + size_t(tq) * LL + ro;
+                pout[i] = pn[c];
+                x[i] = axpy<double>(alpha, rp[c], rx[c]);
+            }
+        }
+    };
+    const int t0 = mpos.t0, t1 = mpos.t1;
+    double2 pn[4];
+    load_slab(t0);
+    form(t0, cur, true, pn);
+    load_slab(t0 + 1 == Lt ? 0 : t0 + 1);
+    load_phi(t0);
+    double part = 0.0;
+    for (int tau = t0; tau < t1; ++tau) {
+        const int tn = tau + 1 == Lt ? 0 : tau + 1;
+        const bool own_next = tau + 1 < t1;
+        double2 pnx[4];
+        form(tn, nxt, own_next, pnx);
+        const double g1 = f1, g2 = f2, g3 = f3;
+        if (own_next) {
+            load_slab(tn + 1 == Lt ? 0 : tn + 1);
+            load_phi(tn);
+        }
+        __syncthreads();
+        if (inner) {
+            double2 o[4], cen[4];
+            stencil_site_lds(cur, lr, xrow, y, L, g1, g2, g3, cf, tau == Lt - 1 ? -1.0 : 1.0, pnx, o, cen);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                t[size_t(c) * vol + size_t(tau) * LL + ro] = o[c];
+                part += norm2<double>(o[c]);
+            }
+        }
+        __syncthreads();
+        double2* sw = cur;
+        cur = nxt;
+        nxt = sw;
+    }
+    store_partial(ctl, PEND_TT, pos, part);
+    if (threadIdx.x == 0) {
+        CgState& W = cg_shared();
+        W.alpha = 0.0;
+        W.pbuf = 1 - pb;
+        W.pending = PEND_TT;
+    }
+    cg_publish(ctl, pos);
 }
 
 }  // namespace hmc

@@ -140,6 +140,19 @@ class HMC:
         pr = {None: -1, "fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]
         check(self.lib.hmc_set_mdm_shape(self._ctx, pr, int(rows), int(slices)), "hmc_set_mdm_shape")
 
+    def set_cg_march(self, rows=0, slices=0, precision=None):
+        """CG step A as a march of row bands through time slices (hmc_set_cg_march); rows = 0
+        keeps the tile kernels."""
+        pr = {None: -1, "fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]
+        check(self.lib.hmc_set_cg_march(self._ctx, pr, int(rows), int(slices)), "hmc_set_cg_march")
+
+    def cg_march(self, precision="fp64"):
+        """(rows per band, slices per segment) of step A; rows 0: the tile kernels."""
+        r, t = ctypes.c_int(), ctypes.c_int()
+        self._call("hmc_get_cg_march", {"fp64": HMC_FP64, "mixed": HMC_MIXED}[precision], ctypes.byref(r),
+                   ctypes.byref(t))
+        return r.value, t.value
+
     def mdm_shape(self, precision="fp64", n=1):
         """(rows per band, slices per segment, workgroups) of a one-pass M^dagger M of n vectors."""
         r, t, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

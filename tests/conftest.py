@@ -7,6 +7,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# launch shapes come from the library's defaults, not from an autotuner cache left on the machine
+# (the test of the cache names its own file)
+os.environ["HMC_TUNE_CACHE"] = "off"
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")

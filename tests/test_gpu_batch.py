@@ -117,6 +117,7 @@ def test_batch_chain_equals_single_context(hip, precision):
     for i, (L, Lt, r) in enumerate(SMALL):
         h = hip.HMC(L, Lt, n_pf=2, cg_tol=1e-10, precision=precision, model=dict(r=r))
         h.set_cg_workgroups(wg)
+        h.set_cg_march(0)          # the batch's step A (tile kernels)
         x1, st1 = h.cg_solve(dev(phis[i]), dev(bs[i]))
         say(f"  chain {i} {L}x{L}x{Lt}: batch iters {st['iterations'][2 * i:2 * i + 2]} "
             f"single {st1.iterations}")
@@ -181,6 +182,7 @@ def test_batch_trajectory_matches_single_and_oracle(hip, precision):
         h = hip.HMC(L, Lt, n_pf=n_pf, eps=eps, n_leap=n_leap, cg_tol=1e-12, precision=precision,
                     model=dict(r=r))
         h.set_cg_workgroups(8)
+        h.set_cg_march(0)          # the batch's step A (tile kernels)
         p1 = dev(ins[i][0])
         s1 = h.trajectory(p1, dev(ins[i][1]), dev(ins[i][2]), u[i])
         assert s1["dH"] == dH, (i, s1["dH"], dH)
@@ -267,6 +269,7 @@ def test_batch_full_workload(hip):
                 model=dict(r=r))
     h.set_cg_workgroups(wg, "mixed")
     h.set_cg_workgroups(bt.cg_workgroups()["fp64"], "fp64")
+    h.set_cg_march(0)          # the batch's step A (tile kernels)
     p1 = dev(ins[i][0])
     s1 = h.trajectory(p1, dev(ins[i][1]), dev(ins[i][2]), u[i])
     assert s1["dH"] == st["dH_chains"][i]

@@ -108,11 +108,22 @@ def test_autotune_then_solve(hip):
         wg, us = res[prec]
         assert 1 <= wg <= ntiles2 and us > 0
         tried = res["tried"][prec]
-        assert (wg, us) in tried and us == min(t for _, t in tried)
         assert len({w for w, _ in tried}) == len(tried)
+        # the workgroup count is the fastest of the tile-kernel runs; the time reported is the
+        # fastest of everything timed, the march shapes included (rows 0: the tile kernels won)
+        assert wg == min(tried, key=lambda t: t[1])[0]
+        times = [t for _, t in tried] + [t for _, _, t in res["march_tried"][prec]]
+        assert us == min(times)
+        rows, slices = res["march"][prec]
+        if rows:
+            assert (rows, slices, us) in res["march_tried"][prec]
+        else:
+            assert (wg, us) in tried
+        assert h.cg_march(prec) == (rows, slices)
     assert h.cg_workgroups() == {"fp64": res["fp64"][0], "mixed": res["mixed"][0]}
     h2 = hip.HMC(L, Lt, cg_tol=1e-10, precision="mixed")
     assert h2.cg_workgroups() == h.cg_workgroups()
+    assert h2.cg_march("mixed") == h.cg_march("mixed") and h2.cg_march("fp64") == h.cg_march("fp64")
     for hh in (h, h2):
         x, st = hh.cg_solve(torch.from_numpy(phi).cuda(), torch.from_numpy(b).cuda())
         r = b[0] - O.apply_MdagM(m, phi, x.cpu().numpy()[0])

@@ -124,6 +124,7 @@ def test_pcg_batch_matches_oracle_and_single(hip, precision):
             assert resid(m, phis[i], bs[i][k], xs[i][k].cpu().numpy()) <= 1e-10
         h = hip.HMC(L, Lt, n_pf=2, cg_tol=1e-10, precision=precision, precond="fourier", model=dict(r=r))
         h.set_cg_workgroups(8)
+        h.set_cg_march(0)          # the batch's step A (tile kernels)
         x1, st1 = h.cg_solve(dev(phis[i]), dev(bs[i]))
         assert st1.iterations == st["iterations"][2 * i:2 * i + 2]
         assert torch.equal(x1.reshape(xs[i].shape), xs[i])
@@ -154,6 +155,7 @@ def test_pcg_batch_full_chunks(hip, precision, Lt):
         assert resid(m, phis[i], bs[i][0], xs[i][0].cpu().numpy()) <= 1e-10
         h = hip.HMC(L, Lt_, n_pf=1, cg_tol=1e-10, precision=precision, precond="fourier", model=dict(r=r))
         h.set_cg_workgroups(8)
+        h.set_cg_march(0)          # the batch's step A (tile kernels)
         x1, st1 = h.cg_solve(dev(phis[i]), dev(bs[i]))
         assert st1.iterations == st["iterations"][i:i + 1]
         assert torch.equal(x1.reshape(xs[i].shape), xs[i])
@@ -179,6 +181,7 @@ def test_pcg_batch_uneven_time_extents(hip, precision):
         assert resid(m, phis[i], bs[i][0], xs[i][0].cpu().numpy()) <= 1e-10
         h = hip.HMC(L, Lt, n_pf=1, cg_tol=1e-10, precision=precision, precond="fourier", model=dict(r=r))
         h.set_cg_workgroups(8)
+        h.set_cg_march(0)          # the batch's step A (tile kernels)
         x1, st1 = h.cg_solve(dev(phis[i]), dev(bs[i]))
         assert st1.iterations == st["iterations"][i:i + 1]
         assert torch.equal(x1.reshape(xs[i].shape), xs[i])
