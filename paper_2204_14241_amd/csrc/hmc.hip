@@ -36,6 +36,11 @@
 #include "probe.h"
 #include "march.h"
 
+// Hash of the sources the library was built from (set by the build; keys the tuning cache).
+#ifndef HMC_SOURCE_HASH
+#define HMC_SOURCE_HASH "unknown"
+#endif
+
 using namespace hmc;
 
 namespace {
@@ -210,6 +215,9 @@ struct hmc_ctx {
     // per segment (0: the default)
     int cgm_rows[2] = {0, 0};
     int cgm_seg[2] = {0, 0};
+    // partial sums the last launched kernel left per unit when its workgroup count is not the
+    // CG launch shape's (a march); the next launch's control block takes it over
+    int next_nparts = 0;
 
     // device address of the static scratch on this context's GPU (null if it could not be
     // resolved; only hmc_apply_MdagM_noalloc uses it)
@@ -523,10 +531,6 @@ struct TuneKey {
 static std::mutex g_tune_mu;
 static std::map<TuneKey, TuneChoice> g_tuned;
 
-#ifndef HMC_SOURCE_HASH
-#define HMC_SOURCE_HASH "unknown"
-#endif
-
 // The on-disk cache: one line per key, "<key> bpr64 bpr32 rows64 slices64 rows32 slices32".
 static std::string tune_cache_path() {
     const char* e = std::getenv("HMC_TUNE_CACHE");
@@ -718,7 +722,8 @@ static CgCtl next_ctl(hmc_ctx* c, int expect) {
     k.part = c->part;
     k.nslots = c->pslots;
     k.expect = expect;
-    k.nparts = 0;
+    k.nparts = c->next_nparts;
+    c->next_nparts = 0;
     c->seq += 1;
     return k;
 }
@@ -797,11 +802,12 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
     for (int i = 0; i < chunk; ++i) {
         const int expect_a = lc.pc ? PEND_NONE : (i > 0 ? PEND_RR : (first ? PEND_BB : PEND_NONE));
         const CgCtl ka = next_ctl(c, expect_a);
-        CgCtl kb = next_ctl(c, PEND_TT);
         if constexpr (std::is_same<Geo, GeoOne>::value) {
             if (lc.cgm_per_unit > 0) {
-                // step A as a march; step B then reduces the march's partials
-                kb.nparts = lc.cgm_per_unit;
+                // step A as a march; step B (the tile kernel, which reads t while the MALL still
+                // holds it) reduces the march's partials
+                c->next_nparts = lc.cgm_per_unit;
+                const CgCtl kb = next_ctl(c, PEND_TT);
                 const hipEvent_t* e = (sample && i == chunk / 2) ? c->tev[kslot] : nullptr;
                 const int g = lc.cgm_per_unit * n;
                 if constexpr (sizeof(R) == sizeof(float)) {
@@ -831,6 +837,7 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
                 continue;
             }
         }
+        const CgCtl kb = next_ctl(c, PEND_TT);
         if (sample && i == chunk / 2) {
             // timestamps from the dispatches themselves (not captured into graphs)
             hipEvent_t* e = c->tev[kslot];
@@ -913,6 +920,7 @@ static int prepare_graphs(hmc_ctx* c, const Launch<Geo>& lc, int n, const double
     for (int g = 0; g < 2; ++g) {
         hipGraph_t graph = nullptr;
         c->seq = parity;                              // every chunk starts at this parity
+        c->next_nparts = 0;
         HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
         const int rc = enqueue_chunk<R, Geo>(c, lc, n, phi64, b, x, chunk, filter, g == 0, false, 0, c->cap_stream);
         const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
@@ -960,6 +968,7 @@ static int cg_run(hmc_ctx* c, const Launch<Geo>& lc, int n, const double* phi64,
         if (rc) return rc;
     }
     c->seq = 0;
+    c->next_nparts = 0;
     hipLaunchKernelGGL((k_cg_init<R, Geo>), dim3(lc.ncg), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), lc.cg, b, x,
                        v, tol * tol, mixed ? kRuDrop2 : 0.0, c->p.cg_maxit, lc.pc ? 1 : 0);
     LAUNCHCHK();
@@ -1797,6 +1806,7 @@ static int apply_precond_impl(hmc_ctx* c, const double2* in, void* out, int n, d
     const size_t bytes = size_t(n) * 4 * size_t(c->vol) * sizeof(C2<R>);
     HIPCHK(hipMemsetAsync(v.z, 0, bytes, s));   // P 0 = 0: a zero input leaves z untouched
     c->seq = 0;
+    c->next_nparts = 0;
     hipLaunchKernelGGL((k_cg_init<R, GeoOne>), dim3(lc.ncg), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), lc.cg,
                        in, c->xsol, v, 0.0, 0.0, 1, 1);
     LAUNCHCHK();
