@@ -85,15 +85,14 @@ def parse():
                          "iterations per precision at 256, 512, 1024 and 2048 workgroups")
     ap.add_argument("--applies-only", action="store_true",
                     help="only the isolated M^dagger M legs (two-pass and one-pass, both precisions)")
-    ap.add_argument("--mall-bpr", type=int, default=0,
-                    help="--profile-mall: CG workgroups per right-hand side (0: the default)")
     ap.add_argument("--profile-fused", action="store_true",
                     help="short fixed sequence for counter runs of the one-pass M^dagger M: a 512 MiB "
                          "device copy, then three FP32 and three FP64 applies at the workload size")
     ap.add_argument("--profile-mall", action="store_true",
                     help="short fixed sequence for counter runs with a working set above the MALL: a "
-                         "512 MiB device copy, then 60 mixed-precision CG iterations on 4 right-hand "
-                         "sides at once at the workload size")
+                         "512 MiB device copy, the autotuner for 4 right-hand sides (--no-tune skips "
+                         "it), then 60 mixed-precision CG iterations on 4 right-hand sides at once at "
+                         "the workload size")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="short fixed sequence for counter runs: a 512 MiB device copy (the "
                          "byte-counter calibration), the autotuner (the benchmark's launch shape; "
@@ -192,8 +191,8 @@ def profile_mall(args):
     eta = torch.from_numpy(S.draw_eta(g, L, Lt, 4)).to(dev)
     h = hmcmod.HMC(L, Lt, precision="mixed", n_pf=4, max_rhs=4, cg_tol=1e-30, cg_maxit=60, reliable_every=50)
     chi = h.heatbath(phi, eta)
-    if args.mall_bpr > 0:
-        h.set_cg_workgroups(args.mall_bpr, "mixed")
+    if not args.no_tune:
+        log(f"autotune: {h.autotune(phi, chi)}")   # the launch shape of the benchmark's leg
     try:
         h.cg_solve(phi, chi)
     except HmcError as e:          # the tolerance is never met: 60 iterations run
