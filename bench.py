@@ -512,10 +512,15 @@ def apply_bench(hmcmod, torch, L, Lt, f32, reps, seed):
     return 1e3 / ms, bps / (ms * 1e-3) / 1e9, ms, nsets
 
 
-def fused_apply_bench(hmcmod, torch, L, Lt, f32, reps, seed, rows_set=(2, 4, 6, 8, 12, 16), slices_set=(1, 2, 4)):
+FUSED_SHAPES = {True: ((12, 1), (6, 8), (8, 4), (8, 6), (8, 8), (8, 10), (12, 8), (16, 4)),
+                False: ((6, 1), (2, 8), (3, 8), (4, 4), (4, 8), (6, 4), (6, 8), (7, 8))}
+
+
+def fused_apply_bench(hmcmod, torch, L, Lt, f32, reps, seed):
     """The one-pass M^dagger M (hmc_apply_MdagM / _f32) with buffer sets rotated through more than
-    512 MB, at each launch shape (rows per band, slices per segment); 76 B (FP32) or 152 B (FP64)
-    per site.  Returns the fastest shape's rate and every shape's time."""
+    512 MB, at each launch shape of FUSED_SHAPES (rows per band, slices per segment: 1 is the
+    one-slice kernel, more the march); 76 B (FP32) or 152 B (FP64) per site.  Returns the fastest
+    shape's rate and every shape's time."""
     import numpy as np
     import synth_inputs as S
     dev = torch.device("cuda")
@@ -534,8 +539,8 @@ def fused_apply_bench(hmcmod, torch, L, Lt, f32, reps, seed, rows_set=(2, 4, 6, 
     name = "hmc_apply_MdagM_f32" if f32 else "hmc_apply_MdagM"
     bps = launch_bytes("apply_f32" if f32 else "apply_f64", vol)
     tried = []
-    for rows in rows_set:
-        for sl in slices_set:
+    for rows, sl in FUSED_SHAPES[f32]:
+        if True:
             h.set_mdm_shape(rows, sl, prec)
             shape = h.mdm_shape(prec, 1)
             for i in range(nsets):

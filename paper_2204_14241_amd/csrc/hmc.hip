@@ -1688,52 +1688,44 @@ static int apply_impl(hmc_ctx* c, const R* phi, const void* in, void* out, int n
     return launch_apply<R, DAG>(c, phi, in, out, n, (hipStream_t)stream);
 }
 
-// Launch shape of the fused M^dagger M for n vectors: rows per band (so that the chi rows fit
-// 64 KB of LDS), slices per segment (1: one workgroup per slice and band, k_mdm*_tile; more:
-// the march), threads (one per element of the band, at most 512) and elements per thread (at
-// most 4).  The shape does not depend on n.
+// Launch shape of the fused M^dagger M for n vectors: rows per band, slices per segment (1: one
+// workgroup per slice and band, k_mdm*_tile, whose chi rows fit 64 KB of LDS; more: the march,
+// k_mdm*_march), threads (one per element of the rows a workgroup holds, at most 512).  The
+// shape does not depend on n.
 struct MdmShape {
     MarchPlan plan;
-    int threads, ept;
+    int threads;
     size_t lds;
-    bool tile;   // one slice per workgroup (k_mdm*_tile), else the march
+    bool tile;   // one slice per workgroup (k_mdm*_tile), else the march (k_mdm*_march)
 };
 template <typename R>
 static MdmShape mdm_shape(const hmc_ctx* c, int n) {
     const int pi = sizeof(R) == sizeof(float) ? 1 : 0;
     const int L = c->L, Lt = c->Lt, per_row = pi ? L / 2 : L;
-    // defaults: the fastest shapes at 80 x 80 x 200 (one slice per workgroup; 12 rows FP32, 6 FP64)
-    int rows = c->mdm_rows[pi] > 0 ? c->mdm_rows[pi] : (pi ? 12 : 6);
+    // defaults: the fastest shapes at 80 x 80 x 200 (the march: 8 rows FP32, 4 rows FP64, 8 slices)
+    int rows = c->mdm_rows[pi] > 0 ? c->mdm_rows[pi] : (pi ? 8 : 4);
     const int rows_lds = int((size_t(64) << 10) / (4 * size_t(L) * sizeof(C2<R>))) - 2;
     rows = std::max(1, std::min({rows, rows_lds, 4 * kMarchMaxThreads / per_row}));
-    const int seg = c->mdm_seg[pi] > 0 ? c->mdm_seg[pi] : 1;
+    const int seg = c->mdm_seg[pi] > 0 ? c->mdm_seg[pi] : 8;
     (void)n;
     MdmShape m;
     m.tile = seg == 1;
-    if (m.tile) rows = std::max(1, std::min(rows, kMarchMaxThreads / per_row));
-    m.plan = make_march_plan(L, Lt, rows, seg);
-    const int elems = m.plan.R * per_row;
     if (m.tile) {
+        rows = std::max(1, std::min(rows, kMarchMaxThreads / per_row));
+        m.plan = make_march_plan(L, Lt, rows, seg);
         // one element of the band per thread, and the rows beside it on the first 2 rows' worth
-        m.threads = (std::max(elems, 2 * per_row) + 63) / 64 * 64;
-        m.ept = 1;
+        m.threads = (std::max(m.plan.R * per_row, 2 * per_row) + 63) / 64 * 64;
+        m.lds = march_lds<R>(m.plan.R, L);
     } else {
-        m.threads = std::min(kMarchMaxThreads, (elems + 63) / 64 * 64);
-        m.ept = (elems + m.threads - 1) / m.threads;
+        // the march: one thread per element of the band and of the two rows on either side;
+        // psi of two slices and chi of one in LDS (at most 160 KB)
+        const int rows_lds = int((size_t(160) << 10) / (4 * size_t(L) * sizeof(C2<R>)) - 10) / 3;
+        rows = std::max(1, std::min({rows, kMdmMarchThreads / per_row - 4, rows_lds}));
+        m.plan = make_march_plan(L, Lt, rows, seg);
+        m.threads = ((std::min(rows, L) + 4) * per_row + 63) / 64 * 64;
+        m.lds = mdm_march_lds<R>(m.plan.R, L);
     }
-    m.lds = march_lds<R>(m.plan.R, L);
     return m;
-}
-
-template <typename R, int EPT>
-static void launch_mdm_ept(const hmc_ctx* c, const MdmShape& m, int grid, const R* phi, const void* in,
-                           void* out, hipStream_t s) {
-    if constexpr (sizeof(R) == sizeof(float))
-        hipLaunchKernelGGL((k_mdm2<EPT>), dim3(grid), dim3(m.threads), m.lds, s, c->lat, m.plan,
-                           static_cast<const float2*>(in), static_cast<float2*>(out), phi, c->cf32);
-    else
-        hipLaunchKernelGGL((k_mdm<EPT>), dim3(grid), dim3(m.threads), m.lds, s, c->lat, m.plan,
-                           static_cast<const double2*>(in), static_cast<double2*>(out), phi, c->cf64);
 }
 
 // out = M^dagger M in, one pass (nearest-neighbour operator, one lattice).
@@ -1742,22 +1734,33 @@ static int launch_mdm(hmc_ctx* c, const R* phi, const void* in, void* out, int n
     const MdmShape m = mdm_shape<R>(c, n);
     const long long grid = (long long)n * m.plan.nband * m.plan.nseg;
     if (grid >= (1LL << 31)) return fail(HMC_ERR_INVALID_ARG, "too many vectors");
-    if (m.tile) {
-        if constexpr (sizeof(R) == sizeof(float))
-            hipLaunchKernelGGL(k_mdm2_tile, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat, m.plan,
-                               static_cast<const float2*>(in), static_cast<float2*>(out), phi, c->cf32);
+    if (m.threads > (m.tile ? kMarchMaxThreads : kMdmMarchThreads) || m.lds > (size_t(160) << 10))
+        return fail(HMC_ERR_INVALID_ARG, "one-pass M^dagger M: no launch shape fits this lattice");
+    const bool narrow = m.threads <= kMarchMaxThreads;
+    if constexpr (sizeof(R) == sizeof(float)) {
+        const float2* a = static_cast<const float2*>(in);
+        float2* b = static_cast<float2*>(out);
+        if (m.tile)
+            hipLaunchKernelGGL(k_mdm2_tile, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat, m.plan, a, b, phi,
+                               c->cf32);
+        else if (narrow)
+            hipLaunchKernelGGL(k_mdm2_march<kMarchMaxThreads>, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat,
+                               m.plan, a, b, phi, c->cf32);
         else
-            hipLaunchKernelGGL(k_mdm_tile, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat, m.plan,
-                               static_cast<const double2*>(in), static_cast<double2*>(out), phi, c->cf64);
-        LAUNCHCHK();
-        return HMC_OK;
-    }
-    switch (m.ept) {
-        case 1: launch_mdm_ept<R, 1>(c, m, int(grid), phi, in, out, s); break;
-        case 2: launch_mdm_ept<R, 2>(c, m, int(grid), phi, in, out, s); break;
-        case 3: launch_mdm_ept<R, 3>(c, m, int(grid), phi, in, out, s); break;
-        case 4: launch_mdm_ept<R, 4>(c, m, int(grid), phi, in, out, s); break;
-        default: return fail(HMC_ERR_INVALID_ARG, "fused M^dagger M shape needs %d elements per thread", m.ept);
+            hipLaunchKernelGGL(k_mdm2_march<kMdmMarchThreads>, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat,
+                               m.plan, a, b, phi, c->cf32);
+    } else {
+        const double2* a = static_cast<const double2*>(in);
+        double2* b = static_cast<double2*>(out);
+        if (m.tile)
+            hipLaunchKernelGGL(k_mdm_tile, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat, m.plan, a, b, phi,
+                               c->cf64);
+        else if (narrow)
+            hipLaunchKernelGGL(k_mdm_march<kMarchMaxThreads>, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat,
+                               m.plan, a, b, phi, c->cf64);
+        else
+            hipLaunchKernelGGL(k_mdm_march<kMdmMarchThreads>, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat,
+                               m.plan, a, b, phi, c->cf64);
     }
     LAUNCHCHK();
     return HMC_OK;
@@ -2049,6 +2052,13 @@ int hmc_create(int L, int Lt, double dtau, const hmc_params* params, hmc_ctx** o
     }
     (void)set_cg_shape(c, HMC_FP64, kDefaultBpr64);
     (void)set_cg_shape(c, HMC_MIXED, kDefaultBpr32);
+    // the one-pass M^dagger M march holds two slices of psi and one of chi in LDS (above 64 KB)
+    for (const void* k : {reinterpret_cast<const void*>(&k_mdm2_march<kMarchMaxThreads>),
+                          reinterpret_cast<const void*>(&k_mdm2_march<kMdmMarchThreads>),
+                          reinterpret_cast<const void*>(&k_mdm_march<kMarchMaxThreads>),
+                          reinterpret_cast<const void*>(&k_mdm_march<kMdmMarchThreads>)})
+        (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 << 10);
+    (void)hipGetLastError();
     // step A marches by default (the tile kernels where a lattice's band does not fit)
     c->cgm_rows[0] = 4;
     c->cgm_rows[1] = 8;

@@ -1,25 +1,21 @@
-// march.h -- the normal operator M^dagger M of Eq. (22) in one pass over HBM.
+// march.h -- kernels that walk a band of lattice rows through consecutive time slices, holding
+// the reuse along tau on chip: the normal operator M^dagger M of Eq. (22) in one pass over HBM,
+// and step A of the conjugate-gradient iteration.
 //
 // With chi = M psi (Eq. 17):  (M^dagger M psi)(tau) = A_tau chi(tau) + s_{tau-1} chi(tau - 1),
 // where A_tau is the time-local part of M (diagonal, hopping, Yukawa coupling to phi(tau)) and
 // s_{tau-1} the sign of the time link (-1 across the antiperiodic wrap at tau = 0).  Applying
 // A_tau needs chi(tau) at the spatial neighbours, so chi(tau) = A_tau psi(tau) + s_tau psi(tau+1)
-// is formed one row beyond the rows a workgroup writes, and chi(tau - 1) is the previous slice of
-// the same workgroup.
+// is formed one row beyond the rows a workgroup writes, and chi(tau - 1) is the previous slice
+// of the same workgroup.  HBM then sees psi and phi read once and the result written once:
+// 76 B per site in FP32 (complex64 spinors, FP32 phi), 152 B in FP64, half the two-pass bytes.
 //
-// A workgroup owns a band of R whole rows (x0 .. x0 + R - 1, every y) of one vector and marches
-// through a segment of time slices.  Per slice it computes chi on the R + 2 rows of its band and
-// the two rows beside it into LDS (psi and phi come through the cache hierarchy: the rows beside
-// a band are the neighbour bands' own rows, read by the workgroups next to it on the same XCD),
-// then forms M^dagger M psi on its R rows from LDS and from chi(tau - 1), which each thread keeps
-// in registers for the sites it writes.  The first slice of a segment forms chi(t0 - 1) at those
-// sites first.  HBM sees psi and phi read once and the result written once: 76 B per site in
-// FP32 (complex64 spinors, FP32 phi), 152 B in FP64, against twice that for two passes.
-// Workgroups are ordered segment-major, so with the XCD remap each XCD sweeps every band of a
-// run of consecutive segments: the rows beside a band and the slice before a segment are read
-// through the same L2.
+// Workgroups own a band of whole rows (every y) of one vector and a segment of slices; they are
+// ordered segment-major, so with the XCD remap each XCD sweeps every band of a run of
+// consecutive segments and the rows beside a band are read through the same L2.  A second form
+// of the normal operator takes one slice per workgroup and forms chi(tau - 1) itself.
 //
-// The nearest-neighbour operator only (the two-site hops need a band two rows wider); the
+// The nearest-neighbour operator only (the two-site hops need bands two rows wider); the
 // arithmetic per site is that of the two-pass kernels, in the same order.
 #pragma once
 
@@ -130,70 +126,6 @@ __device__ __forceinline__ void mdag_pair_lds(const float2* __restrict__ chi, in
     stencil_pair_lds(chi, r, x, y, lat.L, P1, P2, P3, cf, ts, tt, o, cen);
 }
 
-// FP32: an element is a pair of neighbouring sites (y even), as in the pair kernels.
-// EPT: pairs of the band's rows per thread (the launch has at least R * L / (2 EPT) threads,
-// at most kMarchMaxThreads).
-template <int EPT>
-__global__ __launch_bounds__(kMarchMaxThreads) void k_mdm2(Lat lat, MarchPlan mp, const float2* __restrict__ in,
-                                               float2* __restrict__ out, const float* __restrict__ phi,
-                                               Coef<float> cf) {
-    extern __shared__ __align__(16) unsigned char march_smem[];
-    float2* chi = reinterpret_cast<float2*>(march_smem);      // [row][component][y]
-    const int L = lat.L, vol = lat.vol, P = L / 2, rowc = 4 * L;
-    const MarchPos mpos = march_pos(lat, mp, xcd_remap(blockIdx.x, gridDim.x));
-    const size_t voff = size_t(mpos.k) * 4 * vol;
-    const SrcPlain2 src{in + voff, vol};
-    float2* dst = out + voff;
-    const int nint = mpos.nr * P, nhalo = (mpos.nr + 2) * P;
-
-    // chi(t0 - 1) at this thread's pairs
-    float4 prev[EPT][4];
-    {
-        const int tm = mpos.t0 == 0 ? lat.Lt - 1 : mpos.t0 - 1;
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const int e = threadIdx.x + j * blockDim.x;
-            if (e < nint) {
-                const int lr = e / P, py = e - lr * P;
-                const int s = (tm * L + mpos.x0 + lr) * L + 2 * py;
-                float4 cen[4];
-                dslash_pair<false, false>(src, phi, lat, cf, neighbours(lat, s), s, prev[j], cen);
-            }
-        }
-    }
-    for (int tau = mpos.t0; tau < mpos.t1; ++tau) {
-        // chi(tau) = M psi on the band's rows and the row on either side
-        for (int e = threadIdx.x; e < nhalo; e += blockDim.x) {
-            const int lr = e / P, py = e - lr * P;
-            const int s = (tau * L + wrap_row(mpos.x0 - 1 + lr, L)) * L + 2 * py;
-            float4 o[4], cen[4];
-            dslash_pair<false, false>(src, phi, lat, cf, neighbours(lat, s), s, o, cen);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) *reinterpret_cast<float4*>(chi + lr * rowc + c * L + 2 * py) = o[c];
-        }
-        __syncthreads();
-        // M^dagger chi on the band's rows: A_tau chi(tau) from LDS, the time link from chi(tau - 1)
-        const float ts = tau == 0 ? -1.f : 1.f;
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const int e = threadIdx.x + j * blockDim.x;
-            if (e < nint) {
-                const int lr = e / P, py = e - lr * P, y = 2 * py;
-                const int x = mpos.x0 + lr;
-                const int s = (tau * L + x) * L + y;
-                float4 cen[4], o[4];
-                mdag_pair_lds(chi, lr + 1, x, y, s, lat, phi, cf, ts, prev[j], o, cen);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    st4(dst, size_t(c) * vol + s, o[c]);
-                    prev[j][c] = cen[c];
-                }
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // FP64 form of stencil_pair_lds at the site (x, y), phi(tau) there given as (q1, q2, q3) before
 // the coupling and the staggered sign are applied.
 __device__ __forceinline__ void stencil_site_lds(const double2* __restrict__ chi, int r, int x, int y, int L,
@@ -233,65 +165,6 @@ __device__ __forceinline__ void mdag_site_lds(const double2* __restrict__ chi, i
                                               double2 (&o)[4], double2 (&cen)[4]) {
     const int vol = lat.vol;
     stencil_site_lds(chi, r, x, y, lat.L, phi[s], phi[vol + s], phi[2 * vol + s], cf, ts, tt, o, cen);
-}
-
-// FP64: an element is one site.
-template <int EPT>
-__global__ __launch_bounds__(kMarchMaxThreads) void k_mdm(Lat lat, MarchPlan mp, const double2* __restrict__ in,
-                                              double2* __restrict__ out, const double* __restrict__ phi,
-                                              Coef<double> cf) {
-    extern __shared__ __align__(16) unsigned char march_smem[];
-    double2* chi = reinterpret_cast<double2*>(march_smem);    // [row][component][y]
-    const int L = lat.L, vol = lat.vol, rowc = 4 * L;
-    const MarchPos mpos = march_pos(lat, mp, xcd_remap(blockIdx.x, gridDim.x));
-    const size_t voff = size_t(mpos.k) * 4 * vol;
-    const SrcPlain<double> src{in + voff, vol};
-    double2* dst = out + voff;
-    const int nint = mpos.nr * L, nhalo = (mpos.nr + 2) * L;
-
-    double2 prev[EPT][4];
-    {
-        const int tm = mpos.t0 == 0 ? lat.Lt - 1 : mpos.t0 - 1;
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const int e = threadIdx.x + j * blockDim.x;
-            if (e < nint) {
-                const int lr = e / L, y = e - lr * L;
-                const int s = (tm * L + mpos.x0 + lr) * L + y;
-                double2 cen[4];
-                dslash_site<double, false, false>(src, phi, lat, cf, neighbours(lat, s), s, prev[j], cen);
-            }
-        }
-    }
-    for (int tau = mpos.t0; tau < mpos.t1; ++tau) {
-        for (int e = threadIdx.x; e < nhalo; e += blockDim.x) {
-            const int lr = e / L, y = e - lr * L;
-            const int s = (tau * L + wrap_row(mpos.x0 - 1 + lr, L)) * L + y;
-            double2 o[4], cen[4];
-            dslash_site<double, false, false>(src, phi, lat, cf, neighbours(lat, s), s, o, cen);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) chi[lr * rowc + c * L + y] = o[c];
-        }
-        __syncthreads();
-        const double ts = tau == 0 ? -1.0 : 1.0;
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const int e = threadIdx.x + j * blockDim.x;
-            if (e < nint) {
-                const int lr = e / L, y = e - lr * L;
-                const int x = mpos.x0 + lr;
-                const int s = (tau * L + x) * L + y;
-                double2 cen[4], o[4];
-                mdag_site_lds(chi, lr + 1, x, y, s, lat, phi, cf, ts, prev[j], o, cen);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    dst[size_t(c) * vol + s] = o[c];
-                    prev[j][c] = cen[c];
-                }
-            }
-        }
-        __syncthreads();
-    }
 }
 
 // The same operator with one workgroup per (vector, time slice, band) and no march: chi(tau) on
@@ -653,6 +526,223 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, Lat l
         W.pending = PEND_TT;
     }
     cg_publish(ctl, pos);
+}
+
+// ------------------------------------------------------------------------------------
+// M^dagger M in one pass as a march with the loads one slice ahead (the structure of the CG
+// step-A march): a workgroup owns a band of R rows of one vector and the two rows on either
+// side of it, and walks a segment of slices.  psi of two consecutive slices sits in LDS on the
+// R + 4 rows; each slice it forms chi(tau) = A_tau psi(tau) + s_tau psi(tau + 1) on the R + 2
+// rows that M^dagger reaches into LDS, then (M^dagger chi)(tau) = A_tau chi(tau) +
+// s_{tau-1} chi(tau - 1) on its R rows, chi(tau - 1) kept in registers from the slice before;
+// the next slice's psi and phi are loaded while the current one is computed.  The first slice
+// of a segment forms chi(t0 - 1) at the band's rows first.  HBM: psi and phi read once (plus
+// the rows beside each band, which its neighbours read too, and one slice per segment), the
+// result written once.
+// Most threads of a one-pass M^dagger M march workgroup (one per element of its rows).  The
+// kernels are instantiated for at most 512 threads (up to 256 VGPRs each) and for 1024 (128
+// VGPRs, a few spilled): narrow bands take the first, wide ones the second.
+constexpr int kMdmMarchThreads = 1024;
+
+template <typename R>
+__host__ __device__ inline size_t mdm_march_lds(int Rrows, int L) {
+    return size_t(3 * Rrows + 10) * 4 * size_t(L) * sizeof(C2<R>);
+}
+
+template <int MAXT>
+__global__ __launch_bounds__(MAXT) void k_mdm2_march(Lat lat, MarchPlan mp, const float2* __restrict__ in,
+                                                                float2* __restrict__ out,
+                                                                const float* __restrict__ phi, Coef<float> cf) {
+    extern __shared__ __align__(16) unsigned char march_smem[];
+    const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, P = L / 2, rowc = 4 * L;
+    const MarchPos mpos = march_pos(lat, mp, xcd_remap(blockIdx.x, gridDim.x));
+    const size_t voff = size_t(mpos.k) * 4 * vol;
+    const float2* psi = in + voff;
+    float2* dst = out + voff;
+    float2* cur = reinterpret_cast<float2*>(march_smem);        // psi(tau), rows x0 - 2 .. x0 + nr + 1
+    float2* nxt = cur + size_t(mp.R + 4) * rowc;                  // psi(tau + 1)
+    float2* chi = nxt + size_t(mp.R + 4) * rowc;                  // chi(tau), rows x0 - 1 .. x0 + nr
+    const int e = threadIdx.x, nh = (mpos.nr + 4) * P;
+    const bool act = e < nh;
+    const int lr = act ? e / P : 0, py = act ? e - lr * P : 0, y = 2 * py;
+    const int xrow = wrap_row(mpos.x0 - 2 + lr, L);
+    const bool chirow = act && lr >= 1 && lr <= mpos.nr + 2;     // M psi is formed here
+    const bool inner = act && lr >= 2 && lr <= mpos.nr + 1;      // M^dagger M psi is written here
+    const int ro = xrow * L + y;
+    float4 rv[4];
+    float2 f1 = make_float2(0.f, 0.f), f2 = f1, f3 = f1;
+    auto load_psi = [&](int tq) {
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rv[c] = ld4(psi, size_t(c) * vol + size_t(tq) * LL + ro);
+        }
+    };
+    auto load_phi = [&](int tq) {
+        if (chirow) {
+            const size_t i = size_t(tq) * LL + ro;
+            f1 = *reinterpret_cast<const float2*>(phi + i);
+            f2 = *reinterpret_cast<const float2*>(phi + vol + i);
+            f3 = *reinterpret_cast<const float2*>(phi + 2 * vol + i);
+        }
+    };
+    auto put = [&](float2* buf) {
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) *reinterpret_cast<float4*>(buf + lr * rowc + c * L + y) = rv[c];
+        }
+    };
+    const int t0 = mpos.t0, t1 = mpos.t1;
+    const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
+    // chi(t0 - 1) at the band's rows, from psi(t0 - 1) and psi(t0)
+    float4 prev[4], own[4];
+    load_psi(tm);
+    load_phi(tm);
+    put(nxt);
+    load_psi(t0);
+    __syncthreads();
+    put(cur);
+    const float2 h1 = f1, h2 = f2, h3 = f3;
+    float4 pv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pv[c] = rv[c];
+    load_psi(t0 + 1 == Lt ? 0 : t0 + 1);
+    load_phi(t0);
+    __syncthreads();
+    if (inner) {
+        float4 cen[4];
+        stencil_pair_lds(nxt, lr, xrow, y, L, h1, h2, h3, cf, tm == Lt - 1 ? -1.f : 1.f, pv, prev, cen);
+    }
+    __syncthreads();
+    for (int tau = t0; tau < t1; ++tau) {
+        // rv holds psi(tau + 1), f phi(tau)
+        put(nxt);
+        float4 pn[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pn[c] = rv[c];
+        const float2 g1 = f1, g2 = f2, g3 = f3;
+        if (tau + 1 < t1) {
+            const int tn = tau + 1 == Lt ? 0 : tau + 1;
+            load_psi(tn + 1 == Lt ? 0 : tn + 1);
+            load_phi(tn);
+        }
+        __syncthreads();
+        if (chirow) {
+            float4 cen[4];
+            stencil_pair_lds(cur, lr, xrow, y, L, g1, g2, g3, cf, tau == Lt - 1 ? -1.f : 1.f, pn, own, cen);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) *reinterpret_cast<float4*>(chi + (lr - 1) * rowc + c * L + y) = own[c];
+        }
+        __syncthreads();
+        if (inner) {
+            float4 o[4], cen[4];
+            stencil_pair_lds(chi, lr - 1, xrow, y, L, g1, g2, g3, cf, tau == 0 ? -1.f : 1.f, prev, o, cen);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                st4(dst, size_t(c) * vol + size_t(tau) * LL + ro, o[c]);
+                prev[c] = own[c];
+            }
+        }
+        float2* sw = cur;
+        cur = nxt;
+        nxt = sw;
+    }
+}
+
+template <int MAXT>
+__global__ __launch_bounds__(MAXT) void k_mdm_march(Lat lat, MarchPlan mp, const double2* __restrict__ in,
+                                                               double2* __restrict__ out,
+                                                               const double* __restrict__ phi, Coef<double> cf) {
+    extern __shared__ __align__(16) unsigned char march_smem[];
+    const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, rowc = 4 * L;
+    const MarchPos mpos = march_pos(lat, mp, xcd_remap(blockIdx.x, gridDim.x));
+    const size_t voff = size_t(mpos.k) * 4 * vol;
+    const double2* psi = in + voff;
+    double2* dst = out + voff;
+    double2* cur = reinterpret_cast<double2*>(march_smem);
+    double2* nxt = cur + size_t(mp.R + 4) * rowc;
+    double2* chi = nxt + size_t(mp.R + 4) * rowc;
+    const int e = threadIdx.x, nh = (mpos.nr + 4) * L;
+    const bool act = e < nh;
+    const int lr = act ? e / L : 0, y = act ? e - lr * L : 0;
+    const int xrow = wrap_row(mpos.x0 - 2 + lr, L);
+    const bool chirow = act && lr >= 1 && lr <= mpos.nr + 2;
+    const bool inner = act && lr >= 2 && lr <= mpos.nr + 1;
+    const int ro = xrow * L + y;
+    double2 rv[4];
+    double f1 = 0.0, f2 = 0.0, f3 = 0.0;
+    auto load_psi = [&](int tq) {
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rv[c] = psi[size_t(c) * vol + size_t(tq) * LL + ro];
+        }
+    };
+    auto load_phi = [&](int tq) {
+        if (chirow) {
+            const size_t i = size_t(tq) * LL + ro;
+            f1 = phi[i];
+            f2 = phi[vol + i];
+            f3 = phi[2 * vol + i];
+        }
+    };
+    auto put = [&](double2* buf) {
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) buf[lr * rowc + c * L + y] = rv[c];
+        }
+    };
+    const int t0 = mpos.t0, t1 = mpos.t1;
+    const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
+    double2 prev[4], own[4];
+    load_psi(tm);
+    load_phi(tm);
+    put(nxt);
+    load_psi(t0);
+    __syncthreads();
+    put(cur);
+    const double h1 = f1, h2 = f2, h3 = f3;
+    double2 pv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pv[c] = rv[c];
+    load_psi(t0 + 1 == Lt ? 0 : t0 + 1);
+    load_phi(t0);
+    __syncthreads();
+    if (inner) {
+        double2 cen[4];
+        stencil_site_lds(nxt, lr, xrow, y, L, h1, h2, h3, cf, tm == Lt - 1 ? -1.0 : 1.0, pv, prev, cen);
+    }
+    __syncthreads();
+    for (int tau = t0; tau < t1; ++tau) {
+        put(nxt);
+        double2 pn[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pn[c] = rv[c];
+        const double g1 = f1, g2 = f2, g3 = f3;
+        if (tau + 1 < t1) {
+            const int tn = tau + 1 == Lt ? 0 : tau + 1;
+            load_psi(tn + 1 == Lt ? 0 : tn + 1);
+            load_phi(tn);
+        }
+        __syncthreads();
+        if (chirow) {
+            double2 cen[4];
+            stencil_site_lds(cur, lr, xrow, y, L, g1, g2, g3, cf, tau == Lt - 1 ? -1.0 : 1.0, pn, own, cen);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) chi[(lr - 1) * rowc + c * L + y] = own[c];
+        }
+        __syncthreads();
+        if (inner) {
+            double2 o[4], cen[4];
+            stencil_site_lds(chi, lr - 1, xrow, y, L, g1, g2, g3, cf, tau == 0 ? -1.0 : 1.0, prev, o, cen);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                dst[size_t(c) * vol + size_t(tau) * LL + ro] = o[c];
+                prev[c] = own[c];
+            }
+        }
+        double2* sw = cur;
+        cur = nxt;
+        nxt = sw;
+    }
 }
 
 }  // namespace hmc

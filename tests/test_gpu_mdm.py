@@ -29,7 +29,7 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-SHAPES = [(0, 0), (1, 1), (4, 1), (12, 1), (3, 2), (8, 3), (16, 1000)]
+SHAPES = [(0, 0), (1, 1), (4, 1), (12, 1), (1, 2), (3, 2), (8, 3), (16, 1000)]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
