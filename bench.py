@@ -643,7 +643,56 @@ def batch_bench(hmcmod, torch, seed, steps, warmup):
             out.update(rec)
         else:
             out["pcg_trajectories"] = rec
+    # plain trajectories again from the same field, each leapfrog step's drift and solve
+    # replayed from one HIP graph (one untimed trajectory sizes and captures the graphs)
+    bt.set_params(precond=None)
+    bt.set_step_graphs(True)
+    phi.copy_(phi_start)
+    bt.trajectory(phi, pi0, eta, u)
+    phi.copy_(phi_start)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = 0
+    for i in range(steps):
+        its += bt.trajectory(phi, pi0, eta, u)["cg_iterations"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["step_graphs"] = {"s_per_batch_trajectory": el / steps, "unit_cg_iterations": its,
+                          "same_iterations": its == out["unit_cg_iterations"],
+                          "vs_chunk_graphs_speedup": out["s_per_batch_trajectory"] / (el / steps)}
+    log(f"batch trajectories with step graphs: {el / steps:.3f} s, unit CG iterations {its}")
     bt.close()
+    return out
+
+
+def step_graph_bench(hmcmod, torch, L, Lt, common, phi_start, d_traj, first, n):
+    """The same n mixed-precision trajectories (indices first ...) from one field, with each
+    leapfrog step's drift and solve launched kernel by kernel and replayed from one HIP graph
+    (hmc_set_step_graphs).  An untimed trajectory first sizes and captures the graphs."""
+    out = {}
+    for graphs in (False, True):
+        h = hmcmod.HMC(L, Lt, precision="mixed", **common)
+        h.set_step_graphs(graphs)
+        p, e, u = d_traj[first]
+        h.trajectory(phi_start.clone(), p, e, u)
+        phi = phi_start.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, dHs = [], []
+        for i in range(first, first + n):
+            p, e, u = d_traj[i]
+            st = h.trajectory(phi, p, e, u)
+            its.append(st["cg_iterations"])
+            dHs.append(st["dH"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        h.close()
+        key = "graph" if graphs else "eager"
+        out[key] = {"s_per_traj": el / n, "cg_iterations": its, "dH": dHs,
+                    "ms_per_cg_iteration": 1e3 * el / sum(its)}
+        log(f"step graphs {key}: {el / n:.3f} s per trajectory, iterations {its}")
+    out["same_results"] = out["graph"]["dH"] == out["eager"]["dH"]
+    out["graph_vs_eager_speedup"] = out["eager"]["s_per_traj"] / out["graph"]["s_per_traj"]
     return out
 
 
@@ -979,6 +1028,8 @@ def main():
                 "mixed_vs_fp64_per_iteration_speedup": (el64 / it_64) / (el_m / it_m),
             }
             extras["mixed_vs_fp64_traj_speedup"] = el64 / el_m
+        extras["step_graphs_80x80x200"] = step_graph_bench(hmcmod, torch, L, Lt, common, phi_w, d_traj, W,
+                                                           min(2, K))
         extras["pcg_80x80x200"] = pcg_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, W, args.pcg_steps)
         extras["metric_80x80x200"] = metric_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, args.seed)
         extras["production_model_80x80x200"] = prod_bench(hmcmod, torch, L, Lt, common, phi0, d_traj)

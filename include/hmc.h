@@ -193,9 +193,10 @@ int hmc_heatbath(hmc_ctx* ctx, const double* phi, const void* eta, void* chi, in
  * S_PF = sum_k chi_k^dagger (M^dagger M)^{-1} chi_k (Eq. 21).  Solves by CG (settings of
  * the context), then per site: Y = M x, dS_PF/dphi_l = -2 dtau lambda (-1)^(x+y)
  * Re sum_k [Y_{band x}^dagger Pauli_l x_{band y} + Y_{band y}^dagger Pauli_l x_{band x}].
- * force: double[3][L_tau][L][L] (overwritten).  S_pf (host, may be NULL) receives
- * sum_k Re <chi_k, x_k>; stats (host, may be NULL) the solver statistics.
- * Synchronises the stream.  Errors as hmc_cg_solve. */
+ * force: double[3][L_tau][L][L] (overwritten).  S_pf (DEVICE scalar, may be NULL) receives
+ * sum_k Re <chi_k, x_k> (0 without HMC_FORCE_PF), written on the stream after the gradient;
+ * stats (host, may be NULL) the solver statistics.  Synchronises the stream (the solver reads
+ * its convergence status).  Errors as hmc_cg_solve. */
 int hmc_force(hmc_ctx* ctx, const double* phi, const void* chi, int n_pf, double* force,
               double* S_pf, int flags, hmc_cg_stats* stats, void* stream);
 
@@ -442,6 +443,18 @@ int hmc_get_kernel_times(const hmc_ctx* ctx, hmc_kernel_times* out);
  * stream of the context.  Default: off for a single lattice, on for a batch. */
 int hmc_set_graphs(hmc_ctx* ctx, int enable);
 
+/* Replay each leapfrog step's drift and CG solve (Methods D, the update of phi by Eq. (29)
+ * and the solve of Eq. (22) at the new phi), and a trajectory's first solve, from one
+ * HIP graph (enable != 0): the drift, the solve's start and K status chunks, with K the most
+ * iterations of any right-hand side in the previous solve plus a tenth and one chunk, rounded
+ * up to an even count.  The host reads the CG records once after the graph and finishes a
+ * solve that needs more chunks with ordinary launches; chunks past convergence do nothing.
+ * Graphs are cached per shape (K, pointers, step size, launch shape, coefficients), at most 8.
+ * The force and the kicks stay ordinary launches.  Results are bitwise those of eager
+ * launches.  Applies with the identity metric (hmc_set_metric not in use); otherwise it is
+ * ignored.  Default: off. */
+int hmc_set_step_graphs(hmc_ctx* ctx, int enable);
+
 /* -----------------------------------------------------------------------------------------
  * Batch of independent lattices.
  *
@@ -482,6 +495,8 @@ int hmc_batch_layout(const hmc_batch* batch, long long* phi_offsets, long long* 
 int hmc_batch_set_cg_workgroups(hmc_batch* batch, int precision, int max_per_unit);
 int hmc_batch_get_cg_workgroups(const hmc_batch* batch, int precision);
 int hmc_batch_set_graphs(hmc_batch* batch, int enable);
+/* As hmc_set_step_graphs, for the batch's trajectories. */
+int hmc_batch_set_step_graphs(hmc_batch* batch, int enable);
 
 /* Replace the run parameters; n_pf must equal the value given at creation. */
 int hmc_batch_set_params(hmc_batch* batch, const hmc_params* params);

@@ -35,14 +35,14 @@ EXPORTED = [
     "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap", "hmc_test_tile_span", "hmc_test_fft",
     "hmc_test_fft_freq", "hmc_test_precond", "hmc_test_apply_precond", "hmc_stream_probe",
     "hmc_set_kernel_timing", "hmc_get_kernel_times", "hmc_set_cg_workgroups",
-    "hmc_get_cg_workgroups", "hmc_set_mdm_shape", "hmc_get_mdm_shape", "hmc_set_cg_march", "hmc_get_cg_march", "hmc_leapfrog", "hmc_autotune", "hmc_set_graphs",
+    "hmc_get_cg_workgroups", "hmc_set_mdm_shape", "hmc_get_mdm_shape", "hmc_set_cg_march", "hmc_get_cg_march", "hmc_leapfrog", "hmc_autotune", "hmc_set_graphs", "hmc_set_step_graphs",
     "hmc_set_metric", "hmc_metric_momenta", "hmc_metric_kinetic", "hmc_metric_norm2",
     "hmc_metric_accumulate", "hmc_tuner_init", "hmc_tuner_add_step", "hmc_tuner_add_jump",
     "hmc_tuner_best_length", "hmc_jitter", "hmc_warmup_iteration", "hmc_sdw_accumulate",
     "hmc_order_parameter", "hmc_binder",
     "hmc_batch_create", "hmc_batch_destroy", "hmc_batch_workspace_bytes",
     "hmc_batch_set_workspace", "hmc_batch_layout", "hmc_batch_set_cg_workgroups",
-    "hmc_batch_get_cg_workgroups", "hmc_batch_set_graphs", "hmc_batch_set_params",
+    "hmc_batch_get_cg_workgroups", "hmc_batch_set_graphs", "hmc_batch_set_step_graphs", "hmc_batch_set_params",
     "hmc_batch_apply", "hmc_batch_cg_solve", "hmc_batch_autotune", "hmc_batch_trajectory",
 ]
 
@@ -182,7 +182,7 @@ def load():
         "hmc_apply_MdagM_noalloc": (I, [P, P, P, P, I, P]),
         "hmc_cg_solve": (I, [P, P, P, P, I, ctypes.POINTER(HmcCgStats), P]),
         "hmc_heatbath": (I, [P, P, P, P, I, P]),
-        "hmc_force": (I, [P, P, P, I, P, ctypes.POINTER(D), I, ctypes.POINTER(HmcCgStats), P]),
+        "hmc_force": (I, [P, P, P, I, P, P, I, ctypes.POINTER(HmcCgStats), P]),
         "hmc_force_from_solution": (I, [P, P, P, I, P, I, P]),
         "hmc_pf_action": (I, [P, P, P, I, P, ctypes.POINTER(D), ctypes.POINTER(HmcCgStats), P]),
         "hmc_boson_action": (I, [P, P, ctypes.POINTER(D), P]),
@@ -209,6 +209,7 @@ def load():
         "hmc_get_mdm_shape": (I, [P, I, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "hmc_autotune": (I, [P, P, P, I, ctypes.POINTER(HmcTuneResult), P]),
         "hmc_set_graphs": (I, [P, I]),
+        "hmc_set_step_graphs": (I, [P, I]),
         "hmc_set_metric": (I, [P, P]),
         "hmc_metric_momenta": (I, [P, P, P, P]),
         "hmc_metric_kinetic": (I, [P, P, ctypes.POINTER(D), P]),
@@ -234,6 +235,7 @@ def load():
         "hmc_batch_set_cg_workgroups": (I, [P, I, I]),
         "hmc_batch_get_cg_workgroups": (I, [P, I]),
         "hmc_batch_set_graphs": (I, [P, I]),
+        "hmc_batch_set_step_graphs": (I, [P, I]),
         "hmc_batch_set_params": (I, [P, ctypes.POINTER(HmcParams)]),
         "hmc_batch_apply": (I, [P, I, I, P, P, P, P]),
         "hmc_batch_cg_solve": (I, [P, P, P, P, ctypes.POINTER(I), ctypes.POINTER(D), P]),

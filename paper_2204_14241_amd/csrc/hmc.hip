@@ -223,6 +223,17 @@ struct hmc_ctx {
     // resolved; only hmc_apply_MdagM_noalloc uses it)
     void* scratch = nullptr;
 
+    // one graph per leapfrog step: the drift, the solve's start and a fixed number of status
+    // chunks (sized from the previous solve), cached by shape
+    bool step_graphs = false;
+    int sg_last_iters = 0;     // most iterations of a unit in the last solve
+    struct StepGraph {
+        std::tuple<int, int, const void*, const void*, const void*, const void*, int, long, int, int, double, int> key;
+        hipGraphExec_t exec = nullptr;
+        int seq_after = 0;
+    };
+    std::vector<StepGraph> sgs;
+
     // graph replay of CG chunks
     bool graphs = false;
     hipStream_t cap_stream = nullptr;
@@ -947,9 +958,11 @@ static int prepare_graphs(hmc_ctx* c, const Launch<Geo>& lc, int n, const double
 
 // Solve (M^dagger M) x_u = b_u for the n units of the launch.  Final records are left in
 // c->h_st[0 .. n).  Returns HMC_OK, HMC_ERR_NOT_CONVERGED or HMC_ERR_NONFINITE.
+// The start of a solve: FP32 copy of phi (mixed precision), the CG start (x = 0, r = b, |b|^2),
+// and with the preconditioner z = P b.  Resets the launch counter.
 template <typename R, class Geo>
-static int cg_run(hmc_ctx* c, const Launch<Geo>& lc, int n, const double* phi64, const double2* b,
-                  double2* x, hipStream_t s) {
+static int cg_prologue(hmc_ctx* c, const Launch<Geo>& lc, const double* phi64, const double2* b, double2* x,
+                       hipStream_t s) {
     const bool mixed = sizeof(R) == sizeof(float);
     CgVecs<R> v = KrylovBufs<R>::get(c, x, lc.pc);
     if (mixed) {
@@ -957,6 +970,26 @@ static int cg_run(hmc_ctx* c, const Launch<Geo>& lc, int n, const double* phi64,
                            c->phi32, int(3 * c->phi_sites));
         LAUNCHCHK();
     }
+    const double tol = c->p.cg_tol;
+    c->seq = 0;
+    c->next_nparts = 0;
+    hipLaunchKernelGGL((k_cg_init<R, Geo>), dim3(lc.ncg), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), lc.cg, b, x,
+                       v, tol * tol, mixed ? kRuDrop2 : 0.0, c->p.cg_maxit, lc.pc ? 1 : 0);
+    LAUNCHCHK();
+    if (lc.pc) {
+        int rc = enqueue_pc<R, Geo>(c, lc, v, PEND_BB, s);
+        if (rc) return rc;
+    }
+    return HMC_OK;
+}
+
+// k0 > 0: the start and the first k0 status chunks are already on the stream (a step graph);
+// the host reads the records once and goes on with further chunks only if some unit is not
+// finished.
+template <typename R, class Geo>
+static int cg_run(hmc_ctx* c, const Launch<Geo>& lc, int n, const double* phi64, const double2* b,
+                  double2* x, hipStream_t s, int k0 = 0) {
+    const bool mixed = sizeof(R) == sizeof(float);
     const double tol = c->p.cg_tol;
     const int chunk = mixed ? c->p.reliable_every : kCheckEvery;
     const int ru_filter = mixed ? (F_ACTIVE | F_CONV_ITER | F_MAXIT) : (F_CONV_ITER | F_MAXIT);
@@ -967,27 +1000,28 @@ static int cg_run(hmc_ctx* c, const Launch<Geo>& lc, int n, const double* phi64,
         int rc = prepare_graphs<R, Geo>(c, lc, n, phi64, b, x, chunk, ru_filter, parity);
         if (rc) return rc;
     }
-    c->seq = 0;
-    c->next_nparts = 0;
-    hipLaunchKernelGGL((k_cg_init<R, Geo>), dim3(lc.ncg), dim3(kBlock), 0, s, next_ctl(c, PEND_NONE), lc.cg, b, x,
-                       v, tol * tol, mixed ? kRuDrop2 : 0.0, c->p.cg_maxit, lc.pc ? 1 : 0);
-    LAUNCHCHK();
-    if (lc.pc) {
-        int rc = enqueue_pc<R, Geo>(c, lc, v, PEND_BB, s);
+    const size_t st_bytes = sizeof(CgState) * size_t(n);
+    bool done_early = false;
+    if (k0 == 0) {
+        int rc = cg_prologue<R, Geo>(c, lc, phi64, b, x, s);
         if (rc) return rc;
+    } else {
+        HIPCHK(hipMemcpyAsync(c->h_st, current_states(c), st_bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        done_early = true;
+        for (int j = 0; j < n; ++j) done_early = done_early && finished(c->h_st[j].mode);
     }
 
-    const size_t st_bytes = sizeof(CgState) * size_t(n);
     const int nlaunch = chunk_launches(chunk, lc.pc);
-    int issued = 0;
-    int k = 0;
+    int issued = k0 * chunk;
+    int k = k0;
     bool have_prev = false;
     const int kt_a = mixed ? 0 : 2;
     const bool sample = c->timing && !use_graphs;
     bool start_active_prev = true;   // were all units iterating when chunk k-1 began
     // Chunks are issued one ahead of the status read, so the GPU never idles on the host;
     // once every unit is finished the remaining launches return at once.
-    for (;;) {
+    for (; !done_early;) {
         if (use_graphs) {
             HIPCHK(hipGraphLaunch(c->cgg[mixed ? 1 : 0].exec[k == 0 ? 0 : 1], s));
             c->seq += nlaunch;
@@ -1027,9 +1061,13 @@ static int cg_run(hmc_ctx* c, const Launch<Geo>& lc, int n, const double* phi64,
         // the device enforces cg_maxit; this bound only guards the host loop
         if (issued > c->p.cg_maxit + 4 * chunk) break;
     }
-    HIPCHK(hipMemcpyAsync(c->h_st, current_states(c), st_bytes, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    if (!done_early) {
+        HIPCHK(hipMemcpyAsync(c->h_st, current_states(c), st_bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
     int status = HMC_OK;
+    c->sg_last_iters = 0;
+    for (int j = 0; j < n; ++j) c->sg_last_iters = std::max(c->sg_last_iters, c->h_st[j].iters);
     for (int j = 0; j < n; ++j) {
         const CgState& h = c->h_st[j];
         if (h.mode == CG_FAILED) status = HMC_ERR_NONFINITE;
@@ -1039,6 +1077,63 @@ static int cg_run(hmc_ctx* c, const Launch<Geo>& lc, int n, const double* phi64,
     if (status == HMC_ERR_NOT_CONVERGED)
         return fail(status, "CG did not reach tol %.3g within %d iterations", tol, c->p.cg_maxit);
     return HMC_OK;
+}
+
+// A leapfrog step's drift (drift_pi non-null: phi += eps pi) and solve, or a trajectory's first
+// solve, replayed from one graph: the drift, the solve's start and K status chunks, K from the
+// last solve's iterations with a margin of a tenth and one chunk, rounded up to an even count
+// (finished units make the spare chunks' kernels return after reading their record).  The host then reads the records once and
+// finishes the solve with further chunks if K did not suffice.  Graphs are cached by shape.
+template <typename R, class Geo>
+static int solve_step_graph(hmc_ctx* c, const Launch<Geo>& lc, int n, double* phi, const double* drift_pi,
+                            double eps, const double2* b, double2* x, hipStream_t s) {
+    const bool mixed = sizeof(R) == sizeof(float);
+    const int chunk = mixed ? c->p.reliable_every : kCheckEvery;
+    const int ru_filter = mixed ? (F_ACTIVE | F_CONV_ITER | F_MAXIT) : (F_CONV_ITER | F_MAXIT);
+    int K = (int(1.1 * c->sg_last_iters) + 2 * chunk - 1) / chunk;
+    K = std::min((K + 1) / 2 * 2, c->p.cg_maxit / chunk + 2);
+    const auto key = std::make_tuple(K, drift_pi ? 1 : 0, (const void*)phi, (const void*)drift_pi, (const void*)b,
+                                     (const void*)x, n, c->generation, lc.pc ? 1 : 0, mixed ? 1 : 0, eps,
+                                     c->nunits);
+    hmc_ctx::StepGraph* g = nullptr;
+    for (auto& e : c->sgs)
+        if (e.key == key) g = &e;
+    if (g == nullptr) {
+        if (c->sgs.size() >= 8) {
+            (void)hipGraphExecDestroy(c->sgs.front().exec);
+            c->sgs.erase(c->sgs.begin());
+        }
+        if (c->cap_stream == nullptr) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        int rc = HMC_OK;
+        if (drift_pi) {
+            hipLaunchKernelGGL(k_drift, dim3(elem_grid(3LL * c->phi_sites)), dim3(kBlock), 0, c->cap_stream, phi,
+                               drift_pi, eps, int(3 * c->phi_sites));
+            if (hipGetLastError() != hipSuccess) rc = HMC_ERR_HIP;
+        }
+        if (rc == HMC_OK) rc = cg_prologue<R, Geo>(c, lc, phi, b, x, c->cap_stream);
+        for (int k = 0; k < K && rc == HMC_OK; ++k)
+            rc = enqueue_chunk<R, Geo>(c, lc, n, phi, b, x, chunk, ru_filter, k == 0, false, 0, c->cap_stream);
+        const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(HMC_ERR_HIP, "step graph capture failed: %s", hipGetErrorString(e));
+        hmc_ctx::StepGraph sg;
+        sg.key = key;
+        sg.seq_after = c->seq;
+        const hipError_t ei = hipGraphInstantiate(&sg.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(HMC_ERR_HIP, "step graph instantiate failed: %s", hipGetErrorString(ei));
+        c->sgs.push_back(sg);
+        g = &c->sgs.back();
+    }
+    HIPCHK(hipGraphLaunch(g->exec, s));
+    c->seq = g->seq_after;
+    c->next_nparts = 0;
+    return cg_run<R, Geo>(c, lc, n, phi, b, x, s, K);
 }
 
 static double true_resid_of(const CgState& h) { return h.bb > 0.0 ? std::sqrt(h.rr_true / h.bb) : 0.0; }
@@ -1056,22 +1151,43 @@ static void fill_cg_stats(const hmc_ctx* c, int n, int status, hmc_cg_stats* sta
     }
 }
 
-// One lattice, n right-hand sides.
-static int cg_dispatch(hmc_ctx* c, const double* phi, const double2* b, double2* x, int n,
-                       hmc_cg_stats* stats, hipStream_t s) {
+static int drift(hmc_ctx* c, double* phi, const double* pi, double eps, hipStream_t s);
+
+// The drift phi += eps pi (pi non-null) and a solve: from a step graph when they are enabled,
+// the metric is the identity and an earlier solve sized the graph; else launched one by one.
+template <typename R, class Geo>
+static int drift_solve(hmc_ctx* c, const Launch<Geo>& lc, int n, double* phi, const double* pi, double eps,
+                       const double2* b, double2* x, hipStream_t s) {
+    if (c->step_graphs && c->sigma == nullptr && c->sg_last_iters > 0)
+        return solve_step_graph<R, Geo>(c, lc, n, phi, pi, eps, b, x, s);
+    if (pi) {
+        int rc = drift(c, phi, pi, eps, s);
+        if (rc) return rc;
+    }
+    return cg_run<R, Geo>(c, lc, n, phi, b, x, s);
+}
+
+// One lattice, n right-hand sides; with pi, the drift phi += eps pi first (phi is written
+// only then).
+static int cg_dispatch(hmc_ctx* c, const double* phi, const double2* b, double2* x, int n, hmc_cg_stats* stats,
+                       hipStream_t s, const double* pi = nullptr, double eps = 0.0) {
     int rc;
+    double* pw = const_cast<double*>(phi);
     if (c->p.precision == HMC_MIXED)
-        rc = cg_run<float>(c, launch_one<float>(c, n), n, phi, b, x, s);
+        rc = drift_solve<float>(c, launch_one<float>(c, n), n, pw, pi, eps, b, x, s);
     else
-        rc = cg_run<double>(c, launch_one<double>(c, n), n, phi, b, x, s);
+        rc = drift_solve<double>(c, launch_one<double>(c, n), n, pw, pi, eps, b, x, s);
     if (rc == HMC_OK || rc == HMC_ERR_NOT_CONVERGED || rc == HMC_ERR_NONFINITE) fill_cg_stats(c, n, rc, stats);
     return rc;
 }
 
 // A batch: every (lattice, right-hand side) unit.
-static int cg_dispatch_batch(hmc_ctx* c, const double* phi, const double2* b, double2* x, hipStream_t s) {
-    if (c->p.precision == HMC_MIXED) return cg_run<float>(c, launch_batch<float>(c), c->nunits, phi, b, x, s);
-    return cg_run<double>(c, launch_batch<double>(c), c->nunits, phi, b, x, s);
+static int cg_dispatch_batch(hmc_ctx* c, const double* phi, const double2* b, double2* x, hipStream_t s,
+                             const double* pi = nullptr, double eps = 0.0) {
+    double* pw = const_cast<double*>(phi);
+    if (c->p.precision == HMC_MIXED)
+        return drift_solve<float>(c, launch_batch<float>(c), c->nunits, pw, pi, eps, b, x, s);
+    return drift_solve<double>(c, launch_batch<double>(c), c->nunits, pw, pi, eps, b, x, s);
 }
 
 static void merge_stats(hmc_traj_stats* t, const hmc_cg_stats& cs) {
@@ -1233,10 +1349,11 @@ static int md_integrate(hmc_ctx* c, double* phi, double* pi, const double2* chi,
     const double eps = c->p.eps, h = 0.5 * eps;
     const int nl = c->p.n_leap;
     const int flags = HMC_FORCE_BOSON | (n_pf > 0 ? HMC_FORCE_PF : 0);
-    auto solve = [&]() -> int {
-        if (n_pf == 0) return HMC_OK;
+    // with dpi: the drift phi += eps dpi, then the solve
+    auto solve = [&](const double* dpi) -> int {
+        if (n_pf == 0) return dpi ? drift(c, phi, dpi, eps, s) : HMC_OK;
         if (c->is_batch) {
-            const int r = cg_dispatch_batch(c, phi, chi, c->xsol, s);
+            const int r = cg_dispatch_batch(c, phi, chi, c->xsol, s, dpi, eps);
             if (r == HMC_OK || r == HMC_ERR_NOT_CONVERGED || r == HMC_ERR_NONFINITE) {
                 stats->cg_solves += 1;
                 for (int j = 0; j < c->nunits; ++j) {
@@ -1248,11 +1365,11 @@ static int md_integrate(hmc_ctx* c, double* phi, double* pi, const double2* chi,
             return r;
         }
         hmc_cg_stats cs;
-        const int r = cg_dispatch(c, phi, chi, c->xsol, n_pf, &cs, s);
+        const int r = cg_dispatch(c, phi, chi, c->xsol, n_pf, &cs, s, dpi, eps);
         if (r == HMC_OK || r == HMC_ERR_NOT_CONVERGED || r == HMC_ERR_NONFINITE) merge_stats(stats, cs);
         return r;
     };
-    int rc = solve();
+    int rc = solve(nullptr);
     if (rc) return rc;
     if (first_action && n_pf > 0) {
         rc = dot_re(c, chi, c->xsol, n_pf, SL_SPF0, s);
@@ -1262,9 +1379,7 @@ static int md_integrate(hmc_ctx* c, double* phi, double* pi, const double2* chi,
     rc = launch_force(c, phi, c->xsol, n_pf, flags, nullptr, pi, h, nl > 0 ? 1 : 0, s);
     if (rc) return rc;
     for (int step = 0; step < nl; ++step) {
-        rc = drift(c, phi, pi, eps, s);
-        if (rc) return rc;
-        rc = solve();
+        rc = solve(pi);
         if (rc) return rc;
         // closing half kick of this step, then the opening half kick of the next one
         rc = launch_force(c, phi, c->xsol, n_pf, flags, nullptr, pi, h, step + 1 < nl ? 2 : 1, s);
@@ -1458,6 +1573,9 @@ static void destroy_common(hmc_ctx* c) {
     for (int p = 0; p < 2; ++p)
         for (int g = 0; g < 2; ++g)
             if (c->cgg[p].exec[g]) (void)hipGraphExecDestroy(c->cgg[p].exec[g]);
+    for (auto& g : c->sgs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    c->sgs.clear();
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->h_st) (void)hipHostFree(c->h_st);
     if (c->h_slots) (void)hipHostFree(c->h_slots);
@@ -2207,6 +2325,12 @@ int hmc_set_graphs(hmc_ctx* c, int enable) {
     return HMC_OK;
 }
 
+int hmc_set_step_graphs(hmc_ctx* c, int enable) {
+    if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
+    c->step_graphs = enable != 0;
+    return HMC_OK;
+}
+
 int hmc_set_cg_workgroups(hmc_ctx* c, int precision, int max_per_rhs) {
     if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
     if (precision != HMC_FP64 && precision != HMC_MIXED && precision != -1)
@@ -2422,11 +2546,9 @@ int hmc_force(hmc_ctx* c, const double* phi, const void* chi, int n_pf, double* 
     if ((flags & HMC_FORCE_PF) && S_pf) {
         rc2 = dot_re(c, static_cast<const double2*>(chi), c->xsol, n_pf, SL_TMP, s);
         if (rc2) return rc2;
-        rc2 = read_slots(c, s);
-        if (rc2) return rc2;
-        *S_pf = c->h_slots[SL_TMP];
+        HIPCHK(hipMemcpyAsync(S_pf, c->slots + SL_TMP, sizeof(double), hipMemcpyDeviceToDevice, s));
     } else if (S_pf) {
-        *S_pf = 0.0;
+        HIPCHK(hipMemsetAsync(S_pf, 0, sizeof(double), s));
     }
     return rc;
 }
@@ -2799,6 +2921,12 @@ int hmc_batch_get_cg_workgroups(const hmc_batch* hb, int precision) {
 int hmc_batch_set_graphs(hmc_batch* hb, int enable) {
     if (hb == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL batch");
     hb->c.graphs = enable != 0;
+    return HMC_OK;
+}
+
+int hmc_batch_set_step_graphs(hmc_batch* hb, int enable) {
+    if (hb == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL batch");
+    hb->c.step_graphs = enable != 0;
     return HMC_OK;
 }
 

@@ -128,6 +128,11 @@ class HMC:
         """Replay the CG status chunks from HIP graphs (see hmc_set_graphs)."""
         check(self.lib.hmc_set_graphs(self._ctx, 1 if enable else 0), "hmc_set_graphs")
 
+    def set_step_graphs(self, enable=True):
+        """Replay each leapfrog step's drift and solve from one HIP graph (see
+        hmc_set_step_graphs)."""
+        check(self.lib.hmc_set_step_graphs(self._ctx, 1 if enable else 0), "hmc_set_step_graphs")
+
     def set_cg_workgroups(self, n, precision=None):
         """Workgroups per right-hand side of the CG kernels ("fp64", "mixed" or both);
         returns {precision: count in use}."""
@@ -339,11 +344,11 @@ class HMC:
         if flags & HMC_FORCE_PF:
             chi, n = self._spinors(chi)
         F = torch.empty_like(phi)
-        S = ctypes.c_double(0.0)
+        S = torch.empty(1, dtype=torch.float64, device=self.device)     # device scalar
         st = HmcCgStats()
         self._call("hmc_force", _ptr(phi), _ptr(chi) if chi is not None else None, n, _ptr(F),
-                   ctypes.byref(S), flags, ctypes.byref(st), _stream())
-        return F, S.value, _cg_stats(st, n)
+                   _ptr(S), flags, ctypes.byref(st), _stream())
+        return F, S.item(), _cg_stats(st, n)
 
     def force_from_solution(self, phi, x, flags=HMC_FORCE_PF):
         self._phi(phi)
@@ -523,6 +528,9 @@ class Batch:
     # ---------------------------------------------------------------- controls
     def set_graphs(self, enable=True):
         self._call("hmc_batch_set_graphs", 1 if enable else 0)
+
+    def set_step_graphs(self, enable=True):
+        self._call("hmc_batch_set_step_graphs", 1 if enable else 0)
 
     def set_cg_workgroups(self, n, precision=None):
         pr = {None: -1, "fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]
