@@ -642,6 +642,11 @@ struct Launch {
     MarchPlan cgm{};
     int cgm_threads = 0, cgm_per_unit = 0;
     size_t cgm_lds = 0;
+    // the FP64 stencils of the reliable update as marches (with the FP64 march shape, whenever
+    // step A marches): plan, threads, LDS and workgroups per unit (0: the tile kernels)
+    MarchPlan rum{};
+    int rum_threads = 0, rum_per_unit = 0;
+    size_t rum_lds = 0;
 };
 
 template <typename R>
@@ -679,6 +684,22 @@ static Launch<GeoOne> launch_one(const hmc_ctx* c, int n) {
             if (l.cgm_per_unit > c->pstride) l.cgm_per_unit = 0;   // partial slots: keep the tile kernels
             l.cgm_threads = ((std::min(rows, c->L) + 2) * per_row + 63) / 64 * 64;
             l.cgm_lds = lds;
+        }
+    }
+    // the reliable update's FP64 marches: one thread per element of the band and its two
+    // neighbour rows, as the FP64 step-A march
+    if (l.cgm_per_unit > 0 && c->cgm_rows[0] > 0) {
+        const int rows = std::max(1, std::min(c->cgm_rows[0], kMarchCgThreads / c->L - 2));
+        const size_t lds = march_cg_lds<double>(rows, c->L);
+        if ((rows + 2) * c->L <= kMarchCgThreads && lds <= (size_t(64) << 10)) {
+            const int nband = (c->L + std::min(rows, c->L) - 1) / std::min(rows, c->L);
+            int seg = c->cgm_seg[0];
+            if (seg <= 0) seg = std::max(2, (c->Lt * nband * n + 255) / 256);
+            l.rum = make_march_plan(c->L, c->Lt, rows, seg);
+            l.rum_per_unit = l.rum.nband * l.rum.nseg;
+            if (l.rum_per_unit > c->pstride) l.rum_per_unit = 0;
+            l.rum_threads = ((std::min(rows, c->L) + 2) * c->L + 63) / 64 * 64;
+            l.rum_lds = lds;
         }
     }
     return l;
@@ -890,12 +911,31 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
     hipLaunchKernelGGL((k_ru_fold<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, lc.pc ? PEND_NONE : PEND_RR),
                        geo, x, v, filter);
     LAUNCHCHK();
-    HMC_LAUNCH_NN2(lc.nn2, (k_ru_apply<Geo, true>), (k_ru_apply<Geo, false>), dim3(grid), dim3(kBlock), 0, s,
-                   next_ctl(c, PEND_NONE), geo, x, c->t64, phi64, c->cf64, filter);
-    LAUNCHCHK();
-    HMC_LAUNCH_NN2(lc.nn2, (k_ru_resid<R, Geo, true>), (k_ru_resid<R, Geo, false>), dim3(grid), dim3(kBlock), 0,
-                   s, next_ctl(c, PEND_NONE), geo, b, c->t64, phi64, c->cf64, v.r, filter);
-    LAUNCHCHK();
+    bool ru_march = false;
+    if constexpr (std::is_same<Geo, GeoOne>::value) {
+        if (lc.rum_per_unit > 0) {
+            // t64 = M x64 and r = b - M^dagger t64 as marches; the record after them reduces
+            // the march's partials
+            ru_march = true;
+            const int g = lc.rum_per_unit * n;
+            hipLaunchKernelGGL(k_ru_apply_march, dim3(g), dim3(lc.rum_threads), lc.rum_lds, s, next_ctl(c, PEND_NONE),
+                               geo.lat, lc.rum, geo.bpr, c->pstride, x, c->t64, phi64, c->cf64, filter);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_ru_resid_march<R>, dim3(g), dim3(lc.rum_threads), lc.rum_lds, s,
+                               next_ctl(c, PEND_NONE), geo.lat, lc.rum, geo.bpr, c->pstride, b, c->t64, phi64,
+                               c->cf64, v.r, filter);
+            LAUNCHCHK();
+            c->next_nparts = lc.rum_per_unit;
+        }
+    }
+    if (!ru_march) {
+        HMC_LAUNCH_NN2(lc.nn2, (k_ru_apply<Geo, true>), (k_ru_apply<Geo, false>), dim3(grid), dim3(kBlock), 0, s,
+                       next_ctl(c, PEND_NONE), geo, x, c->t64, phi64, c->cf64, filter);
+        LAUNCHCHK();
+        HMC_LAUNCH_NN2(lc.nn2, (k_ru_resid<R, Geo, true>), (k_ru_resid<R, Geo, false>), dim3(grid), dim3(kBlock), 0,
+                       s, next_ctl(c, PEND_NONE), geo, b, c->t64, phi64, c->cf64, v.r, filter);
+        LAUNCHCHK();
+    }
     if (lc.pc) {
         int rc = enqueue_pc<R, Geo>(c, lc, v, PEND_RU, s);
         if (rc) return rc;

@@ -529,6 +529,186 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, Lat l
 }
 
 // ------------------------------------------------------------------------------------
+// The FP64 reliable update of the conjugate-gradient solve (after the elementwise fold of the
+// pending step into x64) as two marches with the FP64 step-A march's cut and thread layout:
+// t64 = M x64, then r = b - M^dagger t64 with the FP64 partial |r|^2.  They replace the two
+// FP64 tile stencils, which read their inputs again from L2 for every neighbour.
+
+// t64 = M x64 for the units in `filter` (Eq. 17): each slice, x64(tau + 1) on the band's rows
+// and the rows beside it goes to LDS while M at tau is formed from the previous slice's copy,
+// the time link taken from the thread's own element of tau + 1.  Reads x64 and phi once (plus
+// the rows beside each band and one slice per segment), writes t64 once.
+__global__ __launch_bounds__(kMarchCgThreads) void k_ru_apply_march(CgCtl ctl, Lat lat, MarchPlan mp, int nparts_in,
+                                                                    int pstride, const double2* __restrict__ x64,
+                                                                    double2* __restrict__ t64,
+                                                                    const double* __restrict__ phi, Coef<double> cf,
+                                                                    int filter) {
+    extern __shared__ __align__(16) unsigned char march_smem[];
+    const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, rowc = 4 * L;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x), per_vec = mp.nseg * mp.nband;
+    const MarchPos mpos = march_pos(lat, mp, wg);
+    const UPos pos = march_unit(lat, mpos.k, wg - mpos.k * per_vec, nparts_in, pstride);
+    cg_finalize(ctl, pos, nparts_in);
+    const int mode = cg_shared().mode;
+    cg_publish(ctl, pos);
+    if (!((1 << mode) & filter)) return;
+    const size_t off = pos.voff;
+    const double2* xin = x64 + off;
+    double2* t = t64 + off;
+    double2* cur = reinterpret_cast<double2*>(march_smem);
+    double2* nxt = cur + size_t(mp.R + 2) * rowc;
+    const int e = threadIdx.x, nh = (mpos.nr + 2) * L;
+    const bool act = e < nh;
+    const int lr = act ? e / L : 0, y = act ? e - lr * L : 0;
+    const int xrow = wrap_row(mpos.x0 - 1 + lr, L);
+    const bool inner = act && lr >= 1 && lr <= mpos.nr;
+    const int ro = xrow * L + y;
+    double2 rv[4];
+    double f1 = 0.0, f2 = 0.0, f3 = 0.0;
+    auto load_slab = [&](int tq) {
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rv[c] = xin[size_t(c) * vol + size_t(tq) * LL + ro];
+        }
+    };
+    auto load_phi = [&](int tq) {
+        if (inner) {
+            const size_t i = size_t(tq) * LL + ro;
+            f1 = phi[i];
+            f2 = phi[vol + i];
+            f3 = phi[2 * vol + i];
+        }
+    };
+    auto place = [&](double2* buf, double2 (&v)[4]) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = rv[c];
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) buf[lr * rowc + c * L + y] = v[c];
+        }
+    };
+    const int t0 = mpos.t0, t1 = mpos.t1;
+    double2 v0[4];
+    load_slab(t0);
+    place(cur, v0);
+    load_slab(t0 + 1 == Lt ? 0 : t0 + 1);
+    load_phi(t0);
+    for (int tau = t0; tau < t1; ++tau) {
+        const int tn = tau + 1 == Lt ? 0 : tau + 1;
+        double2 vn[4];
+        place(nxt, vn);
+        const double g1 = f1, g2 = f2, g3 = f3;
+        if (tau + 1 < t1) {
+            load_slab(tn + 1 == Lt ? 0 : tn + 1);
+            load_phi(tn);
+        }
+        __syncthreads();
+        if (inner) {
+            double2 o[4], cen[4];
+            stencil_site_lds(cur, lr, xrow, y, L, g1, g2, g3, cf, tau == Lt - 1 ? -1.0 : 1.0, vn, o, cen);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) t[size_t(c) * vol + size_t(tau) * LL + ro] = o[c];
+        }
+        __syncthreads();
+        double2* sw = cur;
+        cur = nxt;
+        nxt = sw;
+    }
+}
+
+// r = b - M^dagger t64 in FP64, stored in the Krylov precision, with the FP64 partial |r|^2
+// (PEND_RU, one per workgroup) for the units in `filter`.  M^dagger needs t64(tau - 1) only at
+// the site itself: each slice's own element is kept in registers for the next.  LDS holds
+// t64(tau) on the band's rows and the rows beside it, alternating between two buffers so that
+// one barrier per slice suffices; the next slice's loads are in flight meanwhile.
+template <typename R>
+__global__ __launch_bounds__(kMarchCgThreads) void k_ru_resid_march(CgCtl ctl, Lat lat, MarchPlan mp, int nparts_in,
+                                                                    int pstride, const double2* __restrict__ b,
+                                                                    const double2* __restrict__ t64,
+                                                                    const double* __restrict__ phi, Coef<double> cf,
+                                                                    C2<R>* __restrict__ r, int filter) {
+    extern __shared__ __align__(16) unsigned char march_smem[];
+    const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, rowc = 4 * L;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x), per_vec = mp.nseg * mp.nband;
+    const MarchPos mpos = march_pos(lat, mp, wg);
+    const UPos pos = march_unit(lat, mpos.k, wg - mpos.k * per_vec, nparts_in, pstride);
+    cg_finalize(ctl, pos, nparts_in);
+    if (!((1 << cg_shared().mode) & filter)) {
+        cg_publish(ctl, pos);
+        return;
+    }
+    const size_t off = pos.voff;
+    const double2* tin = t64 + off;
+    const double2* bb = b + off;
+    C2<R>* rr = r + off;
+    double2* buf0 = reinterpret_cast<double2*>(march_smem);
+    double2* buf1 = buf0 + size_t(mp.R + 2) * rowc;
+    const int e = threadIdx.x, nh = (mpos.nr + 2) * L;
+    const bool act = e < nh;
+    const int lr = act ? e / L : 0, y = act ? e - lr * L : 0;
+    const int xrow = wrap_row(mpos.x0 - 1 + lr, L);
+    const bool inner = act && lr >= 1 && lr <= mpos.nr;
+    const int ro = xrow * L + y;
+    double2 rv[4], bv[4], prev[4];
+    double f1 = 0.0, f2 = 0.0, f3 = 0.0;
+    auto load_slab = [&](int tq) {
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rv[c] = tin[size_t(c) * vol + size_t(tq) * LL + ro];
+        }
+    };
+    auto load_site = [&](int tq) {
+        if (inner) {
+            const size_t i = size_t(tq) * LL + ro;
+            f1 = phi[i];
+            f2 = phi[vol + i];
+            f3 = phi[2 * vol + i];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) bv[c] = bb[size_t(c) * vol + i];
+        }
+    };
+    const int t0 = mpos.t0, t1 = mpos.t1;
+    if (inner) {
+        const int tp = t0 == 0 ? Lt - 1 : t0 - 1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) prev[c] = tin[size_t(c) * vol + size_t(tp) * LL + ro];
+    }
+    load_slab(t0);
+    load_site(t0);
+    double part = 0.0;
+    for (int tau = t0; tau < t1; ++tau) {
+        double2* cur = (tau - t0) & 1 ? buf1 : buf0;
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cur[lr * rowc + c * L + y] = rv[c];
+        }
+        const double g1 = f1, g2 = f2, g3 = f3;
+        double2 bt[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bt[c] = bv[c];
+        if (tau + 1 < t1) {
+            load_slab(tau + 1);
+            load_site(tau + 1);
+        }
+        __syncthreads();
+        if (inner) {
+            double2 o[4], cen[4];
+            stencil_site_lds(cur, lr, xrow, y, L, g1, g2, g3, cf, tau == 0 ? -1.0 : 1.0, prev, o, cen);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double2 d = sub<double>(bt[c], o[c]);
+                part += norm2<double>(d);
+                rr[size_t(c) * vol + size_t(tau) * LL + ro] = mk<R>(R(d.x), R(d.y));
+                prev[c] = cen[c];
+            }
+        }
+    }
+    store_partial(ctl, PEND_RU, pos, part);
+    if (threadIdx.x == 0) cg_shared().pending = PEND_RU;
+    cg_publish(ctl, pos);
+}
+
+// ------------------------------------------------------------------------------------
 // M^dagger M in one pass as a march with the loads one slice ahead (the structure of the CG
 // step-A march): a workgroup owns a band of R rows of one vector and the two rows on either
 // side of it, and walks a segment of slices.  psi of two consecutive slices sits in LDS on the
