@@ -1894,7 +1894,7 @@ static int launch_mdm(hmc_ctx* c, const R* phi, const void* in, void* out, int n
     if (grid >= (1LL << 31)) return fail(HMC_ERR_INVALID_ARG, "too many vectors");
     if (m.threads > (m.tile ? kMarchMaxThreads : kMdmMarchThreads) || m.lds > (size_t(160) << 10))
         return fail(HMC_ERR_INVALID_ARG, "one-pass M^dagger M: no launch shape fits this lattice");
-    const bool narrow = m.threads <= kMarchMaxThreads;
+    const bool narrow = m.threads <= kMarchMaxThreads, mid = m.threads <= kMdmMidThreads;
     if constexpr (sizeof(R) == sizeof(float)) {
         const float2* a = static_cast<const float2*>(in);
         float2* b = static_cast<float2*>(out);
@@ -1903,6 +1903,9 @@ static int launch_mdm(hmc_ctx* c, const R* phi, const void* in, void* out, int n
                                c->cf32);
         else if (narrow)
             hipLaunchKernelGGL(k_mdm2_march<kMarchMaxThreads>, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat,
+                               m.plan, a, b, phi, c->cf32);
+        else if (mid)
+            hipLaunchKernelGGL(k_mdm2_march<kMdmMidThreads>, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat,
                                m.plan, a, b, phi, c->cf32);
         else
             hipLaunchKernelGGL(k_mdm2_march<kMdmMarchThreads>, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat,
@@ -1915,6 +1918,9 @@ static int launch_mdm(hmc_ctx* c, const R* phi, const void* in, void* out, int n
                                c->cf64);
         else if (narrow)
             hipLaunchKernelGGL(k_mdm_march<kMarchMaxThreads>, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat,
+                               m.plan, a, b, phi, c->cf64);
+        else if (mid)
+            hipLaunchKernelGGL(k_mdm_march<kMdmMidThreads>, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat,
                                m.plan, a, b, phi, c->cf64);
         else
             hipLaunchKernelGGL(k_mdm_march<kMdmMarchThreads>, dim3(int(grid)), dim3(m.threads), m.lds, s, c->lat,
@@ -2212,8 +2218,10 @@ int hmc_create(int L, int Lt, double dtau, const hmc_params* params, hmc_ctx** o
     (void)set_cg_shape(c, HMC_MIXED, kDefaultBpr32);
     // the one-pass M^dagger M march holds two slices of psi and one of chi in LDS (above 64 KB)
     for (const void* k : {reinterpret_cast<const void*>(&k_mdm2_march<kMarchMaxThreads>),
+                          reinterpret_cast<const void*>(&k_mdm2_march<kMdmMidThreads>),
                           reinterpret_cast<const void*>(&k_mdm2_march<kMdmMarchThreads>),
                           reinterpret_cast<const void*>(&k_mdm_march<kMarchMaxThreads>),
+                          reinterpret_cast<const void*>(&k_mdm_march<kMdmMidThreads>),
                           reinterpret_cast<const void*>(&k_mdm_march<kMdmMarchThreads>)})
         (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 << 10);
     (void)hipGetLastError();

@@ -649,7 +649,10 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_ru_resid_march(CgCtl ctl, L
     const int xrow = wrap_row(mpos.x0 - 1 + lr, L);
     const bool inner = act && lr >= 1 && lr <= mpos.nr;
     const int ro = xrow * L + y;
+    // defined on every thread (a conditionally loaded array would be kept in scratch memory)
     double2 rv[4], bv[4], prev[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rv[c] = bv[c] = prev[c] = make_double2(0.0, 0.0);
     double f1 = 0.0, f2 = 0.0, f3 = 0.0;
     auto load_slab = [&](int tq) {
         if (act) {
@@ -720,8 +723,10 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_ru_resid_march(CgCtl ctl, L
 // the rows beside each band, which its neighbours read too, and one slice per segment), the
 // result written once.
 // Most threads of a one-pass M^dagger M march workgroup (one per element of its rows).  The
-// kernels are instantiated for at most 512 threads (up to 256 VGPRs each) and for 1024 (128
-// VGPRs, a few spilled): narrow bands take the first, wide ones the second.
+// kernels are instantiated for at most 512 threads (up to 256 VGPRs each), 768 (168 VGPRs,
+// enough for both precisions) and 1024 (128 VGPRs, a few spilled): a band takes the smallest
+// that holds it.
+constexpr int kMdmMidThreads = 768;
 constexpr int kMdmMarchThreads = 1024;
 
 template <typename R>
