@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--apply-reps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default CG launch shapes")
-    ap.add_argument("--pcg-steps", type=int, default=1,
+    ap.add_argument("--pcg-steps", type=int, default=3,
                     help="timed Fourier-preconditioned mixed trajectories (0: solves only)")
     ap.add_argument("--batch-steps", type=int, default=1,
                     help="timed trajectories of the 64-chain batched workload (0 skips it)")
