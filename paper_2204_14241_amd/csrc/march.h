@@ -1,6 +1,6 @@
 // march.h -- kernels that walk a band of lattice rows through consecutive time slices, holding
 // the reuse along tau on chip: the normal operator M^dagger M of Eq. (22) in one pass over HBM,
-// and step A of the conjugate-gradient iteration.
+// step A of the conjugate-gradient iteration, and the FP64 stencils of its reliable update.
 //
 // With chi = M psi (Eq. 17):  (M^dagger M psi)(tau) = A_tau chi(tau) + s_{tau-1} chi(tau - 1),
 // where A_tau is the time-local part of M (diagonal, hopping, Yukawa coupling to phi(tau)) and
