@@ -35,9 +35,13 @@ HBM_PEAK_GBS = 8000.0
 # numbers per site (64 B in FP64, 32 B in FP32); phi is 3 reals (24 B / 12 B), read once per
 # launch however many right-hand sides the launch covers.
 KERNEL_STREAMS = {
-    # t = M p_new with p_new = r + beta p_old, x += alpha p_old: reads r, p_old, x, phi;
-    # writes p_new, t, x
-    "cg_a": (6, 1),
+    # step A, t = M p_new with p_new = r + beta p_old, alternates between two kinds of launch:
+    # one defers the solution update (reads r, p_old, phi; writes p_new, t), the next adds both
+    # pending steps to x (also reads x and the older direction, writes x); per launch on average
+    # 5.5 spinor streams
+    "cg_a": (5.5, 1),
+    "cg_a_defer": (4, 1),
+    "cg_a_fold": (7, 1),
     # r -= alpha M^dagger t: reads t, r, phi; writes r
     "cg_b": (3, 1),
     # one M or M^dagger apply: reads psi, phi; writes psi
@@ -52,7 +56,7 @@ def launch_bytes(name, vol, nrhs=1):
     right-hand sides of a vol-site lattice."""
     kern, prec = name.rsplit("_", 1)
     ns, nphi = KERNEL_STREAMS[kern]
-    return vol * (nrhs * ns * SPINOR_BYTES[prec] + nphi * PHI_BYTES[prec])
+    return int(vol * (nrhs * ns * SPINOR_BYTES[prec] + nphi * PHI_BYTES[prec]))
 
 
 # per site of one right-hand side
@@ -234,7 +238,7 @@ def profile_shapes(args):
             h.set_kernel_timing(True)
             solve()
             torch.cuda.synchronize()
-            kt = h.kernel_times()
+            kt = merge_step_a(h.kernel_times())
             h.set_kernel_timing(False)
             out[f"{prec}_{bpr}"] = {"cg_a_us": 1e3 * kt["cg_a_" + suf][0], "cg_b_us": 1e3 * kt["cg_b_" + suf][0]}
             log(f"{prec} {bpr} workgroups: step A {1e3 * kt['cg_a_' + suf][0]:.1f} us, "
@@ -294,6 +298,20 @@ def measured_traffic(kname):
     return None if t is None else t["read_bytes"] + t["write_bytes"]
 
 
+def merge_step_a(kt):
+    """Step A updates the solution every second iteration, so its launches alternate between two
+    kinds; the library samples one of each ("cg_a_*" and "cg_a_next_*", consecutive
+    iterations).  Returns the kernel times with "cg_a_*" the mean over both samples, the
+    average launch whose algorithmic bytes are BYTES_PER_SITE["cg_a_*"] (None without a sample
+    of each kind)."""
+    out = dict(kt)
+    for p in ("f32", "f64"):
+        (m0, n0), (m1, n1) = kt[f"cg_a_{p}"], kt[f"cg_a_next_{p}"]
+        out[f"cg_a_first_{p}"] = (m0, n0)
+        out[f"cg_a_{p}"] = ((m0 * n0 + m1 * n1) / (n0 + n1), n0 + n1) if n0 and n1 else (None, 0)
+    return out
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -334,7 +352,7 @@ def prod_bench(hmcmod, torch, L, Lt, common, phi0, d_traj):
         _, st = h.cg_solve(phi, chi)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        kt = h.kernel_times()
+        kt = merge_step_a(h.kernel_times())
         rec = {"ms": 1e3 * el, "iterations": st.iterations[0], "true_resid": st.true_resid[0]}
         for name in ("cg_a_f32", "cg_b_f32"):
             ms, n = kt[name]
@@ -378,7 +396,7 @@ def fp64_configs_bench(hmcmod, torch, seed, cpu):
             _, st = h.cg_solve(phi, chi)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
-            kt = h.kernel_times()
+            kt = merge_step_a(h.kernel_times())
             h.set_kernel_timing(False)
             its = sum(st.iterations)
             rec["cg_solve"] = {"ms": 1e3 * el, "iterations": list(st.iterations),
@@ -738,7 +756,7 @@ def pcg_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, warmup, steps):
         out["cg_iterations_per_traj_mixed_pcg"] = its / steps
         # live per-kernel samples of the preconditioned iteration (HIP events on the kernels'
         # own dispatches); each preconditioner pass reads and writes one FP32 spinor
-        kt = h.kernel_times()
+        kt = merge_step_a(h.kernel_times())
         vol = Lt * L * L
         passes = {}
         for name, bps in (("cg_a_f32", BYTES_PER_SITE["cg_a_f32"]), ("cg_b_f32", BYTES_PER_SITE["cg_b_f32"]),
@@ -834,7 +852,7 @@ def mall_controlled_bench(hmcmod, torch, L, Lt, phi0, seed, nrhs=4):
     _, st = h.cg_solve(phi, chi)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    kt = h.kernel_times()
+    kt = merge_step_a(h.kernel_times())
     ws = vol * (5 * nrhs * SPINOR_BYTES["f32"] + PHI_BYTES["f32"])
     rec = {"rhs": nrhs, "working_set_bytes": ws, "solve_s": el, "iterations": list(st.iterations),
            "max_true_resid": max(st.true_resid), "bpr": h.cg_workgroups()["mixed"], "autotune": tune}
@@ -939,7 +957,7 @@ def main():
                 f"{out[-1]['accepted']} cg iters {out[-1]['cg_iterations']} max resid {out[-1]['max_true_resid']:.2e}")
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        kt = h.kernel_times() if timing else None
+        kt = merge_step_a(h.kernel_times()) if timing else None
         h.close()
         return el, out, kt, phi_at
 
@@ -987,7 +1005,11 @@ def main():
                               "frac": ach / HBM_PEAK_GBS,
                               "traffic": measured_traffic(kname) if args.workload == "large_80x80x200" else None,
                               "kernel": "hmc::" + kname, "avg_ms": ms_dom, "samples": nsamp,
-                              "bytes_per_launch": bytes_launch}
+                              "bytes_per_launch": bytes_launch,
+                              "launch_kinds": {"sampled_ms": [kt["cg_a_first_f32"][0], kt["cg_a_next_f32"][0]],
+                                               "bytes_defer": BYTES_PER_SITE["cg_a_defer_f32"] * vol,
+                                               "bytes_fold": BYTES_PER_SITE["cg_a_fold_f32"] * vol}
+                              if dom == "cg_a_f32" else None}
     extras = {
         "autotune": tuning,
         "traj_per_hour_mixed": 3600.0 * K / el,

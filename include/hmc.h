@@ -352,12 +352,14 @@ int hmc_warmup_iteration(hmc_ctx* ctx, hmc_tuner* t, double* phi_inout, const do
  * own dispatches, hipExtLaunchKernel events, so nothing is inserted between kernels) and
  * adds the two kernel durations to the accumulators below.  Eager launches only (no
  * samples while CG chunks replay from graphs).  Enabling resets them.
- * Index: [0] CG step A (t = M p with the fused x and p updates), FP32 Krylov precision;
+ * Index: [0] CG step A (t = M p with the fused p update), FP32 Krylov precision;
  * [1] CG step B (r -= alpha M^dagger t), FP32; [2] step A, FP64; [3] step B, FP64.
  * With the Fourier preconditioner the three passes of z = P r in the same sampled
  * iteration: [4] forward slice FFT, [5] time-direction pass, [6] inverse slice FFT, FP32;
- * [7], [8], [9] the same in FP64. */
-#define HMC_KT_SLOTS 10
+ * [7], [8], [9] the same in FP64.  [10], [11]: step A of the iteration after the sampled one,
+ * FP32 and FP64 (step A updates the solution every second iteration, so [0] and [10] time
+ * one launch of each kind). */
+#define HMC_KT_SLOTS 12
 typedef struct hmc_kernel_times {
     double ms[HMC_KT_SLOTS];     /* summed durations in milliseconds                      */
     long   count[HMC_KT_SLOTS];  /* number of sampled launches                            */

@@ -146,11 +146,12 @@ class HmcWarmupStats(ctypes.Structure):
 
 
 class HmcKernelTimes(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 10), ("count", ctypes.c_long * 10)]
+    _fields_ = [("ms", ctypes.c_double * 12), ("count", ctypes.c_long * 12)]
 
 
 KT_NAMES = ("cg_a_f32", "cg_b_f32", "cg_a_f64", "cg_b_f64",
-            "pc_xy_fwd_f32", "pc_t_f32", "pc_xy_inv_f32", "pc_xy_fwd_f64", "pc_t_f64", "pc_xy_inv_f64")
+            "pc_xy_fwd_f32", "pc_t_f32", "pc_xy_inv_f32", "pc_xy_fwd_f64", "pc_t_f64", "pc_xy_inv_f64",
+            "cg_a_next_f32", "cg_a_next_f64")
 
 _lib = None
 

@@ -203,7 +203,7 @@ struct hmc_ctx {
     // preconditioner passes, taken by the dispatch of the kernel itself (no marker packets
     // between kernels), one set per status slot
     bool timing = false;
-    static constexpr int kEv = 10;
+    static constexpr int kEv = 12;
     hipEvent_t tev[2][kEv] = {};
     hmc_kernel_times kt{};
 
@@ -841,10 +841,12 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
                 c->next_nparts = lc.cgm_per_unit;
                 const CgCtl kb = next_ctl(c, PEND_TT);
                 const hipEvent_t* e = (sample && i == chunk / 2) ? c->tev[kslot] : nullptr;
+                // the next iteration's step A too (the solution update alternates between them)
+                const hipEvent_t* ea = e ? e : (sample && i == chunk / 2 + 1) ? c->tev[kslot] + 10 : nullptr;
                 const int g = lc.cgm_per_unit * n;
                 if constexpr (sizeof(R) == sizeof(float)) {
-                    if (e) hipExtLaunchKernelGGL(k_cg_a2_march, dim3(g), dim3(lc.cgm_threads), lc.cgm_lds, s, e[0], e[1], 0,
-                                                 ka, geo.lat, lc.cgm, geo.bpr, c->pstride, v, phik, cf);
+                    if (ea) hipExtLaunchKernelGGL(k_cg_a2_march, dim3(g), dim3(lc.cgm_threads), lc.cgm_lds, s, ea[0], ea[1], 0,
+                                                  ka, geo.lat, lc.cgm, geo.bpr, c->pstride, v, phik, cf);
                     else hipLaunchKernelGGL(k_cg_a2_march, dim3(g), dim3(lc.cgm_threads), lc.cgm_lds, s, ka, geo.lat,
                                             lc.cgm, geo.bpr, c->pstride, v, phik, cf);
                     LAUNCHCHK();
@@ -852,8 +854,8 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
                                                  geo, v, phik, cf);
                     else hipLaunchKernelGGL((k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
                 } else {
-                    if (e) hipExtLaunchKernelGGL(k_cg_a_march, dim3(g), dim3(lc.cgm_threads), lc.cgm_lds, s, e[0], e[1], 0,
-                                                 ka, geo.lat, lc.cgm, geo.bpr, c->pstride, v, phik, cf);
+                    if (ea) hipExtLaunchKernelGGL(k_cg_a_march, dim3(g), dim3(lc.cgm_threads), lc.cgm_lds, s, ea[0], ea[1], 0,
+                                                  ka, geo.lat, lc.cgm, geo.bpr, c->pstride, v, phik, cf);
                     else hipLaunchKernelGGL(k_cg_a_march, dim3(g), dim3(lc.cgm_threads), lc.cgm_lds, s, ka, geo.lat,
                                             lc.cgm, geo.bpr, c->pstride, v, phik, cf);
                     LAUNCHCHK();
@@ -885,6 +887,23 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
                 LAUNCHCHK();
                 HMC_EXT_LAUNCH_NN2(lc.nn2, (k_cg_b<R, Geo, true>), (k_cg_b<R, Geo, false>), dim3(grid), dim3(kBlock), 0,
                                    s, e[2], e[3], 0, kb, geo, v, phik, cf);
+            }
+            LAUNCHCHK();
+        } else if (sample && i == chunk / 2 + 1) {
+            // the next iteration's step A (the solution update alternates between them)
+            hipEvent_t* e = c->tev[kslot] + 10;
+            if constexpr (sizeof(R) == sizeof(float)) {
+                HMC_EXT_LAUNCH_NN2(lc.nn2, (k_cg_a2<Geo, true>), (k_cg_a2<Geo, false>), dim3(grid), dim3(kBlock), 0, s,
+                                   e[0], e[1], 0, ka, geo, v, phik, cf);
+                LAUNCHCHK();
+                HMC_LAUNCH_NN2(lc.nn2, (k_cg_b2<Geo, true>), (k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0, s, kb,
+                               geo, v, phik, cf);
+            } else {
+                HMC_EXT_LAUNCH_NN2(lc.nn2, (k_cg_a<R, Geo, true>), (k_cg_a<R, Geo, false>), dim3(grid), dim3(kBlock), 0,
+                                   s, e[0], e[1], 0, ka, geo, v, phik, cf);
+                LAUNCHCHK();
+                HMC_LAUNCH_NN2(lc.nn2, (k_cg_b<R, Geo, true>), (k_cg_b<R, Geo, false>), dim3(grid), dim3(kBlock), 0, s,
+                               kb, geo, v, phik, cf);
             }
             LAUNCHCHK();
         } else {
@@ -1091,6 +1110,12 @@ static int cg_run(hmc_ctx* c, const Launch<Geo>& lc, int n, const double* phi64,
                     const int slot = q < 2 ? kt_a + q : (mixed ? 4 : 7) + q - 2;
                     c->kt.ms[slot] += t;
                     c->kt.count[slot] += 1;
+                }
+                if (chunk / 2 + 1 < chunk) {
+                    float t = 0.f;
+                    HIPCHK(hipEventElapsedTime(&t, ev[10], ev[11]));
+                    c->kt.ms[mixed ? 10 : 11] += t;
+                    c->kt.count[mixed ? 10 : 11] += 1;
                 }
             }
             start_active_prev = all_active;

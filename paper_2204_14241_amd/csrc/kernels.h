@@ -94,6 +94,8 @@ struct CgState {
     double rr;          // current iterated |r|^2
     double rr_prev;     // |r|^2 of the previous iteration
     double alpha;       // step still to be added to x along the current p (pending)
+    double alpha_old;   // step still to be added along the previous p, held in the other
+                        // direction buffer (0: none; step A adds both every second iteration)
     double alpha_cur;   // step of the iteration in flight
     double beta;        // coefficient of the next direction update p <- r + beta p
     double rr_true;     // last FP64 true residual |b - A x|^2
@@ -305,6 +307,7 @@ __device__ __forceinline__ int cg_finalize(const CgCtl& c, const UPos& pos, int 
                     s.rr_true = tot;
                     s.n_ru += 1;
                     s.alpha = 0.0;
+                    s.alpha_old = 0.0;
                     if (!finite(tot)) {
                         s.mode = CG_FAILED;
                     } else if (tot <= s.stop_rr) {
@@ -467,9 +470,12 @@ __device__ __forceinline__ void store_partial(const CgCtl& c, int kind, const UP
     if (threadIdx.x == 0) part_slot(c, kind, p)[p.blk] = a[0];
 }
 
-// CG step A (iteration k):  x += alpha_{k-1} p_{k-1};  p_k = r_k + beta_{k-1} p_{k-1};
-// t = M p_k;  partial |t|^2 = <p_k, M^dagger M p_k>.  p is double-buffered because
-// neighbouring sites read the old direction.
+// CG step A (iteration k):  p_k = r_k + beta_{k-1} p_{k-1};  t = M p_k;  partial |t|^2 =
+// <p_k, M^dagger M p_k>.  p is double-buffered because neighbouring sites read the old
+// direction.  The solution is updated every second iteration: when the previous step A left its
+// step pending (alpha_old), x += alpha_{k-2} p_{k-2} + alpha_{k-1} p_{k-1}, p_{k-2} read from the
+// buffer about to receive p_k; otherwise x is not touched and alpha_{k-1} becomes alpha_old.
+// Per iteration that is 1.5 vector reads and 0.5 writes for x instead of one of each.
 template <typename R, class Geo, bool NN2>
 __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, Geo geo, CgVecs<R> v,
                                                  const R* __restrict__ phi_base, Coef<R> cf) {
@@ -482,7 +488,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, Geo geo, CgVecs<R> v
         cg_publish(ctl, pos);
         return;
     }
-    const R alpha = R(S.alpha), beta = R(S.beta);
+    const R alpha = R(S.alpha), alpha_old = R(S.alpha_old), beta = R(S.beta);
+    const bool fold = S.alpha_old != 0.0;
+    const double defer = S.alpha;
     const int pb = S.pbuf;
     const size_t off = pos.voff;
     const C2<R>* pin = (pb ? v.p1 : v.p0) + off;
@@ -495,6 +503,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, Geo geo, CgVecs<R> v
         const int tile = sp.first;
         const int s = tile * kBlock + threadIdx.x;
         if (s < lat.vol) {
+            if (fold) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int i = c * lat.vol + s;
+                    x[i] = axpy<R>(alpha, pin[i], axpy<R>(alpha_old, pout[i], x[i]));
+                }
+            }
             const Nbr nb = neighbours(lat, s);
             C2<R> o[4], pn[4];
             dslash_site<R, false, NN2>(src, phi, lat, cf, nb, s, o, pn);
@@ -502,7 +517,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, Geo geo, CgVecs<R> v
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int i = c * lat.vol + s;
-                x[i] = axpy<R>(alpha, pin[i], x[i]);
                 pout[i] = pn[c];
                 t[i] = o[c];
                 acc += norm2<R>(o[c]);
@@ -513,6 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgCtl ctl, Geo geo, CgVecs<R> v
     store_partial(ctl, PEND_TT, pos, part);
     if (threadIdx.x == 0) {
         CgState& W = cg_shared();
+        W.alpha_old = fold ? 0.0 : defer;
         W.alpha = 0.0;
         W.pbuf = 1 - pb;
         W.pending = PEND_TT;
@@ -561,8 +576,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(CgCtl ctl, Geo geo, CgVecs<R> v
     cg_publish(ctl, pos);
 }
 
-// Reliable update, part 1 (elementwise): fold the pending step into the FP64 solution,
-// x64 += x_lo + alpha p (mixed) or x64 += alpha p (FP64, where v.x is x64), clear x_lo.
+// Reliable update, part 1 (elementwise): fold the pending steps into the FP64 solution,
+// x64 += alpha_old p_prev + alpha p + x_lo (mixed) or x64 += alpha_old p_prev + alpha p (FP64,
+// where v.x is x64), clear x_lo.
 template <typename R, class Geo>
 __global__ __launch_bounds__(kBlock) void k_ru_fold(CgCtl ctl, Geo geo, double2* __restrict__ x64,
                                                     CgVecs<R> v, int filter) {
@@ -574,10 +590,11 @@ __global__ __launch_bounds__(kBlock) void k_ru_fold(CgCtl ctl, Geo geo, double2*
         cg_publish(ctl, pos);
         return;
     }
-    const double alpha = S.alpha;
+    const double alpha = S.alpha, alpha_old = S.alpha_old;
     const size_t off = pos.voff;
     const C2<R>* p = (S.pbuf ? v.p1 : v.p0) + off;
-    const bool separate = (void*)v.x != (void*)x64;
+    const C2<R>* q = (S.pbuf ? v.p0 : v.p1) + off;   // the previous direction
+    const bool separate = (void*)v.x != (void*)x64, both = alpha_old != 0.0;
     for (TileSpan sp = tile_span(pos.blk, pos.bpr, tiles1(lat)); sp.first < sp.end; sp.first += sp.step) {
         const int tile = sp.first;
         const int s = tile * kBlock + threadIdx.x;
@@ -587,6 +604,11 @@ __global__ __launch_bounds__(kBlock) void k_ru_fold(CgCtl ctl, Geo geo, double2*
             const size_t i = off + size_t(c) * lat.vol + s;
             const C2<R> pc = p[c * lat.vol + s];
             double2 xv = x64[i];
+            if (both) {
+                const C2<R> qc = q[c * lat.vol + s];
+                xv.x += alpha_old * double(qc.x);
+                xv.y += alpha_old * double(qc.y);
+            }
             xv.x += alpha * double(pc.x);
             xv.y += alpha * double(pc.y);
             if (separate) {
@@ -599,7 +621,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_fold(CgCtl ctl, Geo geo, double2*
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) cg_shared().alpha = 0.0;
+    if (threadIdx.x == 0) cg_shared().alpha = cg_shared().alpha_old = 0.0;
     cg_publish(ctl, pos);
 }
 
@@ -863,7 +885,9 @@ void k_cg_a2(CgCtl ctl, Geo geo, CgVecs<float> v, const float* __restrict__ phi_
         cg_publish(ctl, pos);
         return;
     }
-    const float alpha = float(S.alpha), beta = float(S.beta);
+    const float alpha = float(S.alpha), alpha_old = float(S.alpha_old), beta = float(S.beta);
+    const bool fold = S.alpha_old != 0.0;
+    const double defer = S.alpha;
     const int pb = S.pbuf;
     const size_t off = pos.voff;
     const float2* pin = (pb ? v.p1 : v.p0) + off;
@@ -876,6 +900,13 @@ void k_cg_a2(CgCtl ctl, Geo geo, CgVecs<float> v, const float* __restrict__ phi_
         const int tile = sp.first;
         const int s = 2 * (tile * kBlock + threadIdx.x);
         if (s < lat.vol) {
+            if (fold) {   // before the stencil: its registers are free again when the stencil runs
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const size_t i = size_t(c) * lat.vol + s;
+                    st4(x, i, f4axpy(alpha, ld4(pin, i), f4axpy(alpha_old, ld4(pout, i), ld4(x, i))));
+                }
+            }
             const Nbr nb = neighbours(lat, s);
             float4 o[4], pn[4];
             dslash_pair<false, NN2>(src, phi, lat, cf, nb, s, o, pn);
@@ -883,7 +914,6 @@ void k_cg_a2(CgCtl ctl, Geo geo, CgVecs<float> v, const float* __restrict__ phi_
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const size_t i = size_t(c) * lat.vol + s;
-                st4(x, i, f4axpy(alpha, ld4(pin, i), ld4(x, i)));
                 st4(pout, i, pn[c]);
                 st4(t, i, o[c]);
                 acc += f4norm2(o[c]);
@@ -894,6 +924,7 @@ void k_cg_a2(CgCtl ctl, Geo geo, CgVecs<float> v, const float* __restrict__ phi_
     store_partial(ctl, PEND_TT, pos, part);
     if (threadIdx.x == 0) {
         CgState& W = cg_shared();
+        W.alpha_old = fold ? 0.0 : defer;
         W.alpha = 0.0;
         W.pbuf = 1 - pb;
         W.pending = PEND_TT;

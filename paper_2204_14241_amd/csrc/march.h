@@ -314,7 +314,9 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, Lat 
         cg_publish(ctl, pos);
         return;
     }
-    const float alpha = float(S.alpha), beta = float(S.beta);
+    const float alpha = float(S.alpha), alpha_old = float(S.alpha_old), beta = float(S.beta);
+    const bool fold = S.alpha_old != 0.0;   // x += both pending steps this iteration (see k_cg_a)
+    const double defer = S.alpha;
     const int pb = S.pbuf;
     const size_t off = pos.voff;
     const float2* pin = (pb ? v.p1 : v.p0) + off;
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, Lat 
     const int xrow = wrap_row(mpos.x0 - 1 + lr, L);
     const bool inner = act && lr >= 1 && lr <= mpos.nr;
     const int ro = xrow * L + y;                      // offset of the element within a slice
-    float4 rz[4], rp[4], rx[4];
+    float4 rz[4], rp[4], rx[4], rq[4];
     float2 f1 = make_float2(0.f, 0.f), f2 = f1, f3 = f1;
     auto load_slab = [&](int tq) {
         if (act) {
@@ -342,9 +344,13 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, Lat 
                 rp[c] = ld4(pin, i);
             }
         }
-        if (inner) {
+        if (inner && fold) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) rx[c] = ld4(x, size_t(c) * vol + size_t(tq) * LL + ro);
+            for (int c = 0; c < 4; ++c) {
+                const size_t i = size_t(c) * vol + size_t(tq) * LL + ro;
+                rx[c] = ld4(x, i);
+                rq[c] = ld4(pout, i);
+            }
         }
     };
     auto load_phi = [&](int tq) {
@@ -368,7 +374,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, Lat 
             for (int c = 0; c < 4; ++c) {
                 const size_t i = size_t(c) * vol + size_t(tq) * LL + ro;
                 st4(pout, i, pn[c]);
-                st4(x, i, f4axpy(alpha, rp[c], rx[c]));
+                if (fold) st4(x, i, f4axpy(alpha, rp[c], f4axpy(alpha_old, rq[c], rx[c])));
             }
         }
     };
@@ -409,6 +415,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, Lat 
     store_partial(ctl, PEND_TT, pos, part);
     if (threadIdx.x == 0) {
         CgState& W = cg_shared();
+        W.alpha_old = fold ? 0.0 : defer;
         W.alpha = 0.0;
         W.pbuf = 1 - pb;
         W.pending = PEND_TT;
@@ -430,7 +437,9 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, Lat l
         cg_publish(ctl, pos);
         return;
     }
-    const double alpha = S.alpha, beta = S.beta;
+    const double alpha = S.alpha, alpha_old = S.alpha_old, beta = S.beta;
+    const bool fold = alpha_old != 0.0;     // x += both pending steps this iteration (see k_cg_a)
+    const double defer = S.alpha;
     const int pb = S.pbuf;
     const size_t off = pos.voff;
     const double2* pin = (pb ? v.p1 : v.p0) + off;
@@ -446,7 +455,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, Lat l
     const int xrow = wrap_row(mpos.x0 - 1 + lr, L);
     const bool inner = act && lr >= 1 && lr <= mpos.nr;
     const int ro = xrow * L + y;
-    double2 rz[4], rp[4], rx[4];
+    double2 rz[4], rp[4], rx[4], rq[4];
     double f1 = 0.0, f2 = 0.0, f3 = 0.0;
     auto load_slab = [&](int tq) {
         if (act) {
@@ -457,9 +466,13 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, Lat l
                 rp[c] = pin[i];
             }
         }
-        if (inner) {
+        if (inner && fold) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) rx[c] = x[size_t(c) * vol + size_t(tq) * LL + ro];
+            for (int c = 0; c < 4; ++c) {
+                const size_t i = size_t(c) * vol + size_t(tq) * LL + ro;
+                rx[c] = x[i];
+                rq[c] = pout[i];
+            }
         }
     };
     auto load_phi = [&](int tq) {
@@ -482,7 +495,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, Lat l
             for (int c = 0; c < 4; ++c) {
                 const size_t i = size_t(c) * vol + size_t(tq) * LL + ro;
                 pout[i] = pn[c];
-                x[i] = axpy<double>(alpha, rp[c], rx[c]);
+                if (fold) x[i] = axpy<double>(alpha, rp[c], axpy<double>(alpha_old, rq[c], rx[c]));
             }
         }
     };
@@ -521,6 +534,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, Lat l
     store_partial(ctl, PEND_TT, pos, part);
     if (threadIdx.x == 0) {
         CgState& W = cg_shared();
+        W.alpha_old = fold ? 0.0 : defer;
         W.alpha = 0.0;
         W.pbuf = 1 - pb;
         W.pending = PEND_TT;

@@ -29,20 +29,38 @@ def test_world_size_above_one_is_refused():
 def test_launch_bytes_count_every_right_hand_side_and_phi_once():
     """Bytes of one CG launch: the spinor streams of every right-hand side the launch covers,
     the boson field once (the launch shape of csrc/hmc.hip runs all right-hand sides of a solve
-    in one grid)."""
+    in one grid).  Step A alternates between a launch that defers the solution update and one
+    that adds both pending steps, so its per-launch figure is the mean of the two."""
     sys.path.insert(0, ROOT)
     import bench
     vol = 40 * 40 * 100
-    # step A reads r, p_old, x and writes p_new, t, x per right-hand side; step B reads t, r and
-    # writes r; an apply reads psi and writes psi (spinor 64 B FP64 / 32 B FP32, phi 24 / 12 B)
+    # step A defers x (reads r, p_old; writes p_new, t) or updates it (also reads x and the
+    # older direction, writes x): 4 or 7 spinor streams; step B reads t, r and writes r; an
+    # apply reads psi and writes psi (spinor 64 B FP64 / 32 B FP32, phi 24 / 12 B)
     for n in (1, 2, 4):
-        assert bench.launch_bytes("cg_a_f64", vol, n) == vol * (n * 6 * 64 + 24)
+        assert bench.launch_bytes("cg_a_defer_f64", vol, n) == vol * (n * 4 * 64 + 24)
+        assert bench.launch_bytes("cg_a_fold_f64", vol, n) == vol * (n * 7 * 64 + 24)
+        assert 2 * bench.launch_bytes("cg_a_f64", vol, n) == (bench.launch_bytes("cg_a_defer_f64", vol, n)
+                                                             + bench.launch_bytes("cg_a_fold_f64", vol, n))
         assert bench.launch_bytes("cg_b_f64", vol, n) == vol * (n * 3 * 64 + 24)
-        assert bench.launch_bytes("cg_a_f32", vol, n) == vol * (n * 6 * 32 + 12)
+        assert bench.launch_bytes("cg_a_defer_f32", vol, n) == vol * (n * 4 * 32 + 12)
+        assert bench.launch_bytes("cg_a_fold_f32", vol, n) == vol * (n * 7 * 32 + 12)
         assert bench.launch_bytes("cg_b_f32", vol, n) == vol * (n * 3 * 32 + 12)
         assert bench.launch_bytes("apply_f64", vol, n) == vol * (n * 2 * 64 + 24)
     # two right-hand sides move almost twice the bytes of one (the 40x40x100 FP64 leg)
     r = bench.launch_bytes("cg_a_f64", vol, 2) / bench.launch_bytes("cg_a_f64", vol, 1)
     assert 1.9 < r < 2.0
-    assert bench.BYTES_PER_SITE["cg_a_f32"] == 204 and bench.BYTES_PER_SITE["cg_b_f32"] == 108
+    assert bench.BYTES_PER_SITE["cg_a_f32"] == 188 and bench.BYTES_PER_SITE["cg_b_f32"] == 108
     assert bench.HBM_PEAK_GBS == 8000.0
+
+
+def test_step_a_samples_are_averaged_over_both_kinds():
+    sys.path.insert(0, ROOT)
+    import bench
+    kt = {n: (None, 0) for n in ("cg_a_f32", "cg_a_next_f32", "cg_a_f64", "cg_a_next_f64")}
+    kt["cg_a_f32"], kt["cg_a_next_f32"] = (0.030, 4), (0.050, 4)
+    kt["cg_a_f64"] = (0.1, 3)
+    m = bench.merge_step_a(kt)
+    assert abs(m["cg_a_f32"][0] - 0.040) < 1e-15 and m["cg_a_f32"][1] == 8
+    assert m["cg_a_first_f32"] == (0.030, 4)
+    assert m["cg_a_f64"] == (None, 0)      # one kind only: no per-launch average

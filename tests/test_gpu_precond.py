@@ -234,7 +234,8 @@ def test_pcg_kernel_timing_samples_every_pass(hip, precision):
     _, st = h.cg_solve(phi, b)
     kt = h.kernel_times()
     suf = "f32" if precision == "mixed" else "f64"
-    names = [f"cg_a_{suf}", f"cg_b_{suf}", f"pc_xy_fwd_{suf}", f"pc_t_{suf}", f"pc_xy_inv_{suf}"]
+    names = [f"cg_a_{suf}", f"cg_b_{suf}", f"pc_xy_fwd_{suf}", f"pc_t_{suf}", f"pc_xy_inv_{suf}",
+             f"cg_a_next_{suf}"]
     counts = {kt[n][1] for n in names}
     say(f"  iterations {st.iterations}; samples {[(n, kt[n]) for n in names]}")
     assert len(counts) == 1 and counts.pop() >= 1
