@@ -500,6 +500,21 @@ int hmc_batch_set_graphs(hmc_batch* batch, int enable);
 /* As hmc_set_step_graphs, for the batch's trajectories. */
 int hmc_batch_set_step_graphs(hmc_batch* batch, int enable);
 
+/* Step A of CG, and the FP64 stencils of its reliable update, as marches of row bands through
+ * time slices (as hmc_set_cg_march), each lattice of the batch with its own cut: at most `rows`
+ * rows per band (and at most what a 512-thread workgroup holds for the lattice's L: one element
+ * per thread in FP64, two in FP32), `slices` slices per segment (0: 8; more when a lattice's
+ * partial-sum slots require it).  The reliable update uses the FP64 setting.  rows = 0 selects
+ * the tile kernels; so does a lattice that fits no cut (then for the whole batch) and the
+ * production model's two-site hops.  Defaults: 4 rows FP64, 8 FP32, 8 slices; hmc_batch_autotune
+ * searches them.  precision: HMC_FP64, HMC_MIXED or -1 for both.  Results depend on the cut only
+ * through the order of the FP64 partial sums; a chain reproduces, bit for bit, a one-lattice
+ * context given the same cut.  hmc_batch_get_cg_march reports the cut chain `chain` uses in
+ * `precision` (0 rows: the tile kernels). */
+int hmc_batch_set_cg_march(hmc_batch* batch, int precision, int rows, int slices);
+int hmc_batch_get_cg_march(const hmc_batch* batch, int chain, int precision, int* rows, int* slices,
+                           int* ru_rows, int* ru_slices);
+
 /* Replace the run parameters; n_pf must equal the value given at creation. */
 int hmc_batch_set_params(hmc_batch* batch, const hmc_params* params);
 

@@ -42,7 +42,7 @@ EXPORTED = [
     "hmc_order_parameter", "hmc_binder",
     "hmc_batch_create", "hmc_batch_destroy", "hmc_batch_workspace_bytes",
     "hmc_batch_set_workspace", "hmc_batch_layout", "hmc_batch_set_cg_workgroups",
-    "hmc_batch_get_cg_workgroups", "hmc_batch_set_graphs", "hmc_batch_set_step_graphs", "hmc_batch_set_params",
+    "hmc_batch_get_cg_workgroups", "hmc_batch_set_graphs", "hmc_batch_set_step_graphs", "hmc_batch_set_cg_march", "hmc_batch_get_cg_march", "hmc_batch_set_params",
     "hmc_batch_apply", "hmc_batch_cg_solve", "hmc_batch_autotune", "hmc_batch_trajectory",
 ]
 
@@ -237,6 +237,9 @@ def load():
         "hmc_batch_get_cg_workgroups": (I, [P, I]),
         "hmc_batch_set_graphs": (I, [P, I]),
         "hmc_batch_set_step_graphs": (I, [P, I]),
+        "hmc_batch_set_cg_march": (I, [P, I, I, I]),
+        "hmc_batch_get_cg_march": (I, [P, I, I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
         "hmc_batch_set_params": (I, [P, ctypes.POINTER(HmcParams)]),
         "hmc_batch_apply": (I, [P, I, I, P, P, P, P]),
         "hmc_batch_cg_solve": (I, [P, P, P, P, ctypes.POINTER(I), ctypes.POINTER(D), P]),

@@ -117,6 +117,14 @@ struct BatchInfo {
     UnitDesc* units[2] = {nullptr, nullptr};
     int2* blocks[2] = {nullptr, nullptr};
     int nblocks[2] = {0, 0};
+    // step A and the reliable update's FP64 stencils as marches (0 workgroups: the tile
+    // kernels): block tables (unit, workgroup), workgroups, threads and LDS of a launch
+    int2* mblocks[2] = {nullptr, nullptr};
+    int2* rblocks[2] = {nullptr, nullptr};
+    int mgrid[2] = {0, 0}, rgrid[2] = {0, 0};
+    int mthreads[2] = {0, 0}, rthreads[2] = {0, 0};
+    size_t mlds[2] = {0, 0}, rlds[2] = {0, 0};
+    std::vector<UnitDesc> hunits[2];  // host copies of the unit tables
     int2* pxy_blocks = nullptr;       // preconditioner slice passes: (unit, slice)
     int2* pt_blocks[2] = {nullptr, nullptr};   // tau pass: (unit, column group) [FP64, FP32]
     ChainDesc* chains = nullptr;
@@ -411,7 +419,8 @@ static size_t ws_layout(hmc_ctx* c, char* base) {
     char* mp = c->is_batch ? nullptr : take(sizeof(double) * 3 * size_t(std::max(pc_groups(c->lat.LL, pc_ncol<double>()), 256)));
     char* pw = c->is_batch ? nullptr : take(3 * PS * sizeof(double));
     char *un0 = nullptr, *un1 = nullptr, *bl0 = nullptr, *bl1 = nullptr, *ch = nullptr,
-         *cb = nullptr, *cf = nullptr, *cs = nullptr, *pxy = nullptr, *pt0 = nullptr, *pt1 = nullptr;
+         *cb = nullptr, *cf = nullptr, *cs = nullptr, *pxy = nullptr, *pt0 = nullptr, *pt1 = nullptr,
+         *mb0 = nullptr, *mb1 = nullptr, *rb0 = nullptr, *rb1 = nullptr;
     if (c->is_batch) {
         const size_t nch = size_t(c->bi.nchains);
         un0 = take(sizeof(UnitDesc) * nu);
@@ -425,6 +434,10 @@ static size_t ws_layout(hmc_ctx* c, char* base) {
         pxy = take(sizeof(int2) * size_t(c->bi.nslices));
         pt0 = take(sizeof(int2) * size_t(c->bi.ngroups[0]));
         pt1 = take(sizeof(int2) * size_t(c->bi.ngroups[1]));
+        mb0 = take(sizeof(int2) * size_t(c->pslots));
+        mb1 = take(sizeof(int2) * size_t(c->pslots));
+        rb0 = take(sizeof(int2) * size_t(c->pslots));
+        rb1 = take(sizeof(int2) * size_t(c->pslots));
     }
     if (base) {
         c->st = reinterpret_cast<CgState*>(st);
@@ -462,6 +475,10 @@ static size_t ws_layout(hmc_ctx* c, char* base) {
             c->bi.pxy_blocks = reinterpret_cast<int2*>(pxy);
             c->bi.pt_blocks[0] = reinterpret_cast<int2*>(pt0);
             c->bi.pt_blocks[1] = reinterpret_cast<int2*>(pt1);
+            c->bi.mblocks[0] = reinterpret_cast<int2*>(mb0);
+            c->bi.mblocks[1] = reinterpret_cast<int2*>(mb1);
+            c->bi.rblocks[0] = reinterpret_cast<int2*>(rb0);
+            c->bi.rblocks[1] = reinterpret_cast<int2*>(rb1);
         }
     }
     return off;
@@ -477,11 +494,39 @@ static int unit_slots(const Lat& l) {
     return std::max(clamp_bpr(tiles2_host(l.vol), kMaxBpr), 4 * pc_groups(l.LL, kPcCols));
 }
 
-// Batch: (re)write the unit and block tables of one precision's launch shape.
+// A unit's march cut: rows per band at most `rows` (and at most what one thread per element, or
+// pair of elements in FP32, of a 512-thread workgroup and 64 KB of LDS allow), `seg` slices per
+// segment (default 8), more slices per segment if the unit's partial slots require it.  Zero
+// workgroups when rows = 0 or no cut fits.
+static MarchPlan batch_march_plan(const Lat& l, int rows, int seg, bool f32, int slots, int& parts, int& threads,
+                                  size_t& lds) {
+    parts = 0;
+    threads = 0;
+    lds = 0;
+    if (rows <= 0) return MarchPlan{};
+    const int per_row = f32 ? l.L / 2 : l.L;
+    const int R = std::min({rows, l.L, kMarchCgThreads / per_row - 2});
+    if (R < 1) return MarchPlan{};
+    const size_t need = f32 ? march_cg_lds<float>(R, l.L) : march_cg_lds<double>(R, l.L);
+    if (need > (size_t(64) << 10)) return MarchPlan{};
+    MarchPlan mp = make_march_plan(l.L, l.Lt, R, seg > 0 ? seg : 8);
+    while (mp.nband * mp.nseg > slots && mp.seglen < l.Lt) mp = make_march_plan(l.L, l.Lt, R, mp.seglen * 2);
+    if (mp.nband * mp.nseg > slots) return MarchPlan{};
+    parts = mp.nband * mp.nseg;
+    threads = ((R + 2) * per_row + 63) / 64 * 64;
+    lds = need;
+    return mp;
+}
+
+// Batch: (re)write the unit and block tables of one precision's launch shape, with the march
+// cuts of step A (this precision) and of the reliable update (FP64).
 static int upload_batch_shape(hmc_ctx* c, int pi, int max_bpr) {
     BatchInfo& b = c->bi;
     std::vector<UnitDesc> units(size_t(c->nunits));
-    std::vector<int2> blocks;
+    std::vector<int2> blocks, mblocks, rblocks;
+    bool m_ok = c->cgm_rows[pi] > 0, r_ok = m_ok && c->cgm_rows[0] > 0;
+    b.mthreads[pi] = b.rthreads[pi] = 0;
+    b.mlds[pi] = b.rlds[pi] = 0;
     int part = 0;
     for (int ch = 0; ch < b.nchains; ++ch) {
         const Lat& lat = b.lats[size_t(ch)];
@@ -497,14 +542,34 @@ static int upload_batch_shape(hmc_ctx* c, int pi, int max_bpr) {
             d.chain = ch;
             d.pcoff = int(b.pcoff[size_t(ch)]);
             for (int w = 0; w < d.bpr; ++w) blocks.push_back(make_int2(u, w));
+            int th = 0;
+            size_t lds = 0;
+            d.mp = batch_march_plan(lat, c->cgm_rows[pi], c->cgm_seg[pi], pi == 1, unit_slots(lat), d.mparts, th, lds);
+            m_ok = m_ok && d.mparts > 0;
+            b.mthreads[pi] = std::max(b.mthreads[pi], th);
+            b.mlds[pi] = std::max(b.mlds[pi], lds);
+            for (int w = 0; w < d.mparts; ++w) mblocks.push_back(make_int2(u, w));
+            d.rmp = batch_march_plan(lat, c->cgm_rows[0], c->cgm_seg[0], false, unit_slots(lat), d.rparts, th, lds);
+            r_ok = r_ok && d.rparts > 0;
+            b.rthreads[pi] = std::max(b.rthreads[pi], th);
+            b.rlds[pi] = std::max(b.rlds[pi], lds);
+            for (int w = 0; w < d.rparts; ++w) rblocks.push_back(make_int2(u, w));
         }
     }
     b.nblocks[pi] = int(blocks.size());
+    // a launch marches every unit or none
+    b.mgrid[pi] = m_ok ? int(mblocks.size()) : 0;
+    b.rgrid[pi] = r_ok ? int(rblocks.size()) : 0;
+    b.hunits[pi] = units;
     if (c->ws != nullptr) {
         // launches already queued may still read the old tables
         HIPCHK(hipDeviceSynchronize());
         HIPCHK(hipMemcpy(b.units[pi], units.data(), sizeof(UnitDesc) * units.size(), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b.blocks[pi], blocks.data(), sizeof(int2) * blocks.size(), hipMemcpyHostToDevice));
+        if (b.mgrid[pi] > 0)
+            HIPCHK(hipMemcpy(b.mblocks[pi], mblocks.data(), sizeof(int2) * mblocks.size(), hipMemcpyHostToDevice));
+        if (b.rgrid[pi] > 0)
+            HIPCHK(hipMemcpy(b.rblocks[pi], rblocks.data(), sizeof(int2) * rblocks.size(), hipMemcpyHostToDevice));
     }
     return HMC_OK;
 }
@@ -647,6 +712,10 @@ struct Launch {
     MarchPlan rum{};
     int rum_threads = 0, rum_per_unit = 0;
     size_t rum_lds = 0;
+    // a batch's marches: every unit with its own cut (0 workgroups: the tile kernels)
+    MGeoBatch bm{}, br{};
+    int bm_grid = 0, bm_threads = 0, br_grid = 0, br_threads = 0;
+    size_t bm_lds = 0, br_lds = 0;
 };
 
 template <typename R>
@@ -722,6 +791,18 @@ static Launch<GeoBatch> launch_batch(const hmc_ctx* c) {
     l.pt_full = c->pc_full[pi];
     l.nn2 = c->cf64.nn2 != 0;
     l.r7 = c->pc_r7;
+    if (!l.nn2 && c->bi.mgrid[pi] > 0) {
+        l.bm = MGeoBatch{c->bi.units[pi], c->bi.mblocks[pi], 0};
+        l.bm_grid = c->bi.mgrid[pi];
+        l.bm_threads = c->bi.mthreads[pi];
+        l.bm_lds = c->bi.mlds[pi];
+        if (c->bi.rgrid[pi] > 0) {
+            l.br = MGeoBatch{c->bi.units[pi], c->bi.rblocks[pi], 1};
+            l.br_grid = c->bi.rgrid[pi];
+            l.br_threads = c->bi.rthreads[pi];
+            l.br_lds = c->bi.rlds[pi];
+        }
+    }
     return l;
 }
 
@@ -819,6 +900,28 @@ static int chunk_launches(int chunk, bool pc) {
     return n + (n & 1);
 }
 
+// Step A as a march: one lattice (every vector cut alike) or a batch (each unit its own cut);
+// ev: start/stop events for a timed launch.
+template <typename R, class Geo>
+static void launch_step_a_march(hmc_ctx* c, const Launch<Geo>& lc, const CgCtl& ka, const CgVecs<R>& v, const R* phik,
+                                const Coef<R>& cf, int grid, int threads, size_t lds, const hipEvent_t* ev,
+                                hipStream_t s) {
+    auto go = [&](auto mg) {
+        using MG = decltype(mg);
+        if constexpr (sizeof(R) == sizeof(float)) {
+            if (ev) hipExtLaunchKernelGGL((k_cg_a2_march<MG>), dim3(grid), dim3(threads), lds, s, ev[0], ev[1], 0, ka, mg,
+                                          v, phik, cf);
+            else hipLaunchKernelGGL((k_cg_a2_march<MG>), dim3(grid), dim3(threads), lds, s, ka, mg, v, phik, cf);
+        } else {
+            if (ev) hipExtLaunchKernelGGL((k_cg_a_march<MG>), dim3(grid), dim3(threads), lds, s, ev[0], ev[1], 0, ka, mg,
+                                          v, phik, cf);
+            else hipLaunchKernelGGL((k_cg_a_march<MG>), dim3(grid), dim3(threads), lds, s, ka, mg, v, phik, cf);
+        }
+    };
+    if constexpr (std::is_same<Geo, GeoOne>::value) go(MGeoOne{lc.cg.lat, lc.cgm, lc.cg.bpr, c->pstride});
+    else go(lc.bm);
+}
+
 // One status chunk: `chunk` iterations (steps A and B, and the preconditioner passes), then
 // the reliable-update / true-residual sequence for units in `filter`, then what makes the
 // published records complete.  first: the first chunk of an unpreconditioned solve (its
@@ -834,42 +937,47 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
     for (int i = 0; i < chunk; ++i) {
         const int expect_a = lc.pc ? PEND_NONE : (i > 0 ? PEND_RR : (first ? PEND_BB : PEND_NONE));
         const CgCtl ka = next_ctl(c, expect_a);
+        // step A as a march (one lattice, or every unit of a batch with its own cut); step B
+        // (the tile kernel, which reads t while the MALL still holds it) reduces the march's
+        // partials
+        int mgrid = 0, mthreads = 0, mparts = 0;
+        size_t mlds = 0;
         if constexpr (std::is_same<Geo, GeoOne>::value) {
             if (lc.cgm_per_unit > 0) {
-                // step A as a march; step B (the tile kernel, which reads t while the MALL still
-                // holds it) reduces the march's partials
-                c->next_nparts = lc.cgm_per_unit;
-                const CgCtl kb = next_ctl(c, PEND_TT);
-                const hipEvent_t* e = (sample && i == chunk / 2) ? c->tev[kslot] : nullptr;
-                // the next iteration's step A too (the solution update alternates between them)
-                const hipEvent_t* ea = e ? e : (sample && i == chunk / 2 + 1) ? c->tev[kslot] + 10 : nullptr;
-                const int g = lc.cgm_per_unit * n;
-                if constexpr (sizeof(R) == sizeof(float)) {
-                    if (ea) hipExtLaunchKernelGGL(k_cg_a2_march, dim3(g), dim3(lc.cgm_threads), lc.cgm_lds, s, ea[0], ea[1], 0,
-                                                  ka, geo.lat, lc.cgm, geo.bpr, c->pstride, v, phik, cf);
-                    else hipLaunchKernelGGL(k_cg_a2_march, dim3(g), dim3(lc.cgm_threads), lc.cgm_lds, s, ka, geo.lat,
-                                            lc.cgm, geo.bpr, c->pstride, v, phik, cf);
-                    LAUNCHCHK();
-                    if (e) hipExtLaunchKernelGGL((k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0, s, e[2], e[3], 0, kb,
-                                                 geo, v, phik, cf);
-                    else hipLaunchKernelGGL((k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
-                } else {
-                    if (ea) hipExtLaunchKernelGGL(k_cg_a_march, dim3(g), dim3(lc.cgm_threads), lc.cgm_lds, s, ea[0], ea[1], 0,
-                                                  ka, geo.lat, lc.cgm, geo.bpr, c->pstride, v, phik, cf);
-                    else hipLaunchKernelGGL(k_cg_a_march, dim3(g), dim3(lc.cgm_threads), lc.cgm_lds, s, ka, geo.lat,
-                                            lc.cgm, geo.bpr, c->pstride, v, phik, cf);
-                    LAUNCHCHK();
-                    if (e) hipExtLaunchKernelGGL((k_cg_b<R, Geo, false>), dim3(grid), dim3(kBlock), 0, s, e[2], e[3], 0,
-                                                 kb, geo, v, phik, cf);
-                    else hipLaunchKernelGGL((k_cg_b<R, Geo, false>), dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
-                }
-                LAUNCHCHK();
-                if (lc.pc) {
-                    int rc = enqueue_pc<R, Geo>(c, lc, v, PEND_RR, s, e ? c->tev[kslot] + 4 : nullptr);
-                    if (rc) return rc;
-                }
-                continue;
+                mgrid = lc.cgm_per_unit * n;
+                mthreads = lc.cgm_threads;
+                mlds = lc.cgm_lds;
+                mparts = lc.cgm_per_unit;
             }
+        } else if (lc.bm_grid > 0) {
+            mgrid = lc.bm_grid;
+            mthreads = lc.bm_threads;
+            mlds = lc.bm_lds;
+            mparts = kPartsMarch;
+        }
+        if (mgrid > 0) {
+            c->next_nparts = mparts;
+            const CgCtl kb = next_ctl(c, PEND_TT);
+            const hipEvent_t* e = (sample && i == chunk / 2) ? c->tev[kslot] : nullptr;
+            // the next iteration's step A too (the solution update alternates between them)
+            const hipEvent_t* ea = e ? e : (sample && i == chunk / 2 + 1) ? c->tev[kslot] + 10 : nullptr;
+            launch_step_a_march<R, Geo>(c, lc, ka, v, phik, cf, mgrid, mthreads, mlds, ea, s);
+            LAUNCHCHK();
+            if constexpr (sizeof(R) == sizeof(float)) {
+                if (e) hipExtLaunchKernelGGL((k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0, s, e[2], e[3], 0, kb,
+                                             geo, v, phik, cf);
+                else hipLaunchKernelGGL((k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
+            } else {
+                if (e) hipExtLaunchKernelGGL((k_cg_b<R, Geo, false>), dim3(grid), dim3(kBlock), 0, s, e[2], e[3], 0,
+                                             kb, geo, v, phik, cf);
+                else hipLaunchKernelGGL((k_cg_b<R, Geo, false>), dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
+            }
+            LAUNCHCHK();
+            if (lc.pc) {
+                int rc = enqueue_pc<R, Geo>(c, lc, v, PEND_RR, s, e ? c->tev[kslot] + 4 : nullptr);
+                if (rc) return rc;
+            }
+            continue;
         }
         const CgCtl kb = next_ctl(c, PEND_TT);
         if (sample && i == chunk / 2) {
@@ -930,22 +1038,36 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
     hipLaunchKernelGGL((k_ru_fold<R, Geo>), dim3(grid), dim3(kBlock), 0, s, next_ctl(c, lc.pc ? PEND_NONE : PEND_RR),
                        geo, x, v, filter);
     LAUNCHCHK();
-    bool ru_march = false;
+    // t64 = M x64 and r = b - M^dagger t64 as marches; the record after them reduces the
+    // march's partials
+    int rgrid = 0, rthreads = 0, rparts = 0;
+    size_t rlds = 0;
     if constexpr (std::is_same<Geo, GeoOne>::value) {
         if (lc.rum_per_unit > 0) {
-            // t64 = M x64 and r = b - M^dagger t64 as marches; the record after them reduces
-            // the march's partials
-            ru_march = true;
-            const int g = lc.rum_per_unit * n;
-            hipLaunchKernelGGL(k_ru_apply_march, dim3(g), dim3(lc.rum_threads), lc.rum_lds, s, next_ctl(c, PEND_NONE),
-                               geo.lat, lc.rum, geo.bpr, c->pstride, x, c->t64, phi64, c->cf64, filter);
-            LAUNCHCHK();
-            hipLaunchKernelGGL(k_ru_resid_march<R>, dim3(g), dim3(lc.rum_threads), lc.rum_lds, s,
-                               next_ctl(c, PEND_NONE), geo.lat, lc.rum, geo.bpr, c->pstride, b, c->t64, phi64,
-                               c->cf64, v.r, filter);
-            LAUNCHCHK();
-            c->next_nparts = lc.rum_per_unit;
+            rgrid = lc.rum_per_unit * n;
+            rthreads = lc.rum_threads;
+            rlds = lc.rum_lds;
+            rparts = lc.rum_per_unit;
         }
+    } else if (lc.br_grid > 0) {
+        rgrid = lc.br_grid;
+        rthreads = lc.br_threads;
+        rlds = lc.br_lds;
+        rparts = kPartsRu;
+    }
+    const bool ru_march = rgrid > 0;
+    if (ru_march) {
+        auto go = [&](auto mg) {
+            using MG = decltype(mg);
+            hipLaunchKernelGGL((k_ru_apply_march<MG>), dim3(rgrid), dim3(rthreads), rlds, s, next_ctl(c, PEND_NONE), mg,
+                               x, c->t64, phi64, c->cf64, filter);
+            hipLaunchKernelGGL((k_ru_resid_march<R, MG>), dim3(rgrid), dim3(rthreads), rlds, s, next_ctl(c, PEND_NONE),
+                               mg, b, c->t64, phi64, c->cf64, v.r, filter);
+        };
+        if constexpr (std::is_same<Geo, GeoOne>::value) go(MGeoOne{geo.lat, lc.rum, geo.bpr, c->pstride});
+        else go(lc.br);
+        LAUNCHCHK();
+        c->next_nparts = rparts;
     }
     if (!ru_march) {
         HMC_LAUNCH_NN2(lc.nn2, (k_ru_apply<Geo, true>), (k_ru_apply<Geo, false>), dim3(grid), dim3(kBlock), 0, s,
@@ -1700,11 +1822,10 @@ static int set_workspace_common(hmc_ctx* c, void* ptr, size_t bytes) {
 static void apply_choice(hmc_ctx* c, const TuneChoice& ch) {
     c->bpr64 = c->is_batch ? ch.bpr[0] : clamp_bpr(c->nblk2, ch.bpr[0]);
     c->bpr32 = c->is_batch ? ch.bpr[1] : clamp_bpr(c->nblk2, ch.bpr[1]);
-    if (!c->is_batch)
-        for (int pi = 0; pi < 2; ++pi) {
-            c->cgm_rows[pi] = ch.mrows[pi];
-            c->cgm_seg[pi] = ch.mseg[pi];
-        }
+    for (int pi = 0; pi < 2; ++pi) {
+        c->cgm_rows[pi] = ch.mrows[pi];
+        c->cgm_seg[pi] = ch.mseg[pi];
+    }
     c->generation += 1;
 }
 
@@ -1772,26 +1893,39 @@ static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int 
             out->cg_workgroups[pi] = best_bpr;
             out->us_per_iter[pi] = best;
         }
-        // step A as a march (one lattice, nearest neighbours): rows per band x slices per segment
-        if (result == HMC_OK && !c->is_batch && !c->cf64.nn2) {
+        // step A as a march (nearest neighbours): rows per band x slices per segment; in a
+        // batch the rows are a cap, each lattice taking at most what its band allows
+        if (result == HMC_OK && !c->cf64.nn2) {
             static const int rows32[] = {4, 6, 8, 10}, rows64[] = {2, 3, 4};
             static const int segs32[] = {4, 6, 8}, segs64[] = {4, 6, 8, 12};
+            static const int brows32[] = {4, 8, 12, 16}, bsegs[] = {4, 8};
             const int per_row = pi ? c->L / 2 : c->L;
             int best_r = 0, best_s = 0;
-            const int* rows = pi ? rows32 : rows64;
-            const int* segs = pi ? segs32 : segs64;
-            const int nr = pi ? 4 : 3, ns = pi ? 3 : 4;
+            const int* rows = c->is_batch ? (pi ? brows32 : rows64) : (pi ? rows32 : rows64);
+            const int* segs = c->is_batch ? bsegs : (pi ? segs32 : segs64);
+            const int nr = pi ? 4 : 3, ns = c->is_batch ? 2 : (pi ? 3 : 4);
+            // in a batch the FP32 shape's reliable-update cut follows the FP64 rows
+            auto apply_march = [&](int r, int sl) -> int {
+                c->cgm_rows[pi] = r;
+                c->cgm_seg[pi] = sl;
+                c->generation += 1;
+                if (!c->is_batch) return HMC_OK;
+                int rc = upload_batch_shape(c, pi, pi ? c->bpr32 : c->bpr64);
+                if (rc == HMC_OK && pi == 0) rc = upload_batch_shape(c, 1, c->bpr32);
+                return rc;
+            };
             for (int a = 0; a < nr && result == HMC_OK; ++a) {
-                if ((rows[a] + 2) * per_row > kMarchCgThreads || rows[a] > c->L) continue;
+                if (!c->is_batch && ((rows[a] + 2) * per_row > kMarchCgThreads || rows[a] > c->L)) continue;
                 for (int q = 0; q < ns && result == HMC_OK; ++q) {
                     if (out->mtried[pi] >= HMC_TUNE_MARCH_MAX) break;
-                    c->cgm_rows[pi] = rows[a];
-                    c->cgm_seg[pi] = segs[q];
-                    c->generation += 1;
+                    result = apply_march(rows[a], segs[q]);
+                    if (result) break;
+                    if (c->is_batch && c->bi.mgrid[pi] == 0) continue;     // no lattice of the batch marches
                     float ms = 0.f;
                     for (int rep = 0; rep < 2; ++rep) {
                         if (hipEventRecord(e0, s) != hipSuccess) { result = HMC_ERR_HIP; break; }
-                        const int r = cg_dispatch(c, phi, b, c->xsol, n, nullptr, s);
+                        const int r = c->is_batch ? cg_dispatch_batch(c, phi, b, c->xsol, s)
+                                                  : cg_dispatch(c, phi, b, c->xsol, n, nullptr, s);
                         if (r != HMC_OK && r != HMC_ERR_NOT_CONVERGED) { result = r; break; }
                         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { result = HMC_ERR_HIP; break; }
@@ -1810,9 +1944,7 @@ static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int 
                     }
                 }
             }
-            c->cgm_rows[pi] = best_r;
-            c->cgm_seg[pi] = best_s;
-            c->generation += 1;
+            if (result == HMC_OK) result = apply_march(best_r, best_s);
             out->march_rows[pi] = best_r;
             out->march_slices[pi] = best_s;
             out->us_per_iter[pi] = best;
@@ -1822,13 +1954,11 @@ static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int 
     (void)hipEventDestroy(e1);
     c->p = saved;
     if (result != HMC_OK) {
+        c->cgm_rows[0] = 4;
+        c->cgm_rows[1] = 8;
+        c->cgm_seg[0] = c->cgm_seg[1] = 8;
         (void)set_cg_shape(c, HMC_FP64, kDefaultBpr64);
         (void)set_cg_shape(c, HMC_MIXED, kDefaultBpr32);
-        if (!c->is_batch) {
-            c->cgm_rows[0] = 4;
-            c->cgm_rows[1] = 8;
-            c->cgm_seg[0] = c->cgm_seg[1] = 8;
-        }
         return result == HMC_ERR_HIP ? fail(result, "autotune: HIP call failed") : result;
     }
     return HMC_OK;
@@ -2942,12 +3072,14 @@ int hmc_batch_create(int nchains, const int* L, const int* L_tau, const double* 
     }
     c->bpr64 = kDefaultBpr64;
     c->bpr32 = kDefaultBpr32;
+    // step A and the reliable update march by default (row caps per band; every lattice takes
+    // the rows its band allows, or the tile kernels if some lattice fits no cut)
+    c->cgm_rows[0] = 4;
+    c->cgm_rows[1] = 8;
+    c->cgm_seg[0] = c->cgm_seg[1] = 8;
     {
         TuneChoice ch;
-        if (tune_cache_lookup(tune_key(c), ch)) {
-            c->bpr64 = ch.bpr[0];
-            c->bpr32 = ch.bpr[1];
-        }
+        if (tune_cache_lookup(tune_key(c), ch)) apply_choice(c, ch);
     }
     (void)upload_batch_shape(c, 0, c->bpr64);    // counts only until the workspace is set
     (void)upload_batch_shape(c, 1, c->bpr32);
@@ -2994,6 +3126,42 @@ int hmc_batch_get_cg_workgroups(const hmc_batch* hb, int precision) {
 int hmc_batch_set_graphs(hmc_batch* hb, int enable) {
     if (hb == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL batch");
     hb->c.graphs = enable != 0;
+    return HMC_OK;
+}
+
+int hmc_batch_set_cg_march(hmc_batch* hb, int precision, int rows, int slices) {
+    if (hb == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL batch");
+    hmc_ctx* c = &hb->c;
+    if (precision != HMC_FP64 && precision != HMC_MIXED && precision != -1)
+        return fail(HMC_ERR_INVALID_ARG, "unknown precision");
+    if (rows < 0 || rows > 256 || slices < 0 || slices > 1 << 20)
+        return fail(HMC_ERR_INVALID_ARG, "rows must lie in [0, 256] and slices be >= 0");
+    for (int pi = 0; pi < 2; ++pi)
+        if (precision == -1 || precision == (pi ? HMC_MIXED : HMC_FP64)) {
+            c->cgm_rows[pi] = rows;
+            c->cgm_seg[pi] = slices;
+        }
+    c->generation += 1;
+    int rc = upload_batch_shape(c, 0, c->bpr64);
+    if (rc == HMC_OK) rc = upload_batch_shape(c, 1, c->bpr32);
+    return rc;
+}
+
+int hmc_batch_get_cg_march(const hmc_batch* hb, int chain, int precision, int* rows, int* slices, int* ru_rows,
+                           int* ru_slices) {
+    if (hb == nullptr || rows == nullptr || slices == nullptr || ru_rows == nullptr || ru_slices == nullptr)
+        return fail(HMC_ERR_INVALID_ARG, "NULL argument");
+    const BatchInfo& b = hb->c.bi;
+    if (chain < 0 || chain >= b.nchains) return fail(HMC_ERR_INVALID_ARG, "chain out of range");
+    if (precision != HMC_FP64 && precision != HMC_MIXED) return fail(HMC_ERR_INVALID_ARG, "unknown precision");
+    const int pi = precision == HMC_MIXED ? 1 : 0;
+    const bool nn2 = hb->c.cf64.nn2 != 0;
+    const UnitDesc& u = b.hunits[pi][size_t(chain) * size_t(b.nrhs)];
+    const bool m = !nn2 && b.mgrid[pi] > 0, r = m && b.rgrid[pi] > 0;
+    *rows = m ? u.mp.R : 0;
+    *slices = m ? u.mp.seglen : 0;
+    *ru_rows = r ? u.rmp.R : 0;
+    *ru_slices = r ? u.rmp.seglen : 0;
     return HMC_OK;
 }
 
@@ -3055,6 +3223,7 @@ int hmc_batch_autotune(hmc_batch* hb, const double* phi, const void* b, hmc_tune
     if (reuse_cached()) {
         TuneChoice ch;
         if (tune_cache_lookup(tune_key(c), ch)) {
+            apply_choice(c, ch);
             rc = set_cg_shape(c, HMC_FP64, ch.bpr[0]);
             if (rc == HMC_OK) rc = set_cg_shape(c, HMC_MIXED, ch.bpr[1]);
             if (rc) return rc;

@@ -116,6 +116,23 @@ struct CgState {
     int pad;
 };
 
+// Cut of one lattice into bands of rows and segments of time slices.
+struct MarchPlan {
+    int R;        // rows per band (the last band may have fewer)
+    int nband;    // bands: ceil(L / R)
+    int seglen;   // slices per segment (the last segment may have fewer)
+    int nseg;     // segments: ceil(L_tau / seglen)
+};
+
+__host__ __device__ inline MarchPlan make_march_plan(int L, int Lt, int R, int seglen) {
+    MarchPlan p;
+    p.R = R < L ? R : L;
+    p.nband = (L + p.R - 1) / p.R;
+    p.seglen = seglen < Lt ? seglen : Lt;
+    p.nseg = (Lt + p.seglen - 1) / p.seglen;
+    return p;
+}
+
 // One right-hand side of one lattice: the unit the CG state machine tracks.  A solve on a
 // single lattice has one unit per right-hand side; a batch of independent lattices (chains)
 // of different sizes has one per (chain, right-hand side), all in one launch.
@@ -127,6 +144,10 @@ struct UnitDesc {
     int part;           // first partial-sum slot of the unit (within one kind)
     int chain;          // lattice the unit belongs to
     int pcoff;          // first double of its lattice's preconditioner tables
+    MarchPlan mp;       // step A as a march in this launch shape's precision (march.h)
+    int mparts;         // its workgroups (bands x segments); 0: the tile kernels
+    MarchPlan rmp;      // the reliable update's FP64 marches
+    int rparts;         // their workgroups; 0: the tile kernels
 };
 
 // Where a workgroup works: its unit and its rank within the unit.
@@ -138,6 +159,8 @@ struct UPos {
     int bpr;            // CG workgroups on the unit (the count of its step partials)
     int part;           // first partial slot of the unit
     int pcoff;          // first double of the preconditioner tables of its lattice
+    int mparts;         // batch: workgroups of the unit's step-A march (0 for one lattice)
+    int rparts;         // batch: workgroups of the unit's reliable-update marches
 };
 
 // One lattice: unit k = right-hand side k; a launch runs nblk workgroups per unit in k-major
@@ -158,6 +181,7 @@ struct GeoOne {
         p.bpr = bpr;
         p.part = k * pstride;
         p.pcoff = 0;
+        p.mparts = p.rparts = 0;
         return p;
     }
     __device__ __forceinline__ UPos at(int logical) const {
@@ -181,6 +205,8 @@ struct GeoBatch {
         p.bpr = u.bpr;
         p.part = u.part;
         p.pcoff = u.pcoff;
+        p.mparts = u.mparts;
+        p.rparts = u.rparts;
         return p;
     }
     __device__ __forceinline__ UPos at(int logical) const {
@@ -227,8 +253,11 @@ struct CgCtl {
     int nslots;         // partial slots per kind
     int expect;         // the only partial kind that can be pending at this launch
     int nparts;         // > 0: partials the previous kernel left per unit (when its workgroup
-                        // count differs from the caller's default)
+                        // count differs from the caller's default); kPartsMarch / kPartsRu:
+                        // each unit's own march workgroup count (a batch's march launches)
 };
+constexpr int kPartsMarch = -1;
+constexpr int kPartsRu = -2;
 
 __device__ __forceinline__ double* part_slot(const CgCtl& c, int kind, const UPos& p) {
     return c.part + size_t(kind - 1) * c.nslots + p.part;
@@ -258,7 +287,12 @@ __device__ __forceinline__ int cg_finalize(const CgCtl& c, const UPos& pos, int 
     unsigned w = 0u;
     if (t < kStateWords) w = reinterpret_cast<const unsigned*>(c.st_in + k)[t];
     double tot = 0.0;
-    if (c.expect != PEND_NONE) tot = sum_partials(part_slot(c, c.expect, pos), c.nparts > 0 ? c.nparts : nparts);
+    if (c.expect != PEND_NONE) {
+        const int np = c.nparts > 0 ? c.nparts
+                       : c.nparts == kPartsMarch ? pos.mparts
+                       : c.nparts == kPartsRu ? pos.rparts : nparts;
+        tot = sum_partials(part_slot(c, c.expect, pos), np);
+    }
     if (t < kStateWords) reinterpret_cast<unsigned*>(&sh)[t] = w;
     __syncthreads();
     if (t == 0) {

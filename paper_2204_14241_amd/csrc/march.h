@@ -26,38 +26,26 @@ namespace hmc {
 // Most threads of a marching workgroup (8 waves: up to 256 VGPRs per thread).
 constexpr int kMarchMaxThreads = 512;
 
-// Cut of one lattice into bands of rows and segments of time slices.
-struct MarchPlan {
-    int R;        // rows per band (the last band may have fewer)
-    int nband;    // bands: ceil(L / R)
-    int seglen;   // slices per segment (the last segment may have fewer)
-    int nseg;     // segments: ceil(L_tau / seglen)
-};
-
-__host__ __device__ inline MarchPlan make_march_plan(int L, int Lt, int R, int seglen) {
-    MarchPlan p;
-    p.R = R < L ? R : L;
-    p.nband = (L + p.R - 1) / p.R;
-    p.seglen = seglen < Lt ? seglen : Lt;
-    p.nseg = (Lt + p.seglen - 1) / p.seglen;
-    return p;
-}
-
 // The workgroup's vector, band and segment.
 struct MarchPos {
     int k, x0, nr, t0, t1;
 };
-__device__ __forceinline__ MarchPos march_pos(const Lat& lat, const MarchPlan& mp, int wg) {
-    const int per_vec = mp.nseg * mp.nband;
+// Workgroup `rem` of vector k: segment-major, bands within a segment.
+__device__ __forceinline__ MarchPos march_pos_in(const Lat& lat, const MarchPlan& mp, int k, int rem) {
     MarchPos p;
-    p.k = wg / per_vec;
-    const int rem = wg - p.k * per_vec;
+    p.k = k;
     const int seg = rem / mp.nband, band = rem - seg * mp.nband;
     p.x0 = band * mp.R;
     p.nr = lat.L - p.x0 < mp.R ? lat.L - p.x0 : mp.R;
     p.t0 = seg * mp.seglen;
     p.t1 = lat.Lt - p.t0 < mp.seglen ? lat.Lt : p.t0 + mp.seglen;
     return p;
+}
+// Workgroup wg of a launch over vectors cut alike, vector-major.
+__device__ __forceinline__ MarchPos march_pos(const Lat& lat, const MarchPlan& mp, int wg) {
+    const int per_vec = mp.nseg * mp.nband;
+    const int k = wg / per_vec;
+    return march_pos_in(lat, mp, k, wg - k * per_vec);
 }
 
 __device__ __forceinline__ int wrap_row(int x, int L) { return x < 0 ? x + L : (x >= L ? x - L : x); }
@@ -297,18 +285,69 @@ __device__ __forceinline__ UPos march_unit(const Lat& lat, int k, int blk, int n
     p.bpr = nparts_in;
     p.part = k * pstride;
     p.pcoff = 0;
+    p.mparts = p.rparts = 0;
     return p;
 }
 
-__global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, Lat lat, MarchPlan mp, int nparts_in,
-                                                                 int pstride, CgVecs<float> v,
-                                                                 const float* __restrict__ phi, Coef<float> cf) {
+// Where a CG march workgroup works: its lattice, cut, band and segment, its unit record, and
+// the partial count the previous kernel left per unit.
+struct MarchWork {
+    Lat lat;
+    MarchPlan mp;
+    MarchPos mpos;
+    UPos pos;
+    int nparts_in;
+};
+
+// One lattice: the vectors of a solve cut alike, workgroups vector-major.
+struct MGeoOne {
+    Lat lat;
+    MarchPlan mp;
+    int nparts_in;
+    int pstride;
+    __device__ __forceinline__ MarchWork at(int wg) const {
+        MarchWork w;
+        w.lat = lat;
+        w.mp = mp;
+        w.mpos = march_pos(lat, mp, wg);
+        const int per_vec = mp.nseg * mp.nband;
+        w.pos = march_unit(lat, w.mpos.k, wg - w.mpos.k * per_vec, nparts_in, pstride);
+        w.nparts_in = nparts_in;
+        return w;
+    }
+};
+
+// A batch of lattices: blocks[wg] = (unit, workgroup within the unit), each unit with its own
+// cut (step A's, or with ru the reliable update's FP64 one).
+struct MGeoBatch {
+    const UnitDesc* units;
+    const int2* blocks;
+    int ru;
+    __device__ __forceinline__ MarchWork at(int wg) const {
+        const int2 e = blocks[wg];
+        const UnitDesc& u = units[e.x];
+        MarchWork w;
+        w.lat = u.lat;
+        w.mp = ru ? u.rmp : u.mp;
+        w.mpos = march_pos_in(u.lat, w.mp, e.x, e.y);
+        w.pos = GeoBatch{units, blocks}.unit(e.x, e.y);
+        w.nparts_in = u.bpr;
+        return w;
+    }
+};
+
+template <class MG>
+__global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG mg, CgVecs<float> v,
+                                                                 const float* __restrict__ phi_base, Coef<float> cf) {
     extern __shared__ __align__(16) unsigned char march_smem[];
+    const MarchWork w = mg.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = w.lat;
+    const MarchPlan& mp = w.mp;
+    const MarchPos& mpos = w.mpos;
+    const UPos& pos = w.pos;
+    const float* phi = phi_base + pos.phioff;
     const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, P = L / 2, rowc = 4 * L;
-    const int wg = xcd_remap(blockIdx.x, gridDim.x), per_vec = mp.nseg * mp.nband;
-    const MarchPos mpos = march_pos(lat, mp, wg);
-    const UPos pos = march_unit(lat, mpos.k, wg - mpos.k * per_vec, nparts_in, pstride);
-    cg_finalize(ctl, pos, nparts_in);
+    cg_finalize(ctl, pos, w.nparts_in);
     const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
         cg_publish(ctl, pos);
@@ -423,15 +462,18 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, Lat 
     cg_publish(ctl, pos);
 }
 
-__global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, Lat lat, MarchPlan mp, int nparts_in,
-                                                                int pstride, CgVecs<double> v,
-                                                                const double* __restrict__ phi, Coef<double> cf) {
+template <class MG>
+__global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg, CgVecs<double> v,
+                                                                const double* __restrict__ phi_base, Coef<double> cf) {
     extern __shared__ __align__(16) unsigned char march_smem[];
+    const MarchWork w = mg.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = w.lat;
+    const MarchPlan& mp = w.mp;
+    const MarchPos& mpos = w.mpos;
+    const UPos& pos = w.pos;
+    const double* phi = phi_base + pos.phioff;
     const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, rowc = 4 * L;
-    const int wg = xcd_remap(blockIdx.x, gridDim.x), per_vec = mp.nseg * mp.nband;
-    const MarchPos mpos = march_pos(lat, mp, wg);
-    const UPos pos = march_unit(lat, mpos.k, wg - mpos.k * per_vec, nparts_in, pstride);
-    cg_finalize(ctl, pos, nparts_in);
+    cg_finalize(ctl, pos, w.nparts_in);
     const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
         cg_publish(ctl, pos);
@@ -552,17 +594,20 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, Lat l
 // and the rows beside it goes to LDS while M at tau is formed from the previous slice's copy,
 // the time link taken from the thread's own element of tau + 1.  Reads x64 and phi once (plus
 // the rows beside each band and one slice per segment), writes t64 once.
-__global__ __launch_bounds__(kMarchCgThreads) void k_ru_apply_march(CgCtl ctl, Lat lat, MarchPlan mp, int nparts_in,
-                                                                    int pstride, const double2* __restrict__ x64,
+template <class MG>
+__global__ __launch_bounds__(kMarchCgThreads) void k_ru_apply_march(CgCtl ctl, MG mg, const double2* __restrict__ x64,
                                                                     double2* __restrict__ t64,
-                                                                    const double* __restrict__ phi, Coef<double> cf,
-                                                                    int filter) {
+                                                                    const double* __restrict__ phi_base,
+                                                                    Coef<double> cf, int filter) {
     extern __shared__ __align__(16) unsigned char march_smem[];
+    const MarchWork w = mg.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = w.lat;
+    const MarchPlan& mp = w.mp;
+    const MarchPos& mpos = w.mpos;
+    const UPos& pos = w.pos;
+    const double* phi = phi_base + pos.phioff;
     const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, rowc = 4 * L;
-    const int wg = xcd_remap(blockIdx.x, gridDim.x), per_vec = mp.nseg * mp.nband;
-    const MarchPos mpos = march_pos(lat, mp, wg);
-    const UPos pos = march_unit(lat, mpos.k, wg - mpos.k * per_vec, nparts_in, pstride);
-    cg_finalize(ctl, pos, nparts_in);
+    cg_finalize(ctl, pos, w.nparts_in);
     const int mode = cg_shared().mode;
     cg_publish(ctl, pos);
     if (!((1 << mode) & filter)) return;
@@ -635,18 +680,20 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_ru_apply_march(CgCtl ctl, L
 // the site itself: each slice's own element is kept in registers for the next.  LDS holds
 // t64(tau) on the band's rows and the rows beside it, alternating between two buffers so that
 // one barrier per slice suffices; the next slice's loads are in flight meanwhile.
-template <typename R>
-__global__ __launch_bounds__(kMarchCgThreads) void k_ru_resid_march(CgCtl ctl, Lat lat, MarchPlan mp, int nparts_in,
-                                                                    int pstride, const double2* __restrict__ b,
+template <typename R, class MG>
+__global__ __launch_bounds__(kMarchCgThreads) void k_ru_resid_march(CgCtl ctl, MG mg, const double2* __restrict__ b,
                                                                     const double2* __restrict__ t64,
-                                                                    const double* __restrict__ phi, Coef<double> cf,
-                                                                    C2<R>* __restrict__ r, int filter) {
+                                                                    const double* __restrict__ phi_base,
+                                                                    Coef<double> cf, C2<R>* __restrict__ r, int filter) {
     extern __shared__ __align__(16) unsigned char march_smem[];
+    const MarchWork w = mg.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = w.lat;
+    const MarchPlan& mp = w.mp;
+    const MarchPos& mpos = w.mpos;
+    const UPos& pos = w.pos;
+    const double* phi = phi_base + pos.phioff;
     const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, rowc = 4 * L;
-    const int wg = xcd_remap(blockIdx.x, gridDim.x), per_vec = mp.nseg * mp.nband;
-    const MarchPos mpos = march_pos(lat, mp, wg);
-    const UPos pos = march_unit(lat, mpos.k, wg - mpos.k * per_vec, nparts_in, pstride);
-    cg_finalize(ctl, pos, nparts_in);
+    cg_finalize(ctl, pos, w.nparts_in);
     if (!((1 << cg_shared().mode) & filter)) {
         cg_publish(ctl, pos);
         return;

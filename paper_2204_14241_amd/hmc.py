@@ -532,6 +532,20 @@ class Batch:
     def set_step_graphs(self, enable=True):
         self._call("hmc_batch_set_step_graphs", 1 if enable else 0)
 
+    def set_cg_march(self, rows=0, slices=0, precision=None):
+        """Step A and the reliable update as marches, each lattice with its own cut of at most
+        `rows` rows per band (hmc_batch_set_cg_march); rows = 0 keeps the tile kernels."""
+        pr = {None: -1, "fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]
+        self._call("hmc_batch_set_cg_march", pr, int(rows), int(slices))
+
+    def cg_march(self, chain, precision="mixed"):
+        """(rows, slices) of chain's step-A cut and (rows, slices) of its reliable-update cut in
+        `precision` (0 rows: the tile kernels)."""
+        v = [ctypes.c_int() for _ in range(4)]
+        self._call("hmc_batch_get_cg_march", int(chain), {"fp64": HMC_FP64, "mixed": HMC_MIXED}[precision],
+                   *[ctypes.byref(x) for x in v])
+        return (v[0].value, v[1].value), (v[2].value, v[3].value)
+
     def set_cg_workgroups(self, n, precision=None):
         pr = {None: -1, "fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]
         self._call("hmc_batch_set_cg_workgroups", pr, int(n))

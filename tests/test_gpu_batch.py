@@ -34,6 +34,15 @@ def dev(a, dtype=None):
     return (t.to(dtype) if dtype is not None else t).cuda()
 
 
+def mirror_cut(h, bt, chain, precision):
+    """Give a one-lattice context the march cuts (step A, reliable update) that chain `chain`
+    of the batch uses, so that the two run the same arithmetic in the same order."""
+    (r, sl), (rr, rs) = bt.cg_march(chain, precision)
+    h.set_cg_march(r, sl, precision)
+    if precision == "mixed":
+        h.set_cg_march(rr, rs, "fp64")
+
+
 def model_of(L, Lt, r):
     return O.Model(L=L, Lt=Lt, r=r)
 
@@ -117,7 +126,7 @@ def test_batch_chain_equals_single_context(hip, precision):
     for i, (L, Lt, r) in enumerate(SMALL):
         h = hip.HMC(L, Lt, n_pf=2, cg_tol=1e-10, precision=precision, model=dict(r=r))
         h.set_cg_workgroups(wg)
-        h.set_cg_march(0)          # the batch's step A (tile kernels)
+        mirror_cut(h, bt, i, precision)          # the batch's march cuts
         x1, st1 = h.cg_solve(dev(phis[i]), dev(bs[i]))
         say(f"  chain {i} {L}x{L}x{Lt}: batch iters {st['iterations'][2 * i:2 * i + 2]} "
             f"single {st1.iterations}")
@@ -182,7 +191,7 @@ def test_batch_trajectory_matches_single_and_oracle(hip, precision):
         h = hip.HMC(L, Lt, n_pf=n_pf, eps=eps, n_leap=n_leap, cg_tol=1e-12, precision=precision,
                     model=dict(r=r))
         h.set_cg_workgroups(8)
-        h.set_cg_march(0)          # the batch's step A (tile kernels)
+        mirror_cut(h, bt, i, precision)          # the batch's march cuts
         p1 = dev(ins[i][0])
         s1 = h.trajectory(p1, dev(ins[i][1]), dev(ins[i][2]), u[i])
         assert s1["dH"] == dH, (i, s1["dH"], dH)
@@ -269,9 +278,39 @@ def test_batch_full_workload(hip):
                 model=dict(r=r))
     h.set_cg_workgroups(wg, "mixed")
     h.set_cg_workgroups(bt.cg_workgroups()["fp64"], "fp64")
-    h.set_cg_march(0)          # the batch's step A (tile kernels)
+    mirror_cut(h, bt, i, "mixed")          # the batch's march cuts
     p1 = dev(ins[i][0])
     s1 = h.trajectory(p1, dev(ins[i][1]), dev(ins[i][2]), u[i])
     assert s1["dH"] == st["dH_chains"][i]
     assert torch.equal(p1, bt.unpack_phi(phi)[i])
+    bt.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_march_cuts_and_tile_kernels(hip, precision):
+    """By default every lattice of a batch marches step A and the reliable update, each with a
+    cut its L allows; the tile kernels (rows 0) solve the same systems with iteration counts
+    that differ only through the order of the FP64 partial sums."""
+    chains = SMALL
+    g = S.rng(305)
+    phis = [S.draw_phi(g, L, Lt, 0.5) for L, Lt, _ in chains]
+    bs = [S.draw_spinor(g, L, Lt, 1) for L, Lt, _ in chains]
+    bt = hip.Batch(chains, n_pf=1, cg_tol=1e-10, precision=precision)
+    phi, b = packed(bt, phis), packed(bt, bs, spinor=True)
+    cuts = [bt.cg_march(i, precision) for i in range(len(chains))]
+    say(f"batch march cuts {precision}: {cuts}")
+    for (L, Lt, _), ((r, sl), (rr, rs)) in zip(chains, cuts):
+        assert 1 <= r <= L and 1 <= sl <= Lt
+        assert 1 <= rr <= L and 1 <= rs <= Lt
+    x, st = bt.cg_solve(phi, b)
+    bt.set_cg_march(0)
+    assert all(bt.cg_march(i, precision) == ((0, 0), (0, 0)) for i in range(len(chains)))
+    x0, st0 = bt.cg_solve(phi, b)
+    xs, xs0 = bt.unpack_spinors(x), bt.unpack_spinors(x0)
+    for i, (L, Lt, r) in enumerate(chains):
+        m = model_of(L, Lt, r)
+        for xx in (xs[i], xs0[i]):
+            e = np.linalg.norm(bs[i][0] - O.apply_MdagM(m, phis[i], xx.cpu().numpy().reshape(bs[i].shape)[0]))
+            assert e <= 1e-10 * np.linalg.norm(bs[i][0])
+        assert abs(st["iterations"][i] - st0["iterations"][i]) <= max(2, st0["iterations"][i] // 50)
     bt.close()

@@ -26,6 +26,15 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
+def mirror_cut(h, bt, chain, precision):
+    """Give a one-lattice context the march cuts (step A, reliable update) that chain `chain`
+    of the batch uses, so that the two run the same arithmetic in the same order."""
+    (r, sl), (rr, rs) = bt.cg_march(chain, precision)
+    h.set_cg_march(r, sl, precision)
+    if precision == "mixed":
+        h.set_cg_march(rr, rs, "fp64")
+
+
 def resid(m, phi, b, x):
     return np.linalg.norm(b - O.apply_MdagM(m, phi, x)) / np.linalg.norm(b)
 
@@ -124,7 +133,7 @@ def test_pcg_batch_matches_oracle_and_single(hip, precision):
             assert resid(m, phis[i], bs[i][k], xs[i][k].cpu().numpy()) <= 1e-10
         h = hip.HMC(L, Lt, n_pf=2, cg_tol=1e-10, precision=precision, precond="fourier", model=dict(r=r))
         h.set_cg_workgroups(8)
-        h.set_cg_march(0)          # the batch's step A (tile kernels)
+        mirror_cut(h, bt, i, precision)          # the batch's march cuts
         x1, st1 = h.cg_solve(dev(phis[i]), dev(bs[i]))
         assert st1.iterations == st["iterations"][2 * i:2 * i + 2]
         assert torch.equal(x1.reshape(xs[i].shape), xs[i])
@@ -155,7 +164,7 @@ def test_pcg_batch_full_chunks(hip, precision, Lt):
         assert resid(m, phis[i], bs[i][0], xs[i][0].cpu().numpy()) <= 1e-10
         h = hip.HMC(L, Lt_, n_pf=1, cg_tol=1e-10, precision=precision, precond="fourier", model=dict(r=r))
         h.set_cg_workgroups(8)
-        h.set_cg_march(0)          # the batch's step A (tile kernels)
+        mirror_cut(h, bt, i, precision)          # the batch's march cuts
         x1, st1 = h.cg_solve(dev(phis[i]), dev(bs[i]))
         assert st1.iterations == st["iterations"][i:i + 1]
         assert torch.equal(x1.reshape(xs[i].shape), xs[i])
@@ -181,7 +190,7 @@ def test_pcg_batch_uneven_time_extents(hip, precision):
         assert resid(m, phis[i], bs[i][0], xs[i][0].cpu().numpy()) <= 1e-10
         h = hip.HMC(L, Lt, n_pf=1, cg_tol=1e-10, precision=precision, precond="fourier", model=dict(r=r))
         h.set_cg_workgroups(8)
-        h.set_cg_march(0)          # the batch's step A (tile kernels)
+        mirror_cut(h, bt, i, precision)          # the batch's march cuts
         x1, st1 = h.cg_solve(dev(phis[i]), dev(bs[i]))
         assert st1.iterations == st["iterations"][i:i + 1]
         assert torch.equal(x1.reshape(xs[i].shape), xs[i])
