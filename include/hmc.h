@@ -386,8 +386,9 @@ int hmc_get_cg_workgroups(const hmc_ctx* ctx, int precision);
 int hmc_set_mdm_shape(hmc_ctx* ctx, int precision, int rows, int slices);
 int hmc_get_mdm_shape(const hmc_ctx* ctx, int precision, int n, int* rows, int* slices, int* workgroups);
 
-/* CG step A (the direction update, t = M p and the fused x update) as a march (one lattice,
- * nearest-neighbour operator): each workgroup owns a band of `rows` lattice rows of one
+/* CG step A (the direction update, t = M p and the fused x update) as a march (one lattice;
+ * with the production model's two-site hops the band carries two rows beside it on either side
+ * instead of one): each workgroup owns a band of `rows` lattice rows of one
  * right-hand side and walks `slices` consecutive time slices, holding the new direction of two
  * consecutive slices in LDS and loading the next slice while it computes the current one, so
  * that every value of r (z), p, x and phi leaves HBM once.  rows = 0 switches back to the tile
@@ -395,8 +396,10 @@ int hmc_get_mdm_shape(const hmc_ctx* ctx, int precision, int n, int* rows, int* 
  * contexts: 8 rows (FP32) / 4 rows (FP64), 8 slices, or the autotuner's choice.  precision:
  * HMC_FP64, HMC_MIXED or -1 for both.  The algebra is that of the tile kernels; only the order
  * of the FP64 partial sums differs.  One-lattice contexts only (HMC_ERR_INVALID_ARG on a
- * batch); lattices whose band does not fit (rows + 2 rows of one thread per element, at most
- * 512 threads) keep the tile kernels. */
+ * batch: hmc_batch_set_cg_march); lattices whose band does not fit (rows + 2 rows, or rows + 4
+ * with the two-site hops, of one thread per element in FP64 or per pair in FP32, at most 512
+ * threads) keep the tile kernels.  The FP64 setting also cuts the reliable update's FP64
+ * stencils into marches (nearest-neighbour operator). */
 int hmc_set_cg_march(hmc_ctx* ctx, int precision, int rows, int slices);
 /* The setting in use for `precision` (host ints; rows 0: the tile kernels). */
 int hmc_get_cg_march(const hmc_ctx* ctx, int precision, int* rows, int* slices);

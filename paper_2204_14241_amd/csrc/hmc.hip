@@ -740,24 +740,25 @@ static Launch<GeoOne> launch_one(const hmc_ctx* c, int n) {
     // step A as a march: rows per band so that the band and its two neighbour rows have one
     // thread each (at most kMarchCgThreads); slices per segment for about one workgroup per
     // compute unit over all right-hand sides (at least 2)
-    if (c->cgm_rows[pi] > 0 && !l.nn2) {
-        const int per_row = pi ? c->L / 2 : c->L;
-        const int rows = std::max(1, std::min(c->cgm_rows[pi], kMarchCgThreads / per_row - 2));
-        const size_t lds = march_cg_lds<R>(rows, c->L);
-        if (rows >= 1 && (rows + 2) * per_row <= kMarchCgThreads && lds <= (size_t(64) << 10)) {
+    // (the production model's two-site hops need two rows beside the band on either side)
+    if (c->cgm_rows[pi] > 0) {
+        const int per_row = pi ? c->L / 2 : c->L, H = l.nn2 ? 2 : 1;
+        const int rows = std::max(1, std::min(c->cgm_rows[pi], kMarchCgThreads / per_row - 2 * H));
+        const size_t lds = march_cg_lds<R>(rows + 2 * H - 2, c->L);
+        if (rows >= 1 && (rows + 2 * H) * per_row <= kMarchCgThreads && lds <= (size_t(64) << 10)) {
             const int nband = (c->L + std::min(rows, c->L) - 1) / std::min(rows, c->L);
             int seg = c->cgm_seg[pi];
             if (seg <= 0) seg = std::max(2, (c->Lt * nband * n + 255) / 256);
             l.cgm = make_march_plan(c->L, c->Lt, rows, seg);
             l.cgm_per_unit = l.cgm.nband * l.cgm.nseg;
             if (l.cgm_per_unit > c->pstride) l.cgm_per_unit = 0;   // partial slots: keep the tile kernels
-            l.cgm_threads = ((std::min(rows, c->L) + 2) * per_row + 63) / 64 * 64;
+            l.cgm_threads = ((std::min(rows, c->L) + 2 * H) * per_row + 63) / 64 * 64;
             l.cgm_lds = lds;
         }
     }
     // the reliable update's FP64 marches: one thread per element of the band and its two
     // neighbour rows, as the FP64 step-A march
-    if (l.cgm_per_unit > 0 && c->cgm_rows[0] > 0) {
+    if (l.cgm_per_unit > 0 && c->cgm_rows[0] > 0 && !l.nn2) {
         const int rows = std::max(1, std::min(c->cgm_rows[0], kMarchCgThreads / c->L - 2));
         const size_t lds = march_cg_lds<double>(rows, c->L);
         if ((rows + 2) * c->L <= kMarchCgThreads && lds <= (size_t(64) << 10)) {
@@ -906,20 +907,27 @@ template <typename R, class Geo>
 static void launch_step_a_march(hmc_ctx* c, const Launch<Geo>& lc, const CgCtl& ka, const CgVecs<R>& v, const R* phik,
                                 const Coef<R>& cf, int grid, int threads, size_t lds, const hipEvent_t* ev,
                                 hipStream_t s) {
-    auto go = [&](auto mg) {
+    auto go = [&](auto mg, auto nn2) {
         using MG = decltype(mg);
+        constexpr bool N2 = decltype(nn2)::value;
         if constexpr (sizeof(R) == sizeof(float)) {
-            if (ev) hipExtLaunchKernelGGL((k_cg_a2_march<MG>), dim3(grid), dim3(threads), lds, s, ev[0], ev[1], 0, ka, mg,
-                                          v, phik, cf);
-            else hipLaunchKernelGGL((k_cg_a2_march<MG>), dim3(grid), dim3(threads), lds, s, ka, mg, v, phik, cf);
+            if (ev) hipExtLaunchKernelGGL((k_cg_a2_march<MG, N2>), dim3(grid), dim3(threads), lds, s, ev[0], ev[1], 0,
+                                          ka, mg, v, phik, cf);
+            else hipLaunchKernelGGL((k_cg_a2_march<MG, N2>), dim3(grid), dim3(threads), lds, s, ka, mg, v, phik, cf);
         } else {
-            if (ev) hipExtLaunchKernelGGL((k_cg_a_march<MG>), dim3(grid), dim3(threads), lds, s, ev[0], ev[1], 0, ka, mg,
-                                          v, phik, cf);
-            else hipLaunchKernelGGL((k_cg_a_march<MG>), dim3(grid), dim3(threads), lds, s, ka, mg, v, phik, cf);
+            if (ev) hipExtLaunchKernelGGL((k_cg_a_march<MG, N2>), dim3(grid), dim3(threads), lds, s, ev[0], ev[1], 0,
+                                          ka, mg, v, phik, cf);
+            else hipLaunchKernelGGL((k_cg_a_march<MG, N2>), dim3(grid), dim3(threads), lds, s, ka, mg, v, phik, cf);
         }
     };
-    if constexpr (std::is_same<Geo, GeoOne>::value) go(MGeoOne{lc.cg.lat, lc.cgm, lc.cg.bpr, c->pstride});
-    else go(lc.bm);
+    // batches march the nearest-neighbour operator only
+    if constexpr (std::is_same<Geo, GeoOne>::value) {
+        const MGeoOne mg{lc.cg.lat, lc.cgm, lc.cg.bpr, c->pstride};
+        if (lc.nn2) go(mg, std::true_type{});
+        else go(mg, std::false_type{});
+    } else {
+        go(lc.bm, std::false_type{});
+    }
 }
 
 // One status chunk: `chunk` iterations (steps A and B, and the preconditioner passes), then
@@ -964,13 +972,15 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
             launch_step_a_march<R, Geo>(c, lc, ka, v, phik, cf, mgrid, mthreads, mlds, ea, s);
             LAUNCHCHK();
             if constexpr (sizeof(R) == sizeof(float)) {
-                if (e) hipExtLaunchKernelGGL((k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0, s, e[2], e[3], 0, kb,
-                                             geo, v, phik, cf);
-                else hipLaunchKernelGGL((k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
+                if (e) HMC_EXT_LAUNCH_NN2(lc.nn2, (k_cg_b2<Geo, true>), (k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock),
+                                          0, s, e[2], e[3], 0, kb, geo, v, phik, cf);
+                else HMC_LAUNCH_NN2(lc.nn2, (k_cg_b2<Geo, true>), (k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0, s,
+                                    kb, geo, v, phik, cf);
             } else {
-                if (e) hipExtLaunchKernelGGL((k_cg_b<R, Geo, false>), dim3(grid), dim3(kBlock), 0, s, e[2], e[3], 0,
-                                             kb, geo, v, phik, cf);
-                else hipLaunchKernelGGL((k_cg_b<R, Geo, false>), dim3(grid), dim3(kBlock), 0, s, kb, geo, v, phik, cf);
+                if (e) HMC_EXT_LAUNCH_NN2(lc.nn2, (k_cg_b<R, Geo, true>), (k_cg_b<R, Geo, false>), dim3(grid),
+                                          dim3(kBlock), 0, s, e[2], e[3], 0, kb, geo, v, phik, cf);
+                else HMC_LAUNCH_NN2(lc.nn2, (k_cg_b<R, Geo, true>), (k_cg_b<R, Geo, false>), dim3(grid), dim3(kBlock), 0,
+                                    s, kb, geo, v, phik, cf);
             }
             LAUNCHCHK();
             if (lc.pc) {
@@ -1895,7 +1905,7 @@ static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int 
         }
         // step A as a march (nearest neighbours): rows per band x slices per segment; in a
         // batch the rows are a cap, each lattice taking at most what its band allows
-        if (result == HMC_OK && !c->cf64.nn2) {
+        if (result == HMC_OK && !(c->is_batch && c->cf64.nn2)) {
             static const int rows32[] = {4, 6, 8, 10}, rows64[] = {2, 3, 4};
             static const int segs32[] = {4, 6, 8}, segs64[] = {4, 6, 8, 12};
             static const int brows32[] = {4, 8, 12, 16}, bsegs[] = {4, 8};
@@ -1915,7 +1925,8 @@ static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int 
                 return rc;
             };
             for (int a = 0; a < nr && result == HMC_OK; ++a) {
-                if (!c->is_batch && ((rows[a] + 2) * per_row > kMarchCgThreads || rows[a] > c->L)) continue;
+                if (!c->is_batch && ((rows[a] + (c->cf64.nn2 ? 4 : 2)) * per_row > kMarchCgThreads || rows[a] > c->L))
+                    continue;
                 for (int q = 0; q < ns && result == HMC_OK; ++q) {
                     if (out->mtried[pi] >= HMC_TUNE_MARCH_MAX) break;
                     result = apply_march(rows[a], segs[q]);

@@ -15,8 +15,10 @@
 // consecutive segments and the rows beside a band are read through the same L2.  A second form
 // of the normal operator takes one slice per workgroup and forms chi(tau - 1) itself.
 //
-// The nearest-neighbour operator only (the two-site hops need bands two rows wider); the
-// arithmetic per site is that of the two-pass kernels, in the same order.
+// The one-pass normal operator and the reliable-update marches take the nearest-neighbour
+// operator only; step A also takes the production model's two-site hops, with two rows beside
+// the band on either side.  The arithmetic per site is that of the two-pass kernels, in the same
+// order.
 #pragma once
 
 #include "kernels.h"
@@ -62,19 +64,33 @@ __host__ __device__ inline size_t march_lds(int Rrows, int L) {
 // the two sites.  The arithmetic of the two-pass pair stencil (dslash_pair) in its order, so
 // both M (tt = v(tau + 1), ts = s_tau) and M^dagger (tt = v(tau - 1), ts = s_{tau-1}) come out
 // as the separate passes compute them.  cen receives v(tau) at the pair.
+// NN2: also the hops by two sites of the production model (rows r +- 2 of the buffer, the pairs
+// (y - 2, y - 1) and (y + 2, y + 3)), added as the two-pass pair stencil adds them.
+template <bool NN2 = false>
 __device__ __forceinline__ void stencil_pair_lds(const float2* __restrict__ chi, int r, int x, int y, int L,
                                                  float2 P1, float2 P2, float2 P3, const Coef<float>& cf, float ts,
                                                  const float4 (&tt)[4], float4 (&o)[4], float4 (&cen)[4]) {
     const int rowc = 4 * L;
     auto lds4 = [&](int rr, int c, int yy) { return *reinterpret_cast<const float4*>(chi + rr * rowc + c * L + yy); };
     const int yl = y == 0 ? L - 1 : y - 1, yr = y + 2 == L ? 0 : y + 2;
+    const int ym2 = y == 0 ? L - 2 : y - 2;
 #pragma unroll
     for (int c = 0; c < 4; ++c) cen[c] = lds4(r, c, y);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int a = c >> 1;
         const float4 xp = lds4(r + 1, c, y), xm = lds4(r - 1, c, y), t4 = tt[c];
-        const float2 lo = chi[r * rowc + c * L + yl], hi = chi[r * rowc + c * L + yr];
+        float2 lo, hi;
+        float4 m2, p2;
+        if constexpr (NN2) {
+            m2 = lds4(r, c, ym2);
+            p2 = lds4(r, c, yr);
+            lo = make_float2(m2.z, m2.w);
+            hi = make_float2(p2.x, p2.y);
+        } else {
+            lo = chi[r * rowc + c * L + yl];
+            hi = chi[r * rowc + c * L + yr];
+        }
         const float4 ce = cen[c];
         const float dg = cf.diag[a], h0 = cf.hop[a][0], h1 = cf.hop[a][1];
         float4 v;
@@ -82,6 +98,14 @@ __device__ __forceinline__ void stencil_pair_lds(const float2* __restrict__ chi,
         v.y = dg * ce.y + h0 * (xp.y + xm.y) + h1 * (lo.y + ce.w) + ts * t4.y;
         v.z = dg * ce.z + h0 * (xp.z + xm.z) + h1 * (ce.x + hi.x) + ts * t4.z;
         v.w = dg * ce.w + h0 * (xp.w + xm.w) + h1 * (ce.y + hi.y) + ts * t4.w;
+        if constexpr (NN2) {
+            const float4 xx = f4add(lds4(r + 2, c, y), lds4(r - 2, c, y)), yy = f4add(m2, p2);
+            const float u0 = cf.hop2[a][0], u1 = cf.hop2[a][1];
+            v.x += u0 * xx.x + u1 * yy.x;
+            v.y += u0 * xx.y + u1 * yy.y;
+            v.z += u0 * xx.z + u1 * yy.z;
+            v.w += u0 * xx.w + u1 * yy.w;
+        }
         o[c] = v;
     }
     const float g0 = cf.cpl * float((x & 1) ? -1 : 1), g1 = -g0;   // (-1)^(x+y), y even
@@ -116,12 +140,14 @@ __device__ __forceinline__ void mdag_pair_lds(const float2* __restrict__ chi, in
 
 // FP64 form of stencil_pair_lds at the site (x, y), phi(tau) there given as (q1, q2, q3) before
 // the coupling and the staggered sign are applied.
+template <bool NN2 = false>
 __device__ __forceinline__ void stencil_site_lds(const double2* __restrict__ chi, int r, int x, int y, int L,
                                                  double f1, double f2, double f3, const Coef<double>& cf,
                                                  double ts, const double2 (&tt)[4], double2 (&o)[4],
                                                  double2 (&cen)[4]) {
     const int rowc = 4 * L;
     const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
+    const int ypp = y + 2 >= L ? y + 2 - L : y + 2, ymm = y < 2 ? y - 2 + L : y - 2;
 #pragma unroll
     for (int c = 0; c < 4; ++c) cen[c] = chi[r * rowc + c * L + y];
 #pragma unroll
@@ -133,6 +159,10 @@ __device__ __forceinline__ void stencil_site_lds(const double2* __restrict__ chi
         v = axpy<double>(cf.hop[a][0], hx, v);
         v = axpy<double>(cf.hop[a][1], hy, v);
         v = axpy<double>(ts, tt[c], v);
+        if constexpr (NN2) {
+            v = axpy<double>(cf.hop2[a][0], add<double>(chi[(r + 2) * rowc + c * L + y], chi[(r - 2) * rowc + c * L + y]), v);
+            v = axpy<double>(cf.hop2[a][1], add<double>(chi[r * rowc + c * L + ypp], chi[r * rowc + c * L + ymm]), v);
+        }
         o[c] = v;
     }
     const double g = cf.cpl * double(((x + y) & 1) ? -1 : 1);
@@ -336,7 +366,7 @@ struct MGeoBatch {
     }
 };
 
-template <class MG>
+template <class MG, bool NN2>
 __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG mg, CgVecs<float> v,
                                                                  const float* __restrict__ phi_base, Coef<float> cf) {
     extern __shared__ __align__(16) unsigned char march_smem[];
@@ -347,6 +377,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG m
     const UPos& pos = w.pos;
     const float* phi = phi_base + pos.phioff;
     const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, P = L / 2, rowc = 4 * L;
+    constexpr int H = NN2 ? 2 : 1;    // rows beside the band on either side
     cg_finalize(ctl, pos, w.nparts_in);
     const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
@@ -364,13 +395,13 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG m
     float2* t = v.t + off;
     const float2* z = v.z + off;
     float2* cur = reinterpret_cast<float2*>(march_smem);
-    float2* nxt = cur + size_t(mp.R + 2) * rowc;
+    float2* nxt = cur + size_t(mp.R + 2 * H) * rowc;
     // this thread's element: row lr of the band buffer (0 and nr + 1 are the rows beside the band)
-    const int e = threadIdx.x, nh = (mpos.nr + 2) * P;
+    const int e = threadIdx.x, nh = (mpos.nr + 2 * H) * P;
     const bool act = e < nh;
     const int lr = act ? e / P : 0, py = act ? e - lr * P : 0, y = 2 * py;
-    const int xrow = wrap_row(mpos.x0 - 1 + lr, L);
-    const bool inner = act && lr >= 1 && lr <= mpos.nr;
+    const int xrow = wrap_row(mpos.x0 - H + lr, L);
+    const bool inner = act && lr >= H && lr < mpos.nr + H;
     const int ro = xrow * L + y;                      // offset of the element within a slice
     float4 rz[4], rp[4], rx[4], rq[4];
     float2 f1 = make_float2(0.f, 0.f), f2 = f1, f3 = f1;
@@ -437,7 +468,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG m
         __syncthreads();
         if (inner) {
             float4 o[4], cen[4];
-            stencil_pair_lds(cur, lr, xrow, y, L, g1, g2, g3, cf, tau == Lt - 1 ? -1.f : 1.f, pnx, o, cen);
+            stencil_pair_lds<NN2>(cur, lr, xrow, y, L, g1, g2, g3, cf, tau == Lt - 1 ? -1.f : 1.f, pnx, o, cen);
             float acc = 0.f;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -462,7 +493,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG m
     cg_publish(ctl, pos);
 }
 
-template <class MG>
+template <class MG, bool NN2>
 __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg, CgVecs<double> v,
                                                                 const double* __restrict__ phi_base, Coef<double> cf) {
     extern __shared__ __align__(16) unsigned char march_smem[];
@@ -473,6 +504,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg
     const UPos& pos = w.pos;
     const double* phi = phi_base + pos.phioff;
     const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, rowc = 4 * L;
+    constexpr int H = NN2 ? 2 : 1;    // rows beside the band on either side
     cg_finalize(ctl, pos, w.nparts_in);
     const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
@@ -490,12 +522,12 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg
     double2* t = v.t + off;
     const double2* z = v.z + off;
     double2* cur = reinterpret_cast<double2*>(march_smem);
-    double2* nxt = cur + size_t(mp.R + 2) * rowc;
-    const int e = threadIdx.x, nh = (mpos.nr + 2) * L;
+    double2* nxt = cur + size_t(mp.R + 2 * H) * rowc;
+    const int e = threadIdx.x, nh = (mpos.nr + 2 * H) * L;
     const bool act = e < nh;
     const int lr = act ? e / L : 0, y = act ? e - lr * L : 0;
-    const int xrow = wrap_row(mpos.x0 - 1 + lr, L);
-    const bool inner = act && lr >= 1 && lr <= mpos.nr;
+    const int xrow = wrap_row(mpos.x0 - H + lr, L);
+    const bool inner = act && lr >= H && lr < mpos.nr + H;
     const int ro = xrow * L + y;
     double2 rz[4], rp[4], rx[4], rq[4];
     double f1 = 0.0, f2 = 0.0, f3 = 0.0;
@@ -561,7 +593,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg
         __syncthreads();
         if (inner) {
             double2 o[4], cen[4];
-            stencil_site_lds(cur, lr, xrow, y, L, g1, g2, g3, cf, tau == Lt - 1 ? -1.0 : 1.0, pnx, o, cen);
+            stencil_site_lds<NN2>(cur, lr, xrow, y, L, g1, g2, g3, cf, tau == Lt - 1 ? -1.0 : 1.0, pnx, o, cen);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 t[size_t(c) * vol + size_t(tau) * LL + ro] = o[c];

@@ -93,6 +93,31 @@ def test_nnn_cg_true_residual(hip, precision, precond):
     assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b[0])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_nnn_march_matches_tile_kernels(hip, precision):
+    """Step A as a march with the two-site hops (two rows beside each band, bands of one row, a
+    ragged last band and one band for the lattice): the same solve as the tile kernels, so the
+    iteration counts agree up to the order of the FP64 partial sums, and the true residual by
+    the oracle's operator meets the bar."""
+    L, Lt = 12, 40
+    m = model(L, Lt)
+    g = S.rng(825)
+    phi = S.draw_phi(g, L, Lt, 0.5)
+    b = S.draw_spinor(g, L, Lt, 1)
+    h = hip.HMC(L, Lt, cg_tol=1e-10, precision=precision, model=PROD)
+    h.set_cg_march(0)
+    _, st0 = h.cg_solve(dev(phi), dev(b))
+    for rows, slices in ((1, 3), (5, 8), (12, 40)):
+        h.set_cg_march(rows, slices, precision)
+        x, st = h.cg_solve(dev(phi), dev(b))
+        say(f"nnn march {precision} rows {rows} slices {slices}: iterations {st.iterations} "
+            f"(tile {st0.iterations})")
+        assert st.status == 0
+        assert abs(st.iterations[0] - st0.iterations[0]) <= max(2, st0.iterations[0] // 50)
+        r = b[0] - O.apply_MdagM(m, phi, host(x)[0])
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b[0])
+
+
 def test_nnn_force_matches_oracle(hip):
     L, Lt = 6, 10
     m = model(L, Lt)
