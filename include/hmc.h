@@ -404,6 +404,16 @@ int hmc_set_cg_march(hmc_ctx* ctx, int precision, int rows, int slices);
 /* The setting in use for `precision` (host ints; rows 0: the tile kernels). */
 int hmc_get_cg_march(const hmc_ctx* ctx, int precision, int* rows, int* slices);
 
+/* Whether CG step B (r -= alpha M^dagger t, Methods C) also marches when step A does, with
+ * step A's cut (enable != 0), or runs its tile kernel (0).  The march reads t once through LDS
+ * (helps where the tile kernel re-reads t from HBM: FP64, several right-hand sides); the tile
+ * kernel reads t while the MALL still holds it (one FP32 right-hand side).  Defaults: on for
+ * FP64, off for FP32; hmc_autotune times both.  precision: HMC_FP64, HMC_MIXED or -1.  Results
+ * depend on it only through the order of the FP64 partial sums.  hmc_get_cg_march_step_b
+ * returns the setting (-1 on a bad argument). */
+int hmc_set_cg_march_step_b(hmc_ctx* ctx, int precision, int enable);
+int hmc_get_cg_march_step_b(const hmc_ctx* ctx, int precision);
+
 /* Result of hmc_autotune (host struct).  Index [0] FP64, [1] mixed precision. */
 #define HMC_TUNE_MAX 12
 #define HMC_TUNE_MARCH_MAX 16
@@ -421,6 +431,9 @@ typedef struct hmc_tune_result {
     int    mtried_slices[2][HMC_TUNE_MARCH_MAX];
     double mtried_us[2][HMC_TUNE_MARCH_MAX];
     int    from_cache;         /* 1: the shapes came from the on-disk cache, nothing was timed */
+    int    march_step_b[2];    /* 1: step B marches with step A's cut; 0: its tile kernel      */
+    double step_b_us[2][2];    /* us per iteration with step B's tile kernel [0] and march [1] at
+                                  the chosen cut (0: not timed)                                */
 } hmc_tune_result;
 
 /* Autotuner of the CG launch shape.  For each precision, times 100 CG iterations on the
@@ -513,10 +526,12 @@ int hmc_batch_set_step_graphs(hmc_batch* batch, int enable);
  * searches them.  precision: HMC_FP64, HMC_MIXED or -1 for both.  Results depend on the cut only
  * through the order of the FP64 partial sums; a chain reproduces, bit for bit, a one-lattice
  * context given the same cut.  hmc_batch_get_cg_march reports the cut chain `chain` uses in
- * `precision` (0 rows: the tile kernels). */
+ * `precision` (0 rows: the tile kernels) and whether step B marches with it. */
 int hmc_batch_set_cg_march(hmc_batch* batch, int precision, int rows, int slices);
 int hmc_batch_get_cg_march(const hmc_batch* batch, int chain, int precision, int* rows, int* slices,
-                           int* ru_rows, int* ru_slices);
+                           int* ru_rows, int* ru_slices, int* step_b);
+/* As hmc_set_cg_march_step_b, for the batch. */
+int hmc_batch_set_cg_march_step_b(hmc_batch* batch, int precision, int enable);
 
 /* Replace the run parameters; n_pf must equal the value given at creation. */
 int hmc_batch_set_params(hmc_batch* batch, const hmc_params* params);

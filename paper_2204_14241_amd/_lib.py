@@ -35,14 +35,14 @@ EXPORTED = [
     "hmc_strerror", "hmc_last_error", "hmc_test_site", "hmc_test_xcd_remap", "hmc_test_tile_span", "hmc_test_fft",
     "hmc_test_fft_freq", "hmc_test_precond", "hmc_test_apply_precond", "hmc_stream_probe",
     "hmc_set_kernel_timing", "hmc_get_kernel_times", "hmc_set_cg_workgroups",
-    "hmc_get_cg_workgroups", "hmc_set_mdm_shape", "hmc_get_mdm_shape", "hmc_set_cg_march", "hmc_get_cg_march", "hmc_leapfrog", "hmc_autotune", "hmc_set_graphs", "hmc_set_step_graphs",
+    "hmc_get_cg_workgroups", "hmc_set_mdm_shape", "hmc_get_mdm_shape", "hmc_set_cg_march", "hmc_get_cg_march", "hmc_set_cg_march_step_b", "hmc_get_cg_march_step_b", "hmc_leapfrog", "hmc_autotune", "hmc_set_graphs", "hmc_set_step_graphs",
     "hmc_set_metric", "hmc_metric_momenta", "hmc_metric_kinetic", "hmc_metric_norm2",
     "hmc_metric_accumulate", "hmc_tuner_init", "hmc_tuner_add_step", "hmc_tuner_add_jump",
     "hmc_tuner_best_length", "hmc_jitter", "hmc_warmup_iteration", "hmc_sdw_accumulate",
     "hmc_order_parameter", "hmc_binder",
     "hmc_batch_create", "hmc_batch_destroy", "hmc_batch_workspace_bytes",
     "hmc_batch_set_workspace", "hmc_batch_layout", "hmc_batch_set_cg_workgroups",
-    "hmc_batch_get_cg_workgroups", "hmc_batch_set_graphs", "hmc_batch_set_step_graphs", "hmc_batch_set_cg_march", "hmc_batch_get_cg_march", "hmc_batch_set_params",
+    "hmc_batch_get_cg_workgroups", "hmc_batch_set_graphs", "hmc_batch_set_step_graphs", "hmc_batch_set_cg_march", "hmc_batch_get_cg_march", "hmc_batch_set_cg_march_step_b", "hmc_batch_set_params",
     "hmc_batch_apply", "hmc_batch_cg_solve", "hmc_batch_autotune", "hmc_batch_trajectory",
 ]
 
@@ -109,7 +109,8 @@ class HmcTuneResult(ctypes.Structure):
                 ("mtried_rows", (ctypes.c_int * HMC_TUNE_MARCH_MAX) * 2),
                 ("mtried_slices", (ctypes.c_int * HMC_TUNE_MARCH_MAX) * 2),
                 ("mtried_us", (ctypes.c_double * HMC_TUNE_MARCH_MAX) * 2),
-                ("from_cache", ctypes.c_int)]
+                ("from_cache", ctypes.c_int), ("march_step_b", ctypes.c_int * 2),
+                ("step_b_us", (ctypes.c_double * 2) * 2)]
 
 
 def tune_dict(r):
@@ -124,6 +125,8 @@ def tune_dict(r):
     out["march_tried"] = {names[i]: [(r.mtried_rows[i][j], r.mtried_slices[i][j], r.mtried_us[i][j])
                                      for j in range(r.mtried[i])] for i in range(2)}
     out["from_cache"] = r.from_cache
+    out["march_step_b"] = {"fp64": r.march_step_b[0], "mixed": r.march_step_b[1]}
+    out["step_b_us"] = {"fp64": tuple(r.step_b_us[0]), "mixed": tuple(r.step_b_us[1])}
     return out
 
 
@@ -239,7 +242,11 @@ def load():
         "hmc_batch_set_step_graphs": (I, [P, I]),
         "hmc_batch_set_cg_march": (I, [P, I, I, I]),
         "hmc_batch_get_cg_march": (I, [P, I, I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int)]),
+        "hmc_batch_set_cg_march_step_b": (I, [P, I, I]),
+        "hmc_set_cg_march_step_b": (I, [P, I, I]),
+        "hmc_get_cg_march_step_b": (I, [P, I]),
         "hmc_batch_set_params": (I, [P, ctypes.POINTER(HmcParams)]),
         "hmc_batch_apply": (I, [P, I, I, P, P, P, P]),
         "hmc_batch_cg_solve": (I, [P, P, P, P, ctypes.POINTER(I), ctypes.POINTER(D), P]),

@@ -223,6 +223,7 @@ struct hmc_ctx {
     // per segment (0: the default)
     int cgm_rows[2] = {0, 0};
     int cgm_seg[2] = {0, 0};
+    int cgb_march[2] = {1, 0};   // step B marches too (with step A's cut) [FP64, FP32]
     // partial sums the last launched kernel left per unit when its workgroup count is not the
     // CG launch shape's (a march); the next launch's control block takes it over
     int next_nparts = 0;
@@ -597,6 +598,7 @@ struct TuneChoice {
     int bpr[2] = {0, 0};    // [FP64, FP32]
     int mrows[2] = {0, 0};
     int mseg[2] = {0, 0};
+    int mb[2] = {1, 0};     // step B marches too
 };
 struct TuneKey {
     int L, Lt, n, dev;
@@ -607,7 +609,8 @@ struct TuneKey {
 static std::mutex g_tune_mu;
 static std::map<TuneKey, TuneChoice> g_tuned;
 
-// The on-disk cache: one line per key, "<key> bpr64 bpr32 rows64 slices64 rows32 slices32".
+// The on-disk cache: one line per key, "<key> bpr64 bpr32 rows64 slices64 rows32 slices32 stepb64
+// stepb32".
 static std::string tune_cache_path() {
     const char* e = std::getenv("HMC_TUNE_CACHE");
     if (e != nullptr) return (*e == 0 || std::strcmp(e, "off") == 0) ? std::string() : std::string(e);
@@ -639,8 +642,8 @@ static bool tune_cache_lookup(const std::string& key, TuneChoice& out) {
         const size_t kl = key.size();
         if (std::strncmp(line, key.c_str(), kl) != 0 || line[kl] != ' ') continue;
         TuneChoice c;
-        if (std::sscanf(line + kl, "%d %d %d %d %d %d", &c.bpr[0], &c.bpr[1], &c.mrows[0], &c.mseg[0], &c.mrows[1],
-                        &c.mseg[1]) == 6 &&
+        if (std::sscanf(line + kl, "%d %d %d %d %d %d %d %d", &c.bpr[0], &c.bpr[1], &c.mrows[0], &c.mseg[0],
+                        &c.mrows[1], &c.mseg[1], &c.mb[0], &c.mb[1]) == 8 &&
             c.bpr[0] >= 1 && c.bpr[1] >= 1) {
             out = c;
             found = true;   // the last matching line wins
@@ -674,8 +677,8 @@ static void tune_cache_store(const std::string& key, const TuneChoice& c) {
     FILE* f = std::fopen(tmp.c_str(), "w");
     if (f == nullptr) return;
     for (const std::string& l : keep) std::fputs(l.c_str(), f);
-    std::fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), c.bpr[0], c.bpr[1], c.mrows[0], c.mseg[0], c.mrows[1],
-                 c.mseg[1]);
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %d\n", key.c_str(), c.bpr[0], c.bpr[1], c.mrows[0], c.mseg[0],
+                 c.mrows[1], c.mseg[1], c.mb[0], c.mb[1]);
     const bool ok = std::fclose(f) == 0;
     if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) (void)std::remove(tmp.c_str());
 }
@@ -707,6 +710,7 @@ struct Launch {
     MarchPlan cgm{};
     int cgm_threads = 0, cgm_per_unit = 0;
     size_t cgm_lds = 0;
+    bool cgbm = false;    // step B marches with step A's cut
     // the FP64 stencils of the reliable update as marches (with the FP64 march shape, whenever
     // step A marches): plan, threads, LDS and workgroups per unit (0: the tile kernels)
     MarchPlan rum{};
@@ -737,6 +741,7 @@ static Launch<GeoOne> launch_one(const hmc_ctx* c, int n) {
     l.pt_full = c->pc_full[pi];
     l.nn2 = c->cf64.nn2 != 0;
     l.r7 = c->pc_r7;
+    l.cgbm = c->cgb_march[pi] != 0;
     // step A as a march: rows per band so that the band and its two neighbour rows have one
     // thread each (at most kMarchCgThreads); slices per segment for about one workgroup per
     // compute unit over all right-hand sides (at least 2)
@@ -792,6 +797,7 @@ static Launch<GeoBatch> launch_batch(const hmc_ctx* c) {
     l.pt_full = c->pc_full[pi];
     l.nn2 = c->cf64.nn2 != 0;
     l.r7 = c->pc_r7;
+    l.cgbm = c->cgb_march[pi] != 0;
     if (!l.nn2 && c->bi.mgrid[pi] > 0) {
         l.bm = MGeoBatch{c->bi.units[pi], c->bi.mblocks[pi], 0};
         l.bm_grid = c->bi.mgrid[pi];
@@ -901,23 +907,25 @@ static int chunk_launches(int chunk, bool pc) {
     return n + (n & 1);
 }
 
-// Step A as a march: one lattice (every vector cut alike) or a batch (each unit its own cut);
-// ev: start/stop events for a timed launch.
+// Step A (step_b false) or step B as a march: one lattice (every vector cut alike) or a batch
+// (each unit its own cut); ev: start/stop events for a timed launch.
 template <typename R, class Geo>
-static void launch_step_a_march(hmc_ctx* c, const Launch<Geo>& lc, const CgCtl& ka, const CgVecs<R>& v, const R* phik,
-                                const Coef<R>& cf, int grid, int threads, size_t lds, const hipEvent_t* ev,
-                                hipStream_t s) {
+static void launch_step_march(hmc_ctx* c, const Launch<Geo>& lc, bool step_b, const CgCtl& ka, const CgVecs<R>& v,
+                              const R* phik, const Coef<R>& cf, int grid, int threads, size_t lds, const hipEvent_t* ev,
+                              hipStream_t s) {
     auto go = [&](auto mg, auto nn2) {
         using MG = decltype(mg);
         constexpr bool N2 = decltype(nn2)::value;
+        auto launch = [&](auto kern) {
+            if (ev) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, ev[0], ev[1], 0, ka, mg, v, phik, cf);
+            else hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, ka, mg, v, phik, cf);
+        };
         if constexpr (sizeof(R) == sizeof(float)) {
-            if (ev) hipExtLaunchKernelGGL((k_cg_a2_march<MG, N2>), dim3(grid), dim3(threads), lds, s, ev[0], ev[1], 0,
-                                          ka, mg, v, phik, cf);
-            else hipLaunchKernelGGL((k_cg_a2_march<MG, N2>), dim3(grid), dim3(threads), lds, s, ka, mg, v, phik, cf);
+            if (step_b) launch(k_cg_b2_march<MG, N2>);
+            else launch(k_cg_a2_march<MG, N2>);
         } else {
-            if (ev) hipExtLaunchKernelGGL((k_cg_a_march<MG, N2>), dim3(grid), dim3(threads), lds, s, ev[0], ev[1], 0,
-                                          ka, mg, v, phik, cf);
-            else hipLaunchKernelGGL((k_cg_a_march<MG, N2>), dim3(grid), dim3(threads), lds, s, ka, mg, v, phik, cf);
+            if (step_b) launch(k_cg_b_march<MG, N2>);
+            else launch(k_cg_a_march<MG, N2>);
         }
     };
     // batches march the nearest-neighbour operator only
@@ -969,20 +977,28 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
             const hipEvent_t* e = (sample && i == chunk / 2) ? c->tev[kslot] : nullptr;
             // the next iteration's step A too (the solution update alternates between them)
             const hipEvent_t* ea = e ? e : (sample && i == chunk / 2 + 1) ? c->tev[kslot] + 10 : nullptr;
-            launch_step_a_march<R, Geo>(c, lc, ka, v, phik, cf, mgrid, mthreads, mlds, ea, s);
+            launch_step_march<R, Geo>(c, lc, false, ka, v, phik, cf, mgrid, mthreads, mlds, ea, s);
             LAUNCHCHK();
-            if constexpr (sizeof(R) == sizeof(float)) {
-                if (e) HMC_EXT_LAUNCH_NN2(lc.nn2, (k_cg_b2<Geo, true>), (k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock),
-                                          0, s, e[2], e[3], 0, kb, geo, v, phik, cf);
-                else HMC_LAUNCH_NN2(lc.nn2, (k_cg_b2<Geo, true>), (k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0, s,
-                                    kb, geo, v, phik, cf);
+            if (lc.cgbm) {
+                // step B with the same cut; the next kernel reduces its partials
+                launch_step_march<R, Geo>(c, lc, true, kb, v, phik, cf, mgrid, mthreads, mlds, e ? e + 2 : nullptr, s);
+                LAUNCHCHK();
+                c->next_nparts = mparts;
             } else {
-                if (e) HMC_EXT_LAUNCH_NN2(lc.nn2, (k_cg_b<R, Geo, true>), (k_cg_b<R, Geo, false>), dim3(grid),
-                                          dim3(kBlock), 0, s, e[2], e[3], 0, kb, geo, v, phik, cf);
-                else HMC_LAUNCH_NN2(lc.nn2, (k_cg_b<R, Geo, true>), (k_cg_b<R, Geo, false>), dim3(grid), dim3(kBlock), 0,
-                                    s, kb, geo, v, phik, cf);
+                // the tile kernel, which reads t while the MALL still holds it
+                if constexpr (sizeof(R) == sizeof(float)) {
+                    if (e) HMC_EXT_LAUNCH_NN2(lc.nn2, (k_cg_b2<Geo, true>), (k_cg_b2<Geo, false>), dim3(grid),
+                                              dim3(kBlock), 0, s, e[2], e[3], 0, kb, geo, v, phik, cf);
+                    else HMC_LAUNCH_NN2(lc.nn2, (k_cg_b2<Geo, true>), (k_cg_b2<Geo, false>), dim3(grid), dim3(kBlock), 0,
+                                        s, kb, geo, v, phik, cf);
+                } else {
+                    if (e) HMC_EXT_LAUNCH_NN2(lc.nn2, (k_cg_b<R, Geo, true>), (k_cg_b<R, Geo, false>), dim3(grid),
+                                              dim3(kBlock), 0, s, e[2], e[3], 0, kb, geo, v, phik, cf);
+                    else HMC_LAUNCH_NN2(lc.nn2, (k_cg_b<R, Geo, true>), (k_cg_b<R, Geo, false>), dim3(grid),
+                                        dim3(kBlock), 0, s, kb, geo, v, phik, cf);
+                }
+                LAUNCHCHK();
             }
-            LAUNCHCHK();
             if (lc.pc) {
                 int rc = enqueue_pc<R, Geo>(c, lc, v, PEND_RR, s, e ? c->tev[kslot] + 4 : nullptr);
                 if (rc) return rc;
@@ -1835,6 +1851,7 @@ static void apply_choice(hmc_ctx* c, const TuneChoice& ch) {
     for (int pi = 0; pi < 2; ++pi) {
         c->cgm_rows[pi] = ch.mrows[pi];
         c->cgm_seg[pi] = ch.mseg[pi];
+        c->cgb_march[pi] = ch.mb[pi];
     }
     c->generation += 1;
 }
@@ -1846,6 +1863,7 @@ static TuneChoice current_choice(const hmc_ctx* c) {
     for (int pi = 0; pi < 2; ++pi) {
         ch.mrows[pi] = c->cgm_rows[pi];
         ch.mseg[pi] = c->cgm_seg[pi];
+        ch.mb[pi] = c->cgb_march[pi];
     }
     return ch;
 }
@@ -1956,6 +1974,31 @@ static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int 
                 }
             }
             if (result == HMC_OK) result = apply_march(best_r, best_s);
+            // step B as a march too, or the tile kernel, with the chosen cut
+            if (result == HMC_OK && best_r > 0 && (!c->is_batch || c->bi.mgrid[pi] > 0)) {
+                double tb[2] = {1e300, 1e300};
+                for (int mb = 0; mb < 2 && result == HMC_OK; ++mb) {
+                    c->cgb_march[pi] = mb;
+                    c->generation += 1;
+                    float ms = 0.f;
+                    for (int rep = 0; rep < 2; ++rep) {
+                        if (hipEventRecord(e0, s) != hipSuccess) { result = HMC_ERR_HIP; break; }
+                        const int r = c->is_batch ? cg_dispatch_batch(c, phi, b, c->xsol, s)
+                                                  : cg_dispatch(c, phi, b, c->xsol, n, nullptr, s);
+                        if (r != HMC_OK && r != HMC_ERR_NOT_CONVERGED) { result = r; break; }
+                        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { result = HMC_ERR_HIP; break; }
+                    }
+                    if (result != HMC_OK) break;
+                    out->candidates += 1;
+                    tb[mb] = 1e3 * ms / iters;
+                    out->step_b_us[pi][mb] = tb[mb];
+                }
+                c->cgb_march[pi] = tb[1] < tb[0] ? 1 : 0;
+                c->generation += 1;
+                best = std::min(best, std::min(tb[0], tb[1]));
+            }
+            out->march_step_b[pi] = c->cgb_march[pi];
             out->march_rows[pi] = best_r;
             out->march_slices[pi] = best_s;
             out->us_per_iter[pi] = best;
@@ -1968,6 +2011,8 @@ static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int 
         c->cgm_rows[0] = 4;
         c->cgm_rows[1] = 8;
         c->cgm_seg[0] = c->cgm_seg[1] = 8;
+        c->cgb_march[0] = 1;
+        c->cgb_march[1] = 0;
         (void)set_cg_shape(c, HMC_FP64, kDefaultBpr64);
         (void)set_cg_shape(c, HMC_MIXED, kDefaultBpr32);
         return result == HMC_ERR_HIP ? fail(result, "autotune: HIP call failed") : result;
@@ -1982,6 +2027,7 @@ static void choice_result(const TuneChoice& ch, hmc_tune_result* out) {
         out->cg_workgroups[pi] = ch.bpr[pi];
         out->march_rows[pi] = ch.mrows[pi];
         out->march_slices[pi] = ch.mseg[pi];
+        out->march_step_b[pi] = ch.mb[pi];
     }
     out->from_cache = 1;
 }
@@ -2584,6 +2630,21 @@ int hmc_set_cg_march(hmc_ctx* c, int precision, int rows, int slices) {
     return HMC_OK;
 }
 
+int hmc_set_cg_march_step_b(hmc_ctx* c, int precision, int enable) {
+    if (c == nullptr) return fail(HMC_ERR_INVALID_ARG, "ctx is NULL");
+    if (precision != HMC_FP64 && precision != HMC_MIXED && precision != -1)
+        return fail(HMC_ERR_INVALID_ARG, "unknown precision");
+    for (int pi = 0; pi < 2; ++pi)
+        if (precision == -1 || precision == (pi ? HMC_MIXED : HMC_FP64)) c->cgb_march[pi] = enable != 0;
+    c->generation += 1;   // captured graphs hold the launch shape
+    return HMC_OK;
+}
+
+int hmc_get_cg_march_step_b(const hmc_ctx* c, int precision) {
+    if (c == nullptr || (precision != HMC_FP64 && precision != HMC_MIXED)) return -1;
+    return c->cgb_march[precision == HMC_MIXED ? 1 : 0];
+}
+
 int hmc_get_cg_march(const hmc_ctx* c, int precision, int* rows, int* slices) {
     if (c == nullptr || rows == nullptr || slices == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL argument");
     if (precision != HMC_FP64 && precision != HMC_MIXED) return fail(HMC_ERR_INVALID_ARG, "unknown precision");
@@ -3158,9 +3219,15 @@ int hmc_batch_set_cg_march(hmc_batch* hb, int precision, int rows, int slices) {
     return rc;
 }
 
+int hmc_batch_set_cg_march_step_b(hmc_batch* hb, int precision, int enable) {
+    if (hb == nullptr) return fail(HMC_ERR_INVALID_ARG, "NULL batch");
+    return hmc_set_cg_march_step_b(&hb->c, precision, enable);
+}
+
 int hmc_batch_get_cg_march(const hmc_batch* hb, int chain, int precision, int* rows, int* slices, int* ru_rows,
-                           int* ru_slices) {
-    if (hb == nullptr || rows == nullptr || slices == nullptr || ru_rows == nullptr || ru_slices == nullptr)
+                           int* ru_slices, int* step_b) {
+    if (hb == nullptr || rows == nullptr || slices == nullptr || ru_rows == nullptr || ru_slices == nullptr ||
+        step_b == nullptr)
         return fail(HMC_ERR_INVALID_ARG, "NULL argument");
     const BatchInfo& b = hb->c.bi;
     if (chain < 0 || chain >= b.nchains) return fail(HMC_ERR_INVALID_ARG, "chain out of range");
@@ -3173,6 +3240,7 @@ int hmc_batch_get_cg_march(const hmc_batch* hb, int chain, int precision, int* r
     *slices = m ? u.mp.seglen : 0;
     *ru_rows = r ? u.rmp.R : 0;
     *ru_slices = r ? u.rmp.seglen : 0;
+    *step_b = m ? hb->c.cgb_march[pi] : 0;
     return HMC_OK;
 }
 

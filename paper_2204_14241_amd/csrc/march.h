@@ -617,6 +617,199 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg
 }
 
 // ------------------------------------------------------------------------------------
+// CG step B as a march with step A's cut: r -= alpha_k M^dagger t, partial |r|^2 (PEND_RR, one
+// per workgroup; the next kernel is told the count).  M^dagger needs t(tau - 1) only at the
+// site itself, kept in registers from the slice before; LDS holds t(tau) on the band's rows and
+// the rows beside it, alternating between two buffers (one barrier per slice), the next
+// slice's loads in flight meanwhile.  The arithmetic per site is that of k_cg_b / k_cg_b2.
+template <class MG, bool NN2>
+__global__ __launch_bounds__(kMarchCgThreads) void k_cg_b2_march(CgCtl ctl, MG mg, CgVecs<float> v,
+                                                                 const float* __restrict__ phi_base, Coef<float> cf) {
+    extern __shared__ __align__(16) unsigned char march_smem[];
+    const MarchWork w = mg.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = w.lat;
+    const MarchPlan& mp = w.mp;
+    const MarchPos& mpos = w.mpos;
+    const UPos& pos = w.pos;
+    const float* phi = phi_base + pos.phioff;
+    const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, P = L / 2, rowc = 4 * L;
+    constexpr int H = NN2 ? 2 : 1;
+    cg_finalize(ctl, pos, w.nparts_in);
+    const CgState& S = cg_shared();
+    if (S.mode != CG_ACTIVE) {
+        cg_publish(ctl, pos);
+        return;
+    }
+    const float alpha = float(S.alpha_cur);
+    const size_t off = pos.voff;
+    const float2* tin = v.t + off;
+    float2* r = v.r + off;
+    float2* buf0 = reinterpret_cast<float2*>(march_smem);
+    float2* buf1 = buf0 + size_t(mp.R + 2 * H) * rowc;
+    const int e = threadIdx.x, nh = (mpos.nr + 2 * H) * P;
+    const bool act = e < nh;
+    const int lr = act ? e / P : 0, py = act ? e - lr * P : 0, y = 2 * py;
+    const int xrow = wrap_row(mpos.x0 - H + lr, L);
+    const bool inner = act && lr >= H && lr < mpos.nr + H;
+    const int ro = xrow * L + y;
+    // defined on every thread (a conditionally loaded array would be kept in scratch memory)
+    float4 rv[4], rs[4], prev[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rv[c] = rs[c] = prev[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+    float2 f1 = make_float2(0.f, 0.f), f2 = f1, f3 = f1;
+    auto load_slab = [&](int tq) {
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rv[c] = ld4(tin, size_t(c) * vol + size_t(tq) * LL + ro);
+        }
+    };
+    auto load_site = [&](int tq) {
+        if (inner) {
+            const size_t i = size_t(tq) * LL + ro;
+            f1 = *reinterpret_cast<const float2*>(phi + i);
+            f2 = *reinterpret_cast<const float2*>(phi + vol + i);
+            f3 = *reinterpret_cast<const float2*>(phi + 2 * vol + i);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rs[c] = ld4(r, size_t(c) * vol + i);
+        }
+    };
+    const int t0 = mpos.t0, t1 = mpos.t1;
+    if (inner) {
+        const int tp = t0 == 0 ? Lt - 1 : t0 - 1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) prev[c] = ld4(tin, size_t(c) * vol + size_t(tp) * LL + ro);
+    }
+    load_slab(t0);
+    load_site(t0);
+    double part = 0.0;
+    for (int tau = t0; tau < t1; ++tau) {
+        float2* cur = (tau - t0) & 1 ? buf1 : buf0;
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) *reinterpret_cast<float4*>(cur + lr * rowc + c * L + y) = rv[c];
+        }
+        const float2 g1 = f1, g2 = f2, g3 = f3;
+        float4 rt[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) rt[c] = rs[c];
+        if (tau + 1 < t1) {
+            load_slab(tau + 1);
+            load_site(tau + 1);
+        }
+        __syncthreads();
+        if (inner) {
+            float4 o[4], cen[4];
+            stencil_pair_lds<NN2>(cur, lr, xrow, y, L, g1, g2, g3, cf, tau == 0 ? -1.f : 1.f, prev, o, cen);
+            float acc = 0.f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float4 rn = f4axpy(-alpha, o[c], rt[c]);
+                st4(r, size_t(c) * vol + size_t(tau) * LL + ro, rn);
+                acc += f4norm2(rn);
+                prev[c] = cen[c];
+            }
+            part += double(acc);
+        }
+    }
+    store_partial(ctl, PEND_RR, pos, part);
+    if (threadIdx.x == 0) cg_shared().pending = PEND_RR;
+    cg_publish(ctl, pos);
+}
+
+template <class MG, bool NN2>
+__global__ __launch_bounds__(kMarchCgThreads) void k_cg_b_march(CgCtl ctl, MG mg, CgVecs<double> v,
+                                                                const double* __restrict__ phi_base, Coef<double> cf) {
+    extern __shared__ __align__(16) unsigned char march_smem[];
+    const MarchWork w = mg.at(xcd_remap(blockIdx.x, gridDim.x));
+    const Lat& lat = w.lat;
+    const MarchPlan& mp = w.mp;
+    const MarchPos& mpos = w.mpos;
+    const UPos& pos = w.pos;
+    const double* phi = phi_base + pos.phioff;
+    const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, rowc = 4 * L;
+    constexpr int H = NN2 ? 2 : 1;
+    cg_finalize(ctl, pos, w.nparts_in);
+    const CgState& S = cg_shared();
+    if (S.mode != CG_ACTIVE) {
+        cg_publish(ctl, pos);
+        return;
+    }
+    const double alpha = S.alpha_cur;
+    const size_t off = pos.voff;
+    const double2* tin = v.t + off;
+    double2* r = v.r + off;
+    double2* buf0 = reinterpret_cast<double2*>(march_smem);
+    double2* buf1 = buf0 + size_t(mp.R + 2 * H) * rowc;
+    const int e = threadIdx.x, nh = (mpos.nr + 2 * H) * L;
+    const bool act = e < nh;
+    const int lr = act ? e / L : 0, y = act ? e - lr * L : 0;
+    const int xrow = wrap_row(mpos.x0 - H + lr, L);
+    const bool inner = act && lr >= H && lr < mpos.nr + H;
+    const int ro = xrow * L + y;
+    double2 rv[4], rs[4], prev[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rv[c] = rs[c] = prev[c] = make_double2(0.0, 0.0);
+    double f1 = 0.0, f2 = 0.0, f3 = 0.0;
+    auto load_slab = [&](int tq) {
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rv[c] = tin[size_t(c) * vol + size_t(tq) * LL + ro];
+        }
+    };
+    auto load_site = [&](int tq) {
+        if (inner) {
+            const size_t i = size_t(tq) * LL + ro;
+            f1 = phi[i];
+            f2 = phi[vol + i];
+            f3 = phi[2 * vol + i];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rs[c] = r[size_t(c) * vol + i];
+        }
+    };
+    const int t0 = mpos.t0, t1 = mpos.t1;
+    if (inner) {
+        const int tp = t0 == 0 ? Lt - 1 : t0 - 1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) prev[c] = tin[size_t(c) * vol + size_t(tp) * LL + ro];
+    }
+    load_slab(t0);
+    load_site(t0);
+    double part = 0.0;
+    for (int tau = t0; tau < t1; ++tau) {
+        double2* cur = (tau - t0) & 1 ? buf1 : buf0;
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cur[lr * rowc + c * L + y] = rv[c];
+        }
+        const double g1 = f1, g2 = f2, g3 = f3;
+        double2 rt[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) rt[c] = rs[c];
+        if (tau + 1 < t1) {
+            load_slab(tau + 1);
+            load_site(tau + 1);
+        }
+        __syncthreads();
+        if (inner) {
+            double2 o[4], cen[4];
+            stencil_site_lds<NN2>(cur, lr, xrow, y, L, g1, g2, g3, cf, tau == 0 ? -1.0 : 1.0, prev, o, cen);
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double2 rn = axpy<double>(-alpha, o[c], rt[c]);
+                r[size_t(c) * vol + size_t(tau) * LL + ro] = rn;
+                acc += norm2<double>(rn);
+                prev[c] = cen[c];
+            }
+            part += acc;
+        }
+    }
+    store_partial(ctl, PEND_RR, pos, part);
+    if (threadIdx.x == 0) cg_shared().pending = PEND_RR;
+    cg_publish(ctl, pos);
+}
+
+// ------------------------------------------------------------------------------------
 // The FP64 reliable update of the conjugate-gradient solve (after the elementwise fold of the
 // pending step into x64) as two marches with the FP64 step-A march's cut and thread layout:
 // t64 = M x64, then r = b - M^dagger t64 with the FP64 partial |r|^2.  They replace the two

@@ -151,6 +151,14 @@ class HMC:
         pr = {None: -1, "fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]
         check(self.lib.hmc_set_cg_march(self._ctx, pr, int(rows), int(slices)), "hmc_set_cg_march")
 
+    def set_cg_march_step_b(self, enable=True, precision=None):
+        """Step B marches with step A's cut (hmc_set_cg_march_step_b)."""
+        pr = {None: -1, "fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]
+        check(self.lib.hmc_set_cg_march_step_b(self._ctx, pr, 1 if enable else 0), "hmc_set_cg_march_step_b")
+
+    def cg_march_step_b(self, precision="fp64"):
+        return bool(self.lib.hmc_get_cg_march_step_b(self._ctx, {"fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]))
+
     def cg_march(self, precision="fp64"):
         """(rows per band, slices per segment) of step A; rows 0: the tile kernels."""
         r, t = ctypes.c_int(), ctypes.c_int()
@@ -539,12 +547,16 @@ class Batch:
         self._call("hmc_batch_set_cg_march", pr, int(rows), int(slices))
 
     def cg_march(self, chain, precision="mixed"):
-        """(rows, slices) of chain's step-A cut and (rows, slices) of its reliable-update cut in
-        `precision` (0 rows: the tile kernels)."""
-        v = [ctypes.c_int() for _ in range(4)]
+        """(rows, slices) of chain's step-A cut, (rows, slices) of its reliable-update cut in
+        `precision` (0 rows: the tile kernels), and whether step B marches with the first."""
+        v = [ctypes.c_int() for _ in range(5)]
         self._call("hmc_batch_get_cg_march", int(chain), {"fp64": HMC_FP64, "mixed": HMC_MIXED}[precision],
                    *[ctypes.byref(x) for x in v])
-        return (v[0].value, v[1].value), (v[2].value, v[3].value)
+        return (v[0].value, v[1].value), (v[2].value, v[3].value), bool(v[4].value)
+
+    def set_cg_march_step_b(self, enable=True, precision=None):
+        pr = {None: -1, "fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]
+        self._call("hmc_batch_set_cg_march_step_b", pr, 1 if enable else 0)
 
     def set_cg_workgroups(self, n, precision=None):
         pr = {None: -1, "fp64": HMC_FP64, "mixed": HMC_MIXED}[precision]

@@ -46,8 +46,9 @@ def test_struct_layouts_match_c(tmp_path):
                    'sizeof(hmc_kernel_times), offsetof(hmc_kernel_times, count));'
                    'printf("%zu %zu %zu %zu\\n", sizeof(hmc_tuner), offsetof(hmc_tuner, esjd_count), '
                    'sizeof(hmc_warmup_stats), offsetof(hmc_warmup_stats, max_true_resid));'
-                   'printf("%zu %zu %zu\\n", offsetof(hmc_tune_result, march_rows), '
-                   'offsetof(hmc_tune_result, mtried_us), offsetof(hmc_tune_result, from_cache));'
+                   'printf("%zu %zu %zu %zu %zu\\n", offsetof(hmc_tune_result, march_rows), '
+                   'offsetof(hmc_tune_result, mtried_us), offsetof(hmc_tune_result, from_cache), '
+                   'offsetof(hmc_tune_result, march_step_b), offsetof(hmc_tune_result, step_b_us));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -59,7 +60,8 @@ def test_struct_layouts_match_c(tmp_path):
                    C.true_resid.offset, T.max_true_resid.offset, ctypes.sizeof(U),
                    U.tried_us.offset, ctypes.sizeof(K), K.count.offset,
                    ctypes.sizeof(Tu), Tu.esjd_count.offset, ctypes.sizeof(W), W.max_true_resid.offset,
-                   U.march_rows.offset, U.mtried_us.offset, U.from_cache.offset]
+                   U.march_rows.offset, U.mtried_us.offset, U.from_cache.offset, U.march_step_b.offset,
+                   U.step_b_us.offset]
 
 
 def test_error_strings():

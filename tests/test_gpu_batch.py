@@ -35,10 +35,11 @@ def dev(a, dtype=None):
 
 
 def mirror_cut(h, bt, chain, precision):
-    """Give a one-lattice context the march cuts (step A, reliable update) that chain `chain`
+    """Give a one-lattice context the march cuts (steps A and B, reliable update) that chain `chain`
     of the batch uses, so that the two run the same arithmetic in the same order."""
-    (r, sl), (rr, rs) = bt.cg_march(chain, precision)
+    (r, sl), (rr, rs), step_b = bt.cg_march(chain, precision)
     h.set_cg_march(r, sl, precision)
+    h.set_cg_march_step_b(step_b, precision)
     if precision == "mixed":
         h.set_cg_march(rr, rs, "fp64")
 
@@ -299,12 +300,12 @@ def test_batch_march_cuts_and_tile_kernels(hip, precision):
     phi, b = packed(bt, phis), packed(bt, bs, spinor=True)
     cuts = [bt.cg_march(i, precision) for i in range(len(chains))]
     say(f"batch march cuts {precision}: {cuts}")
-    for (L, Lt, _), ((r, sl), (rr, rs)) in zip(chains, cuts):
+    for (L, Lt, _), ((r, sl), (rr, rs), _) in zip(chains, cuts):
         assert 1 <= r <= L and 1 <= sl <= Lt
         assert 1 <= rr <= L and 1 <= rs <= Lt
     x, st = bt.cg_solve(phi, b)
     bt.set_cg_march(0)
-    assert all(bt.cg_march(i, precision) == ((0, 0), (0, 0)) for i in range(len(chains)))
+    assert all(bt.cg_march(i, precision) == ((0, 0), (0, 0), False) for i in range(len(chains)))
     x0, st0 = bt.cg_solve(phi, b)
     xs, xs0 = bt.unpack_spinors(x), bt.unpack_spinors(x0)
     for i, (L, Lt, r) in enumerate(chains):

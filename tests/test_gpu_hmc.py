@@ -110,15 +110,20 @@ def test_autotune_then_solve(hip):
         tried = res["tried"][prec]
         assert len({w for w, _ in tried}) == len(tried)
         # the workgroup count is the fastest of the tile-kernel runs; the time reported is the
-        # fastest of everything timed, the march shapes included (rows 0: the tile kernels won)
+        # fastest of everything timed, the march shapes and step B's two kernels at the chosen
+        # cut included (rows 0: the tile kernels won, step B was not timed)
         assert wg == min(tried, key=lambda t: t[1])[0]
         times = [t for _, t in tried] + [t for _, _, t in res["march_tried"][prec]]
-        assert us == min(times)
+        step_b = [t for t in res["step_b_us"][prec] if t > 0]
+        assert us == min(times + step_b)
         rows, slices = res["march"][prec]
         if rows:
-            assert (rows, slices, us) in res["march_tried"][prec]
+            assert (rows, slices) in [(r, sl) for r, sl, _ in res["march_tried"][prec]]
+            assert len(step_b) == 2
+            assert res["march_step_b"][prec] == int(step_b[1] < step_b[0])
+            assert h.cg_march_step_b(prec) == bool(res["march_step_b"][prec])
         else:
-            assert (wg, us) in tried
+            assert (wg, us) in tried and not step_b
         assert h.cg_march(prec) == (rows, slices)
     assert h.cg_workgroups() == {"fp64": res["fp64"][0], "mixed": res["mixed"][0]}
     h2 = hip.HMC(L, Lt, cg_tol=1e-10, precision="mixed")

@@ -3,8 +3,9 @@ oracle: the FP64 true residual by the oracle's M^dagger M (Eq. 22) <= 1e-10 |b| 
 precisions, over lattice and launch shapes that cover bands of one row, a last band with fewer
 rows, one band holding the whole lattice, segments of one or two slices and one segment for all
 of N_tau (the antiperiodic link inside a segment), several right-hand sides, and the Fourier
-preconditioner; iteration counts as with the tile kernels (the algebra is the same, only the
-order of the FP64 partial sums differs)."""
+preconditioner; step B marching with step A's cut or running its tile kernel
+(hmc_set_cg_march_step_b); iteration counts as with the tile kernels (the algebra is the same,
+only the order of the FP64 partial sums differs)."""
 import sys
 
 import numpy as np
@@ -43,15 +44,18 @@ def test_march_cg_matches_oracle(hip, precision, L, Lt):
     h = hip.HMC(L, Lt, n_pf=2, cg_tol=1e-10, precision=precision)
     _, st0 = h.cg_solve(dev(phi), dev(b))
     for rows, slices in SHAPES:
-        h.set_cg_march(rows, slices, precision)
-        x, st = h.cg_solve(dev(phi), dev(b))
-        xs = x.cpu().numpy()
-        e = max(resid(m, phi, b[k], xs[k]) for k in range(2))
-        say(f"march {precision} {L}x{L}x{Lt} rows {rows} slices {slices}: iterations {st.iterations} "
-            f"(tile {st0.iterations}), oracle residual {e:.2e}")
-        assert st.status == 0 and e <= 1e-10
-        for k in range(2):
-            assert abs(st.iterations[k] - st0.iterations[k]) <= max(2, st0.iterations[k] // 50)
+        for step_b in ((True, False) if rows else (True,)):
+            h.set_cg_march(rows, slices, precision)
+            h.set_cg_march_step_b(step_b, precision)
+            assert h.cg_march_step_b(precision) == step_b
+            x, st = h.cg_solve(dev(phi), dev(b))
+            xs = x.cpu().numpy()
+            e = max(resid(m, phi, b[k], xs[k]) for k in range(2))
+            say(f"march {precision} {L}x{L}x{Lt} rows {rows} slices {slices} step B march {step_b}: "
+                f"iterations {st.iterations} (tile {st0.iterations}), oracle residual {e:.2e}")
+            assert st.status == 0 and e <= 1e-10
+            for k in range(2):
+                assert abs(st.iterations[k] - st0.iterations[k]) <= max(2, st0.iterations[k] // 50)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -61,12 +65,14 @@ def test_march_cg_40x40x100_and_fourier(hip, precision):
     g = S.rng(870)
     phi = S.draw_phi(g, L, Lt, 0.5)
     b = S.draw_spinor(g, L, Lt, 1)
-    for pc in (None, "fourier"):
+    for pc, step_b in ((None, True), (None, False), ("fourier", True)):
         h = hip.HMC(L, Lt, cg_tol=1e-10, precision=precision, precond=pc, cg_maxit=20000)
         h.set_cg_march(4, 0, precision)
+        h.set_cg_march_step_b(step_b, precision)
         x, st = h.cg_solve(dev(phi), dev(b))
         e = resid(m, phi, b[0], x.cpu().numpy()[0])
-        say(f"march {precision} 40x40x100 precond={pc}: iterations {st.iterations}, oracle residual {e:.2e}")
+        say(f"march {precision} 40x40x100 precond={pc} step B march {step_b}: iterations {st.iterations}, "
+            f"oracle residual {e:.2e}")
         assert st.status == 0 and e <= 1e-10
 
 
@@ -101,16 +107,19 @@ def test_autotune_picks_march_shapes_and_caches_them_on_disk(hip, tmp_path, monk
     say(f"autotune 12x12x40: {r['fp64']} {r['mixed']} march {r['march']}, {r['candidates']} candidates")
     assert r["from_cache"] == 0 and r["march_tried"]["mixed"] and r["march_tried"]["fp64"]
     assert (h.cg_march("fp64"), h.cg_march("mixed")) == (tuple(r["march"]["fp64"]), tuple(r["march"]["mixed"]))
+    assert {p: int(h.cg_march_step_b(p)) for p in ("fp64", "mixed")} == r["march_step_b"]
     assert cache.exists() and "one 12 40 1 " in cache.read_text()
     # a new context of the same lattice starts from the cached shapes
     h2 = hip.HMC(L, Lt)
     assert h2.cg_workgroups() == h.cg_workgroups()
     assert h2.cg_march("mixed") == h.cg_march("mixed") and h2.cg_march("fp64") == h.cg_march("fp64")
+    assert all(h2.cg_march_step_b(p) == h.cg_march_step_b(p) for p in ("fp64", "mixed"))
     # and HMC_TUNE_REUSE=1 returns the cached choice without timing anything
     monkeypatch.setenv("HMC_TUNE_REUSE", "1")
     r2 = h2.autotune(dev(phi), dev(b))
     assert r2["from_cache"] == 1 and r2["candidates"] == 0
     assert r2["march"] == r["march"] and r2["fp64"][0] == r["fp64"][0] and r2["mixed"][0] == r["mixed"][0]
+    assert r2["march_step_b"] == r["march_step_b"]
     for prec in ("fp64", "mixed"):
         h2.set_params(precision=prec)
         x, st = h2.cg_solve(dev(phi), dev(b))

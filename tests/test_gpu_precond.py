@@ -27,10 +27,11 @@ def dev(a):
 
 
 def mirror_cut(h, bt, chain, precision):
-    """Give a one-lattice context the march cuts (step A, reliable update) that chain `chain`
+    """Give a one-lattice context the march cuts (steps A and B, reliable update) that chain `chain`
     of the batch uses, so that the two run the same arithmetic in the same order."""
-    (r, sl), (rr, rs) = bt.cg_march(chain, precision)
+    (r, sl), (rr, rs), step_b = bt.cg_march(chain, precision)
     h.set_cg_march(r, sl, precision)
+    h.set_cg_march_step_b(step_b, precision)
     if precision == "mixed":
         h.set_cg_march(rr, rs, "fp64")
 
