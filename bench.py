@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--apply-reps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-trajectory", action="store_true",
+                    help="also time one full oracle trajectory at 40x40x100 on the host (about 15 "
+                         "minutes of one core; off by default)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default CG launch shapes")
     ap.add_argument("--pcg-steps", type=int, default=3,
                     help="timed Fourier-preconditioned mixed trajectories (0: solves only)")
@@ -365,12 +368,12 @@ def prod_bench(hmcmod, torch, L, Lt, common, phi0, d_traj):
     return out
 
 
-def fp64_configs_bench(hmcmod, torch, seed, cpu):
+def fp64_configs_bench(hmcmod, torch, seed, cpu, cpu_traj=False):
     """The plain FP64 workloads beside the headline one: 40x40x100 with two pseudofermions (the
     autotuned launch shape, one CG solve with its sampled kernel times, one 20-step trajectory,
-    and the oracle's M^dag M on the host for comparison) and 60x60x160 with one (the
-    differentiable action's forward and backward, recomputing the solution, and one 20-step
-    trajectory)."""
+    and the oracle's CG on the host for comparison; with cpu_traj also one full oracle trajectory
+    on the same inputs) and 60x60x160 with one (the differentiable action's forward and backward,
+    recomputing the solution, and one 20-step trajectory)."""
     import synth_inputs as S
     from paper_2204_14241_amd.autograd import pf_action
     dev = torch.device("cuda")
@@ -439,6 +442,11 @@ def fp64_configs_bench(hmcmod, torch, seed, cpu):
                              "dH": tr["dH"], "accepted": tr["accepted"],
                              "cg_iterations": tr["cg_iterations"], "max_true_resid": tr["max_true_resid"]}
         log(f"FP64 {name}: trajectory {el:.2f} s, cg iterations {tr['cg_iterations']}")
+        if cpu_traj and name.startswith("medium"):
+            rec["cpu_trajectory"] = cpu_trajectory(L, Lt, cfg, phi0, trajs[0])
+            rec["gpu_vs_cpu_trajectory"] = rec["trajectory"]["traj_per_hour"] / rec["cpu_trajectory"]["value"]
+            log(f"FP64 {name}: oracle trajectory {rec['cpu_trajectory']['s']:.0f} s on the host, dH "
+                f"{rec['cpu_trajectory']['dH']:.6e} (GPU {tr['dH']:.6e})")
         h.close()
         out[name] = rec
     return out
@@ -870,23 +878,40 @@ def mall_controlled_bench(hmcmod, torch, L, Lt, phi0, seed, nrhs=4):
 
 
 def cpu_baseline(L, Lt, seed, budget_s=15.0):
-    """The FP64 oracle's M^dagger M apply on the host (NumPy, one thread), bounded sample."""
+    """The FP64 oracle's CG on the host (NumPy, one thread), bounded sample: as many iterations
+    of its M^dagger M solve as fit the budget (a tolerance it never reaches), so that the rate
+    is in the headline's unit, M^dagger M applies per second inside CG iterations.  The solve
+    ends with one more M^dagger M (its true residual), which the rate does not count."""
     import oracle as O
     import synth_inputs as S
     m = O.Model(L=L, Lt=Lt)
     g = S.rng(seed)
     phi = S.draw_phi(g, L, Lt, 0.5)
-    psi = S.draw_spinor(g, L, Lt, 1)[0]
-    O.apply_MdagM(m, phi, psi)             # warm-up (page faults of first use)
-    n, t0 = 0, time.perf_counter()
-    while True:
-        O.apply_MdagM(m, phi, psi)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or n >= 50:
-            break
-    return dict(value=n / el, unit="M^dag M applies/s", cores=1, kind="oracle",
-                sample=f"{n} FP64 oracle M^dag M applies at {L}x{L}x{Lt} ({el:.1f} s, NumPy, 1 thread)")
+    b = S.draw_spinor(g, L, Lt, 1)[0]
+    t0 = time.perf_counter()
+    O.apply_MdagM(m, phi, b)               # warm-up (page faults of first use) and the estimate
+    n = max(3, min(50, int(budget_s / (time.perf_counter() - t0))))
+    t0 = time.perf_counter()
+    _, its, _ = O.cg_solve(m, phi, b, tol=1e-300, maxit=n)
+    el = time.perf_counter() - t0
+    return dict(value=its / el, unit="M^dag M applies/s", cores=1, kind="oracle",
+                sample=f"{its} iterations of the FP64 oracle's CG on M^dag M at {L}x{L}x{Lt} plus its "
+                       f"closing true-residual apply ({el:.1f} s, NumPy, 1 thread)")
+
+
+def cpu_trajectory(L, Lt, cfg, phi0, traj):
+    """One full HMC trajectory of the FP64 oracle on the host (NumPy, one thread): heat-bath,
+    cfg["n_leap"] leapfrog steps with CG solves to 1e-10, Metropolis, on the GPU leg's inputs."""
+    import oracle as O
+    m = O.Model(L=L, Lt=Lt)
+    pi0, etas, u = traj
+    t0 = time.perf_counter()
+    res = O.trajectory(m, phi0, pi0, list(etas), u, cfg["eps"], cfg["n_leap"], tol=1e-10)
+    el = time.perf_counter() - t0
+    return dict(value=3600.0 / el, unit="trajectories/h", cores=1, kind="oracle", s=el, dH=res["dH"],
+                accepted=res["accepted"],
+                sample=f"one {cfg['n_leap']}-step FP64 oracle trajectory at {L}x{L}x{Lt} with "
+                       f"{len(etas)} pseudofermions ({el:.0f} s, NumPy, 1 thread)")
 
 
 def main():
@@ -1055,7 +1080,8 @@ def main():
         extras["pcg_80x80x200"] = pcg_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, W, args.pcg_steps)
         extras["metric_80x80x200"] = metric_bench(hmcmod, torch, L, Lt, common, phi0, d_traj, args.seed)
         extras["production_model_80x80x200"] = prod_bench(hmcmod, torch, L, Lt, common, phi0, d_traj)
-        extras["fp64_workloads"] = fp64_configs_bench(hmcmod, torch, args.seed, not args.no_cpu)
+        extras["fp64_workloads"] = fp64_configs_bench(hmcmod, torch, args.seed, not args.no_cpu,
+                                                      args.cpu_trajectory)
         for f32 in (True, False):
             aps, gbs, ms, nsets = apply_bench(hmcmod, torch, L, Lt, f32, args.apply_reps, args.seed + 1)
             extras["mdagm_apply_" + ("f32" if f32 else "f64")] = {
