@@ -87,12 +87,17 @@ def bench_field_and_rhs(L, Lt, model=None):
     return m, phi0, chi
 
 
-@pytest.mark.parametrize("precision,precond", [("fp64", None), ("fp64", "fourier"), ("mixed", "fourier")])
-def test_solve_80x80x200_true_residual(hip, precision, precond):
+# step B marching or not: both are launch shapes the autotuner may pick (None: the default)
+@pytest.mark.parametrize("precision,precond,step_b", [("fp64", None, None), ("fp64", None, False),
+                                                      ("fp64", "fourier", None), ("mixed", None, True),
+                                                      ("mixed", "fourier", None)])
+def test_solve_80x80x200_true_residual(hip, precision, precond, step_b):
     L, Lt = 80, 200
-    say(f"{precision} solve precond={precond} at {L}x{L}x{Lt}")
+    say(f"{precision} solve precond={precond} step B march {step_b} at {L}x{L}x{Lt}")
     m, phi, chi = bench_field_and_rhs(L, Lt)
     h = hip.HMC(L, Lt, precision=precision, precond=precond, cg_tol=1e-10, cg_maxit=20000)
+    if step_b is not None:
+        h.set_cg_march_step_b(step_b, precision)
     x, st = h.cg_solve(dev(phi), dev(chi[None]))
     e = resid(m, phi, chi, x.cpu().numpy()[0])
     say(f"  iterations {st.iterations[0]}, reliable updates {st.reliable_updates[0]}, "
