@@ -443,7 +443,9 @@ def fp64_configs_bench(hmcmod, torch, seed, cpu, cpu_traj=False):
                              "cg_iterations": tr["cg_iterations"], "max_true_resid": tr["max_true_resid"]}
         log(f"FP64 {name}: trajectory {el:.2f} s, cg iterations {tr['cg_iterations']}")
         if cpu_traj and name.startswith("medium"):
-            rec["cpu_trajectory"] = cpu_trajectory(L, Lt, cfg, phi0, trajs[0])
+            rec["cpu_trajectory"] = cpu_trajectory(
+                L, Lt, cfg, phi0, trajs[0],
+                progress=lambda k, t: log(f"oracle trajectory: leapfrog step {k + 1} done, {t:.0f} s"))
             rec["gpu_vs_cpu_trajectory"] = rec["trajectory"]["traj_per_hour"] / rec["cpu_trajectory"]["value"]
             log(f"FP64 {name}: oracle trajectory {rec['cpu_trajectory']['s']:.0f} s on the host, dH "
                 f"{rec['cpu_trajectory']['dH']:.6e} (GPU {tr['dH']:.6e})")
@@ -899,17 +901,27 @@ def cpu_baseline(L, Lt, seed, budget_s=15.0):
                        f"closing true-residual apply ({el:.1f} s, NumPy, 1 thread)")
 
 
-def cpu_trajectory(L, Lt, cfg, phi0, traj):
+def cpu_trajectory(L, Lt, cfg, phi0, traj, progress=None):
     """One full HMC trajectory of the FP64 oracle on the host (NumPy, one thread): heat-bath,
-    cfg["n_leap"] leapfrog steps with CG solves to 1e-10, Metropolis, on the GPU leg's inputs."""
+    cfg["n_leap"] leapfrog steps with CG solves to 1e-10, Metropolis, on the GPU leg's inputs.
+    The oracle's own steps in its trajectory's order (heat-bath, H0, one leapfrog step at a
+    time carrying the force, H1), so that `progress(step, seconds)` can report each step."""
+    import numpy as np
     import oracle as O
     m = O.Model(L=L, Lt=Lt)
     pi0, etas, u = traj
     t0 = time.perf_counter()
-    res = O.trajectory(m, phi0, pi0, list(etas), u, cfg["eps"], cfg["n_leap"], tol=1e-10)
+    chis = [O.heatbath(m, phi0, eta) for eta in etas]
+    H0 = O.hamiltonian(m, phi0, pi0, sum(float(np.vdot(e.ravel(), e.ravel()).real) for e in etas))
+    phi, pi, F = phi0, pi0, None
+    for k in range(cfg["n_leap"]):
+        phi, pi, F, _, S_pf = O.leapfrog(m, phi, pi, chis, cfg["eps"], 1, tol=1e-10, F=F)
+        if progress:
+            progress(k, time.perf_counter() - t0)
+    dH = O.hamiltonian(m, phi, pi, S_pf) - H0
     el = time.perf_counter() - t0
-    return dict(value=3600.0 / el, unit="trajectories/h", cores=1, kind="oracle", s=el, dH=res["dH"],
-                accepted=res["accepted"],
+    return dict(value=3600.0 / el, unit="trajectories/h", cores=1, kind="oracle", s=el, dH=float(dH),
+                accepted=O.metropolis_accept(dH, u),
                 sample=f"one {cfg['n_leap']}-step FP64 oracle trajectory at {L}x{L}x{Lt} with "
                        f"{len(etas)} pseudofermions ({el:.0f} s, NumPy, 1 thread)")
 

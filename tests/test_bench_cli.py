@@ -64,3 +64,21 @@ def test_step_a_samples_are_averaged_over_both_kinds():
     assert abs(m["cg_a_f32"][0] - 0.040) < 1e-15 and m["cg_a_f32"][1] == 8
     assert m["cg_a_first_f32"] == (0.030, 4)
     assert m["cg_a_f64"] == (None, 0)      # one kind only: no per-launch average
+
+
+def test_cpu_trajectory_leg_is_the_oracles_trajectory():
+    """The host trajectory leg runs the oracle's steps one leapfrog step at a time (to report
+    progress); dH and the decision are those of the oracle's trajectory, bit for bit."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import oracle as O
+    import synth_inputs as S
+    cfg = dict(S.WORKLOADS["tiny_4x4x8"])
+    phi0, trajs = S.hmc_inputs(3, 4, 8, cfg["phi_var"], 2, n_traj=1)
+    steps = []
+    r = bench.cpu_trajectory(4, 8, cfg, phi0, trajs[0], progress=lambda k, t: steps.append(k))
+    pi0, etas, u = trajs[0]
+    ref = O.trajectory(O.Model(L=4, Lt=8), phi0, pi0, list(etas), u, cfg["eps"], cfg["n_leap"], tol=1e-10)
+    assert steps == list(range(cfg["n_leap"]))
+    assert r["dH"] == ref["dH"] and r["accepted"] == ref["accepted"]
+    assert r["unit"] == "trajectories/h" and r["kind"] == "oracle"
