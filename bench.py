@@ -338,7 +338,7 @@ PROD_MODEL = dict(t=((1.0, 0.0), (0.0, 1.0)), tn=((0.0, 0.45), (-0.45, 0.0)), mu
 
 def prod_bench(hmcmod, torch, L, Lt, common, phi0, d_traj):
     """The production model at the workload size: one mixed solve of M^dag M x = M^dag eta
-    plain and Fourier-preconditioned, with the sampled kernel times of the instantiations
+    plain and Fourier-preconditioned at the autotuned launch shape, with the sampled kernel times of the instantiations
     that read the sites two steps away (same algorithmic bytes as the nearest-neighbour
     kernels: the extra neighbours are re-reads)."""
     dev = torch.device("cuda")
@@ -348,6 +348,7 @@ def prod_bench(hmcmod, torch, L, Lt, common, phi0, d_traj):
     for pc in (None, "fourier"):
         h = hmcmod.HMC(L, Lt, precision="mixed", precond=pc, model=PROD_MODEL, **common)
         chi = h.heatbath(phi, d_traj[0][1])
+        tune = h.autotune(phi, chi)          # the launch shapes for this model (remembered per lattice)
         h.cg_solve(phi, chi)
         h.set_kernel_timing(True)
         torch.cuda.synchronize()
@@ -356,7 +357,8 @@ def prod_bench(hmcmod, torch, L, Lt, common, phi0, d_traj):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         kt = merge_step_a(h.kernel_times())
-        rec = {"ms": 1e3 * el, "iterations": st.iterations[0], "true_resid": st.true_resid[0]}
+        rec = {"ms": 1e3 * el, "iterations": st.iterations[0], "true_resid": st.true_resid[0],
+               "march": tune["march"]["mixed"], "march_step_b": tune["march_step_b"]["mixed"]}
         for name in ("cg_a_f32", "cg_b_f32"):
             ms, n = kt[name]
             if ms:

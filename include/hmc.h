@@ -406,9 +406,10 @@ int hmc_get_cg_march(const hmc_ctx* ctx, int precision, int* rows, int* slices);
 
 /* Whether CG step B (r -= alpha M^dagger t, Methods C) also marches when step A does, with
  * step A's cut (enable != 0), or runs its tile kernel (0).  The march reads t once through LDS
- * (helps where the tile kernel re-reads t from HBM: FP64, several right-hand sides); the tile
- * kernel reads t while the MALL still holds it (one FP32 right-hand side).  Defaults: on for
- * FP64, off for FP32; hmc_autotune times both.  precision: HMC_FP64, HMC_MIXED or -1.  Results
+ * (helps where the tile kernel re-reads t from HBM or L2: FP64, several right-hand sides, the
+ * two-site hops); with one FP32 right-hand side of the nearest-neighbour model the two are
+ * within a few percent (the tile kernel reads t while the MALL still holds it).  Default: on in
+ * both precisions; hmc_autotune times both.  precision: HMC_FP64, HMC_MIXED or -1.  Results
  * depend on it only through the order of the FP64 partial sums.  hmc_get_cg_march_step_b
  * returns the setting (-1 on a bad argument). */
 int hmc_set_cg_march_step_b(hmc_ctx* ctx, int precision, int enable);

@@ -223,7 +223,7 @@ struct hmc_ctx {
     // per segment (0: the default)
     int cgm_rows[2] = {0, 0};
     int cgm_seg[2] = {0, 0};
-    int cgb_march[2] = {1, 0};   // step B marches too (with step A's cut) [FP64, FP32]
+    int cgb_march[2] = {1, 1};   // step B marches too (with step A's cut) [FP64, FP32]
     // partial sums the last launched kernel left per unit when its workgroup count is not the
     // CG launch shape's (a march); the next launch's control block takes it over
     int next_nparts = 0;
@@ -257,7 +257,7 @@ struct hmc_batch {
 static std::string device_tag(int dev);
 
 // Cache key of a context: one lattice "one L Lt n", a batch "batch <hash of the chain list>",
-// then the device and the kernel-source hash.
+// " nn2" with the two-site hops, then the device and the kernel-source hash.
 static std::string tune_key(const hmc_ctx* c) {
     std::string k;
     if (c->is_batch) {
@@ -280,6 +280,7 @@ static std::string tune_key(const hmc_ctx* c) {
     } else {
         k = "one " + std::to_string(c->L) + " " + std::to_string(c->Lt) + " " + std::to_string(c->cap);
     }
+    if (c->cf64.nn2) k += " nn2";   // the two-site hops run other instantiations
     return k + " " + device_tag(c->device) + " " + HMC_SOURCE_HASH;
 }
 
@@ -598,12 +599,12 @@ struct TuneChoice {
     int bpr[2] = {0, 0};    // [FP64, FP32]
     int mrows[2] = {0, 0};
     int mseg[2] = {0, 0};
-    int mb[2] = {1, 0};     // step B marches too
+    int mb[2] = {1, 1};     // step B marches too
 };
 struct TuneKey {
-    int L, Lt, n, dev;
+    int L, Lt, n, dev, nn2;
     bool operator<(const TuneKey& o) const {
-        return std::tie(L, Lt, n, dev) < std::tie(o.L, o.Lt, o.n, o.dev);
+        return std::tie(L, Lt, n, dev, nn2) < std::tie(o.L, o.Lt, o.n, o.dev, o.nn2);
     }
 };
 static std::mutex g_tune_mu;
@@ -2012,7 +2013,7 @@ static int autotune_common(hmc_ctx* c, const double* phi, const double2* b, int 
         c->cgm_rows[1] = 8;
         c->cgm_seg[0] = c->cgm_seg[1] = 8;
         c->cgb_march[0] = 1;
-        c->cgb_march[1] = 0;
+        c->cgb_march[1] = 1;
         (void)set_cg_shape(c, HMC_FP64, kDefaultBpr64);
         (void)set_cg_shape(c, HMC_MIXED, kDefaultBpr32);
         return result == HMC_ERR_HIP ? fail(result, "autotune: HIP call failed") : result;
@@ -2443,7 +2444,7 @@ int hmc_create(int L, int Lt, double dtau, const hmc_params* params, hmc_ctx** o
     c->cgm_seg[0] = c->cgm_seg[1] = 8;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tuned.find(TuneKey{L, Lt, c->cap, c->device});
+        auto it = g_tuned.find(TuneKey{L, Lt, c->cap, c->device, c->cf64.nn2 != 0});
         TuneChoice ch;
         bool have = it != g_tuned.end();
         if (have) ch = it->second;
@@ -2682,7 +2683,7 @@ int hmc_autotune(hmc_ctx* c, const double* phi, const void* b, int n, hmc_tune_r
             apply_choice(c, ch);
             choice_result(ch, out);
             std::lock_guard<std::mutex> lk(g_tune_mu);
-            g_tuned[TuneKey{c->L, c->Lt, c->cap, c->device}] = ch;
+            g_tuned[TuneKey{c->L, c->Lt, c->cap, c->device, c->cf64.nn2 != 0}] = ch;
             return HMC_OK;
         }
     }
@@ -2691,7 +2692,7 @@ int hmc_autotune(hmc_ctx* c, const double* phi, const void* b, int n, hmc_tune_r
     const TuneChoice ch = current_choice(c);
     tune_cache_store(tune_key(c), ch);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[TuneKey{c->L, c->Lt, c->cap, c->device}] = ch;
+    g_tuned[TuneKey{c->L, c->Lt, c->cap, c->device, c->cf64.nn2 != 0}] = ch;
     return HMC_OK;
 }
 

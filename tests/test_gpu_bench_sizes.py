@@ -89,7 +89,7 @@ def bench_field_and_rhs(L, Lt, model=None):
 
 # step B marching or not: both are launch shapes the autotuner may pick (None: the default)
 @pytest.mark.parametrize("precision,precond,step_b", [("fp64", None, None), ("fp64", None, False),
-                                                      ("fp64", "fourier", None), ("mixed", None, True),
+                                                      ("fp64", "fourier", None), ("mixed", None, False),
                                                       ("mixed", "fourier", None)])
 def test_solve_80x80x200_true_residual(hip, precision, precond, step_b):
     L, Lt = 80, 200
