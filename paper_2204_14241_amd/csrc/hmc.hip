@@ -954,9 +954,8 @@ static int enqueue_chunk(hmc_ctx* c, const Launch<Geo>& lc, int n, const double*
     for (int i = 0; i < chunk; ++i) {
         const int expect_a = lc.pc ? PEND_NONE : (i > 0 ? PEND_RR : (first ? PEND_BB : PEND_NONE));
         const CgCtl ka = next_ctl(c, expect_a);
-        // step A as a march (one lattice, or every unit of a batch with its own cut); step B
-        // (the tile kernel, which reads t while the MALL still holds it) reduces the march's
-        // partials
+        // step A as a march (one lattice, or every unit of a batch with its own cut); step B, a
+        // march with the same cut or its tile kernel, reduces the march's partials
         int mgrid = 0, mthreads = 0, mparts = 0;
         size_t mlds = 0;
         if constexpr (std::is_same<Geo, GeoOne>::value) {
