@@ -378,6 +378,32 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG m
     const float* phi = phi_base + pos.phioff;
     const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, P = L / 2, rowc = 4 * L;
     constexpr int H = NN2 ? 2 : 1;    // rows beside the band on either side
+    const size_t off = pos.voff;
+    const float2* z = v.z + off;
+    // this thread's element: row lr of the band buffer (0 and nr + 1 are the rows beside the band)
+    const int e = threadIdx.x, nh = (mpos.nr + 2 * H) * P;
+    const bool act = e < nh;
+    const int lr = act ? e / P : 0, py = act ? e - lr * P : 0, y = 2 * py;
+    const int xrow = wrap_row(mpos.x0 - H + lr, L);
+    const bool inner = act && lr >= H && lr < mpos.nr + H;
+    const int ro = xrow * L + y;                      // offset of the element within a slice
+    const int t0 = mpos.t0, t1 = mpos.t1;
+    float4 rz[4], rp[4], rx[4], rq[4];
+    float2 f1 = make_float2(0.f, 0.f), f2 = f1, f3 = f1;
+    auto load_phi = [&](int tq) {
+        if (inner) {
+            const size_t i = size_t(tq) * LL + ro;
+            f1 = *reinterpret_cast<const float2*>(phi + i);
+            f2 = *reinterpret_cast<const float2*>(phi + vol + i);
+            f3 = *reinterpret_cast<const float2*>(phi + 2 * vol + i);
+        }
+    };
+    // the first slice's z and phi do not depend on the record: in flight while it is reduced
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) rz[c] = ld4(z, size_t(c) * vol + size_t(t0) * LL + ro);
+    }
+    load_phi(t0);
     cg_finalize(ctl, pos, w.nparts_in);
     const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
@@ -388,29 +414,18 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG m
     const bool fold = S.alpha_old != 0.0;   // x += both pending steps this iteration (see k_cg_a)
     const double defer = S.alpha;
     const int pb = S.pbuf;
-    const size_t off = pos.voff;
     const float2* pin = (pb ? v.p1 : v.p0) + off;
     float2* pout = (pb ? v.p0 : v.p1) + off;
     float2* x = v.x + off;
     float2* t = v.t + off;
-    const float2* z = v.z + off;
     float2* cur = reinterpret_cast<float2*>(march_smem);
     float2* nxt = cur + size_t(mp.R + 2 * H) * rowc;
-    // this thread's element: row lr of the band buffer (0 and nr + 1 are the rows beside the band)
-    const int e = threadIdx.x, nh = (mpos.nr + 2 * H) * P;
-    const bool act = e < nh;
-    const int lr = act ? e / P : 0, py = act ? e - lr * P : 0, y = 2 * py;
-    const int xrow = wrap_row(mpos.x0 - H + lr, L);
-    const bool inner = act && lr >= H && lr < mpos.nr + H;
-    const int ro = xrow * L + y;                      // offset of the element within a slice
-    float4 rz[4], rp[4], rx[4], rq[4];
-    float2 f1 = make_float2(0.f, 0.f), f2 = f1, f3 = f1;
-    auto load_slab = [&](int tq) {
+    auto load_slab = [&](int tq, bool with_z) {
         if (act) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const size_t i = size_t(c) * vol + size_t(tq) * LL + ro;
-                rz[c] = ld4(z, i);
+                if (with_z) rz[c] = ld4(z, i);
                 rp[c] = ld4(pin, i);
             }
         }
@@ -421,14 +436,6 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG m
                 rx[c] = ld4(x, i);
                 rq[c] = ld4(pout, i);
             }
-        }
-    };
-    auto load_phi = [&](int tq) {
-        if (inner) {
-            const size_t i = size_t(tq) * LL + ro;
-            f1 = *reinterpret_cast<const float2*>(phi + i);
-            f2 = *reinterpret_cast<const float2*>(phi + vol + i);
-            f3 = *reinterpret_cast<const float2*>(phi + 2 * vol + i);
         }
     };
     // p_new at slice tq from the loaded z, p_old (into buf, and stored with the x update when own)
@@ -448,12 +455,10 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG m
             }
         }
     };
-    const int t0 = mpos.t0, t1 = mpos.t1;
     float4 pn[4];
-    load_slab(t0);
+    load_slab(t0, false);
     form(t0, cur, true, pn);
-    load_slab(t0 + 1 == Lt ? 0 : t0 + 1);
-    load_phi(t0);
+    load_slab(t0 + 1 == Lt ? 0 : t0 + 1, true);
     double part = 0.0;
     for (int tau = t0; tau < t1; ++tau) {
         const int tn = tau + 1 == Lt ? 0 : tau + 1;
@@ -462,7 +467,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG m
         form(tn, nxt, own_next, pnx);
         const float2 g1 = f1, g2 = f2, g3 = f3;
         if (own_next) {
-            load_slab(tn + 1 == Lt ? 0 : tn + 1);
+            load_slab(tn + 1 == Lt ? 0 : tn + 1, true);
             load_phi(tn);
         }
         __syncthreads();
@@ -505,6 +510,31 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg
     const double* phi = phi_base + pos.phioff;
     const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, rowc = 4 * L;
     constexpr int H = NN2 ? 2 : 1;    // rows beside the band on either side
+    const size_t off = pos.voff;
+    const double2* z = v.z + off;
+    const int e = threadIdx.x, nh = (mpos.nr + 2 * H) * L;
+    const bool act = e < nh;
+    const int lr = act ? e / L : 0, y = act ? e - lr * L : 0;
+    const int xrow = wrap_row(mpos.x0 - H + lr, L);
+    const bool inner = act && lr >= H && lr < mpos.nr + H;
+    const int ro = xrow * L + y;
+    const int t0 = mpos.t0, t1 = mpos.t1;
+    double2 rz[4], rp[4], rx[4], rq[4];
+    double f1 = 0.0, f2 = 0.0, f3 = 0.0;
+    auto load_phi = [&](int tq) {
+        if (inner) {
+            const size_t i = size_t(tq) * LL + ro;
+            f1 = phi[i];
+            f2 = phi[vol + i];
+            f3 = phi[2 * vol + i];
+        }
+    };
+    // the first slice's z and phi do not depend on the record: in flight while it is reduced
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) rz[c] = z[size_t(c) * vol + size_t(t0) * LL + ro];
+    }
+    load_phi(t0);
     cg_finalize(ctl, pos, w.nparts_in);
     const CgState& S = cg_shared();
     if (S.mode != CG_ACTIVE) {
@@ -515,28 +545,18 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg
     const bool fold = alpha_old != 0.0;     // x += both pending steps this iteration (see k_cg_a)
     const double defer = S.alpha;
     const int pb = S.pbuf;
-    const size_t off = pos.voff;
     const double2* pin = (pb ? v.p1 : v.p0) + off;
     double2* pout = (pb ? v.p0 : v.p1) + off;
     double2* x = v.x + off;
     double2* t = v.t + off;
-    const double2* z = v.z + off;
     double2* cur = reinterpret_cast<double2*>(march_smem);
     double2* nxt = cur + size_t(mp.R + 2 * H) * rowc;
-    const int e = threadIdx.x, nh = (mpos.nr + 2 * H) * L;
-    const bool act = e < nh;
-    const int lr = act ? e / L : 0, y = act ? e - lr * L : 0;
-    const int xrow = wrap_row(mpos.x0 - H + lr, L);
-    const bool inner = act && lr >= H && lr < mpos.nr + H;
-    const int ro = xrow * L + y;
-    double2 rz[4], rp[4], rx[4], rq[4];
-    double f1 = 0.0, f2 = 0.0, f3 = 0.0;
-    auto load_slab = [&](int tq) {
+    auto load_slab = [&](int tq, bool with_z) {
         if (act) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const size_t i = size_t(c) * vol + size_t(tq) * LL + ro;
-                rz[c] = z[i];
+                if (with_z) rz[c] = z[i];
                 rp[c] = pin[i];
             }
         }
@@ -547,14 +567,6 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg
                 rx[c] = x[i];
                 rq[c] = pout[i];
             }
-        }
-    };
-    auto load_phi = [&](int tq) {
-        if (inner) {
-            const size_t i = size_t(tq) * LL + ro;
-            f1 = phi[i];
-            f2 = phi[vol + i];
-            f3 = phi[2 * vol + i];
         }
     };
     auto form = [&](int tq, double2* buf, bool own, double2 (&pn)[4]) {
@@ -573,12 +585,10 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg
             }
         }
     };
-    const int t0 = mpos.t0, t1 = mpos.t1;
     double2 pn[4];
-    load_slab(t0);
+    load_slab(t0, false);
     form(t0, cur, true, pn);
-    load_slab(t0 + 1 == Lt ? 0 : t0 + 1);
-    load_phi(t0);
+    load_slab(t0 + 1 == Lt ? 0 : t0 + 1, true);
     double part = 0.0;
     for (int tau = t0; tau < t1; ++tau) {
         const int tn = tau + 1 == Lt ? 0 : tau + 1;
@@ -587,7 +597,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg
         form(tn, nxt, own_next, pnx);
         const double g1 = f1, g2 = f2, g3 = f3;
         if (own_next) {
-            load_slab(tn + 1 == Lt ? 0 : tn + 1);
+            load_slab(tn + 1 == Lt ? 0 : tn + 1, true);
             load_phi(tn);
         }
         __syncthreads();
@@ -634,13 +644,6 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_b2_march(CgCtl ctl, MG m
     const float* phi = phi_base + pos.phioff;
     const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, P = L / 2, rowc = 4 * L;
     constexpr int H = NN2 ? 2 : 1;
-    cg_finalize(ctl, pos, w.nparts_in);
-    const CgState& S = cg_shared();
-    if (S.mode != CG_ACTIVE) {
-        cg_publish(ctl, pos);
-        return;
-    }
-    const float alpha = float(S.alpha_cur);
     const size_t off = pos.voff;
     const float2* tin = v.t + off;
     float2* r = v.r + off;
@@ -679,8 +682,16 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_b2_march(CgCtl ctl, MG m
 #pragma unroll
         for (int c = 0; c < 4; ++c) prev[c] = ld4(tin, size_t(c) * vol + size_t(tp) * LL + ro);
     }
+    // the first slice's loads do not depend on the record: in flight while it is reduced
     load_slab(t0);
     load_site(t0);
+    cg_finalize(ctl, pos, w.nparts_in);
+    const CgState& S = cg_shared();
+    if (S.mode != CG_ACTIVE) {
+        cg_publish(ctl, pos);
+        return;
+    }
+    const float alpha = float(S.alpha_cur);
     double part = 0.0;
     for (int tau = t0; tau < t1; ++tau) {
         float2* cur = (tau - t0) & 1 ? buf1 : buf0;
@@ -728,13 +739,6 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_b_march(CgCtl ctl, MG mg
     const double* phi = phi_base + pos.phioff;
     const int L = lat.L, Lt = lat.Lt, LL = lat.LL, vol = lat.vol, rowc = 4 * L;
     constexpr int H = NN2 ? 2 : 1;
-    cg_finalize(ctl, pos, w.nparts_in);
-    const CgState& S = cg_shared();
-    if (S.mode != CG_ACTIVE) {
-        cg_publish(ctl, pos);
-        return;
-    }
-    const double alpha = S.alpha_cur;
     const size_t off = pos.voff;
     const double2* tin = v.t + off;
     double2* r = v.r + off;
@@ -772,8 +776,16 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_b_march(CgCtl ctl, MG mg
 #pragma unroll
         for (int c = 0; c < 4; ++c) prev[c] = tin[size_t(c) * vol + size_t(tp) * LL + ro];
     }
+    // the first slice's loads do not depend on the record: in flight while it is reduced
     load_slab(t0);
     load_site(t0);
+    cg_finalize(ctl, pos, w.nparts_in);
+    const CgState& S = cg_shared();
+    if (S.mode != CG_ACTIVE) {
+        cg_publish(ctl, pos);
+        return;
+    }
+    const double alpha = S.alpha_cur;
     double part = 0.0;
     for (int tau = t0; tau < t1; ++tau) {
         double2* cur = (tau - t0) & 1 ? buf1 : buf0;
