@@ -807,13 +807,15 @@ def copy_bench(torch, reps=20):
 
 def probe_bench(hmcmod, torch, reps=10, grids=(1024, 2048, 4096, 8192)):
     """The library's streaming reference kernels (hmc_stream_probe) on buffers far larger than
-    the 256 MB MALL, two buffer sets alternated: read-only, write-only, copy (1 GiB per stream)
-    and three reads with three writes (512 MiB per stream, the mix of one fused CG step).
+    the 256 MB MALL, two buffer sets alternated: read-only (plain and with nontemporal loads),
+    write-only, copy (1 GiB per stream) and three reads with three writes (512 MiB per stream,
+    the mix of one fused CG step).
     Each is timed at several grid sizes with HIP events; the fastest is kept.  These are the
     rates this GPU sustains for plain streams: the achievable reference beside the nominal
     8 TB/s."""
     GiB = 2 ** 30
-    kinds = {"read": (1, 0, GiB), "write": (0, 1, GiB), "copy": (1, 1, GiB), "3r3w": (3, 3, GiB // 2)}
+    kinds = {"read": (1, 0, GiB), "read_nt": (1, 0, GiB), "write": (0, 1, GiB), "copy": (1, 1, GiB),
+             "3r3w": (3, 3, GiB // 2)}
     out = {}
     for kind, (nr, nw, nb) in kinds.items():
         sets = []

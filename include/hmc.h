@@ -580,13 +580,15 @@ int hmc_batch_trajectory(hmc_batch* batch, double* phi, const double* pi0, const
  *   HMC_PROBE_WRITE  writes dst (bytes); src unused (may be NULL);
  *   HMC_PROBE_COPY   reads src, writes dst (bytes each);
  *   HMC_PROBE_3R3W   reads three streams (src: 3 * bytes) and writes three (dst: 3 * bytes),
- *                    the mix of one fused CG step.
+ *                    the mix of one fused CG step;
+ *   HMC_PROBE_READ_NT as HMC_PROBE_READ with nontemporal loads, eight in flight per thread.
  * Device pointers, 16-byte aligned, caller-owned; asynchronous on the stream.  Errors:
  * HMC_ERR_INVALID_ARG (kind, size, alignment, NULL, grid outside [1, 65536]), HMC_ERR_HIP. */
 #define HMC_PROBE_READ  0
 #define HMC_PROBE_WRITE 1
 #define HMC_PROBE_COPY  2
 #define HMC_PROBE_3R3W  3
+#define HMC_PROBE_READ_NT 4
 int hmc_stream_probe(int kind, const void* src, void* dst, size_t bytes, int grid, void* stream);
 
 /* Text for an HMC_* code. */

@@ -26,6 +26,7 @@ HMC_PROBE_READ = 0
 HMC_PROBE_WRITE = 1
 HMC_PROBE_COPY = 2
 HMC_PROBE_3R3W = 3
+HMC_PROBE_READ_NT = 4
 
 EXPORTED = [
     "hmc_create", "hmc_destroy", "hmc_set_params", "hmc_workspace_bytes", "hmc_set_workspace",

@@ -2372,6 +2372,10 @@ int hmc_stream_probe(int kind, const void* src, void* dst, size_t bytes, int gri
         case HMC_PROBE_3R3W:
             hipLaunchKernelGGL((k_stream<3, 3>), dim3(grid), dim3(kBlock), 0, s, a, b, n4, nullptr);
             break;
+        case HMC_PROBE_READ_NT:
+            hipLaunchKernelGGL((k_stream<1, 0, true>), dim3(grid), dim3(kBlock), 0, s, a, nullptr, n4,
+                               static_cast<double*>(dst));
+            break;
         default:
             return fail(HMC_ERR_INVALID_ARG, "unknown probe kind %d", kind);
     }

@@ -638,10 +638,10 @@ def _traj_dict(st, code):
 
 def stream_probe(kind, src, dst, nbytes, grid=0):
     """One launch of the library's streaming reference kernel (hmc_stream_probe) on the current
-    stream: kind "read", "write", "copy" or "3r3w"; src/dst: device tensors (src may be None for
-    "write"); nbytes: bytes per stream."""
+    stream: kind "read", "read_nt", "write", "copy" or "3r3w"; src/dst: device tensors (src may
+    be None for "write"); nbytes: bytes per stream."""
     k = {"read": _lib.HMC_PROBE_READ, "write": _lib.HMC_PROBE_WRITE, "copy": _lib.HMC_PROBE_COPY,
-         "3r3w": _lib.HMC_PROBE_3R3W}[kind]
+         "3r3w": _lib.HMC_PROBE_3R3W, "read_nt": _lib.HMC_PROBE_READ_NT}[kind]
     check(_lib.load().hmc_stream_probe(k, _ptr(src), _ptr(dst), int(nbytes), int(grid), _stream()),
           "hmc_stream_probe")
 
