@@ -6,6 +6,8 @@ matrix, the BSS identity of Eq. (18), the positivity that the paper's anti-unita
 symmetry guarantees, a finite-difference derivative, or an exact identity of the
 pseudofermion method (Eq. 19-21) and of leapfrog (Methods D).
 """
+import warnings
+
 import numpy as np
 import pytest
 
@@ -276,6 +278,10 @@ def test_metropolis_rule():
     assert O.metropolis_accept(0.5, np.exp(-0.5) - 1e-12)
     assert not O.metropolis_accept(0.5, np.exp(-0.5))
     assert not O.metropolis_accept(np.inf, 0.0)
+    assert not O.metropolis_accept(np.nan, 0.0)
+    with warnings.catch_warnings():
+        warnings.simplefilter("error")           # no overflow on a large energy decrease
+        assert O.metropolis_accept(-1.0e4, 0.999)
 
 
 # ---------------------------------------------------------------------------------------------
