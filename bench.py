@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--apply-reps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-trajectory", action="store_true",
-                    help="also time one full oracle trajectory at 40x40x100 on the host (about 15 "
+                    help="also time one full oracle trajectory at 40x40x100 on the host (about 20 "
                          "minutes of one core; off by default)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default CG launch shapes")
     ap.add_argument("--pcg-steps", type=int, default=3,
