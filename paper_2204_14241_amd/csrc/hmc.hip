@@ -2088,8 +2088,8 @@ static MdmShape mdm_shape(const hmc_ctx* c, int n) {
         m.lds = march_lds<R>(m.plan.R, L);
     } else {
         // the march: one thread per element of the band and of the two rows on either side;
-        // psi of two slices and chi of one in LDS (at most 160 KB)
-        const int rows_lds = int((size_t(160) << 10) / (4 * size_t(L) * sizeof(C2<R>)) - 10) / 3;
+        // psi and chi of two slices each in LDS (at most 160 KB)
+        const int rows_lds = int((size_t(160) << 10) / (4 * size_t(L) * sizeof(C2<R>)) - 12) / 4;
         rows = std::max(1, std::min({rows, kMdmMarchThreads / per_row - 4, rows_lds}));
         m.plan = make_march_plan(L, Lt, rows, seg);
         m.threads = ((std::min(rows, L) + 4) * per_row + 63) / 64 * 64;
@@ -2432,7 +2432,7 @@ int hmc_create(int L, int Lt, double dtau, const hmc_params* params, hmc_ctx** o
     }
     (void)set_cg_shape(c, HMC_FP64, kDefaultBpr64);
     (void)set_cg_shape(c, HMC_MIXED, kDefaultBpr32);
-    // the one-pass M^dagger M march holds two slices of psi and one of chi in LDS (above 64 KB)
+    // the one-pass M^dagger M march holds two slices of psi and two of chi in LDS (above 64 KB)
     for (const void* k : {reinterpret_cast<const void*>(&k_mdm2_march<kMarchMaxThreads>),
                           reinterpret_cast<const void*>(&k_mdm2_march<kMdmMidThreads>),
                           reinterpret_cast<const void*>(&k_mdm2_march<kMdmMarchThreads>),

@@ -1012,14 +1012,16 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_ru_resid_march(CgCtl ctl, M
 // ------------------------------------------------------------------------------------
 // M^dagger M in one pass as a march with the loads one slice ahead (the structure of the CG
 // step-A march): a workgroup owns a band of R rows of one vector and the two rows on either
-// side of it, and walks a segment of slices.  psi of two consecutive slices sits in LDS on the
-// R + 4 rows; each slice it forms chi(tau) = A_tau psi(tau) + s_tau psi(tau + 1) on the R + 2
-// rows that M^dagger reaches into LDS, then (M^dagger chi)(tau) = A_tau chi(tau) +
-// s_{tau-1} chi(tau - 1) on its R rows, chi(tau - 1) kept in registers from the slice before;
-// the next slice's psi and phi are loaded while the current one is computed.  The first slice
-// of a segment forms chi(t0 - 1) at the band's rows first.  HBM: psi and phi read once (plus
-// the rows beside each band, which its neighbours read too, and one slice per segment), the
-// result written once.
+// side of it, and walks a segment of slices.  chi(tau) = A_tau psi(tau) + s_tau psi(tau + 1) is
+// formed on the R + 2 rows that M^dagger reaches, and (M^dagger chi)(tau) = A_tau chi(tau) +
+// s_{tau-1} chi(tau - 1) on the band's R rows, chi(tau - 1) kept in registers.  The two are
+// software-pipelined: while slice tau's M^dagger reads chi(tau) from LDS, chi(tau + 1) is formed
+// from psi(tau + 1) in LDS and written to a second chi buffer, and psi(tau + 2) to a second psi
+// buffer, so one barrier per slice separates every LDS write from its reads (two slices of psi
+// on R + 4 rows and two of chi on R + 2 in LDS); the next slice's psi and phi are loaded while
+// the current one is computed.  A segment starts by forming chi(t0 - 1) at the band's rows and
+// chi(t0).  HBM: psi and phi read once (plus the rows beside each band, which its neighbours
+// read too, and one slice per segment), the result written once.
 // Most threads of a one-pass M^dagger M march workgroup (one per element of its rows).  The
 // kernels are instantiated for at most 512 threads (up to 256 VGPRs each), 768 (168 VGPRs,
 // enough for both precisions) and 1024 (128 VGPRs, a few spilled): a band takes the smallest
@@ -1029,7 +1031,7 @@ constexpr int kMdmMarchThreads = 1024;
 
 template <typename R>
 __host__ __device__ inline size_t mdm_march_lds(int Rrows, int L) {
-    return size_t(3 * Rrows + 10) * 4 * size_t(L) * sizeof(C2<R>);
+    return size_t(4 * Rrows + 12) * 4 * size_t(L) * sizeof(C2<R>);
 }
 
 template <int MAXT>
@@ -1042,9 +1044,12 @@ __global__ __launch_bounds__(MAXT) void k_mdm2_march(Lat lat, MarchPlan mp, cons
     const size_t voff = size_t(mpos.k) * 4 * vol;
     const float2* psi = in + voff;
     float2* dst = out + voff;
-    float2* cur = reinterpret_cast<float2*>(march_smem);        // psi(tau), rows x0 - 2 .. x0 + nr + 1
-    float2* nxt = cur + size_t(mp.R + 4) * rowc;                  // psi(tau + 1)
-    float2* chi = nxt + size_t(mp.R + 4) * rowc;                  // chi(tau), rows x0 - 1 .. x0 + nr
+    // psi of a slice (rows x0 - 2 .. x0 + nr + 1) and chi of a slice (rows x0 - 1 .. x0 + nr), two
+    // of each
+    float2* pa = reinterpret_cast<float2*>(march_smem);
+    float2* pb = pa + size_t(mp.R + 4) * rowc;
+    float2* ca = pb + size_t(mp.R + 4) * rowc;
+    float2* cb = ca + size_t(mp.R + 2) * rowc;
     const int e = threadIdx.x, nh = (mpos.nr + 4) * P;
     const bool act = e < nh;
     const int lr = act ? e / P : 0, py = act ? e - lr * P : 0, y = 2 * py;
@@ -1053,6 +1058,8 @@ __global__ __launch_bounds__(MAXT) void k_mdm2_march(Lat lat, MarchPlan mp, cons
     const bool inner = act && lr >= 2 && lr <= mpos.nr + 1;      // M^dagger M psi is written here
     const int ro = xrow * L + y;
     float4 rv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rv[c] = make_float4(0.f, 0.f, 0.f, 0.f);
     float2 f1 = make_float2(0.f, 0.f), f2 = f1, f3 = f1;
     auto load_psi = [&](int tq) {
         if (act) {
@@ -1068,66 +1075,88 @@ __global__ __launch_bounds__(MAXT) void k_mdm2_march(Lat lat, MarchPlan mp, cons
             f3 = *reinterpret_cast<const float2*>(phi + 2 * vol + i);
         }
     };
-    auto put = [&](float2* buf) {
+    auto put = [&](float2* buf, const float4 (&v)[4]) {
         if (act) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) *reinterpret_cast<float4*>(buf + lr * rowc + c * L + y) = rv[c];
+            for (int c = 0; c < 4; ++c) *reinterpret_cast<float4*>(buf + lr * rowc + c * L + y) = v[c];
         }
     };
     const int t0 = mpos.t0, t1 = mpos.t1;
     const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
-    // chi(t0 - 1) at the band's rows, from psi(t0 - 1) and psi(t0)
-    float4 prev[4], own[4];
+    auto wrapt = [&](int t) { return t >= Lt ? t - Lt : t; };
+    float4 prev[4], own[4], cen[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) prev[c] = own[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+    // chi(t0 - 1) at the band's rows, from psi(t0 - 1) (LDS) and psi(t0) (own site)
     load_psi(tm);
     load_phi(tm);
-    put(nxt);
+    put(pa, rv);
+    const float2 h1 = f1, h2 = f2, h3 = f3;
     load_psi(t0);
     __syncthreads();
-    put(cur);
-    const float2 h1 = f1, h2 = f2, h3 = f3;
     float4 pv[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) pv[c] = rv[c];
-    load_psi(t0 + 1 == Lt ? 0 : t0 + 1);
+    put(pb, pv);
+    load_psi(wrapt(t0 + 1));
     load_phi(t0);
+    if (inner) stencil_pair_lds(pa, lr, xrow, y, L, h1, h2, h3, cf, tm == Lt - 1 ? -1.f : 1.f, pv, prev, cen);
     __syncthreads();
-    if (inner) {
-        float4 cen[4];
-        stencil_pair_lds(nxt, lr, xrow, y, L, h1, h2, h3, cf, tm == Lt - 1 ? -1.f : 1.f, pv, prev, cen);
+    // chi(t0) on the R + 2 rows, from psi(t0) (LDS) and psi(t0 + 1) (own site)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pv[c] = rv[c];
+    float2 c1 = f1, c2 = f2, c3 = f3;
+    put(pa, pv);
+    if (t0 + 1 < t1) {
+        load_psi(wrapt(t0 + 2));
+        load_phi(t0 + 1);
+    }
+    if (chirow) {
+        stencil_pair_lds(pb, lr, xrow, y, L, c1, c2, c3, cf, t0 == Lt - 1 ? -1.f : 1.f, pv, own, cen);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) *reinterpret_cast<float4*>(ca + (lr - 1) * rowc + c * L + y) = own[c];
     }
     __syncthreads();
+    // slice tau: psi(tau + 1) and chi(tau) are in LDS; chi(tau + 1) and (M^dagger chi)(tau) do not
+    // depend on each other, so one barrier per slice separates the writes from the next reads
+    float2 *pcur = pa, *pnxt = pb, *ccur = ca, *cnxt = cb;
     for (int tau = t0; tau < t1; ++tau) {
-        // rv holds psi(tau + 1), f phi(tau)
-        put(nxt);
+        const bool more = tau + 1 < t1;
         float4 pn[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) pn[c] = rv[c];
-        const float2 g1 = f1, g2 = f2, g3 = f3;
-        if (tau + 1 < t1) {
-            const int tn = tau + 1 == Lt ? 0 : tau + 1;
-            load_psi(tn + 1 == Lt ? 0 : tn + 1);
-            load_phi(tn);
+        for (int c = 0; c < 4; ++c) pn[c] = rv[c];                  // psi(tau + 2)
+        const float2 g1 = f1, g2 = f2, g3 = f3;                      // phi(tau + 1)
+        if (tau + 2 < t1) {
+            load_psi(wrapt(tau + 3));
+            load_phi(tau + 2);
         }
-        __syncthreads();
-        if (chirow) {
-            float4 cen[4];
-            stencil_pair_lds(cur, lr, xrow, y, L, g1, g2, g3, cf, tau == Lt - 1 ? -1.f : 1.f, pn, own, cen);
+        if (more) {
+            put(pnxt, pn);
+            if (chirow) {
+                stencil_pair_lds(pcur, lr, xrow, y, L, g1, g2, g3, cf, tau + 1 == Lt - 1 ? -1.f : 1.f, pn, own, cen);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) *reinterpret_cast<float4*>(chi + (lr - 1) * rowc + c * L + y) = own[c];
+                for (int c = 0; c < 4; ++c) *reinterpret_cast<float4*>(cnxt + (lr - 1) * rowc + c * L + y) = own[c];
+            }
         }
-        __syncthreads();
         if (inner) {
-            float4 o[4], cen[4];
-            stencil_pair_lds(chi, lr - 1, xrow, y, L, g1, g2, g3, cf, tau == 0 ? -1.f : 1.f, prev, o, cen);
+            float4 o[4];
+            stencil_pair_lds(ccur, lr - 1, xrow, y, L, c1, c2, c3, cf, tau == 0 ? -1.f : 1.f, prev, o, cen);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 st4(dst, size_t(c) * vol + size_t(tau) * LL + ro, o[c]);
-                prev[c] = own[c];
+                prev[c] = cen[c];
             }
         }
-        float2* sw = cur;
-        cur = nxt;
-        nxt = sw;
+        c1 = g1;
+        c2 = g2;
+        c3 = g3;
+        __syncthreads();
+        float2* sw = pcur;
+        pcur = pnxt;
+        pnxt = sw;
+        sw = ccur;
+        ccur = cnxt;
+        cnxt = sw;
     }
 }
 
@@ -1141,9 +1170,10 @@ __global__ __launch_bounds__(MAXT) void k_mdm_march(Lat lat, MarchPlan mp, const
     const size_t voff = size_t(mpos.k) * 4 * vol;
     const double2* psi = in + voff;
     double2* dst = out + voff;
-    double2* cur = reinterpret_cast<double2*>(march_smem);
-    double2* nxt = cur + size_t(mp.R + 4) * rowc;
-    double2* chi = nxt + size_t(mp.R + 4) * rowc;
+    double2* pa = reinterpret_cast<double2*>(march_smem);
+    double2* pb = pa + size_t(mp.R + 4) * rowc;
+    double2* ca = pb + size_t(mp.R + 4) * rowc;
+    double2* cb = ca + size_t(mp.R + 2) * rowc;
     const int e = threadIdx.x, nh = (mpos.nr + 4) * L;
     const bool act = e < nh;
     const int lr = act ? e / L : 0, y = act ? e - lr * L : 0;
@@ -1152,6 +1182,8 @@ __global__ __launch_bounds__(MAXT) void k_mdm_march(Lat lat, MarchPlan mp, const
     const bool inner = act && lr >= 2 && lr <= mpos.nr + 1;
     const int ro = xrow * L + y;
     double2 rv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rv[c] = make_double2(0.0, 0.0);
     double f1 = 0.0, f2 = 0.0, f3 = 0.0;
     auto load_psi = [&](int tq) {
         if (act) {
@@ -1167,64 +1199,87 @@ __global__ __launch_bounds__(MAXT) void k_mdm_march(Lat lat, MarchPlan mp, const
             f3 = phi[2 * vol + i];
         }
     };
-    auto put = [&](double2* buf) {
+    auto put = [&](double2* buf, const double2 (&v)[4]) {
         if (act) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) buf[lr * rowc + c * L + y] = rv[c];
+            for (int c = 0; c < 4; ++c) buf[lr * rowc + c * L + y] = v[c];
         }
     };
     const int t0 = mpos.t0, t1 = mpos.t1;
     const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
-    double2 prev[4], own[4];
+    auto wrapt = [&](int t) { return t >= Lt ? t - Lt : t; };
+    double2 prev[4], own[4], cen[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) prev[c] = own[c] = make_double2(0.0, 0.0);
+    // chi(t0 - 1) at the band's rows, from psi(t0 - 1) (LDS) and psi(t0) (own site)
     load_psi(tm);
     load_phi(tm);
-    put(nxt);
+    put(pa, rv);
+    const double h1 = f1, h2 = f2, h3 = f3;
     load_psi(t0);
     __syncthreads();
-    put(cur);
-    const double h1 = f1, h2 = f2, h3 = f3;
     double2 pv[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) pv[c] = rv[c];
-    load_psi(t0 + 1 == Lt ? 0 : t0 + 1);
+    put(pb, pv);
+    load_psi(wrapt(t0 + 1));
     load_phi(t0);
+    if (inner) stencil_site_lds(pa, lr, xrow, y, L, h1, h2, h3, cf, tm == Lt - 1 ? -1.0 : 1.0, pv, prev, cen);
     __syncthreads();
-    if (inner) {
-        double2 cen[4];
-        stencil_site_lds(nxt, lr, xrow, y, L, h1, h2, h3, cf, tm == Lt - 1 ? -1.0 : 1.0, pv, prev, cen);
+    // chi(t0) on the R + 2 rows, from psi(t0) (LDS) and psi(t0 + 1) (own site)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pv[c] = rv[c];
+    double c1 = f1, c2 = f2, c3 = f3;
+    put(pa, pv);
+    if (t0 + 1 < t1) {
+        load_psi(wrapt(t0 + 2));
+        load_phi(t0 + 1);
+    }
+    if (chirow) {
+        stencil_site_lds(pb, lr, xrow, y, L, c1, c2, c3, cf, t0 == Lt - 1 ? -1.0 : 1.0, pv, own, cen);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ca[(lr - 1) * rowc + c * L + y] = own[c];
     }
     __syncthreads();
+    // slice tau: as in k_mdm2_march, chi(tau + 1) and (M^dagger chi)(tau) between two barriers
+    double2 *pcur = pa, *pnxt = pb, *ccur = ca, *cnxt = cb;
     for (int tau = t0; tau < t1; ++tau) {
-        put(nxt);
+        const bool more = tau + 1 < t1;
         double2 pn[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) pn[c] = rv[c];
-        const double g1 = f1, g2 = f2, g3 = f3;
-        if (tau + 1 < t1) {
-            const int tn = tau + 1 == Lt ? 0 : tau + 1;
-            load_psi(tn + 1 == Lt ? 0 : tn + 1);
-            load_phi(tn);
+        for (int c = 0; c < 4; ++c) pn[c] = rv[c];                  // psi(tau + 2)
+        const double g1 = f1, g2 = f2, g3 = f3;                      // phi(tau + 1)
+        if (tau + 2 < t1) {
+            load_psi(wrapt(tau + 3));
+            load_phi(tau + 2);
         }
-        __syncthreads();
-        if (chirow) {
-            double2 cen[4];
-            stencil_site_lds(cur, lr, xrow, y, L, g1, g2, g3, cf, tau == Lt - 1 ? -1.0 : 1.0, pn, own, cen);
+        if (more) {
+            put(pnxt, pn);
+            if (chirow) {
+                stencil_site_lds(pcur, lr, xrow, y, L, g1, g2, g3, cf, tau + 1 == Lt - 1 ? -1.0 : 1.0, pn, own, cen);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) chi[(lr - 1) * rowc + c * L + y] = own[c];
+                for (int c = 0; c < 4; ++c) cnxt[(lr - 1) * rowc + c * L + y] = own[c];
+            }
         }
-        __syncthreads();
         if (inner) {
-            double2 o[4], cen[4];
-            stencil_site_lds(chi, lr - 1, xrow, y, L, g1, g2, g3, cf, tau == 0 ? -1.0 : 1.0, prev, o, cen);
+            double2 o[4];
+            stencil_site_lds(ccur, lr - 1, xrow, y, L, c1, c2, c3, cf, tau == 0 ? -1.0 : 1.0, prev, o, cen);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 dst[size_t(c) * vol + size_t(tau) * LL + ro] = o[c];
-                prev[c] = own[c];
+                prev[c] = cen[c];
             }
         }
-        double2* sw = cur;
-        cur = nxt;
-        nxt = sw;
+        c1 = g1;
+        c2 = g2;
+        c3 = g3;
+        __syncthreads();
+        double2* sw = pcur;
+        pcur = pnxt;
+        pnxt = sw;
+        sw = ccur;
+        ccur = cnxt;
+        cnxt = sw;
     }
 }
 
