@@ -43,9 +43,9 @@ def leapfrog(m, phi, pi, chis, eps, n_leap, tol=1e-12, F=None, sigma=None):
 
 
 def metropolis_accept(dH, u):
-    # min(1, exp(-dH)) is 1 for dH <= 0: accept without evaluating an exponential that would
-    # overflow for a large energy decrease
-    return bool(dH <= 0.0 or u < np.exp(-dH))
+    # exp(-dH) is +inf for a large energy decrease, which accepts every finite u
+    with np.errstate(over="ignore"):
+        return bool(u < np.exp(-dH))
 
 
 def trajectory(m, phi0, pi0, etas, u, eps, n_leap, tol=1e-12, sigma=None):

@@ -279,8 +279,9 @@ def test_metropolis_rule():
     assert not O.metropolis_accept(0.5, np.exp(-0.5))
     assert not O.metropolis_accept(np.inf, 0.0)
     assert not O.metropolis_accept(np.nan, 0.0)
+    assert not O.metropolis_accept(-1.0, np.inf)   # u = inf rejects whatever dH (a test device)
     with warnings.catch_warnings():
-        warnings.simplefilter("error")           # no overflow on a large energy decrease
+        warnings.simplefilter("error")           # no overflow warning on a large energy decrease
         assert O.metropolis_accept(-1.0e4, 0.999)
 
 
