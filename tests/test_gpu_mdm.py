@@ -73,3 +73,32 @@ def test_fused_mdagm_equals_two_passes_in_fp64(hip):
     d = (one - two).abs().max().item() / two.abs().max().item()
     say(f"one pass against two: {d:.2e}")
     assert d <= 1e-15
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_mdagm_at_80x80x200_default_shape(hip, precision):
+    """At the benchmark's lattice and the default launch shape (several bands and segments per
+    vector, the pipelined slices): the one-pass form against the two passes of the same
+    precision and, in FP64, against the oracle's operator."""
+    L, Lt = 80, 200
+    g = S.rng(830)
+    phi_np = S.draw_phi(g, L, Lt, 0.5)
+    psi_np = S.draw_spinor(g, L, Lt, 1)
+    h = hip.HMC(L, Lt)
+    if precision == "fp64":
+        phi, psi = dev(phi_np), dev(psi_np)
+        one = h.apply_MdagM(phi, psi)
+        two = h.apply_Mdag(phi, h.apply_M(phi, psi))
+        ref = O.apply_MdagM(O.Model(L=L, Lt=Lt), phi_np, psi_np[0])
+        e = np.abs(one.cpu().numpy()[0] - ref).max() / np.abs(ref).max()
+        say(f"fused M^dag M fp64 80x80x200 shape {h.mdm_shape('fp64', 1)}: oracle {e:.2e}")
+        assert e <= 1e-14
+        bar = 1e-15
+    else:
+        phi, psi = dev(phi_np).float(), dev(psi_np).to(torch.complex64)
+        one = h.apply_MdagM_f32(phi, psi)
+        two = h.apply_Mdag_f32(phi, h.apply_M_f32(phi, psi))
+        bar = 1e-6
+    d = (one - two).abs().max().item() / two.abs().max().item()
+    say(f"fused M^dag M {precision} 80x80x200: one pass against two {d:.2e}")
+    assert d <= bar
