@@ -420,8 +420,11 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG m
     float2* t = v.t + off;
     float2* cur = reinterpret_cast<float2*>(march_smem);
     float2* nxt = cur + size_t(mp.R + 2 * H) * rowc;
-    auto load_slab = [&](int tq, bool with_z) {
-        if (act) {
+    // slice tq of z and p_old (and x and the older direction when the solution update is due);
+    // the slice after the segment (own false) is needed only at the band's own sites, for the
+    // time link, and its solution update belongs to the next segment
+    auto load_slab = [&](int tq, bool with_z, bool own) {
+        if (own ? act : inner) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const size_t i = size_t(c) * vol + size_t(tq) * LL + ro;
@@ -429,7 +432,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG m
                 rp[c] = ld4(pin, i);
             }
         }
-        if (inner && fold) {
+        if (inner && fold && own) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const size_t i = size_t(c) * vol + size_t(tq) * LL + ro;
@@ -456,9 +459,9 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG m
         }
     };
     float4 pn[4];
-    load_slab(t0, false);
+    load_slab(t0, false, true);
     form(t0, cur, true, pn);
-    load_slab(t0 + 1 == Lt ? 0 : t0 + 1, true);
+    load_slab(t0 + 1 == Lt ? 0 : t0 + 1, true, t0 + 1 < t1);
     double part = 0.0;
     for (int tau = t0; tau < t1; ++tau) {
         const int tn = tau + 1 == Lt ? 0 : tau + 1;
@@ -467,7 +470,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a2_march(CgCtl ctl, MG m
         form(tn, nxt, own_next, pnx);
         const float2 g1 = f1, g2 = f2, g3 = f3;
         if (own_next) {
-            load_slab(tn + 1 == Lt ? 0 : tn + 1, true);
+            load_slab(tn + 1 == Lt ? 0 : tn + 1, true, tau + 2 < t1);
             load_phi(tn);
         }
         __syncthreads();
@@ -551,8 +554,11 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg
     double2* t = v.t + off;
     double2* cur = reinterpret_cast<double2*>(march_smem);
     double2* nxt = cur + size_t(mp.R + 2 * H) * rowc;
-    auto load_slab = [&](int tq, bool with_z) {
-        if (act) {
+    // slice tq of z and p_old (and x and the older direction when the solution update is due);
+    // the slice after the segment (own false) is needed only at the band's own sites, for the
+    // time link, and its solution update belongs to the next segment
+    auto load_slab = [&](int tq, bool with_z, bool own) {
+        if (own ? act : inner) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const size_t i = size_t(c) * vol + size_t(tq) * LL + ro;
@@ -560,7 +566,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg
                 rp[c] = pin[i];
             }
         }
-        if (inner && fold) {
+        if (inner && fold && own) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const size_t i = size_t(c) * vol + size_t(tq) * LL + ro;
@@ -586,9 +592,9 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg
         }
     };
     double2 pn[4];
-    load_slab(t0, false);
+    load_slab(t0, false, true);
     form(t0, cur, true, pn);
-    load_slab(t0 + 1 == Lt ? 0 : t0 + 1, true);
+    load_slab(t0 + 1 == Lt ? 0 : t0 + 1, true, t0 + 1 < t1);
     double part = 0.0;
     for (int tau = t0; tau < t1; ++tau) {
         const int tn = tau + 1 == Lt ? 0 : tau + 1;
@@ -597,7 +603,7 @@ __global__ __launch_bounds__(kMarchCgThreads) void k_cg_a_march(CgCtl ctl, MG mg
         form(tn, nxt, own_next, pnx);
         const double g1 = f1, g2 = f2, g3 = f3;
         if (own_next) {
-            load_slab(tn + 1 == Lt ? 0 : tn + 1, true);
+            load_slab(tn + 1 == Lt ? 0 : tn + 1, true, tau + 2 < t1);
             load_phi(tn);
         }
         __syncthreads();
